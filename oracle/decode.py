@@ -1,0 +1,140 @@
+"""FP64 numpy oracle for decoding, decoder training, Adam and the training-step
+loss (test infrastructure only; never imported by the product path).
+
+  decode_plain   Sec. 3.3 Eq. 4 (cosine max-similarity search over the
+                 discrete feature space S) applied to a rendered compact
+                 feature lifted to the codebook dimension by a fixed projection;
+                 softmax over the scores, top-1 = argmax (lowest index on ties).
+  mlp_forward    Eq. 8 / supplementary inference equation: softmax(D_MLP(R_s)),
+                 D_MLP a stack of 1x1 convolutions = per-pixel linear layers
+                 with ReLU (Table 3 gives the layer pattern); bf16 rounding of
+                 the input, weights and hidden activations is emulated exactly,
+                 accumulation is in float64.
+  mlp_train_step Eq. 9 cross-entropy against index labels, gradients by the
+                 chain rule (straight through the bf16 roundings), then Adam.
+  adam           Sec. 4: Adam, lr 1e-3, betas (0.9, 0.999); no weight decay.
+  l1_loss_grad   per-view mean absolute error over RGB and semantic channels
+                 plus lambda_u * mean(R_u) (Eq. 11) and its gradient.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def bf16(x) -> np.ndarray:
+    """Round to the nearest bfloat16 (ties to even), returned as float64.
+    Works directly from float64 (a single rounding); normal range only
+    (no subnormal, overflow or NaN handling: activations here stay normal)."""
+    x = np.asarray(x, np.float64)
+    m, e = np.frexp(x)                        # x = m * 2**e, 0.5 <= |m| < 1
+    r = np.round(np.ldexp(m, 8))              # 8 significant bits, half to even
+    return np.ldexp(r, e - 8)
+
+
+def decode_plain(feat, proj, codebook):
+    """feat [P, d_s], proj [D, d_s], codebook [K, D] (unit rows).
+    Returns (probs [P, K] float64, top1 [P] int64)."""
+    f = np.asarray(feat, np.float64)
+    Pm = np.asarray(proj, np.float64)
+    Cb = np.asarray(codebook, np.float64)
+    z = f @ Pm.T                              # lifted feature, [P, D]
+    nz = np.sqrt(np.sum(z * z, axis=1))
+    dots = z @ Cb.T
+    cn = np.sqrt(np.sum(Cb * Cb, axis=1))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        s = dots / (nz[:, None] * cn[None, :])
+    s[nz == 0] = 0.0
+    s = s - s.max(axis=1, keepdims=True)
+    e = np.exp(s)
+    probs = e / e.sum(axis=1, keepdims=True)
+    top1 = np.argmax(dots / np.where(nz == 0, 1.0, nz)[:, None] / cn[None, :], axis=1)
+    top1[nz == 0] = 0
+    return probs, top1
+
+
+def mlp_forward(feat, weights, biases):
+    """Per-pixel MLP with ReLU between layers. weights[l] is [out, in] (float32
+    master), biases[l] [out] (float32). Returns a dict with the bf16-rounded
+    input, pre-activations z_l, post-activations h_l and float64 logits."""
+    x = bf16(np.asarray(feat, np.float32).astype(np.float64))
+    hs = [x]
+    zs = []
+    h = x
+    L = len(weights)
+    for l in range(L):
+        W = bf16(np.asarray(weights[l], np.float32).astype(np.float64))
+        b = np.asarray(biases[l], np.float32).astype(np.float64)
+        z = h @ W.T + b
+        zs.append(z)
+        if l < L - 1:
+            h = bf16(np.maximum(z, 0.0))
+            hs.append(h)
+    return dict(x=x, hs=hs, zs=zs, logits=zs[-1])
+
+
+def softmax(z):
+    z = z - z.max(axis=1, keepdims=True)
+    e = np.exp(z)
+    return e / e.sum(axis=1, keepdims=True)
+
+
+def mlp_grads(feat, labels, weights, biases):
+    """Mean cross-entropy over the batch and its gradients w.r.t. every weight
+    and bias (straight-through for the bf16 roundings)."""
+    fw = mlp_forward(feat, weights, biases)
+    B = feat.shape[0]
+    p = softmax(fw["logits"])
+    y = np.asarray(labels, np.int64)
+    loss = float(-np.mean(np.log(p[np.arange(B), y])))
+    dz = p.copy()
+    dz[np.arange(B), y] -= 1.0
+    dz /= B
+    L = len(weights)
+    gW = [None] * L
+    gb = [None] * L
+    for l in range(L - 1, -1, -1):
+        h_in = fw["hs"][l]
+        gW[l] = dz.T @ h_in
+        gb[l] = dz.sum(axis=0)
+        if l > 0:
+            W = bf16(np.asarray(weights[l], np.float32).astype(np.float64))
+            dh = dz @ W
+            dz = dh * (fw["zs"][l - 1] > 0.0)
+    return loss, gW, gb
+
+
+def adam(p, g, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (bias-corrected, no weight decay). Returns (p, m, v) float64."""
+    p = np.asarray(p, np.float64)
+    g = np.asarray(g, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** step)
+    vh = v / (1.0 - beta2 ** step)
+    p = p - lr * mh / (np.sqrt(vh) + eps)
+    return p, m, v
+
+
+def l1_loss_grad(out_flat, target_flat, cams, n_channels, d_sem, lambda_u=1.0):
+    """out/target planar [C][H][W] per view, concatenated. Loss per view:
+    mean |out - target| over the RGB and semantic channels, plus lambda_u times
+    the mean rendered uncertainty; summed over views. Returns (loss, grad)."""
+    out = np.asarray(out_flat, np.float64)
+    tgt = np.asarray(target_flat, np.float64)
+    grad = np.zeros_like(out)
+    loss = 0.0
+    off = 0
+    n_fit = 3 + d_sem
+    for cam in cams:
+        hw = cam.width * cam.height
+        o = out[off:off + n_channels * hw].reshape(n_channels, hw)
+        t = tgt[off:off + n_channels * hw].reshape(n_channels, hw)
+        g = grad[off:off + n_channels * hw].reshape(n_channels, hw)
+        d = o[:n_fit] - t[:n_fit]
+        loss += float(np.abs(d).sum() / (n_fit * hw))
+        g[:n_fit] = np.sign(d) / (n_fit * hw)
+        for c in range(n_fit, n_channels):
+            loss += lambda_u * float(o[c].sum() / hw)
+            g[c] = lambda_u / hw
+        off += n_channels * hw
+    return loss, grad
