@@ -1,0 +1,200 @@
+/*
+ * legs.h -- C ABI of the MI355X (gfx950) splatting and decoding library for
+ * Language Embedded 3D Gaussians (arXiv 2311.18482).
+ *
+ * The library renders anisotropic 3D Gaussians that carry RGB, a compact
+ * semantic feature s_G and an uncertainty u (Sec. 3.4.1, 3.4.2) through the
+ * differentiable rasteriser I = R(p, Sigma, c, alpha; p_cam) of Sec. 3.1,
+ * Eq. 1, back-propagates a loss through it, and decodes rendered semantic
+ * features into a distribution over the discrete feature space S (Sec. 3.3,
+ * Eq. 4; Sec. 3.4.1, Eq. 8; supplementary inference equation).
+ *
+ * Conventions shared by every call
+ *  - Every pointer argument named *_dev or documented as "device" is device
+ *    memory of the context's GPU, allocated and owned by the caller. The
+ *    library never allocates on the calls below (the context owns nothing but
+ *    its error text).
+ *  - All work is enqueued on `stream` (a hipStream_t; NULL = legacy default
+ *    stream) and is asynchronous unless stated otherwise.
+ *  - Return codes: LEGS_OK, or a negative LEGS_ERR_* code. On error nothing is
+ *    launched unless stated, and legs_last_error(ctx) holds a message.
+ *  - Gaussian parameters are row-major float32: mean [n][3], log_scale [n][3],
+ *    quat [n][4] as (w, x, y, z) (normalised inside, need not be unit),
+ *    opacity_logit [n] (opacity = sigmoid(logit)), channels [n][C] with
+ *    C <= LEGS_MAX_CHANNELS (RGB, s_G and u are ordinary channels).
+ *  - Rendered outputs are planar per view, views concatenated in order:
+ *    out[C * pixel_offset(v) + c * H_v * W_v + y * W_v + x]; per-pixel
+ *    auxiliaries (final transmittance, last contributor) are
+ *    [pixel_offset(v) + y * W_v + x].
+ *  - Projected records and per-(Gaussian, view) gradients are indexed
+ *    gv = v * n + g ("G-view").
+ */
+#ifndef LEGS_H
+#define LEGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LEGS_OK 0
+#define LEGS_ERR_ARG (-1)         /* invalid argument; nothing launched */
+#define LEGS_ERR_CAPACITY (-2)    /* instance list longer than its buffers */
+#define LEGS_ERR_HIP (-3)         /* a HIP runtime call failed */
+#define LEGS_ERR_UNSUPPORTED (-4) /* valid request this build does not serve */
+
+#define LEGS_MAX_CHANNELS 64
+#define LEGS_MAX_VIEWS 4096
+
+typedef struct legs_ctx legs_ctx;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward); world -> camera
+ * x_c = R x_w + t; pixel (i, j) has its centre at (i + 1/2, j + 1/2). */
+typedef struct {
+    int32_t width, height;
+    double fx, fy, cx, cy;
+    double R[9]; /* row-major */
+    double t[3];
+} legs_camera;
+
+/* One entry of the view table (built on the host by legs_views_build, then
+ * copied by the caller into device memory for the calls below). */
+typedef struct {
+    legs_camera cam;
+    int32_t tiles_x, tiles_y;
+    int64_t tile_offset;  /* first global tile id of this view */
+    int64_t pixel_offset; /* first pixel of this view in the concatenated planes */
+} legs_view;
+
+/* Rasteriser options. Defaults (legs_opts_default): tile 16, lds_batch 256,
+ * alpha_max 0.99, alpha_min 1/255, t_min 1e-4, lowpass 0.3 px^2, z_near 0.2,
+ * guard 1.3. */
+typedef struct {
+    int32_t tile;      /* tile edge in pixels: 8, 16 or 32 */
+    int32_t lds_batch; /* Gaussians staged in LDS per round: 64, 128 or 256 */
+    float alpha_max;   /* alpha = min(alpha_max, opacity * exp(power)) */
+    float alpha_min;   /* skip a Gaussian at a pixel when alpha < alpha_min */
+    float t_min;       /* stop (without blending) when T * (1 - alpha) < t_min */
+    float pad0;
+    double lowpass;    /* added to both diagonal entries of the 2D covariance */
+    double z_near;     /* cull Gaussians with camera-space z <= z_near */
+    double guard;      /* Jacobian evaluated at x/z clamped to +-guard * W / (2 fx) */
+} legs_opts;
+
+/* Per-G-view projected records (device, caller-owned, length n_views * n
+ * except block_offsets):
+ *   mean2d  [G][2] double  2D mean in pixels (EWA projection of p)
+ *   conic   [G][4] float   (A, B, C, opacity): inverse 2D covariance and sigmoid(logit)
+ *   box     [G][4] int32   inclusive pixel box (x0, x1, y0, y1): pixels with
+ *                          |x + 1/2 - mx| <= r and |y + 1/2 - my| <= r,
+ *                          r = ceil(3 sqrt(lambda_max)); x0 > x1 when culled
+ *   depth   [G]    float   camera-space z rounded to float (sort key)
+ *   ntiles  [G]    uint32  tiles touched by the box (0 when culled)
+ *   block_offsets [2 * (legs_projected_blocks(n, n_views) + 1)] uint64 scratch:
+ *                          per-block instance counts (written by legs_project),
+ *                          then their exclusive scan (written by legs_bin_sort) */
+typedef struct {
+    double *mean2d;
+    float *conic;
+    int32_t *box;
+    float *depth;
+    uint32_t *ntiles;
+    uint64_t *block_offsets;
+} legs_projected;
+
+/* Tile lists (device, caller-owned). keys/ids hold the sorted instance list on
+ * return: key = (global_tile << 32) | bits(depth), sorted ascending, ties in
+ * Gaussian order. ranges[2 t], ranges[2 t + 1] = [start, end) of tile t.
+ * keys_alt/ids_alt are ping-pong buffers; scratch is legs_sort_scratch_bytes. */
+typedef struct {
+    uint64_t *keys, *keys_alt;  /* [capacity] */
+    uint32_t *ids, *ids_alt;    /* [capacity] */
+    uint32_t *ranges;           /* [total_tiles][2] */
+    void *scratch;
+    uint64_t *count;            /* [1] number of instances (may exceed capacity) */
+    int64_t capacity;
+} legs_bins;
+
+/* ---- context ------------------------------------------------------------- */
+
+/* Create a context bound to HIP device `device`. Returns LEGS_ERR_ARG for a
+ * bad device, LEGS_ERR_UNSUPPORTED if it is not gfx950. */
+int32_t legs_create(int32_t device, legs_ctx **out);
+int32_t legs_destroy(legs_ctx *ctx);
+/* Text of the last error on this context (static storage inside ctx). */
+const char *legs_last_error(const legs_ctx *ctx);
+int32_t legs_version(void);
+void legs_opts_default(legs_opts *o);
+
+/* ---- host-side sizing (no GPU work) --------------------------------------- */
+
+/* Fill the view table for n_views cameras and the chosen tile size; returns
+ * the total tile and pixel counts. LEGS_ERR_ARG on bad sizes. */
+int32_t legs_views_build(const legs_camera *cams, int32_t n_views, const legs_opts *opts,
+                         legs_view *out_host, int64_t *total_tiles, int64_t *total_pixels);
+/* Number of 256-entry blocks the projection uses for n Gaussians x n_views. */
+int64_t legs_projected_blocks(int64_t n, int32_t n_views);
+/* Bytes of legs_bins.scratch for a given instance capacity and tile count. */
+int64_t legs_sort_scratch_bytes(int64_t capacity, int64_t total_tiles);
+/* Radix passes the sort runs for total_tiles tiles (8-bit digits over the
+ * 32 depth bits plus ceil(log2 total_tiles) tile bits). */
+int32_t legs_sort_passes(int64_t total_tiles);
+
+/* ---- rasteriser (Sec. 3.1 Eq. 1; Sec. 3.4.1 R_s; Sec. 3.4.2 R_u) ---------- */
+
+/* EWA projection of every (Gaussian, view): camera transform, 3D covariance
+ * R S S^T R^T from quaternion and exp(log_scale), 2D covariance
+ * J W Sigma W^T J^T + lowpass I with the guard-band clamped Jacobian, conic,
+ * 2D mean, 3-sigma integer pixel box, tile count and depth key; also the
+ * per-block instance counts in out->block_offsets. Computed in float64.
+ * views_dev: device legs_view[n_views]. */
+int32_t legs_project(legs_ctx *ctx, const float *mean, const float *log_scale, const float *quat,
+                     const float *opacity_logit, int64_t n, const legs_view *views_dev,
+                     int32_t n_views, const legs_opts *opts, legs_projected *out, void *stream);
+
+/* Tile binning: scan of the tile counts, emission of one (key, id) per
+ * (tile, Gaussian) overlap, stable LSD onesweep radix sort of the keys, and
+ * per-tile [start, end) ranges. If host_count != NULL the call waits for the
+ * instance total, stores it in *host_count and returns LEGS_ERR_CAPACITY
+ * (launching nothing further) when it exceeds bins->capacity. With
+ * host_count == NULL nothing waits (graph-capturable): the lists are then
+ * truncated to the capacity and *bins->count > capacity signals overflow. */
+int32_t legs_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t n,
+                      const legs_view *views_dev, int32_t n_views, int64_t total_tiles,
+                      const legs_opts *opts, legs_bins *bins, int64_t *host_count, void *stream);
+
+/* Front-to-back compositing of all C channels per pixel over its tile list:
+ * alpha = min(alpha_max, opacity * exp(power)) inside the Gaussian's box,
+ * skipped when alpha < alpha_min, stopped (not blended) when
+ * T * (1 - alpha) < t_min; background 0. Writes out (planar, see top),
+ * T_final and last = 1 + tile-list position of the last blended Gaussian. */
+int32_t legs_render_forward(legs_ctx *ctx, const legs_projected *proj, int64_t n,
+                            const legs_bins *bins, const legs_view *views_dev, int32_t n_views,
+                            int64_t total_tiles, const float *channels, int32_t C,
+                            const legs_opts *opts, float *out, float *T_final, uint32_t *last,
+                            void *stream);
+
+/* Gradient of a loss with dL/d(out) = d_out (planar like out) through the
+ * compositing, replaying each pixel back to front from (T_final, last).
+ * Accumulates (+=) into grad2d [G][8] = d(mx, my, A, B, C, opacity, -, -)
+ * and d_channels [n][C]; the caller zeroes them first. */
+int32_t legs_render_backward(legs_ctx *ctx, const legs_projected *proj, int64_t n,
+                             const legs_bins *bins, const legs_view *views_dev, int32_t n_views,
+                             int64_t total_tiles, const float *channels, int32_t C,
+                             const legs_opts *opts, const float *T_final, const uint32_t *last,
+                             const float *d_out, float *grad2d, float *d_channels, void *stream);
+
+/* Chain rule from grad2d back to mean, log_scale, (unnormalised) quaternion
+ * and opacity logit, summed over views; accumulates (+=) into the outputs. */
+int32_t legs_project_backward(legs_ctx *ctx, const float *mean, const float *log_scale,
+                              const float *quat, const float *opacity_logit, int64_t n,
+                              const legs_view *views_dev, int32_t n_views, const legs_opts *opts,
+                              const legs_projected *proj, const float *grad2d, float *d_mean,
+                              float *d_log_scale, float *d_quat, float *d_opacity_logit,
+                              void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LEGS_H */

@@ -1,0 +1,259 @@
+// C ABI entry points of liblegs.so: argument validation, then the launchers
+// in project.hip, sort.hip and blend.hip. See include/legs.h for the contract
+// of each call.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "legs_internal.h"
+
+int32_t legs_set_error(legs_ctx *ctx, int32_t code, const char *fmt, ...)
+{
+    if (ctx) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(ctx->err, sizeof ctx->err, fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+namespace {
+
+int32_t check_opts(legs_ctx *ctx, const legs_opts *o)
+{
+    if (!o) return legs_set_error(ctx, LEGS_ERR_ARG, "opts is NULL");
+    if (o->tile != 8 && o->tile != 16 && o->tile != 32)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "tile %d not in {8, 16, 32}", o->tile);
+    if (o->lds_batch != 64 && o->lds_batch != 128 && o->lds_batch != 256)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "lds_batch %d not in {64, 128, 256}", o->lds_batch);
+    if (!(o->alpha_max > 0.f && o->alpha_max < 1.f) || !(o->alpha_min >= 0.f) || !(o->t_min > 0.f))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "alpha/transmittance thresholds out of range");
+    if (!(o->z_near > 0.0) || !(o->guard > 0.0) || !(o->lowpass >= 0.0))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "z_near/guard/lowpass out of range");
+    return LEGS_OK;
+}
+
+int32_t check_views(legs_ctx *ctx, const legs_view *views, int32_t n_views)
+{
+    if (!views) return legs_set_error(ctx, LEGS_ERR_ARG, "views is NULL");
+    if (n_views < 1 || n_views > LEGS_MAX_VIEWS)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "n_views %d out of [1, %d]", n_views, LEGS_MAX_VIEWS);
+    return LEGS_OK;
+}
+
+int32_t use_device(legs_ctx *ctx)
+{
+    int cur = -1;
+    LEGS_CHECK_HIP(ctx, hipGetDevice(&cur));
+    if (cur != ctx->device) LEGS_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    return LEGS_OK;
+}
+
+bool proj_ok(const legs_projected *p)
+{
+    return p && p->mean2d && p->conic && p->box && p->depth && p->ntiles && p->block_offsets;
+}
+
+bool bins_ok(const legs_bins *b)
+{
+    return b && b->keys && b->keys_alt && b->ids && b->ids_alt && b->ranges && b->scratch &&
+           b->count && b->capacity >= 0;
+}
+
+} // namespace
+
+#define LEGS_TRY(expr)                  \
+    do {                                \
+        int32_t r_ = (expr);            \
+        if (r_ != LEGS_OK) return r_;   \
+    } while (0)
+
+extern "C" {
+
+int32_t legs_version(void) { return 1; }
+
+void legs_opts_default(legs_opts *o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->tile = 16;
+    o->lds_batch = 256;
+    o->alpha_max = 0.99f;
+    o->alpha_min = 1.0f / 255.0f;
+    o->t_min = 1e-4f;
+    o->lowpass = 0.3;
+    o->z_near = 0.2;
+    o->guard = 1.3;
+}
+
+int32_t legs_create(int32_t device, legs_ctx **out)
+{
+    if (!out) return LEGS_ERR_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return LEGS_ERR_ARG;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return LEGS_ERR_HIP;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LEGS_ERR_UNSUPPORTED;
+    legs_ctx *c = new legs_ctx;
+    c->device = device;
+    c->num_cus = prop.multiProcessorCount;
+    c->err[0] = 0;
+    *out = c;
+    return LEGS_OK;
+}
+
+int32_t legs_destroy(legs_ctx *ctx)
+{
+    delete ctx;
+    return LEGS_OK;
+}
+
+const char *legs_last_error(const legs_ctx *ctx) { return ctx ? ctx->err : "no context"; }
+
+int32_t legs_views_build(const legs_camera *cams, int32_t n_views, const legs_opts *opts,
+                         legs_view *out_host, int64_t *total_tiles, int64_t *total_pixels)
+{
+    if (!cams || !opts || !out_host || n_views < 1 || n_views > LEGS_MAX_VIEWS) return LEGS_ERR_ARG;
+    const int T = opts->tile;
+    if (T != 8 && T != 16 && T != 32) return LEGS_ERR_ARG;
+    int64_t tiles = 0, pix = 0;
+    for (int32_t v = 0; v < n_views; ++v) {
+        const legs_camera &c = cams[v];
+        if (c.width < 1 || c.height < 1 || c.width > 32767 || c.height > 32767) return LEGS_ERR_ARG;
+        if (!(c.fx > 0.0) || !(c.fy > 0.0)) return LEGS_ERR_ARG;
+        legs_view &w = out_host[v];
+        w.cam = c;
+        w.tiles_x = (c.width + T - 1) / T;
+        w.tiles_y = (c.height + T - 1) / T;
+        w.tile_offset = tiles;
+        w.pixel_offset = pix;
+        tiles += (int64_t)w.tiles_x * w.tiles_y;
+        pix += (int64_t)c.width * c.height;
+    }
+    if (tiles >= (1ll << 32)) return LEGS_ERR_ARG;
+    if (total_tiles) *total_tiles = tiles;
+    if (total_pixels) *total_pixels = pix;
+    return LEGS_OK;
+}
+
+int64_t legs_projected_blocks(int64_t n, int32_t n_views)
+{
+    if (n < 0 || n_views < 1) return -1;
+    return ((n + LEGS_PROJ_BLOCK - 1) / LEGS_PROJ_BLOCK) * (int64_t)n_views;
+}
+
+int64_t legs_sort_scratch_bytes(int64_t capacity, int64_t total_tiles)
+{
+    (void)total_tiles;
+    if (capacity < 0) return -1;
+    return legs_sort_layout_for(capacity).total;
+}
+
+int32_t legs_sort_passes(int64_t total_tiles)
+{
+    int bits = 0;
+    while (bits < 32 && (1ll << bits) < total_tiles) ++bits;
+    return (32 + bits + 7) / 8;
+}
+
+int32_t legs_project(legs_ctx *ctx, const float *mean, const float *log_scale, const float *quat,
+                     const float *opacity_logit, int64_t n, const legs_view *views_dev,
+                     int32_t n_views, const legs_opts *opts, legs_projected *out, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (n < 0 || n >= (1ll << 32)) return legs_set_error(ctx, LEGS_ERR_ARG, "n out of range");
+    if (n > 0 && (!mean || !log_scale || !quat || !opacity_logit))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "NULL Gaussian parameter");
+    if (!proj_ok(out)) return legs_set_error(ctx, LEGS_ERR_ARG, "incomplete projected buffers");
+    LEGS_TRY(check_opts(ctx, opts));
+    LEGS_TRY(check_views(ctx, views_dev, n_views));
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_project(ctx, mean, log_scale, quat, opacity_logit, n, views_dev, n_views,
+                               opts, out, (hipStream_t)stream);
+}
+
+int32_t legs_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t n,
+                      const legs_view *views_dev, int32_t n_views, int64_t total_tiles,
+                      const legs_opts *opts, legs_bins *bins, int64_t *host_count, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (n < 0 || n >= (1ll << 32)) return legs_set_error(ctx, LEGS_ERR_ARG, "n out of range");
+    if (!proj_ok(proj)) return legs_set_error(ctx, LEGS_ERR_ARG, "incomplete projected buffers");
+    if (!bins_ok(bins)) return legs_set_error(ctx, LEGS_ERR_ARG, "incomplete bin buffers");
+    if (bins->capacity >= (1ll << 32))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "capacity must be below 2^32");
+    if (total_tiles < 1 || total_tiles >= (1ll << 32))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "total_tiles out of range");
+    LEGS_TRY(check_opts(ctx, opts));
+    LEGS_TRY(check_views(ctx, views_dev, n_views));
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_bin_sort(ctx, proj, n, views_dev, n_views, total_tiles, opts, bins,
+                                host_count, (hipStream_t)stream);
+}
+
+int32_t legs_render_forward(legs_ctx *ctx, const legs_projected *proj, int64_t n,
+                            const legs_bins *bins, const legs_view *views_dev, int32_t n_views,
+                            int64_t total_tiles, const float *channels, int32_t C,
+                            const legs_opts *opts, float *out, float *T_final, uint32_t *last,
+                            void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (!proj_ok(proj) || !bins_ok(bins)) return legs_set_error(ctx, LEGS_ERR_ARG, "incomplete buffers");
+    if (C < 1 || C > LEGS_MAX_CHANNELS) return legs_set_error(ctx, LEGS_ERR_ARG, "C out of range");
+    if ((n > 0 && !channels) || !out || !T_final || !last)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "NULL output or channels");
+    if (total_tiles < 1 || total_tiles >= (1ll << 32))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "total_tiles out of range");
+    LEGS_TRY(check_opts(ctx, opts));
+    LEGS_TRY(check_views(ctx, views_dev, n_views));
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_blend_forward(ctx, proj, n, bins, views_dev, n_views, total_tiles, channels,
+                                     C, opts, out, T_final, last, (hipStream_t)stream);
+}
+
+int32_t legs_render_backward(legs_ctx *ctx, const legs_projected *proj, int64_t n,
+                             const legs_bins *bins, const legs_view *views_dev, int32_t n_views,
+                             int64_t total_tiles, const float *channels, int32_t C,
+                             const legs_opts *opts, const float *T_final, const uint32_t *last,
+                             const float *d_out, float *grad2d, float *d_channels, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (!proj_ok(proj) || !bins_ok(bins)) return legs_set_error(ctx, LEGS_ERR_ARG, "incomplete buffers");
+    if (C < 1 || C > LEGS_MAX_CHANNELS) return legs_set_error(ctx, LEGS_ERR_ARG, "C out of range");
+    if ((n > 0 && !channels) || !T_final || !last || !d_out || !grad2d || !d_channels)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "NULL input or gradient buffer");
+    if (total_tiles < 1 || total_tiles >= (1ll << 32))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "total_tiles out of range");
+    LEGS_TRY(check_opts(ctx, opts));
+    LEGS_TRY(check_views(ctx, views_dev, n_views));
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_blend_backward(ctx, proj, n, bins, views_dev, n_views, total_tiles,
+                                      channels, C, opts, T_final, last, d_out, grad2d, d_channels,
+                                      (hipStream_t)stream);
+}
+
+int32_t legs_project_backward(legs_ctx *ctx, const float *mean, const float *log_scale,
+                              const float *quat, const float *opacity_logit, int64_t n,
+                              const legs_view *views_dev, int32_t n_views, const legs_opts *opts,
+                              const legs_projected *proj, const float *grad2d, float *d_mean,
+                              float *d_log_scale, float *d_quat, float *d_opacity_logit,
+                              void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (n < 0 || n >= (1ll << 32)) return legs_set_error(ctx, LEGS_ERR_ARG, "n out of range");
+    if (n > 0 && (!mean || !log_scale || !quat || !opacity_logit || !grad2d || !d_mean ||
+                  !d_log_scale || !d_quat || !d_opacity_logit))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "NULL parameter or gradient");
+    if (!proj_ok(proj)) return legs_set_error(ctx, LEGS_ERR_ARG, "incomplete projected buffers");
+    LEGS_TRY(check_opts(ctx, opts));
+    LEGS_TRY(check_views(ctx, views_dev, n_views));
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_project_backward(ctx, mean, log_scale, quat, opacity_logit, n, views_dev,
+                                        n_views, opts, proj, grad2d, d_mean, d_log_scale, d_quat,
+                                        d_opacity_logit, (hipStream_t)stream);
+}
+
+} // extern "C"

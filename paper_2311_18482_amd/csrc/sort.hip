@@ -1,0 +1,457 @@
+// Tile binning for the rasteriser (gfx950): instance scan, key emission, a
+// stable LSD onesweep radix sort of 64-bit (tile << 32 | depth bits) keys with
+// 32-bit Gaussian ids, and per-tile [start, end) ranges.
+//
+// Every kernel after the scan reads the instance count from device memory and
+// walks it with a fixed grid, so the whole chain can be captured in a HIP
+// graph without knowing the count on the host.
+//
+// Onesweep (one pass per 8-bit digit): digit histograms for every pass come
+// from one upfront read of the keys; each pass then ranks a 4096-key
+// partition per workgroup with wave64 ballots (stable: ties keep input order),
+// publishes per-digit partition counts, and resolves its global offsets by
+// decoupled look-back over earlier partitions. Partition ids are handed out
+// by an atomic counter in launch order, so every partition a workgroup waits
+// on belongs to a workgroup that is already running (forward progress without
+// relying on blockIdx scheduling order). Keys are first scattered into LDS in
+// digit order, then written out so consecutive lanes write consecutive
+// addresses within a digit run.
+#include "legs_internal.h"
+
+namespace {
+
+constexpr uint64_t FLAG_AGG = 1ull << 62;
+constexpr uint64_t FLAG_INC = 2ull << 62;
+constexpr uint64_t VALUE_MASK = (1ull << 62) - 1;
+
+__device__ __forceinline__ uint64_t ld_status(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_status(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---- scan of the per-block instance counts -----------------------------------
+
+// One workgroup: exclusive scan of counts[0..nb) into offsets[0..nb], total
+// in offsets[nb] and in *total (counts stay intact, so the binning can rerun).
+__global__ void __launch_bounds__(1024)
+k_scan_blocks(const uint64_t *__restrict__ counts, uint64_t *__restrict__ offsets, int64_t nb,
+              uint64_t *__restrict__ total)
+{
+    __shared__ uint64_t s_w[16];
+    __shared__ uint64_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    const int lane = legs_lane(), wave = threadIdx.x / LEGS_WAVE;
+    for (int64_t base = 0; base < nb; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const uint64_t x = i < nb ? counts[i] : 0;
+        uint64_t incl = x;
+#pragma unroll
+        for (int off = 1; off < LEGS_WAVE; off <<= 1) {
+            const uint64_t y = __shfl_up(incl, off, LEGS_WAVE);
+            if (lane >= off) incl += y;
+        }
+        if (lane == LEGS_WAVE - 1) s_w[wave] = incl;
+        __syncthreads();
+        uint64_t wpre = 0;
+        for (int w = 0; w < wave; ++w) wpre += s_w[w];
+        const uint64_t carry = s_carry;
+        if (i < nb) offsets[i] = carry + wpre + incl - x;
+        __syncthreads();
+        if (threadIdx.x == 1023) s_carry = carry + wpre + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        offsets[nb] = s_carry;
+        *total = s_carry;
+    }
+}
+
+// ---- emission -------------------------------------------------------------------
+
+// Same grid as the projection: block (bx, v) owns G-views [v n + 256 bx, ...).
+// The block's instances are laid out Gaussian-major, tiles row-major inside
+// each rectangle; threads stride over them (balanced even when one Gaussian
+// covers thousands of tiles) and find their owner by binary search in LDS.
+__global__ void __launch_bounds__(LEGS_PROJ_BLOCK)
+k_emit(const int4 *__restrict__ box, const float *__restrict__ depth,
+       const uint32_t *__restrict__ ntiles, const uint64_t *__restrict__ block_offsets, int64_t n,
+       const legs_view *__restrict__ views, int tile, int64_t capacity,
+       uint64_t *__restrict__ keys, uint32_t *__restrict__ ids)
+{
+    __shared__ uint32_t s_start[LEGS_PROJ_BLOCK + 1];
+    __shared__ int s_tx0[LEGS_PROJ_BLOCK], s_ty0[LEGS_PROJ_BLOCK], s_rw[LEGS_PROJ_BLOCK];
+    __shared__ uint32_t s_bits[LEGS_PROJ_BLOCK];
+    const int v = blockIdx.y;
+    const int64_t g = (int64_t)blockIdx.x * LEGS_PROJ_BLOCK + threadIdx.x;
+    const int64_t gv = (int64_t)v * n + g;
+    uint32_t cnt = 0;
+    if (g < n) {
+        cnt = ntiles[gv];
+        if (cnt) {
+            const int4 b = box[gv];
+            s_tx0[threadIdx.x] = b.x / tile;
+            s_ty0[threadIdx.x] = b.z / tile;
+            s_rw[threadIdx.x] = b.y / tile - b.x / tile + 1;
+            s_bits[threadIdx.x] = __float_as_uint(depth[gv]);
+        }
+    }
+    // block-exclusive scan of cnt
+    const int lane = legs_lane(), wave = threadIdx.x / LEGS_WAVE;
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int off = 1; off < LEGS_WAVE; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, LEGS_WAVE);
+        if (lane >= off) incl += y;
+    }
+    __shared__ uint32_t s_w[LEGS_PROJ_BLOCK / LEGS_WAVE];
+    if (lane == LEGS_WAVE - 1) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t wpre = 0;
+    for (int w = 0; w < wave; ++w) wpre += s_w[w];
+    s_start[threadIdx.x] = wpre + incl - cnt;
+    if (threadIdx.x == LEGS_PROJ_BLOCK - 1) s_start[LEGS_PROJ_BLOCK] = wpre + incl;
+    __syncthreads();
+    const uint32_t total = s_start[LEGS_PROJ_BLOCK];
+    const uint64_t base = block_offsets[(int64_t)v * gridDim.x + blockIdx.x];
+    const legs_view vw = views[v];
+    for (uint32_t k = threadIdx.x; k < total; k += LEGS_PROJ_BLOCK) {
+        // owner: last o with s_start[o] <= k
+        int lo = 0, hi = LEGS_PROJ_BLOCK - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_start[mid] <= k) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t local = k - s_start[lo];
+        const int rw = s_rw[lo];
+        const int ty = s_ty0[lo] + (int)(local / (uint32_t)rw);
+        const int tx = s_tx0[lo] + (int)(local % (uint32_t)rw);
+        const uint64_t gt = (uint64_t)(vw.tile_offset + (int64_t)ty * vw.tiles_x + tx);
+        const uint64_t pos = base + k;
+        if (pos < (uint64_t)capacity) {
+            keys[pos] = (gt << 32) | s_bits[lo];
+            ids[pos] = (uint32_t)((int64_t)blockIdx.x * LEGS_PROJ_BLOCK + lo);
+        }
+    }
+}
+
+// ---- digit histograms for every pass in one read -----------------------------
+
+__global__ void __launch_bounds__(256)
+k_histogram(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ count,
+            int64_t capacity, int passes, uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t s_h[LEGS_SORT_MAX_PASSES][256];
+    for (int i = threadIdx.x; i < LEGS_SORT_MAX_PASSES * 256; i += 256) (&s_h[0][0])[i] = 0;
+    __syncthreads();
+    const uint64_t cnt = *count;
+    const int64_t m = (int64_t)(cnt < (uint64_t)capacity ? cnt : (uint64_t)capacity);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
+        const uint64_t k = keys[i];
+        for (int p = 0; p < passes; ++p) atomicAdd(&s_h[p][(k >> (8 * p)) & 255], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < passes * 256; i += 256) {
+        const uint32_t c = (&s_h[0][0])[i];
+        if (c) atomicAdd(&hist[i], c);
+    }
+}
+
+// Exclusive scan of each pass's 256 digit counts (one workgroup per pass).
+__global__ void __launch_bounds__(256)
+k_digit_starts(const uint32_t *__restrict__ hist, uint32_t *__restrict__ starts)
+{
+    const int p = blockIdx.x, d = threadIdx.x;
+    const int lane = legs_lane(), wave = d / LEGS_WAVE;
+    const uint32_t x = hist[p * 256 + d];
+    uint32_t incl = x;
+#pragma unroll
+    for (int off = 1; off < LEGS_WAVE; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, LEGS_WAVE);
+        if (lane >= off) incl += y;
+    }
+    __shared__ uint32_t s_w[4];
+    if (lane == LEGS_WAVE - 1) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int w = 0; w < wave; ++w) pre += s_w[w];
+    starts[p * 256 + d] = pre + incl - x;
+}
+
+// Zero the look-back status words of every pass and the partition counters,
+// only as far as the partitions this count needs.
+__global__ void __launch_bounds__(256)
+k_sort_clear(uint64_t *__restrict__ status, int64_t parts_cap, int passes,
+             uint32_t *__restrict__ counters, uint32_t *__restrict__ hist,
+             const uint64_t *__restrict__ count, int64_t capacity)
+{
+    const uint64_t cnt = *count;
+    const int64_t m = (int64_t)(cnt < (uint64_t)capacity ? cnt : (uint64_t)capacity);
+    const int64_t parts = (m + LEGS_SORT_PART - 1) / LEGS_SORT_PART;
+    const int64_t per_pass = parts * 256;
+    const int64_t tot = per_pass * passes;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < tot; i += stride) {
+        const int64_t p = i / per_pass, r = i - p * per_pass;
+        status[p * parts_cap * 256 + r] = 0;
+    }
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < 16) counters[threadIdx.x] = 0;
+        for (int i = threadIdx.x; i < LEGS_SORT_MAX_PASSES * 256; i += 256) hist[i] = 0;
+    }
+}
+
+// One onesweep pass over digit `pass` (bits 8 pass .. 8 pass + 7).
+__global__ void __launch_bounds__(LEGS_SORT_THREADS)
+k_onesweep(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+           uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
+           const uint64_t *__restrict__ count, int64_t capacity, int pass,
+           const uint32_t *__restrict__ digit_starts, uint64_t *__restrict__ status,
+           uint32_t *__restrict__ counter)
+{
+    constexpr int NW = LEGS_SORT_THREADS / LEGS_WAVE;
+    __shared__ uint64_t s_keys[LEGS_SORT_PART];
+    __shared__ uint32_t s_vals[LEGS_SORT_PART];
+    __shared__ uint32_t s_wh[NW][256];      // per-wave digit counts, then wave offsets
+    __shared__ uint32_t s_lstart[256];      // block-local start of each digit
+    __shared__ uint64_t s_gstart[256];      // global start of this partition's digit run
+    __shared__ uint32_t s_tmp[NW];
+    __shared__ int64_t s_part;
+
+    const uint64_t cnt = *count;
+    const int64_t m = (int64_t)(cnt < (uint64_t)capacity ? cnt : (uint64_t)capacity);
+    const int64_t parts = (m + LEGS_SORT_PART - 1) / LEGS_SORT_PART;
+    const int shift = 8 * pass;
+    const int tid = threadIdx.x, lane = legs_lane(), wave = tid / LEGS_WAVE;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+    for (;;) {
+        if (tid == 0) s_part = (int64_t)atomicAdd(counter, 1u);
+        for (int i = tid; i < NW * 256; i += LEGS_SORT_THREADS) (&s_wh[0][0])[i] = 0;
+        __syncthreads();
+        const int64_t part = s_part;
+        if (part >= parts) break;
+        const int64_t base = part * LEGS_SORT_PART;
+        const int64_t nvalid64 = m - base < LEGS_SORT_PART ? m - base : LEGS_SORT_PART;
+        const int nvalid = (int)nvalid64;
+
+        uint64_t key[LEGS_SORT_ITEMS];
+        uint32_t val[LEGS_SORT_ITEMS];
+        uint32_t rank[LEGS_SORT_ITEMS];
+        // wave-striped: item i of lane l of wave w is partition element w*64*ITEMS + i*64 + l
+#pragma unroll
+        for (int i = 0; i < LEGS_SORT_ITEMS; ++i) {
+            const int e = wave * LEGS_WAVE * LEGS_SORT_ITEMS + i * LEGS_WAVE + lane;
+            if (e < nvalid) { key[i] = kin[base + e]; val[i] = vin[base + e]; }
+            else { key[i] = ~0ull; val[i] = 0; }
+        }
+        // rank within the wave: peers with the same digit via 8 ballots
+#pragma unroll
+        for (int i = 0; i < LEGS_SORT_ITEMS; ++i) {
+            const int e = wave * LEGS_WAVE * LEGS_SORT_ITEMS + i * LEGS_WAVE + lane;
+            const bool ok = e < nvalid;
+            const uint32_t d = (uint32_t)(key[i] >> shift) & 255u;
+            uint64_t peers = legs_ballot(ok);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const uint64_t bal = legs_ballot((d >> b) & 1u);
+                peers &= ((d >> b) & 1u) ? bal : ~bal;
+            }
+            // the lowest peer reserves the run for all of them; an LDS atomic keeps
+            // the reservation ordered against the next item's reservation
+            const int leader = ok ? __ffsll((unsigned long long)peers) - 1 : lane;
+            uint32_t pre = 0;
+            if (ok && lane == leader) pre = atomicAdd(&s_wh[wave][d], (uint32_t)__popcll(peers));
+            const uint32_t lbase = (uint32_t)__shfl((int)pre, leader, LEGS_WAVE);
+            rank[i] = lbase + (uint32_t)__popcll(peers & lt_mask);
+        }
+        __syncthreads();
+        // per digit: offsets of each wave, block total, look-back
+        {
+            const int d = tid; // LEGS_SORT_THREADS == 256 digits
+            uint32_t t = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t c = s_wh[w][d];
+                s_wh[w][d] = t;
+                t += c;
+            }
+            uint64_t *st = status + part * 256 + d;
+            if (part == 0) st_status(st, FLAG_INC | (uint64_t)t);
+            else st_status(st, FLAG_AGG | (uint64_t)t);
+            uint64_t excl = 0;
+            if (part > 0) {
+                int64_t j = part - 1;
+                for (;;) {
+                    const uint64_t sv = ld_status(status + j * 256 + d);
+                    const uint64_t f = sv & ~VALUE_MASK;
+                    if (f == 0) continue;            // not published yet
+                    excl += sv & VALUE_MASK;
+                    if (f == FLAG_INC) break;
+                    --j;
+                }
+                st_status(st, FLAG_INC | (excl + t));
+            }
+            s_gstart[d] = (uint64_t)digit_starts[pass * 256 + d] + excl;
+            // block-local exclusive scan of digit totals
+            uint32_t incl = t;
+#pragma unroll
+            for (int off = 1; off < LEGS_WAVE; off <<= 1) {
+                const uint32_t y = __shfl_up(incl, off, LEGS_WAVE);
+                if (lane >= off) incl += y;
+            }
+            if (lane == LEGS_WAVE - 1) s_tmp[wave] = incl;
+            __syncthreads();
+            uint32_t wp = 0;
+            for (int w = 0; w < wave; ++w) wp += s_tmp[w];
+            s_lstart[d] = wp + incl - t;
+        }
+        __syncthreads();
+        // scatter into LDS in digit order
+#pragma unroll
+        for (int i = 0; i < LEGS_SORT_ITEMS; ++i) {
+            const int e = wave * LEGS_WAVE * LEGS_SORT_ITEMS + i * LEGS_WAVE + lane;
+            if (e < nvalid) {
+                const uint32_t d = (uint32_t)(key[i] >> shift) & 255u;
+                const uint32_t pos = s_lstart[d] + s_wh[wave][d] + rank[i];
+                s_keys[pos] = key[i];
+                s_vals[pos] = val[i];
+            }
+        }
+        __syncthreads();
+        // write out digit runs
+        for (int k = tid; k < nvalid; k += LEGS_SORT_THREADS) {
+            const uint64_t kk = s_keys[k];
+            const uint32_t d = (uint32_t)(kk >> shift) & 255u;
+            const uint64_t gpos = s_gstart[d] + (uint64_t)(k - (int)s_lstart[d]);
+            kout[gpos] = kk;
+            vout[gpos] = s_vals[k];
+        }
+        __syncthreads();
+    }
+}
+
+// ---- tile ranges --------------------------------------------------------------
+
+__global__ void __launch_bounds__(256)
+k_fill_u32(uint32_t *__restrict__ p, int64_t n, uint32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = v;
+}
+
+__global__ void __launch_bounds__(256)
+k_ranges(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ count, int64_t capacity,
+         uint32_t *__restrict__ ranges)
+{
+    const uint64_t cnt = *count;
+    const int64_t m = (int64_t)(cnt < (uint64_t)capacity ? cnt : (uint64_t)capacity);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
+        const uint32_t t = (uint32_t)(keys[i] >> 32);
+        if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[2 * (int64_t)t] = (uint32_t)i;
+        if (i == m - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
+    }
+}
+
+} // namespace
+
+legs_sort_layout legs_sort_layout_for(int64_t capacity)
+{
+    legs_sort_layout L;
+    const int64_t parts = (capacity + LEGS_SORT_PART - 1) / LEGS_SORT_PART;
+    L.parts = parts > 0 ? parts : 1;
+    L.hist_off = 0;
+    L.start_off = L.hist_off + 4 * LEGS_SORT_MAX_PASSES * 256;
+    L.counter_off = L.start_off + 4 * LEGS_SORT_MAX_PASSES * 256;
+    L.status_off = L.counter_off + 256;  // 16 counters, padded
+    L.total = L.status_off + 8 * (int64_t)LEGS_SORT_MAX_PASSES * L.parts * 256;
+    return L;
+}
+
+static int grid_for(legs_ctx *ctx, int64_t work, int per_block, int waves_per_cu)
+{
+    int64_t b = (work + per_block - 1) / per_block;
+    const int64_t cap = (int64_t)ctx->num_cus * waves_per_cu;
+    if (b > cap) b = cap;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t n,
+                             const legs_view *views, int32_t n_views, int64_t total_tiles,
+                             const legs_opts *o, legs_bins *bins, int64_t *host_count,
+                             hipStream_t s)
+{
+    const int64_t bx = (n + LEGS_PROJ_BLOCK - 1) / LEGS_PROJ_BLOCK;
+    const int64_t nb = bx * n_views;
+    const int passes = legs_sort_passes(total_tiles);
+    const legs_sort_layout L = legs_sort_layout_for(bins->capacity);
+    char *scr = static_cast<char *>(bins->scratch);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(scr + L.hist_off);
+    uint32_t *starts = reinterpret_cast<uint32_t *>(scr + L.start_off);
+    uint32_t *counters = reinterpret_cast<uint32_t *>(scr + L.counter_off);
+    uint64_t *status = reinterpret_cast<uint64_t *>(scr + L.status_off);
+
+    // 1. exclusive scan of the per-block counts -> instance offsets and total
+    uint64_t *offsets = proj->block_offsets + nb + 1;
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, proj->block_offsets, offsets, nb,
+                       bins->count);
+    LEGS_CHECK_LAUNCH(ctx);
+    if (host_count) {
+        uint64_t tot = 0;
+        LEGS_CHECK_HIP(ctx, hipMemcpyAsync(&tot, bins->count, sizeof(tot), hipMemcpyDeviceToHost, s));
+        LEGS_CHECK_HIP(ctx, hipStreamSynchronize(s));
+        *host_count = (int64_t)tot;
+        if ((int64_t)tot > bins->capacity)
+            return legs_set_error(ctx, LEGS_ERR_CAPACITY,
+                                  "legs_bin_sort: %lld instances exceed capacity %lld",
+                                  (long long)tot, (long long)bins->capacity);
+    }
+    // 2. emission: the final sorted list must land in keys/ids after `passes`
+    //    ping-pong passes, so emit into the buffer of the right parity.
+    uint64_t *k0 = (passes % 2 == 0) ? bins->keys : bins->keys_alt;
+    uint32_t *v0 = (passes % 2 == 0) ? bins->ids : bins->ids_alt;
+    uint64_t *k1 = (passes % 2 == 0) ? bins->keys_alt : bins->keys;
+    uint32_t *v1 = (passes % 2 == 0) ? bins->ids_alt : bins->ids;
+    if (n > 0 && n_views > 0) {
+        hipLaunchKernelGGL(k_emit, dim3((unsigned)bx, (unsigned)n_views), dim3(LEGS_PROJ_BLOCK), 0, s,
+                           reinterpret_cast<const int4 *>(proj->box), proj->depth, proj->ntiles,
+                           offsets, n, views, o->tile, bins->capacity, k0, v0);
+        LEGS_CHECK_LAUNCH(ctx);
+    }
+    // 3. sort
+    const int gclear = grid_for(ctx, (int64_t)L.parts * 256 * passes, 256, 8);
+    hipLaunchKernelGGL(k_sort_clear, dim3(gclear), dim3(256), 0, s, status, L.parts, passes,
+                       counters, hist, bins->count, bins->capacity);
+    LEGS_CHECK_LAUNCH(ctx);
+    const int ghist = grid_for(ctx, bins->capacity, 256 * 16, 4);
+    hipLaunchKernelGGL(k_histogram, dim3(ghist), dim3(256), 0, s, k0, bins->count, bins->capacity,
+                       passes, hist);
+    LEGS_CHECK_LAUNCH(ctx);
+    hipLaunchKernelGGL(k_digit_starts, dim3(passes), dim3(256), 0, s, hist, starts);
+    LEGS_CHECK_LAUNCH(ctx);
+    const int gsort = grid_for(ctx, bins->capacity, LEGS_SORT_PART, 2);
+    uint64_t *ka = k0, *kb = k1;
+    uint32_t *va = v0, *vb = v1;
+    for (int p = 0; p < passes; ++p) {
+        hipLaunchKernelGGL(k_onesweep, dim3(gsort), dim3(LEGS_SORT_THREADS), 0, s, ka, va, kb, vb,
+                           bins->count, bins->capacity, p, starts,
+                           status + (int64_t)p * L.parts * 256, counters + p);
+        LEGS_CHECK_LAUNCH(ctx);
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        uint32_t *tv = va; va = vb; vb = tv;
+    }
+    // 4. ranges (the sorted list is now in bins->keys)
+    const int gfill = grid_for(ctx, 2 * total_tiles, 256, 8);
+    hipLaunchKernelGGL(k_fill_u32, dim3(gfill), dim3(256), 0, s, bins->ranges, 2 * total_tiles, 0u);
+    LEGS_CHECK_LAUNCH(ctx);
+    const int grng = grid_for(ctx, bins->capacity, 256, 16);
+    hipLaunchKernelGGL(k_ranges, dim3(grng), dim3(256), 0, s, bins->keys, bins->count,
+                       bins->capacity, bins->ranges);
+    LEGS_CHECK_LAUNCH(ctx);
+    return LEGS_OK;
+}

@@ -1,0 +1,160 @@
+"""Shared helpers for GPU-vs-oracle parity tests (not collected by pytest).
+
+Comparison rules
+  - integer work (boxes, tile counts, keys, ids, ranges, last): bit-exact;
+  - rendered channels and final transmittance: |gpu - oracle| <= 1e-4 per
+    pixel and channel. Where a skip (alpha vs 1/255) or stop (T (1 - alpha) vs
+    1e-4) decision lies within a relative margin of 1e-5 / 1e-4 of its
+    threshold, float32 and float64 may legitimately take different branches:
+    such a pixel also passes if it matches the oracle with that decision
+    inverted (up to the first four ambiguous events, any combination);
+  - gradients: per Gaussian and parameter group,
+    ||g - g_ref|| <= 1e-3 * max(||g_ref||, 1e-3 * RMS of the group), with the
+    oracle replaying each pixel along the branch the GPU took.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from oracle import oracle as O
+
+GROUPS = ("mean", "log_scale", "quat", "opacity_logit", "channels")
+
+
+def to_dev(scene, device="cuda"):
+    return dict(mean=torch.from_numpy(scene.mean).to(device),
+                log_scale=torch.from_numpy(scene.log_scale).to(device),
+                quat=torch.from_numpy(scene.quat).to(device),
+                opacity_logit=torch.from_numpy(scene.opacity_logit).to(device),
+                channels=torch.from_numpy(scene.channels).to(device))
+
+
+def oracle_opts(o, eps_alpha=1e-5, eps_t=1e-4):
+    return O.make_opts(tile=o.tile, lowpass=o.lowpass, z_near=o.z_near, guard=o.guard,
+                       eps_alpha=eps_alpha, eps_t=eps_t)
+
+
+def compare_projection(proj_gpu, fwd, n):
+    """GPU projected records vs the oracle's: integers exact, floats close."""
+    P = fwd["proj"].reshape(-1)
+    box = proj_gpu.box.cpu().numpy()
+    nt = proj_gpu.ntiles.cpu().numpy().astype(np.int64)
+    valid = P["valid"] == 1
+    want_box = np.stack([P["x0"], P["x1"], P["y0"], P["y1"]], 1)
+    assert np.array_equal(nt, np.where(valid, P["ntiles"], 0)), "tile counts differ"
+    assert np.array_equal(box[valid], want_box[valid]), "pixel boxes differ"
+    assert (box[~valid, 0] > box[~valid, 1]).all(), "culled Gaussians must have empty boxes"
+    depth = proj_gpu.depth.cpu().numpy()
+    assert np.array_equal(depth[valid].view(np.uint32), P["depth32"][valid].view(np.uint32))
+    m2 = proj_gpu.mean2d.cpu().numpy()
+    assert np.allclose(m2[valid, 0], P["mx"][valid], rtol=1e-13, atol=1e-9)
+    assert np.allclose(m2[valid, 1], P["my"][valid], rtol=1e-13, atol=1e-9)
+    cn = proj_gpu.conic.cpu().numpy().astype(np.float64)
+    scale = np.maximum(np.abs(P["A"]), np.abs(P["C"]))
+    for k, f in enumerate(("A", "B", "C")):
+        assert (np.abs(cn[valid, k] - P[f][valid]) <= 2.5e-7 * scale[valid]).all(), f"conic {f}"
+    assert np.allclose(cn[valid, 3], P["sig"][valid], rtol=2e-7, atol=0)
+    return int(valid.sum())
+
+
+def compare_bins(bins_gpu, fwd):
+    n_inst = int(bins_gpu.count.item())
+    assert n_inst == len(fwd["keys"]), (n_inst, len(fwd["keys"]))
+    keys = bins_gpu.keys[:n_inst].cpu().numpy().view(np.uint64)
+    ids = bins_gpu.ids[:n_inst].cpu().numpy().view(np.uint32)
+    assert np.array_equal(keys, fwd["keys"]), "sorted keys differ"
+    assert np.array_equal(ids, fwd["ids"]), "sorted ids differ"
+    rg = bins_gpu.ranges.cpu().numpy().view(np.uint32)
+    empty_o = fwd["ranges"][:, 0] == fwd["ranges"][:, 1]
+    empty_g = rg[:, 0] == rg[:, 1]
+    assert np.array_equal(empty_o, empty_g)
+    assert np.array_equal(rg[~empty_g], fwd["ranges"][~empty_o])
+    return n_inst
+
+
+def compare_render(out_g, T_g, last_g, scene, cams, oo, fwd, tol=1e-4, pix_subset=None):
+    """Per-pixel parity with the ambiguity rule. Returns (flip masks per view,
+    stats). pix_subset: optional per-view arrays of linear pixel indices to
+    check (the oracle renders only those)."""
+    C = scene.n_channels
+    out_g = out_g.cpu().numpy()
+    T_g = T_g.cpu().numpy()
+    last_g = last_g.cpu().numpy().astype(np.int64)
+    off_pix = 0
+    masks = []
+    stats = dict(pixels=0, ambiguous=0, flipped=0, max_err=0.0)
+    for v, cam in enumerate(cams):
+        hw = cam.width * cam.height
+        go = out_g[C * off_pix:C * (off_pix + hw)].reshape(C, hw)
+        gT = T_g[off_pix:off_pix + hw]
+        gl = last_g[off_pix:off_pix + hw]
+        if pix_subset is None:
+            r = fwd["views"][v]
+            pix = np.arange(hw)
+        else:
+            pix = np.asarray(pix_subset[v], np.int64)
+            r = O.render_view(fwd["proj"][v], cam, oo, scene.channels, fwd["ids"], fwd["ranges"],
+                              fwd["offsets"][v], pix=pix)
+        go, gT, gl = go[:, pix], gT[pix], gl[pix]
+        err = np.maximum(np.abs(go - r["out"]).max(axis=0), np.abs(gT - r["T"]))
+        ok = (err <= tol) & (gl == r["last"])
+        mask = np.zeros(len(pix), np.uint32)
+        bad = np.nonzero(~ok)[0]
+        stats["pixels"] += len(pix)
+        stats["ambiguous"] += int((r["n_amb"] > 0).sum())
+        if len(bad):
+            namb = r["n_amb"][bad]
+            unresolved = bad[namb == 0]
+            assert len(unresolved) == 0, (
+                f"view {v}: {len(unresolved)} unambiguous pixels differ; first {pix[unresolved[:5]]},"
+                f" err {err[unresolved[:5]]}, last gpu {gl[unresolved[:5]]} oracle {r['last'][unresolved[:5]]}")
+            cand = bad
+            for m in range(1, 16):
+                if len(cand) == 0:
+                    break
+                sel = cand[r["n_amb"][cand] >= m.bit_length()]
+                if len(sel) == 0:
+                    continue
+                rf = O.render_view(fwd["proj"][v], cam, oo, scene.channels, fwd["ids"],
+                                   fwd["ranges"], fwd["offsets"][v], pix=pix[sel],
+                                   flip_mask=np.full(len(sel), m, np.uint32))
+                e2 = np.maximum(np.abs(go[:, sel] - rf["out"]).max(axis=0), np.abs(gT[sel] - rf["T"]))
+                good = (e2 <= tol) & (gl[sel] == rf["last"])
+                mask[sel[good]] = m
+                cand = np.setdiff1d(cand, sel[good])
+            assert len(cand) == 0, (f"view {v}: {len(cand)} ambiguous pixels match no branch; "
+                                    f"first {pix[cand[:5]]} err {err[cand[:5]]}")
+            stats["flipped"] += len(bad)
+        stats["max_err"] = max(stats["max_err"], float(err[ok].max()) if ok.any() else 0.0)
+        full = np.zeros(hw, np.uint32)
+        full[pix] = mask
+        masks.append(full)
+        off_pix += hw
+    return masks, stats
+
+
+def gpu_grads_to_np(grads, d_ch):
+    out = {k: grads[k].cpu().numpy().astype(np.float64) for k in ("mean", "log_scale", "quat", "opacity_logit")}
+    out["channels"] = d_ch.cpu().numpy().astype(np.float64)
+    return out
+
+
+def compare_grads(g, ref, n, tol=1e-3, groups=GROUPS, subset=None):
+    """Per-Gaussian group check; returns worst ratio err / bound per group."""
+    worst = {}
+    for grp in groups:
+        a = np.asarray(g[grp], np.float64).reshape(n, -1)
+        r = np.asarray(ref[grp], np.float64).reshape(n, -1)
+        if subset is not None:
+            a, r = a[subset], r[subset]
+        nz = np.abs(r).sum(axis=1) > 0
+        rms = np.sqrt(np.mean(r[nz] ** 2)) if nz.any() else 0.0
+        err = np.linalg.norm(a - r, axis=1)
+        bound = tol * np.maximum(np.linalg.norm(r, axis=1), 1e-3 * rms)
+        bad = err > bound
+        if nz.any() or bad.any():
+            worst[grp] = float(np.max(err / np.maximum(bound, 1e-300)))
+        assert not bad.any(), (f"{grp}: {int(bad.sum())} of {len(a)} Gaussians exceed tolerance; "
+                               f"worst ratio {worst[grp]:.3g}")
+    return worst

@@ -1,0 +1,246 @@
+"""GPU parity of the splatting path (projection, binning, blending and their
+backward) against the FP64 CPU oracle, through the C ABI of liblegs.so.
+
+Renderer: Sec. 3.1 Eq. 1 with the semantic (Sec. 3.4.1, R_s) and
+uncertainty (Sec. 3.4.2, R_u) channels blended alongside RGB.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import fd
+from oracle import oracle as O
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2311_18482_amd import raster
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return raster
+
+
+def run_forward(R, scene, cams, o):
+    rast = R.Rasterizer(cams, o)
+    d = PT.to_dev(scene)
+    proj, bins, out, T, last = rast.forward(d["mean"], d["log_scale"], d["quat"],
+                                            d["opacity_logit"], d["channels"])
+    torch.cuda.synchronize()
+    return rast, d, proj, bins, out, T, last
+
+
+def run_backward(R, rast, d, proj, bins, T, last, G):
+    Gd = torch.from_numpy(G).cuda()
+    grad2d, d_ch = R.render_backward(rast.ctx, proj, bins, rast.views, d["channels"], rast.o, T,
+                                     last, Gd)
+    grads = R.project_backward(rast.ctx, d["mean"], d["log_scale"], d["quat"], d["opacity_logit"],
+                               rast.views, rast.o, proj, grad2d)
+    torch.cuda.synchronize()
+    return grad2d, grads, d_ch
+
+
+def full_check(R, scene, cams, tile=16, batch=256, grads=True, seed_g=200):
+    o = R.opts(tile=tile, lds_batch=batch)
+    oo = PT.oracle_opts(o)
+    note(f"forward n={scene.n} views={len(cams)} tile={tile} batch={batch}")
+    rast, d, proj, bins, out, T, last = run_forward(R, scene, cams, o)
+    fwd = O.forward(scene, cams, oo)
+    PT.compare_projection(proj, fwd, scene.n)
+    PT.compare_bins(bins, fwd)
+    masks, stats = PT.compare_render(out, T, last, scene, cams, oo, fwd)
+    note(f"render stats {stats}")
+    if not grads:
+        return stats
+    G = synth.upstream_grads(cams, scene.n_channels, seed_g)
+    note("backward")
+    grad2d, g, d_ch = run_backward(R, rast, d, proj, bins, T, last, G)
+    ref = O.backward(scene, cams, oo, fwd, G.astype(np.float64), flip_masks=masks)
+    # per-G-view screen-space gradients
+    g2 = grad2d.cpu().numpy()[:, :6].astype(np.float64)
+    ref2 = ref["grad2d"].reshape(-1, 6)
+    PT.compare_grads({"g2": g2}, {"g2": ref2}, g2.shape[0], groups=("g2",))
+    worst = PT.compare_grads(PT.gpu_grads_to_np(g, d_ch), ref, scene.n)
+    note(f"gradient worst ratios {worst}")
+    return stats
+
+
+def test_c1_forward_backward(R):
+    scene, cams = synth.workload_c1()
+    full_check(R, scene, cams)
+
+
+@pytest.mark.parametrize("tile,batch", [(8, 64), (32, 128), (16, 64)])
+def test_c1_other_tiles(R, tile, batch):
+    scene, cams = synth.workload_c1()
+    full_check(R, scene, cams, tile=tile, batch=batch)
+
+
+def test_ragged_multiview(R):
+    """Views whose sizes are not multiples of the tile, seen from different poses."""
+    scene = synth.make_scene(6000, 12, synth.VOL_C1, d_sem=8)
+    cams = [synth.camera_front(100, 75, 110.0), synth.camera_front(37, 53, 40.0)]
+    R2, t2 = synth.look_at((2.0, 1.0, -2.0), target=(0.0, 0.0, 4.0))
+    cams.append(synth.Camera(150, 90, 140.0, 150.0, 70.0, 47.0, R2, t2))
+    for tile in (8, 16, 32):
+        full_check(R, scene, cams, tile=tile, batch=128)
+
+
+def test_uncommon_channel_counts(R):
+    for d_sem in (0, 5, 16, 30):
+        scene = synth.make_scene(3000, 13 + d_sem, synth.VOL_C1, d_sem=d_sem)
+        cams = [synth.camera_front(64, 48, 64.0)]
+        full_check(R, scene, cams, tile=16, batch=64)
+
+
+def test_degenerate_scenes(R):
+    # everything behind the camera, or nothing at all touches the image
+    scene = synth.make_scene(500, 14, synth.VOL_C1, d_sem=2)
+    scene.mean[:, 2] = -3.0
+    cams = [synth.camera_front(64, 64, 64.0)]
+    stats = full_check(R, scene, cams)
+    assert stats["pixels"] == 64 * 64
+    # a single Gaussian
+    one = synth.make_scene(1, 15, synth.VOL_C1, d_sem=3)
+    one.mean[0] = (0.0, 0.0, 3.0)
+    one.log_scale[0] = (-1.5, -1.5, -1.5)
+    full_check(R, one, cams)
+
+
+def test_c2_forward_backward_and_fd(R):
+    scene, cams = synth.workload_c2()
+    o = R.opts(tile=16, lds_batch=256)
+    oo = PT.oracle_opts(o)
+    note("c2 forward")
+    rast, d, proj, bins, out, T, last = run_forward(R, scene, cams, o)
+    fwd = O.forward(scene, cams, oo)
+    PT.compare_projection(proj, fwd, scene.n)
+    PT.compare_bins(bins, fwd)
+    masks, stats = PT.compare_render(out, T, last, scene, cams, oo, fwd)
+    note(f"c2 render stats {stats}")
+    G = synth.upstream_grads(cams, scene.n_channels, 202)
+    note("c2 backward")
+    grad2d, g, d_ch = run_backward(R, rast, d, proj, bins, T, last, G)
+    ref = O.backward(scene, cams, oo, fwd, G.astype(np.float64), flip_masks=masks)
+    gg = PT.gpu_grads_to_np(g, d_ch)
+    worst = PT.compare_grads(gg, ref, scene.n)
+    note(f"c2 gradient worst ratios {worst}")
+    # central finite differences on 64 seeded Gaussians blended somewhere,
+    # with boxes small enough for the FD re-renders to stay cheap
+    ids = fd.blended_gaussians(ref)
+    P = fwd["proj"][0]
+    small = ids[(P["radius"][ids] <= 40)]
+    sel = np.random.default_rng(302).choice(small, 64, replace=False)
+    n_valid = 0
+    for k, gidx in enumerate(sel):
+        r = fd.fd_gaussian(fwd["params"], scene.channels, cams, oo, fwd["proj"], G.astype(np.float64), gidx)
+        for grp in PT.GROUPS:
+            vals, ok = r[grp]
+            a = gg[grp].reshape(scene.n, -1)[gidx][ok]
+            rms = np.sqrt(np.mean(ref[grp][ids] ** 2))
+            err = np.linalg.norm(a - vals[ok])
+            bound = 1e-3 * max(np.linalg.norm(vals[ok]), 1e-3 * rms)
+            assert err <= bound, (int(gidx), grp, err, bound)
+            n_valid += int(ok.sum())
+    note(f"c2 fd entries checked {n_valid}")
+    assert n_valid >= 64 * 20
+
+
+def test_tile_and_batch_invariance(R):
+    """Images and final transmittance are bit-identical for every tile size and
+    LDS batch size (the per-pixel box rule makes them tile-free)."""
+    scene = synth.make_scene(50_000, 16, synth.VOL_C2, d_sem=8)
+    cams = [synth.camera_front(333, 250, 300.0)]
+    ref = None
+    for tile in (8, 16, 32):
+        for batch in (64, 128, 256):
+            note(f"invariance tile={tile} batch={batch}")
+            _, _, _, _, out, T, _ = run_forward(R, scene, cams, R.opts(tile=tile, lds_batch=batch))
+            cur = (out.cpu().numpy(), T.cpu().numpy())
+            if ref is None:
+                ref = cur
+            else:
+                assert np.array_equal(cur[0], ref[0]) and np.array_equal(cur[1], ref[1])
+
+
+def test_determinism_and_permutation(R):
+    scene = synth.make_scene(40_000, 17, synth.VOL_C2, d_sem=8)
+    cams = [synth.camera_front(300, 200, 280.0)]
+    o = R.opts()
+    _, _, _, _, out1, T1, l1 = run_forward(R, scene, cams, o)
+    _, _, _, _, out2, T2, l2 = run_forward(R, scene, cams, o)
+    assert torch.equal(out1, out2) and torch.equal(T1, T2) and torch.equal(l1, l2)
+    perm = np.random.default_rng(3).permutation(scene.n)
+    _, _, _, _, out3, T3, l3 = run_forward(R, scene.subset(perm), cams, o)
+    assert torch.equal(out1, out3) and torch.equal(T1, T3) and torch.equal(l1, l3)
+
+
+def test_capacity_overflow_is_reported(R):
+    from paper_2311_18482_amd import _lib as L
+    scene, cams = synth.workload_c1()
+    o = R.opts()
+    rast = R.Rasterizer(cams, o)
+    d = PT.to_dev(scene)
+    proj = R.project(rast.ctx, d["mean"], d["log_scale"], d["quat"], d["opacity_logit"], rast.views, o)
+    small = R.BinsBuf(1000, rast.views.total_tiles, d["mean"].device)
+    import ctypes as ct
+    cnt = ct.c_int64(0)
+    ps, bs = proj.struct(), small.struct()
+    code = L.lib().legs_bin_sort(rast.ctx.handle, ct.byref(ps), scene.n, R._p(rast.views.dev), 1,
+                                 rast.views.total_tiles, ct.byref(o), ct.byref(bs), ct.byref(cnt),
+                                 R._stream())
+    assert code == L.LEGS_ERR_CAPACITY and cnt.value > 1000
+    # without the host read-back, kernels truncate to the capacity and flag it on device
+    code = L.lib().legs_bin_sort(rast.ctx.handle, ct.byref(ps), scene.n, R._p(rast.views.dev), 1,
+                                 rast.views.total_tiles, ct.byref(o), ct.byref(bs), None, R._stream())
+    assert code == L.LEGS_OK
+    torch.cuda.synchronize()
+    assert int(small.count.item()) == cnt.value
+    # the wrapper grows its buffers and gets the exact lists
+    bins = R.bin_sort(rast.ctx, proj, rast.views, o, small)
+    assert bins.n_instances == cnt.value and bins.capacity >= cnt.value
+
+
+def test_invalid_arguments(R):
+    from paper_2311_18482_amd import _lib as L
+    import ctypes as ct
+    scene, cams = synth.workload_c1()
+    rast = R.Rasterizer(cams, R.opts())
+    d = PT.to_dev(scene)
+    bad = R.opts(tile=12)
+    proj = R.ProjectedBuf(scene.n, 1, d["mean"].device)
+    ps = proj.struct()
+    code = L.lib().legs_project(rast.ctx.handle, R._p(d["mean"]), R._p(d["log_scale"]),
+                                R._p(d["quat"]), R._p(d["opacity_logit"]), scene.n,
+                                R._p(rast.views.dev), 1, ct.byref(bad), ct.byref(ps), R._stream())
+    assert code == L.LEGS_ERR_ARG
+    assert b"tile" in L.lib().legs_last_error(rast.ctx.handle)
+    code = L.lib().legs_project(rast.ctx.handle, None, R._p(d["log_scale"]), R._p(d["quat"]),
+                                R._p(d["opacity_logit"]), scene.n, R._p(rast.views.dev), 1,
+                                ct.byref(rast.o), ct.byref(ps), R._stream())
+    assert code == L.LEGS_ERR_ARG
+
+
+def test_autograd_function(R):
+    scene, cams = synth.workload_c1()
+    rast = R.Rasterizer(cams, R.opts())
+    d = PT.to_dev(scene)
+    params = {k: v.clone().requires_grad_(True) for k, v in d.items()}
+    out, T = R.rasterize(params["mean"], params["log_scale"], params["quat"],
+                         params["opacity_logit"], params["channels"], rast)
+    G = torch.from_numpy(synth.upstream_grads(cams, scene.n_channels, 203)).cuda()
+    (out * G).sum().backward()
+    _, _, proj, bins, _, T2, last = run_forward(R, scene, cams, rast.o)
+    grad2d, g, d_ch = run_backward(R, rast, d, proj, bins, T2, last, G.cpu().numpy())
+    for k in ("mean", "log_scale", "quat", "opacity_logit"):
+        torch.testing.assert_close(params[k].grad, g[k], rtol=1e-5, atol=1e-6)
+    torch.testing.assert_close(params["channels"].grad, d_ch, rtol=1e-5, atol=1e-6)
