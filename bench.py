@@ -1,0 +1,185 @@
+#!/usr/bin/env python
+"""Throughput of the splatting hot path on one MI355X.
+
+One step = project -> bin/sort -> blend forward -> blend backward ->
+project backward for every view of the workload (the forward + backward
+rasteriser pass of Sec. 3.1 Eq. 1 with the R_s and R_u channels of Sec. 3.4),
+inputs resident in HBM. value = total view pixels / median step time, in
+Mpixels/s. Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 1m_1080p]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import synth
+    if name == "1m_1080p":
+        scene, cams = synth.workload_1m_1080p()
+        desc = "1M Gaussians in [-4,4]^3, 1 view 1920x1080 on the r=8 sphere, C=12 (RGB+8 sem+u)"
+    elif name == "c2":
+        scene, cams = synth.workload_c2()
+        desc = "300k Gaussians, 1 view 1080x720, C=12"
+    elif name == "c3":
+        scene, cams = synth.workload_c3()
+        desc = "1M Gaussians, 16 uneven views on the r=8 sphere, C=12"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return scene, cams, desc
+
+
+def cpu_baseline(scene, cams, tile, budget_s=30.0):
+    """The FP64 oracle as it stands, on this host's cores: one full forward +
+    backward of the same workload (projection, lists, blending, backward)."""
+    import synth
+    from oracle import oracle as O
+    oo = O.make_opts(tile)
+    t0 = time.perf_counter()
+    fwd = O.forward(scene, cams, oo)
+    G = synth.upstream_grads(cams, scene.n_channels, 200).astype(np.float64)
+    O.backward(scene, cams, oo, fwd, G)
+    dt = time.perf_counter() - t0
+    px = sum(c.width * c.height for c in cams)
+    return dict(value=px / dt / 1e6, unit="Mpixels/s", cores=O.threads(), kind="oracle",
+                sample=f"one full forward+backward step of the same workload ({px} px), {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="1m_1080p")
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--lds-batch", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the rasteriser would shard by view with one gradient all-reduce).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2311_18482_amd import raster as R
+
+    scene, cams, desc = workload(args.workload)
+    log(f"workload {desc}")
+    o = R.opts(tile=args.tile, lds_batch=args.lds_batch)
+    rast = R.Rasterizer(cams, o)
+    dev = rast.ctx.device
+    d = {k: torch.from_numpy(getattr(scene, k)).to(dev)
+         for k in ("mean", "log_scale", "quat", "opacity_logit", "channels")}
+    n, C = scene.channels.shape
+    views = rast.views
+    proj = R.ProjectedBuf(n, views.n_views, dev)
+    R.project(rast.ctx, d["mean"], d["log_scale"], d["quat"], d["opacity_logit"], views, o, out=proj)
+    bins = R.bin_sort(rast.ctx, proj, views, o)           # sizes the lists once (host read-back)
+    n_inst = bins.n_instances
+    bins = R.BinsBuf(int(n_inst * 1.05) + 4096, views.total_tiles, dev)
+    out = torch.empty(C * views.total_pixels, dtype=torch.float32, device=dev)
+    T = torch.empty(views.total_pixels, dtype=torch.float32, device=dev)
+    last = torch.empty(views.total_pixels, dtype=torch.int32, device=dev)
+    G = torch.from_numpy(__import__("synth").upstream_grads(cams, C, 200)).to(dev)
+    grad2d = torch.zeros((n * views.n_views, 8), dtype=torch.float32, device=dev)
+    d_ch = torch.zeros((n, C), dtype=torch.float32, device=dev)
+    grads = {k: torch.zeros_like(d[k]) for k in ("mean", "log_scale", "quat", "opacity_logit")}
+    stages = ("project", "bin_sort", "blend_fwd", "zero", "blend_bwd", "project_bwd")
+
+    def step(ev=None):
+        def mark(i):
+            if ev is not None:
+                ev[i].record()
+        mark(0)
+        R.project(rast.ctx, d["mean"], d["log_scale"], d["quat"], d["opacity_logit"], views, o, out=proj)
+        mark(1)
+        R.bin_sort(rast.ctx, proj, views, o, bins, sync_count=False)
+        mark(2)
+        R.render_forward(rast.ctx, proj, bins, views, d["channels"], o, out, T, last)
+        mark(3)
+        grad2d.zero_()
+        d_ch.zero_()
+        for g in grads.values():
+            g.zero_()
+        mark(4)
+        R.render_backward(rast.ctx, proj, bins, views, d["channels"], o, T, last, G, grad2d, d_ch)
+        mark(5)
+        R.project_backward(rast.ctx, d["mean"], d["log_scale"], d["quat"], d["opacity_logit"],
+                           views, o, proj, grad2d, grads)
+        mark(6)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    assert int(bins.count.item()) <= bins.capacity, "instance list overflowed"
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_step = np.array([evs[k][0].elapsed_time(evs[k][6]) for k in range(args.steps)])
+    stage_ms = {s: float(np.median([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)]))
+                for i, s in enumerate(stages)}
+    ms = float(np.median(per_step))
+    px = views.total_pixels
+    value = px / (ms * 1e-3) / 1e6
+    log(f"stages (median ms): {json.dumps(stage_ms)}; wall {wall:.3f}s for {args.steps} steps; "
+        f"instances {n_inst}")
+
+    # dominant kernel roofline: the onesweep sort is bandwidth-bound; the blend
+    # kernels are bound by vector ALU work (see the roofline section of the design)
+    dom = max(stage_ms, key=stage_ms.get)
+    roofline = None
+    if dom in ("bin_sort", "project", "project_bwd"):
+        if dom == "bin_sort":
+            passes = int(R.L.lib().legs_sort_passes(views.total_tiles))
+            bytes_ = n_inst * (12 + 8 + 24 * passes + 8)
+        elif dom == "project":
+            bytes_ = n * views.n_views * (44 + 16 + 16 + 16 + 4 + 4)
+        else:
+            bytes_ = n * views.n_views * (44 + 32 + 44 + 4)
+        ach = bytes_ / (stage_ms[dom] * 1e-3) / 1e9
+        roofline = dict(bound="hbm", kernel=dom, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=ach / HBM_PEAK_GBS, traffic=None)
+    else:
+        roofline = dict(bound="alu", kernel=dom, achieved=None, peak=FP32_VECTOR_PEAK_TFLOPS,
+                        unit="TFLOP/s", frac=None, traffic=None)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
+        cpu = cpu_baseline(scene, cams, args.tile)
+
+    rec = dict(metric="fwd+bwd Mpixels/s, 1M Gaussians @1080p", value=value, unit="Mpixels/s",
+               n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+               data="synthetic",
+               config=dict(workload=desc, n_gaussians=int(n), views=len(cams), pixels=int(px),
+                           channels=int(C), tile=args.tile, lds_batch=args.lds_batch,
+                           instances=int(n_inst), stage_ms=stage_ms),
+               roofline=roofline, cpu_baseline=cpu)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -194,6 +194,90 @@ int32_t legs_project_backward(legs_ctx *ctx, const float *mean, const float *log
                               float *d_log_scale, float *d_quat, float *d_opacity_logit,
                               void *stream);
 
+
+/* ---- decoding (Sec. 3.3 Eq. 4; Sec. 3.4.1 Eq. 8; supplementary inference) --- */
+
+/* Rendered compact features have LEGS_DECODE_DIN channels. A feature element
+ * (pixel p, channel c) is read at feat[c * c_stride + p * p_stride], so the
+ * planar maps of legs_render_forward (c_stride = H W, p_stride = 1, starting
+ * at the first semantic channel) and row-major [P][8] arrays (c_stride = 1,
+ * p_stride = 8) both work without a copy. K (codes) is 32, 64 or 128.
+ * probs (nullable) is [P][K] float; top1 is [P] int32, lowest index on ties. */
+#define LEGS_DECODE_DIN 8
+
+/* Plain decode: z = P f (proj [D][8], D a multiple of 32 up to 512), cosine
+ * scores s_k = <c_k, z> / (|c_k| |z|) against codebook [K][D] (Eq. 4's
+ * max-similarity search), softmax over k, argmax. s = 0 when z = 0. */
+int32_t legs_decode_plain(legs_ctx *ctx, const float *feat, int64_t P, int64_t c_stride,
+                          int64_t p_stride, const float *proj, int32_t D, const float *codebook,
+                          int32_t K, float *probs, int32_t *top1, void *stream);
+
+/* Exact algebraic folding of the plain decode: folded [(K + 8) * 8] floats =
+ * rows (c_k P) / |c_k| followed by the Gram matrix P^T P (float64 sums). */
+int32_t legs_decode_fold(legs_ctx *ctx, const float *proj, int32_t D, const float *codebook,
+                         int32_t K, float *folded, void *stream);
+/* The plain decode's scores from the folded form: s_k = (M f)_k / sqrt(f^T Q f). */
+int32_t legs_decode_folded(legs_ctx *ctx, const float *feat, int64_t P, int64_t c_stride,
+                           int64_t p_stride, const float *folded, int32_t K, float *probs,
+                           int32_t *top1, void *stream);
+
+/* Learned decode softmax(D_MLP(f)), D_MLP = 8 -> 64 -> 64 -> K per-pixel
+ * linear layers with ReLU (1x1 convolutions, the pattern of Table 3). params
+ * are float32 masters packed W1 [64][8], b1 [64], W2 [64][64], b2 [64],
+ * W3 [K][64], b3 [K]; weights, input and hidden activations are rounded to
+ * bf16 (nearest even), accumulation and biases are float32. */
+int64_t legs_mlp_param_count(int32_t K);
+int32_t legs_decode_mlp(legs_ctx *ctx, const float *feat, int64_t P, int64_t c_stride,
+                        int64_t p_stride, const float *params, int32_t K, float *probs,
+                        int32_t *top1, void *stream);
+
+/* Gradient of the mean cross-entropy (Eq. 9) of B pixels against labels
+ * [B] int32 in [0, K): grad [legs_mlp_param_count(K)] is overwritten, loss [1]
+ * receives the mean loss. Straight-through for the bf16 roundings.
+ * workspace: legs_mlp_workspace_bytes(B, K) bytes of device memory. */
+int64_t legs_mlp_workspace_bytes(int64_t B, int32_t K);
+int32_t legs_mlp_grad(legs_ctx *ctx, const float *feat, int64_t B, int64_t c_stride,
+                      int64_t p_stride, const int32_t *labels, int32_t K, const float *params,
+                      void *workspace, float *grad, float *loss, void *stream);
+
+/* ---- optimisation (Sec. 4: Adam, lr 1e-3, betas (0.9, 0.999)) ------------- */
+
+/* One parameter group of a fused Adam step (all device pointers, n floats).
+ * Elements j with clamp_every > 0 and j % clamp_every == clamp_offset are
+ * clamped to [clamp_lo, clamp_hi] after the update (the uncertainty u in [0, 1]
+ * of Sec. 3.4.2 stored as a channel column). */
+typedef struct {
+    float *param;
+    const float *grad;
+    float *m, *v;
+    int64_t n;
+    int32_t clamp_every, clamp_offset;
+    float clamp_lo, clamp_hi;
+} legs_adam_group;
+#define LEGS_ADAM_MAX_GROUPS 8
+
+/* m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
+ * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps); one launch
+ * over every group (groups is a host array of n_groups <= 8). */
+int32_t legs_adam(legs_ctx *ctx, const legs_adam_group *groups, int32_t n_groups, int32_t step,
+                  float lr, float beta1, float beta2, float eps, void *stream);
+
+/* One decoder training step: legs_mlp_grad, then legs_adam on params with
+ * moment buffers m, v [legs_mlp_param_count(K)]; grad is scratch. */
+int32_t legs_mlp_train_step(legs_ctx *ctx, const float *feat, int64_t B, int64_t c_stride,
+                            int64_t p_stride, const int32_t *labels, int32_t K, float *params,
+                            float *m, float *v, float *grad, int32_t step, float lr, float beta1,
+                            float beta2, float eps, void *workspace, float *loss, void *stream);
+
+/* Per view: mean |out - target| over the first n_fit channels (RGB and s_G)
+ * plus lambda_u times the mean of the remaining channels (R_u, Eq. 11),
+ * summed over views. Writes d_out = dL/d(out) (planar like out) and the loss
+ * into loss [1] (overwritten). */
+int32_t legs_l1_loss_grad(legs_ctx *ctx, const float *out, const float *target,
+                          const legs_view *views_dev, int32_t n_views, int64_t total_pixels,
+                          int32_t C, int32_t n_fit, float lambda_u, float *d_out, float *loss,
+                          void *stream);
+
 #ifdef __cplusplus
 }
 #endif

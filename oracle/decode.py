@@ -52,14 +52,20 @@ def decode_plain(feat, proj, codebook):
     return probs, top1
 
 
-def mlp_forward(feat, weights, biases):
+def mlp_forward(feat, weights, biases, amb_tol=2e-6):
     """Per-pixel MLP with ReLU between layers. weights[l] is [out, in] (float32
     master), biases[l] [out] (float32). Returns a dict with the bf16-rounded
-    input, pre-activations z_l, post-activations h_l and float64 logits."""
+    input, pre-activations z_l, post-activations h_l and float64 logits.
+
+    `ambiguous` flags pixels with a hidden activation within a relative amb_tol
+    of a bf16 rounding midpoint: a float32 accumulation (error ~1e-7 relative)
+    may round such a value to the other neighbour, so those pixels are checked
+    only loosely against an implementation that accumulates in float32."""
     x = bf16(np.asarray(feat, np.float32).astype(np.float64))
     hs = [x]
     zs = []
     h = x
+    amb = np.zeros(x.shape[0], bool)
     L = len(weights)
     for l in range(L):
         W = bf16(np.asarray(weights[l], np.float32).astype(np.float64))
@@ -67,9 +73,11 @@ def mlp_forward(feat, weights, biases):
         z = h @ W.T + b
         zs.append(z)
         if l < L - 1:
-            h = bf16(np.maximum(z, 0.0))
+            r = np.maximum(z, 0.0)
+            h = bf16(r)
+            amb |= np.any(bf16(r * (1 + amb_tol)) != bf16(r * (1 - amb_tol)), axis=1)
             hs.append(h)
-    return dict(x=x, hs=hs, zs=zs, logits=zs[-1])
+    return dict(x=x, hs=hs, zs=zs, logits=zs[-1], ambiguous=amb)
 
 
 def softmax(z):

@@ -41,12 +41,39 @@ def _region(states, cam):
     return min(xs0), min(ys0), max(xs1) - min(xs0) + 1, max(ys1) - min(ys0) + 1
 
 
-def _loss_state(proj_v, g, state, cam, opts, channels, Gv, region):
-    pv = proj_v.copy()
-    pv[g] = state
+class _Local:
+    """The Gaussians whose pixel boxes intersect a margin around Gaussian g,
+    kept in id order (so depth ties resolve exactly as over the full set).
+    Any region inside the margin renders identically from this subset."""
+
+    def __init__(self, proj_v, g, cam, channels, margin=24):
+        p = proj_v[g]
+        self.x0 = max(0, int(p["x0"]) - margin)
+        self.y0 = max(0, int(p["y0"]) - margin)
+        self.x1 = min(cam.width - 1, int(p["x1"]) + margin)
+        self.y1 = min(cam.height - 1, int(p["y1"]) + margin)
+        v = proj_v["valid"] == 1
+        hit = v & (proj_v["x1"] >= self.x0) & (proj_v["x0"] <= self.x1) & \
+            (proj_v["y1"] >= self.y0) & (proj_v["y0"] <= self.y1)
+        hit[g] = True
+        self.idx = np.nonzero(hit)[0]
+        self.k = int(np.searchsorted(self.idx, g))
+        self.proj = np.ascontiguousarray(proj_v[self.idx])
+        self.channels = np.ascontiguousarray(np.asarray(channels, np.float64)[self.idx])
+
+    def covers(self, region):
+        x0, y0, w, h = region
+        return x0 >= self.x0 and y0 >= self.y0 and x0 + w - 1 <= self.x1 and y0 + h - 1 <= self.y1
+
+
+def _loss_state(local, state, cam, opts, Gv, region, channels=None):
+    pv = local.proj.copy()
+    pv[local.k] = state
     x0, y0, w, h = region
+    assert local.covers(region)
     Gr = Gv.reshape(Gv.shape[0], cam.height, cam.width)[:, y0:y0 + h, x0:x0 + w]
-    r = O.render_region(pv, cam, opts, channels, x0, y0, w, h, np.ascontiguousarray(Gr))
+    ch = local.channels if channels is None else channels
+    r = O.render_region(pv, cam, opts, ch, x0, y0, w, h, np.ascontiguousarray(Gr))
     return r["loss"], r["hash"]
 
 
@@ -62,6 +89,8 @@ def fd_gaussian(params: O.Params, channels, cams, opts, proj, G_flat, g,
         Gvs.append(G_flat[off:off + C * hw].reshape(C, hw))
         off += C * hw
     res = {}
+    locals_ = [(_Local(proj[v], g, cam, channels) if proj[v][g]["valid"] else None)
+               for v, cam in enumerate(cams)]
     steps = (2.0, 1.0, -1.0, -2.0)
     coef = (-1.0, 8.0, -8.0, 1.0)
     for group, k in GROUPS:
@@ -75,20 +104,24 @@ def fd_gaussian(params: O.Params, channels, cams, opts, proj, G_flat, g,
                 total = 0.0
                 valid = True
                 for v, cam in enumerate(cams):
-                    pp = params.copy()
-                    pa = _param_array(pp, group).reshape(params.n, -1)
+                    pp = O.Params(params.mean[g:g + 1], params.log_scale[g:g + 1],
+                                  params.quat[g:g + 1], params.omega[g:g + 1]).copy()
+                    pa = _param_array(pp, group).reshape(1, -1)
                     states = []
                     for st in steps:
-                        pa[g, comp] = theta + st * h
-                        states.append(_project_single(pp, g, cam, opts))
+                        pa[0, comp] = theta + st * h
+                        states.append(_project_single(pp, 0, cam, opts))
                     s0 = proj[v][g]
                     reg = _region([s0] + states, cam)
                     if reg is None:
                         continue
-                    _, h0 = _loss_state(proj[v], g, s0, cam, opts, channels, Gvs[v], reg)
+                    loc = locals_[v]
+                    if loc is None or not loc.covers(reg):
+                        loc = _Local(proj[v], g, cam, channels, margin=10 ** 6)
+                    _, h0 = _loss_state(loc, s0, cam, opts, Gvs[v], reg)
                     acc = 0.0
                     for st, cf, sx in zip(steps, coef, states):
-                        l, hx = _loss_state(proj[v], g, sx, cam, opts, channels, Gvs[v], reg)
+                        l, hx = _loss_state(loc, sx, cam, opts, Gvs[v], reg)
                         if hx != h0:
                             valid = False
                             break
@@ -113,11 +146,12 @@ def fd_gaussian(params: O.Params, channels, cams, opts, proj, G_flat, g,
             reg = _region([s0], cam)
             if reg is None:
                 continue
-            chp = np.array(channels, np.float64)
-            chp[g, comp] = theta + h
-            lp, _ = _loss_state(proj[v], g, s0, cam, opts, chp, Gvs[v], reg)
-            chp[g, comp] = theta - h
-            lm, _ = _loss_state(proj[v], g, s0, cam, opts, chp, Gvs[v], reg)
+            loc = locals_[v]
+            chp = loc.channels.copy()
+            chp[loc.k, comp] = theta + h
+            lp, _ = _loss_state(loc, s0, cam, opts, Gvs[v], reg, chp)
+            chp[loc.k, comp] = theta - h
+            lm, _ = _loss_state(loc, s0, cam, opts, Gvs[v], reg, chp)
             total += (lp - lm) / (2.0 * h)
         vals[comp] = total
     res["channels"] = (vals, np.ones(C, bool))

@@ -290,10 +290,7 @@ static void blend_pixel(int i, int j, const uint32_t *list, int64_t len, const o
     for (int64_t k = 0; k < len; ++k) {
         const uint32_t g = list[k];
         const oproj_t *p = P + g;
-        if (!p->valid || i < p->x0 || i > p->x1 || j < p->y0 || j > p->y1) {
-            if (hash) *hash = fnv(fnv(*hash, g), DEC_BOX);
-            continue;
-        }
+        if (!p->valid || i < p->x0 || i > p->x1 || j < p->y0 || j > p->y1) continue;
         const double dx = p->mx - px, dy = p->my - py;
         double power = -0.5 * (p->A * dx * dx + p->C * dy * dy) - p->B * dx * dy;
         if (power > 0.0) power = 0.0;
@@ -398,8 +395,11 @@ static int cmp_cand(const void *x, const void *y)
 
 /* Render the rectangle [x0, x0+w) x [y0, y0+h) directly from the definition:
  * for each pixel, every valid Gaussian whose pixel box contains it, ordered by
- * (depth32 bits, id). Returns sum(G * out) when G != NULL, and a hash of every
- * box / skip / blend / clamp / stop decision. */
+ * (depth32 bits, id). Candidates are those whose box meets the rectangle; each
+ * 8x8 cell of the rectangle keeps, in that order, the candidates whose box
+ * meets the cell (a superset of every pixel's list there, in the same order,
+ * so the result equals a scan over all candidates). Returns sum(G * out) when
+ * G != NULL, and a hash of every skip / blend / clamp / stop decision. */
 double oracle_render_region(int64_t n, const oproj_t *pv, const ocam_t *cam, const oopts_t *o,
                             const double *ch, int32_t C, int32_t x0, int32_t y0, int32_t w,
                             int32_t h, const double *G, double *out, double *T_out,
@@ -422,27 +422,60 @@ double oracle_render_region(int64_t n, const oproj_t *pv, const ocam_t *cam, con
         }
     }
     qsort(cand, (size_t)m, sizeof(ocand_t), cmp_cand);
-    uint32_t *list = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(m > 0 ? m : 1));
-    for (int64_t k = 0; k < m; ++k) list[k] = cand[k].id;
+    /* per-cell candidate lists (CSR) */
+    const int cw = (w + 7) / 8, chh = (h + 7) / 8, ncell = cw * chh;
+    int64_t *cstart = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    for (int64_t k = 0; k < m; ++k) {
+        const oproj_t *p = pv + cand[k].id;
+        const int cx0 = (p->x0 > x0 ? p->x0 - x0 : 0) / 8, cx1 = (p->x1 - x0 < w - 1 ? p->x1 - x0 : w - 1) / 8;
+        const int cy0 = (p->y0 > y0 ? p->y0 - y0 : 0) / 8, cy1 = (p->y1 - y0 < h - 1 ? p->y1 - y0 : h - 1) / 8;
+        for (int cy = cy0; cy <= cy1; ++cy)
+            for (int cx = cx0; cx <= cx1; ++cx) cstart[cy * cw + cx + 1]++;
+    }
+    for (int c = 0; c < ncell; ++c) cstart[c + 1] += cstart[c];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ncell > 0 ? ncell : 1));
+    for (int c = 0; c < ncell; ++c) fill[c] = cstart[c];
+    uint32_t *lists = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(cstart[ncell] > 0 ? cstart[ncell] : 1));
+    for (int64_t k = 0; k < m; ++k) {
+        const oproj_t *p = pv + cand[k].id;
+        const int cx0 = (p->x0 > x0 ? p->x0 - x0 : 0) / 8, cx1 = (p->x1 - x0 < w - 1 ? p->x1 - x0 : w - 1) / 8;
+        const int cy0 = (p->y0 > y0 ? p->y0 - y0 : 0) / 8, cy1 = (p->y1 - y0 < h - 1 ? p->y1 - y0 : h - 1) / 8;
+        for (int cy = cy0; cy <= cy1; ++cy)
+            for (int cx = cx0; cx <= cx1; ++cx) lists[fill[cy * cw + cx]++] = cand[k].id;
+    }
     free(cand);
+    free(fill);
+    const int64_t hw = (int64_t)w * h;
+    uint64_t *phash = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(hw > 0 ? hw : 1));
+    double *ploss = (double *)malloc(sizeof(double) * (size_t)(hw > 0 ? hw : 1));
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t q = 0; q < hw; ++q) {
+        const int32_t jj = (int32_t)(q / w), ii = (int32_t)(q % w);
+        const int cell = (jj / 8) * cw + ii / 8;
+        double acc[64];
+        double T; int64_t l;
+        uint64_t hh = 1469598103934665603ULL;
+        blend_pixel(x0 + ii, y0 + jj, lists + cstart[cell], cstart[cell + 1] - cstart[cell], pv, ch,
+                    C, o, 0u, acc, &T, &l, NULL, NULL, NULL, NULL, &hh);
+        double lq = 0.0;
+        for (int cc = 0; cc < C; ++cc) {
+            if (out) out[(int64_t)cc * hw + q] = acc[cc];
+            if (G) lq += G[(int64_t)cc * hw + q] * acc[cc];
+        }
+        if (T_out) T_out[q] = T;
+        phash[q] = hh;
+        ploss[q] = lq;
+    }
     double loss = 0.0;
     uint64_t hash = 1469598103934665603ULL;
-    const int64_t hw = (int64_t)w * h;
-    for (int32_t jj = 0; jj < h; ++jj)
-        for (int32_t ii = 0; ii < w; ++ii) {
-            double acc[64];
-            double T; int64_t l;
-            hash = fnv(hash, ((uint64_t)(uint32_t)jj << 32) | (uint32_t)ii);
-            blend_pixel(x0 + ii, y0 + jj, list, m, pv, ch, C, o, 0u, acc, &T, &l, NULL, NULL,
-                        NULL, NULL, &hash);
-            const int64_t q = (int64_t)jj * w + ii;
-            for (int cc = 0; cc < C; ++cc) {
-                if (out) out[(int64_t)cc * hw + q] = acc[cc];
-                if (G) loss += G[(int64_t)cc * hw + q] * acc[cc];
-            }
-            if (T_out) T_out[q] = T;
-        }
-    free(list);
+    for (int64_t q = 0; q < hw; ++q) {
+        hash = fnv(hash, phash[q]);
+        loss += ploss[q];
+    }
+    free(phash);
+    free(ploss);
+    free(lists);
+    free(cstart);
     if (hash_out) *hash_out = hash;
     return loss;
 }

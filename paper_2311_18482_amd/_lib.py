@@ -47,6 +47,12 @@ class Projected(ct.Structure):
                 ("depth", ct.c_void_p), ("ntiles", ct.c_void_p), ("block_offsets", ct.c_void_p)]
 
 
+class AdamGroup(ct.Structure):
+    _fields_ = [("param", ct.c_void_p), ("grad", ct.c_void_p), ("m", ct.c_void_p),
+                ("v", ct.c_void_p), ("n", ct.c_int64), ("clamp_every", ct.c_int32),
+                ("clamp_offset", ct.c_int32), ("clamp_lo", ct.c_float), ("clamp_hi", ct.c_float)]
+
+
 class Bins(ct.Structure):
     _fields_ = [("keys", ct.c_void_p), ("keys_alt", ct.c_void_p), ("ids", ct.c_void_p),
                 ("ids_alt", ct.c_void_p), ("ranges", ct.c_void_p), ("scratch", ct.c_void_p),
@@ -78,6 +84,18 @@ _SIGS = {
                                    P, I32, ct.POINTER(Opts), P, P, P, P, P, P]),
     "legs_project_backward": (I32, [P, P, P, P, P, I64, P, I32, ct.POINTER(Opts),
                                     ct.POINTER(Projected), P, P, P, P, P, P]),
+    "legs_decode_plain": (I32, [P, P, I64, I64, I64, P, I32, P, I32, P, P, P]),
+    "legs_decode_fold": (I32, [P, P, I32, P, I32, P, P]),
+    "legs_decode_folded": (I32, [P, P, I64, I64, I64, P, I32, P, P, P]),
+    "legs_mlp_param_count": (I64, [I32]),
+    "legs_decode_mlp": (I32, [P, P, I64, I64, I64, P, I32, P, P, P]),
+    "legs_mlp_workspace_bytes": (I64, [I64, I32]),
+    "legs_mlp_grad": (I32, [P, P, I64, I64, I64, P, I32, P, P, P, P, P]),
+    "legs_adam": (I32, [P, ct.POINTER(AdamGroup), I32, I32, ct.c_float, ct.c_float, ct.c_float,
+                        ct.c_float, P]),
+    "legs_mlp_train_step": (I32, [P, P, I64, I64, I64, P, I32, P, P, P, P, I32, ct.c_float,
+                                  ct.c_float, ct.c_float, ct.c_float, P, P, P]),
+    "legs_l1_loss_grad": (I32, [P, P, P, P, I32, I64, I32, I32, ct.c_float, P, P, P]),
 }
 
 

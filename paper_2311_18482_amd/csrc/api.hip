@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include "legs_internal.h"
+#include "legs_decode_internal.h"
 
 int32_t legs_set_error(legs_ctx *ctx, int32_t code, const char *fmt, ...)
 {
@@ -254,6 +255,147 @@ int32_t legs_project_backward(legs_ctx *ctx, const float *mean, const float *log
     return legs_launch_project_backward(ctx, mean, log_scale, quat, opacity_logit, n, views_dev,
                                         n_views, opts, proj, grad2d, d_mean, d_log_scale, d_quat,
                                         d_opacity_logit, (hipStream_t)stream);
+}
+
+
+static int32_t check_feat(legs_ctx *ctx, const float *feat, int64_t P, int64_t cs, int64_t ps,
+                          int32_t K, int32_t *top1)
+{
+    if (P < 0) return legs_set_error(ctx, LEGS_ERR_ARG, "P < 0");
+    if (P > 0 && (!feat || !top1)) return legs_set_error(ctx, LEGS_ERR_ARG, "NULL feat or top1");
+    if (cs < 0 || ps < 0) return legs_set_error(ctx, LEGS_ERR_ARG, "negative stride");
+    if (K != 32 && K != 64 && K != 128) return legs_set_error(ctx, LEGS_ERR_ARG, "K must be 32, 64 or 128");
+    return LEGS_OK;
+}
+
+int32_t legs_decode_plain(legs_ctx *ctx, const float *feat, int64_t P, int64_t c_stride,
+                          int64_t p_stride, const float *proj, int32_t D, const float *codebook,
+                          int32_t K, float *probs, int32_t *top1, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    LEGS_TRY(check_feat(ctx, feat, P, c_stride, p_stride, K, top1));
+    if (!proj || !codebook) return legs_set_error(ctx, LEGS_ERR_ARG, "NULL proj or codebook");
+    if (D < 32 || D > LEGS_DECODE_MAXD || D % 32)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "D must be a multiple of 32 in [32, %d]", LEGS_DECODE_MAXD);
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_decode_plain(ctx, feat, P, c_stride, p_stride, proj, D, codebook, K, probs,
+                                    top1, (hipStream_t)stream);
+}
+
+int32_t legs_decode_fold(legs_ctx *ctx, const float *proj, int32_t D, const float *codebook,
+                         int32_t K, float *folded, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (!proj || !codebook || !folded) return legs_set_error(ctx, LEGS_ERR_ARG, "NULL argument");
+    if (D < 1 || (K != 32 && K != 64 && K != 128)) return legs_set_error(ctx, LEGS_ERR_ARG, "bad D or K");
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_decode_fold(ctx, proj, D, codebook, K, folded, (hipStream_t)stream);
+}
+
+int32_t legs_decode_folded(legs_ctx *ctx, const float *feat, int64_t P, int64_t c_stride,
+                           int64_t p_stride, const float *folded, int32_t K, float *probs,
+                           int32_t *top1, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    LEGS_TRY(check_feat(ctx, feat, P, c_stride, p_stride, K, top1));
+    if (!folded) return legs_set_error(ctx, LEGS_ERR_ARG, "NULL folded");
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_decode_folded(ctx, feat, P, c_stride, p_stride, folded, K, probs, top1,
+                                     (hipStream_t)stream);
+}
+
+int64_t legs_mlp_param_count(int32_t K)
+{
+    if (K != 32 && K != 64 && K != 128) return -1;
+    return LEGS_MLP_NPARAMS(K / 32);
+}
+
+int32_t legs_decode_mlp(legs_ctx *ctx, const float *feat, int64_t P, int64_t c_stride,
+                        int64_t p_stride, const float *params, int32_t K, float *probs,
+                        int32_t *top1, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    LEGS_TRY(check_feat(ctx, feat, P, c_stride, p_stride, K, top1));
+    if (!params) return legs_set_error(ctx, LEGS_ERR_ARG, "NULL params");
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_decode_mlp(ctx, feat, P, c_stride, p_stride, params, K, probs, top1,
+                                  (hipStream_t)stream);
+}
+
+int64_t legs_mlp_workspace_bytes(int64_t B, int32_t K)
+{
+    if (B < 0 || (K != 32 && K != 64 && K != 128)) return -1;
+    return 4 * legs_mlp_workspace_floats(B, K);
+}
+
+int32_t legs_mlp_grad(legs_ctx *ctx, const float *feat, int64_t B, int64_t c_stride,
+                      int64_t p_stride, const int32_t *labels, int32_t K, const float *params,
+                      void *workspace, float *grad, float *loss, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (B < 0 || B > (1ll << 31)) return legs_set_error(ctx, LEGS_ERR_ARG, "B out of range");
+    if (K != 32 && K != 64 && K != 128) return legs_set_error(ctx, LEGS_ERR_ARG, "K must be 32, 64 or 128");
+    if (!params || !grad || !loss || (B > 0 && (!feat || !labels || !workspace)))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "NULL argument");
+    if (c_stride < 0 || p_stride < 0) return legs_set_error(ctx, LEGS_ERR_ARG, "negative stride");
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_mlp_grad(ctx, feat, B, c_stride, p_stride, labels, K, params,
+                                static_cast<float *>(workspace), grad, loss, (hipStream_t)stream);
+}
+
+int32_t legs_adam(legs_ctx *ctx, const legs_adam_group *groups, int32_t n_groups, int32_t step,
+                  float lr, float beta1, float beta2, float eps, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (!groups || n_groups < 1 || n_groups > LEGS_ADAM_MAX_GROUPS)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "n_groups out of [1, %d]", LEGS_ADAM_MAX_GROUPS);
+    if (step < 1) return legs_set_error(ctx, LEGS_ERR_ARG, "step must be >= 1");
+    if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "bad Adam hyper-parameters");
+    for (int k = 0; k < n_groups; ++k) {
+        const legs_adam_group &g = groups[k];
+        if (g.n < 0 || (g.n > 0 && (!g.param || !g.grad || !g.m || !g.v)))
+            return legs_set_error(ctx, LEGS_ERR_ARG, "group %d incomplete", k);
+        if (g.clamp_every < 0 || (g.clamp_every > 0 && (g.clamp_offset < 0 || g.clamp_offset >= g.clamp_every)))
+            return legs_set_error(ctx, LEGS_ERR_ARG, "group %d bad clamp", k);
+    }
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_adam(ctx, groups, n_groups, step, lr, beta1, beta2, eps, (hipStream_t)stream);
+}
+
+int32_t legs_mlp_train_step(legs_ctx *ctx, const float *feat, int64_t B, int64_t c_stride,
+                            int64_t p_stride, const int32_t *labels, int32_t K, float *params,
+                            float *m, float *v, float *grad, int32_t step, float lr, float beta1,
+                            float beta2, float eps, void *workspace, float *loss, void *stream)
+{
+    LEGS_TRY(legs_mlp_grad(ctx, feat, B, c_stride, p_stride, labels, K, params, workspace, grad,
+                           loss, stream));
+    legs_adam_group g;
+    g.param = params;
+    g.grad = grad;
+    g.m = m;
+    g.v = v;
+    g.n = legs_mlp_param_count(K);
+    g.clamp_every = 0;
+    g.clamp_offset = 0;
+    g.clamp_lo = 0.f;
+    g.clamp_hi = 0.f;
+    return legs_adam(ctx, &g, 1, step, lr, beta1, beta2, eps, stream);
+}
+
+int32_t legs_l1_loss_grad(legs_ctx *ctx, const float *out, const float *target,
+                          const legs_view *views_dev, int32_t n_views, int64_t total_pixels,
+                          int32_t C, int32_t n_fit, float lambda_u, float *d_out, float *loss,
+                          void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (!out || !target || !d_out || !loss) return legs_set_error(ctx, LEGS_ERR_ARG, "NULL argument");
+    if (C < 1 || C > LEGS_MAX_CHANNELS || n_fit < 0 || n_fit > C || total_pixels < 0)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "bad sizes");
+    LEGS_TRY(check_views(ctx, views_dev, n_views));
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_l1_loss_grad(ctx, out, target, views_dev, n_views, total_pixels, C, n_fit,
+                                    lambda_u, d_out, loss, (hipStream_t)stream);
 }
 
 } // extern "C"

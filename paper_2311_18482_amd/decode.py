@@ -1,0 +1,148 @@
+"""Python face of the decoding, decoder-training, Adam and loss calls of
+liblegs.so (names of the C ABI without the `legs_` prefix). Marshalling only:
+every step runs in the HIP kernels behind include/legs.h.
+
+Feature arguments are (tensor, P, c_stride, p_stride): element (p, c) of a
+rendered compact feature is tensor[c * c_stride + p * p_stride].
+"""
+from __future__ import annotations
+
+import ctypes as ct
+
+import torch
+
+from . import _lib as L
+from .raster import Context, _p, _stream
+
+DIN = 8
+
+
+def planar_features(out, views, C, first_channel, view=None):
+    """Feature view into render_forward's planar output: returns
+    (base tensor, P, c_stride, p_stride) for one view (or for all pixels when
+    the output holds a single view)."""
+    v = 0 if view is None else view
+    W, H = views.sizes[v]
+    hw = W * H
+    off = C * views.pixel_offsets[v] + first_channel * hw
+    return out[off:], hw, hw, 1
+
+
+def rowmajor_features(feat):
+    assert feat.dim() == 2 and feat.shape[1] == DIN and feat.is_contiguous()
+    return feat, int(feat.shape[0]), 1, DIN
+
+
+def _feat_args(f):
+    t, P, cs, ps = f
+    assert t.is_cuda and t.dtype == torch.float32
+    return _p(t), int(P), int(cs), int(ps)
+
+
+def decode_plain(ctx: Context, f, proj, codebook, probs=False):
+    tp, P, cs, ps = _feat_args(f)
+    K, D = codebook.shape
+    top1 = torch.empty(max(P, 1), dtype=torch.int32, device=ctx.device)
+    pr = torch.empty((P, K), dtype=torch.float32, device=ctx.device) if probs else None
+    ctx.check(L.lib().legs_decode_plain(ctx.handle, tp, P, cs, ps, _p(proj), D, _p(codebook), K,
+                                        _p(pr), _p(top1), _stream()))
+    return top1[:P], pr
+
+
+def decode_fold(ctx: Context, proj, codebook):
+    K, D = codebook.shape
+    folded = torch.empty((K + DIN) * DIN, dtype=torch.float32, device=ctx.device)
+    ctx.check(L.lib().legs_decode_fold(ctx.handle, _p(proj), D, _p(codebook), K, _p(folded),
+                                       _stream()))
+    return folded
+
+
+def decode_folded(ctx: Context, f, folded, K, probs=False):
+    tp, P, cs, ps = _feat_args(f)
+    top1 = torch.empty(max(P, 1), dtype=torch.int32, device=ctx.device)
+    pr = torch.empty((P, K), dtype=torch.float32, device=ctx.device) if probs else None
+    ctx.check(L.lib().legs_decode_folded(ctx.handle, tp, P, cs, ps, _p(folded), K, _p(pr),
+                                         _p(top1), _stream()))
+    return top1[:P], pr
+
+
+def mlp_param_count(K):
+    return int(L.lib().legs_mlp_param_count(K))
+
+
+def mlp_pack(ws, bs):
+    """Pack [W1, W2, W3], [b1, b2, b3] (float32, W as [out][in]) in ABI order."""
+    parts = []
+    for W, b in zip(ws, bs):
+        parts += [torch.as_tensor(W, dtype=torch.float32).reshape(-1),
+                  torch.as_tensor(b, dtype=torch.float32).reshape(-1)]
+    return torch.cat(parts)
+
+
+def decode_mlp(ctx: Context, f, params, K, probs=False, top1=None):
+    tp, P, cs, ps = _feat_args(f)
+    if top1 is None:
+        top1 = torch.empty(max(P, 1), dtype=torch.int32, device=ctx.device)
+    pr = torch.empty((P, K), dtype=torch.float32, device=ctx.device) if probs else None
+    ctx.check(L.lib().legs_decode_mlp(ctx.handle, tp, P, cs, ps, _p(params), K, _p(pr), _p(top1),
+                                      _stream()))
+    return top1[:P], pr
+
+
+class MlpTrainer:
+    """Decoder parameters, Adam moments and scratch for legs_mlp_train_step."""
+
+    def __init__(self, ctx: Context, params, K, batch, lr=1e-3, betas=(0.9, 0.999), eps=1e-8):
+        self.ctx, self.K, self.lr, self.betas, self.eps = ctx, K, lr, betas, eps
+        self.params = params.to(ctx.device).contiguous().clone()
+        n = mlp_param_count(K)
+        assert self.params.numel() == n
+        self.m = torch.zeros(n, dtype=torch.float32, device=ctx.device)
+        self.v = torch.zeros(n, dtype=torch.float32, device=ctx.device)
+        self.grad = torch.zeros(n, dtype=torch.float32, device=ctx.device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=ctx.device)
+        nbytes = int(L.lib().legs_mlp_workspace_bytes(batch, K))
+        self.ws = torch.empty(max(nbytes, 4), dtype=torch.uint8, device=ctx.device)
+        self.batch = batch
+        self.step_count = 0
+
+    def grad_only(self, f, labels):
+        tp, P, cs, ps = _feat_args(f)
+        assert P <= self.batch
+        self.ctx.check(L.lib().legs_mlp_grad(self.ctx.handle, tp, P, cs, ps, _p(labels), self.K,
+                                             _p(self.params), _p(self.ws), _p(self.grad),
+                                             _p(self.loss), _stream()))
+        return self.grad, self.loss
+
+    def step(self, f, labels):
+        tp, P, cs, ps = _feat_args(f)
+        assert P <= self.batch
+        self.step_count += 1
+        self.ctx.check(L.lib().legs_mlp_train_step(
+            self.ctx.handle, tp, P, cs, ps, _p(labels), self.K, _p(self.params), _p(self.m),
+            _p(self.v), _p(self.grad), self.step_count, self.lr, self.betas[0], self.betas[1],
+            self.eps, _p(self.ws), _p(self.loss), _stream()))
+        return self.loss
+
+
+def adam(ctx: Context, groups, step, lr=1e-3, betas=(0.9, 0.999), eps=1e-8):
+    """groups: list of dicts with param, grad, m, v (float32 tensors) and
+    optional clamp=(every, offset, lo, hi)."""
+    arr = (L.AdamGroup * len(groups))()
+    for i, g in enumerate(groups):
+        ce, co, lo, hi = g.get("clamp", (0, 0, 0.0, 0.0))
+        arr[i] = L.AdamGroup(g["param"].data_ptr(), g["grad"].data_ptr(), g["m"].data_ptr(),
+                             g["v"].data_ptr(), g["param"].numel(), ce, co, lo, hi)
+    ctx.check(L.lib().legs_adam(ctx.handle, arr, len(groups), int(step), lr, betas[0], betas[1],
+                                eps, _stream()))
+
+
+def l1_loss_grad(ctx: Context, out, target, views, C, n_fit, lambda_u=1.0, d_out=None, loss=None):
+    if d_out is None:
+        d_out = torch.empty_like(out)
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float32, device=out.device)
+    ctx.check(L.lib().legs_l1_loss_grad(ctx.handle, _p(out), _p(target), _p(views.dev),
+                                        views.n_views, views.total_pixels, C, n_fit, lambda_u,
+                                        _p(d_out), _p(loss), _stream()))
+    return d_out, loss

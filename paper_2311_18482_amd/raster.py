@@ -91,7 +91,7 @@ def views_build(cams, o: L.Opts, device) -> Views:
 
 class ProjectedBuf:
     def __init__(self, n, n_views, device):
-        G = n * n_views
+        G = max(n * n_views, 1)       # never a NULL device pointer, even when empty
         nb = int(L.lib().legs_projected_blocks(n, n_views))
         self.n, self.n_views = n, n_views
         self.mean2d = torch.empty((G, 2), dtype=torch.float64, device=device)
@@ -164,13 +164,16 @@ def bin_sort(ctx: Context, proj: ProjectedBuf, views: Views, o: L.Opts,
 
 
 def render_forward(ctx: Context, proj: ProjectedBuf, bins: BinsBuf, views: Views, channels,
-                   o: L.Opts):
+                   o: L.Opts, out=None, T=None, last=None):
     assert channels.is_cuda and channels.dtype == torch.float32 and channels.is_contiguous()
     n, C = channels.shape
     device = channels.device
-    out = torch.empty(C * views.total_pixels, dtype=torch.float32, device=device)
-    T = torch.empty(views.total_pixels, dtype=torch.float32, device=device)
-    last = torch.empty(views.total_pixels, dtype=torch.int32, device=device)
+    if out is None:
+        out = torch.empty(C * views.total_pixels, dtype=torch.float32, device=device)
+    if T is None:
+        T = torch.empty(views.total_pixels, dtype=torch.float32, device=device)
+    if last is None:
+        last = torch.empty(views.total_pixels, dtype=torch.int32, device=device)
     ps, bs = proj.struct(), bins.struct()
     ctx.check(L.lib().legs_render_forward(ctx.handle, ct.byref(ps), n, ct.byref(bs), _p(views.dev),
                                           views.n_views, views.total_tiles, _p(channels), C,

@@ -1,0 +1,167 @@
+"""GPU parity of decoding, decoder training, Adam and the training-step loss
+against the FP64 oracle, through the C ABI.
+
+Plain decode: Sec. 3.3 Eq. 4 (cosine max-similarity over S); learned decode:
+Eq. 8 and the supplementary inference equation; training: Eq. 9 with Adam
+(Sec. 4); loss: per-view L1 plus the L_u regulariser of Eq. 11.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import decode as D
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2311_18482_amd import raster
+    assert torch.cuda.is_available()
+    return raster.Context(0)
+
+
+@pytest.fixture(scope="module")
+def DEC():
+    from paper_2311_18482_amd import decode
+    return decode
+
+
+def features(n, seed):
+    rng = np.random.default_rng(seed)
+    f = rng.normal(0, 1, (n, 8)).astype(np.float32)
+    f[: n // 20] *= rng.uniform(0, 0.05, (n // 20, 1)).astype(np.float32)   # near-transparent pixels
+    f[0] = 0.0
+    return f
+
+
+def check_top1(top_g, score_ref, top_ref, rel_margin):
+    s = np.sort(score_ref, axis=1)
+    gap = s[:, -1] - s[:, -2]
+    clear = gap > rel_margin * np.maximum(np.abs(s[:, -1]), 1e-30)
+    assert np.array_equal(top_g[clear], top_ref[clear]), int((top_g[clear] != top_ref[clear]).sum())
+    return int((~clear).sum())
+
+
+@pytest.mark.parametrize("K,Dm", [(128, 512), (64, 256), (32, 64)])
+def test_plain_and_folded_decode(ctx, DEC, K, Dm):
+    n = 9001                                                      # ragged final tile
+    f = features(n, 1 + K)
+    Pm = synth.projection(Dm, 8, 9)
+    Cb = synth.codebook(K, Dm, 10)
+    probs_ref, top_ref = D.decode_plain(f, Pm, Cb)
+    z = f.astype(np.float64) @ Pm.astype(np.float64).T
+    cos = (z @ Cb.astype(np.float64).T) / np.maximum(np.linalg.norm(z, axis=1, keepdims=True), 1e-300)
+    fd_ = torch.from_numpy(f).cuda()
+    Pd, Cd = torch.from_numpy(Pm).cuda(), torch.from_numpy(Cb).cuda()
+    # row-major [P][8] and planar [8][P] inputs
+    for feat in (DEC.rowmajor_features(fd_), (fd_.t().contiguous(), n, n, 1)):
+        top, pr = DEC.decode_plain(ctx, feat, Pd, Cd, probs=True)
+        torch.cuda.synchronize()
+        amb = check_top1(top.cpu().numpy(), cos, top_ref, 1e-5)
+        assert amb < n // 100
+        assert np.abs(pr.cpu().numpy() - probs_ref).max() < 1e-5
+        assert top[0].item() == 0
+    folded = DEC.decode_fold(ctx, Pd, Cd)
+    top, pr = DEC.decode_folded(ctx, DEC.rowmajor_features(fd_), folded, K, probs=True)
+    torch.cuda.synchronize()
+    check_top1(top.cpu().numpy(), cos, top_ref, 1e-5)
+    assert np.abs(pr.cpu().numpy() - probs_ref).max() < 1e-5
+
+
+@pytest.mark.parametrize("K", [128, 64, 32])
+def test_mlp_decode(ctx, DEC, K):
+    n = 5000 + 17
+    f = features(n, 20 + K)
+    ws, bs = synth.mlp_init((8, 64, 64, K), 30 + K)
+    ref = D.mlp_forward(f, ws, bs)
+    params = DEC.mlp_pack(ws, bs).cuda()
+    top, pr = DEC.decode_mlp(ctx, DEC.rowmajor_features(torch.from_numpy(f).cuda()), params, K, probs=True)
+    torch.cuda.synchronize()
+    top, pr = top.cpu().numpy(), pr.cpu().numpy()
+    p_ref = D.softmax(ref["logits"])
+    ok = ~ref["ambiguous"]
+    assert ok.mean() > 0.5, ok.mean()
+    # non-ambiguous pixels: identical bf16 activations, float32 vs float64 sums only
+    s = np.sort(ref["logits"][ok], axis=1)
+    clear = (s[:, -1] - s[:, -2]) > 1e-4 * (np.abs(s[:, -1]) + 1)
+    t_ref = np.argmax(ref["logits"], axis=1)
+    assert np.array_equal(top[ok][clear], t_ref[ok][clear])
+    assert np.abs(pr[ok] - p_ref[ok]).max() < 2e-5
+    # ambiguous pixels differ by at most a few bf16 ulps in some hidden unit
+    assert np.abs(pr[~ok] - p_ref[~ok]).max() < 2e-2
+    assert (top == t_ref).mean() > 0.995
+
+
+def test_mlp_gradient_and_train_step(ctx, DEC):
+    K, B = 128, 6000
+    f = features(B, 40)
+    rng = np.random.default_rng(41)
+    y = rng.integers(0, K, B).astype(np.int32)
+    ws, bs = synth.mlp_init((8, 64, 64, K), 42)
+    loss_ref, gW, gb = D.mlp_grads(f, y, ws, bs)
+    tr = DEC.MlpTrainer(ctx, DEC.mlp_pack(ws, bs), K, B)
+    fd_ = torch.from_numpy(f).cuda()
+    yd = torch.from_numpy(y).cuda()
+    grad, loss = tr.grad_only(DEC.rowmajor_features(fd_), yd)
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy().astype(np.float64)
+    ref = np.concatenate([np.concatenate([w.reshape(-1), b]) for w, b in zip(gW, gb)])
+    assert abs(loss.item() - loss_ref) < 1e-5 * abs(loss_ref)
+    off = 0
+    for w, b in zip(gW, gb):
+        for part in (w.reshape(-1), b):
+            seg = g[off:off + part.size]
+            assert np.linalg.norm(seg - part) <= 1e-3 * np.linalg.norm(part), off
+            off += part.size
+    assert off == g.size
+    # one full step (gradient + Adam) vs the oracle's Adam on the oracle gradient
+    p0 = DEC.mlp_pack(ws, bs).numpy().astype(np.float64)
+    tr.step(DEC.rowmajor_features(fd_), yd)
+    torch.cuda.synchronize()
+    p1_ref, _, _ = D.adam(p0, ref, np.zeros_like(p0), np.zeros_like(p0), 1)
+    p1 = tr.params.cpu().numpy().astype(np.float64)
+    # first Adam step moves each weight by ~lr * sign(g); compare the moves
+    moved = np.abs(ref) > 1e-4 * np.abs(ref).max()
+    assert np.allclose(p1[moved], p1_ref[moved], rtol=0, atol=2e-6)
+
+
+def test_adam_groups_and_clamp(ctx, DEC):
+    rng = np.random.default_rng(50)
+    sizes = [1000, 37, 4096 * 5]
+    host = [dict(p=rng.normal(0, 1, n), m=np.zeros(n), v=np.zeros(n)) for n in sizes]
+    dev = [dict(param=torch.tensor(h["p"], dtype=torch.float32).cuda(),
+                m=torch.zeros(n, dtype=torch.float32).cuda(),
+                v=torch.zeros(n, dtype=torch.float32).cuda(),
+                grad=torch.zeros(n, dtype=torch.float32).cuda()) for h, n in zip(host, sizes)]
+    dev[2]["clamp"] = (5, 4, 0.0, 1.0)             # every 5th column clamped to [0, 1]
+    for step in range(1, 5):
+        for h, d in zip(host, dev):
+            g = rng.normal(0, 1, h["p"].size).astype(np.float32)
+            d["grad"].copy_(torch.from_numpy(g))
+            h["p"], h["m"], h["v"] = D.adam(h["p"], g.astype(np.float64), h["m"], h["v"], step,
+                                            lr=1e-2)
+        host[2]["p"][4::5] = np.clip(host[2]["p"][4::5], 0.0, 1.0)
+        DEC.adam(ctx, dev, step, lr=1e-2)
+    torch.cuda.synchronize()
+    for h, d in zip(host, dev):
+        got = d["param"].cpu().numpy().astype(np.float64)
+        assert np.allclose(got, h["p"], rtol=1e-6, atol=1e-6)
+
+
+def test_l1_loss_gradient(ctx, DEC):
+    from paper_2311_18482_amd import raster as R
+    cams = [synth.camera_front(37, 21, 40.0), synth.camera_front(64, 48, 64.0)]
+    C, ds = 20, 16
+    rng = np.random.default_rng(60)
+    total = sum(C * c.width * c.height for c in cams)
+    out = rng.normal(0, 1, total).astype(np.float32)
+    tgt = synth.targets_l1(cams, C, ds, 61)
+    loss_ref, g_ref = D.l1_loss_grad(out, tgt, cams, C, ds, lambda_u=1.0)
+    views = R.views_build(cams, R.opts(), ctx.device)
+    d_out, loss = DEC.l1_loss_grad(ctx, torch.from_numpy(out).cuda(), torch.from_numpy(tgt).cuda(),
+                                   views, C, 3 + ds, 1.0)
+    torch.cuda.synchronize()
+    assert np.allclose(d_out.cpu().numpy(), g_ref, rtol=1e-6, atol=1e-12)
+    assert loss.item() == pytest.approx(loss_ref, rel=1e-5)
