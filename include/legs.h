@@ -67,6 +67,11 @@ typedef struct {
     int64_t pixel_offset; /* first pixel of this view in the concatenated planes */
 } legs_view;
 
+/* Blend kernels as one persistent launch per call (workgroups take tiles from
+ * an atomic counter in the sort scratch until every tile of every view is
+ * done) instead of one workgroup per tile. Results are identical. */
+#define LEGS_FLAG_PERSISTENT 1
+
 /* Rasteriser options. Defaults (legs_opts_default): tile 16, lds_batch 256,
  * alpha_max 0.99, alpha_min 1/255, t_min 1e-4, lowpass 0.3 px^2, z_near 0.2,
  * guard 1.3. */
@@ -76,7 +81,7 @@ typedef struct {
     float alpha_max;   /* alpha = min(alpha_max, opacity * exp(power)) */
     float alpha_min;   /* skip a Gaussian at a pixel when alpha < alpha_min */
     float t_min;       /* stop (without blending) when T * (1 - alpha) < t_min */
-    float pad0;
+    int32_t flags;     /* LEGS_FLAG_* bits */
     double lowpass;    /* added to both diagonal entries of the 2D covariance */
     double z_near;     /* cull Gaussians with camera-space z <= z_near */
     double guard;      /* Jacobian evaluated at x/z clamped to +-guard * W / (2 fx) */
@@ -277,6 +282,32 @@ int32_t legs_l1_loss_grad(legs_ctx *ctx, const float *out, const float *target,
                           const legs_view *views_dev, int32_t n_views, int64_t total_pixels,
                           int32_t C, int32_t n_fit, float lambda_u, float *d_out, float *loss,
                           void *stream);
+
+/* ---- runtime: graph capture and autotuning -------------------------------- */
+
+typedef struct legs_graph legs_graph;
+/* Begin capturing the work the caller enqueues on `stream` (not the legacy
+ * default stream) into a HIP graph. Every call above is capturable when
+ * legs_bin_sort runs with host_count == NULL (sizes are then read on device).
+ * Buffers referenced during capture must stay allocated while the graph lives. */
+int32_t legs_capture_begin(legs_ctx *ctx, void *stream);
+/* End the capture and instantiate the graph. */
+int32_t legs_capture_end(legs_ctx *ctx, void *stream, legs_graph **out);
+int32_t legs_graph_launch(legs_ctx *ctx, legs_graph *graph, void *stream);
+int32_t legs_graph_destroy(legs_graph *graph);
+
+/* Time one full step (project, bin/sort, forward, and when d_out != NULL the
+ * backward through legs_project_backward) for tile in {8, 16, 32} x
+ * lds_batch in {64, 128, 256}, averaged over `reps` after one warm-up, and
+ * return the fastest options in *best (other fields copied from *base).
+ * ms_table (nullable) receives the nine times, tile-major. Set-up call: it
+ * allocates and frees its own device buffers and waits on `stream`. Images are
+ * identical for every setting, so only speed depends on the choice. */
+int32_t legs_autotune(legs_ctx *ctx, const float *mean, const float *log_scale, const float *quat,
+                      const float *opacity_logit, const float *channels, int64_t n, int32_t C,
+                      const legs_camera *cams_host, int32_t n_views, const legs_opts *base,
+                      const float *d_out, int32_t reps, legs_opts *best, float *ms_table,
+                      void *stream);
 
 #ifdef __cplusplus
 }

@@ -17,6 +17,7 @@ LEGS_ERR_CAPACITY = -2
 LEGS_ERR_HIP = -3
 LEGS_ERR_UNSUPPORTED = -4
 LEGS_MAX_CHANNELS = 64
+LEGS_FLAG_PERSISTENT = 1
 
 
 class LegsError(RuntimeError):
@@ -38,7 +39,7 @@ class View(ct.Structure):
 
 class Opts(ct.Structure):
     _fields_ = [("tile", ct.c_int32), ("lds_batch", ct.c_int32), ("alpha_max", ct.c_float),
-                ("alpha_min", ct.c_float), ("t_min", ct.c_float), ("pad0", ct.c_float),
+                ("alpha_min", ct.c_float), ("t_min", ct.c_float), ("flags", ct.c_int32),
                 ("lowpass", ct.c_double), ("z_near", ct.c_double), ("guard", ct.c_double)]
 
 
@@ -96,6 +97,12 @@ _SIGS = {
     "legs_mlp_train_step": (I32, [P, P, I64, I64, I64, P, I32, P, P, P, P, I32, ct.c_float,
                                   ct.c_float, ct.c_float, ct.c_float, P, P, P]),
     "legs_l1_loss_grad": (I32, [P, P, P, P, I32, I64, I32, I32, ct.c_float, P, P, P]),
+    "legs_capture_begin": (I32, [P, P]),
+    "legs_capture_end": (I32, [P, P, ct.POINTER(P)]),
+    "legs_graph_launch": (I32, [P, P, P]),
+    "legs_graph_destroy": (I32, [P]),
+    "legs_autotune": (I32, [P, P, P, P, P, P, I64, I32, ct.POINTER(Camera), I32, ct.POINTER(Opts),
+                            P, I32, ct.POINTER(Opts), P, P]),
 }
 
 

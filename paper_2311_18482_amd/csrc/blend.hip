@@ -6,21 +6,29 @@
 // Sec. 3.4.2 renders u into R_u the same way, so all C channels are blended
 // with one set of weights alpha_k T_k.
 //
-// Work mapping: one workgroup per screen tile (TILE x TILE pixels, TILE in
-// {8, 16, 32}); each wave64 owns an 8 x 8 quadrant, one pixel per lane, so a
-// Gaussian whose box misses the quadrant is skipped by the whole wave with a
-// scalar test. The tile's depth-ordered list is staged through LDS in batches
-// (records first, then channels with consecutive lanes reading consecutive
-// channel words), and every lane reads the staged entry with broadcast LDS
-// loads. Means are staged relative to the tile origin (rounded once from
-// float64), which keeps dx, dy accurate to float32 relative precision
-// anywhere on a 4K image.
+// One workgroup per screen tile (TILE x TILE pixels, TILE in {8, 16, 32}), or
+// a persistent grid taking tiles from an atomic counter. The tile's
+// depth-ordered list is staged through LDS in batches (records first, then
+// channels with consecutive lanes reading consecutive words); every lane then
+// reads the staged entry with broadcast LDS loads.
 //
-// The backward pass replays each pixel back to front from its final
-// transmittance and last-contributor position (no per-sample state is
-// stored): the same alpha expression (same instructions, same inputs) decides
-// box and skip, T_k = T_{k+1} / (1 - alpha_k), and per-Gaussian sums are
-// reduced across the wave before one atomic per value.
+// Means are staged relative to the centre of the first pixel of each 8-pixel
+// block column / row (rounded once from float64). Those block origins do not
+// depend on the tile size, so every pixel computes the same float32 offset
+// (dx, dy) for every tile size and LDS batch size, forward and backward alike:
+// images are bit-identical across launch settings and the backward replays the
+// forward's decisions exactly. The offsets are also accurate to float32
+// relative precision anywhere on a 4K image.
+//
+// Forward: each wave64 owns an 8 x 8 quadrant, one pixel per lane; a Gaussian
+// whose box misses the quadrant is skipped by a scalar test; early exit per
+// wave (ballot) and per workgroup (__syncthreads_count).
+// Backward: each wave owns a 16 x 16 block with 4 pixels per lane (16 x 8 with
+// 2 for 17-32 channels, 8 x 8 with 1 for wider sets or 8-pixel tiles), and replays them back to front from (T_final,
+// last): T_k = T_{k+1} / (1 - alpha_k). Per Gaussian, a lane first sums its own
+// pixels in registers, then the wave sums across lanes with DPP row operations
+// and four lane reads, and one lane issues one float atomic per value: the
+// reductions and atomics per pixel drop by the pixels-per-lane factor.
 #include "legs_internal.h"
 
 namespace {
@@ -39,6 +47,7 @@ struct BlendParams {
     int C;
     int batch;
     float amax, amin, tmin;
+    uint32_t *counter;  // non-NULL: persistent launch, tiles taken from this counter
 };
 
 // The opacity-weighted Gaussian falloff at offset (dx, dy) from the mean.
@@ -56,292 +65,341 @@ __device__ __forceinline__ float falloff_alpha(float dx, float dy, float A, floa
 
 __device__ __forceinline__ int sext8(uint32_t v, int sh) { return (int)(int8_t)((v >> sh) & 0xffu); }
 
-// Stage list entries [lo, lo + nb) of a tile into LDS.
+// LDS layout of one staged batch of B entries.
 template <int TILE, int CP>
+struct Stage {
+    static constexpr int NQ = TILE / 8;  // 8-pixel block columns (rows) per tile
+    float4 *c;       // [B] (A, B, C, opacity)
+    float *ch;       // [B][CP]
+    float *qx, *qy;  // [B][NQ] mean minus the centre of the block's first pixel
+    uint32_t *box;   // [B] tile-relative box, 4 x int8
+    uint32_t *id;    // [B]
+    __device__ Stage(void *base, int B)
+    {
+        c = static_cast<float4 *>(base);
+        ch = reinterpret_cast<float *>(c + B);
+        qx = ch + (size_t)B * CP;
+        qy = qx + (size_t)B * NQ;
+        box = reinterpret_cast<uint32_t *>(qy + (size_t)B * NQ);
+        id = box + B;
+    }
+    static size_t bytes(int B) { return (size_t)B * (16 + 4 * CP + 8 * NQ + 4 + 4); }
+};
+
+template <int TILE, int CP, int NT>
 __device__ __forceinline__ void stage_batch(const BlendParams &P, int v, int tile_x0, int tile_y0,
-                                            uint32_t lo, int nb, float4 *s_g1, float4 *s_g2,
-                                            uint32_t *s_id, float *s_ch)
+                                            uint32_t lo, int nb, Stage<TILE, CP> &S)
 {
-    constexpr int NT = TILE * TILE;
+    constexpr int NQ = TILE / 8;
     const int tid = threadIdx.x;
     for (int k = tid; k < nb; k += NT) {
         const uint32_t gid = P.ids[lo + k];
         const int64_t gv = (int64_t)v * P.n + gid;
         const double2 m = P.mean2d[gv];
-        const float4 cn = P.conic[gv];
         const int4 b = P.box[gv];
-        const float mxr = (float)(m.x - ((double)tile_x0 + 0.5));
-        const float myr = (float)(m.y - ((double)tile_y0 + 0.5));
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            S.qx[k * NQ + q] = (float)(m.x - ((double)(tile_x0 + 8 * q) + 0.5));
+            S.qy[k * NQ + q] = (float)(m.y - ((double)(tile_y0 + 8 * q) + 0.5));
+        }
         const int x0 = min(max(b.x - tile_x0, -1), TILE), x1 = min(max(b.y - tile_x0, -1), TILE);
         const int y0 = min(max(b.z - tile_y0, -1), TILE), y1 = min(max(b.w - tile_y0, -1), TILE);
-        const uint32_t pk = (uint32_t)(x0 & 0xff) | ((uint32_t)(x1 & 0xff) << 8) |
-                            ((uint32_t)(y0 & 0xff) << 16) | ((uint32_t)(y1 & 0xff) << 24);
-        s_g1[k] = make_float4(mxr, myr, cn.x, cn.y);
-        s_g2[k] = make_float4(cn.z, cn.w, __uint_as_float(pk), 0.0f);
-        s_id[k] = gid;
+        S.box[k] = (uint32_t)(x0 & 0xff) | ((uint32_t)(x1 & 0xff) << 8) |
+                   ((uint32_t)(y0 & 0xff) << 16) | ((uint32_t)(y1 & 0xff) << 24);
+        S.c[k] = P.conic[gv];
+        S.id[k] = gid;
     }
     __syncthreads();
     const int C = P.C;
     for (int e = tid; e < nb * CP; e += NT) {
         const int k = e / CP, c = e - k * CP;
-        s_ch[e] = c < C ? P.ch[(int64_t)s_id[k] * C + c] : 0.0f;
+        S.ch[e] = c < C ? P.ch[(int64_t)S.id[k] * C + c] : 0.0f;
     }
     __syncthreads();
 }
 
+struct TileInfo {
+    int v, W, H, tile_x0, tile_y0;
+    int64_t pixel_offset;
+    uint32_t rs, re;
+};
+
 template <int TILE>
-__device__ __forceinline__ void lane_pixel(int &lx, int &ly, int &qx0, int &qy0)
+__device__ __forceinline__ TileInfo tile_info(const BlendParams &P, int64_t tile)
 {
-    const int w = threadIdx.x / LEGS_WAVE, l = threadIdx.x % LEGS_WAVE;
-    qx0 = (w % (TILE / 8)) * 8;
-    qy0 = (w / (TILE / 8)) * 8;
-    lx = qx0 + (l & 7);
-    ly = qy0 + (l >> 3);
+    TileInfo t;
+    t.v = legs_view_of_tile(P.views, P.n_views, tile);
+    const legs_view &vw = P.views[t.v];
+    t.W = vw.cam.width;
+    t.H = vw.cam.height;
+    const int64_t lt = tile - vw.tile_offset;
+    t.tile_x0 = (int)(lt % vw.tiles_x) * TILE;
+    t.tile_y0 = (int)(lt / vw.tiles_x) * TILE;
+    t.pixel_offset = vw.pixel_offset;
+    t.rs = P.ranges[2 * tile];
+    t.re = P.ranges[2 * tile + 1];
+    return t;
 }
+
+// Next tile of this workgroup: one tile per workgroup, or from the persistent counter.
+__device__ __forceinline__ int64_t next_tile(const BlendParams &P, int64_t prev, int64_t *s_tile)
+{
+    if (P.counter) {
+        if (threadIdx.x == 0) *s_tile = (int64_t)atomicAdd(P.counter, 1u);
+        __syncthreads();
+        const int64_t t = *s_tile;
+        __syncthreads();
+        return t;
+    }
+    return prev < 0 ? (int64_t)blockIdx.x : P.total_tiles;
+}
+
+// ---- forward ---------------------------------------------------------------------
 
 template <int TILE, int CP>
 __global__ void __launch_bounds__(TILE *TILE)
 k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
-            uint32_t *__restrict__ last, uint32_t *__restrict__ tile_counter)
+            uint32_t *__restrict__ last)
 {
+    constexpr int NT = TILE * TILE, NQ = TILE / 8;
     extern __shared__ float4 s_dyn[];
-    const int B = P.batch;
-    float4 *s_g1 = s_dyn;
-    float4 *s_g2 = s_g1 + B;
-    uint32_t *s_id = reinterpret_cast<uint32_t *>(s_g2 + B);
-    float *s_ch = reinterpret_cast<float *>(s_id + B);
+    Stage<TILE, CP> S(s_dyn, P.batch);
     __shared__ int64_t s_tile;
+    const int B = P.batch;
+    const int w = threadIdx.x / LEGS_WAVE, l = threadIdx.x % LEGS_WAVE;
+    const int qxi = w % NQ, qyi = w / NQ;            // this wave's 8 x 8 quadrant
+    const int qx0 = 8 * qxi, qy0 = 8 * qyi;
+    const int lx = qx0 + (l & 7), ly = qy0 + (l >> 3);
+    const float fx = (float)(l & 7), fy = (float)(l >> 3);
 
-    int lx, ly, qx0, qy0;
-    lane_pixel<TILE>(lx, ly, qx0, qy0);
-    const float fx = (float)lx, fy = (float)ly;
-
-    for (int64_t it = blockIdx.x;; it += gridDim.x) {
-        int64_t tile = it;
-        if (tile_counter) {
-            if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(tile_counter, 1u);
-            __syncthreads();
-            tile = s_tile;
-            __syncthreads();
-        }
-        if (tile >= P.total_tiles) break;
-        const int v = legs_view_of_tile(P.views, P.n_views, tile);
-        const legs_view &vw = P.views[v];
-        const int W = vw.cam.width, H = vw.cam.height;
-        const int64_t lt = tile - vw.tile_offset;
-        const int tile_x0 = (int)(lt % vw.tiles_x) * TILE, tile_y0 = (int)(lt / vw.tiles_x) * TILE;
-        const int px = tile_x0 + lx, py = tile_y0 + ly;
-        const bool inside = px < W && py < H;
-        const uint32_t rs = P.ranges[2 * tile], re = P.ranges[2 * tile + 1];
-
+    for (int64_t tile = next_tile(P, -1, &s_tile); tile < P.total_tiles; tile = next_tile(P, tile, &s_tile)) {
+        const TileInfo ti = tile_info<TILE>(P, tile);
+        const int px = ti.tile_x0 + lx, py = ti.tile_y0 + ly;
+        const bool inside = px < ti.W && py < ti.H;
         float acc[CP];
 #pragma unroll
         for (int c = 0; c < CP; ++c) acc[c] = 0.0f;
         float T = 1.0f;
         uint32_t lastpos = 0;
         bool done = !inside;
-
-        for (uint32_t lo = rs; lo < re; lo += (uint32_t)B) {
+        for (uint32_t lo = ti.rs; lo < ti.re; lo += (uint32_t)B) {
             if (__syncthreads_count(!done) == 0) break;
-            const int nb = (int)min((uint32_t)B, re - lo);
-            stage_batch<TILE, CP>(P, v, tile_x0, tile_y0, lo, nb, s_g1, s_g2, s_id, s_ch);
+            const int nb = (int)min((uint32_t)B, ti.re - lo);
+            stage_batch<TILE, CP, NT>(P, ti.v, ti.tile_x0, ti.tile_y0, lo, nb, S);
             for (int j = 0; j < nb; ++j) {
                 if (legs_ballot(!done) == 0) break;
-                const float4 g2 = s_g2[j];
-                const uint32_t pk = __builtin_amdgcn_readfirstlane(__float_as_uint(g2.z));
+                const uint32_t pk = __builtin_amdgcn_readfirstlane(S.box[j]);
                 const int x0 = sext8(pk, 0), x1 = sext8(pk, 8), y0 = sext8(pk, 16), y1 = sext8(pk, 24);
                 if (x1 < qx0 || x0 > qx0 + 7 || y1 < qy0 || y0 > qy0 + 7) continue;
                 if (done || lx < x0 || lx > x1 || ly < y0 || ly > y1) continue;
-                const float4 g1 = s_g1[j];
+                const float4 cn = S.c[j];
+                const float dx = S.qx[j * NQ + qxi] - fx, dy = S.qy[j * NQ + qyi] - fy;
                 float ep;
                 bool clamped;
-                const float alpha = falloff_alpha(g1.x - fx, g1.y - fy, g1.z, g1.w, g2.x, g2.y,
-                                                  P.amax, ep, clamped);
+                const float alpha = falloff_alpha(dx, dy, cn.x, cn.y, cn.z, cn.w, P.amax, ep, clamped);
                 if (alpha < P.amin) continue;
                 const float Tn = T * (1.0f - alpha);
                 if (Tn < P.tmin) { done = true; continue; }
                 const float wgt = alpha * T;
-                const float *cj = s_ch + j * CP;
+                const float *cj = S.ch + j * CP;
 #pragma unroll
                 for (int c = 0; c < CP; ++c) acc[c] += wgt * cj[c];
                 T = Tn;
-                lastpos = (lo - rs) + (uint32_t)j + 1u;
+                lastpos = (lo - ti.rs) + (uint32_t)j + 1u;
             }
         }
         if (inside) {
-            const int64_t pix = vw.pixel_offset + (int64_t)py * W + px;
-            const int64_t hw = (int64_t)W * H;
-            float *o = out + (int64_t)P.C * vw.pixel_offset + (int64_t)py * W + px;
+            const int64_t pix = ti.pixel_offset + (int64_t)py * ti.W + px;
+            const int64_t hw = (int64_t)ti.W * ti.H;
+            float *o = out + (int64_t)P.C * ti.pixel_offset + (int64_t)py * ti.W + px;
 #pragma unroll
             for (int c = 0; c < CP; ++c)
                 if (c < P.C) o[c * hw] = acc[c];
             Tf[pix] = T;
             last[pix] = lastpos;
         }
-        if (!tile_counter && it + gridDim.x >= P.total_tiles) break;
     }
 }
 
+// ---- backward ----------------------------------------------------------------------
+
+// Sum over the 64 lanes, returned in every lane (wave-uniform): DPP butterflies
+// within each row of 16 lanes, then the four row sums read into scalars.
 __device__ __forceinline__ float wave_sum(float x)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, LEGS_WAVE);
-    return x;
+    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x4E, 0xF, 0xF, false));
+    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x141, 0xF, 0xF, false));
+    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x140, 0xF, 0xF, false));
+    const int xi = __builtin_bit_cast(int, x);
+    return (__builtin_bit_cast(float, __builtin_amdgcn_readlane(xi, 0)) +
+            __builtin_bit_cast(float, __builtin_amdgcn_readlane(xi, 16))) +
+           (__builtin_bit_cast(float, __builtin_amdgcn_readlane(xi, 32)) +
+            __builtin_bit_cast(float, __builtin_amdgcn_readlane(xi, 48)));
 }
 
+// Per-wave block of the backward: SW x SH pixels, PPL = SW * SH / 64 per lane.
+template <int TILE, int CP> struct BwdShape {
+    static constexpr int SW = (TILE == 8 || CP > 32) ? 8 : 16;
+    static constexpr int SH = (TILE == 8 || CP > 32) ? 8 : (CP <= 16 ? 16 : 8);
+    static constexpr int PPL = SW * SH / LEGS_WAVE;
+    static constexpr int NT = TILE * TILE / PPL;
+    static constexpr int ROWSTEP = LEGS_WAVE / SW;
+};
+
 template <int TILE, int CP>
-__global__ void __launch_bounds__(TILE *TILE)
+__global__ void __launch_bounds__((BwdShape<TILE, CP>::NT))
 k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restrict__ last,
-            const float *__restrict__ d_out, float *__restrict__ grad2d,
-            float *__restrict__ d_ch, uint32_t *__restrict__ tile_counter)
+            const float *__restrict__ d_out, float *__restrict__ grad2d, float *__restrict__ d_ch)
 {
+    using Shp = BwdShape<TILE, CP>;
+    constexpr int NT = Shp::NT, PPL = Shp::PPL, NQ = TILE / 8;
     extern __shared__ float4 s_dyn[];
-    const int B = P.batch;
-    float4 *s_g1 = s_dyn;
-    float4 *s_g2 = s_g1 + B;
-    uint32_t *s_id = reinterpret_cast<uint32_t *>(s_g2 + B);
-    float *s_ch = reinterpret_cast<float *>(s_id + B);
+    Stage<TILE, CP> S(s_dyn, P.batch);
     __shared__ int64_t s_tile;
     __shared__ uint32_t s_maxlast;
+    const int B = P.batch;
+    const int w = threadIdx.x / LEGS_WAVE, l = threadIdx.x % LEGS_WAVE;
+    constexpr int BX = TILE / Shp::SW;                 // wave blocks per tile row
+    const int bx0 = (w % BX) * Shp::SW, by0 = (w / BX) * Shp::SH;
+    const int lx = bx0 + (l % Shp::SW);
+    const int ly0 = by0 + (l / Shp::SW);               // pixel p of this lane: row ly0 + ROWSTEP p
+    const float fx = (float)(lx & 7);
+    const int qxi = lx >> 3;
 
-    int lx, ly, qx0, qy0;
-    lane_pixel<TILE>(lx, ly, qx0, qy0);
-    const float fx = (float)lx, fy = (float)ly;
-    const int lane = legs_lane();
-
-    for (int64_t it = blockIdx.x;; it += gridDim.x) {
-        int64_t tile = it;
-        if (tile_counter) {
-            if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(tile_counter, 1u);
-            __syncthreads();
-            tile = s_tile;
-            __syncthreads();
+    for (int64_t tile = next_tile(P, -1, &s_tile); tile < P.total_tiles; tile = next_tile(P, tile, &s_tile)) {
+        const TileInfo ti = tile_info<TILE>(P, tile);
+        const int64_t hw = (int64_t)ti.W * ti.H;
+        float G[PPL][CP], Bs[PPL][CP], T[PPL];
+        uint32_t L[PPL];
+        uint32_t myL = 0;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            const int px = ti.tile_x0 + lx, py = ti.tile_y0 + ly0 + Shp::ROWSTEP * p;
+            T[p] = 1.0f;
+            L[p] = 0;
+            if (px < ti.W && py < ti.H) {
+                const int64_t pix = ti.pixel_offset + (int64_t)py * ti.W + px;
+                const float *g = d_out + (int64_t)P.C * ti.pixel_offset + (int64_t)py * ti.W + px;
+#pragma unroll
+                for (int c = 0; c < CP; ++c) G[p][c] = c < P.C ? g[c * hw] : 0.0f;
+                T[p] = Tf[pix];
+                L[p] = last[pix];
+            } else {
+#pragma unroll
+                for (int c = 0; c < CP; ++c) G[p][c] = 0.0f;
+            }
+#pragma unroll
+            for (int c = 0; c < CP; ++c) Bs[p][c] = 0.0f;
+            myL = max(myL, L[p]);
         }
-        if (tile >= P.total_tiles) break;
-        const int v = legs_view_of_tile(P.views, P.n_views, tile);
-        const legs_view &vw = P.views[v];
-        const int W = vw.cam.width, H = vw.cam.height;
-        const int64_t lt = tile - vw.tile_offset;
-        const int tile_x0 = (int)(lt % vw.tiles_x) * TILE, tile_y0 = (int)(lt / vw.tiles_x) * TILE;
-        const int px = tile_x0 + lx, py = tile_y0 + ly;
-        const bool inside = px < W && py < H;
-        const uint32_t rs = P.ranges[2 * tile], re = P.ranges[2 * tile + 1];
-
-        float G[CP], Bs[CP];
-        float T = 1.0f;
-        uint32_t L = 0;
-        const int64_t hw = (int64_t)W * H;
-        if (inside) {
-            const int64_t pix = vw.pixel_offset + (int64_t)py * W + px;
-            const float *g = d_out + (int64_t)P.C * vw.pixel_offset + (int64_t)py * W + px;
-#pragma unroll
-            for (int c = 0; c < CP; ++c) G[c] = c < P.C ? g[c * hw] : 0.0f;
-            T = Tf[pix];
-            L = last[pix];
-        } else {
-#pragma unroll
-            for (int c = 0; c < CP; ++c) G[c] = 0.0f;
-        }
-#pragma unroll
-        for (int c = 0; c < CP; ++c) Bs[c] = 0.0f;
         if (threadIdx.x == 0) s_maxlast = 0;
         __syncthreads();
-        if (L) atomicMax(&s_maxlast, L);
+        if (myL) atomicMax(&s_maxlast, myL);
         __syncthreads();
-        const uint32_t maxL = min(s_maxlast, re - rs);
+        const uint32_t maxL = min(s_maxlast, ti.re - ti.rs);
 
         for (uint32_t hi = maxL; hi > 0;) {
             const uint32_t lo_rel = hi > (uint32_t)B ? hi - (uint32_t)B : 0u;
             const int nb = (int)(hi - lo_rel);
-            stage_batch<TILE, CP>(P, v, tile_x0, tile_y0, rs + lo_rel, nb, s_g1, s_g2, s_id, s_ch);
+            stage_batch<TILE, CP, NT>(P, ti.v, ti.tile_x0, ti.tile_y0, ti.rs + lo_rel, nb, S);
             for (int j = nb - 1; j >= 0; --j) {
-                const uint32_t pos = lo_rel + (uint32_t)j;  // 0-based list position
-                const float4 g2 = s_g2[j];
-                const uint32_t pk = __builtin_amdgcn_readfirstlane(__float_as_uint(g2.z));
+                const uint32_t pos = lo_rel + (uint32_t)j;   // 0-based list position
+                const uint32_t pk = __builtin_amdgcn_readfirstlane(S.box[j]);
                 const int x0 = sext8(pk, 0), x1 = sext8(pk, 8), y0 = sext8(pk, 16), y1 = sext8(pk, 24);
-                if (x1 < qx0 || x0 > qx0 + 7 || y1 < qy0 || y0 > qy0 + 7) continue;
-                bool contrib = pos < L && lx >= x0 && lx <= x1 && ly >= y0 && ly <= y1;
-                const float4 g1 = s_g1[j];
-                const float dx = g1.x - fx, dy = g1.y - fy;
-                float ep = 0.0f, alpha = 0.0f;
-                bool clamped = false;
-                if (contrib) {
-                    alpha = falloff_alpha(dx, dy, g1.z, g1.w, g2.x, g2.y, P.amax, ep, clamped);
-                    contrib = alpha >= P.amin;
-                }
-                if (legs_ballot(contrib) == 0) continue;
-                const float *cj = s_ch + j * CP;
-                float dmx = 0.f, dmy = 0.f, dA = 0.f, dB = 0.f, dC = 0.f, dop = 0.f;
-                float dch[CP];
-                if (contrib) {
-                    const float Tk = T / (1.0f - alpha);
+                if (x1 < bx0 || x0 > bx0 + Shp::SW - 1 || y1 < by0 || y0 > by0 + Shp::SH - 1) continue;
+                const float4 cn = S.c[j];
+                const float mqx = S.qx[j * NQ + qxi];
+                const float *cj = S.ch + j * CP;
+                float sdmx = 0.f, sdmy = 0.f, sdA = 0.f, sdB = 0.f, sdC = 0.f, sdop = 0.f;
+                float sch[CP];
+#pragma unroll
+                for (int c = 0; c < CP; ++c) sch[c] = 0.0f;
+                bool any = false;
+#pragma unroll
+                for (int p = 0; p < PPL; ++p) {
+                    const int ly = ly0 + Shp::ROWSTEP * p;
+                    if (!(pos < L[p] && lx >= x0 && lx <= x1 && ly >= y0 && ly <= y1)) continue;
+                    const float dx = mqx - fx, dy = S.qy[j * NQ + (ly >> 3)] - (float)(ly & 7);
+                    float ep;
+                    bool clamped;
+                    const float alpha = falloff_alpha(dx, dy, cn.x, cn.y, cn.z, cn.w, P.amax, ep, clamped);
+                    if (alpha < P.amin) continue;
+                    any = true;
+                    const float Tk = T[p] / (1.0f - alpha);
                     const float wgt = alpha * Tk;
                     float dot = 0.0f;
 #pragma unroll
                     for (int c = 0; c < CP; ++c) {
-                        dch[c] = wgt * G[c];
-                        dot += G[c] * (cj[c] - Bs[c]);
-                        Bs[c] = alpha * cj[c] + (1.0f - alpha) * Bs[c];
+                        sch[c] += wgt * G[p][c];
+                        const float d = cj[c] - Bs[p][c];
+                        dot += G[p][c] * d;
+                        Bs[p][c] += alpha * d;
                     }
                     const float dalpha = Tk * dot;
-                    T = Tk;
+                    T[p] = Tk;
                     if (!clamped) {
-                        dop = dalpha * ep;
+                        sdop += dalpha * ep;
                         const float dpow = dalpha * alpha;
-                        dA = -0.5f * dpow * dx * dx;
-                        dB = -dpow * dx * dy;
-                        dC = -0.5f * dpow * dy * dy;
-                        dmx = -dpow * (g1.z * dx + g1.w * dy);
-                        dmy = -dpow * (g1.w * dx + g2.x * dy);
+                        sdA += -0.5f * dpow * dx * dx;
+                        sdB += -dpow * dx * dy;
+                        sdC += -0.5f * dpow * dy * dy;
+                        sdmx += -dpow * (cn.x * dx + cn.y * dy);
+                        sdmy += -dpow * (cn.y * dx + cn.z * dy);
                     }
-                } else {
-#pragma unroll
-                    for (int c = 0; c < CP; ++c) dch[c] = 0.0f;
                 }
-                dmx = wave_sum(dmx); dmy = wave_sum(dmy); dA = wave_sum(dA);
-                dB = wave_sum(dB); dC = wave_sum(dC); dop = wave_sum(dop);
+                if (legs_ballot(any) == 0) continue;
+                const float r0 = wave_sum(sdmx), r1 = wave_sum(sdmy), r2 = wave_sum(sdA);
+                const float r3 = wave_sum(sdB), r4 = wave_sum(sdC), r5 = wave_sum(sdop);
+                float rc[CP];
 #pragma unroll
-                for (int c = 0; c < CP; ++c) dch[c] = wave_sum(dch[c]);
-                if (lane == 0) {
-                    const uint32_t gid = s_id[j];
-                    float *g2d = grad2d + 8 * ((int64_t)v * P.n + gid);
-                    atomicAdd(g2d + 0, dmx);
-                    atomicAdd(g2d + 1, dmy);
-                    atomicAdd(g2d + 2, dA);
-                    atomicAdd(g2d + 3, dB);
-                    atomicAdd(g2d + 4, dC);
-                    atomicAdd(g2d + 5, dop);
+                for (int c = 0; c < CP; ++c) rc[c] = wave_sum(sch[c]);
+                if (l == 0) {
+                    const uint32_t gid = S.id[j];
+                    float *g2d = grad2d + 8 * ((int64_t)ti.v * P.n + gid);
+                    if (r0 != 0.f) atomicAdd(g2d + 0, r0);
+                    if (r1 != 0.f) atomicAdd(g2d + 1, r1);
+                    if (r2 != 0.f) atomicAdd(g2d + 2, r2);
+                    if (r3 != 0.f) atomicAdd(g2d + 3, r3);
+                    if (r4 != 0.f) atomicAdd(g2d + 4, r4);
+                    if (r5 != 0.f) atomicAdd(g2d + 5, r5);
                     float *dc = d_ch + (int64_t)gid * P.C;
 #pragma unroll
                     for (int c = 0; c < CP; ++c)
-                        if (c < P.C) atomicAdd(dc + c, dch[c]);
+                        if (c < P.C && rc[c] != 0.f) atomicAdd(dc + c, rc[c]);
                 }
             }
             hi = lo_rel;
             __syncthreads();
         }
-        if (!tile_counter && it + gridDim.x >= P.total_tiles) break;
     }
 }
 
-template <int TILE, int CP>
-size_t lds_bytes(int batch) { return (size_t)batch * (16 + 16 + 4 + 4 * CP); }
+__global__ void k_zero_counter(uint32_t *c) { *c = 0u; }
 
 template <int TILE, int CP>
 int32_t launch_tile_cp(legs_ctx *ctx, bool fwd, const BlendParams &P, float *out, float *Tf,
                        uint32_t *last, const float *cTf, const uint32_t *clast, const float *d_out,
                        float *grad2d, float *d_ch, hipStream_t s)
 {
-    const size_t lds = lds_bytes<TILE, CP>(P.batch);
+    const size_t lds = Stage<TILE, CP>::bytes(P.batch);
     if (lds > 65536) return legs_set_error(ctx, LEGS_ERR_UNSUPPORTED, "LDS batch too large for C");
-    const int64_t grid = P.total_tiles;
+    int64_t grid = P.total_tiles;
     if (grid <= 0) return LEGS_OK;
+    const int threads = fwd ? TILE * TILE : BwdShape<TILE, CP>::NT;
+    if (P.counter) {
+        // enough workgroups to fill every CU several times; each loops over tiles
+        const int64_t per_cu = threads >= 1024 ? 2 : (threads >= 256 ? 6 : 12);
+        const int64_t cap = (int64_t)ctx->num_cus * per_cu;
+        grid = grid < cap ? grid : cap;
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, P.counter);
+    }
     if (fwd) {
-        hipLaunchKernelGGL((k_blend_fwd<TILE, CP>), dim3((unsigned)grid), dim3(TILE * TILE), lds, s,
-                           P, out, Tf, last, (uint32_t *)nullptr);
+        hipLaunchKernelGGL((k_blend_fwd<TILE, CP>), dim3((unsigned)grid), dim3(threads), lds, s,
+                           P, out, Tf, last);
     } else {
-        hipLaunchKernelGGL((k_blend_bwd<TILE, CP>), dim3((unsigned)grid), dim3(TILE * TILE), lds, s,
-                           P, cTf, clast, d_out, grad2d, d_ch, (uint32_t *)nullptr);
+        hipLaunchKernelGGL((k_blend_bwd<TILE, CP>), dim3((unsigned)grid), dim3(threads), lds, s,
+                           P, cTf, clast, d_out, grad2d, d_ch);
     }
     LEGS_CHECK_LAUNCH(ctx);
     return LEGS_OK;
@@ -382,9 +440,14 @@ int32_t launch(legs_ctx *ctx, bool fwd, const BlendParams &P, float *out, float 
 
 BlendParams make_params(const legs_projected *proj, int64_t n, const legs_bins *bins,
                         const legs_view *views, int32_t n_views, int64_t total_tiles,
-                        const float *channels, int32_t C, const legs_opts *o)
+                        const float *channels, int32_t C, const legs_opts *o, int slot)
 {
     BlendParams P;
+    P.counter = nullptr;
+    if (o->flags & LEGS_FLAG_PERSISTENT) {
+        const legs_sort_layout Ls = legs_sort_layout_for(bins->capacity);
+        P.counter = reinterpret_cast<uint32_t *>(static_cast<char *>(bins->scratch) + Ls.counter_off) + slot;
+    }
     P.mean2d = reinterpret_cast<const double2 *>(proj->mean2d);
     P.conic = reinterpret_cast<const float4 *>(proj->conic);
     P.box = reinterpret_cast<const int4 *>(proj->box);
@@ -411,7 +474,8 @@ int32_t legs_launch_blend_forward(legs_ctx *ctx, const legs_projected *proj, int
                                   const legs_opts *o, float *out, float *T_final, uint32_t *last,
                                   hipStream_t s)
 {
-    const BlendParams P = make_params(proj, n, bins, views, n_views, total_tiles, channels, C, o);
+    const BlendParams P = make_params(proj, n, bins, views, n_views, total_tiles, channels, C, o,
+                                      LEGS_BLEND_COUNTER_FWD);
     return launch(ctx, true, P, out, T_final, last, nullptr, nullptr, nullptr, nullptr, nullptr,
                   o->tile, s);
 }
@@ -423,7 +487,8 @@ int32_t legs_launch_blend_backward(legs_ctx *ctx, const legs_projected *proj, in
                                    const float *d_out, float *grad2d, float *d_channels,
                                    hipStream_t s)
 {
-    const BlendParams P = make_params(proj, n, bins, views, n_views, total_tiles, channels, C, o);
+    const BlendParams P = make_params(proj, n, bins, views, n_views, total_tiles, channels, C, o,
+                                      LEGS_BLEND_COUNTER_BWD);
     return launch(ctx, false, P, nullptr, nullptr, nullptr, T_final, last, d_out, grad2d,
                   d_channels, o->tile, s);
 }

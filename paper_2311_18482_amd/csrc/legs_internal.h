@@ -85,3 +85,6 @@ legs_sort_layout legs_sort_layout_for(int64_t capacity);
 #define LEGS_SORT_ITEMS 16
 #define LEGS_SORT_PART (LEGS_SORT_THREADS * LEGS_SORT_ITEMS)
 #define LEGS_SORT_MAX_PASSES 8
+// counter slots (u32) in the sort scratch's counter block: 0..15 sort passes
+#define LEGS_BLEND_COUNTER_FWD 32
+#define LEGS_BLEND_COUNTER_BWD 33

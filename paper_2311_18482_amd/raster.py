@@ -24,10 +24,11 @@ def _stream(device=None):
 
 
 def opts(tile=16, lds_batch=256, alpha_max=0.99, alpha_min=1.0 / 255.0, t_min=1e-4,
-         lowpass=0.3, z_near=0.2, guard=1.3) -> L.Opts:
+         lowpass=0.3, z_near=0.2, guard=1.3, persistent=False) -> L.Opts:
     o = L.Opts()
     L.lib().legs_opts_default(ct.byref(o))
     o.tile, o.lds_batch = int(tile), int(lds_batch)
+    o.flags = L.LEGS_FLAG_PERSISTENT if persistent else 0
     o.alpha_max, o.alpha_min, o.t_min = alpha_max, alpha_min, t_min
     o.lowpass, o.z_near, o.guard = lowpass, z_near, guard
     return o
@@ -255,3 +256,64 @@ class RasterizeFn(torch.autograd.Function):
 
 def rasterize(mean, log_scale, quat, opacity_logit, channels, rast: Rasterizer):
     return RasterizeFn.apply(mean, log_scale, quat, opacity_logit, channels, rast)
+
+
+class Graph:
+    """A captured HIP graph (legs_capture_begin / legs_capture_end). Use as
+
+        g = Graph(ctx)
+        with torch.cuda.stream(side_stream):
+            with g.capture():
+                ...  # calls of this module, with bin_sort(sync_count=False)
+        g.launch()   # on the current stream
+    """
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        self.handle = None
+
+    class _Cap:
+        def __init__(self, g):
+            self.g = g
+
+        def __enter__(self):
+            self.g.ctx.check(L.lib().legs_capture_begin(self.g.ctx.handle, _stream()))
+            return self.g
+
+        def __exit__(self, et, ev, tb):
+            h = ct.c_void_p()
+            code = L.lib().legs_capture_end(self.g.ctx.handle, _stream(), ct.byref(h))
+            if et is None:
+                self.g.ctx.check(code)
+                self.g.handle = h
+            return False
+
+    def capture(self):
+        return Graph._Cap(self)
+
+    def launch(self):
+        self.ctx.check(L.lib().legs_graph_launch(self.ctx.handle, self.handle, _stream()))
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                L.lib().legs_graph_destroy(self.handle)
+            except Exception:
+                pass
+            self.handle = None
+
+
+def autotune(ctx: Context, mean, log_scale, quat, opacity_logit, channels, cams, base: L.Opts,
+             d_out=None, reps=3):
+    """Returns (best options, {(tile, lds_batch): ms})."""
+    n, C = channels.shape
+    carr = (L.Camera * len(cams))(*[to_camera(c) for c in cams])
+    best = L.Opts()
+    table = (ct.c_float * 9)()
+    ctx.check(L.lib().legs_autotune(ctx.handle, _p(mean), _p(log_scale), _p(quat),
+                                    _p(opacity_logit), _p(channels), n, C, carr, len(cams),
+                                    ct.byref(base), _p(d_out) if d_out is not None else None,
+                                    reps, ct.byref(best), table, _stream()))
+    times = {(t, b): float(table[3 * i + j]) for i, t in enumerate((8, 16, 32))
+             for j, b in enumerate((64, 128, 256))}
+    return best, times
