@@ -245,9 +245,10 @@ def test_autograd_function(R):
     (out * G).sum().backward()
     _, _, proj, bins, _, T2, last = run_forward(R, scene, cams, rast.o)
     grad2d, g, d_ch = run_backward(R, rast, d, proj, bins, T2, last, G.cpu().numpy())
-    for k in ("mean", "log_scale", "quat", "opacity_logit"):
-        torch.testing.assert_close(params[k].grad, g[k], rtol=1e-5, atol=1e-6)
-    torch.testing.assert_close(params["channels"].grad, d_ch, rtol=1e-5, atol=1e-6)
+    # same kernels, float atomics in a different order
+    got = {k: params[k].grad.cpu().numpy().astype(np.float64) for k in ("mean", "log_scale", "quat", "opacity_logit")}
+    got["channels"] = params["channels"].grad.cpu().numpy().astype(np.float64)
+    PT.compare_grads(got, PT.gpu_grads_to_np(g, d_ch), scene.n, tol=1e-4)
 
 
 def test_persistent_launch_matches(R):
