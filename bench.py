@@ -25,6 +25,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+FLOPS_EVAL = 16        # one alpha evaluation: offsets, quadratic form, clamp, exp, opacity, tests
 
 
 def log(msg):
@@ -146,24 +147,40 @@ def main():
     log(f"stages (median ms): {json.dumps(stage_ms)}; wall {wall:.3f}s for {args.steps} steps; "
         f"instances {n_inst}")
 
-    # dominant kernel roofline: the onesweep sort is bandwidth-bound; the blend
-    # kernels are bound by vector ALU work (see the roofline section of the design)
-    dom = max(stage_ms, key=stage_ms.get)
-    roofline = None
-    if dom in ("bin_sort", "project", "project_bwd"):
-        if dom == "bin_sort":
-            passes = int(R.L.lib().legs_sort_passes(views.total_tiles))
-            bytes_ = n_inst * (12 + 8 + 24 * passes + 8)
-        elif dom == "project":
-            bytes_ = n * views.n_views * (44 + 16 + 16 + 16 + 4 + 4)
-        else:
-            bytes_ = n * views.n_views * (44 + 32 + 44 + 4)
-        ach = bytes_ / (stage_ms[dom] * 1e-3) / 1e9
-        roofline = dict(bound="hbm", kernel=dom, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+    # Algorithmic work per stage (section "Roofline" of the design notes):
+    #  - bin_sort: bytes of emission, the onesweep passes and the ranges per instance;
+    #  - project / project_bwd: bytes read and written per (Gaussian, view);
+    #  - blend_fwd / blend_bwd: FP32 vector flops per alpha evaluation and per
+    #    blended entry, from the work counts of the lists (a statistics pass run
+    #    once, outside the timed steps).
+    ev, blended, ev_bwd, _walked = R.render_counts(rast.ctx, proj, bins, views, o)
+    passes = int(R.L.lib().legs_sort_passes(views.total_tiles))
+    G_views = n * views.n_views
+    work = {
+        "project": ("hbm", G_views * (44 + 16 + 16 + 16 + 4 + 4)),
+        "bin_sort": ("hbm", n_inst * (12 + 8 + 24 * passes + 8)),
+        "project_bwd": ("hbm", G_views * (44 + 32 + 44 + 4)),
+        "blend_fwd": ("alu", ev * FLOPS_EVAL + blended * (4 + 2 * C)),
+        "blend_bwd": ("alu", ev_bwd * FLOPS_EVAL + blended * (40 + 7 * C)),
+    }
+
+    def roof(stage):
+        bound, amount = work[stage]
+        sec = stage_ms[stage] * 1e-3
+        if bound == "hbm":
+            ach = amount / sec / 1e9
+            return dict(bound="hbm", kernel=stage, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=ach / HBM_PEAK_GBS, traffic=None)
-    else:
-        roofline = dict(bound="alu", kernel=dom, achieved=None, peak=FP32_VECTOR_PEAK_TFLOPS,
-                        unit="TFLOP/s", frac=None, traffic=None)
+        ach = amount / sec / 1e12
+        return dict(bound="alu", kernel=stage, achieved=ach, peak=FP32_VECTOR_PEAK_TFLOPS,
+                    unit="TFLOP/s", frac=ach / FP32_VECTOR_PEAK_TFLOPS, traffic=None)
+
+    dom = max(work, key=lambda s_: stage_ms[s_])
+    roofline = roof(dom)
+    roofline["other_stages"] = {s_: {k: roof(s_)[k] for k in ("bound", "achieved", "unit", "frac")}
+                                for s_ in work if s_ != dom}
+    log(f"work counts: evaluations {ev} blended {blended} bwd evaluations {ev_bwd}; "
+        f"roofline {json.dumps(roofline)}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -176,7 +193,8 @@ def main():
                data="synthetic",
                config=dict(workload=desc, n_gaussians=int(n), views=len(cams), pixels=int(px),
                            channels=int(C), tile=args.tile, lds_batch=args.lds_batch,
-                           instances=int(n_inst), stage_ms=stage_ms),
+                           instances=int(n_inst), alpha_evaluations=int(ev),
+                           blended_entries=int(blended), stage_ms=stage_ms),
                roofline=roofline, cpu_baseline=cpu)
     print(json.dumps(rec), flush=True)
 

@@ -71,6 +71,10 @@ typedef struct {
  * an atomic counter in the sort scratch until every tile of every view is
  * done) instead of one workgroup per tile. Results are identical. */
 #define LEGS_FLAG_PERSISTENT 1
+/* Bin with all 8-bit digits of the 64-bit keys sorted over the instances
+ * (6 passes at 8160 tiles) instead of sorting the G-views by depth first and
+ * the instances by their tile digits only. The lists are identical. */
+#define LEGS_FLAG_FULL_SORT 2
 
 /* Rasteriser options. Defaults (legs_opts_default): tile 16, lds_batch 256,
  * alpha_max 0.99, alpha_min 1/255, t_min 1e-4, lowpass 0.3 px^2, z_near 0.2,
@@ -98,7 +102,10 @@ typedef struct {
  *   ntiles  [G]    uint32  tiles touched by the box (0 when culled)
  *   block_offsets [2 * (legs_projected_blocks(n, n_views) + 1)] uint64 scratch:
  *                          per-block instance counts (written by legs_project),
- *                          then their exclusive scan (written by legs_bin_sort) */
+ *                          then their exclusive scan (written by legs_bin_sort)
+ *   order   legs_order_scratch_bytes(n, n_views) bytes of scratch for the depth
+ *           order of the G-views used by legs_bin_sort (NULL: the binning
+ *           falls back to sorting every key digit over the instances) */
 typedef struct {
     double *mean2d;
     float *conic;
@@ -106,6 +113,7 @@ typedef struct {
     float *depth;
     uint32_t *ntiles;
     uint64_t *block_offsets;
+    void *order;
 } legs_projected;
 
 /* Tile lists (device, caller-owned). keys/ids hold the sorted instance list on
@@ -140,6 +148,8 @@ int32_t legs_views_build(const legs_camera *cams, int32_t n_views, const legs_op
                          legs_view *out_host, int64_t *total_tiles, int64_t *total_pixels);
 /* Number of 256-entry blocks the projection uses for n Gaussians x n_views. */
 int64_t legs_projected_blocks(int64_t n, int32_t n_views);
+/* Bytes of legs_projected.order for n Gaussians x n_views. */
+int64_t legs_order_scratch_bytes(int64_t n, int32_t n_views);
 /* Bytes of legs_bins.scratch for a given instance capacity and tile count. */
 int64_t legs_sort_scratch_bytes(int64_t capacity, int64_t total_tiles);
 /* Radix passes the sort runs for total_tiles tiles (8-bit digits over the
@@ -158,9 +168,13 @@ int32_t legs_project(legs_ctx *ctx, const float *mean, const float *log_scale, c
                      const float *opacity_logit, int64_t n, const legs_view *views_dev,
                      int32_t n_views, const legs_opts *opts, legs_projected *out, void *stream);
 
-/* Tile binning: scan of the tile counts, emission of one (key, id) per
- * (tile, Gaussian) overlap, stable LSD onesweep radix sort of the keys, and
- * per-tile [start, end) ranges. If host_count != NULL the call waits for the
+/* Tile binning: one (key, id) per (tile, Gaussian) overlap, sorted by the
+ * 64-bit key (global_tile << 32) | bits(depth) with a stable LSD onesweep
+ * radix sort, and per-tile [start, end) ranges. By default the depth digits
+ * are sorted once per G-view (every instance of a Gaussian in a view shares
+ * its depth), the instances are emitted in that order and only the tile
+ * digits are sorted over the instances; LEGS_FLAG_FULL_SORT sorts every digit
+ * over the instances. Both give the same lists. If host_count != NULL the call waits for the
  * instance total, stores it in *host_count and returns LEGS_ERR_CAPACITY
  * (launching nothing further) when it exceeds bins->capacity. With
  * host_count == NULL nothing waits (graph-capturable): the lists are then
@@ -189,6 +203,17 @@ int32_t legs_render_backward(legs_ctx *ctx, const legs_projected *proj, int64_t 
                              int64_t total_tiles, const float *channels, int32_t C,
                              const legs_opts *opts, const float *T_final, const uint32_t *last,
                              const float *d_out, float *grad2d, float *d_channels, void *stream);
+
+/* Work counts of the compositing kernels for the given lists (a statistics
+ * pass for roofline reports; it replays the forward decisions). counts [4]
+ * uint64 device: alpha evaluations of the forward (entries inside a pixel's
+ * box up to and including the stop), blended entries, alpha evaluations of
+ * the backward (entries inside the box before `last`), list positions walked
+ * by a per-pixel traversal. Overwritten. */
+int32_t legs_render_counts(legs_ctx *ctx, const legs_projected *proj, int64_t n,
+                           const legs_bins *bins, const legs_view *views_dev, int32_t n_views,
+                           int64_t total_tiles, const legs_opts *opts, uint64_t *counts,
+                           void *stream);
 
 /* Chain rule from grad2d back to mean, log_scale, (unnormalised) quaternion
  * and opacity logit, summed over views; accumulates (+=) into the outputs. */

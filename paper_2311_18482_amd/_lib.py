@@ -18,6 +18,7 @@ LEGS_ERR_HIP = -3
 LEGS_ERR_UNSUPPORTED = -4
 LEGS_MAX_CHANNELS = 64
 LEGS_FLAG_PERSISTENT = 1
+LEGS_FLAG_FULL_SORT = 2
 
 
 class LegsError(RuntimeError):
@@ -45,7 +46,8 @@ class Opts(ct.Structure):
 
 class Projected(ct.Structure):
     _fields_ = [("mean2d", ct.c_void_p), ("conic", ct.c_void_p), ("box", ct.c_void_p),
-                ("depth", ct.c_void_p), ("ntiles", ct.c_void_p), ("block_offsets", ct.c_void_p)]
+                ("depth", ct.c_void_p), ("ntiles", ct.c_void_p), ("block_offsets", ct.c_void_p),
+                ("order", ct.c_void_p)]
 
 
 class AdamGroup(ct.Structure):
@@ -75,6 +77,7 @@ _SIGS = {
                                ct.POINTER(I64), ct.POINTER(I64)]),
     "legs_projected_blocks": (I64, [I64, I32]),
     "legs_sort_scratch_bytes": (I64, [I64, I64]),
+    "legs_order_scratch_bytes": (I64, [I64, I32]),
     "legs_sort_passes": (I32, [I64]),
     "legs_project": (I32, [P, P, P, P, P, I64, P, I32, ct.POINTER(Opts), ct.POINTER(Projected), P]),
     "legs_bin_sort": (I32, [P, ct.POINTER(Projected), I64, P, I32, I64, ct.POINTER(Opts),
@@ -83,6 +86,8 @@ _SIGS = {
                                   I32, ct.POINTER(Opts), P, P, P, P]),
     "legs_render_backward": (I32, [P, ct.POINTER(Projected), I64, ct.POINTER(Bins), P, I32, I64,
                                    P, I32, ct.POINTER(Opts), P, P, P, P, P, P]),
+    "legs_render_counts": (I32, [P, ct.POINTER(Projected), I64, ct.POINTER(Bins), P, I32, I64,
+                                 ct.POINTER(Opts), P, P]),
     "legs_project_backward": (I32, [P, P, P, P, P, I64, P, I32, ct.POINTER(Opts),
                                     ct.POINTER(Projected), P, P, P, P, P, P]),
     "legs_decode_plain": (I32, [P, P, I64, I64, I64, P, I32, P, I32, P, P, P]),

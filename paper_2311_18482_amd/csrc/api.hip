@@ -236,6 +236,23 @@ int32_t legs_render_backward(legs_ctx *ctx, const legs_projected *proj, int64_t 
                                       (hipStream_t)stream);
 }
 
+int32_t legs_render_counts(legs_ctx *ctx, const legs_projected *proj, int64_t n,
+                           const legs_bins *bins, const legs_view *views_dev, int32_t n_views,
+                           int64_t total_tiles, const legs_opts *opts, uint64_t *counts,
+                           void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (!proj_ok(proj) || !bins_ok(bins) || !counts)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "incomplete buffers");
+    if (total_tiles < 1 || total_tiles >= (1ll << 32))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "total_tiles out of range");
+    LEGS_TRY(check_opts(ctx, opts));
+    LEGS_TRY(check_views(ctx, views_dev, n_views));
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_blend_counts(ctx, proj, n, bins, views_dev, n_views, total_tiles, opts,
+                                    counts, (hipStream_t)stream);
+}
+
 int32_t legs_project_backward(legs_ctx *ctx, const float *mean, const float *log_scale,
                               const float *quat, const float *opacity_logit, int64_t n,
                               const legs_view *views_dev, int32_t n_views, const legs_opts *opts,

@@ -375,6 +375,61 @@ k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restr
     }
 }
 
+// ---- work counts (a statistics pass, not on the hot path) -------------------------
+
+// Replays the forward decisions of every pixel and counts the algorithmic work
+// units of the two blend kernels: counts[0] = alpha evaluations of the forward
+// (list entries inside the pixel's box up to and including the stop),
+// counts[1] = blended entries, counts[2] = alpha evaluations of the backward
+// (entries inside the box before `last`), counts[3] = list positions walked.
+template <int TILE>
+__global__ void __launch_bounds__(TILE *TILE)
+k_blend_count(BlendParams P, unsigned long long *__restrict__ counts)
+{
+    const int64_t tile = blockIdx.x;
+    const TileInfo ti = tile_info<TILE>(P, tile);
+    const int lx = threadIdx.x % TILE, ly = threadIdx.x / TILE;
+    const int px = ti.tile_x0 + lx, py = ti.tile_y0 + ly;
+    uint64_t ef = 0, bl = 0, eb = 0, walked = 0;
+    if (px < ti.W && py < ti.H) {
+        const int bx = px & ~7, by = py & ~7;
+        const float fx = (float)(px & 7), fy = (float)(py & 7);
+        float T = 1.0f;
+        uint64_t skipped_since_blend = 0;
+        for (uint32_t k = ti.rs; k < ti.re; ++k) {
+            ++walked;
+            const uint32_t gid = P.ids[k];
+            const int64_t gv = (int64_t)ti.v * P.n + gid;
+            const int4 b = P.box[gv];
+            if (px < b.x || px > b.y || py < b.z || py > b.w) continue;
+            const double2 m = P.mean2d[gv];
+            const float4 cn = P.conic[gv];
+            const float dx = (float)(m.x - ((double)bx + 0.5)) - fx;
+            const float dy = (float)(m.y - ((double)by + 0.5)) - fy;
+            float ep;
+            bool clamped;
+            const float alpha = falloff_alpha(dx, dy, cn.x, cn.y, cn.z, cn.w, P.amax, ep, clamped);
+            ++ef;
+            if (alpha < P.amin) { ++skipped_since_blend; continue; }
+            const float Tn = T * (1.0f - alpha);
+            if (Tn < P.tmin) break;
+            T = Tn;
+            ++bl;
+            eb += skipped_since_blend + 1;
+            skipped_since_blend = 0;
+        }
+    }
+    const uint64_t v[4] = {ef, bl, eb, walked};
+    for (int q = 0; q < 4; ++q) {
+        uint64_t x = v[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, LEGS_WAVE);
+        if (legs_lane() == 0 && x) atomicAdd(counts + q, (unsigned long long)x);
+    }
+}
+
+__global__ void k_zero_counts(unsigned long long *c) { c[threadIdx.x] = 0ull; }
+
 __global__ void k_zero_counter(uint32_t *c) { *c = 0u; }
 
 template <int TILE, int CP>
@@ -491,4 +546,25 @@ int32_t legs_launch_blend_backward(legs_ctx *ctx, const legs_projected *proj, in
                                       LEGS_BLEND_COUNTER_BWD);
     return launch(ctx, false, P, nullptr, nullptr, nullptr, T_final, last, d_out, grad2d,
                   d_channels, o->tile, s);
+}
+
+int32_t legs_launch_blend_counts(legs_ctx *ctx, const legs_projected *proj, int64_t n,
+                                 const legs_bins *bins, const legs_view *views, int32_t n_views,
+                                 int64_t total_tiles, const legs_opts *o, uint64_t *counts,
+                                 hipStream_t s)
+{
+    const BlendParams P = make_params(proj, n, bins, views, n_views, total_tiles, nullptr, 1, o,
+                                      LEGS_BLEND_COUNTER_FWD);
+    unsigned long long *c = reinterpret_cast<unsigned long long *>(counts);
+    hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(4), 0, s, c);
+    if (total_tiles > 0) {
+        switch (o->tile) {
+        case 8: hipLaunchKernelGGL(k_blend_count<8>, dim3((unsigned)total_tiles), dim3(64), 0, s, P, c); break;
+        case 16: hipLaunchKernelGGL(k_blend_count<16>, dim3((unsigned)total_tiles), dim3(256), 0, s, P, c); break;
+        case 32: hipLaunchKernelGGL(k_blend_count<32>, dim3((unsigned)total_tiles), dim3(1024), 0, s, P, c); break;
+        default: return legs_set_error(ctx, LEGS_ERR_ARG, "tile must be 8, 16 or 32");
+        }
+    }
+    LEGS_CHECK_LAUNCH(ctx);
+    return LEGS_OK;
 }

@@ -70,6 +70,11 @@ int32_t legs_launch_blend_backward(legs_ctx *ctx, const legs_projected *proj, in
                                    const float *d_out, float *grad2d, float *d_channels,
                                    hipStream_t s);
 
+int32_t legs_launch_blend_counts(legs_ctx *ctx, const legs_projected *proj, int64_t n,
+                                 const legs_bins *bins, const legs_view *views, int32_t n_views,
+                                 int64_t total_tiles, const legs_opts *o, uint64_t *counts,
+                                 hipStream_t s);
+
 // Sort scratch layout (bytes), shared by the sizing function and the launcher.
 struct legs_sort_layout {
     int64_t hist_off;      // uint32 [8][256] digit histograms

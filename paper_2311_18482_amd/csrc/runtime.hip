@@ -130,6 +130,7 @@ extern "C" int32_t legs_autotune(legs_ctx *ctx, const float *mean, const float *
         proj.depth = tr.alloc<float>(G);
         proj.ntiles = tr.alloc<uint32_t>(G);
         proj.block_offsets = tr.alloc<uint64_t>(2 * (nb + 1));
+        proj.order = tr.alloc<char>(legs_order_scratch_bytes(n, n_views));
         float *out = tr.alloc<float>(C * total_px), *Tf = tr.alloc<float>(total_px);
         uint32_t *last = tr.alloc<uint32_t>(total_px);
         float *g2 = tr.alloc<float>(8 * G), *dch = tr.alloc<float>(n * C);

@@ -141,31 +141,56 @@ k_emit(const int4 *__restrict__ box, const float *__restrict__ depth,
 
 // ---- digit histograms for every pass in one read -----------------------------
 
+constexpr int HIST_RUN = 16;  // keys per lane per block iteration
+
+// Digit histograms of passes [first, first + npass) in one read of the keys.
+// Loads are coalesced (lane l reads key base + 64 i + l); within each wave a
+// run of equal digits in consecutive lanes is counted with one LDS atomic by
+// its first lane (run starts from a ballot). Instance keys come in long runs
+// (every tile of one Gaussian shares its depth digits, consecutive tiles of a
+// row share the high tile digits), so hot digits no longer serialise.
 __global__ void __launch_bounds__(256)
 k_histogram(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ count,
-            int64_t capacity, int passes, uint32_t *__restrict__ hist)
+            int64_t capacity, int first, int npass, uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t s_h[LEGS_SORT_MAX_PASSES][256];
     for (int i = threadIdx.x; i < LEGS_SORT_MAX_PASSES * 256; i += 256) (&s_h[0][0])[i] = 0;
     __syncthreads();
     const uint64_t cnt = *count;
     const int64_t m = (int64_t)(cnt < (uint64_t)capacity ? cnt : (uint64_t)capacity);
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
-        const uint64_t k = keys[i];
-        for (int p = 0; p < passes; ++p) atomicAdd(&s_h[p][(k >> (8 * p)) & 255], 1u);
+    const int lane = legs_lane(), wave = threadIdx.x / LEGS_WAVE;
+    const uint64_t above = lane == 63 ? 0ull : (~0ull << (lane + 1));
+    const int64_t chunk = (int64_t)256 * HIST_RUN;
+    for (int64_t base = (int64_t)blockIdx.x * chunk; base < m; base += (int64_t)gridDim.x * chunk) {
+        const int64_t wbase = base + (int64_t)wave * LEGS_WAVE * HIST_RUN;
+        for (int i = 0; i < HIST_RUN; ++i) {
+            const int64_t idx = wbase + (int64_t)i * LEGS_WAVE + lane;
+            const bool ok = idx < m;
+            const uint64_t k = ok ? keys[idx] : 0ull;
+            for (int p = 0; p < npass; ++p) {
+                const uint32_t d = ok ? ((uint32_t)(k >> (8 * (first + p))) & 255u) : 256u;
+                const uint32_t dp = (uint32_t)__shfl_up((int)d, 1, LEGS_WAVE);
+                const uint64_t starts = legs_ballot(lane == 0 || d != dp);
+                if (ok && (lane == 0 || d != dp)) {
+                    const uint64_t nxt = starts & above;
+                    const int end = nxt ? __ffsll((unsigned long long)nxt) - 1 : LEGS_WAVE;
+                    atomicAdd(&s_h[p][d], (uint32_t)(end - lane));
+                }
+            }
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < passes * 256; i += 256) {
+    for (int i = threadIdx.x; i < npass * 256; i += 256) {
         const uint32_t c = (&s_h[0][0])[i];
-        if (c) atomicAdd(&hist[i], c);
+        if (c) atomicAdd(&hist[(first + i / 256) * 256 + (i % 256)], c);
     }
 }
 
 // Exclusive scan of each pass's 256 digit counts (one workgroup per pass).
 __global__ void __launch_bounds__(256)
-k_digit_starts(const uint32_t *__restrict__ hist, uint32_t *__restrict__ starts)
+k_digit_starts(const uint32_t *__restrict__ hist, uint32_t *__restrict__ starts, int first)
 {
-    const int p = blockIdx.x, d = threadIdx.x;
+    const int p = first + blockIdx.x, d = threadIdx.x;
     const int lane = legs_lane(), wave = d / LEGS_WAVE;
     const uint32_t x = hist[p * 256 + d];
     uint32_t incl = x;
@@ -335,6 +360,109 @@ k_onesweep(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     }
 }
 
+// ---- depth order of the G-views ---------------------------------------------------
+
+// key = (view << 32) | bits(depth) for visible G-views (culled ones sort last,
+// they emit nothing); value = G-view index. Also stores G for the sort.
+__global__ void __launch_bounds__(256)
+k_order_keys(const uint32_t *__restrict__ ntiles, const float *__restrict__ depth, int64_t n,
+             int64_t G, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+             uint64_t *__restrict__ gcount)
+{
+    const int64_t gv = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gv == 0) *gcount = (uint64_t)G;
+    if (gv >= G) return;
+    const uint64_t v = (uint64_t)(gv / n);
+    keys[gv] = ntiles[gv] ? ((v << 32) | __float_as_uint(depth[gv])) : ~0ull;
+    vals[gv] = (uint32_t)gv;
+}
+
+// Instance counts per block of 256 G-views in depth order.
+__global__ void __launch_bounds__(LEGS_PROJ_BLOCK)
+k_sorted_block_counts(const uint32_t *__restrict__ perm, const uint32_t *__restrict__ ntiles,
+                      int64_t G, uint64_t *__restrict__ block_counts)
+{
+    const int64_t pos = (int64_t)blockIdx.x * LEGS_PROJ_BLOCK + threadIdx.x;
+    uint64_t c = pos < G ? ntiles[perm[pos]] : 0u;
+#pragma unroll
+    for (int off = LEGS_WAVE / 2; off > 0; off >>= 1) c += __shfl_down(c, off, LEGS_WAVE);
+    __shared__ uint64_t s_w[LEGS_PROJ_BLOCK / LEGS_WAVE];
+    if (legs_lane() == 0) s_w[threadIdx.x / LEGS_WAVE] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < LEGS_PROJ_BLOCK / LEGS_WAVE; ++w) t += s_w[w];
+        block_counts[blockIdx.x] = t;
+    }
+}
+
+// Emission in depth order: block b owns sorted positions [256 b, 256 b + 256).
+// Same balanced scheme as k_emit; owners may belong to different views.
+__global__ void __launch_bounds__(LEGS_PROJ_BLOCK)
+k_emit_sorted(const uint32_t *__restrict__ perm, const int4 *__restrict__ box,
+              const float *__restrict__ depth, const uint32_t *__restrict__ ntiles,
+              const uint64_t *__restrict__ block_offsets, int64_t n, int64_t G,
+              const legs_view *__restrict__ views, int tile, int64_t capacity,
+              uint64_t *__restrict__ keys, uint32_t *__restrict__ ids)
+{
+    __shared__ uint32_t s_start[LEGS_PROJ_BLOCK + 1];
+    __shared__ int s_tx0[LEGS_PROJ_BLOCK], s_ty0[LEGS_PROJ_BLOCK], s_rw[LEGS_PROJ_BLOCK];
+    __shared__ int s_tilesx[LEGS_PROJ_BLOCK];
+    __shared__ int64_t s_toff[LEGS_PROJ_BLOCK];
+    __shared__ uint32_t s_bits[LEGS_PROJ_BLOCK], s_g[LEGS_PROJ_BLOCK];
+    const int64_t pos = (int64_t)blockIdx.x * LEGS_PROJ_BLOCK + threadIdx.x;
+    uint32_t cnt = 0;
+    if (pos < G) {
+        const int64_t gv = perm[pos];
+        cnt = ntiles[gv];
+        if (cnt) {
+            const int64_t v = gv / n;
+            const int4 b = box[gv];
+            s_tx0[threadIdx.x] = b.x / tile;
+            s_ty0[threadIdx.x] = b.z / tile;
+            s_rw[threadIdx.x] = b.y / tile - b.x / tile + 1;
+            s_bits[threadIdx.x] = __float_as_uint(depth[gv]);
+            s_g[threadIdx.x] = (uint32_t)(gv - v * n);
+            s_toff[threadIdx.x] = views[v].tile_offset;
+            s_tilesx[threadIdx.x] = views[v].tiles_x;
+        }
+    }
+    const int lane = legs_lane(), wave = threadIdx.x / LEGS_WAVE;
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int off = 1; off < LEGS_WAVE; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, LEGS_WAVE);
+        if (lane >= off) incl += y;
+    }
+    __shared__ uint32_t s_w[LEGS_PROJ_BLOCK / LEGS_WAVE];
+    if (lane == LEGS_WAVE - 1) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t wpre = 0;
+    for (int w = 0; w < wave; ++w) wpre += s_w[w];
+    s_start[threadIdx.x] = wpre + incl - cnt;
+    if (threadIdx.x == LEGS_PROJ_BLOCK - 1) s_start[LEGS_PROJ_BLOCK] = wpre + incl;
+    __syncthreads();
+    const uint32_t total = s_start[LEGS_PROJ_BLOCK];
+    const uint64_t base = block_offsets[blockIdx.x];
+    for (uint32_t k = threadIdx.x; k < total; k += LEGS_PROJ_BLOCK) {
+        int lo = 0, hi = LEGS_PROJ_BLOCK - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_start[mid] <= k) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t local = k - s_start[lo];
+        const int rw = s_rw[lo];
+        const int ty = s_ty0[lo] + (int)(local / (uint32_t)rw);
+        const int tx = s_tx0[lo] + (int)(local % (uint32_t)rw);
+        const uint64_t gt = (uint64_t)(s_toff[lo] + (int64_t)ty * s_tilesx[lo] + tx);
+        const uint64_t p = base + k;
+        if (p < (uint64_t)capacity) {
+            keys[p] = (gt << 32) | s_bits[lo];
+            ids[p] = s_g[lo];
+        }
+    }
+}
+
 // ---- tile ranges --------------------------------------------------------------
 
 __global__ void __launch_bounds__(256)
@@ -381,25 +509,139 @@ static int grid_for(legs_ctx *ctx, int64_t work, int per_block, int waves_per_cu
     return (int)b;
 }
 
+namespace {
+
+struct SortScratch {
+    uint32_t *hist, *starts, *counters;
+    uint64_t *status;
+    int64_t parts;
+};
+
+SortScratch sort_scratch_at(void *base, int64_t capacity)
+{
+    const legs_sort_layout L = legs_sort_layout_for(capacity);
+    char *b = static_cast<char *>(base);
+    SortScratch S;
+    S.hist = reinterpret_cast<uint32_t *>(b + L.hist_off);
+    S.starts = reinterpret_cast<uint32_t *>(b + L.start_off);
+    S.counters = reinterpret_cast<uint32_t *>(b + L.counter_off);
+    S.status = reinterpret_cast<uint64_t *>(b + L.status_off);
+    S.parts = L.parts;
+    return S;
+}
+
+// LSD onesweep passes over digits [first, last) of (key, value) pairs; the
+// input is in (k0, v0) and the buffers ping-pong, so the result ends in
+// (k0, v0) when last - first is even and in (k1, v1) otherwise.
+int32_t radix_passes(legs_ctx *ctx, const SortScratch &S, uint64_t *k0, uint32_t *v0,
+                     uint64_t *k1, uint32_t *v1, const uint64_t *count, int64_t capacity,
+                     int first, int last, hipStream_t s)
+{
+    const int np = last - first;
+    if (np <= 0) return LEGS_OK;
+    const int gclear = grid_for(ctx, S.parts * 256 * np, 256, 8);
+    hipLaunchKernelGGL(k_sort_clear, dim3(gclear), dim3(256), 0, s, S.status, S.parts, np,
+                       S.counters, S.hist, count, capacity);
+    const int ghist = grid_for(ctx, capacity, 256 * HIST_RUN, 4);
+    hipLaunchKernelGGL(k_histogram, dim3(ghist), dim3(256), 0, s, k0, count, capacity, first, np,
+                       S.hist);
+    hipLaunchKernelGGL(k_digit_starts, dim3(np), dim3(256), 0, s, S.hist, S.starts, first);
+    LEGS_CHECK_LAUNCH(ctx);
+    const int gsort = grid_for(ctx, capacity, LEGS_SORT_PART, 2);
+    uint64_t *ka = k0, *kb = k1;
+    uint32_t *va = v0, *vb = v1;
+    for (int p = first; p < last; ++p) {
+        hipLaunchKernelGGL(k_onesweep, dim3(gsort), dim3(LEGS_SORT_THREADS), 0, s, ka, va, kb, vb,
+                           count, capacity, p, S.starts,
+                           S.status + (int64_t)(p - first) * S.parts * 256, S.counters + (p - first));
+        LEGS_CHECK_LAUNCH(ctx);
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        uint32_t *tv = va; va = vb; vb = tv;
+    }
+    return LEGS_OK;
+}
+
+struct OrderLayout {
+    int64_t G, nbs;
+    int64_t k0, k1, v0, v1, bcounts, offsets, gcount, sort, total;
+};
+
+int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+OrderLayout order_layout(int64_t n, int32_t n_views)
+{
+    OrderLayout L;
+    L.G = n * (int64_t)n_views;
+    L.nbs = (L.G + LEGS_PROJ_BLOCK - 1) / LEGS_PROJ_BLOCK;
+    int64_t o = 0;
+    L.k0 = o; o = align256(o + 8 * L.G);
+    L.k1 = o; o = align256(o + 8 * L.G);
+    L.v0 = o; o = align256(o + 4 * L.G);
+    L.v1 = o; o = align256(o + 4 * L.G);
+    L.bcounts = o; o = align256(o + 8 * (L.nbs + 1));
+    L.offsets = o; o = align256(o + 8 * (L.nbs + 1));
+    L.gcount = o; o = align256(o + 8);
+    L.sort = o; o = align256(o + legs_sort_layout_for(L.G).total);
+    L.total = o;
+    return L;
+}
+
+int bits_for(int64_t count)
+{
+    int b = 0;
+    while (b < 32 && (1ll << b) < count) ++b;
+    return b;
+}
+
+} // namespace
+
+int64_t legs_order_scratch_bytes(int64_t n, int32_t n_views) { return order_layout(n, n_views).total; }
+
 int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t n,
                              const legs_view *views, int32_t n_views, int64_t total_tiles,
                              const legs_opts *o, legs_bins *bins, int64_t *host_count,
                              hipStream_t s)
 {
-    const int64_t bx = (n + LEGS_PROJ_BLOCK - 1) / LEGS_PROJ_BLOCK;
-    const int64_t nb = bx * n_views;
     const int passes = legs_sort_passes(total_tiles);
-    const legs_sort_layout L = legs_sort_layout_for(bins->capacity);
-    char *scr = static_cast<char *>(bins->scratch);
-    uint32_t *hist = reinterpret_cast<uint32_t *>(scr + L.hist_off);
-    uint32_t *starts = reinterpret_cast<uint32_t *>(scr + L.start_off);
-    uint32_t *counters = reinterpret_cast<uint32_t *>(scr + L.counter_off);
-    uint64_t *status = reinterpret_cast<uint64_t *>(scr + L.status_off);
-
-    // 1. exclusive scan of the per-block counts -> instance offsets and total
-    uint64_t *offsets = proj->block_offsets + nb + 1;
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, proj->block_offsets, offsets, nb,
-                       bins->count);
+    const SortScratch S = sort_scratch_at(bins->scratch, bins->capacity);
+    const bool full = (o->flags & LEGS_FLAG_FULL_SORT) != 0 || !proj->order;
+    uint64_t *offsets = nullptr;
+    const uint32_t *perm = nullptr;
+    int64_t nblocks = 0;
+    char *ord = static_cast<char *>(proj->order);
+    OrderLayout OL;
+    if (!full) {
+        // 1. depth order of every visible G-view: the four depth-digit passes of
+        //    the key sort, run once per Gaussian instead of once per instance
+        OL = order_layout(n, n_views);
+        uint64_t *ok0 = reinterpret_cast<uint64_t *>(ord + OL.k0), *ok1 = reinterpret_cast<uint64_t *>(ord + OL.k1);
+        uint32_t *ov0 = reinterpret_cast<uint32_t *>(ord + OL.v0), *ov1 = reinterpret_cast<uint32_t *>(ord + OL.v1);
+        uint64_t *gcount = reinterpret_cast<uint64_t *>(ord + OL.gcount);
+        if (OL.G > 0)
+            hipLaunchKernelGGL(k_order_keys, dim3((unsigned)((OL.G + 255) / 256)), dim3(256), 0, s,
+                               proj->ntiles, proj->depth, n, OL.G, ok0, ov0, gcount);
+        LEGS_CHECK_LAUNCH(ctx);
+        const int gpass = (32 + bits_for(n_views) + 7) / 8;
+        if (OL.G > 0) {
+            const int32_t r = radix_passes(ctx, sort_scratch_at(ord + OL.sort, OL.G), ok0, ov0, ok1, ov1,
+                                           gcount, OL.G, 0, gpass, s);
+            if (r != LEGS_OK) return r;
+        }
+        perm = (gpass % 2 == 0) ? ov0 : ov1;
+        nblocks = OL.nbs;
+        uint64_t *bcounts = reinterpret_cast<uint64_t *>(ord + OL.bcounts);
+        offsets = reinterpret_cast<uint64_t *>(ord + OL.offsets);
+        if (nblocks > 0)
+            hipLaunchKernelGGL(k_sorted_block_counts, dim3((unsigned)nblocks), dim3(LEGS_PROJ_BLOCK), 0, s,
+                               perm, proj->ntiles, OL.G, bcounts);
+        hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, bcounts, offsets, nblocks, bins->count);
+    } else {
+        // 1'. instance offsets in Gaussian order from the projection's block counts
+        nblocks = ((n + LEGS_PROJ_BLOCK - 1) / LEGS_PROJ_BLOCK) * n_views;
+        offsets = proj->block_offsets + nblocks + 1;
+        hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, proj->block_offsets, offsets,
+                           nblocks, bins->count);
+    }
     LEGS_CHECK_LAUNCH(ctx);
     if (host_count) {
         uint64_t tot = 0;
@@ -411,39 +653,32 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
                                   "legs_bin_sort: %lld instances exceed capacity %lld",
                                   (long long)tot, (long long)bins->capacity);
     }
-    // 2. emission: the final sorted list must land in keys/ids after `passes`
-    //    ping-pong passes, so emit into the buffer of the right parity.
-    uint64_t *k0 = (passes % 2 == 0) ? bins->keys : bins->keys_alt;
-    uint32_t *v0 = (passes % 2 == 0) ? bins->ids : bins->ids_alt;
-    uint64_t *k1 = (passes % 2 == 0) ? bins->keys_alt : bins->keys;
-    uint32_t *v1 = (passes % 2 == 0) ? bins->ids_alt : bins->ids;
+    // 2. emission; the digit passes still to run decide which ping-pong buffer
+    //    to emit into so that the sorted list ends in keys / ids
+    const int first = full ? 0 : 4;
+    const int np = passes - first;
+    uint64_t *k0 = (np % 2 == 0) ? bins->keys : bins->keys_alt;
+    uint32_t *v0 = (np % 2 == 0) ? bins->ids : bins->ids_alt;
+    uint64_t *k1 = (np % 2 == 0) ? bins->keys_alt : bins->keys;
+    uint32_t *v1 = (np % 2 == 0) ? bins->ids_alt : bins->ids;
     if (n > 0 && n_views > 0) {
-        hipLaunchKernelGGL(k_emit, dim3((unsigned)bx, (unsigned)n_views), dim3(LEGS_PROJ_BLOCK), 0, s,
-                           reinterpret_cast<const int4 *>(proj->box), proj->depth, proj->ntiles,
-                           offsets, n, views, o->tile, bins->capacity, k0, v0);
+        if (full) {
+            const int64_t bx = (n + LEGS_PROJ_BLOCK - 1) / LEGS_PROJ_BLOCK;
+            hipLaunchKernelGGL(k_emit, dim3((unsigned)bx, (unsigned)n_views), dim3(LEGS_PROJ_BLOCK), 0, s,
+                               reinterpret_cast<const int4 *>(proj->box), proj->depth, proj->ntiles,
+                               offsets, n, views, o->tile, bins->capacity, k0, v0);
+        } else {
+            hipLaunchKernelGGL(k_emit_sorted, dim3((unsigned)nblocks), dim3(LEGS_PROJ_BLOCK), 0, s,
+                               perm, reinterpret_cast<const int4 *>(proj->box), proj->depth,
+                               proj->ntiles, offsets, n, OL.G, views, o->tile, bins->capacity, k0, v0);
+        }
         LEGS_CHECK_LAUNCH(ctx);
     }
-    // 3. sort
-    const int gclear = grid_for(ctx, (int64_t)L.parts * 256 * passes, 256, 8);
-    hipLaunchKernelGGL(k_sort_clear, dim3(gclear), dim3(256), 0, s, status, L.parts, passes,
-                       counters, hist, bins->count, bins->capacity);
-    LEGS_CHECK_LAUNCH(ctx);
-    const int ghist = grid_for(ctx, bins->capacity, 256 * 16, 4);
-    hipLaunchKernelGGL(k_histogram, dim3(ghist), dim3(256), 0, s, k0, bins->count, bins->capacity,
-                       passes, hist);
-    LEGS_CHECK_LAUNCH(ctx);
-    hipLaunchKernelGGL(k_digit_starts, dim3(passes), dim3(256), 0, s, hist, starts);
-    LEGS_CHECK_LAUNCH(ctx);
-    const int gsort = grid_for(ctx, bins->capacity, LEGS_SORT_PART, 2);
-    uint64_t *ka = k0, *kb = k1;
-    uint32_t *va = v0, *vb = v1;
-    for (int p = 0; p < passes; ++p) {
-        hipLaunchKernelGGL(k_onesweep, dim3(gsort), dim3(LEGS_SORT_THREADS), 0, s, ka, va, kb, vb,
-                           bins->count, bins->capacity, p, starts,
-                           status + (int64_t)p * L.parts * 256, counters + p);
-        LEGS_CHECK_LAUNCH(ctx);
-        uint64_t *tk = ka; ka = kb; kb = tk;
-        uint32_t *tv = va; va = vb; vb = tv;
+    // 3. remaining digit passes over the instances (the tile digits, or all)
+    {
+        const int32_t r = radix_passes(ctx, S, k0, v0, k1, v1, bins->count, bins->capacity, first,
+                                       passes, s);
+        if (r != LEGS_OK) return r;
     }
     // 4. ranges (the sorted list is now in bins->keys)
     const int gfill = grid_for(ctx, 2 * total_tiles, 256, 8);

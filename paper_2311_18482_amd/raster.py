@@ -24,11 +24,11 @@ def _stream(device=None):
 
 
 def opts(tile=16, lds_batch=256, alpha_max=0.99, alpha_min=1.0 / 255.0, t_min=1e-4,
-         lowpass=0.3, z_near=0.2, guard=1.3, persistent=False) -> L.Opts:
+         lowpass=0.3, z_near=0.2, guard=1.3, persistent=False, full_sort=False) -> L.Opts:
     o = L.Opts()
     L.lib().legs_opts_default(ct.byref(o))
     o.tile, o.lds_batch = int(tile), int(lds_batch)
-    o.flags = L.LEGS_FLAG_PERSISTENT if persistent else 0
+    o.flags = (L.LEGS_FLAG_PERSISTENT if persistent else 0) | (L.LEGS_FLAG_FULL_SORT if full_sort else 0)
     o.alpha_max, o.alpha_min, o.t_min = alpha_max, alpha_min, t_min
     o.lowpass, o.z_near, o.guard = lowpass, z_near, guard
     return o
@@ -101,11 +101,13 @@ class ProjectedBuf:
         self.depth = torch.empty(G, dtype=torch.float32, device=device)
         self.ntiles = torch.empty(G, dtype=torch.int32, device=device)
         self.block_offsets = torch.empty(2 * (nb + 1), dtype=torch.int64, device=device)
+        ob = int(L.lib().legs_order_scratch_bytes(n, n_views))
+        self.order = torch.empty(max(ob, 256), dtype=torch.uint8, device=device)
 
     def struct(self):
         return L.Projected(self.mean2d.data_ptr(), self.conic.data_ptr(), self.box.data_ptr(),
                            self.depth.data_ptr(), self.ntiles.data_ptr(),
-                           self.block_offsets.data_ptr())
+                           self.block_offsets.data_ptr(), self.order.data_ptr())
 
 
 class BinsBuf:
@@ -197,6 +199,17 @@ def render_backward(ctx: Context, proj: ProjectedBuf, bins: BinsBuf, views: View
                                            _p(channels), C, ct.byref(o), _p(T), _p(last),
                                            _p(d_out), _p(grad2d), _p(d_channels), _stream()))
     return grad2d, d_channels
+
+
+def render_counts(ctx: Context, proj: ProjectedBuf, bins: BinsBuf, views: Views, o: L.Opts):
+    """(forward alpha evaluations, blended entries, backward alpha evaluations,
+    list positions walked) for these lists."""
+    counts = torch.zeros(4, dtype=torch.int64, device=proj.mean2d.device)
+    ps, bs = proj.struct(), bins.struct()
+    ctx.check(L.lib().legs_render_counts(ctx.handle, ct.byref(ps), proj.n, ct.byref(bs),
+                                         _p(views.dev), views.n_views, views.total_tiles,
+                                         ct.byref(o), _p(counts), _stream()))
+    return [int(x) for x in counts.cpu()]
 
 
 def project_backward(ctx: Context, mean, log_scale, quat, opacity_logit, views: Views, o: L.Opts,

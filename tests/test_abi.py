@@ -43,7 +43,7 @@ def test_struct_sizes_match_header(L):
     assert ct.sizeof(L.Camera) == 8 + 4 * 8 + 9 * 8 + 3 * 8
     assert ct.sizeof(L.View) == ct.sizeof(L.Camera) + 8 + 16
     assert ct.sizeof(L.Opts) == 24 + 24
-    assert ct.sizeof(L.Projected) == 6 * 8
+    assert ct.sizeof(L.Projected) == 7 * 8
     assert ct.sizeof(L.Bins) == 8 * 8
 
 

@@ -342,3 +342,88 @@ def test_autotune_returns_a_valid_setting(R):
     assert best.tile in (8, 16, 32) and best.lds_batch in (64, 128, 256)
     assert all(t > 0 for t in times.values())
     assert times[(best.tile, best.lds_batch)] == min(times.values())
+
+
+def test_depth_first_and_full_sort_lists_identical(R):
+    """Sorting the depth digits per G-view before expansion gives the same
+    instance lists as sorting all eight key digits over the instances."""
+    scene = synth.make_scene(80_000, 21, synth.VOL_CUBE, d_sem=8)
+    cams = synth.cameras_sphere(3, 121, 8.0, ((320, 240), (640, 360), (200, 150)))
+    lists = []
+    for full in (False, True):
+        for tile in (8, 16):
+            note(f"full_sort={full} tile={tile}")
+            o = R.opts(tile=tile, full_sort=full)
+            rast, d, proj, bins, out, T, last = run_forward(R, scene, cams, o)
+            n_inst = int(bins.count.item())
+            lists.append((tile, bins.keys[:n_inst].cpu().numpy(), bins.ids[:n_inst].cpu().numpy(),
+                          bins.ranges.cpu().numpy(), out.cpu().numpy()))
+            if not full and tile == 16:
+                fwd = O.forward(scene, cams, PT.oracle_opts(o))
+                PT.compare_bins(bins, fwd)
+    for a, b in zip(lists[:2], lists[2:]):
+        assert a[0] == b[0]
+        for x, y in zip(a[1:], b[1:]):
+            assert np.array_equal(x, y)
+
+
+def _expected_counts(proj_v, cam, ids, ranges, tile_offset, tile, amin, amax, tmin):
+    """Per-pixel walk of the tile lists in FP64 (numpy over the pixels of one
+    tile at a time): alpha evaluations of the forward, blended entries, alpha
+    evaluations of the backward and list positions walked."""
+    tx_n = (cam.width + tile - 1) // tile
+    ty_n = (cam.height + tile - 1) // tile
+    tot = np.zeros(4)
+    for t in range(tx_n * ty_n):
+        s, e = ranges[tile_offset + t]
+        if e <= s:
+            continue
+        g = ids[s:e].astype(np.int64)
+        p = proj_v[g]
+        x0, y0 = (t % tx_n) * tile, (t // tx_n) * tile
+        xs, ys = np.meshgrid(np.arange(x0, min(x0 + tile, cam.width)),
+                             np.arange(y0, min(y0 + tile, cam.height)))
+        px, py = xs.reshape(-1, 1), ys.reshape(-1, 1)
+        inbox = ((p["valid"] != 0) & (px >= p["x0"]) & (px <= p["x1"]) & (py >= p["y0"])
+                 & (py <= p["y1"]))
+        dx, dy = p["mx"] - (px + 0.5), p["my"] - (py + 0.5)
+        power = np.minimum(-0.5 * (p["A"] * dx * dx + p["C"] * dy * dy) - p["B"] * dx * dy, 0.0)
+        alpha = np.minimum(p["sig"] * np.exp(power), amax)
+        blend = inbox & (alpha >= amin)
+        f = np.where(blend, 1.0 - alpha, 1.0)
+        T_before = np.concatenate([np.ones((len(px), 1)), np.cumprod(f, axis=1)[:, :-1]], axis=1)
+        stop = blend & (T_before * (1.0 - alpha) < tmin)
+        L = len(g)
+        has = stop.any(axis=1)
+        k_stop = np.where(has, stop.argmax(axis=1), L)          # position of the stop (or L)
+        pos = np.arange(L)[None, :]
+        before_stop = pos < k_stop[:, None]
+        blended = blend & before_stop
+        last = np.where(blended.any(axis=1), L - 1 - np.argmax(blended[:, ::-1], axis=1), -1)
+        tot[0] += (inbox & (pos <= k_stop[:, None])).sum()
+        tot[1] += blended.sum()
+        tot[2] += (inbox & (pos <= last[:, None])).sum()
+        tot[3] += np.minimum(k_stop + 1, L).sum()
+    return tot
+
+
+def test_render_counts_match_a_per_pixel_walk(R):
+    """The work counts behind the blend kernels' ALU roofline equal a plain
+    per-pixel walk of the same lists (FP64; up to the rare decisions that FP32
+    and FP64 take differently)."""
+    scene = synth.make_scene(20_000, 31, synth.VOL_C1, d_sem=8)
+    cams = [synth.camera_front(256, 192, 240.0), synth.camera_front(200, 150, 190.0)]
+    for tile in (8, 16):
+        note(f"render_counts tile={tile}")
+        o = R.opts(tile=tile)
+        rast, d, proj, bins, out, T, last = run_forward(R, scene, cams, o)
+        counts = R.render_counts(rast.ctx, proj, bins, rast.views, o)
+        fwd = O.forward(scene, cams, PT.oracle_opts(o))
+        exp = np.zeros(4)
+        for v, cam in enumerate(cams):
+            exp += _expected_counts(fwd["proj"][v], cam, fwd["ids"], fwd["ranges"],
+                                    fwd["offsets"][v], tile, o.alpha_min, o.alpha_max, o.t_min)
+        note(f"counts {counts} expected {exp.tolist()}")
+        assert exp[1] > 0 and exp[0] >= exp[2] >= exp[1]
+        for c, x in zip(counts, exp):
+            assert abs(c - x) <= 1e-4 * x + 2, (counts, exp)
