@@ -48,6 +48,30 @@ def workload(name):
     return scene, cams, desc
 
 
+# kernel of each stage and the source file it is built from
+STAGE_KERNEL = {"blend_bwd": ("k_blend_bwd", "blend.hip"), "blend_fwd": ("k_blend_fwd", "blend.hip"),
+                "project": ("k_project", "project.hip"), "project_bwd": ("k_project_backward", "project.hip")}
+
+
+def measured_traffic(stage, args):
+    """HBM bytes per launch of the stage's kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known
+    size), or None when there is none for this workload or the kernel's source
+    has changed since the counters were taken."""
+    import hashlib
+    if stage not in STAGE_KERNEL:
+        return None
+    kernel, src = STAGE_KERNEL[stage]
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{args.workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2311_18482_amd", "csrc", src), "rb").read()).hexdigest()
+    if rec.get("source_sha256") != sha or rec.get("tile") != args.tile or rec.get("lds_batch") != args.lds_batch:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def cpu_baseline(scene, cams, tile, budget_s=30.0):
     """The FP64 oracle as it stands, on this host's cores: one full forward +
     backward of the same workload (projection, lists, blending, backward)."""
@@ -73,6 +97,9 @@ def main():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--lds-batch", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run one plain 1 GiB elementwise copy (torch.neg), "
+                         "the reference dispatch that scales FETCH_SIZE / WRITE_SIZE to bytes")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -177,10 +204,20 @@ def main():
 
     dom = max(work, key=lambda s_: stage_ms[s_])
     roofline = roof(dom)
+    roofline["traffic"] = measured_traffic(dom, args)
     roofline["other_stages"] = {s_: {k: roof(s_)[k] for k in ("bound", "achieved", "unit", "frac")}
                                 for s_ in work if s_ != dom}
     log(f"work counts: evaluations {ev} blended {blended} bwd evaluations {ev_bwd}; "
         f"roofline {json.dumps(roofline)}")
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)          # one elementwise dispatch: 1 GiB read, 1 GiB written
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read, 1 GiB written (neg kernel)")
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

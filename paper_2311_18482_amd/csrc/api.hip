@@ -148,9 +148,8 @@ int64_t legs_projected_blocks(int64_t n, int32_t n_views)
 
 int64_t legs_sort_scratch_bytes(int64_t capacity, int64_t total_tiles)
 {
-    (void)total_tiles;
-    if (capacity < 0) return -1;
-    return legs_sort_layout_for(capacity).total;
+    if (capacity < 0 || total_tiles < 0) return -1;
+    return legs_sort_layout_for(capacity, total_tiles).total;
 }
 
 int32_t legs_sort_passes(int64_t total_tiles)

@@ -24,12 +24,14 @@
 // whose box misses the quadrant is skipped by a scalar test; early exit per
 // wave (ballot) and per workgroup (__syncthreads_count).
 // Backward: each wave owns a 16 x 16 block with 4 pixels per lane (16 x 8 with
-// 2 for 17-32 channels, 8 x 8 with 1 for wider sets or 8-pixel tiles), and replays them back to front from (T_final,
-// last): T_k = T_{k+1} / (1 - alpha_k). Per Gaussian, a lane first sums its own
-// pixels in registers, then the wave sums across lanes with DPP row operations
-// and four lane reads, and one lane issues one float atomic per value: the
-// reductions and atomics per pixel drop by the pixels-per-lane factor.
+// 2 for 17-32 channels, 8 x 8 with 1 for wider sets or 8-pixel tiles), and
+// replays them back to front from (T_final, last): T_k = T_{k+1} / (1 - alpha_k).
+// Per Gaussian, a lane first sums its own pixels in registers, then the wave
+// sums the 6 + C values with a transpose reduction (lane swaps and DPP moves
+// that leave each total in one lane), and one atomic instruction adds all of
+// them, one lane per value.
 #include "legs_internal.h"
+#include "wave_reduce.h"
 
 namespace {
 
@@ -166,7 +168,7 @@ k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
     Stage<TILE, CP> S(s_dyn, P.batch);
     __shared__ int64_t s_tile;
     const int B = P.batch;
-    const int w = threadIdx.x / LEGS_WAVE, l = threadIdx.x % LEGS_WAVE;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / LEGS_WAVE), l = threadIdx.x % LEGS_WAVE;
     const int qxi = w % NQ, qyi = w / NQ;            // this wave's 8 x 8 quadrant
     const int qx0 = 8 * qxi, qy0 = 8 * qyi;
     const int lx = qx0 + (l & 7), ly = qy0 + (l >> 3);
@@ -203,7 +205,7 @@ k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
                 const float wgt = alpha * T;
                 const float *cj = S.ch + j * CP;
 #pragma unroll
-                for (int c = 0; c < CP; ++c) acc[c] += wgt * cj[c];
+                for (int c = 0; c < CP; ++c) acc[c] = fmaf(wgt, cj[c], acc[c]);
                 T = Tn;
                 lastpos = (lo - ti.rs) + (uint32_t)j + 1u;
             }
@@ -223,21 +225,6 @@ k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
 
 // ---- backward ----------------------------------------------------------------------
 
-// Sum over the 64 lanes, returned in every lane (wave-uniform): DPP butterflies
-// within each row of 16 lanes, then the four row sums read into scalars.
-__device__ __forceinline__ float wave_sum(float x)
-{
-    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
-    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x4E, 0xF, 0xF, false));
-    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x141, 0xF, 0xF, false));
-    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x140, 0xF, 0xF, false));
-    const int xi = __builtin_bit_cast(int, x);
-    return (__builtin_bit_cast(float, __builtin_amdgcn_readlane(xi, 0)) +
-            __builtin_bit_cast(float, __builtin_amdgcn_readlane(xi, 16))) +
-           (__builtin_bit_cast(float, __builtin_amdgcn_readlane(xi, 32)) +
-            __builtin_bit_cast(float, __builtin_amdgcn_readlane(xi, 48)));
-}
-
 // Per-wave block of the backward: SW x SH pixels, PPL = SW * SH / 64 per lane.
 template <int TILE, int CP> struct BwdShape {
     static constexpr int SW = (TILE == 8 || CP > 32) ? 8 : 16;
@@ -247,6 +234,16 @@ template <int TILE, int CP> struct BwdShape {
     static constexpr int ROWSTEP = LEGS_WAVE / SW;
 };
 
+// Backward of Eq. 1 per pixel, back to front from (T_final, last). With
+// w_k = alpha_k T_k and g_k = sum_c G_c c_{k,c} (G = dL/dR at the pixel),
+//   dL/dc_{k,c}  += w_k G_c
+//   dL/dalpha_k  += T_k (g_k - s_k),   s_{k-1} = alpha_k g_k + (1 - alpha_k) s_k,
+// where s_k = sum_c G_c (colour composited behind k, renormalised), so the
+// recurrence carries one scalar per pixel instead of one per channel; and
+// alpha_k = min(alpha_max, o_k exp(power)) gives dL/dpower = alpha dL/dalpha
+// and dL/do = exp(power) dL/dalpha when not clamped. The power's derivatives
+// (mean offset and conic) are summed per lane as moments of (dx, dy) and
+// turned into gradients once per Gaussian (the map is linear).
 template <int TILE, int CP>
 __global__ void __launch_bounds__((BwdShape<TILE, CP>::NT))
 k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restrict__ last,
@@ -254,23 +251,36 @@ k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restr
 {
     using Shp = BwdShape<TILE, CP>;
     constexpr int NT = Shp::NT, PPL = Shp::PPL, NQ = TILE / 8;
+    constexpr int NV = 6 + CP;                          // values summed per Gaussian
+    constexpr int KF = legs_tr::final_k(NV);
     extern __shared__ float4 s_dyn[];
     Stage<TILE, CP> S(s_dyn, P.batch);
     __shared__ int64_t s_tile;
     __shared__ uint32_t s_maxlast;
     const int B = P.batch;
-    const int w = threadIdx.x / LEGS_WAVE, l = threadIdx.x % LEGS_WAVE;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / LEGS_WAVE), l = threadIdx.x % LEGS_WAVE;
     constexpr int BX = TILE / Shp::SW;                 // wave blocks per tile row
     const int bx0 = (w % BX) * Shp::SW, by0 = (w / BX) * Shp::SH;
     const int lx = bx0 + (l % Shp::SW);
     const int ly0 = by0 + (l / Shp::SW);               // pixel p of this lane: row ly0 + ROWSTEP p
     const float fx = (float)(lx & 7);
     const int qxi = lx >> 3;
+    // which summed value this lane adds to memory after the wave reduction
+    int vidx[NV];
+    legs_tr::index<NV>(vidx, l);
+    bool vgeo[KF], vok[KF];
+    int voff[KF];
+#pragma unroll
+    for (int r = 0; r < KF; ++r) {
+        vgeo[r] = vidx[r] >= 0 && vidx[r] < 6;
+        voff[r] = vgeo[r] ? vidx[r] : vidx[r] - 6;
+        vok[r] = vidx[r] >= 0 && (vgeo[r] || voff[r] < P.C);
+    }
 
     for (int64_t tile = next_tile(P, -1, &s_tile); tile < P.total_tiles; tile = next_tile(P, tile, &s_tile)) {
         const TileInfo ti = tile_info<TILE>(P, tile);
         const int64_t hw = (int64_t)ti.W * ti.H;
-        float G[PPL][CP], Bs[PPL][CP], T[PPL];
+        float G[PPL][CP], T[PPL], gs[PPL];
         uint32_t L[PPL];
         uint32_t myL = 0;
 #pragma unroll
@@ -278,6 +288,7 @@ k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restr
             const int px = ti.tile_x0 + lx, py = ti.tile_y0 + ly0 + Shp::ROWSTEP * p;
             T[p] = 1.0f;
             L[p] = 0;
+            gs[p] = 0.0f;
             if (px < ti.W && py < ti.H) {
                 const int64_t pix = ti.pixel_offset + (int64_t)py * ti.W + px;
                 const float *g = d_out + (int64_t)P.C * ti.pixel_offset + (int64_t)py * ti.W + px;
@@ -289,8 +300,6 @@ k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restr
 #pragma unroll
                 for (int c = 0; c < CP; ++c) G[p][c] = 0.0f;
             }
-#pragma unroll
-            for (int c = 0; c < CP; ++c) Bs[p][c] = 0.0f;
             myL = max(myL, L[p]);
         }
         if (threadIdx.x == 0) s_maxlast = 0;
@@ -310,64 +319,67 @@ k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restr
                 if (x1 < bx0 || x0 > bx0 + Shp::SW - 1 || y1 < by0 || y0 > by0 + Shp::SH - 1) continue;
                 const float4 cn = S.c[j];
                 const float mqx = S.qx[j * NQ + qxi];
-                const float *cj = S.ch + j * CP;
-                float sdmx = 0.f, sdmy = 0.f, sdA = 0.f, sdB = 0.f, sdC = 0.f, sdop = 0.f;
-                float sch[CP];
+                float cv[CP];
 #pragma unroll
-                for (int c = 0; c < CP; ++c) sch[c] = 0.0f;
+                for (int c = 0; c < CP; ++c) cv[c] = S.ch[j * CP + c];
+                float sx = 0.f, sy = 0.f, sxx = 0.f, sxy = 0.f, syy = 0.f, sop = 0.f;
+                float acc[NV];
+#pragma unroll
+                for (int c = 0; c < CP; ++c) acc[6 + c] = 0.0f;
                 bool any = false;
+                // Per-lane conditions are folded into the arithmetic (zero weights)
+                // so that only wave-uniform branches remain.
 #pragma unroll
                 for (int p = 0; p < PPL; ++p) {
+                    // rows of band p: by0 + ROWSTEP p + [0, ROWSTEP)
+                    if (y1 < by0 + Shp::ROWSTEP * p || y0 > by0 + Shp::ROWSTEP * p + Shp::ROWSTEP - 1) continue;
                     const int ly = ly0 + Shp::ROWSTEP * p;
-                    if (!(pos < L[p] && lx >= x0 && lx <= x1 && ly >= y0 && ly <= y1)) continue;
+                    const bool inside = pos < L[p] && lx >= x0 && lx <= x1 && ly >= y0 && ly <= y1;
+                    if (legs_ballot(inside) == 0) continue;
                     const float dx = mqx - fx, dy = S.qy[j * NQ + (ly >> 3)] - (float)(ly & 7);
                     float ep;
                     bool clamped;
                     const float alpha = falloff_alpha(dx, dy, cn.x, cn.y, cn.z, cn.w, P.amax, ep, clamped);
-                    if (alpha < P.amin) continue;
+                    const bool bl = inside && !(alpha < P.amin);
+                    if (legs_ballot(bl) == 0) continue;
                     any = true;
-                    const float Tk = T[p] / (1.0f - alpha);
-                    const float wgt = alpha * Tk;
-                    float dot = 0.0f;
+                    const float Tk = bl ? T[p] * __builtin_amdgcn_rcpf(1.0f - alpha) : T[p];
+                    const float wgt = bl ? alpha * Tk : 0.0f;
+                    float g = 0.0f;
 #pragma unroll
                     for (int c = 0; c < CP; ++c) {
-                        sch[c] += wgt * G[p][c];
-                        const float d = cj[c] - Bs[p][c];
-                        dot += G[p][c] * d;
-                        Bs[p][c] += alpha * d;
+                        acc[6 + c] = fmaf(wgt, G[p][c], acc[6 + c]);
+                        g = fmaf(G[p][c], cv[c], g);
                     }
-                    const float dalpha = Tk * dot;
+                    const float dot = g - gs[p];
+                    const float dalpha = bl ? Tk * dot : 0.0f;
+                    gs[p] = bl ? fmaf(alpha, dot, gs[p]) : gs[p];
                     T[p] = Tk;
-                    if (!clamped) {
-                        sdop += dalpha * ep;
-                        const float dpow = dalpha * alpha;
-                        sdA += -0.5f * dpow * dx * dx;
-                        sdB += -dpow * dx * dy;
-                        sdC += -0.5f * dpow * dy * dy;
-                        sdmx += -dpow * (cn.x * dx + cn.y * dy);
-                        sdmy += -dpow * (cn.y * dx + cn.z * dy);
-                    }
+                    const float dg = clamped ? 0.0f : dalpha;
+                    sop = fmaf(dg, ep, sop);
+                    const float dpow = dg * alpha;
+                    const float ex = dpow * dx, ey = dpow * dy;
+                    sx += ex;
+                    sy += ey;
+                    sxx = fmaf(ex, dx, sxx);
+                    sxy = fmaf(ex, dy, sxy);
+                    syy = fmaf(ey, dy, syy);
                 }
-                if (legs_ballot(any) == 0) continue;
-                const float r0 = wave_sum(sdmx), r1 = wave_sum(sdmy), r2 = wave_sum(sdA);
-                const float r3 = wave_sum(sdB), r4 = wave_sum(sdC), r5 = wave_sum(sdop);
-                float rc[CP];
+                if (!any) continue;
+                // d/dmean = -(conic . (dx, dy)) dpow, d/dA = -dx^2/2 dpow, d/dB = -dx dy dpow, ...
+                acc[0] = -fmaf(cn.x, sx, cn.y * sy);
+                acc[1] = -fmaf(cn.y, sx, cn.z * sy);
+                acc[2] = -0.5f * sxx;
+                acc[3] = -sxy;
+                acc[4] = -0.5f * syy;
+                acc[5] = sop;
+                legs_tr::reduce<NV>(acc, l);
+                const uint32_t gid = S.id[j];
+                float *g2d = grad2d + 8 * ((int64_t)ti.v * P.n + gid);
+                float *dc = d_ch + (int64_t)gid * P.C;
 #pragma unroll
-                for (int c = 0; c < CP; ++c) rc[c] = wave_sum(sch[c]);
-                if (l == 0) {
-                    const uint32_t gid = S.id[j];
-                    float *g2d = grad2d + 8 * ((int64_t)ti.v * P.n + gid);
-                    if (r0 != 0.f) atomicAdd(g2d + 0, r0);
-                    if (r1 != 0.f) atomicAdd(g2d + 1, r1);
-                    if (r2 != 0.f) atomicAdd(g2d + 2, r2);
-                    if (r3 != 0.f) atomicAdd(g2d + 3, r3);
-                    if (r4 != 0.f) atomicAdd(g2d + 4, r4);
-                    if (r5 != 0.f) atomicAdd(g2d + 5, r5);
-                    float *dc = d_ch + (int64_t)gid * P.C;
-#pragma unroll
-                    for (int c = 0; c < CP; ++c)
-                        if (c < P.C && rc[c] != 0.f) atomicAdd(dc + c, rc[c]);
-                }
+                for (int r = 0; r < KF; ++r)
+                    if (vok[r] && acc[r] != 0.0f) atomicAdd((vgeo[r] ? g2d : dc) + voff[r], acc[r]);
             }
             hi = lo_rel;
             __syncthreads();

@@ -79,12 +79,16 @@ int32_t legs_launch_blend_counts(legs_ctx *ctx, const legs_projected *proj, int6
 struct legs_sort_layout {
     int64_t hist_off;      // uint32 [8][256] digit histograms
     int64_t start_off;     // uint32 [8][256] exclusive digit starts
-    int64_t counter_off;   // uint32 [16] partition counters per pass
+    int64_t counter_off;   // uint32 [64] partition counters per pass, blend tile counters
     int64_t status_off;    // uint64 [8][parts][256] look-back status words
     int64_t parts;         // partitions at full capacity
+    int64_t tcount_off;    // uint32 [total_tiles] per-tile instance counts
+    int64_t tsum_off;      // uint64 [tile_blocks + 1] per-1024-tile sums
+    int64_t toff_off;      // uint64 [tile_blocks + 1] their exclusive scan
+    int64_t tile_blocks;
     int64_t total;
 };
-legs_sort_layout legs_sort_layout_for(int64_t capacity);
+legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles = 0);
 
 #define LEGS_SORT_THREADS 256
 #define LEGS_SORT_ITEMS 16

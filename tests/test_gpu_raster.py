@@ -427,3 +427,70 @@ def test_render_counts_match_a_per_pixel_walk(R):
         assert exp[1] > 0 and exp[0] >= exp[2] >= exp[1]
         for c, x in zip(counts, exp):
             assert abs(c - x) <= 1e-4 * x + 2, (counts, exp)
+
+
+def _truncated_lists(fwd, cams, tile, n, capacity):
+    """The first `capacity` instances of the depth-ordered stream (G-views by
+    (view, depth bits), ties by Gaussian; each G-view's tiles row-major),
+    stably sorted by tile: keys, ids and ranges, from the oracle projection."""
+    _, _, offsets, total_tiles = O.view_tables(cams, tile)
+    recs = []
+    for v, cam in enumerate(cams):
+        p = fwd["proj"][v]
+        txn = (cam.width + tile - 1) // tile
+        bits = p["depth32"].view(np.uint32).astype(np.uint64)
+        for g in np.nonzero(p["ntiles"] > 0)[0]:
+            recs.append((v, int(bits[g]), int(g), txn, int(offsets[v])))
+    recs.sort(key=lambda r: (r[0], r[1], r[2]))
+    tiles, ids, dbits = [], [], []
+    for v, db, g, txn, toff in recs:
+        p = fwd["proj"][v][g]
+        for ty in range(p["ty0"], p["ty1"] + 1):
+            for tx in range(p["tx0"], p["tx1"] + 1):
+                tiles.append(toff + ty * txn + tx)
+                ids.append(g)
+                dbits.append(db)
+        if len(tiles) >= capacity:
+            break
+    tiles, ids, dbits = (np.array(a[:capacity], np.uint64) for a in (tiles, ids, dbits))
+    order = np.argsort(tiles, kind="stable")
+    keys = (tiles[order] << np.uint64(32)) | dbits[order]
+    ranges = np.zeros((total_tiles, 2), np.int64)
+    t_sorted = tiles[order].astype(np.int64)
+    starts = np.searchsorted(t_sorted, np.arange(total_tiles), "left")
+    ends = np.searchsorted(t_sorted, np.arange(total_tiles), "right")
+    ranges[:, 0], ranges[:, 1] = starts, ends
+    return keys, ids[order].astype(np.uint32), ranges
+
+
+def test_truncated_lists_without_host_count(R):
+    """Without the host read-back an overflowing binning keeps the first
+    `capacity` instances of the depth-ordered stream, sorted by tile, with
+    ranges inside the capacity (so the blend kernels stay in bounds)."""
+    import ctypes as ct
+    from paper_2311_18482_amd import _lib as L
+    scene = synth.make_scene(3000, 41, synth.VOL_C1, d_sem=8)
+    cams = [synth.camera_front(160, 120, 150.0), synth.camera_front(96, 80, 90.0)]
+    for tile in (8, 16):
+        o = R.opts(tile=tile)
+        rast = R.Rasterizer(cams, o)
+        d = PT.to_dev(scene)
+        proj = R.project(rast.ctx, d["mean"], d["log_scale"], d["quat"], d["opacity_logit"],
+                         rast.views, o)
+        full = R.bin_sort(rast.ctx, proj, rast.views, o)
+        total = full.n_instances
+        fwd = O.forward(scene, cams, PT.oracle_opts(o))
+        for cap in (total // 3, total - 7):
+            note(f"truncated lists tile={tile} capacity={cap} of {total}")
+            small = R.BinsBuf(cap, rast.views.total_tiles, d["mean"].device)
+            ps, bs = proj.struct(), small.struct()
+            code = L.lib().legs_bin_sort(rast.ctx.handle, ct.byref(ps), scene.n, R._p(rast.views.dev),
+                                         len(cams), rast.views.total_tiles, ct.byref(o), ct.byref(bs),
+                                         None, R._stream())
+            assert code == L.LEGS_OK
+            torch.cuda.synchronize()
+            assert int(small.count.item()) == total
+            keys, ids, ranges = _truncated_lists(fwd, cams, tile, scene.n, cap)
+            assert np.array_equal(small.keys.cpu().numpy().view(np.uint64), keys)
+            assert np.array_equal(small.ids.cpu().numpy().view(np.uint32), ids)
+            assert np.array_equal(small.ranges.cpu().numpy().astype(np.int64), ranges)
