@@ -86,14 +86,18 @@ struct legs_sort_layout {
     int64_t tsum_off;      // uint64 [tile_blocks + 1] per-1024-tile sums
     int64_t toff_off;      // uint64 [tile_blocks + 1] their exclusive scan
     int64_t tile_blocks;
+    int64_t pstart_off;    // uint32 [parts] first G-view block of each partition
+    int64_t dep_off;       // uint32 [2][capacity] depth bits carried by the tile passes
+    int64_t part_off;      // uint32 [LEGS_TILE_CHUNKS][total_tiles] partial tile-count grids
     int64_t total;
 };
 legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles = 0);
 
-#define LEGS_SORT_THREADS 256
-#define LEGS_SORT_ITEMS 16
+#define LEGS_SORT_THREADS 512
+#define LEGS_SORT_ITEMS 8
 #define LEGS_SORT_PART (LEGS_SORT_THREADS * LEGS_SORT_ITEMS)
 #define LEGS_SORT_MAX_PASSES 8
+#define LEGS_TILE_CHUNKS 128
 // counter slots (u32) in the sort scratch's counter block: 0..15 sort passes
 #define LEGS_BLEND_COUNTER_FWD 32
 #define LEGS_BLEND_COUNTER_BWD 33

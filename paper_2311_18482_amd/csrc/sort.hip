@@ -230,29 +230,30 @@ k_sort_clear(uint64_t *__restrict__ status, int64_t parts_cap, int passes,
     }
 }
 
+// One record per depth-ordered position: everything the tile passes need of
+// the G-view there, read once with one coalesced load.
+struct GRec {
+    uint32_t gid;    // Gaussian index
+    uint32_t cnt;    // tiles of its rectangle (0: culled)
+    uint32_t base;   // global id of its first tile
+    uint32_t rwtx;   // rectangle width | tiles_x of its view << 16
+};
+
 // Inputs of the fused emission (first tile pass of the depth-first binning):
-// the depth-ordered G-views and the instance offset of every 256 of them.
+// the records of the depth-ordered G-views, the instance offset of every 256
+// of them and the first block of each partition.
 struct TileEmit {
-    const uint32_t *perm;      // G-view index at each depth-ordered position
-    const int4 *box;
-    const uint32_t *ntiles;
-    const uint64_t *goff;      // [nblocks + 1] instance offset of each block of 256 positions
-    int64_t nblocks, n, G;
-    const legs_view *views;
-    int tile;
+    const GRec *recs;
+    const uint32_t *dbits;
+    const uint64_t *goff;      // [nblocks + 1]
+    const uint32_t *pstart;    // [partitions]
+    int64_t nblocks, G;
 };
 
-// Output of the last tile pass: the 64-bit keys (tile << 32) | bits(depth).
-struct TileFinal {
-    uint64_t *keys64;
-    const float *depth;
-    int64_t n;
-    const legs_view *views;
-    int n_views;
-};
-
-// Exclusive scan of one value per thread over a 256-thread block (64-bit
-// totals); s_start[256] receives the block total.
+// Exclusive scan over a block of T threads of one 64-bit value per thread
+// (threads >= 256 pass 0); s_start[0..256] receives the scan of the first
+// 256 and their total.
+template <int T>
 __device__ __forceinline__ void block_scan_256(uint64_t x, uint64_t *s_start, uint64_t *s_w)
 {
     const int lane = legs_lane(), wave = threadIdx.x / LEGS_WAVE;
@@ -264,33 +265,44 @@ __device__ __forceinline__ void block_scan_256(uint64_t x, uint64_t *s_start, ui
     }
     if (lane == LEGS_WAVE - 1) s_w[wave] = incl;
     __syncthreads();
-    uint64_t wpre = 0;
-    for (int w = 0; w < wave; ++w) wpre += s_w[w];
-    s_start[threadIdx.x] = wpre + incl - x;
-    if (threadIdx.x == 255) s_start[256] = wpre + incl;
+    if (threadIdx.x < 256) {
+        uint64_t wpre = 0;
+        for (int w = 0; w < wave; ++w) wpre += s_w[w];
+        s_start[threadIdx.x] = wpre + incl - x;
+        if (threadIdx.x == 255) s_start[256] = wpre + incl;
+    }
     __syncthreads();
 }
 
-// One onesweep pass over digit `pass` (bits 8 pass .. 8 pass + 7) of keys K.
-// EMIT: the partition's (tile, id) pairs are generated from the depth-ordered
-// G-views instead of read (instance e of the stream is tile e - start of its
-// G-view's rectangle, row-major). FINAL: the output keys are widened to the
-// 64-bit (tile << 32) | bits(depth) keys of the tile lists.
-template <typename K, bool EMIT, bool FINAL>
-__global__ void __launch_bounds__(LEGS_SORT_THREADS)
+// One onesweep pass over digit `pass` (bits 8 pass .. 8 pass + 7) of keys K
+// with 32-bit values, and with DEP a second 32-bit value (the depth bits)
+// carried along. EMIT: the partition's (tile, id, depth) triples are
+// generated from the depth-ordered G-view records instead of read (instance
+// e is tile e - start of its G-view's rectangle, row-major): each G-view
+// marks the first partition slot it fills, and a running maximum over the
+// slots gives every slot its owner. FINAL: the keys are written as the 64-bit
+// (tile << 32) | depth keys of the tile lists.
+template <typename K, bool DEP, bool EMIT, bool FINAL>
+__global__ void __launch_bounds__(LEGS_SORT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
-           K *__restrict__ kout, uint32_t *__restrict__ vout,
+           const uint32_t *__restrict__ din, K *__restrict__ kout, uint32_t *__restrict__ vout,
+           uint32_t *__restrict__ dout, uint64_t *__restrict__ keys64,
            const uint64_t *__restrict__ count, int64_t capacity, int pass,
            const uint32_t *__restrict__ digit_starts, uint64_t *__restrict__ status,
-           uint32_t *__restrict__ counter, TileEmit E, TileFinal F)
+           uint32_t *__restrict__ counter, TileEmit E)
 {
-    constexpr int NW = LEGS_SORT_THREADS / LEGS_WAVE;
-    static_assert(LEGS_SORT_THREADS == 256, "one thread per digit");
-    __shared__ K s_keys[LEGS_SORT_PART];
-    __shared__ uint32_t s_vals[LEGS_SORT_PART];
+    constexpr int T = LEGS_SORT_THREADS;
+    constexpr int NW = T / LEGS_WAVE;
+    constexpr int ITEMS = LEGS_SORT_ITEMS;
+    constexpr int PART = LEGS_SORT_PART;
+    constexpr int SPT = PART / T;            // partition slots per thread (EMIT)
+    static_assert(T >= 256 && T % 256 == 0, "one thread per digit");
+    __shared__ K s_keys[PART];
+    __shared__ uint32_t s_vals[PART];
+    __shared__ uint32_t s_dep[DEP ? PART : 1];
     __shared__ uint32_t s_wh[NW][256];      // per-wave digit counts, then wave offsets
     __shared__ uint32_t s_lstart[256];      // block-local start of each digit
-    __shared__ uint64_t s_gstart[257];      // global start of this partition's digit runs;
+    __shared__ uint64_t s_gstart[257];      // global position of LDS slot 0 of each digit;
                                             // with EMIT first the G-view scan of a block
     __shared__ uint32_t s_tmp[NW];
     __shared__ uint64_t s_w64[NW];
@@ -298,97 +310,122 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
 
     const uint64_t cnt = *count;
     const int64_t m = (int64_t)(cnt < (uint64_t)capacity ? cnt : (uint64_t)capacity);
-    const int64_t parts = (m + LEGS_SORT_PART - 1) / LEGS_SORT_PART;
+    const int64_t parts = (m + PART - 1) / PART;
     const int shift = 8 * pass;
     const int tid = threadIdx.x, lane = legs_lane(), wave = tid / LEGS_WAVE;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     for (;;) {
         if (tid == 0) s_part = (int64_t)atomicAdd(counter, 1u);
-        for (int i = tid; i < NW * 256; i += LEGS_SORT_THREADS) (&s_wh[0][0])[i] = 0;
+        for (int i = tid; i < NW * 256; i += T) (&s_wh[0][0])[i] = 0;
         __syncthreads();
         const int64_t part = s_part;
         if (part >= parts) break;
-        const int64_t base = part * LEGS_SORT_PART;
-        const int64_t nvalid64 = m - base < LEGS_SORT_PART ? m - base : LEGS_SORT_PART;
+        const int64_t base = part * PART;
+        const int64_t nvalid64 = m - base < PART ? m - base : PART;
         const int nvalid = (int)nvalid64;
 
         if constexpr (EMIT) {
-            // first block of G-views whose instances reach this partition
-            __shared__ int64_t s_b;
-            if (tid == 0) {
-                int64_t lo = 0, hi = E.nblocks - 1;
-                while (lo < hi) {
-                    const int64_t mid = (lo + hi + 1) >> 1;
-                    if (E.goff[mid] <= (uint64_t)base) lo = mid; else hi = mid - 1;
-                }
-                s_b = lo;
-            }
-            __syncthreads();
-            __shared__ int s_tx0[256], s_ty0[256], s_rw[256], s_tilesx[256];
-            __shared__ int64_t s_toff[256];
-            __shared__ uint32_t s_g[256];
-            for (int64_t b = s_b; b < E.nblocks; ++b) {
+            __shared__ uint32_t s_rbase[256], s_rwtx[256], s_rg[256], s_rd[256];
+            __shared__ uint16_t s_own[PART];
+            __shared__ uint32_t s_omax[NW];
+            for (int64_t b = E.pstart[part]; b < E.nblocks; ++b) {
                 const uint64_t ob = E.goff[b];
                 if (ob >= (uint64_t)(base + nvalid)) break;
                 const int64_t pos = b * 256 + tid;
-                uint64_t c = 0;
-                if (pos < E.G) {
-                    const int64_t gv = E.perm[pos];
-                    c = E.ntiles[gv];
-                    if (c) {
-                        const int64_t v = gv / E.n;
-                        const int4 bx = E.box[gv];
-                        s_tx0[tid] = bx.x / E.tile;
-                        s_ty0[tid] = bx.z / E.tile;
-                        s_rw[tid] = bx.y / E.tile - bx.x / E.tile + 1;
-                        s_g[tid] = (uint32_t)(gv - v * E.n);
-                        s_toff[tid] = E.views[v].tile_offset;
-                        s_tilesx[tid] = E.views[v].tiles_x;
-                    }
+                uint32_t c = 0;
+                if (tid < 256 && pos < E.G) {
+                    const GRec r = E.recs[pos];
+                    c = r.cnt;
+                    s_rbase[tid] = r.base;
+                    s_rwtx[tid] = r.rwtx;
+                    s_rg[tid] = r.gid;
+                    s_rd[tid] = c ? E.dbits[pos] : 0u;
                 }
-                block_scan_256(c, s_gstart, s_w64);
+                block_scan_256<T>(c, s_gstart, s_w64);
                 const uint64_t tot = s_gstart[256];
                 const uint64_t lo = (uint64_t)base > ob ? (uint64_t)base - ob : 0;
                 const uint64_t hi = ((uint64_t)(base + nvalid) - ob) < tot ? (uint64_t)(base + nvalid) - ob : tot;
-                for (uint64_t k = lo + tid; k < hi; k += LEGS_SORT_THREADS) {
-                    int l0 = 0, l1 = 255;
-                    while (l0 < l1) {
-                        const int mid = (l0 + l1 + 1) >> 1;
-                        if (s_gstart[mid] <= k) l0 = mid; else l1 = mid - 1;
+                const int e_lo = (int)(ob + lo - (uint64_t)base), e_hi = (int)(ob + hi - (uint64_t)base);
+                // clear the slots of this block, mark each G-view's first slot
+#pragma unroll
+                for (int q = 0; q < SPT; ++q) {
+                    const int e = tid * SPT + q;
+                    if (e >= e_lo && e < e_hi) s_own[e] = 0;
+                }
+                __syncthreads();
+                if (tid < 256 && c) {
+                    const uint64_t st = s_gstart[tid];
+                    const uint64_t first = st > lo ? st : lo;
+                    if (first < hi && first < st + c) s_own[(int)(ob + first - (uint64_t)base)] = (uint16_t)(tid + 1);
+                }
+                __syncthreads();
+                // owner of each slot: running maximum of the marks
+                uint32_t own[SPT];
+                uint32_t run = 0;
+#pragma unroll
+                for (int q = 0; q < SPT; ++q) {
+                    const int e = tid * SPT + q;
+                    const uint32_t mk = (e >= e_lo && e < e_hi) ? (uint32_t)s_own[e] : 0u;
+                    run = mk > run ? mk : run;
+                    own[q] = run;
+                }
+                uint32_t wmax = run;     // inclusive max-scan of the per-thread maxima
+#pragma unroll
+                for (int off = 1; off < LEGS_WAVE; off <<= 1) {
+                    const uint32_t y = (uint32_t)__shfl_up((int)wmax, off, LEGS_WAVE);
+                    if (lane >= off) wmax = y > wmax ? y : wmax;
+                }
+                if (lane == LEGS_WAVE - 1) s_omax[wave] = wmax;
+                __syncthreads();
+                uint32_t prev = (uint32_t)__shfl_up((int)wmax, 1, LEGS_WAVE);
+                if (lane == 0) prev = 0;
+                for (int w = 0; w < wave; ++w) prev = s_omax[w] > prev ? s_omax[w] : prev;
+#pragma unroll
+                for (int q = 0; q < SPT; ++q) {
+                    const int e = tid * SPT + q;
+                    if (e >= e_lo && e < e_hi) {
+                        const int o = (int)(own[q] > prev ? own[q] : prev) - 1;
+                        const uint32_t local = (uint32_t)((uint64_t)base + (uint64_t)e - ob - s_gstart[o]);
+                        const uint32_t rwtx = s_rwtx[o], rw = rwtx & 0xffffu, tx = rwtx >> 16;
+                        const uint32_t qq = local / rw;
+                        s_keys[e] = (K)(s_rbase[o] + qq * tx + (local - qq * rw));
+                        s_vals[e] = s_rg[o];
+                        if constexpr (DEP) s_dep[e] = s_rd[o];
                     }
-                    const uint32_t local = (uint32_t)(k - s_gstart[l0]);
-                    const int rw = s_rw[l0];
-                    const int ty = s_ty0[l0] + (int)(local / (uint32_t)rw);
-                    const int tx = s_tx0[l0] + (int)(local % (uint32_t)rw);
-                    const int64_t e = (int64_t)(ob + k) - base;
-                    s_keys[e] = (K)(s_toff[l0] + (int64_t)ty * s_tilesx[l0] + tx);
-                    s_vals[e] = s_g[l0];
                 }
                 __syncthreads();
             }
         }
 
-        K key[LEGS_SORT_ITEMS];
-        uint32_t val[LEGS_SORT_ITEMS];
-        uint32_t rank[LEGS_SORT_ITEMS];
+        K key[ITEMS];
+        uint32_t val[ITEMS], dep[DEP ? ITEMS : 1];
+        uint32_t rank[ITEMS];
         // wave-striped: item i of lane l of wave w is partition element w*64*ITEMS + i*64 + l
 #pragma unroll
-        for (int i = 0; i < LEGS_SORT_ITEMS; ++i) {
-            const int e = wave * LEGS_WAVE * LEGS_SORT_ITEMS + i * LEGS_WAVE + lane;
+        for (int i = 0; i < ITEMS; ++i) {
+            const int e = wave * LEGS_WAVE * ITEMS + i * LEGS_WAVE + lane;
             if (e < nvalid) {
-                if constexpr (EMIT) { key[i] = s_keys[e]; val[i] = s_vals[e]; }
-                else { key[i] = kin[base + e]; val[i] = vin[base + e]; }
+                if constexpr (EMIT) {
+                    key[i] = s_keys[e];
+                    val[i] = s_vals[e];
+                    if constexpr (DEP) dep[i] = s_dep[e];
+                } else {
+                    key[i] = kin[base + e];
+                    val[i] = vin[base + e];
+                    if constexpr (DEP) dep[i] = din[base + e];
+                }
             } else {
                 key[i] = (K)~(K)0;
                 val[i] = 0;
+                if constexpr (DEP) dep[i] = 0;
             }
         }
-        if constexpr (EMIT) __syncthreads();   // s_keys is reused by the scatter below
+        if constexpr (EMIT) __syncthreads();   // the LDS arrays are reused by the scatter below
         // rank within the wave: peers with the same digit via 8 ballots
 #pragma unroll
-        for (int i = 0; i < LEGS_SORT_ITEMS; ++i) {
-            const int e = wave * LEGS_WAVE * LEGS_SORT_ITEMS + i * LEGS_WAVE + lane;
+        for (int i = 0; i < ITEMS; ++i) {
+            const int e = wave * LEGS_WAVE * ITEMS + i * LEGS_WAVE + lane;
             const bool ok = e < nvalid;
             const uint32_t d = (uint32_t)(key[i] >> shift) & 255u;
             uint64_t peers = legs_ballot(ok);
@@ -406,75 +443,98 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
             rank[i] = lbase + (uint32_t)__popcll(peers & lt_mask);
         }
         __syncthreads();
-        // per digit: offsets of each wave, block total, look-back
-        {
+        // per digit (threads 0..255): offsets of each wave, partition total
+        // (published at once), block-local digit starts
+        uint32_t t = 0, incl = 0, lstart = 0;
+        if (tid < 256) {
             const int d = tid;
-            uint32_t t = 0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
                 const uint32_t c = s_wh[w][d];
                 s_wh[w][d] = t;
                 t += c;
             }
-            uint64_t *st = status + part * 256 + d;
-            if (part == 0) st_status(st, FLAG_INC | (uint64_t)t);
-            else st_status(st, FLAG_AGG | (uint64_t)t);
-            uint64_t excl = 0;
-            if (part > 0) {
-                int64_t j = part - 1;
-                for (;;) {
-                    const uint64_t sv = ld_status(status + j * 256 + d);
-                    const uint64_t f = sv & ~VALUE_MASK;
-                    if (f == 0) continue;            // not published yet
-                    excl += sv & VALUE_MASK;
-                    if (f == FLAG_INC) break;
-                    --j;
-                }
-                st_status(st, FLAG_INC | (excl + t));
-            }
-            s_gstart[d] = (uint64_t)digit_starts[pass * 256 + d] + excl;
-            // block-local exclusive scan of digit totals
-            uint32_t incl = t;
+            st_status(status + part * 256 + d, (part == 0 ? FLAG_INC : FLAG_AGG) | (uint64_t)t);
+            incl = t;
 #pragma unroll
             for (int off = 1; off < LEGS_WAVE; off <<= 1) {
                 const uint32_t y = __shfl_up(incl, off, LEGS_WAVE);
                 if (lane >= off) incl += y;
             }
             if (lane == LEGS_WAVE - 1) s_tmp[wave] = incl;
-            __syncthreads();
+        }
+        __syncthreads();
+        if (tid < 256) {
             uint32_t wp = 0;
             for (int w = 0; w < wave; ++w) wp += s_tmp[w];
-            s_lstart[d] = wp + incl - t;
+            lstart = wp + incl - t;
+            s_lstart[tid] = lstart;
         }
         __syncthreads();
         // scatter into LDS in digit order
 #pragma unroll
-        for (int i = 0; i < LEGS_SORT_ITEMS; ++i) {
-            const int e = wave * LEGS_WAVE * LEGS_SORT_ITEMS + i * LEGS_WAVE + lane;
+        for (int i = 0; i < ITEMS; ++i) {
+            const int e = wave * LEGS_WAVE * ITEMS + i * LEGS_WAVE + lane;
             if (e < nvalid) {
                 const uint32_t d = (uint32_t)(key[i] >> shift) & 255u;
                 const uint32_t pos = s_lstart[d] + s_wh[wave][d] + rank[i];
                 s_keys[pos] = key[i];
                 s_vals[pos] = val[i];
+                if constexpr (DEP) s_dep[pos] = dep[i];
             }
         }
+        // look-back for the global start of each digit run
+        if (tid < 256) {
+            const int d = tid;
+            uint64_t excl = 0;
+            if (part > 0) {
+                // a window of LB predecessors per round trip: their status words
+                // are loaded at once, then summed from the nearest outward up to
+                // the first inclusive one (or re-read from the first one not yet
+                // published)
+                constexpr int LB = 16;
+                int64_t j = part - 1;
+                for (;;) {
+                    uint64_t sv[LB];
+#pragma unroll
+                    for (int q = 0; q < LB; ++q)
+                        sv[q] = j - q >= 0 ? ld_status(status + (j - q) * 256 + d) : FLAG_INC;
+                    bool done = false;
+                    int q = 0;
+                    for (; q < LB; ++q) {
+                        const uint64_t f = sv[q] & ~VALUE_MASK;
+                        if (f == 0) break;               // not published yet: re-read from here
+                        excl += sv[q] & VALUE_MASK;
+                        if (f == FLAG_INC) { done = true; break; }
+                    }
+                    if (done) break;
+                    j -= q;
+                }
+                st_status(status + part * 256 + d, FLAG_INC | (excl + t));
+            }
+            s_gstart[d] = (uint64_t)digit_starts[pass * 256 + d] + excl - (uint64_t)lstart;
+        }
         __syncthreads();
-        // write out digit runs (positions past the capacity cannot occur when the
-        // digit histograms count exactly the stored instances; the test keeps a
-        // wrong histogram from writing out of bounds)
-        for (int k = tid; k < nvalid; k += LEGS_SORT_THREADS) {
-            const K kk = s_keys[k];
-            const uint32_t d = (uint32_t)(kk >> shift) & 255u;
-            const uint64_t gpos = s_gstart[d] + (uint64_t)(k - (int)s_lstart[d]);
-            if (gpos >= (uint64_t)capacity) continue;
-            if constexpr (FINAL) {
-                const uint32_t id = s_vals[k];
-                const int v = legs_view_of_tile(F.views, F.n_views, (int64_t)kk);
-                F.keys64[gpos] = ((uint64_t)kk << 32) | __float_as_uint(F.depth[(int64_t)v * F.n + id]);
-                vout[gpos] = id;
-            } else {
-                kout[gpos] = kk;
-                vout[gpos] = s_vals[k];
+        // write out digit runs: consecutive lanes, consecutive addresses (positions
+        // past the capacity cannot occur when the digit histograms count exactly
+        // the stored instances; the test keeps a wrong one in bounds)
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int k = tid + j * T;
+            if (k < nvalid) {
+                const K kk = s_keys[k];
+                const uint32_t d = (uint32_t)(kk >> shift) & 255u;
+                const uint64_t gpos = s_gstart[d] + (uint64_t)k;
+                if (gpos < (uint64_t)capacity) {
+                    if constexpr (FINAL) {
+                        keys64[gpos] = ((uint64_t)kk << 32) | s_dep[k];
+                        vout[gpos] = s_vals[k];
+                    } else {
+                        kout[gpos] = kk;
+                        vout[gpos] = s_vals[k];
+                        if constexpr (DEP) dout[gpos] = s_dep[k];
+                    }
+                }
             }
         }
         __syncthreads();
@@ -498,13 +558,39 @@ k_order_keys(const uint32_t *__restrict__ ntiles, const float *__restrict__ dept
     vals[gv] = (uint32_t)gv;
 }
 
-// Instance counts per block of 256 G-views in depth order.
+// Records, depth bits and per-view position ranges of the depth-ordered
+// G-views, and the instance count of each block of 256 positions.
 __global__ void __launch_bounds__(LEGS_PROJ_BLOCK)
-k_sorted_block_counts(const uint32_t *__restrict__ perm, const uint32_t *__restrict__ ntiles,
-                      int64_t G, uint64_t *__restrict__ block_counts)
+k_sorted_records(const uint32_t *__restrict__ perm, const uint64_t *__restrict__ okeys,
+                 const int4 *__restrict__ box, const float *__restrict__ depth,
+                 const uint32_t *__restrict__ ntiles, int64_t n, int64_t G,
+                 const legs_view *__restrict__ views, int tile, GRec *__restrict__ recs,
+                 uint32_t *__restrict__ dbits, uint64_t *__restrict__ vrange,
+                 uint64_t *__restrict__ block_counts)
 {
     const int64_t pos = (int64_t)blockIdx.x * LEGS_PROJ_BLOCK + threadIdx.x;
-    uint64_t c = pos < G ? ntiles[perm[pos]] : 0u;
+    uint64_t c = 0;
+    if (pos < G) {
+        const int64_t gv = perm[pos];
+        c = ntiles[gv];
+        GRec r = {0u, 0u, 0u, 0u};
+        if (c) {
+            const int64_t v = gv / n;
+            const int4 bx = box[gv];
+            const legs_view &vw = views[v];
+            const int tx0 = bx.x / tile, ty0 = bx.z / tile;
+            r.gid = (uint32_t)(gv - v * n);
+            r.cnt = (uint32_t)c;
+            r.base = (uint32_t)(vw.tile_offset + (int64_t)ty0 * vw.tiles_x + tx0);
+            r.rwtx = (uint32_t)(bx.y / tile - tx0 + 1) | ((uint32_t)vw.tiles_x << 16);
+            dbits[pos] = __float_as_uint(depth[gv]);
+            // first and last position of each view (visible G-views sort by view)
+            const uint64_t kv = okeys[pos] >> 32;
+            if (pos == 0 || (okeys[pos - 1] >> 32) != kv) vrange[2 * kv] = (uint64_t)pos;
+            if (pos == G - 1 || (okeys[pos + 1] >> 32) != kv) vrange[2 * kv + 1] = (uint64_t)pos + 1;
+        }
+        recs[pos] = r;
+    }
 #pragma unroll
     for (int off = LEGS_WAVE / 2; off > 0; off >>= 1) c += __shfl_down(c, off, LEGS_WAVE);
     __shared__ uint64_t s_w[LEGS_PROJ_BLOCK / LEGS_WAVE];
@@ -517,6 +603,20 @@ k_sorted_block_counts(const uint32_t *__restrict__ perm, const uint32_t *__restr
     }
 }
 
+// First block of 256 positions of every partition of the instance stream:
+// partition p starts in block b when goff[b] <= p * PART < goff[b + 1].
+__global__ void __launch_bounds__(256)
+k_part_blocks(const uint64_t *__restrict__ goff, int64_t nblocks, int64_t parts_cap,
+              uint32_t *__restrict__ pstart)
+{
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= nblocks) return;
+    const int64_t plo = (int64_t)((goff[b] + LEGS_SORT_PART - 1) / LEGS_SORT_PART);
+    int64_t phi = (int64_t)((goff[b + 1] + LEGS_SORT_PART - 1) / LEGS_SORT_PART);
+    if (phi > parts_cap) phi = parts_cap;
+    for (int64_t p = plo; p < phi; ++p) pstart[p] = (uint32_t)b;
+}
+
 // ---- per-tile counts of the depth-ordered instance stream ----------------------
 
 // The first `capacity` instances of the depth-ordered stream are counted per
@@ -526,43 +626,84 @@ k_sorted_block_counts(const uint32_t *__restrict__ perm, const uint32_t *__restr
 // row-major order (full rows plus one partial row). The counts give the
 // tile ranges and the digit histograms of the tile passes without reading
 // the instances.
-__device__ __forceinline__ void diff_rect(uint32_t *diff, const legs_view &vw, int x0, int x1,
-                                          int y0, int y1)
+// +1 / -1 at the corners of a tile rectangle (view-local tile coordinates).
+__device__ __forceinline__ void diff_rect(uint32_t *g, int W, int H, int x0, int x1, int y0, int y1)
 {
-    uint32_t *g = diff + vw.tile_offset;
-    const int W = vw.tiles_x, H = vw.tiles_y;
-    atomicAdd(g + (int64_t)y0 * W + x0, 1u);
-    if (x1 + 1 < W) atomicAdd(g + (int64_t)y0 * W + x1 + 1, 0xffffffffu);
-    if (y1 + 1 < H) atomicAdd(g + (int64_t)(y1 + 1) * W + x0, 0xffffffffu);
-    if (x1 + 1 < W && y1 + 1 < H) atomicAdd(g + (int64_t)(y1 + 1) * W + x1 + 1, 1u);
+    atomicAdd(g + y0 * W + x0, 1u);
+    if (x1 + 1 < W) atomicAdd(g + y0 * W + x1 + 1, 0xffffffffu);
+    if (y1 + 1 < H) atomicAdd(g + (y1 + 1) * W + x0, 0xffffffffu);
+    if (x1 + 1 < W && y1 + 1 < H) atomicAdd(g + (y1 + 1) * W + x1 + 1, 1u);
 }
 
+constexpr int TILE_LDS_CELLS = 16384;   // views with at most this many tiles count in LDS
+
+// Workgroup (c, v) adds the rectangles of view v's G-views in position blocks
+// c, c + gridDim.x, ... into an LDS copy of the view's tile grid and stores it
+// in partial[c] (views with more tiles than fit add straight into the global
+// grid with atomics); k_tile_merge then sums the partial grids. Hot corner
+// cells cost LDS atomics instead of global ones.
 __global__ void __launch_bounds__(256)
-k_tile_corners(const uint32_t *__restrict__ perm, const int4 *__restrict__ box,
-               const uint32_t *__restrict__ ntiles, const uint64_t *__restrict__ goff, int64_t n,
-               int64_t G, const legs_view *__restrict__ views, int tile, int64_t capacity,
-               uint32_t *__restrict__ diff)
+k_tile_corners(const GRec *__restrict__ recs, const uint64_t *__restrict__ goff,
+               const uint64_t *__restrict__ vrange, int64_t G,
+               const legs_view *__restrict__ views, int64_t capacity, int64_t total_tiles,
+               uint32_t *__restrict__ diff, uint32_t *__restrict__ partial)
 {
+    __shared__ uint32_t s_grid[TILE_LDS_CELLS];
     __shared__ uint64_t s_start[257];
     __shared__ uint64_t s_w[4];
-    const int64_t pos = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t gv = pos < G ? (int64_t)perm[pos] : 0;
-    const uint64_t c = pos < G ? ntiles[gv] : 0u;
-    block_scan_256(c, s_start, s_w);
-    const uint64_t off = goff[blockIdx.x] + s_start[threadIdx.x];
-    if (c == 0 || off >= (uint64_t)capacity) return;
-    const uint64_t keep = (uint64_t)capacity - off < c ? (uint64_t)capacity - off : c;
-    const int64_t v = gv / n;
+    const int v = blockIdx.y;
     const legs_view vw = views[v];
-    const int4 b = box[gv];
-    const int x0 = b.x / tile, x1 = b.y / tile, y0 = b.z / tile, y1 = b.w / tile;
-    if (keep == c) {
-        diff_rect(diff, vw, x0, x1, y0, y1);
-    } else {
-        const int rw = x1 - x0 + 1;
-        const int rows = (int)(keep / (uint64_t)rw), rem = (int)(keep % (uint64_t)rw);
-        if (rows > 0) diff_rect(diff, vw, x0, x1, y0, y0 + rows - 1);
-        if (rem > 0) diff_rect(diff, vw, x0, x0 + rem - 1, y0 + rows, y0 + rows);
+    const int W = vw.tiles_x, H = vw.tiles_y;
+    const int ncell = W * H;
+    const bool lds = ncell <= TILE_LDS_CELLS;
+    uint32_t *g = lds ? s_grid : diff + vw.tile_offset;
+    if (lds)
+        for (int i = threadIdx.x; i < ncell; i += 256) s_grid[i] = 0u;
+    const int64_t p0 = (int64_t)vrange[2 * v], p1 = (int64_t)vrange[2 * v + 1];
+    __syncthreads();
+    if (p1 > p0) {
+        for (int64_t b = p0 / 256 + blockIdx.x; b <= (p1 - 1) / 256; b += gridDim.x) {
+            const int64_t pos = b * 256 + threadIdx.x;
+            const GRec r = pos < G ? recs[pos] : GRec{0u, 0u, 0u, 0u};
+            block_scan_256<256>(r.cnt, s_start, s_w);
+            const uint64_t off = goff[b] + s_start[threadIdx.x];
+            if (pos >= p0 && pos < p1 && r.cnt && off < (uint64_t)capacity) {
+                const uint64_t keep = (uint64_t)capacity - off < r.cnt ? (uint64_t)capacity - off : r.cnt;
+                const int rw = (int)(r.rwtx & 0xffffu);
+                const int local = (int)((int64_t)r.base - vw.tile_offset);
+                const int x0 = local % W, y0 = local / W;
+                const int rows = (int)(r.cnt / (uint32_t)rw);
+                if (keep == r.cnt) {
+                    diff_rect(g, W, H, x0, x0 + rw - 1, y0, y0 + rows - 1);
+                } else {
+                    const int full = (int)(keep / (uint64_t)rw), rem = (int)(keep % (uint64_t)rw);
+                    if (full > 0) diff_rect(g, W, H, x0, x0 + rw - 1, y0, y0 + full - 1);
+                    if (rem > 0) diff_rect(g, W, H, x0, x0 + rem - 1, y0 + full, y0 + full);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (lds) {
+        __syncthreads();
+        uint32_t *out = partial + (int64_t)blockIdx.x * total_tiles + vw.tile_offset;
+        for (int i = threadIdx.x; i < ncell; i += 256) out[i] = s_grid[i];
+    }
+}
+
+// Sum of the partial grids of views counted in LDS (the others already hold
+// their counts in diff).
+__global__ void __launch_bounds__(256)
+k_tile_merge(const uint32_t *__restrict__ partial, int nch, int64_t total_tiles,
+             const legs_view *__restrict__ views, int n_views, uint32_t *__restrict__ diff)
+{
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total_tiles; t += (int64_t)gridDim.x * 256) {
+        const legs_view &vw = views[legs_view_of_tile(views, n_views, t)];
+        if (vw.tiles_x * vw.tiles_y > TILE_LDS_CELLS) continue;
+        uint32_t acc = 0;
+#pragma unroll 8
+        for (int c = 0; c < nch; ++c) acc += partial[(int64_t)c * total_tiles + t];
+        diff[t] = acc;
     }
 }
 
@@ -697,7 +838,11 @@ legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles)
     L.tile_blocks = (total_tiles + 1023) / 1024;
     L.tsum_off = (L.tcount_off + 4 * total_tiles + 255) & ~(int64_t)255;
     L.toff_off = L.tsum_off + 8 * (L.tile_blocks + 1);
-    L.total = L.toff_off + 8 * (L.tile_blocks + 1) + 8;
+    L.pstart_off = (L.toff_off + 8 * (L.tile_blocks + 1) + 8 + 255) & ~(int64_t)255;
+    const int64_t np_ = total_tiles > 0 ? L.parts : 0;    // the G-view sort needs none of these
+    L.dep_off = (L.pstart_off + 4 * np_ + 255) & ~(int64_t)255;
+    L.part_off = (L.dep_off + (total_tiles > 0 ? 8 * capacity : 0) + 255) & ~(int64_t)255;
+    L.total = L.part_off + 4 * (int64_t)LEGS_TILE_CHUNKS * total_tiles;
     return L;
 }
 
@@ -719,6 +864,7 @@ struct SortScratch {
     uint32_t *tcount;
     uint64_t *tsum, *toff;
     int64_t tile_blocks;
+    uint32_t *pstart, *dep, *partial;
 };
 
 SortScratch sort_scratch_at(void *base, int64_t capacity, int64_t total_tiles = 0)
@@ -735,6 +881,9 @@ SortScratch sort_scratch_at(void *base, int64_t capacity, int64_t total_tiles = 
     S.tsum = reinterpret_cast<uint64_t *>(b + L.tsum_off);
     S.toff = reinterpret_cast<uint64_t *>(b + L.toff_off);
     S.tile_blocks = L.tile_blocks;
+    S.pstart = reinterpret_cast<uint32_t *>(b + L.pstart_off);
+    S.dep = reinterpret_cast<uint32_t *>(b + L.dep_off);
+    S.partial = reinterpret_cast<uint32_t *>(b + L.part_off);
     return S;
 }
 
@@ -759,10 +908,10 @@ int32_t radix_passes(legs_ctx *ctx, const SortScratch &S, uint64_t *k0, uint32_t
     uint64_t *ka = k0, *kb = k1;
     uint32_t *va = v0, *vb = v1;
     for (int p = first; p < last; ++p) {
-        hipLaunchKernelGGL((k_onesweep<uint64_t, false, false>), dim3(gsort), dim3(LEGS_SORT_THREADS), 0, s,
-                           ka, va, kb, vb, count, capacity, p, S.starts,
+        hipLaunchKernelGGL((k_onesweep<uint64_t, false, false, false>), dim3(gsort), dim3(LEGS_SORT_THREADS),
+                           0, s, ka, va, nullptr, kb, vb, nullptr, nullptr, count, capacity, p, S.starts,
                            S.status + (int64_t)(p - first) * S.parts * 256, S.counters + (p - first),
-                           TileEmit{}, TileFinal{});
+                           TileEmit{});
         LEGS_CHECK_LAUNCH(ctx);
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
@@ -772,7 +921,7 @@ int32_t radix_passes(legs_ctx *ctx, const SortScratch &S, uint64_t *k0, uint32_t
 
 struct OrderLayout {
     int64_t G, nbs;
-    int64_t k0, k1, v0, v1, bcounts, offsets, gcount, sort, total;
+    int64_t k0, k1, v0, v1, bcounts, offsets, gcount, recs, dbits, vrange, sort, total;
 };
 
 int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
@@ -790,6 +939,9 @@ OrderLayout order_layout(int64_t n, int32_t n_views)
     L.bcounts = o; o = align256(o + 8 * (L.nbs + 1));
     L.offsets = o; o = align256(o + 8 * (L.nbs + 1));
     L.gcount = o; o = align256(o + 8);
+    L.recs = o; o = align256(o + 16 * L.G);
+    L.dbits = o; o = align256(o + 4 * L.G);
+    L.vrange = o; o = align256(o + 16 * (int64_t)n_views);
     L.sort = o; o = align256(o + legs_sort_layout_for(L.G).total);
     L.total = o;
     return L;
@@ -840,9 +992,15 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
         nblocks = OL.nbs;
         uint64_t *bcounts = reinterpret_cast<uint64_t *>(ord + OL.bcounts);
         offsets = reinterpret_cast<uint64_t *>(ord + OL.offsets);
+        uint64_t *vrange = reinterpret_cast<uint64_t *>(ord + OL.vrange);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t *>(vrange),
+                           (int64_t)4 * n_views, 0u);
         if (nblocks > 0)
-            hipLaunchKernelGGL(k_sorted_block_counts, dim3((unsigned)nblocks), dim3(LEGS_PROJ_BLOCK), 0, s,
-                               perm, proj->ntiles, OL.G, bcounts);
+            hipLaunchKernelGGL(k_sorted_records, dim3((unsigned)nblocks), dim3(LEGS_PROJ_BLOCK), 0, s,
+                               perm, (gpass % 2 == 0) ? ok0 : ok1,
+                               reinterpret_cast<const int4 *>(proj->box), proj->depth, proj->ntiles,
+                               n, OL.G, views, o->tile, reinterpret_cast<GRec *>(ord + OL.recs),
+                               reinterpret_cast<uint32_t *>(ord + OL.dbits), vrange, bcounts);
         hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, bcounts, offsets, nblocks, bins->count);
     } else {
         // 1'. instance offsets in Gaussian order from the projection's block counts
@@ -892,6 +1050,8 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
 
     // 2. per-tile counts of the depth-ordered stream (cut at the capacity),
     //    tile ranges and the tile-digit histograms
+    const GRec *recs = reinterpret_cast<const GRec *>(ord + OL.recs);
+    const uint64_t *vrange = reinterpret_cast<const uint64_t *>(ord + OL.vrange);
     const int tbits = bits_for(total_tiles);
     const int np = tbits > 8 ? (tbits + 7) / 8 : 1;
     const int gclear = grid_for(ctx, S.parts * 256 * np, 256, 8);
@@ -900,11 +1060,13 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(ctx, total_tiles, 256, 8)), dim3(256), 0, s,
                        S.tcount, total_tiles, 0u);
     LEGS_CHECK_LAUNCH(ctx);
-    if (nblocks > 0)
-        hipLaunchKernelGGL(k_tile_corners, dim3((unsigned)nblocks), dim3(256), 0, s, perm,
-                           reinterpret_cast<const int4 *>(proj->box), proj->ntiles, offsets, n,
-                           OL.G, views, o->tile, bins->capacity, S.tcount);
-    LEGS_CHECK_LAUNCH(ctx);
+    // enough workgroups per view to spread the G-views, at most LEGS_TILE_CHUNKS
+    int nch = (int)(((OL.G / (n_views > 0 ? n_views : 1)) + 8191) / 8192);
+    nch = nch < 1 ? 1 : (nch > LEGS_TILE_CHUNKS ? LEGS_TILE_CHUNKS : nch);
+    hipLaunchKernelGGL(k_tile_corners, dim3((unsigned)nch, (unsigned)n_views), dim3(256), 0, s, recs,
+                       offsets, vrange, OL.G, views, bins->capacity, total_tiles, S.tcount, S.partial);
+    hipLaunchKernelGGL(k_tile_merge, dim3(grid_for(ctx, total_tiles, 256, 8)), dim3(256), 0, s,
+                       S.partial, nch, total_tiles, views, n_views, S.tcount);
     hipLaunchKernelGGL(k_tile_rows, dim3(64, (unsigned)n_views), dim3(256), 0, s, S.tcount, views);
     hipLaunchKernelGGL(k_tile_cols, dim3(8, (unsigned)n_views), dim3(256), 0, s, S.tcount, views);
     hipLaunchKernelGGL(k_tile_block_sums, dim3((unsigned)S.tile_blocks), dim3(1024), 0, s, S.tcount,
@@ -914,54 +1076,44 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)S.tile_blocks), dim3(1024), 0, s, S.tcount,
                        total_tiles, S.toff, np, bins->ranges, S.hist);
     hipLaunchKernelGGL(k_digit_starts, dim3(np), dim3(256), 0, s, S.hist, S.starts, 0);
+    if (nblocks > 0)
+        hipLaunchKernelGGL(k_part_blocks, dim3((unsigned)((nblocks + 255) / 256)), dim3(256), 0, s,
+                           offsets, nblocks, S.parts, S.pstart);
     LEGS_CHECK_LAUNCH(ctx);
 
-    // 3. tile passes over 32-bit tile keys: the first generates the instances
-    //    from the depth-ordered G-views, the last writes the 64-bit keys; the
-    //    32-bit keys ping-pong in the two halves of keys_alt, the ids end in ids
+    // 3. tile passes over 32-bit tile keys carrying (id, depth bits): the first
+    //    generates the instances from the depth-ordered G-view records, the last
+    //    writes the 64-bit keys and the ids. The 32-bit keys ping-pong in the two
+    //    halves of keys_alt, the ids between ids_alt and ids, the depth bits in
+    //    the sort scratch.
     uint32_t *tk[2] = {reinterpret_cast<uint32_t *>(bins->keys_alt),
                        reinterpret_cast<uint32_t *>(bins->keys_alt) + bins->capacity};
     uint32_t *tv[2] = {bins->ids, bins->ids_alt};
+    uint32_t *td[2] = {S.dep, S.dep + bins->capacity};
     TileEmit E;
-    E.perm = perm;
-    E.box = reinterpret_cast<const int4 *>(proj->box);
-    E.ntiles = proj->ntiles;
+    E.recs = recs;
+    E.dbits = reinterpret_cast<const uint32_t *>(ord + OL.dbits);
     E.goff = offsets;
+    E.pstart = S.pstart;
     E.nblocks = nblocks;
-    E.n = n;
     E.G = OL.G;
-    E.views = views;
-    E.tile = o->tile;
-    TileFinal F;
-    F.keys64 = bins->keys;
-    F.depth = proj->depth;
-    F.n = n;
-    F.views = views;
-    F.n_views = n_views;
-    const int gsort = grid_for(ctx, bins->capacity, LEGS_SORT_PART, 2);
+    const int gsort = grid_for(ctx, bins->capacity, LEGS_SORT_PART, 3);
     for (int p = 0; p < np; ++p) {
-        // pass p writes buffer (np - 1 - p) % 2, so the last pass writes ids, and
-        // reads what the pass before it wrote
+        // pass p writes buffer (np - 1 - p) % 2 (the last one: ids) and reads
+        // what the pass before it wrote
         const int wo = (np - 1 - p) % 2, ri = 1 - wo;
         uint64_t *st = S.status + (int64_t)p * S.parts * 256;
         uint32_t *ctr = S.counters + p;
         const bool emit = p == 0, fin = p == np - 1;
-        if (emit && fin)
-            hipLaunchKernelGGL((k_onesweep<uint32_t, true, true>), dim3(gsort), dim3(LEGS_SORT_THREADS), 0, s,
-                               tk[ri], tv[ri], tk[wo], tv[wo], bins->count, bins->capacity, p, S.starts,
-                               st, ctr, E, F);
-        else if (emit)
-            hipLaunchKernelGGL((k_onesweep<uint32_t, true, false>), dim3(gsort), dim3(LEGS_SORT_THREADS), 0, s,
-                               tk[ri], tv[ri], tk[wo], tv[wo], bins->count, bins->capacity, p, S.starts,
-                               st, ctr, E, F);
-        else if (fin)
-            hipLaunchKernelGGL((k_onesweep<uint32_t, false, true>), dim3(gsort), dim3(LEGS_SORT_THREADS), 0, s,
-                               tk[ri], tv[ri], tk[wo], tv[wo], bins->count, bins->capacity, p, S.starts,
-                               st, ctr, E, F);
-        else
-            hipLaunchKernelGGL((k_onesweep<uint32_t, false, false>), dim3(gsort), dim3(LEGS_SORT_THREADS), 0, s,
-                               tk[ri], tv[ri], tk[wo], tv[wo], bins->count, bins->capacity, p, S.starts,
-                               st, ctr, E, F);
+#define LEGS_TILE_PASS(EM, FI)                                                                      \
+        hipLaunchKernelGGL((k_onesweep<uint32_t, true, EM, FI>), dim3(gsort), dim3(LEGS_SORT_THREADS), 0, \
+                           s, tk[ri], tv[ri], td[ri], tk[wo], tv[wo], td[wo], bins->keys, bins->count, \
+                           bins->capacity, p, S.starts, st, ctr, E)
+        if (emit && fin) LEGS_TILE_PASS(true, true);
+        else if (emit) LEGS_TILE_PASS(true, false);
+        else if (fin) LEGS_TILE_PASS(false, true);
+        else LEGS_TILE_PASS(false, false);
+#undef LEGS_TILE_PASS
         LEGS_CHECK_LAUNCH(ctx);
     }
     return LEGS_OK;
