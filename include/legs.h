@@ -81,7 +81,8 @@ typedef struct {
  * guard 1.3. */
 typedef struct {
     int32_t tile;      /* tile edge in pixels: 8, 16 or 32 */
-    int32_t lds_batch; /* Gaussians staged in LDS per round: 64, 128 or 256 */
+    int32_t lds_batch; /* Gaussians staged in LDS per round: 64, 128 or 256 (the
+                          backward with one wave per tile stages at most 128) */
     float alpha_max;   /* alpha = min(alpha_max, opacity * exp(power)) */
     float alpha_min;   /* skip a Gaussian at a pixel when alpha < alpha_min */
     float t_min;       /* stop (without blending) when T * (1 - alpha) < t_min */

@@ -65,6 +65,13 @@ __device__ __forceinline__ float falloff_alpha(float dx, float dy, float A, floa
     return clamped ? amax : raw;
 }
 
+__device__ __forceinline__ float opaque_zero()
+{
+    float z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    return z;
+}
+
 __device__ __forceinline__ int sext8(uint32_t v, int sh) { return (int)(int8_t)((v >> sh) & 0xffu); }
 
 // LDS layout of one staged batch of B entries.
@@ -76,6 +83,7 @@ struct Stage {
     float *qx, *qy;  // [B][NQ] mean minus the centre of the block's first pixel
     uint32_t *box;   // [B] tile-relative box, 4 x int8
     uint32_t *id;    // [B]
+    uint32_t *qm;    // [B] bit q: the box meets 8 x 8 block q (row-major) of the tile
     __device__ Stage(void *base, int B)
     {
         c = static_cast<float4 *>(base);
@@ -84,40 +92,87 @@ struct Stage {
         qy = qx + (size_t)B * NQ;
         box = reinterpret_cast<uint32_t *>(qy + (size_t)B * NQ);
         id = box + B;
+        qm = id + B;
     }
-    static size_t bytes(int B) { return (size_t)B * (16 + 4 * CP + 8 * NQ + 4 + 4); }
+    static size_t bytes(int B) { return (size_t)B * (16 + 4 * CP + 8 * NQ + 4 + 4 + 4); }
 };
 
+// Stages nb list entries starting at list position lo: each thread takes
+// entries tid, tid + NT, ...; their ids are loaded first, then every gather of
+// up to two entries is issued before any is stored, so a batch costs two
+// dependent memory latencies. Channel sets of up to 16 values travel the same
+// way; wider ones are read by consecutive threads after the records.
 template <int TILE, int CP, int NT>
 __device__ __forceinline__ void stage_batch(const BlendParams &P, int v, int tile_x0, int tile_y0,
                                             uint32_t lo, int nb, Stage<TILE, CP> &S)
 {
     constexpr int NQ = TILE / 8;
+    constexpr int R = (256 + NT - 1) / NT;       // entries per thread at the largest batch
+    constexpr int RC = R > 2 ? 2 : R;            // entries with loads in flight together
+    constexpr bool DIRECT = CP <= 16;
     const int tid = threadIdx.x;
-    for (int k = tid; k < nb; k += NT) {
-        const uint32_t gid = P.ids[lo + k];
-        const int64_t gv = (int64_t)v * P.n + gid;
-        const double2 m = P.mean2d[gv];
-        const int4 b = P.box[gv];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            S.qx[k * NQ + q] = (float)(m.x - ((double)(tile_x0 + 8 * q) + 0.5));
-            S.qy[k * NQ + q] = (float)(m.y - ((double)(tile_y0 + 8 * q) + 0.5));
-        }
-        const int x0 = min(max(b.x - tile_x0, -1), TILE), x1 = min(max(b.y - tile_x0, -1), TILE);
-        const int y0 = min(max(b.z - tile_y0, -1), TILE), y1 = min(max(b.w - tile_y0, -1), TILE);
-        S.box[k] = (uint32_t)(x0 & 0xff) | ((uint32_t)(x1 & 0xff) << 8) |
-                   ((uint32_t)(y0 & 0xff) << 16) | ((uint32_t)(y1 & 0xff) << 24);
-        S.c[k] = P.conic[gv];
-        S.id[k] = gid;
-    }
-    __syncthreads();
     const int C = P.C;
-    for (int e = tid; e < nb * CP; e += NT) {
-        const int k = e / CP, c = e - k * CP;
-        S.ch[e] = c < C ? P.ch[(int64_t)S.id[k] * C + c] : 0.0f;
+    for (int r0 = 0; r0 < R; r0 += RC) {
+        uint32_t gid[RC];
+        bool ok[RC];
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+            const int k = tid + (r0 + r) * NT;
+            ok[r] = k < nb;
+            gid[r] = ok[r] ? P.ids[lo + k] : 0u;
+        }
+        double2 m[RC];
+        int4 b[RC];
+        float4 cn[RC];
+        float ch[RC][DIRECT ? CP : 1];
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+            if (!ok[r]) continue;
+            const int64_t gv = (int64_t)v * P.n + gid[r];
+            m[r] = P.mean2d[gv];
+            b[r] = P.box[gv];
+            cn[r] = P.conic[gv];
+            if constexpr (DIRECT) {
+                const float *src = P.ch + (int64_t)gid[r] * C;
+#pragma unroll
+                for (int c = 0; c < CP; ++c) ch[r][c] = c < C ? src[c] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+            if (!ok[r]) continue;
+            const int k = tid + (r0 + r) * NT;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                S.qx[k * NQ + q] = (float)(m[r].x - ((double)(tile_x0 + 8 * q) + 0.5));
+                S.qy[k * NQ + q] = (float)(m[r].y - ((double)(tile_y0 + 8 * q) + 0.5));
+            }
+            const int x0 = min(max(b[r].x - tile_x0, -1), TILE), x1 = min(max(b[r].y - tile_x0, -1), TILE);
+            const int y0 = min(max(b[r].z - tile_y0, -1), TILE), y1 = min(max(b[r].w - tile_y0, -1), TILE);
+            S.box[k] = (uint32_t)(x0 & 0xff) | ((uint32_t)(x1 & 0xff) << 8) |
+                       ((uint32_t)(y0 & 0xff) << 16) | ((uint32_t)(y1 & 0xff) << 24);
+            S.c[k] = cn[r];
+            S.id[k] = gid[r];
+            const int bx0 = max(x0, 0) >> 3, bx1 = min(x1, TILE - 1) >> 3;
+            const int by0 = max(y0, 0) >> 3, by1 = min(y1, TILE - 1) >> 3;
+            uint32_t mk = 0;
+            for (int qy = by0; qy <= by1; ++qy)
+                for (int qx = bx0; qx <= bx1; ++qx) mk |= 1u << (qy * NQ + qx);
+            S.qm[k] = mk;
+            if constexpr (DIRECT) {
+#pragma unroll
+                for (int c = 0; c < CP; ++c) S.ch[k * CP + c] = ch[r][c];
+            }
+        }
     }
     __syncthreads();
+    if constexpr (!DIRECT) {
+        for (int e = tid; e < nb * CP; e += NT) {
+            const int k = e / CP, c = e - k * CP;
+            S.ch[e] = c < C ? P.ch[(int64_t)S.id[k] * C + c] : 0.0f;
+        }
+        __syncthreads();
+    }
 }
 
 struct TileInfo {
@@ -188,26 +243,32 @@ k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
             if (__syncthreads_count(!done) == 0) break;
             const int nb = (int)min((uint32_t)B, ti.re - lo);
             stage_batch<TILE, CP, NT>(P, ti.v, ti.tile_x0, ti.tile_y0, lo, nb, S);
-            for (int j = 0; j < nb; ++j) {
-                if (legs_ballot(!done) == 0) break;
-                const uint32_t pk = __builtin_amdgcn_readfirstlane(S.box[j]);
-                const int x0 = sext8(pk, 0), x1 = sext8(pk, 8), y0 = sext8(pk, 16), y1 = sext8(pk, 24);
-                if (x1 < qx0 || x0 > qx0 + 7 || y1 < qy0 || y0 > qy0 + 7) continue;
-                if (done || lx < x0 || lx > x1 || ly < y0 || ly > y1) continue;
-                const float4 cn = S.c[j];
-                const float dx = S.qx[j * NQ + qxi] - fx, dy = S.qy[j * NQ + qyi] - fy;
-                float ep;
-                bool clamped;
-                const float alpha = falloff_alpha(dx, dy, cn.x, cn.y, cn.z, cn.w, P.amax, ep, clamped);
-                if (alpha < P.amin) continue;
-                const float Tn = T * (1.0f - alpha);
-                if (Tn < P.tmin) { done = true; continue; }
-                const float wgt = alpha * T;
-                const float *cj = S.ch + j * CP;
+            // entries whose box meets this wave's 8 x 8 block, 64 at a time from a ballot
+            bool alive = true;
+            for (int c0 = 0; c0 < nb && alive; c0 += LEGS_WAVE) {
+                uint64_t rel = legs_ballot(c0 + l < nb && ((S.qm[c0 + l] >> w) & 1u));
+                while (rel) {
+                    if (legs_ballot(!done) == 0) { alive = false; break; }
+                    const int j = c0 + (int)__builtin_ctzll(rel);
+                    rel &= rel - 1;
+                    const uint32_t pk = S.box[j];
+                    const int x0 = sext8(pk, 0), x1 = sext8(pk, 8), y0 = sext8(pk, 16), y1 = sext8(pk, 24);
+                    if (done || lx < x0 || lx > x1 || ly < y0 || ly > y1) continue;
+                    const float4 cn = S.c[j];
+                    const float dx = S.qx[j * NQ + qxi] - fx, dy = S.qy[j * NQ + qyi] - fy;
+                    float ep;
+                    bool clamped;
+                    const float alpha = falloff_alpha(dx, dy, cn.x, cn.y, cn.z, cn.w, P.amax, ep, clamped);
+                    if (alpha < P.amin) continue;
+                    const float Tn = T * (1.0f - alpha);
+                    if (Tn < P.tmin) { done = true; continue; }
+                    const float wgt = alpha * T;
+                    const float *cj = S.ch + j * CP;
 #pragma unroll
-                for (int c = 0; c < CP; ++c) acc[c] = fmaf(wgt, cj[c], acc[c]);
-                T = Tn;
-                lastpos = (lo - ti.rs) + (uint32_t)j + 1u;
+                    for (int c = 0; c < CP; ++c) acc[c] = fmaf(wgt, cj[c], acc[c]);
+                    T = Tn;
+                    lastpos = (lo - ti.rs) + (uint32_t)j + 1u;
+                }
             }
         }
         if (inside) {
@@ -322,10 +383,13 @@ k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restr
                 float cv[CP];
 #pragma unroll
                 for (int c = 0; c < CP; ++c) cv[c] = S.ch[j * CP + c];
-                float sx = 0.f, sy = 0.f, sxx = 0.f, sxy = 0.f, syy = 0.f, sop = 0.f;
+                // zeros the compiler cannot fold into the first band's arithmetic (a
+                // folded first band gives the skipped-band paths register copies)
+                float sx = opaque_zero(), sy = opaque_zero(), sxx = opaque_zero(), sxy = opaque_zero(),
+                      syy = opaque_zero(), sop = opaque_zero();
                 float acc[NV];
 #pragma unroll
-                for (int c = 0; c < CP; ++c) acc[6 + c] = 0.0f;
+                for (int c = 0; c < CP; ++c) acc[6 + c] = opaque_zero();
                 bool any = false;
                 // Per-lane conditions are folded into the arithmetic (zero weights)
                 // so that only wave-uniform branches remain.
@@ -445,10 +509,14 @@ __global__ void k_zero_counts(unsigned long long *c) { c[threadIdx.x] = 0ull; }
 __global__ void k_zero_counter(uint32_t *c) { *c = 0u; }
 
 template <int TILE, int CP>
-int32_t launch_tile_cp(legs_ctx *ctx, bool fwd, const BlendParams &P, float *out, float *Tf,
+int32_t launch_tile_cp(legs_ctx *ctx, bool fwd, const BlendParams &P0, float *out, float *Tf,
                        uint32_t *last, const float *cTf, const uint32_t *clast, const float *d_out,
                        float *grad2d, float *d_ch, hipStream_t s)
 {
+    BlendParams P = P0;
+    // single-wave backward workgroups stage at most 128 entries: a 256-entry
+    // batch would let LDS, not registers, cap the waves per CU
+    if (!fwd && BwdShape<TILE, CP>::NT == LEGS_WAVE && P.batch > 128) P.batch = 128;
     const size_t lds = Stage<TILE, CP>::bytes(P.batch);
     if (lds > 65536) return legs_set_error(ctx, LEGS_ERR_UNSUPPORTED, "LDS batch too large for C");
     int64_t grid = P.total_tiles;

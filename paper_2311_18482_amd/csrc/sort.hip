@@ -250,6 +250,24 @@ struct TileEmit {
     int64_t nblocks, G;
 };
 
+// Inclusive maximum over lanes 0..l of a wave (DPP row shifts, then the row
+// broadcasts of lanes 15 and 31).
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x)
+{
+    uint32_t t;
+#define LEGS_DPP_MAX(ctrl, rmask)                                                               \
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, ctrl, rmask, 0xF, false);             \
+    x = t > x ? t : x;
+    LEGS_DPP_MAX(0x111, 0xF)   // row_shr:1
+    LEGS_DPP_MAX(0x112, 0xF)   // row_shr:2
+    LEGS_DPP_MAX(0x114, 0xF)   // row_shr:4
+    LEGS_DPP_MAX(0x118, 0xF)   // row_shr:8
+    LEGS_DPP_MAX(0x142, 0xA)   // row_bcast:15 into rows 1 and 3
+    LEGS_DPP_MAX(0x143, 0xC)   // row_bcast:31 into rows 2 and 3
+#undef LEGS_DPP_MAX
+    return x;
+}
+
 // Exclusive scan over a block of T threads of one 64-bit value per thread
 // (threads >= 256 pass 0); s_start[0..256] receives the scan of the first
 // 256 and their total.
@@ -295,7 +313,7 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
     constexpr int NW = T / LEGS_WAVE;
     constexpr int ITEMS = LEGS_SORT_ITEMS;
     constexpr int PART = LEGS_SORT_PART;
-    constexpr int SPT = PART / T;            // partition slots per thread (EMIT)
+    constexpr int SPW = PART / NW;           // partition slots per wave (EMIT)
     static_assert(T >= 256 && T % 256 == 0, "one thread per digit");
     __shared__ K s_keys[PART];
     __shared__ uint32_t s_vals[PART];
@@ -313,7 +331,6 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
     const int64_t parts = (m + PART - 1) / PART;
     const int shift = 8 * pass;
     const int tid = threadIdx.x, lane = legs_lane(), wave = tid / LEGS_WAVE;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     for (;;) {
         if (tid == 0) s_part = (int64_t)atomicAdd(counter, 1u);
@@ -347,10 +364,11 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                 const uint64_t lo = (uint64_t)base > ob ? (uint64_t)base - ob : 0;
                 const uint64_t hi = ((uint64_t)(base + nvalid) - ob) < tot ? (uint64_t)(base + nvalid) - ob : tot;
                 const int e_lo = (int)(ob + lo - (uint64_t)base), e_hi = (int)(ob + hi - (uint64_t)base);
-                // clear the slots of this block, mark each G-view's first slot
+                // clear the slots of this block, mark each G-view's first slot; wave
+                // w owns slots [w SPW, (w + 1) SPW), lane-contiguous in chunks of 64
 #pragma unroll
-                for (int q = 0; q < SPT; ++q) {
-                    const int e = tid * SPT + q;
+                for (int q = 0; q < SPW / LEGS_WAVE; ++q) {
+                    const int e = wave * SPW + q * LEGS_WAVE + lane;
                     if (e >= e_lo && e < e_hi) s_own[e] = 0;
                 }
                 __syncthreads();
@@ -360,36 +378,38 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                     if (first < hi && first < st + c) s_own[(int)(ob + first - (uint64_t)base)] = (uint16_t)(tid + 1);
                 }
                 __syncthreads();
-                // owner of each slot: running maximum of the marks
-                uint32_t own[SPT];
-                uint32_t run = 0;
+                // owner of each slot: running maximum of the marks (per-wave maxima
+                // first, then a DPP max-scan per chunk carried across chunks)
+                uint32_t wm = 0;
 #pragma unroll
-                for (int q = 0; q < SPT; ++q) {
-                    const int e = tid * SPT + q;
+                for (int q = 0; q < SPW / LEGS_WAVE; ++q) {
+                    const int e = wave * SPW + q * LEGS_WAVE + lane;
                     const uint32_t mk = (e >= e_lo && e < e_hi) ? (uint32_t)s_own[e] : 0u;
-                    run = mk > run ? mk : run;
-                    own[q] = run;
+                    wm = mk > wm ? mk : wm;
                 }
-                uint32_t wmax = run;     // inclusive max-scan of the per-thread maxima
-#pragma unroll
-                for (int off = 1; off < LEGS_WAVE; off <<= 1) {
-                    const uint32_t y = (uint32_t)__shfl_up((int)wmax, off, LEGS_WAVE);
-                    if (lane >= off) wmax = y > wmax ? y : wmax;
-                }
-                if (lane == LEGS_WAVE - 1) s_omax[wave] = wmax;
+                wm = wave_incl_max(wm);
+                if (lane == LEGS_WAVE - 1) s_omax[wave] = wm;
                 __syncthreads();
-                uint32_t prev = (uint32_t)__shfl_up((int)wmax, 1, LEGS_WAVE);
-                if (lane == 0) prev = 0;
-                for (int w = 0; w < wave; ++w) prev = s_omax[w] > prev ? s_omax[w] : prev;
+                uint32_t carry = 0;
+                for (int w = 0; w < wave; ++w) carry = s_omax[w] > carry ? s_omax[w] : carry;
 #pragma unroll
-                for (int q = 0; q < SPT; ++q) {
-                    const int e = tid * SPT + q;
-                    if (e >= e_lo && e < e_hi) {
-                        const int o = (int)(own[q] > prev ? own[q] : prev) - 1;
+                for (int q = 0; q < SPW / LEGS_WAVE; ++q) {
+                    const int e = wave * SPW + q * LEGS_WAVE + lane;
+                    const bool in = e >= e_lo && e < e_hi;
+                    uint32_t own = wave_incl_max(in ? (uint32_t)s_own[e] : 0u);
+                    own = own > carry ? own : carry;
+                    carry = (uint32_t)__builtin_amdgcn_readlane((int)own, LEGS_WAVE - 1);
+                    if (in) {
+                        const int o = (int)own - 1;
                         const uint32_t local = (uint32_t)((uint64_t)base + (uint64_t)e - ob - s_gstart[o]);
                         const uint32_t rwtx = s_rwtx[o], rw = rwtx & 0xffffu, tx = rwtx >> 16;
-                        const uint32_t qq = local / rw;
-                        s_keys[e] = (K)(s_rbase[o] + qq * tx + (local - qq * rw));
+                        // local / rw through a float reciprocal (local < 2^24, rw < 2^16:
+                        // the estimate is off by at most a few units, fixed below)
+                        uint32_t qq = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)rw));
+                        int32_t rr = (int32_t)(local - qq * rw);
+                        while (rr < 0) { --qq; rr += (int32_t)rw; }
+                        while (rr >= (int32_t)rw) { ++qq; rr -= (int32_t)rw; }
+                        s_keys[e] = (K)(s_rbase[o] + qq * tx + (uint32_t)rr);
                         s_vals[e] = s_rg[o];
                         if constexpr (DEP) s_dep[e] = s_rd[o];
                     }
@@ -428,19 +448,25 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
             const int e = wave * LEGS_WAVE * ITEMS + i * LEGS_WAVE + lane;
             const bool ok = e < nvalid;
             const uint32_t d = (uint32_t)(key[i] >> shift) & 255u;
-            uint64_t peers = legs_ballot(ok);
+            // lanes with the same digit: per bit, the ballot where the bit is set
+            // and its complement where it is clear (s: all ones where set)
+            const uint64_t okb = legs_ballot(ok);
+            uint32_t plo = (uint32_t)okb, phi = (uint32_t)(okb >> 32);
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
-                const uint64_t bal = legs_ballot((d >> b) & 1u);
-                peers &= ((d >> b) & 1u) ? bal : ~bal;
+                const int32_t sb = ((int32_t)(d << (31 - b))) >> 31;
+                const uint64_t bal = legs_ballot(sb != 0);
+                plo &= ~((uint32_t)bal ^ (uint32_t)sb);
+                phi &= ~((uint32_t)(bal >> 32) ^ (uint32_t)sb);
             }
             // the lowest peer reserves the run for all of them; an LDS atomic keeps
             // the reservation ordered against the next item's reservation
-            const int leader = ok ? __ffsll((unsigned long long)peers) - 1 : lane;
+            const int leader = plo ? __builtin_ctz(plo) : 32 + __builtin_ctz(phi | 0x80000000u);
             uint32_t pre = 0;
-            if (ok && lane == leader) pre = atomicAdd(&s_wh[wave][d], (uint32_t)__popcll(peers));
-            const uint32_t lbase = (uint32_t)__shfl((int)pre, leader, LEGS_WAVE);
-            rank[i] = lbase + (uint32_t)__popcll(peers & lt_mask);
+            if (ok && lane == leader)
+                pre = atomicAdd(&s_wh[wave][d], (uint32_t)(__builtin_popcount(plo) + __builtin_popcount(phi)));
+            const uint32_t lbase = (uint32_t)__shfl((int)pre, ok ? leader : lane, LEGS_WAVE);
+            rank[i] = lbase + __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
         }
         __syncthreads();
         // per digit (threads 0..255): offsets of each wave, partition total
