@@ -83,7 +83,6 @@ struct Stage {
     float *qx, *qy;  // [B][NQ] mean minus the centre of the block's first pixel
     uint32_t *box;   // [B] tile-relative box, 4 x int8
     uint32_t *id;    // [B]
-    uint32_t *qm;    // [B] bit q: the box meets 8 x 8 block q (row-major) of the tile
     __device__ Stage(void *base, int B)
     {
         c = static_cast<float4 *>(base);
@@ -92,9 +91,8 @@ struct Stage {
         qy = qx + (size_t)B * NQ;
         box = reinterpret_cast<uint32_t *>(qy + (size_t)B * NQ);
         id = box + B;
-        qm = id + B;
     }
-    static size_t bytes(int B) { return (size_t)B * (16 + 4 * CP + 8 * NQ + 4 + 4 + 4); }
+    static size_t bytes(int B) { return (size_t)B * (16 + 4 * CP + 8 * NQ + 4 + 4); }
 };
 
 // Stages nb list entries starting at list position lo: each thread takes
@@ -153,12 +151,6 @@ __device__ __forceinline__ void stage_batch(const BlendParams &P, int v, int til
                        ((uint32_t)(y0 & 0xff) << 16) | ((uint32_t)(y1 & 0xff) << 24);
             S.c[k] = cn[r];
             S.id[k] = gid[r];
-            const int bx0 = max(x0, 0) >> 3, bx1 = min(x1, TILE - 1) >> 3;
-            const int by0 = max(y0, 0) >> 3, by1 = min(y1, TILE - 1) >> 3;
-            uint32_t mk = 0;
-            for (int qy = by0; qy <= by1; ++qy)
-                for (int qx = bx0; qx <= bx1; ++qx) mk |= 1u << (qy * NQ + qx);
-            S.qm[k] = mk;
             if constexpr (DIRECT) {
 #pragma unroll
                 for (int c = 0; c < CP; ++c) S.ch[k * CP + c] = ch[r][c];
@@ -239,35 +231,58 @@ k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
         float T = 1.0f;
         uint32_t lastpos = 0;
         bool done = !inside;
+        uint64_t donemask = legs_ballot(done);
         for (uint32_t lo = ti.rs; lo < ti.re; lo += (uint32_t)B) {
             if (__syncthreads_count(!done) == 0) break;
             const int nb = (int)min((uint32_t)B, ti.re - lo);
             stage_batch<TILE, CP, NT>(P, ti.v, ti.tile_x0, ti.tile_y0, lo, nb, S);
-            // entries whose box meets this wave's 8 x 8 block, 64 at a time from a ballot
-            bool alive = true;
-            for (int c0 = 0; c0 < nb && alive; c0 += LEGS_WAVE) {
-                uint64_t rel = legs_ballot(c0 + l < nb && ((S.qm[c0 + l] >> w) & 1u));
+            // 64 entries at a time: lane l computes the mask of this wave's 8 x 8
+            // block pixels inside entry c0 + l's box; an entry is visited only
+            // while it covers a pixel that is not done, and only those lanes work
+            for (int c0 = 0; c0 < nb && ~donemask; c0 += LEGS_WAVE) {
+                uint32_t mlo = 0, mhi = 0;
+                if (c0 + l < nb) {
+                    const uint32_t pk = S.box[c0 + l];
+                    const int cx0 = max(sext8(pk, 0) - qx0, 0), cx1 = min(sext8(pk, 8) - qx0, 7);
+                    const int ry0 = max(sext8(pk, 16) - qy0, 0), ry1 = min(sext8(pk, 24) - qy0, 7);
+                    if (cx0 <= cx1 && ry0 <= ry1) {
+                        const uint32_t xm = (0xffu << cx0) & (0xffu >> (7 - cx1));
+                        const uint32_t xr = xm * 0x01010101u;
+                        const uint64_t rows = (~0ull << (8 * ry0)) & (~0ull >> (8 * (7 - ry1)));
+                        mlo = (uint32_t)rows & xr;
+                        mhi = (uint32_t)(rows >> 32) & xr;
+                    }
+                }
+                uint64_t rel = legs_ballot(((((uint64_t)mhi << 32) | mlo) & ~donemask) != 0);
                 while (rel) {
-                    if (legs_ballot(!done) == 0) { alive = false; break; }
-                    const int j = c0 + (int)__builtin_ctzll(rel);
+                    const int jl = (int)__builtin_ctzll(rel);
                     rel &= rel - 1;
-                    const uint32_t pk = S.box[j];
-                    const int x0 = sext8(pk, 0), x1 = sext8(pk, 8), y0 = sext8(pk, 16), y1 = sext8(pk, 24);
-                    if (done || lx < x0 || lx > x1 || ly < y0 || ly > y1) continue;
-                    const float4 cn = S.c[j];
-                    const float dx = S.qx[j * NQ + qxi] - fx, dy = S.qy[j * NQ + qyi] - fy;
-                    float ep;
-                    bool clamped;
-                    const float alpha = falloff_alpha(dx, dy, cn.x, cn.y, cn.z, cn.w, P.amax, ep, clamped);
-                    if (alpha < P.amin) continue;
-                    const float Tn = T * (1.0f - alpha);
-                    if (Tn < P.tmin) { done = true; continue; }
-                    const float wgt = alpha * T;
-                    const float *cj = S.ch + j * CP;
+                    const uint64_t act = (((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mhi, jl) << 32) |
+                                          (uint32_t)__builtin_amdgcn_readlane((int)mlo, jl)) & ~donemask;
+                    if (act == 0) continue;
+                    if ((act >> l) & 1ull) {
+                        const int j = c0 + jl;
+                        const float4 cn = S.c[j];
+                        const float dx = S.qx[j * NQ + qxi] - fx, dy = S.qy[j * NQ + qyi] - fy;
+                        float ep;
+                        bool clamped;
+                        const float alpha = falloff_alpha(dx, dy, cn.x, cn.y, cn.z, cn.w, P.amax, ep, clamped);
+                        if (!(alpha < P.amin)) {
+                            const float Tn = T * (1.0f - alpha);
+                            if (Tn < P.tmin) {
+                                done = true;
+                            } else {
+                                const float wgt = alpha * T;
+                                const float *cj = S.ch + j * CP;
 #pragma unroll
-                    for (int c = 0; c < CP; ++c) acc[c] = fmaf(wgt, cj[c], acc[c]);
-                    T = Tn;
-                    lastpos = (lo - ti.rs) + (uint32_t)j + 1u;
+                                for (int c = 0; c < CP; ++c) acc[c] = fmaf(wgt, cj[c], acc[c]);
+                                T = Tn;
+                                lastpos = (lo - ti.rs) + (uint32_t)j + 1u;
+                            }
+                        }
+                    }
+                    donemask = legs_ballot(done);
+                    if (!~donemask) break;
                 }
             }
         }
