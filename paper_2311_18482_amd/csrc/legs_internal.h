@@ -89,6 +89,7 @@ struct legs_sort_layout {
     int64_t pstart_off;    // uint32 [parts] first G-view block of each partition
     int64_t dep_off;       // uint32 [2][capacity] depth bits carried by the tile passes
     int64_t part_off;      // uint32 [LEGS_TILE_CHUNKS][total_tiles] partial tile-count grids
+    int64_t seg_off;       // uint32 [2][LEGS_SEG_MAX][256] segment digit counts and starts
     int64_t total;
 };
 legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles = 0);
@@ -98,6 +99,7 @@ legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles = 0)
 #define LEGS_SORT_PART (LEGS_SORT_THREADS * LEGS_SORT_ITEMS)
 #define LEGS_SORT_MAX_PASSES 8
 #define LEGS_TILE_CHUNKS 128
+#define LEGS_SEG_MAX 1024
 // counter slots (u32) in the sort scratch's counter block: 0..15 sort passes
 #define LEGS_BLEND_COUNTER_FWD 32
 #define LEGS_BLEND_COUNTER_BWD 33

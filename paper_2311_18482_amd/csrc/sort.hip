@@ -292,6 +292,100 @@ __device__ __forceinline__ void block_scan_256(uint64_t x, uint64_t *s_start, ui
     __syncthreads();
 }
 
+// LDS of the fused emission.
+struct EmitLds {
+    uint32_t rbase[256], rwtx[256], rg[256], rd[256];
+    uint16_t own[LEGS_SORT_PART];
+    uint32_t omax[LEGS_SORT_THREADS / LEGS_WAVE];
+    uint64_t gscan[257];
+    uint64_t w64[LEGS_SORT_THREADS / LEGS_WAVE];
+};
+
+// Generates instances [base, base + nvalid) of the depth-ordered stream into
+// LDS slots 0 .. nvalid - 1 (tile key, Gaussian id, depth bits): instance e is
+// tile e - start of its G-view's rectangle, row-major. Each G-view marks the
+// first slot it fills and a running maximum over the slots gives every slot
+// its owner. Called by the whole workgroup.
+template <typename K, bool DEP>
+__device__ __forceinline__ void emit_partition(const TileEmit &E, int64_t part, int64_t base, int nvalid,
+                                               K *s_keys, uint32_t *s_vals, uint32_t *s_dep, EmitLds &M)
+{
+    constexpr int T = LEGS_SORT_THREADS;
+    constexpr int NW = T / LEGS_WAVE;
+    constexpr int SPW = LEGS_SORT_PART / NW;   // partition slots per wave
+    const int tid = threadIdx.x, lane = legs_lane(), wave = tid / LEGS_WAVE;
+    for (int64_t b = E.pstart[part]; b < E.nblocks; ++b) {
+        const uint64_t ob = E.goff[b];
+        if (ob >= (uint64_t)(base + nvalid)) break;
+        const int64_t pos = b * 256 + tid;
+        uint32_t c = 0;
+        if (tid < 256 && pos < E.G) {
+            const GRec r = E.recs[pos];
+            c = r.cnt;
+            M.rbase[tid] = r.base;
+            M.rwtx[tid] = r.rwtx;
+            M.rg[tid] = r.gid;
+            M.rd[tid] = c ? E.dbits[pos] : 0u;
+        }
+        block_scan_256<T>(c, M.gscan, M.w64);
+        const uint64_t tot = M.gscan[256];
+        const uint64_t lo = (uint64_t)base > ob ? (uint64_t)base - ob : 0;
+        const uint64_t hi = ((uint64_t)(base + nvalid) - ob) < tot ? (uint64_t)(base + nvalid) - ob : tot;
+        const int e_lo = (int)(ob + lo - (uint64_t)base), e_hi = (int)(ob + hi - (uint64_t)base);
+        // clear the slots of this block, mark each G-view's first slot; wave w
+        // owns slots [w SPW, (w + 1) SPW), lane-contiguous in chunks of 64
+#pragma unroll
+        for (int q = 0; q < SPW / LEGS_WAVE; ++q) {
+            const int e = wave * SPW + q * LEGS_WAVE + lane;
+            if (e >= e_lo && e < e_hi) M.own[e] = 0;
+        }
+        __syncthreads();
+        if (tid < 256 && c) {
+            const uint64_t st = M.gscan[tid];
+            const uint64_t first = st > lo ? st : lo;
+            if (first < hi && first < st + c) M.own[(int)(ob + first - (uint64_t)base)] = (uint16_t)(tid + 1);
+        }
+        __syncthreads();
+        // owner of each slot: running maximum of the marks (per-wave maxima
+        // first, then a DPP max-scan per chunk carried across chunks)
+        uint32_t wm = 0;
+#pragma unroll
+        for (int q = 0; q < SPW / LEGS_WAVE; ++q) {
+            const int e = wave * SPW + q * LEGS_WAVE + lane;
+            const uint32_t mk = (e >= e_lo && e < e_hi) ? (uint32_t)M.own[e] : 0u;
+            wm = mk > wm ? mk : wm;
+        }
+        wm = wave_incl_max(wm);
+        if (lane == LEGS_WAVE - 1) M.omax[wave] = wm;
+        __syncthreads();
+        uint32_t carry = 0;
+        for (int w = 0; w < wave; ++w) carry = M.omax[w] > carry ? M.omax[w] : carry;
+#pragma unroll
+        for (int q = 0; q < SPW / LEGS_WAVE; ++q) {
+            const int e = wave * SPW + q * LEGS_WAVE + lane;
+            const bool in = e >= e_lo && e < e_hi;
+            uint32_t own = wave_incl_max(in ? (uint32_t)M.own[e] : 0u);
+            own = own > carry ? own : carry;
+            carry = (uint32_t)__builtin_amdgcn_readlane((int)own, LEGS_WAVE - 1);
+            if (in) {
+                const int o = (int)own - 1;
+                const uint32_t local = (uint32_t)((uint64_t)base + (uint64_t)e - ob - M.gscan[o]);
+                const uint32_t rwtx = M.rwtx[o], rw = rwtx & 0xffffu, tx = rwtx >> 16;
+                // local / rw through a float reciprocal (local < 2^24, rw < 2^16:
+                // the estimate is off by at most a few units, fixed below)
+                uint32_t qq = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)rw));
+                int32_t rr = (int32_t)(local - qq * rw);
+                while (rr < 0) { --qq; rr += (int32_t)rw; }
+                while (rr >= (int32_t)rw) { ++qq; rr -= (int32_t)rw; }
+                s_keys[e] = (K)(M.rbase[o] + qq * tx + (uint32_t)rr);
+                s_vals[e] = M.rg[o];
+                if constexpr (DEP) s_dep[e] = M.rd[o];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // One onesweep pass over digit `pass` (bits 8 pass .. 8 pass + 7) of keys K
 // with 32-bit values, and with DEP a second 32-bit value (the depth bits)
 // carried along. EMIT: the partition's (tile, id, depth) triples are
@@ -300,20 +394,19 @@ __device__ __forceinline__ void block_scan_256(uint64_t x, uint64_t *s_start, ui
 // marks the first partition slot it fills, and a running maximum over the
 // slots gives every slot its owner. FINAL: the keys are written as the 64-bit
 // (tile << 32) | depth keys of the tile lists.
-template <typename K, bool DEP, bool EMIT, bool FINAL>
+template <typename K, bool DEP, bool EMIT, bool FINAL, bool SEG>
 __global__ void __launch_bounds__(LEGS_SORT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
            const uint32_t *__restrict__ din, K *__restrict__ kout, uint32_t *__restrict__ vout,
            uint32_t *__restrict__ dout, uint64_t *__restrict__ keys64,
            const uint64_t *__restrict__ count, int64_t capacity, int pass,
            const uint32_t *__restrict__ digit_starts, uint64_t *__restrict__ status,
-           uint32_t *__restrict__ counter, TileEmit E)
+           uint32_t *__restrict__ counter, TileEmit E, const uint32_t *__restrict__ seg_off)
 {
     constexpr int T = LEGS_SORT_THREADS;
     constexpr int NW = T / LEGS_WAVE;
     constexpr int ITEMS = LEGS_SORT_ITEMS;
     constexpr int PART = LEGS_SORT_PART;
-    constexpr int SPW = PART / NW;           // partition slots per wave (EMIT)
     static_assert(T >= 256 && T % 256 == 0, "one thread per digit");
     __shared__ K s_keys[PART];
     __shared__ uint32_t s_vals[PART];
@@ -332,8 +425,21 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
     const int shift = 8 * pass;
     const int tid = threadIdx.x, lane = legs_lane(), wave = tid / LEGS_WAVE;
 
+    // SEG: workgroup b owns partitions [b per, (b + 1) per) in order and keeps
+    // the running global start of every digit, seeded from the segment scan
+    __shared__ uint64_t s_run[SEG ? 256 : 1];
+    int64_t per = 0, iseg = 0;
+    if constexpr (SEG) {
+        per = (parts + gridDim.x - 1) / gridDim.x;
+        if (tid < 256) s_run[tid] = seg_off[(int64_t)blockIdx.x * 256 + tid];
+    }
     for (;;) {
-        if (tid == 0) s_part = (int64_t)atomicAdd(counter, 1u);
+        if constexpr (SEG) {
+            if (tid == 0) s_part = iseg < per ? (int64_t)blockIdx.x * per + iseg : parts;
+            ++iseg;
+        } else {
+            if (tid == 0) s_part = (int64_t)atomicAdd(counter, 1u);
+        }
         for (int i = tid; i < NW * 256; i += T) (&s_wh[0][0])[i] = 0;
         __syncthreads();
         const int64_t part = s_part;
@@ -343,79 +449,8 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
         const int nvalid = (int)nvalid64;
 
         if constexpr (EMIT) {
-            __shared__ uint32_t s_rbase[256], s_rwtx[256], s_rg[256], s_rd[256];
-            __shared__ uint16_t s_own[PART];
-            __shared__ uint32_t s_omax[NW];
-            for (int64_t b = E.pstart[part]; b < E.nblocks; ++b) {
-                const uint64_t ob = E.goff[b];
-                if (ob >= (uint64_t)(base + nvalid)) break;
-                const int64_t pos = b * 256 + tid;
-                uint32_t c = 0;
-                if (tid < 256 && pos < E.G) {
-                    const GRec r = E.recs[pos];
-                    c = r.cnt;
-                    s_rbase[tid] = r.base;
-                    s_rwtx[tid] = r.rwtx;
-                    s_rg[tid] = r.gid;
-                    s_rd[tid] = c ? E.dbits[pos] : 0u;
-                }
-                block_scan_256<T>(c, s_gstart, s_w64);
-                const uint64_t tot = s_gstart[256];
-                const uint64_t lo = (uint64_t)base > ob ? (uint64_t)base - ob : 0;
-                const uint64_t hi = ((uint64_t)(base + nvalid) - ob) < tot ? (uint64_t)(base + nvalid) - ob : tot;
-                const int e_lo = (int)(ob + lo - (uint64_t)base), e_hi = (int)(ob + hi - (uint64_t)base);
-                // clear the slots of this block, mark each G-view's first slot; wave
-                // w owns slots [w SPW, (w + 1) SPW), lane-contiguous in chunks of 64
-#pragma unroll
-                for (int q = 0; q < SPW / LEGS_WAVE; ++q) {
-                    const int e = wave * SPW + q * LEGS_WAVE + lane;
-                    if (e >= e_lo && e < e_hi) s_own[e] = 0;
-                }
-                __syncthreads();
-                if (tid < 256 && c) {
-                    const uint64_t st = s_gstart[tid];
-                    const uint64_t first = st > lo ? st : lo;
-                    if (first < hi && first < st + c) s_own[(int)(ob + first - (uint64_t)base)] = (uint16_t)(tid + 1);
-                }
-                __syncthreads();
-                // owner of each slot: running maximum of the marks (per-wave maxima
-                // first, then a DPP max-scan per chunk carried across chunks)
-                uint32_t wm = 0;
-#pragma unroll
-                for (int q = 0; q < SPW / LEGS_WAVE; ++q) {
-                    const int e = wave * SPW + q * LEGS_WAVE + lane;
-                    const uint32_t mk = (e >= e_lo && e < e_hi) ? (uint32_t)s_own[e] : 0u;
-                    wm = mk > wm ? mk : wm;
-                }
-                wm = wave_incl_max(wm);
-                if (lane == LEGS_WAVE - 1) s_omax[wave] = wm;
-                __syncthreads();
-                uint32_t carry = 0;
-                for (int w = 0; w < wave; ++w) carry = s_omax[w] > carry ? s_omax[w] : carry;
-#pragma unroll
-                for (int q = 0; q < SPW / LEGS_WAVE; ++q) {
-                    const int e = wave * SPW + q * LEGS_WAVE + lane;
-                    const bool in = e >= e_lo && e < e_hi;
-                    uint32_t own = wave_incl_max(in ? (uint32_t)s_own[e] : 0u);
-                    own = own > carry ? own : carry;
-                    carry = (uint32_t)__builtin_amdgcn_readlane((int)own, LEGS_WAVE - 1);
-                    if (in) {
-                        const int o = (int)own - 1;
-                        const uint32_t local = (uint32_t)((uint64_t)base + (uint64_t)e - ob - s_gstart[o]);
-                        const uint32_t rwtx = s_rwtx[o], rw = rwtx & 0xffffu, tx = rwtx >> 16;
-                        // local / rw through a float reciprocal (local < 2^24, rw < 2^16:
-                        // the estimate is off by at most a few units, fixed below)
-                        uint32_t qq = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)rw));
-                        int32_t rr = (int32_t)(local - qq * rw);
-                        while (rr < 0) { --qq; rr += (int32_t)rw; }
-                        while (rr >= (int32_t)rw) { ++qq; rr -= (int32_t)rw; }
-                        s_keys[e] = (K)(s_rbase[o] + qq * tx + (uint32_t)rr);
-                        s_vals[e] = s_rg[o];
-                        if constexpr (DEP) s_dep[e] = s_rd[o];
-                    }
-                }
-                __syncthreads();
-            }
+            __shared__ EmitLds s_emit;
+            emit_partition<K, DEP>(E, part, base, nvalid, s_keys, s_vals, s_dep, s_emit);
         }
 
         K key[ITEMS];
@@ -480,7 +515,7 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                 s_wh[w][d] = t;
                 t += c;
             }
-            st_status(status + part * 256 + d, (part == 0 ? FLAG_INC : FLAG_AGG) | (uint64_t)t);
+            if constexpr (!SEG) st_status(status + part * 256 + d, (part == 0 ? FLAG_INC : FLAG_AGG) | (uint64_t)t);
             incl = t;
 #pragma unroll
             for (int off = 1; off < LEGS_WAVE; off <<= 1) {
@@ -509,8 +544,12 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                 if constexpr (DEP) s_dep[pos] = dep[i];
             }
         }
-        // look-back for the global start of each digit run
-        if (tid < 256) {
+        // global start of each digit run: the segment's running start, or a
+        // look-back over the partitions before this one
+        if (SEG && tid < 256) {
+            s_gstart[tid] = s_run[tid] - (uint64_t)lstart;
+            s_run[tid] += t;
+        } else if (tid < 256) {
             const int d = tid;
             uint64_t excl = 0;
             if (part > 0) {
@@ -565,6 +604,139 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
         }
         __syncthreads();
     }
+}
+
+// Digit counts of pass `pass` over the partitions of segment blockIdx.x (the
+// same segments as the segment passes: per = ceil(partitions / gridDim.x)).
+__global__ void __launch_bounds__(LEGS_SORT_THREADS)
+k_tile_upsweep(const uint32_t *__restrict__ kin, const uint64_t *__restrict__ count, int64_t capacity,
+               int pass, uint32_t *__restrict__ seg_hist)
+{
+    constexpr int T = LEGS_SORT_THREADS, PART = LEGS_SORT_PART, ITEMS = LEGS_SORT_ITEMS;
+    __shared__ uint32_t s_hist[256];
+    const int tid = threadIdx.x;
+    if (tid < 256) s_hist[tid] = 0;
+    __syncthreads();
+    const uint64_t cnt = *count;
+    const int64_t m = (int64_t)(cnt < (uint64_t)capacity ? cnt : (uint64_t)capacity);
+    const int64_t parts = (m + PART - 1) / PART;
+    const int64_t per = (parts + gridDim.x - 1) / gridDim.x;
+    const int shift = 8 * pass;
+    for (int64_t i = 0; i < per; ++i) {
+        const int64_t part = (int64_t)blockIdx.x * per + i;
+        if (part >= parts) break;
+        const int64_t base = part * PART;
+        const int nvalid = (int)(m - base < PART ? m - base : PART);
+        uint32_t k[ITEMS];
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q) {
+            const int e = tid + q * T;
+            k[q] = e < nvalid ? kin[base + e] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q)
+            if (tid + q * T < nvalid) atomicAdd(&s_hist[(k[q] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (tid < 256) seg_hist[(int64_t)blockIdx.x * 256 + tid] = s_hist[tid];
+}
+
+// Start of every digit run of every segment: the digit's global start plus the
+// counts of the segments before. One workgroup per digit, one thread per
+// segment (nseg <= LEGS_SEG_MAX).
+__global__ void __launch_bounds__(LEGS_SEG_MAX)
+k_seg_scan(const uint32_t *__restrict__ seg_hist, int nseg, const uint32_t *__restrict__ digit_starts,
+           int pass, uint32_t *__restrict__ seg_off)
+{
+    __shared__ uint32_t s_w[LEGS_SEG_MAX / LEGS_WAVE];
+    const int d = blockIdx.x, sg = threadIdx.x;
+    const int lane = legs_lane(), wave = sg / LEGS_WAVE;
+    const uint32_t x = sg < nseg ? seg_hist[(int64_t)sg * 256 + d] : 0u;
+    uint32_t incl = x;
+#pragma unroll
+    for (int off = 1; off < LEGS_WAVE; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, LEGS_WAVE);
+        if (lane >= off) incl += y;
+    }
+    if (lane == LEGS_WAVE - 1) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t pre = digit_starts[pass * 256 + d];
+    for (int w = 0; w < wave; ++w) pre += s_w[w];
+    if (sg < nseg) seg_off[(int64_t)sg * 256 + d] = pre + incl - x;
+}
+
+// Low-byte tile counts of segment blockIdx.x of the depth-ordered stream (the
+// first tile pass), from the G-view records without generating the instances:
+// every row of a rectangle covers consecutive tile ids, i.e. a cyclic range
+// of low bytes, added to a 257-entry difference array (full turns of 256 to
+// every byte at once).
+__global__ void __launch_bounds__(256)
+k_tile_upsweep_emit(const uint64_t *__restrict__ count, int64_t capacity, TileEmit E,
+                    uint32_t *__restrict__ seg_hist)
+{
+    constexpr int PART = LEGS_SORT_PART;
+    __shared__ uint32_t s_d[257];
+    __shared__ uint32_t s_all;
+    __shared__ uint64_t s_start[257];
+    __shared__ uint64_t s_w[4];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 257; i += 256) s_d[i] = 0;
+    if (tid == 0) s_all = 0;
+    const uint64_t cnt = *count;
+    const int64_t m = (int64_t)(cnt < (uint64_t)capacity ? cnt : (uint64_t)capacity);
+    const int64_t parts = (m + PART - 1) / PART;
+    const int64_t per = (parts + gridDim.x - 1) / gridDim.x;
+    const int64_t p0 = (int64_t)blockIdx.x * per;
+    __syncthreads();
+    if (p0 < parts) {
+        const uint64_t s0 = (uint64_t)p0 * PART;
+        const uint64_t s1 = (uint64_t)((p0 + per) * PART < m ? (p0 + per) * PART : m);
+        for (int64_t b = E.pstart[p0]; b < E.nblocks; ++b) {
+            const uint64_t ob = E.goff[b];
+            if (ob >= s1) break;
+            const int64_t pos = b * 256 + tid;
+            const GRec r = pos < E.G ? E.recs[pos] : GRec{0u, 0u, 0u, 0u};
+            block_scan_256<256>(r.cnt, s_start, s_w);
+            const uint64_t st = ob + s_start[tid];
+            const uint64_t u0g = st > s0 ? st : s0, u1g = st + r.cnt < s1 ? st + r.cnt : s1;
+            if (r.cnt && u0g < u1g) {
+                const uint32_t rw = r.rwtx & 0xffffu, tx = r.rwtx >> 16;
+                const uint32_t u0 = (uint32_t)(u0g - st), u1 = (uint32_t)(u1g - st);   // [u0, u1) of the rectangle
+                for (uint32_t row = u0 / rw; row * rw < u1; ++row) {
+                    const uint32_t c0 = row * rw < u0 ? u0 - row * rw : 0u;
+                    const uint32_t c1 = (row + 1) * rw < u1 ? rw : u1 - row * rw;   // columns [c0, c1)
+                    const uint32_t a = (r.base + row * tx + c0) & 255u, len = c1 - c0;
+                    if (len >> 8) atomicAdd(&s_all, len >> 8);
+                    const uint32_t rem = len & 255u;
+                    if (rem) {
+                        atomicAdd(&s_d[a], 1u);
+                        if (a + rem <= 256u) {
+                            atomicAdd(&s_d[a + rem], 0xffffffffu);
+                        } else {
+                            atomicAdd(&s_d[256], 0xffffffffu);
+                            atomicAdd(&s_d[0], 1u);
+                            atomicAdd(&s_d[a + rem - 256u], 0xffffffffu);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    // inclusive prefix of the difference array over the 256 bytes
+    const int lane = legs_lane(), wave = tid / LEGS_WAVE;
+    uint32_t incl = s_d[tid];
+#pragma unroll
+    for (int off = 1; off < LEGS_WAVE; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, LEGS_WAVE);
+        if (lane >= off) incl += y;
+    }
+    __shared__ uint32_t s_t[4];
+    if (lane == LEGS_WAVE - 1) s_t[wave] = incl;
+    __syncthreads();
+    for (int w = 0; w < wave; ++w) incl += s_t[w];
+    seg_hist[(int64_t)blockIdx.x * 256 + tid] = incl + s_all;
 }
 
 // ---- depth order of the G-views ---------------------------------------------------
@@ -868,7 +1040,8 @@ legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles)
     const int64_t np_ = total_tiles > 0 ? L.parts : 0;    // the G-view sort needs none of these
     L.dep_off = (L.pstart_off + 4 * np_ + 255) & ~(int64_t)255;
     L.part_off = (L.dep_off + (total_tiles > 0 ? 8 * capacity : 0) + 255) & ~(int64_t)255;
-    L.total = L.part_off + 4 * (int64_t)LEGS_TILE_CHUNKS * total_tiles;
+    L.seg_off = (L.part_off + 4 * (int64_t)LEGS_TILE_CHUNKS * total_tiles + 255) & ~(int64_t)255;
+    L.total = L.seg_off + (total_tiles > 0 ? 2 * 4 * (int64_t)LEGS_SEG_MAX * 256 : 0);
     return L;
 }
 
@@ -890,7 +1063,7 @@ struct SortScratch {
     uint32_t *tcount;
     uint64_t *tsum, *toff;
     int64_t tile_blocks;
-    uint32_t *pstart, *dep, *partial;
+    uint32_t *pstart, *dep, *partial, *seg_hist, *seg_off;
 };
 
 SortScratch sort_scratch_at(void *base, int64_t capacity, int64_t total_tiles = 0)
@@ -910,6 +1083,8 @@ SortScratch sort_scratch_at(void *base, int64_t capacity, int64_t total_tiles = 
     S.pstart = reinterpret_cast<uint32_t *>(b + L.pstart_off);
     S.dep = reinterpret_cast<uint32_t *>(b + L.dep_off);
     S.partial = reinterpret_cast<uint32_t *>(b + L.part_off);
+    S.seg_hist = reinterpret_cast<uint32_t *>(b + L.seg_off);
+    S.seg_off = S.seg_hist + (int64_t)LEGS_SEG_MAX * 256;
     return S;
 }
 
@@ -934,10 +1109,10 @@ int32_t radix_passes(legs_ctx *ctx, const SortScratch &S, uint64_t *k0, uint32_t
     uint64_t *ka = k0, *kb = k1;
     uint32_t *va = v0, *vb = v1;
     for (int p = first; p < last; ++p) {
-        hipLaunchKernelGGL((k_onesweep<uint64_t, false, false, false>), dim3(gsort), dim3(LEGS_SORT_THREADS),
-                           0, s, ka, va, nullptr, kb, vb, nullptr, nullptr, count, capacity, p, S.starts,
-                           S.status + (int64_t)(p - first) * S.parts * 256, S.counters + (p - first),
-                           TileEmit{});
+        hipLaunchKernelGGL((k_onesweep<uint64_t, false, false, false, false>), dim3(gsort),
+                           dim3(LEGS_SORT_THREADS), 0, s, ka, va, nullptr, kb, vb, nullptr, nullptr, count,
+                           capacity, p, S.starts, S.status + (int64_t)(p - first) * S.parts * 256,
+                           S.counters + (p - first), TileEmit{}, nullptr);
         LEGS_CHECK_LAUNCH(ctx);
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
@@ -1080,9 +1255,8 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     const uint64_t *vrange = reinterpret_cast<const uint64_t *>(ord + OL.vrange);
     const int tbits = bits_for(total_tiles);
     const int np = tbits > 8 ? (tbits + 7) / 8 : 1;
-    const int gclear = grid_for(ctx, S.parts * 256 * np, 256, 8);
-    hipLaunchKernelGGL(k_sort_clear, dim3(gclear), dim3(256), 0, s, S.status, S.parts, np,
-                       S.counters, S.hist, bins->count, bins->capacity);
+    hipLaunchKernelGGL(k_sort_clear, dim3(1), dim3(256), 0, s, S.status, S.parts, 0, S.counters,
+                       S.hist, bins->count, bins->capacity);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(ctx, total_tiles, 256, 8)), dim3(256), 0, s,
                        S.tcount, total_tiles, 0u);
     LEGS_CHECK_LAUNCH(ctx);
@@ -1123,18 +1297,26 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     E.pstart = S.pstart;
     E.nblocks = nblocks;
     E.G = OL.G;
-    const int gsort = grid_for(ctx, bins->capacity, LEGS_SORT_PART, 3);
+    // every tile pass: digit counts per segment of partitions, their scan, then
+    // the pass itself with each workgroup walking its own segment in order
+    const int nseg = (int)(ctx->num_cus * 2 < LEGS_SEG_MAX ? ctx->num_cus * 2 : LEGS_SEG_MAX);
     for (int p = 0; p < np; ++p) {
         // pass p writes buffer (np - 1 - p) % 2 (the last one: ids) and reads
         // what the pass before it wrote
         const int wo = (np - 1 - p) % 2, ri = 1 - wo;
-        uint64_t *st = S.status + (int64_t)p * S.parts * 256;
-        uint32_t *ctr = S.counters + p;
         const bool emit = p == 0, fin = p == np - 1;
+        if (emit)
+            hipLaunchKernelGGL(k_tile_upsweep_emit, dim3(nseg), dim3(256), 0, s, bins->count, bins->capacity,
+                               E, S.seg_hist);
+        else
+            hipLaunchKernelGGL(k_tile_upsweep, dim3(nseg), dim3(LEGS_SORT_THREADS), 0, s, tk[ri],
+                               bins->count, bins->capacity, p, S.seg_hist);
+        hipLaunchKernelGGL(k_seg_scan, dim3(256), dim3(LEGS_SEG_MAX), 0, s, S.seg_hist, nseg, S.starts, p,
+                           S.seg_off);
 #define LEGS_TILE_PASS(EM, FI)                                                                      \
-        hipLaunchKernelGGL((k_onesweep<uint32_t, true, EM, FI>), dim3(gsort), dim3(LEGS_SORT_THREADS), 0, \
-                           s, tk[ri], tv[ri], td[ri], tk[wo], tv[wo], td[wo], bins->keys, bins->count, \
-                           bins->capacity, p, S.starts, st, ctr, E)
+        hipLaunchKernelGGL((k_onesweep<uint32_t, true, EM, FI, true>), dim3(nseg), dim3(LEGS_SORT_THREADS), \
+                           0, s, tk[ri], tv[ri], td[ri], tk[wo], tv[wo], td[wo], bins->keys, bins->count, \
+                           bins->capacity, p, S.starts, nullptr, nullptr, E, S.seg_off)
         if (emit && fin) LEGS_TILE_PASS(true, true);
         else if (emit) LEGS_TILE_PASS(true, false);
         else if (fin) LEGS_TILE_PASS(false, true);
