@@ -252,11 +252,14 @@ int32_t legs_decode_folded(legs_ctx *ctx, const float *feat, int64_t P, int64_t 
                            int64_t p_stride, const float *folded, int32_t K, float *probs,
                            int32_t *top1, void *stream);
 
-/* Learned decode softmax(D_MLP(f)), D_MLP = 8 -> 64 -> 64 -> K per-pixel
- * linear layers with ReLU (1x1 convolutions, the pattern of Table 3). params
- * are float32 masters packed W1 [64][8], b1 [64], W2 [64][64], b2 [64],
+/* Learned decode softmax(D_MLP(f / |f|)), D_MLP = 8 -> 64 -> 64 -> K
+ * per-pixel linear layers with ReLU (1x1 convolutions, the pattern of
+ * Table 3) applied to the feature divided by its Euclidean norm (a zero
+ * feature stays zero; the codes depend only on the direction). params are
+ * float32 masters packed W1 [64][8], b1 [64], W2 [64][64], b2 [64],
  * W3 [K][64], b3 [K]; weights, input and hidden activations are rounded to
- * bf16 (nearest even), accumulation and biases are float32. */
+ * bf16 (nearest even), accumulation and biases are float32. Training
+ * (legs_mlp_grad, legs_mlp_train_step) uses the same forward. */
 int64_t legs_mlp_param_count(int32_t K);
 int32_t legs_decode_mlp(legs_ctx *ctx, const float *feat, int64_t P, int64_t c_stride,
                         int64_t p_stride, const float *params, int32_t K, float *probs,

@@ -7,8 +7,9 @@ loss (test infrastructure only; never imported by the product path).
                  softmax over the scores, top-1 = argmax (lowest index on ties).
   mlp_forward    Eq. 8 / supplementary inference equation: softmax(D_MLP(R_s)),
                  D_MLP a stack of 1x1 convolutions = per-pixel linear layers
-                 with ReLU (Table 3 gives the layer pattern); bf16 rounding of
-                 the input, weights and hidden activations is emulated exactly,
+                 with ReLU (Table 3 gives the layer pattern), applied to the
+                 feature divided by its norm; bf16 rounding of the input,
+                 weights and hidden activations is emulated exactly,
                  accumulation is in float64.
   mlp_train_step Eq. 9 cross-entropy against index labels, gradients by the
                  chain rule (straight through the bf16 roundings), then Adam.
@@ -54,18 +55,24 @@ def decode_plain(feat, proj, codebook):
 
 def mlp_forward(feat, weights, biases, amb_tol=2e-6):
     """Per-pixel MLP with ReLU between layers. weights[l] is [out, in] (float32
-    master), biases[l] [out] (float32). Returns a dict with the bf16-rounded
-    input, pre-activations z_l, post-activations h_l and float64 logits.
+    master), biases[l] [out] (float32). The feature is first divided by its
+    Euclidean norm (a zero feature stays zero): the codes it is trained to
+    predict depend only on the feature's direction (cosine scores, Eq. 4).
+    Returns a dict with the bf16-rounded input, pre-activations z_l,
+    post-activations h_l and float64 logits.
 
-    `ambiguous` flags pixels with a hidden activation within a relative amb_tol
-    of a bf16 rounding midpoint: a float32 accumulation (error ~1e-7 relative)
-    may round such a value to the other neighbour, so those pixels are checked
-    only loosely against an implementation that accumulates in float32."""
-    x = bf16(np.asarray(feat, np.float32).astype(np.float64))
+    `ambiguous` flags pixels with an input or hidden activation within a
+    relative amb_tol of a bf16 rounding midpoint: a float32 computation (error
+    ~1e-7 relative) may round such a value to the other neighbour, so those
+    pixels are checked only loosely against an implementation in float32."""
+    f = np.asarray(feat, np.float32).astype(np.float64)
+    nrm = np.sqrt(np.sum(f * f, axis=1, keepdims=True))
+    u = np.where(nrm > 0.0, f / np.where(nrm > 0.0, nrm, 1.0), 0.0)
+    x = bf16(u)
     hs = [x]
     zs = []
     h = x
-    amb = np.zeros(x.shape[0], bool)
+    amb = np.any(bf16(u * (1 + amb_tol)) != bf16(u * (1 - amb_tol)), axis=1)
     L = len(weights)
     for l in range(L):
         W = bf16(np.asarray(weights[l], np.float32).astype(np.float64))

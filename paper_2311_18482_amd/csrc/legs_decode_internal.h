@@ -98,8 +98,16 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds &L, const float *_
     const int lane = __lane_id(), h = lane >> 5;
     legs_bf16x8 x = {};
     if (h == 0 && valid) {
+        // the feature divided by its Euclidean norm (zero stays zero)
+        float v[LEGS_MLP_IN], ss = 0.0f;
 #pragma unroll
-        for (int e = 0; e < LEGS_MLP_IN; ++e) x[e] = (__bf16)legs_ldfeat(feat, p, e, cs, ps);
+        for (int e = 0; e < LEGS_MLP_IN; ++e) {
+            v[e] = legs_ldfeat(feat, p, e, cs, ps);
+            ss = fmaf(v[e], v[e], ss);
+        }
+        const float nrm = sqrtf(ss);
+#pragma unroll
+        for (int e = 0; e < LEGS_MLP_IN; ++e) x[e] = (__bf16)(nrm > 0.0f ? v[e] / nrm : 0.0f);
     }
     T.x = x;
 #pragma unroll

@@ -558,7 +558,8 @@ def test_decode_plain_reduces_to_folded_argmax_and_torch_softmax():
 
 
 def _torch_mlp(torch, x, ws, bs):
-    h = torch.from_numpy(D.bf16(x.astype(np.float64)))
+    xt = torch.from_numpy(x.astype(np.float64))
+    h = torch.from_numpy(D.bf16(torch.nn.functional.normalize(xt, dim=1).numpy()))
     for l, (W, b) in enumerate(zip(ws, bs)):
         h = torch.nn.functional.linear(h, W, b)
         if l < len(ws) - 1:
@@ -585,6 +586,25 @@ def test_mlp_forward_and_grads_match_torch():
     for l in range(3):
         assert np.allclose(gW[l], Wt[l].grad.numpy(), rtol=1e-10, atol=1e-14)
         assert np.allclose(gb[l], bt[l].grad.numpy(), rtol=1e-10, atol=1e-14)
+
+
+def test_mlp_input_is_scale_free():
+    """The decoder sees only the feature's direction: a positive rescale of a
+    feature leaves its logits unchanged, and a zero feature gives the logits
+    of a zero input (the biases pushed through the layers)."""
+    rng = np.random.default_rng(5)
+    x = rng.normal(0, 1, (300, 8)).astype(np.float32)
+    ws, bs = synth.mlp_init((8, 64, 64, 32), 6)
+    a = D.mlp_forward(x, ws, bs)
+    b = D.mlp_forward((x * np.float32(4.0)), ws, bs)    # exact rescale by a power of two
+    assert np.array_equal(a["logits"], b["logits"])
+    z = D.mlp_forward(np.zeros((1, 8), np.float32), ws, bs)["logits"][0]
+    h = np.zeros(8)
+    for l, (W, bb) in enumerate(zip(ws, bs)):
+        h = D.bf16(W.astype(np.float64)) @ h + bb.astype(np.float64)
+        if l < 2:
+            h = D.bf16(np.maximum(h, 0.0))
+    assert np.allclose(z, h, rtol=0, atol=1e-12)
 
 
 def test_adam_first_step_closed_form_and_torch():
