@@ -399,7 +399,7 @@ __global__ void __launch_bounds__(LEGS_SORT_THREADS) __attribute__((amdgpu_waves
 k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
            const uint32_t *__restrict__ din, K *__restrict__ kout, uint32_t *__restrict__ vout,
            uint32_t *__restrict__ dout, uint64_t *__restrict__ keys64,
-           const uint64_t *__restrict__ count, int64_t capacity, int pass,
+           const uint64_t *__restrict__ count, int64_t capacity, int pass, int shift, int rb,
            const uint32_t *__restrict__ digit_starts, uint64_t *__restrict__ status,
            uint32_t *__restrict__ counter, TileEmit E, const uint32_t *__restrict__ seg_off)
 {
@@ -422,7 +422,7 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
     const uint64_t cnt = *count;
     const int64_t m = (int64_t)(cnt < (uint64_t)capacity ? cnt : (uint64_t)capacity);
     const int64_t parts = (m + PART - 1) / PART;
-    const int shift = 8 * pass;
+    const uint32_t dmask = (1u << rb) - 1u;    // digit = bits [shift, shift + rb) of the key
     const int tid = threadIdx.x, lane = legs_lane(), wave = tid / LEGS_WAVE;
 
     // SEG: workgroup b owns partitions [b per, (b + 1) per) in order and keeps
@@ -482,13 +482,14 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
         for (int i = 0; i < ITEMS; ++i) {
             const int e = wave * LEGS_WAVE * ITEMS + i * LEGS_WAVE + lane;
             const bool ok = e < nvalid;
-            const uint32_t d = (uint32_t)(key[i] >> shift) & 255u;
+            const uint32_t d = (uint32_t)(key[i] >> shift) & dmask;
             // lanes with the same digit: per bit, the ballot where the bit is set
             // and its complement where it is clear (s: all ones where set)
             const uint64_t okb = legs_ballot(ok);
             uint32_t plo = (uint32_t)okb, phi = (uint32_t)(okb >> 32);
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
+                if (b >= rb) break;
                 const int32_t sb = ((int32_t)(d << (31 - b))) >> 31;
                 const uint64_t bal = legs_ballot(sb != 0);
                 plo &= ~((uint32_t)bal ^ (uint32_t)sb);
@@ -537,7 +538,7 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
         for (int i = 0; i < ITEMS; ++i) {
             const int e = wave * LEGS_WAVE * ITEMS + i * LEGS_WAVE + lane;
             if (e < nvalid) {
-                const uint32_t d = (uint32_t)(key[i] >> shift) & 255u;
+                const uint32_t d = (uint32_t)(key[i] >> shift) & dmask;
                 const uint32_t pos = s_lstart[d] + s_wh[wave][d] + rank[i];
                 s_keys[pos] = key[i];
                 s_vals[pos] = val[i];
@@ -588,7 +589,7 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
             const int k = tid + j * T;
             if (k < nvalid) {
                 const K kk = s_keys[k];
-                const uint32_t d = (uint32_t)(kk >> shift) & 255u;
+                const uint32_t d = (uint32_t)(kk >> shift) & dmask;
                 const uint64_t gpos = s_gstart[d] + (uint64_t)k;
                 if (gpos < (uint64_t)capacity) {
                     if constexpr (FINAL) {
@@ -610,7 +611,7 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
 // same segments as the segment passes: per = ceil(partitions / gridDim.x)).
 __global__ void __launch_bounds__(LEGS_SORT_THREADS)
 k_tile_upsweep(const uint32_t *__restrict__ kin, const uint64_t *__restrict__ count, int64_t capacity,
-               int pass, uint32_t *__restrict__ seg_hist)
+               int shift, int rb, uint32_t *__restrict__ seg_hist)
 {
     constexpr int T = LEGS_SORT_THREADS, PART = LEGS_SORT_PART, ITEMS = LEGS_SORT_ITEMS;
     __shared__ uint32_t s_hist[256];
@@ -621,7 +622,7 @@ k_tile_upsweep(const uint32_t *__restrict__ kin, const uint64_t *__restrict__ co
     const int64_t m = (int64_t)(cnt < (uint64_t)capacity ? cnt : (uint64_t)capacity);
     const int64_t parts = (m + PART - 1) / PART;
     const int64_t per = (parts + gridDim.x - 1) / gridDim.x;
-    const int shift = 8 * pass;
+    const uint32_t dmask = (1u << rb) - 1u;
     for (int64_t i = 0; i < per; ++i) {
         const int64_t part = (int64_t)blockIdx.x * per + i;
         if (part >= parts) break;
@@ -635,7 +636,7 @@ k_tile_upsweep(const uint32_t *__restrict__ kin, const uint64_t *__restrict__ co
         }
 #pragma unroll
         for (int q = 0; q < ITEMS; ++q)
-            if (tid + q * T < nvalid) atomicAdd(&s_hist[(k[q] >> shift) & 255u], 1u);
+            if (tid + q * T < nvalid) atomicAdd(&s_hist[(k[q] >> shift) & dmask], 1u);
     }
     __syncthreads();
     if (tid < 256) seg_hist[(int64_t)blockIdx.x * 256 + tid] = s_hist[tid];
@@ -665,15 +666,16 @@ k_seg_scan(const uint32_t *__restrict__ seg_hist, int nseg, const uint32_t *__re
     if (sg < nseg) seg_off[(int64_t)sg * 256 + d] = pre + incl - x;
 }
 
-// Low-byte tile counts of segment blockIdx.x of the depth-ordered stream (the
-// first tile pass), from the G-view records without generating the instances:
-// every row of a rectangle covers consecutive tile ids, i.e. a cyclic range
-// of low bytes, added to a 257-entry difference array (full turns of 256 to
-// every byte at once).
+// Counts of the low rb bits of the tile ids in segment blockIdx.x of the
+// depth-ordered stream (the first tile pass), from the G-view records without
+// generating the instances: every row of a rectangle covers consecutive tile
+// ids, i.e. a cyclic range of digits, added to a difference array (full turns
+// of 2^rb to every digit at once).
 __global__ void __launch_bounds__(256)
-k_tile_upsweep_emit(const uint64_t *__restrict__ count, int64_t capacity, TileEmit E,
+k_tile_upsweep_emit(const uint64_t *__restrict__ count, int64_t capacity, TileEmit E, int rb,
                     uint32_t *__restrict__ seg_hist)
 {
+    const uint32_t nd = 1u << rb;   // the first pass sorts the low rb bits of the tile id
     constexpr int PART = LEGS_SORT_PART;
     __shared__ uint32_t s_d[257];
     __shared__ uint32_t s_all;
@@ -705,17 +707,17 @@ k_tile_upsweep_emit(const uint64_t *__restrict__ count, int64_t capacity, TileEm
                 for (uint32_t row = u0 / rw; row * rw < u1; ++row) {
                     const uint32_t c0 = row * rw < u0 ? u0 - row * rw : 0u;
                     const uint32_t c1 = (row + 1) * rw < u1 ? rw : u1 - row * rw;   // columns [c0, c1)
-                    const uint32_t a = (r.base + row * tx + c0) & 255u, len = c1 - c0;
-                    if (len >> 8) atomicAdd(&s_all, len >> 8);
-                    const uint32_t rem = len & 255u;
+                    const uint32_t a = (r.base + row * tx + c0) & (nd - 1u), len = c1 - c0;
+                    if (len >> rb) atomicAdd(&s_all, len >> rb);
+                    const uint32_t rem = len & (nd - 1u);
                     if (rem) {
                         atomicAdd(&s_d[a], 1u);
-                        if (a + rem <= 256u) {
+                        if (a + rem <= nd) {
                             atomicAdd(&s_d[a + rem], 0xffffffffu);
                         } else {
-                            atomicAdd(&s_d[256], 0xffffffffu);
+                            atomicAdd(&s_d[nd], 0xffffffffu);
                             atomicAdd(&s_d[0], 1u);
-                            atomicAdd(&s_d[a + rem - 256u], 0xffffffffu);
+                            atomicAdd(&s_d[a + rem - nd], 0xffffffffu);
                         }
                     }
                 }
@@ -736,7 +738,7 @@ k_tile_upsweep_emit(const uint64_t *__restrict__ count, int64_t capacity, TileEm
     if (lane == LEGS_WAVE - 1) s_t[wave] = incl;
     __syncthreads();
     for (int w = 0; w < wave; ++w) incl += s_t[w];
-    seg_hist[(int64_t)blockIdx.x * 256 + tid] = incl + s_all;
+    seg_hist[(int64_t)blockIdx.x * 256 + tid] = (uint32_t)tid < nd ? incl + s_all : 0u;
 }
 
 // ---- depth order of the G-views ---------------------------------------------------
@@ -963,10 +965,11 @@ k_tile_block_sums(const uint32_t *__restrict__ counts, int64_t total_tiles, uint
 }
 
 // Tile ranges [start, start + count) from the scanned counts, and the digit
-// histograms of the tile passes (digit p of a tile id counts its instances).
+// histograms of the tile passes (pass p's digit: the next (widths >> 4p) & 15
+// bits of the tile id).
 __global__ void __launch_bounds__(1024)
 k_tile_ranges(const uint32_t *__restrict__ counts, int64_t total_tiles,
-              const uint64_t *__restrict__ boff, int npass, uint32_t *__restrict__ ranges,
+              const uint64_t *__restrict__ boff, int npass, uint32_t widths, uint32_t *__restrict__ ranges,
               uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t s_h[4][256];
@@ -989,8 +992,14 @@ k_tile_ranges(const uint32_t *__restrict__ counts, int64_t total_tiles,
         const uint64_t st = boff[blockIdx.x] + wpre + incl - x;
         ranges[2 * t] = (uint32_t)st;
         ranges[2 * t + 1] = (uint32_t)(st + x);
-        if (x)
-            for (int p = 0; p < npass; ++p) atomicAdd(&s_h[p][(uint32_t)(t >> (8 * p)) & 255u], (uint32_t)x);
+        if (x) {
+            int sh = 0;
+            for (int p = 0; p < npass; ++p) {
+                const int w = (int)((widths >> (4 * p)) & 15u);
+                atomicAdd(&s_h[p][(uint32_t)(t >> sh) & ((1u << w) - 1u)], (uint32_t)x);
+                sh += w;
+            }
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < npass * 256; i += 1024) {
@@ -1111,7 +1120,7 @@ int32_t radix_passes(legs_ctx *ctx, const SortScratch &S, uint64_t *k0, uint32_t
     for (int p = first; p < last; ++p) {
         hipLaunchKernelGGL((k_onesweep<uint64_t, false, false, false, false>), dim3(gsort),
                            dim3(LEGS_SORT_THREADS), 0, s, ka, va, nullptr, kb, vb, nullptr, nullptr, count,
-                           capacity, p, S.starts, S.status + (int64_t)(p - first) * S.parts * 256,
+                           capacity, p, 8 * p, 8, S.starts, S.status + (int64_t)(p - first) * S.parts * 256,
                            S.counters + (p - first), TileEmit{}, nullptr);
         LEGS_CHECK_LAUNCH(ctx);
         uint64_t *tk = ka; ka = kb; kb = tk;
@@ -1253,8 +1262,18 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     //    tile ranges and the tile-digit histograms
     const GRec *recs = reinterpret_cast<const GRec *>(ord + OL.recs);
     const uint64_t *vrange = reinterpret_cast<const uint64_t *>(ord + OL.vrange);
-    const int tbits = bits_for(total_tiles);
-    const int np = tbits > 8 ? (tbits + 7) / 8 : 1;
+    // tile-id bits split as evenly as possible over ceil(bits / 8) passes (13 bits:
+    // 7 + 6), so digit runs stay long and the match needs fewer ballots
+    const int tbits = bits_for(total_tiles) > 0 ? bits_for(total_tiles) : 1;
+    const int np = (tbits + 7) / 8;
+    int pw[4] = {0, 0, 0, 0}, psh[4] = {0, 0, 0, 0};
+    uint32_t widths = 0;
+    for (int p = 0, sh = 0; p < np; ++p) {
+        pw[p] = tbits / np + (p < tbits % np ? 1 : 0);
+        psh[p] = sh;
+        sh += pw[p];
+        widths |= (uint32_t)pw[p] << (4 * p);
+    }
     hipLaunchKernelGGL(k_sort_clear, dim3(1), dim3(256), 0, s, S.status, S.parts, 0, S.counters,
                        S.hist, bins->count, bins->capacity);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(ctx, total_tiles, 256, 8)), dim3(256), 0, s,
@@ -1274,7 +1293,7 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, S.tsum, S.toff, S.tile_blocks,
                        S.toff + S.tile_blocks + 1);
     hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)S.tile_blocks), dim3(1024), 0, s, S.tcount,
-                       total_tiles, S.toff, np, bins->ranges, S.hist);
+                       total_tiles, S.toff, np, widths, bins->ranges, S.hist);
     hipLaunchKernelGGL(k_digit_starts, dim3(np), dim3(256), 0, s, S.hist, S.starts, 0);
     if (nblocks > 0)
         hipLaunchKernelGGL(k_part_blocks, dim3((unsigned)((nblocks + 255) / 256)), dim3(256), 0, s,
@@ -1307,16 +1326,16 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
         const bool emit = p == 0, fin = p == np - 1;
         if (emit)
             hipLaunchKernelGGL(k_tile_upsweep_emit, dim3(nseg), dim3(256), 0, s, bins->count, bins->capacity,
-                               E, S.seg_hist);
+                               E, pw[p], S.seg_hist);
         else
             hipLaunchKernelGGL(k_tile_upsweep, dim3(nseg), dim3(LEGS_SORT_THREADS), 0, s, tk[ri],
-                               bins->count, bins->capacity, p, S.seg_hist);
+                               bins->count, bins->capacity, psh[p], pw[p], S.seg_hist);
         hipLaunchKernelGGL(k_seg_scan, dim3(256), dim3(LEGS_SEG_MAX), 0, s, S.seg_hist, nseg, S.starts, p,
                            S.seg_off);
 #define LEGS_TILE_PASS(EM, FI)                                                                      \
         hipLaunchKernelGGL((k_onesweep<uint32_t, true, EM, FI, true>), dim3(nseg), dim3(LEGS_SORT_THREADS), \
                            0, s, tk[ri], tv[ri], td[ri], tk[wo], tv[wo], td[wo], bins->keys, bins->count, \
-                           bins->capacity, p, S.starts, nullptr, nullptr, E, S.seg_off)
+                           bins->capacity, p, psh[p], pw[p], S.starts, nullptr, nullptr, E, S.seg_off)
         if (emit && fin) LEGS_TILE_PASS(true, true);
         else if (emit) LEGS_TILE_PASS(true, false);
         else if (fin) LEGS_TILE_PASS(false, true);
