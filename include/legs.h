@@ -72,8 +72,10 @@ typedef struct {
  * done) instead of one workgroup per tile. Results are identical. */
 #define LEGS_FLAG_PERSISTENT 1
 /* Bin with all 8-bit digits of the 64-bit keys sorted over the instances
- * (6 passes at 8160 tiles) instead of sorting the G-views by depth first and
- * the instances by their tile digits only. The lists are identical. */
+ * (6 passes at 8160 tiles) instead of the depth-first binning: the G-views
+ * sorted by depth, their 8x4-tile super-tile entries sorted by super-tile,
+ * and each super-tile's list compacted into its tiles' lists. The lists are
+ * identical. The depth-first binning needs capacity + total_tiles < 2^32. */
 #define LEGS_FLAG_FULL_SORT 2
 
 /* Rasteriser options. Defaults (legs_opts_default): tile 16, lds_batch 256,

@@ -82,12 +82,22 @@ struct legs_sort_layout {
     int64_t counter_off;   // uint32 [64] partition counters per pass, blend tile counters
     int64_t status_off;    // uint64 [8][parts][256] look-back status words
     int64_t parts;         // partitions at full capacity
+    // depth-first binning only (total_tiles > 0):
+    int64_t tile_blocks;   // ceil(total_tiles / 1024)
     int64_t tcount_off;    // uint32 [total_tiles] per-tile instance counts
     int64_t tsum_off;      // uint64 [tile_blocks + 1] per-1024-tile sums
-    int64_t toff_off;      // uint64 [tile_blocks + 1] their exclusive scan
-    int64_t tile_blocks;
-    int64_t pstart_off;    // uint32 [parts] first G-view block of each partition
-    int64_t dep_off;       // uint32 [2][capacity] depth bits carried by the tile passes
+    int64_t toff_off;      // uint64 [tile_blocks + 2] their exclusive scan and total
+    int64_t scount_off;    // uint32 [total_tiles] per-super-tile counts (fewer super-tiles than tiles)
+    int64_t ssum_off;      // uint64 [tile_blocks + 1]
+    int64_t soff_off;      // uint64 [tile_blocks + 2]
+    int64_t cranges_off;   // uint32 [total_tiles][2] super-tile list ranges
+    int64_t uoff_off;      // uint32 [total_tiles + 1] first compaction unit of each super-tile
+    int64_t desc_off;      // uint32 [32] coarse digit layout, then uint64 [2] capacity cut
+    int64_t ccap;          // coarse list capacity: capacity + total_tiles
+    int64_t cparts;        // partitions of the coarse lists
+    int64_t pstart_off;    // uint32 [cparts] first G-view block of each coarse partition
+    int64_t clist_off;     // uint32 [4][ccap] coarse keys and positions, two buffers each
+    int64_t ucnt_off;      // uint32 [ccap / unit + total_tiles][32] per-unit tile counts / offsets
     int64_t part_off;      // uint32 [LEGS_TILE_CHUNKS][total_tiles] partial tile-count grids
     int64_t seg_off;       // uint32 [2][LEGS_SEG_MAX][256] segment digit counts and starts
     int64_t total;
@@ -100,6 +110,7 @@ legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles = 0)
 #define LEGS_SORT_MAX_PASSES 8
 #define LEGS_TILE_CHUNKS 128
 #define LEGS_SEG_MAX 1024
+#define LEGS_COMPACT_UNIT 256
 // counter slots (u32) in the sort scratch's counter block: 0..15 sort passes
 #define LEGS_BLEND_COUNTER_FWD 32
 #define LEGS_BLEND_COUNTER_BWD 33

@@ -230,21 +230,29 @@ k_sort_clear(uint64_t *__restrict__ status, int64_t parts_cap, int passes,
     }
 }
 
-// One record per depth-ordered position: everything the tile passes need of
-// the G-view there, read once with one coalesced load.
+// Super-tile record of a depth-ordered position: what the coarse pass needs
+// of the G-view there, read once with one coalesced load.
 struct GRec {
-    uint32_t gid;    // Gaussian index
-    uint32_t cnt;    // tiles of its rectangle (0: culled)
-    uint32_t base;   // global id of its first tile
-    uint32_t rwtx;   // rectangle width | tiles_x of its view << 16
+    uint32_t gid;    // the position itself (the coarse lists hold positions)
+    uint32_t cnt;    // super-tiles of its rectangle (0: culled)
+    uint32_t base;   // global id of its first super-tile
+    uint32_t rwtx;   // rectangle width | super-tiles per row of its view << 16
 };
 
-// Inputs of the fused emission (first tile pass of the depth-first binning):
-// the records of the depth-ordered G-views, the instance offset of every 256
-// of them and the first block of each partition.
+// Tile record of a depth-ordered position: its tile rectangle in view-local
+// tile coordinates (the per-tile counts and the compaction read it).
+struct FRec {
+    uint32_t gid;    // Gaussian index
+    uint32_t dbits;  // depth bits
+    uint32_t xy;     // first tile column | first tile row << 16
+    uint32_t wh;     // rectangle width | height << 16 (0: culled)
+};
+
+// Inputs of the fused emission (the first coarse pass): the super-tile
+// records of the depth-ordered G-views, the instance offset of every 256 of
+// them and the first block of each partition.
 struct TileEmit {
     const GRec *recs;
-    const uint32_t *dbits;
     const uint64_t *goff;      // [nblocks + 1]
     const uint32_t *pstart;    // [partitions]
     int64_t nblocks, G;
@@ -294,7 +302,7 @@ __device__ __forceinline__ void block_scan_256(uint64_t x, uint64_t *s_start, ui
 
 // LDS of the fused emission.
 struct EmitLds {
-    uint32_t rbase[256], rwtx[256], rg[256], rd[256];
+    uint32_t rbase[256], rwtx[256], rg[256];
     uint16_t own[LEGS_SORT_PART];
     uint32_t omax[LEGS_SORT_THREADS / LEGS_WAVE];
     uint64_t gscan[257];
@@ -302,13 +310,13 @@ struct EmitLds {
 };
 
 // Generates instances [base, base + nvalid) of the depth-ordered stream into
-// LDS slots 0 .. nvalid - 1 (tile key, Gaussian id, depth bits): instance e is
-// tile e - start of its G-view's rectangle, row-major. Each G-view marks the
-// first slot it fills and a running maximum over the slots gives every slot
-// its owner. Called by the whole workgroup.
-template <typename K, bool DEP>
+// LDS slots 0 .. nvalid - 1 (super-tile key, position): instance e is
+// super-tile e - start of its G-view's rectangle, row-major. Each G-view marks
+// the first slot it fills and a running maximum over the slots gives every
+// slot its owner. Called by the whole workgroup.
+template <typename K>
 __device__ __forceinline__ void emit_partition(const TileEmit &E, int64_t part, int64_t base, int nvalid,
-                                               K *s_keys, uint32_t *s_vals, uint32_t *s_dep, EmitLds &M)
+                                               K *s_keys, uint32_t *s_vals, EmitLds &M)
 {
     constexpr int T = LEGS_SORT_THREADS;
     constexpr int NW = T / LEGS_WAVE;
@@ -325,7 +333,6 @@ __device__ __forceinline__ void emit_partition(const TileEmit &E, int64_t part, 
             M.rbase[tid] = r.base;
             M.rwtx[tid] = r.rwtx;
             M.rg[tid] = r.gid;
-            M.rd[tid] = c ? E.dbits[pos] : 0u;
         }
         block_scan_256<T>(c, M.gscan, M.w64);
         const uint64_t tot = M.gscan[256];
@@ -379,30 +386,38 @@ __device__ __forceinline__ void emit_partition(const TileEmit &E, int64_t part, 
                 while (rr >= (int32_t)rw) { ++qq; rr -= (int32_t)rw; }
                 s_keys[e] = (K)(M.rbase[o] + qq * tx + (uint32_t)rr);
                 s_vals[e] = M.rg[o];
-                if constexpr (DEP) s_dep[e] = M.rd[o];
             }
         }
         __syncthreads();
     }
 }
 
-// One onesweep pass over digit `pass` (bits 8 pass .. 8 pass + 7) of keys K
-// with 32-bit values, and with DEP a second 32-bit value (the depth bits)
-// carried along. EMIT: the partition's (tile, id, depth) triples are
-// generated from the depth-ordered G-view records instead of read (instance
-// e is tile e - start of its G-view's rectangle, row-major): each G-view
-// marks the first partition slot it fills, and a running maximum over the
-// slots gives every slot its owner. FINAL: the keys are written as the 64-bit
-// (tile << 32) | depth keys of the tile lists.
-template <typename K, bool DEP, bool EMIT, bool FINAL, bool SEG>
+// Digit layout of the coarse passes, decided on the device from the number of
+// super-tiles: desc[0] passes, desc[2 + 2p] and desc[3 + 2p] the shift and
+// width of pass p (width 0: the pass is not needed and returns at once).
+constexpr int DESC_WORDS = 2 + 2 * LEGS_SORT_MAX_PASSES;
+
+// One onesweep pass over the digit of `rb` bits at `shift` of keys K with
+// 32-bit values (with desc, shift and width come from desc[2 + 2 pass ..]).
+// EMIT: the partition's (super-tile, position) pairs are generated from the
+// depth-ordered G-view records instead of read (instance e is super-tile
+// e - start of its G-view's rectangle, row-major): each G-view marks the
+// first partition slot it fills, and a running maximum over the slots gives
+// every slot its owner. SEG: workgroups walk fixed segments of partitions in
+// order from the segment digit starts instead of a decoupled look-back.
+template <typename K, bool EMIT, bool SEG>
 __global__ void __launch_bounds__(LEGS_SORT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
-k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
-           const uint32_t *__restrict__ din, K *__restrict__ kout, uint32_t *__restrict__ vout,
-           uint32_t *__restrict__ dout, uint64_t *__restrict__ keys64,
-           const uint64_t *__restrict__ count, int64_t capacity, int pass, int shift, int rb,
-           const uint32_t *__restrict__ digit_starts, uint64_t *__restrict__ status,
-           uint32_t *__restrict__ counter, TileEmit E, const uint32_t *__restrict__ seg_off)
+k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__restrict__ kout,
+           uint32_t *__restrict__ vout, const uint64_t *__restrict__ count, int64_t capacity, int pass,
+           int shift, int rb, const uint32_t *__restrict__ desc, const uint32_t *__restrict__ digit_starts,
+           uint64_t *__restrict__ status, uint32_t *__restrict__ counter, TileEmit E,
+           const uint32_t *__restrict__ seg_off)
 {
+    if (desc) {
+        shift = (int)desc[2 + 2 * pass];
+        rb = (int)desc[3 + 2 * pass];
+        if (rb == 0) return;
+    }
     constexpr int T = LEGS_SORT_THREADS;
     constexpr int NW = T / LEGS_WAVE;
     constexpr int ITEMS = LEGS_SORT_ITEMS;
@@ -410,7 +425,6 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
     static_assert(T >= 256 && T % 256 == 0, "one thread per digit");
     __shared__ K s_keys[PART];
     __shared__ uint32_t s_vals[PART];
-    __shared__ uint32_t s_dep[DEP ? PART : 1];
     __shared__ uint32_t s_wh[NW][256];      // per-wave digit counts, then wave offsets
     __shared__ uint32_t s_lstart[256];      // block-local start of each digit
     __shared__ uint64_t s_gstart[257];      // global position of LDS slot 0 of each digit;
@@ -450,11 +464,11 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
 
         if constexpr (EMIT) {
             __shared__ EmitLds s_emit;
-            emit_partition<K, DEP>(E, part, base, nvalid, s_keys, s_vals, s_dep, s_emit);
+            emit_partition<K>(E, part, base, nvalid, s_keys, s_vals, s_emit);
         }
 
         K key[ITEMS];
-        uint32_t val[ITEMS], dep[DEP ? ITEMS : 1];
+        uint32_t val[ITEMS];
         uint32_t rank[ITEMS];
         // wave-striped: item i of lane l of wave w is partition element w*64*ITEMS + i*64 + l
 #pragma unroll
@@ -464,16 +478,13 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                 if constexpr (EMIT) {
                     key[i] = s_keys[e];
                     val[i] = s_vals[e];
-                    if constexpr (DEP) dep[i] = s_dep[e];
                 } else {
                     key[i] = kin[base + e];
                     val[i] = vin[base + e];
-                    if constexpr (DEP) dep[i] = din[base + e];
                 }
             } else {
                 key[i] = (K)~(K)0;
                 val[i] = 0;
-                if constexpr (DEP) dep[i] = 0;
             }
         }
         if constexpr (EMIT) __syncthreads();   // the LDS arrays are reused by the scatter below
@@ -542,7 +553,6 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                 const uint32_t pos = s_lstart[d] + s_wh[wave][d] + rank[i];
                 s_keys[pos] = key[i];
                 s_vals[pos] = val[i];
-                if constexpr (DEP) s_dep[pos] = dep[i];
             }
         }
         // global start of each digit run: the segment's running start, or a
@@ -592,14 +602,8 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                 const uint32_t d = (uint32_t)(kk >> shift) & dmask;
                 const uint64_t gpos = s_gstart[d] + (uint64_t)k;
                 if (gpos < (uint64_t)capacity) {
-                    if constexpr (FINAL) {
-                        keys64[gpos] = ((uint64_t)kk << 32) | s_dep[k];
-                        vout[gpos] = s_vals[k];
-                    } else {
-                        kout[gpos] = kk;
-                        vout[gpos] = s_vals[k];
-                        if constexpr (DEP) dout[gpos] = s_dep[k];
-                    }
+                    kout[gpos] = kk;
+                    vout[gpos] = s_vals[k];
                 }
             }
         }
@@ -607,13 +611,16 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
     }
 }
 
-// Digit counts of pass `pass` over the partitions of segment blockIdx.x (the
-// same segments as the segment passes: per = ceil(partitions / gridDim.x)).
+// Digit counts of coarse pass `pass` over the partitions of segment
+// blockIdx.x (the same segments as the segment passes: per =
+// ceil(partitions / gridDim.x)).
 __global__ void __launch_bounds__(LEGS_SORT_THREADS)
 k_tile_upsweep(const uint32_t *__restrict__ kin, const uint64_t *__restrict__ count, int64_t capacity,
-               int shift, int rb, uint32_t *__restrict__ seg_hist)
+               const uint32_t *__restrict__ desc, int pass, uint32_t *__restrict__ seg_hist)
 {
     constexpr int T = LEGS_SORT_THREADS, PART = LEGS_SORT_PART, ITEMS = LEGS_SORT_ITEMS;
+    const int shift = (int)desc[2 + 2 * pass], rb = (int)desc[3 + 2 * pass];
+    if (rb == 0) return;
     __shared__ uint32_t s_hist[256];
     const int tid = threadIdx.x;
     if (tid < 256) s_hist[tid] = 0;
@@ -647,8 +654,9 @@ k_tile_upsweep(const uint32_t *__restrict__ kin, const uint64_t *__restrict__ co
 // segment (nseg <= LEGS_SEG_MAX).
 __global__ void __launch_bounds__(LEGS_SEG_MAX)
 k_seg_scan(const uint32_t *__restrict__ seg_hist, int nseg, const uint32_t *__restrict__ digit_starts,
-           int pass, uint32_t *__restrict__ seg_off)
+           const uint32_t *__restrict__ desc, int pass, uint32_t *__restrict__ seg_off)
 {
+    if (desc[3 + 2 * pass] == 0) return;
     __shared__ uint32_t s_w[LEGS_SEG_MAX / LEGS_WAVE];
     const int d = blockIdx.x, sg = threadIdx.x;
     const int lane = legs_lane(), wave = sg / LEGS_WAVE;
@@ -666,16 +674,17 @@ k_seg_scan(const uint32_t *__restrict__ seg_hist, int nseg, const uint32_t *__re
     if (sg < nseg) seg_off[(int64_t)sg * 256 + d] = pre + incl - x;
 }
 
-// Counts of the low rb bits of the tile ids in segment blockIdx.x of the
-// depth-ordered stream (the first tile pass), from the G-view records without
-// generating the instances: every row of a rectangle covers consecutive tile
-// ids, i.e. a cyclic range of digits, added to a difference array (full turns
-// of 2^rb to every digit at once).
+// Counts of the low rb bits of the super-tile ids in segment blockIdx.x of the
+// depth-ordered coarse stream (the first coarse pass), from the G-view records
+// without generating the instances: every row of a rectangle covers
+// consecutive ids, i.e. a cyclic range of digits, added to a difference array
+// (full turns of 2^rb to every digit at once).
 __global__ void __launch_bounds__(256)
-k_tile_upsweep_emit(const uint64_t *__restrict__ count, int64_t capacity, TileEmit E, int rb,
-                    uint32_t *__restrict__ seg_hist)
+k_tile_upsweep_emit(const uint64_t *__restrict__ count, int64_t capacity, TileEmit E,
+                    const uint32_t *__restrict__ desc, uint32_t *__restrict__ seg_hist)
 {
-    const uint32_t nd = 1u << rb;   // the first pass sorts the low rb bits of the tile id
+    const int rb = (int)desc[3];    // the first pass sorts the low bits
+    const uint32_t nd = 1u << rb;
     constexpr int PART = LEGS_SORT_PART;
     __shared__ uint32_t s_d[257];
     __shared__ uint32_t s_all;
@@ -758,48 +767,66 @@ k_order_keys(const uint32_t *__restrict__ ntiles, const float *__restrict__ dept
     vals[gv] = (uint32_t)gv;
 }
 
-// Records, depth bits and per-view position ranges of the depth-ordered
-// G-views, and the instance count of each block of 256 positions.
+// Super-tile edge in tiles: 8 x 4 tiles, one bit each of a 32-bit mask.
+constexpr int SX = 8, SY = 4, SUPER_TILES = SX * SY;
+static_assert(SUPER_TILES == 32, "one mask bit per tile of a super-tile");
+
+// Tile and super-tile records and the per-view position ranges of the
+// depth-ordered G-views, and the tile and super-tile instance counts of each
+// block of LEGS_PROJ_BLOCK positions.
 __global__ void __launch_bounds__(LEGS_PROJ_BLOCK)
 k_sorted_records(const uint32_t *__restrict__ perm, const uint64_t *__restrict__ okeys,
                  const int4 *__restrict__ box, const float *__restrict__ depth,
                  const uint32_t *__restrict__ ntiles, int64_t n, int64_t G,
-                 const legs_view *__restrict__ views, int tile, GRec *__restrict__ recs,
-                 uint32_t *__restrict__ dbits, uint64_t *__restrict__ vrange,
-                 uint64_t *__restrict__ block_counts)
+                 const legs_view *__restrict__ views, const legs_view *__restrict__ sviews, int tile,
+                 FRec *__restrict__ frecs, GRec *__restrict__ crecs, uint64_t *__restrict__ vrange,
+                 uint64_t *__restrict__ block_counts, uint64_t *__restrict__ cblock_counts)
 {
     const int64_t pos = (int64_t)blockIdx.x * LEGS_PROJ_BLOCK + threadIdx.x;
-    uint64_t c = 0;
+    uint64_t c = 0, cc = 0;
     if (pos < G) {
         const int64_t gv = perm[pos];
         c = ntiles[gv];
-        GRec r = {0u, 0u, 0u, 0u};
+        FRec f = {0u, 0u, 0u, 0u};
+        GRec r = {(uint32_t)pos, 0u, 0u, 0u};
         if (c) {
             const int64_t v = gv / n;
             const int4 bx = box[gv];
             const legs_view &vw = views[v];
-            const int tx0 = bx.x / tile, ty0 = bx.z / tile;
-            r.gid = (uint32_t)(gv - v * n);
-            r.cnt = (uint32_t)c;
-            r.base = (uint32_t)(vw.tile_offset + (int64_t)ty0 * vw.tiles_x + tx0);
-            r.rwtx = (uint32_t)(bx.y / tile - tx0 + 1) | ((uint32_t)vw.tiles_x << 16);
-            dbits[pos] = __float_as_uint(depth[gv]);
+            const legs_view &sw = sviews[v];
+            const int tx0 = bx.x / tile, tx1 = bx.y / tile, ty0 = bx.z / tile, ty1 = bx.w / tile;
+            f.gid = (uint32_t)(gv - v * n);
+            f.dbits = __float_as_uint(depth[gv]);
+            f.xy = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
+            f.wh = (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)(ty1 - ty0 + 1) << 16);
+            const int sx0 = tx0 / SX, sx1 = tx1 / SX, sy0 = ty0 / SY, sy1 = ty1 / SY;
+            r.cnt = (uint32_t)((sx1 - sx0 + 1) * (sy1 - sy0 + 1));
+            r.base = (uint32_t)(sw.tile_offset + (int64_t)sy0 * sw.tiles_x + sx0);
+            r.rwtx = (uint32_t)(sx1 - sx0 + 1) | ((uint32_t)sw.tiles_x << 16);
+            cc = r.cnt;
             // first and last position of each view (visible G-views sort by view)
             const uint64_t kv = okeys[pos] >> 32;
             if (pos == 0 || (okeys[pos - 1] >> 32) != kv) vrange[2 * kv] = (uint64_t)pos;
             if (pos == G - 1 || (okeys[pos + 1] >> 32) != kv) vrange[2 * kv + 1] = (uint64_t)pos + 1;
         }
-        recs[pos] = r;
+        frecs[pos] = f;
+        crecs[pos] = r;
     }
 #pragma unroll
-    for (int off = LEGS_WAVE / 2; off > 0; off >>= 1) c += __shfl_down(c, off, LEGS_WAVE);
-    __shared__ uint64_t s_w[LEGS_PROJ_BLOCK / LEGS_WAVE];
-    if (legs_lane() == 0) s_w[threadIdx.x / LEGS_WAVE] = c;
+    for (int off = LEGS_WAVE / 2; off > 0; off >>= 1) {
+        c += __shfl_down(c, off, LEGS_WAVE);
+        cc += __shfl_down(cc, off, LEGS_WAVE);
+    }
+    __shared__ uint64_t s_w[2][LEGS_PROJ_BLOCK / LEGS_WAVE];
+    if (legs_lane() == 0) {
+        s_w[0][threadIdx.x / LEGS_WAVE] = c;
+        s_w[1][threadIdx.x / LEGS_WAVE] = cc;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 2) {
         uint64_t t = 0;
-        for (int w = 0; w < LEGS_PROJ_BLOCK / LEGS_WAVE; ++w) t += s_w[w];
-        block_counts[blockIdx.x] = t;
+        for (int w = 0; w < LEGS_PROJ_BLOCK / LEGS_WAVE; ++w) t += s_w[threadIdx.x][w];
+        (threadIdx.x == 0 ? block_counts : cblock_counts)[blockIdx.x] = t;
     }
 }
 
@@ -837,16 +864,36 @@ __device__ __forceinline__ void diff_rect(uint32_t *g, int W, int H, int x0, int
 
 constexpr int TILE_LDS_CELLS = 16384;   // views with at most this many tiles count in LDS
 
+// Rectangle of a record in view-local (super-)tile coordinates.
+struct Rect {
+    int x0, y0, w, h;
+};
+__device__ __forceinline__ uint32_t rec_count(const FRec &r) { return (r.wh & 0xffffu) * (r.wh >> 16); }
+__device__ __forceinline__ uint32_t rec_count(const GRec &r) { return r.cnt; }
+__device__ __forceinline__ Rect rec_rect(const FRec &r, const legs_view &)
+{
+    return {(int)(r.xy & 0xffffu), (int)(r.xy >> 16), (int)(r.wh & 0xffffu), (int)(r.wh >> 16)};
+}
+__device__ __forceinline__ Rect rec_rect(const GRec &r, const legs_view &vw)
+{
+    const int local = (int)((int64_t)r.base - vw.tile_offset);
+    const int w = (int)(r.rwtx & 0xffffu);
+    return {local % vw.tiles_x, local / vw.tiles_x, w, (int)(r.cnt / (uint32_t)w)};
+}
+
 // Workgroup (c, v) adds the rectangles of view v's G-views in position blocks
 // c, c + gridDim.x, ... into an LDS copy of the view's tile grid and stores it
 // in partial[c] (views with more tiles than fit add straight into the global
 // grid with atomics); k_tile_merge then sums the partial grids. Hot corner
-// cells cost LDS atomics instead of global ones.
+// cells cost LDS atomics instead of global ones. With `cut`, the G-view whose
+// instances reach past the capacity stores its position and how many of its
+// tiles fit (at most one G-view does).
+template <typename R>
 __global__ void __launch_bounds__(256)
-k_tile_corners(const GRec *__restrict__ recs, const uint64_t *__restrict__ goff,
+k_tile_corners(const R *__restrict__ recs, const uint64_t *__restrict__ goff,
                const uint64_t *__restrict__ vrange, int64_t G,
                const legs_view *__restrict__ views, int64_t capacity, int64_t total_tiles,
-               uint32_t *__restrict__ diff, uint32_t *__restrict__ partial)
+               uint32_t *__restrict__ diff, uint32_t *__restrict__ partial, uint64_t *__restrict__ cut)
 {
     __shared__ uint32_t s_grid[TILE_LDS_CELLS];
     __shared__ uint64_t s_start[257];
@@ -864,21 +911,24 @@ k_tile_corners(const GRec *__restrict__ recs, const uint64_t *__restrict__ goff,
     if (p1 > p0) {
         for (int64_t b = p0 / 256 + blockIdx.x; b <= (p1 - 1) / 256; b += gridDim.x) {
             const int64_t pos = b * 256 + threadIdx.x;
-            const GRec r = pos < G ? recs[pos] : GRec{0u, 0u, 0u, 0u};
-            block_scan_256<256>(r.cnt, s_start, s_w);
+            // the whole block is scanned: its offset counts the positions of other views too
+            const R r = pos < G ? recs[pos] : R{0u, 0u, 0u, 0u};
+            block_scan_256<256>(rec_count(r), s_start, s_w);
             const uint64_t off = goff[b] + s_start[threadIdx.x];
-            if (pos >= p0 && pos < p1 && r.cnt && off < (uint64_t)capacity) {
-                const uint64_t keep = (uint64_t)capacity - off < r.cnt ? (uint64_t)capacity - off : r.cnt;
-                const int rw = (int)(r.rwtx & 0xffffu);
-                const int local = (int)((int64_t)r.base - vw.tile_offset);
-                const int x0 = local % W, y0 = local / W;
-                const int rows = (int)(r.cnt / (uint32_t)rw);
-                if (keep == r.cnt) {
-                    diff_rect(g, W, H, x0, x0 + rw - 1, y0, y0 + rows - 1);
+            const uint32_t cnt = pos >= p0 && pos < p1 ? rec_count(r) : 0u;
+            if (cut && cnt && off <= (uint64_t)capacity && off + cnt > (uint64_t)capacity) {
+                cut[0] = (uint64_t)pos;
+                cut[1] = (uint64_t)capacity - off;
+            }
+            if (cnt && off < (uint64_t)capacity) {
+                const uint64_t keep = (uint64_t)capacity - off < cnt ? (uint64_t)capacity - off : cnt;
+                const Rect q = rec_rect(r, vw);
+                if (keep == cnt) {
+                    diff_rect(g, W, H, q.x0, q.x0 + q.w - 1, q.y0, q.y0 + q.h - 1);
                 } else {
-                    const int full = (int)(keep / (uint64_t)rw), rem = (int)(keep % (uint64_t)rw);
-                    if (full > 0) diff_rect(g, W, H, x0, x0 + rw - 1, y0, y0 + full - 1);
-                    if (rem > 0) diff_rect(g, W, H, x0, x0 + rem - 1, y0 + full, y0 + full);
+                    const int full = (int)(keep / (uint64_t)q.w), rem = (int)(keep % (uint64_t)q.w);
+                    if (full > 0) diff_rect(g, W, H, q.x0, q.x0 + q.w - 1, q.y0, q.y0 + full - 1);
+                    if (rem > 0) diff_rect(g, W, H, q.x0, q.x0 + rem - 1, q.y0 + full, q.y0 + full);
                 }
             }
             __syncthreads();
@@ -892,14 +942,16 @@ k_tile_corners(const GRec *__restrict__ recs, const uint64_t *__restrict__ goff,
 }
 
 // Sum of the partial grids of views counted in LDS (the others already hold
-// their counts in diff).
+// their counts in diff). total_tiles may exceed the grid's cells (the
+// super-tile grids): cells past the last view are left alone.
 __global__ void __launch_bounds__(256)
 k_tile_merge(const uint32_t *__restrict__ partial, int nch, int64_t total_tiles,
              const legs_view *__restrict__ views, int n_views, uint32_t *__restrict__ diff)
 {
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total_tiles; t += (int64_t)gridDim.x * 256) {
         const legs_view &vw = views[legs_view_of_tile(views, n_views, t)];
-        if (vw.tiles_x * vw.tiles_y > TILE_LDS_CELLS) continue;
+        const int64_t ncell = (int64_t)vw.tiles_x * vw.tiles_y;
+        if (ncell > TILE_LDS_CELLS || t - vw.tile_offset >= ncell) continue;
         uint32_t acc = 0;
 #pragma unroll 8
         for (int c = 0; c < nch; ++c) acc += partial[(int64_t)c * total_tiles + t];
@@ -964,14 +1016,14 @@ k_tile_block_sums(const uint32_t *__restrict__ counts, int64_t total_tiles, uint
     }
 }
 
-// Tile ranges [start, start + count) from the scanned counts, and the digit
-// histograms of the tile passes (pass p's digit: the next (widths >> 4p) & 15
-// bits of the tile id).
+// Tile ranges [start, start + count) from the scanned counts and, with desc,
+// the digit histograms of the coarse passes over these ids.
 __global__ void __launch_bounds__(1024)
 k_tile_ranges(const uint32_t *__restrict__ counts, int64_t total_tiles,
-              const uint64_t *__restrict__ boff, int npass, uint32_t widths, uint32_t *__restrict__ ranges,
-              uint32_t *__restrict__ hist)
+              const uint64_t *__restrict__ boff, const uint32_t *__restrict__ desc,
+              uint32_t *__restrict__ ranges, uint32_t *__restrict__ hist)
 {
+    const int npass = desc ? (int)desc[0] : 0;
     __shared__ uint32_t s_h[4][256];
     __shared__ uint64_t s_w[16];
     for (int i = threadIdx.x; i < 4 * 256; i += 1024) (&s_h[0][0])[i] = 0;
@@ -992,19 +1044,315 @@ k_tile_ranges(const uint32_t *__restrict__ counts, int64_t total_tiles,
         const uint64_t st = boff[blockIdx.x] + wpre + incl - x;
         ranges[2 * t] = (uint32_t)st;
         ranges[2 * t + 1] = (uint32_t)(st + x);
-        if (x) {
-            int sh = 0;
-            for (int p = 0; p < npass; ++p) {
-                const int w = (int)((widths >> (4 * p)) & 15u);
-                atomicAdd(&s_h[p][(uint32_t)(t >> sh) & ((1u << w) - 1u)], (uint32_t)x);
-                sh += w;
-            }
-        }
+        if (x)
+            for (int p = 0; p < npass; ++p)
+                atomicAdd(&s_h[p][(uint32_t)(t >> desc[2 + 2 * p]) & ((1u << desc[3 + 2 * p]) - 1u)], (uint32_t)x);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < npass * 256; i += 1024) {
         const uint32_t c = (&s_h[0][0])[i];
         if (c) atomicAdd(&hist[i], c);
+    }
+}
+
+// ---- two-level binning: super-tile lists, compacted into tile lists ---------
+
+// Super-tile grids of the views (SX x SY tiles each, numbered after one
+// another like the tile grids) and the digit layout of the coarse passes:
+// ceil(bits / 8) passes over the bits of the super-tile id, split evenly.
+// One thread (n_views is small).
+__global__ void k_super_views(const legs_view *__restrict__ views, int n_views, legs_view *__restrict__ sv,
+                              uint32_t *__restrict__ desc)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t off = 0;
+    for (int v = 0; v < n_views; ++v) {
+        legs_view w = views[v];
+        w.tiles_x = (w.tiles_x + SX - 1) / SX;
+        w.tiles_y = (w.tiles_y + SY - 1) / SY;
+        w.tile_offset = off;
+        off += (int64_t)w.tiles_x * w.tiles_y;
+        sv[v] = w;
+    }
+    int bits = 1;
+    while (bits < 32 && (1ll << bits) < off) ++bits;
+    const int np = (bits + 7) / 8;
+    desc[0] = (uint32_t)np;
+    desc[1] = 0u;
+    for (int p = 0, sh = 0; p < LEGS_SORT_MAX_PASSES; ++p) {
+        const int w = p < np ? bits / np + (p < bits % np ? 1 : 0) : 0;
+        desc[2 + 2 * p] = (uint32_t)sh;
+        desc[3 + 2 * p] = (uint32_t)w;
+        sh += w;
+    }
+}
+
+// Inclusive sum over lanes 0..l of a wave (DPP row shifts, then the row
+// broadcasts of lanes 15 and 31).
+__device__ __forceinline__ uint32_t wave_incl_add(uint32_t x)
+{
+#define LEGS_DPP_ADD(ctrl, rmask) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, ctrl, rmask, 0xF, false);
+    LEGS_DPP_ADD(0x111, 0xF)   // row_shr:1
+    LEGS_DPP_ADD(0x112, 0xF)   // row_shr:2
+    LEGS_DPP_ADD(0x114, 0xF)   // row_shr:4
+    LEGS_DPP_ADD(0x118, 0xF)   // row_shr:8
+    LEGS_DPP_ADD(0x142, 0xA)   // row_bcast:15 into rows 1 and 3
+    LEGS_DPP_ADD(0x143, 0xC)   // row_bcast:31 into rows 2 and 3
+#undef LEGS_DPP_ADD
+    return x;
+}
+
+// Entries of the coarse lists per unit of the compaction (one wave each).
+constexpr int UNIT = LEGS_COMPACT_UNIT;
+
+// Units of the coarse lists: super-tile s's list [cranges[2s], cranges[2s+1])
+// is cut into ceil(length / UNIT) units; uoff[s] is the first unit of s and
+// uoff[n] the number of units. One workgroup.
+__global__ void __launch_bounds__(1024)
+k_units(const uint32_t *__restrict__ cranges, int64_t n, uint32_t *__restrict__ uoff)
+{
+    __shared__ uint32_t s_w[16];
+    const int lane = legs_lane(), wave = threadIdx.x / LEGS_WAVE;
+    uint32_t carry = 0;
+    for (int64_t s0 = 0; s0 < n; s0 += 1024) {
+        const int64_t st = s0 + threadIdx.x;
+        const uint32_t len = st < n ? cranges[2 * st + 1] - cranges[2 * st] : 0u;
+        const uint32_t u = (len + UNIT - 1) / UNIT;
+        const uint32_t incl = wave_incl_add(u);
+        if (lane == LEGS_WAVE - 1) s_w[wave] = incl;
+        __syncthreads();
+        uint32_t pre = 0, tot = 0;
+        for (int w = 0; w < 16; ++w) {
+            pre += w < wave ? s_w[w] : 0u;
+            tot += s_w[w];
+        }
+        if (st < n) uoff[st] = carry + pre + incl - u;
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) uoff[n] = carry;
+}
+
+// What a wave needs of its unit: the list entries [e0, e1), the super-tile's
+// first tile (view-local) and the view's tile grid.
+struct UnitCtx {
+    uint32_t e0, e1;
+    int tx0, ty0, tiles_x, tiles_y;
+    int64_t toff;
+};
+
+__device__ __forceinline__ UnitCtx unit_ctx(uint32_t u, const uint32_t *__restrict__ uoff, int64_t n,
+                                            const uint32_t *__restrict__ cranges,
+                                            const legs_view *__restrict__ sviews,
+                                            const legs_view *__restrict__ views, int n_views)
+{
+    int64_t lo = 0, hi = n - 1;   // the last super-tile whose first unit is <= u
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (uoff[mid] <= u) lo = mid; else hi = mid - 1;
+    }
+    const int64_t st = lo;
+    const int v = legs_view_of_tile(sviews, n_views, st);
+    const int stx = sviews[v].tiles_x;
+    const int local = (int)(st - sviews[v].tile_offset);
+    UnitCtx c;
+    c.ty0 = (local / stx) * SY;
+    c.tx0 = (local - (local / stx) * stx) * SX;
+    c.e0 = cranges[2 * st] + (u - uoff[st]) * UNIT;
+    const uint32_t end = cranges[2 * st + 1];
+    c.e1 = c.e0 + UNIT < end ? c.e0 + UNIT : end;
+    c.tiles_x = views[v].tiles_x;
+    c.tiles_y = views[v].tiles_y;
+    c.toff = views[v].tile_offset;
+    return c;
+}
+
+// Tiles of the super-tile at (tx0, ty0) that the record's rectangle covers:
+// bit (ty - ty0) * SX + (tx - tx0). The G-view at position cut[0] keeps only
+// its first cut[1] tiles in row-major order, the ones after it none (their
+// instances lie past the capacity).
+__device__ __forceinline__ uint32_t entry_mask(uint32_t pos, const FRec &r, const UnitCtx &c, uint64_t cpos,
+                                               uint64_t ckeep)
+{
+    if ((uint64_t)pos > cpos) return 0u;
+    const int x0 = (int)(r.xy & 0xffffu), y0 = (int)(r.xy >> 16);
+    const int w = (int)(r.wh & 0xffffu), h = (int)(r.wh >> 16);
+    const int cx0 = max(x0 - c.tx0, 0), cx1 = min(x0 + w - 1 - c.tx0, SX - 1);
+    const int cy0 = max(y0 - c.ty0, 0), cy1 = min(y0 + h - 1 - c.ty0, SY - 1);
+    if (w == 0 || cx0 > cx1 || cy0 > cy1) return 0u;
+    const uint32_t cols = (0xffu << cx0) & (0xffu >> (SX - 1 - cx1));
+    const uint32_t rows = (0x01010101u << (SX * cy0)) & (0x01010101u >> (SX * (SY - 1 - cy1)));
+    uint32_t m = cols * rows;
+    if ((uint64_t)pos == cpos) {
+        const int kr = (int)(ckeep / (uint64_t)w), kc = (int)(ckeep % (uint64_t)w);
+        for (int y = 0; y < SY; ++y) {
+            const int r_ = c.ty0 + y - y0;   // row of the rectangle
+            uint32_t keep_cols;
+            if (r_ < kr) {
+                keep_cols = 0xffu;
+            } else if (r_ > kr) {
+                keep_cols = 0u;
+            } else {
+                const int lim = x0 + kc - c.tx0;   // columns cx < lim are kept
+                keep_cols = lim <= 0 ? 0u : (lim >= SX ? 0xffu : (0xffu >> (SX - lim)));
+            }
+            m &= ~((~keep_cols & 0xffu) << (SX * y));
+        }
+    }
+    return m;
+}
+
+// Counts of each of the 32 tiles in each unit: ucnt[u * 32 + b].
+__global__ void __launch_bounds__(256)
+k_compact_count(const uint32_t *__restrict__ clist0, const uint32_t *__restrict__ clist1,
+                const uint32_t *__restrict__ desc, const uint32_t *__restrict__ cranges,
+                const uint32_t *__restrict__ uoff, int64_t n, const legs_view *__restrict__ sviews,
+                const legs_view *__restrict__ views, int n_views, const FRec *__restrict__ frecs, int64_t G,
+                const uint64_t *__restrict__ cut, uint32_t *__restrict__ ucnt)
+{
+    // pass p of the coarse sort writes buffer p % 2
+    const uint32_t *clist = ((desc[0] - 1u) & 1u) ? clist1 : clist0;
+    const int lane = legs_lane();
+    const uint32_t nunits = uoff[n];
+    const uint64_t cpos = cut[0], ckeep = cut[1];
+    const uint32_t nw = gridDim.x * (256 / LEGS_WAVE);
+    for (uint32_t u = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * (256 / LEGS_WAVE) + threadIdx.x / LEGS_WAVE));
+         u < nunits; u += nw) {
+        const UnitCtx c = unit_ctx(u, uoff, n, cranges, sviews, views, n_views);
+        uint32_t cnt[SUPER_TILES];
+#pragma unroll
+        for (int b = 0; b < SUPER_TILES; ++b) cnt[b] = 0;
+        for (uint32_t e0 = c.e0; e0 < c.e1; e0 += LEGS_WAVE) {
+            const uint32_t e = e0 + lane;
+            uint32_t m = 0;
+            if (e < c.e1) {
+                const uint32_t pos = clist[e];
+                if ((int64_t)pos < G) m = entry_mask(pos, frecs[pos], c, cpos, ckeep);
+            }
+#pragma unroll
+            for (int b = 0; b < SUPER_TILES; ++b) cnt[b] += (uint32_t)__popcll(legs_ballot((m >> b) & 1u));
+        }
+        uint32_t mine = 0;
+#pragma unroll
+        for (int b = 0; b < SUPER_TILES; ++b) mine = lane == b ? cnt[b] : mine;
+        if (lane < SUPER_TILES) ucnt[(int64_t)u * SUPER_TILES + lane] = mine;
+    }
+}
+
+// Per super-tile (one wave each): the unit counts of each of its tiles become
+// exclusive offsets, starting from the tile's range start.
+__global__ void __launch_bounds__(256)
+k_compact_scan(const uint32_t *__restrict__ uoff, int64_t n, const legs_view *__restrict__ sviews,
+               const legs_view *__restrict__ views, int n_views, const uint32_t *__restrict__ ranges,
+               uint32_t *__restrict__ ucnt)
+{
+    const int lane = legs_lane();
+    const uint32_t nunits = uoff[n];
+    const int64_t nw = (int64_t)gridDim.x * (256 / LEGS_WAVE);
+    for (int64_t st = (int64_t)blockIdx.x * (256 / LEGS_WAVE) + threadIdx.x / LEGS_WAVE; st < n; st += nw) {
+        const uint32_t u0 = uoff[st], u1 = uoff[st + 1];
+        if (u0 >= nunits) break;   // no units from here on
+        if (u0 >= u1) continue;
+        const int v = legs_view_of_tile(sviews, n_views, st);
+        const int stx = sviews[v].tiles_x;
+        const int local = (int)(st - sviews[v].tile_offset);
+        const int ty0 = (local / stx) * SY, tx0 = (local - (local / stx) * stx) * SX;
+        const legs_view &vw = views[v];
+        uint32_t start = 0;
+        if (lane < SUPER_TILES) {
+            const int tx = tx0 + lane % SX, ty = ty0 + lane / SX;
+            if (tx < vw.tiles_x && ty < vw.tiles_y)
+                start = ranges[2 * (vw.tile_offset + (int64_t)ty * vw.tiles_x + tx)];
+        }
+        uint32_t carry[SUPER_TILES];
+#pragma unroll
+        for (int b = 0; b < SUPER_TILES; ++b) carry[b] = (uint32_t)__builtin_amdgcn_readlane((int)start, b);
+        for (uint32_t ub = u0; ub < u1; ub += LEGS_WAVE) {
+            const uint32_t u = ub + lane;
+            const bool ok = u < u1;
+            uint4 q[SUPER_TILES / 4];
+            uint4 *row = reinterpret_cast<uint4 *>(ucnt + (int64_t)u * SUPER_TILES);
+#pragma unroll
+            for (int k = 0; k < SUPER_TILES / 4; ++k) q[k] = ok ? row[k] : make_uint4(0u, 0u, 0u, 0u);
+            uint32_t *x = reinterpret_cast<uint32_t *>(q);
+#pragma unroll
+            for (int b = 0; b < SUPER_TILES; ++b) {
+                const uint32_t incl = wave_incl_add(x[b]);
+                const uint32_t excl = carry[b] + incl - x[b];
+                carry[b] += (uint32_t)__builtin_amdgcn_readlane((int)incl, LEGS_WAVE - 1);
+                x[b] = excl;
+            }
+            if (ok)
+#pragma unroll
+                for (int k = 0; k < SUPER_TILES / 4; ++k) row[k] = q[k];
+        }
+    }
+}
+
+// Writes the tile lists: each wave takes a unit and holds its entries' tile
+// masks, one entry per lane and round of 64. Per tile, the entries covering
+// it get their rank among the unit's hits (ballot per round); their (id,
+// depth) pairs are placed in rank order in an LDS row of the wave, which is
+// then stored as one contiguous run of the tile's list with all lanes.
+__global__ void __launch_bounds__(256)
+k_compact_write(const uint32_t *__restrict__ clist0, const uint32_t *__restrict__ clist1,
+                const uint32_t *__restrict__ desc, const uint32_t *__restrict__ cranges,
+                const uint32_t *__restrict__ uoff, int64_t n, const legs_view *__restrict__ sviews,
+                const legs_view *__restrict__ views, int n_views, const FRec *__restrict__ frecs, int64_t G,
+                const uint64_t *__restrict__ cut, const uint32_t *__restrict__ ucnt, int64_t capacity,
+                uint64_t *__restrict__ keys, uint32_t *__restrict__ ids)
+{
+    constexpr int NQ = UNIT / LEGS_WAVE;
+    __shared__ uint2 s_run[256 / LEGS_WAVE][UNIT];   // (id, depth bits) of one tile's hits, in order
+    const uint32_t *clist = ((desc[0] - 1u) & 1u) ? clist1 : clist0;
+    const int lane = legs_lane(), wave = threadIdx.x / LEGS_WAVE;
+    uint2 *run = s_run[wave];
+    const uint32_t nunits = uoff[n];
+    const uint64_t cpos = cut[0], ckeep = cut[1];
+    const uint32_t nw = gridDim.x * (256 / LEGS_WAVE);
+    for (uint32_t u = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * (256 / LEGS_WAVE) + wave));
+         u < nunits; u += nw) {
+        const UnitCtx c = unit_ctx(u, uoff, n, cranges, sviews, views, n_views);
+        const uint32_t o = lane < SUPER_TILES ? ucnt[(int64_t)u * SUPER_TILES + lane] : 0u;
+        uint32_t m[NQ];
+        uint2 gd[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const uint32_t e = c.e0 + q * LEGS_WAVE + lane;
+            m[q] = 0;
+            gd[q] = make_uint2(0u, 0u);
+            if (e < c.e1) {
+                const uint32_t pos = clist[e];
+                if ((int64_t)pos < G) {
+                    const FRec r = frecs[pos];
+                    m[q] = entry_mask(pos, r, c, cpos, ckeep);
+                    gd[q] = make_uint2(r.gid, r.dbits);
+                }
+            }
+        }
+        const int64_t tbase = c.toff + (int64_t)c.ty0 * c.tiles_x + c.tx0;
+        for (int b = 0; b < SUPER_TILES; ++b) {
+            uint32_t tot = 0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const uint64_t bal = legs_ballot((m[q] >> b) & 1u);
+                if ((m[q] >> b) & 1u)
+                    run[tot + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))] = gd[q];
+                tot += (uint32_t)__popcll(bal);
+            }
+            if (tot == 0) continue;
+            const uint32_t start = (uint32_t)__builtin_amdgcn_readlane((int)o, b);
+            const uint64_t tile = (uint64_t)(tbase + (int64_t)(b / SX) * c.tiles_x + b % SX);
+            for (uint32_t k = lane; k < tot; k += LEGS_WAVE) {
+                const uint2 v = run[k];
+                const int64_t at = (int64_t)start + k;
+                if (at < capacity) {
+                    keys[at] = (tile << 32) | v.y;
+                    ids[at] = v.x;
+                }
+            }
+        }
     }
 }
 
@@ -1034,6 +1382,7 @@ k_ranges(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ count, 
 
 legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles)
 {
+    auto up = [](int64_t x) { return (x + 255) & ~(int64_t)255; };
     legs_sort_layout L;
     const int64_t parts = (capacity + LEGS_SORT_PART - 1) / LEGS_SORT_PART;
     L.parts = parts > 0 ? parts : 1;
@@ -1041,16 +1390,27 @@ legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles)
     L.start_off = L.hist_off + 4 * LEGS_SORT_MAX_PASSES * 256;
     L.counter_off = L.start_off + 4 * LEGS_SORT_MAX_PASSES * 256;
     L.status_off = L.counter_off + 256;  // 64 counters
-    L.tcount_off = L.status_off + 8 * (int64_t)LEGS_SORT_MAX_PASSES * L.parts * 256;
-    L.tile_blocks = (total_tiles + 1023) / 1024;
-    L.tsum_off = (L.tcount_off + 4 * total_tiles + 255) & ~(int64_t)255;
-    L.toff_off = L.tsum_off + 8 * (L.tile_blocks + 1);
-    L.pstart_off = (L.toff_off + 8 * (L.tile_blocks + 1) + 8 + 255) & ~(int64_t)255;
-    const int64_t np_ = total_tiles > 0 ? L.parts : 0;    // the G-view sort needs none of these
-    L.dep_off = (L.pstart_off + 4 * np_ + 255) & ~(int64_t)255;
-    L.part_off = (L.dep_off + (total_tiles > 0 ? 8 * capacity : 0) + 255) & ~(int64_t)255;
-    L.seg_off = (L.part_off + 4 * (int64_t)LEGS_TILE_CHUNKS * total_tiles + 255) & ~(int64_t)255;
-    L.total = L.seg_off + (total_tiles > 0 ? 2 * 4 * (int64_t)LEGS_SEG_MAX * 256 : 0);
+    int64_t o = up(L.status_off + 8 * (int64_t)LEGS_SORT_MAX_PASSES * L.parts * 256);
+    const int64_t T = total_tiles > 0 ? total_tiles : 0;   // the G-view sort needs none of these
+    L.tile_blocks = (T + 1023) / 1024;
+    L.ccap = T > 0 ? capacity + T : 0;
+    L.cparts = (L.ccap + LEGS_SORT_PART - 1) / LEGS_SORT_PART;
+    const int64_t units = T > 0 ? L.ccap / LEGS_COMPACT_UNIT + T : 0;
+    L.tcount_off = o; o = up(o + 4 * T);
+    L.tsum_off = o; o = up(o + 8 * (L.tile_blocks + 1));
+    L.toff_off = o; o = up(o + 8 * (L.tile_blocks + 2));
+    L.scount_off = o; o = up(o + 4 * T);
+    L.ssum_off = o; o = up(o + 8 * (L.tile_blocks + 1));
+    L.soff_off = o; o = up(o + 8 * (L.tile_blocks + 2));
+    L.cranges_off = o; o = up(o + 8 * T);
+    L.uoff_off = o; o = up(o + 4 * (T + 1));
+    L.desc_off = o; o = up(o + 256);
+    L.pstart_off = o; o = up(o + 4 * L.cparts);
+    L.clist_off = o; o = up(o + 16 * L.ccap);
+    L.ucnt_off = o; o = up(o + 4 * 32 * units);
+    L.part_off = o; o = up(o + 4 * (int64_t)LEGS_TILE_CHUNKS * T);
+    L.seg_off = o; o = up(o + (T > 0 ? 2 * 4 * (int64_t)LEGS_SEG_MAX * 256 : 0));
+    L.total = o;
     return L;
 }
 
@@ -1069,30 +1429,42 @@ struct SortScratch {
     uint32_t *hist, *starts, *counters;
     uint64_t *status;
     int64_t parts;
-    uint32_t *tcount;
-    uint64_t *tsum, *toff;
-    int64_t tile_blocks;
-    uint32_t *pstart, *dep, *partial, *seg_hist, *seg_off;
+    // depth-first binning
+    int64_t tile_blocks, ccap, cparts;
+    uint32_t *tcount, *scount, *cranges, *uoff, *desc, *pstart, *clist, *ucnt, *partial, *seg_hist, *seg_off;
+    uint64_t *tsum, *toff, *ssum, *soff, *cut;
 };
 
 SortScratch sort_scratch_at(void *base, int64_t capacity, int64_t total_tiles = 0)
 {
     const legs_sort_layout L = legs_sort_layout_for(capacity, total_tiles);
     char *b = static_cast<char *>(base);
+    auto u32 = [b](int64_t off) { return reinterpret_cast<uint32_t *>(b + off); };
+    auto u64 = [b](int64_t off) { return reinterpret_cast<uint64_t *>(b + off); };
     SortScratch S;
-    S.hist = reinterpret_cast<uint32_t *>(b + L.hist_off);
-    S.starts = reinterpret_cast<uint32_t *>(b + L.start_off);
-    S.counters = reinterpret_cast<uint32_t *>(b + L.counter_off);
-    S.status = reinterpret_cast<uint64_t *>(b + L.status_off);
+    S.hist = u32(L.hist_off);
+    S.starts = u32(L.start_off);
+    S.counters = u32(L.counter_off);
+    S.status = u64(L.status_off);
     S.parts = L.parts;
-    S.tcount = reinterpret_cast<uint32_t *>(b + L.tcount_off);
-    S.tsum = reinterpret_cast<uint64_t *>(b + L.tsum_off);
-    S.toff = reinterpret_cast<uint64_t *>(b + L.toff_off);
     S.tile_blocks = L.tile_blocks;
-    S.pstart = reinterpret_cast<uint32_t *>(b + L.pstart_off);
-    S.dep = reinterpret_cast<uint32_t *>(b + L.dep_off);
-    S.partial = reinterpret_cast<uint32_t *>(b + L.part_off);
-    S.seg_hist = reinterpret_cast<uint32_t *>(b + L.seg_off);
+    S.ccap = L.ccap;
+    S.cparts = L.cparts;
+    S.tcount = u32(L.tcount_off);
+    S.tsum = u64(L.tsum_off);
+    S.toff = u64(L.toff_off);
+    S.scount = u32(L.scount_off);
+    S.ssum = u64(L.ssum_off);
+    S.soff = u64(L.soff_off);
+    S.cranges = u32(L.cranges_off);
+    S.uoff = u32(L.uoff_off);
+    S.desc = u32(L.desc_off);
+    S.cut = u64(L.desc_off + 128);
+    S.pstart = u32(L.pstart_off);
+    S.clist = u32(L.clist_off);
+    S.ucnt = u32(L.ucnt_off);
+    S.partial = u32(L.part_off);
+    S.seg_hist = u32(L.seg_off);
     S.seg_off = S.seg_hist + (int64_t)LEGS_SEG_MAX * 256;
     return S;
 }
@@ -1118,10 +1490,10 @@ int32_t radix_passes(legs_ctx *ctx, const SortScratch &S, uint64_t *k0, uint32_t
     uint64_t *ka = k0, *kb = k1;
     uint32_t *va = v0, *vb = v1;
     for (int p = first; p < last; ++p) {
-        hipLaunchKernelGGL((k_onesweep<uint64_t, false, false, false, false>), dim3(gsort),
-                           dim3(LEGS_SORT_THREADS), 0, s, ka, va, nullptr, kb, vb, nullptr, nullptr, count,
-                           capacity, p, 8 * p, 8, S.starts, S.status + (int64_t)(p - first) * S.parts * 256,
-                           S.counters + (p - first), TileEmit{}, nullptr);
+        hipLaunchKernelGGL((k_onesweep<uint64_t, false, false>), dim3(gsort), dim3(LEGS_SORT_THREADS), 0, s,
+                           ka, va, kb, vb, count, capacity, p, 8 * p, 8, nullptr, S.starts,
+                           S.status + (int64_t)(p - first) * S.parts * 256, S.counters + (p - first),
+                           TileEmit{}, nullptr);
         LEGS_CHECK_LAUNCH(ctx);
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
@@ -1131,7 +1503,8 @@ int32_t radix_passes(legs_ctx *ctx, const SortScratch &S, uint64_t *k0, uint32_t
 
 struct OrderLayout {
     int64_t G, nbs;
-    int64_t k0, k1, v0, v1, bcounts, offsets, gcount, recs, dbits, vrange, sort, total;
+    int64_t k0, k1, v0, v1, bcounts, offsets, cbcounts, coffsets, gcount, ccount, frecs, crecs, vrange,
+        sviews, sort, total;
 };
 
 int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
@@ -1148,10 +1521,14 @@ OrderLayout order_layout(int64_t n, int32_t n_views)
     L.v1 = o; o = align256(o + 4 * L.G);
     L.bcounts = o; o = align256(o + 8 * (L.nbs + 1));
     L.offsets = o; o = align256(o + 8 * (L.nbs + 1));
+    L.cbcounts = o; o = align256(o + 8 * (L.nbs + 1));
+    L.coffsets = o; o = align256(o + 8 * (L.nbs + 1));
     L.gcount = o; o = align256(o + 8);
-    L.recs = o; o = align256(o + 16 * L.G);
-    L.dbits = o; o = align256(o + 4 * L.G);
+    L.ccount = o; o = align256(o + 8);
+    L.frecs = o; o = align256(o + 16 * L.G);
+    L.crecs = o; o = align256(o + 16 * L.G);
     L.vrange = o; o = align256(o + 16 * (int64_t)n_views);
+    L.sviews = o; o = align256(o + (int64_t)sizeof(legs_view) * n_views);
     L.sort = o; o = align256(o + legs_sort_layout_for(L.G).total);
     L.total = o;
     return L;
@@ -1175,12 +1552,17 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
 {
     const int passes = legs_sort_passes(total_tiles);
     const bool full = (o->flags & LEGS_FLAG_FULL_SORT) != 0 || !proj->order;
+    if (!full && bins->capacity + total_tiles >= (1ll << 32))
+        return legs_set_error(ctx, LEGS_ERR_ARG,
+                              "legs_bin_sort: capacity + total_tiles must be below 2^32 for the "
+                              "depth-first binning (LEGS_FLAG_FULL_SORT lifts this)");
     const SortScratch S = sort_scratch_at(bins->scratch, bins->capacity, full ? 0 : total_tiles);
-    uint64_t *offsets = nullptr;
+    uint64_t *offsets = nullptr, *coffsets = nullptr, *ccount = nullptr;
     const uint32_t *perm = nullptr;
     int64_t nblocks = 0;
     char *ord = static_cast<char *>(proj->order);
     OrderLayout OL;
+    legs_view *sviews = nullptr;
     if (!full) {
         // 1. depth order of every visible G-view: the four depth-digit passes of
         //    the key sort, run once per Gaussian instead of once per instance
@@ -1201,17 +1583,23 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
         perm = (gpass % 2 == 0) ? ov0 : ov1;
         nblocks = OL.nbs;
         uint64_t *bcounts = reinterpret_cast<uint64_t *>(ord + OL.bcounts);
+        uint64_t *cbcounts = reinterpret_cast<uint64_t *>(ord + OL.cbcounts);
         offsets = reinterpret_cast<uint64_t *>(ord + OL.offsets);
+        coffsets = reinterpret_cast<uint64_t *>(ord + OL.coffsets);
+        ccount = reinterpret_cast<uint64_t *>(ord + OL.ccount);
         uint64_t *vrange = reinterpret_cast<uint64_t *>(ord + OL.vrange);
+        sviews = reinterpret_cast<legs_view *>(ord + OL.sviews);
+        hipLaunchKernelGGL(k_super_views, dim3(1), dim3(64), 0, s, views, n_views, sviews, S.desc);
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t *>(vrange),
                            (int64_t)4 * n_views, 0u);
         if (nblocks > 0)
             hipLaunchKernelGGL(k_sorted_records, dim3((unsigned)nblocks), dim3(LEGS_PROJ_BLOCK), 0, s,
                                perm, (gpass % 2 == 0) ? ok0 : ok1,
                                reinterpret_cast<const int4 *>(proj->box), proj->depth, proj->ntiles,
-                               n, OL.G, views, o->tile, reinterpret_cast<GRec *>(ord + OL.recs),
-                               reinterpret_cast<uint32_t *>(ord + OL.dbits), vrange, bcounts);
+                               n, OL.G, views, sviews, o->tile, reinterpret_cast<FRec *>(ord + OL.frecs),
+                               reinterpret_cast<GRec *>(ord + OL.crecs), vrange, bcounts, cbcounts);
         hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, bcounts, offsets, nblocks, bins->count);
+        hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, cbcounts, coffsets, nblocks, ccount);
     } else {
         // 1'. instance offsets in Gaussian order from the projection's block counts
         nblocks = ((n + LEGS_PROJ_BLOCK - 1) / LEGS_PROJ_BLOCK) * n_views;
@@ -1258,90 +1646,102 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
         return LEGS_OK;
     }
 
-    // 2. per-tile counts of the depth-ordered stream (cut at the capacity),
-    //    tile ranges and the tile-digit histograms
-    const GRec *recs = reinterpret_cast<const GRec *>(ord + OL.recs);
+    const FRec *frecs = reinterpret_cast<const FRec *>(ord + OL.frecs);
+    const GRec *crecs = reinterpret_cast<const GRec *>(ord + OL.crecs);
     const uint64_t *vrange = reinterpret_cast<const uint64_t *>(ord + OL.vrange);
-    // tile-id bits split as evenly as possible over ceil(bits / 8) passes (13 bits:
-    // 7 + 6), so digit runs stay long and the match needs fewer ballots
-    const int tbits = bits_for(total_tiles) > 0 ? bits_for(total_tiles) : 1;
-    const int np = (tbits + 7) / 8;
-    int pw[4] = {0, 0, 0, 0}, psh[4] = {0, 0, 0, 0};
-    uint32_t widths = 0;
-    for (int p = 0, sh = 0; p < np; ++p) {
-        pw[p] = tbits / np + (p < tbits % np ? 1 : 0);
-        psh[p] = sh;
-        sh += pw[p];
-        widths |= (uint32_t)pw[p] << (4 * p);
-    }
-    hipLaunchKernelGGL(k_sort_clear, dim3(1), dim3(256), 0, s, S.status, S.parts, 0, S.counters,
-                       S.hist, bins->count, bins->capacity);
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(ctx, total_tiles, 256, 8)), dim3(256), 0, s,
-                       S.tcount, total_tiles, 0u);
-    LEGS_CHECK_LAUNCH(ctx);
+    const int64_t T = total_tiles;
+    const int gT = grid_for(ctx, T, 256, 8);
     // enough workgroups per view to spread the G-views, at most LEGS_TILE_CHUNKS
     int nch = (int)(((OL.G / (n_views > 0 ? n_views : 1)) + 8191) / 8192);
     nch = nch < 1 ? 1 : (nch > LEGS_TILE_CHUNKS ? LEGS_TILE_CHUNKS : nch);
-    hipLaunchKernelGGL(k_tile_corners, dim3((unsigned)nch, (unsigned)n_views), dim3(256), 0, s, recs,
-                       offsets, vrange, OL.G, views, bins->capacity, total_tiles, S.tcount, S.partial);
-    hipLaunchKernelGGL(k_tile_merge, dim3(grid_for(ctx, total_tiles, 256, 8)), dim3(256), 0, s,
-                       S.partial, nch, total_tiles, views, n_views, S.tcount);
+
+    // 2. per-tile counts of the depth-ordered instance stream cut at the
+    //    capacity, the tile ranges, and the G-view the cut falls in
+    hipLaunchKernelGGL(k_sort_clear, dim3(1), dim3(256), 0, s, S.status, S.parts, 0, S.counters,
+                       S.hist, bins->count, bins->capacity);
+    hipLaunchKernelGGL(k_fill_u32, dim3(gT), dim3(256), 0, s, S.tcount, T, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t *>(S.cut), (int64_t)4,
+                       0xffffffffu);
+    LEGS_CHECK_LAUNCH(ctx);
+    hipLaunchKernelGGL((k_tile_corners<FRec>), dim3((unsigned)nch, (unsigned)n_views), dim3(256), 0, s, frecs,
+                       offsets, vrange, OL.G, views, bins->capacity, T, S.tcount, S.partial, S.cut);
+    hipLaunchKernelGGL(k_tile_merge, dim3(gT), dim3(256), 0, s, S.partial, nch, T, views, n_views, S.tcount);
     hipLaunchKernelGGL(k_tile_rows, dim3(64, (unsigned)n_views), dim3(256), 0, s, S.tcount, views);
     hipLaunchKernelGGL(k_tile_cols, dim3(8, (unsigned)n_views), dim3(256), 0, s, S.tcount, views);
-    hipLaunchKernelGGL(k_tile_block_sums, dim3((unsigned)S.tile_blocks), dim3(1024), 0, s, S.tcount,
-                       total_tiles, S.tsum);
+    hipLaunchKernelGGL(k_tile_block_sums, dim3((unsigned)S.tile_blocks), dim3(1024), 0, s, S.tcount, T, S.tsum);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, S.tsum, S.toff, S.tile_blocks,
                        S.toff + S.tile_blocks + 1);
-    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)S.tile_blocks), dim3(1024), 0, s, S.tcount,
-                       total_tiles, S.toff, np, widths, bins->ranges, S.hist);
-    hipLaunchKernelGGL(k_digit_starts, dim3(np), dim3(256), 0, s, S.hist, S.starts, 0);
-    if (nblocks > 0)
-        hipLaunchKernelGGL(k_part_blocks, dim3((unsigned)((nblocks + 255) / 256)), dim3(256), 0, s,
-                           offsets, nblocks, S.parts, S.pstart);
+    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)S.tile_blocks), dim3(1024), 0, s, S.tcount, T, S.toff,
+                       nullptr, bins->ranges, S.hist);
     LEGS_CHECK_LAUNCH(ctx);
 
-    // 3. tile passes over 32-bit tile keys carrying (id, depth bits): the first
-    //    generates the instances from the depth-ordered G-view records, the last
-    //    writes the 64-bit keys and the ids. The 32-bit keys ping-pong in the two
-    //    halves of keys_alt, the ids between ids_alt and ids, the depth bits in
-    //    the sort scratch.
-    uint32_t *tk[2] = {reinterpret_cast<uint32_t *>(bins->keys_alt),
-                       reinterpret_cast<uint32_t *>(bins->keys_alt) + bins->capacity};
-    uint32_t *tv[2] = {bins->ids, bins->ids_alt};
-    uint32_t *td[2] = {S.dep, S.dep + bins->capacity};
+    // 3. the same on the super-tile grids for the coarse stream (every G-view's
+    //    super-tile rectangle, cut at the coarse capacity, which holds every
+    //    G-view the tile stream keeps): super-tile list ranges and the digit
+    //    histograms of the coarse passes
+    hipLaunchKernelGGL(k_fill_u32, dim3(gT), dim3(256), 0, s, S.scount, T, 0u);
+    hipLaunchKernelGGL((k_tile_corners<GRec>), dim3((unsigned)nch, (unsigned)n_views), dim3(256), 0, s, crecs,
+                       coffsets, vrange, OL.G, sviews, S.ccap, T, S.scount, S.partial, nullptr);
+    hipLaunchKernelGGL(k_tile_merge, dim3(gT), dim3(256), 0, s, S.partial, nch, T, sviews, n_views, S.scount);
+    hipLaunchKernelGGL(k_tile_rows, dim3(64, (unsigned)n_views), dim3(256), 0, s, S.scount, sviews);
+    hipLaunchKernelGGL(k_tile_cols, dim3(8, (unsigned)n_views), dim3(256), 0, s, S.scount, sviews);
+    hipLaunchKernelGGL(k_tile_block_sums, dim3((unsigned)S.tile_blocks), dim3(1024), 0, s, S.scount, T, S.ssum);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, S.ssum, S.soff, S.tile_blocks,
+                       S.soff + S.tile_blocks + 1);
+    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)S.tile_blocks), dim3(1024), 0, s, S.scount, T, S.soff,
+                       S.desc, S.cranges, S.hist);
+    // passes for the most super-tiles there can be (one per tile); the ones
+    // the actual count does not need return at once
+    const int cpasses = (bits_for(T) + 7) / 8 > 0 ? (bits_for(T) + 7) / 8 : 1;
+    hipLaunchKernelGGL(k_digit_starts, dim3(cpasses), dim3(256), 0, s, S.hist, S.starts, 0);
+    if (nblocks > 0)
+        hipLaunchKernelGGL(k_part_blocks, dim3((unsigned)((nblocks + 255) / 256)), dim3(256), 0, s,
+                           coffsets, nblocks, S.cparts, S.pstart);
+    LEGS_CHECK_LAUNCH(ctx);
+
+    // 4. coarse passes: stable counting sort of (super-tile, position) pairs,
+    //    the first generating them from the records; pass p writes buffer p % 2
+    uint32_t *ck[2] = {S.clist, S.clist + S.ccap};
+    uint32_t *cv[2] = {S.clist + 2 * S.ccap, S.clist + 3 * S.ccap};
     TileEmit E;
-    E.recs = recs;
-    E.dbits = reinterpret_cast<const uint32_t *>(ord + OL.dbits);
-    E.goff = offsets;
+    E.recs = crecs;
+    E.goff = coffsets;
     E.pstart = S.pstart;
     E.nblocks = nblocks;
     E.G = OL.G;
-    // every tile pass: digit counts per segment of partitions, their scan, then
-    // the pass itself with each workgroup walking its own segment in order
     const int nseg = (int)(ctx->num_cus * 2 < LEGS_SEG_MAX ? ctx->num_cus * 2 : LEGS_SEG_MAX);
-    for (int p = 0; p < np; ++p) {
-        // pass p writes buffer (np - 1 - p) % 2 (the last one: ids) and reads
-        // what the pass before it wrote
-        const int wo = (np - 1 - p) % 2, ri = 1 - wo;
-        const bool emit = p == 0, fin = p == np - 1;
-        if (emit)
-            hipLaunchKernelGGL(k_tile_upsweep_emit, dim3(nseg), dim3(256), 0, s, bins->count, bins->capacity,
-                               E, pw[p], S.seg_hist);
+    for (int p = 0; p < cpasses; ++p) {
+        const int wo = p % 2, ri = 1 - wo;
+        if (p == 0)
+            hipLaunchKernelGGL(k_tile_upsweep_emit, dim3(nseg), dim3(256), 0, s, ccount, S.ccap, E, S.desc,
+                               S.seg_hist);
         else
-            hipLaunchKernelGGL(k_tile_upsweep, dim3(nseg), dim3(LEGS_SORT_THREADS), 0, s, tk[ri],
-                               bins->count, bins->capacity, psh[p], pw[p], S.seg_hist);
-        hipLaunchKernelGGL(k_seg_scan, dim3(256), dim3(LEGS_SEG_MAX), 0, s, S.seg_hist, nseg, S.starts, p,
-                           S.seg_off);
-#define LEGS_TILE_PASS(EM, FI)                                                                      \
-        hipLaunchKernelGGL((k_onesweep<uint32_t, true, EM, FI, true>), dim3(nseg), dim3(LEGS_SORT_THREADS), \
-                           0, s, tk[ri], tv[ri], td[ri], tk[wo], tv[wo], td[wo], bins->keys, bins->count, \
-                           bins->capacity, p, psh[p], pw[p], S.starts, nullptr, nullptr, E, S.seg_off)
-        if (emit && fin) LEGS_TILE_PASS(true, true);
-        else if (emit) LEGS_TILE_PASS(true, false);
-        else if (fin) LEGS_TILE_PASS(false, true);
-        else LEGS_TILE_PASS(false, false);
-#undef LEGS_TILE_PASS
+            hipLaunchKernelGGL(k_tile_upsweep, dim3(nseg), dim3(LEGS_SORT_THREADS), 0, s, ck[ri], ccount,
+                               S.ccap, S.desc, p, S.seg_hist);
+        hipLaunchKernelGGL(k_seg_scan, dim3(256), dim3(LEGS_SEG_MAX), 0, s, S.seg_hist, nseg, S.starts, S.desc,
+                           p, S.seg_off);
+        if (p == 0)
+            hipLaunchKernelGGL((k_onesweep<uint32_t, true, true>), dim3(nseg), dim3(LEGS_SORT_THREADS), 0, s,
+                               ck[ri], cv[ri], ck[wo], cv[wo], ccount, S.ccap, p, 0, 0, S.desc, S.starts, nullptr,
+                               nullptr, E, S.seg_off);
+        else
+            hipLaunchKernelGGL((k_onesweep<uint32_t, false, true>), dim3(nseg), dim3(LEGS_SORT_THREADS), 0, s,
+                               ck[ri], cv[ri], ck[wo], cv[wo], ccount, S.ccap, p, 0, 0, S.desc, S.starts, nullptr,
+                               nullptr, E, S.seg_off);
         LEGS_CHECK_LAUNCH(ctx);
     }
+
+    // 5. compaction of the super-tile lists into the tile lists, in units of
+    //    LEGS_COMPACT_UNIT list entries per wave
+    const int64_t max_units = S.ccap / LEGS_COMPACT_UNIT + T;
+    const int gu = grid_for(ctx, max_units, 256 / LEGS_WAVE, 8);
+    hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, s, S.cranges, T, S.uoff);
+    hipLaunchKernelGGL(k_compact_count, dim3(gu), dim3(256), 0, s, cv[0], cv[1], S.desc, S.cranges, S.uoff, T,
+                       sviews, views, n_views, frecs, OL.G, S.cut, S.ucnt);
+    hipLaunchKernelGGL(k_compact_scan, dim3(grid_for(ctx, T, 256 / LEGS_WAVE, 4)), dim3(256), 0, s, S.uoff, T,
+                       sviews, views, n_views, bins->ranges, S.ucnt);
+    hipLaunchKernelGGL(k_compact_write, dim3(gu), dim3(256), 0, s, cv[0], cv[1], S.desc, S.cranges, S.uoff, T,
+                       sviews, views, n_views, frecs, OL.G, S.cut, S.ucnt, bins->capacity, bins->keys, bins->ids);
+    LEGS_CHECK_LAUNCH(ctx);
     return LEGS_OK;
 }
