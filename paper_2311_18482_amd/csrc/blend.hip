@@ -52,17 +52,36 @@ struct BlendParams {
     uint32_t *counter;  // non-NULL: persistent launch, tiles taken from this counter
 };
 
-// The opacity-weighted Gaussian falloff at offset (dx, dy) from the mean.
-// Shared by the forward and backward kernels so both take identical decisions.
-__device__ __forceinline__ float falloff_alpha(float dx, float dy, float A, float B, float Cc,
-                                               float op, float amax, float &ep, bool &clamped)
+// The conic (A, B, C) is staged scaled by (-log2(e)/2, -log2(e), -log2(e)/2),
+// so that the falloff exponent in base 2 is
+//   power * log2(e) = A' dx^2 + B' dx dy + C' dy^2 = a + dy (b + C' dy),
+// with a = A' dx dx and b = B' dx depending on dx only (the backward computes
+// them once per Gaussian and pixel column). ep = exp(power).
+constexpr float CONIC_SCALE_AC = -0.72134752044448170f;   // -log2(e) / 2
+constexpr float CONIC_SCALE_B = -1.44269504088896340f;    // -log2(e)
+
+__device__ __forceinline__ float4 scale_conic(float4 cn)
 {
-    float power = -0.5f * (A * dx * dx + Cc * dy * dy) - B * dx * dy;
-    power = fminf(power, 0.0f);
-    ep = __expf(power);
-    const float raw = op * ep;
+    return make_float4(cn.x * CONIC_SCALE_AC, cn.y * CONIC_SCALE_B, cn.z * CONIC_SCALE_AC, cn.w);
+}
+
+// The dx terms of the exponent for a scaled conic.
+__device__ __forceinline__ void falloff_dx(float dx, float As, float Bs, float &a, float &b)
+{
+    a = (As * dx) * dx;
+    b = Bs * dx;
+}
+
+// The opacity-weighted Gaussian falloff at row offset dy. Shared by the
+// forward and backward kernels so both take identical decisions.
+__device__ __forceinline__ float falloff_alpha(float a, float b, float dy, float Cs, float op, float amax,
+                                               float &ep, bool &clamped)
+{
+    const float p = fminf(fmaf(dy, fmaf(Cs, dy, b), a), 0.0f);
+    ep = __builtin_amdgcn_exp2f(p);
+    const float raw = op * ep;   // >= 0: the clamp to [0, amax] is min(raw, amax)
     clamped = raw > amax;
-    return clamped ? amax : raw;
+    return __builtin_amdgcn_fmed3f(raw, 0.0f, amax);
 }
 
 __device__ __forceinline__ float opaque_zero()
@@ -149,7 +168,7 @@ __device__ __forceinline__ void stage_batch(const BlendParams &P, int v, int til
             const int y0 = min(max(b[r].z - tile_y0, -1), TILE), y1 = min(max(b[r].w - tile_y0, -1), TILE);
             S.box[k] = (uint32_t)(x0 & 0xff) | ((uint32_t)(x1 & 0xff) << 8) |
                        ((uint32_t)(y0 & 0xff) << 16) | ((uint32_t)(y1 & 0xff) << 24);
-            S.c[k] = cn[r];
+            S.c[k] = scale_conic(cn[r]);
             S.id[k] = gid[r];
             if constexpr (DIRECT) {
 #pragma unroll
@@ -215,6 +234,7 @@ k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
     Stage<TILE, CP> S(s_dyn, P.batch);
     __shared__ int64_t s_tile;
     const int B = P.batch;
+    const float amax = P.amax;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / LEGS_WAVE), l = threadIdx.x % LEGS_WAVE;
     const int qxi = w % NQ, qyi = w / NQ;            // this wave's 8 x 8 quadrant
     const int qx0 = 8 * qxi, qy0 = 8 * qyi;
@@ -264,9 +284,10 @@ k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
                         const int j = c0 + jl;
                         const float4 cn = S.c[j];
                         const float dx = S.qx[j * NQ + qxi] - fx, dy = S.qy[j * NQ + qyi] - fy;
-                        float ep;
+                        float a, b, ep;
                         bool clamped;
-                        const float alpha = falloff_alpha(dx, dy, cn.x, cn.y, cn.z, cn.w, P.amax, ep, clamped);
+                        falloff_dx(dx, cn.x, cn.y, a, b);
+                        const float alpha = falloff_alpha(a, b, dy, cn.z, cn.w, amax, ep, clamped);
                         if (!(alpha < P.amin)) {
                             const float Tn = T * (1.0f - alpha);
                             if (Tn < P.tmin) {
@@ -334,6 +355,7 @@ k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restr
     __shared__ int64_t s_tile;
     __shared__ uint32_t s_maxlast;
     const int B = P.batch;
+    const float amax = P.amax;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / LEGS_WAVE), l = threadIdx.x % LEGS_WAVE;
     constexpr int BX = TILE / Shp::SW;                 // wave blocks per tile row
     const int bx0 = (w % BX) * Shp::SW, by0 = (w / BX) * Shp::SH;
@@ -383,6 +405,15 @@ k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restr
         if (myL) atomicMax(&s_maxlast, myL);
         __syncthreads();
         const uint32_t maxL = min(s_maxlast, ti.re - ti.rs);
+        // deepest list position any pixel of each band still blends (wave-uniform)
+        uint32_t bandL[PPL];
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            uint32_t x = L[p];
+#pragma unroll
+            for (int off = 1; off < LEGS_WAVE; off <<= 1) x = max(x, (uint32_t)__shfl_xor((int)x, off, LEGS_WAVE));
+            bandL[p] = (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+        }
 
         for (uint32_t hi = maxL; hi > 0;) {
             const uint32_t lo_rel = hi > (uint32_t)B ? hi - (uint32_t)B : 0u;
@@ -394,62 +425,68 @@ k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restr
                 const int x0 = sext8(pk, 0), x1 = sext8(pk, 8), y0 = sext8(pk, 16), y1 = sext8(pk, 24);
                 if (x1 < bx0 || x0 > bx0 + Shp::SW - 1 || y1 < by0 || y0 > by0 + Shp::SH - 1) continue;
                 const float4 cn = S.c[j];
-                const float mqx = S.qx[j * NQ + qxi];
+                const float dx = S.qx[j * NQ + qxi] - fx;   // constant over this lane's pixels
+                float fa, fb;
+                falloff_dx(dx, cn.x, cn.y, fa, fb);
+                const bool col_in = lx >= x0 && lx <= x1;
                 float cv[CP];
 #pragma unroll
                 for (int c = 0; c < CP; ++c) cv[c] = S.ch[j * CP + c];
                 // zeros the compiler cannot fold into the first band's arithmetic (a
                 // folded first band gives the skipped-band paths register copies)
-                float sx = opaque_zero(), sy = opaque_zero(), sxx = opaque_zero(), sxy = opaque_zero(),
-                      syy = opaque_zero(), sop = opaque_zero();
+                float s0 = opaque_zero(), sy = opaque_zero(), syy = opaque_zero(), sop = opaque_zero();
                 float acc[NV];
 #pragma unroll
                 for (int c = 0; c < CP; ++c) acc[6 + c] = opaque_zero();
                 bool any = false;
-                // Per-lane conditions are folded into the arithmetic (zero weights)
-                // so that only wave-uniform branches remain.
 #pragma unroll
                 for (int p = 0; p < PPL; ++p) {
-                    // rows of band p: by0 + ROWSTEP p + [0, ROWSTEP)
-                    if (y1 < by0 + Shp::ROWSTEP * p || y0 > by0 + Shp::ROWSTEP * p + Shp::ROWSTEP - 1) continue;
+                    // rows of band p: by0 + ROWSTEP p + [0, ROWSTEP); pixels of the band
+                    // stop before position bandL[p]
+                    if (pos >= bandL[p] || y1 < by0 + Shp::ROWSTEP * p ||
+                        y0 > by0 + Shp::ROWSTEP * p + Shp::ROWSTEP - 1)
+                        continue;
                     const int ly = ly0 + Shp::ROWSTEP * p;
-                    const bool inside = pos < L[p] && lx >= x0 && lx <= x1 && ly >= y0 && ly <= y1;
-                    if (legs_ballot(inside) == 0) continue;
-                    const float dx = mqx - fx, dy = S.qy[j * NQ + (ly >> 3)] - (float)(ly & 7);
+                    const bool inside = col_in && pos < L[p] && ly >= y0 && ly <= y1;
+                    const float dy = S.qy[j * NQ + (ly >> 3)] - (float)(ly & 7);
                     float ep;
                     bool clamped;
-                    const float alpha = falloff_alpha(dx, dy, cn.x, cn.y, cn.z, cn.w, P.amax, ep, clamped);
-                    const bool bl = inside && !(alpha < P.amin);
-                    if (legs_ballot(bl) == 0) continue;
-                    any = true;
-                    const float Tk = bl ? T[p] * __builtin_amdgcn_rcpf(1.0f - alpha) : T[p];
-                    const float wgt = bl ? alpha * Tk : 0.0f;
-                    float g = 0.0f;
+                    const float alpha = falloff_alpha(fa, fb, dy, cn.z, cn.w, amax, ep, clamped);
+                    if (inside && !(alpha < P.amin)) {   // this pixel blends entry j
+                        any = true;
+                        const float Tk = T[p] * __builtin_amdgcn_rcpf(1.0f - alpha);
+                        const float wgt = alpha * Tk;
+                        float g0 = 0.0f, g1 = 0.0f;
 #pragma unroll
-                    for (int c = 0; c < CP; ++c) {
-                        acc[6 + c] = fmaf(wgt, G[p][c], acc[6 + c]);
-                        g = fmaf(G[p][c], cv[c], g);
+                        for (int c = 0; c < CP; ++c) {
+                            acc[6 + c] = fmaf(wgt, G[p][c], acc[6 + c]);
+                            if (c & 1) g1 = fmaf(G[p][c], cv[c], g1);
+                            else g0 = fmaf(G[p][c], cv[c], g0);
+                        }
+                        const float dot = (g0 + g1) - gs[p];
+                        gs[p] = fmaf(alpha, dot, gs[p]);
+                        T[p] = Tk;
+                        if (!clamped) {                      // dL/dalpha below the clamp
+                            const float dg = Tk * dot;
+                            sop = fmaf(dg, ep, sop);
+                            const float dpow = dg * alpha;
+                            s0 += dpow;
+                            const float ey = dpow * dy;
+                            sy += ey;
+                            syy = fmaf(ey, dy, syy);
+                        }
                     }
-                    const float dot = g - gs[p];
-                    const float dalpha = bl ? Tk * dot : 0.0f;
-                    gs[p] = bl ? fmaf(alpha, dot, gs[p]) : gs[p];
-                    T[p] = Tk;
-                    const float dg = clamped ? 0.0f : dalpha;
-                    sop = fmaf(dg, ep, sop);
-                    const float dpow = dg * alpha;
-                    const float ex = dpow * dx, ey = dpow * dy;
-                    sx += ex;
-                    sy += ey;
-                    sxx = fmaf(ex, dx, sxx);
-                    sxy = fmaf(ex, dy, sxy);
-                    syy = fmaf(ey, dy, syy);
                 }
-                if (!any) continue;
+                if (legs_ballot(any) == 0) continue;
+                // power = -(A dx^2 + 2 B dx dy + C dy^2) / 2 with the unscaled conic:
                 // d/dmean = -(conic . (dx, dy)) dpow, d/dA = -dx^2/2 dpow, d/dB = -dx dy dpow, ...
-                acc[0] = -fmaf(cn.x, sx, cn.y * sy);
-                acc[1] = -fmaf(cn.y, sx, cn.z * sy);
-                acc[2] = -0.5f * sxx;
-                acc[3] = -sxy;
+                const float A = cn.x * (1.0f / CONIC_SCALE_AC), Bc = cn.y * (1.0f / CONIC_SCALE_B),
+                            Cc = cn.z * (1.0f / CONIC_SCALE_AC);
+                const float sx = dx * s0;
+                acc[0] = -fmaf(A, sx, Bc * sy);
+                acc[1] = -fmaf(Bc, sx, Cc * sy);
+                acc[2] = -0.5f * (dx * sx);
+                acc[3] = -(dx * sy);
                 acc[4] = -0.5f * syy;
                 acc[5] = sop;
                 legs_tr::reduce<NV>(acc, l);
@@ -479,6 +516,7 @@ k_blend_count(BlendParams P, unsigned long long *__restrict__ counts)
 {
     const int64_t tile = blockIdx.x;
     const TileInfo ti = tile_info<TILE>(P, tile);
+    const float amax = P.amax;
     const int lx = threadIdx.x % TILE, ly = threadIdx.x / TILE;
     const int px = ti.tile_x0 + lx, py = ti.tile_y0 + ly;
     uint64_t ef = 0, bl = 0, eb = 0, walked = 0;
@@ -494,12 +532,13 @@ k_blend_count(BlendParams P, unsigned long long *__restrict__ counts)
             const int4 b = P.box[gv];
             if (px < b.x || px > b.y || py < b.z || py > b.w) continue;
             const double2 m = P.mean2d[gv];
-            const float4 cn = P.conic[gv];
+            const float4 cn = scale_conic(P.conic[gv]);
             const float dx = (float)(m.x - ((double)bx + 0.5)) - fx;
             const float dy = (float)(m.y - ((double)by + 0.5)) - fy;
-            float ep;
+            float fa, fb, ep;
             bool clamped;
-            const float alpha = falloff_alpha(dx, dy, cn.x, cn.y, cn.z, cn.w, P.amax, ep, clamped);
+            falloff_dx(dx, cn.x, cn.y, fa, fb);
+            const float alpha = falloff_alpha(fa, fb, dy, cn.z, cn.w, amax, ep, clamped);
             ++ef;
             if (alpha < P.amin) { ++skipped_since_blend; continue; }
             const float Tn = T * (1.0f - alpha);

@@ -28,7 +28,7 @@ int32_t legs_set_error(legs_ctx *ctx, int32_t code, const char *fmt, ...);
 
 // ---- device helpers ---------------------------------------------------------
 
-__device__ __forceinline__ uint64_t legs_ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint64_t legs_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ int legs_lane() { return __lane_id(); }
 
