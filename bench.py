@@ -179,6 +179,15 @@ def cpu_baseline(scene, cams, tile, budget_s=30.0):
                 sample=f"one full forward+backward step of the same workload ({px} px), {dt:.1f} s")
 
 
+def coarse_entries(proj, tile, sx=8, sy=4):
+    """Super-tile entries of the two-level binning (8 x 4-tile super-tiles):
+    statistics for the byte model, computed on the host from the boxes."""
+    box = proj.box.cpu().numpy().astype(np.int64)
+    vis = proj.ntiles.cpu().numpy() > 0
+    tx0, tx1, ty0, ty1 = (box[vis, k] // tile for k in range(4))
+    return int(((tx1 // sx - tx0 // sx + 1) * (ty1 // sy - ty0 // sy + 1)).sum())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,9 +228,16 @@ def main():
     T = torch.empty(views.total_pixels, dtype=torch.float32, device=dev)
     last = torch.empty(views.total_pixels, dtype=torch.int32, device=dev)
     G = torch.from_numpy(__import__("synth").upstream_grads(cams, C, 200)).to(dev)
-    grad2d = torch.zeros((n * views.n_views, 8), dtype=torch.float32, device=dev)
-    d_ch = torch.zeros((n, C), dtype=torch.float32, device=dev)
-    grads = {k: torch.zeros_like(d[k]) for k in ("mean", "log_scale", "quat", "opacity_logit")}
+    # every gradient buffer is a slice of one flat allocation, cleared by one fill per step
+    gshapes = {"grad2d": (n * views.n_views, 8), "d_ch": (n, C)}
+    gshapes.update({k: tuple(d[k].shape) for k in ("mean", "log_scale", "quat", "opacity_logit")})
+    gflat = torch.zeros(sum(int(np.prod(sh)) for sh in gshapes.values()), dtype=torch.float32, device=dev)
+    gviews, at = {}, 0
+    for k, sh in gshapes.items():
+        gviews[k] = gflat[at:at + int(np.prod(sh))].view(sh)
+        at += int(np.prod(sh))
+    grad2d, d_ch = gviews["grad2d"], gviews["d_ch"]
+    grads = {k: gviews[k] for k in ("mean", "log_scale", "quat", "opacity_logit")}
     stages = ("project", "bin_sort", "blend_fwd", "zero", "blend_bwd", "project_bwd")
 
     def step(ev=None):
@@ -235,10 +251,7 @@ def main():
         mark(2)
         R.render_forward(rast.ctx, proj, bins, views, d["channels"], o, out, T, last)
         mark(3)
-        grad2d.zero_()
-        d_ch.zero_()
-        for g in grads.values():
-            g.zero_()
+        gflat.zero_()
         mark(4)
         R.render_backward(rast.ctx, proj, bins, views, d["channels"], o, T, last, G, grad2d, d_ch)
         mark(5)
@@ -275,12 +288,15 @@ def main():
     ev, blended, ev_bwd, _walked = R.render_counts(rast.ctx, proj, bins, views, o)
     G_views = n * views.n_views
     gpasses = (32 + max(1, int(np.ceil(np.log2(max(views.n_views, 1))))) + 7) // 8
+    n_coarse = coarse_entries(proj, args.tile)
     work = {
         "project": ("hbm", G_views * (44 + 16 + 16 + 16 + 4 + 4)),
-        # G-view depth sort (8 + 4 B keys and ids per pass each way) and records,
-        # then per instance: the first tile pass writes 12 B, the second reads 4 B
-        # (its digit counts) and 12 B and writes 12 B
-        "bin_sort": ("hbm", G_views * (24 * gpasses + 20 + 20) + n_inst * 40),
+        # per G-view: the depth sort (8 + 4 B keys and ids per pass each way), the
+        # records (36 B read, 32 B written), the cell counts (32 B) and the coarse
+        # emission (16 B); per super-tile entry: the coarse pass writes 8 B, the
+        # compaction reads the list and the tile record twice (40 B); per
+        # instance: the compaction writes 12 B
+        "bin_sort": ("hbm", G_views * (24 * gpasses + 68 + 32 + 16) + n_coarse * 48 + n_inst * 12),
         "project_bwd": ("hbm", G_views * (44 + 32 + 44 + 4)),
         "blend_fwd": ("alu", ev * FLOPS_EVAL + blended * (4 + 2 * C)),
         "blend_bwd": ("alu", ev_bwd * FLOPS_EVAL + blended * (40 + 7 * C)),
@@ -335,7 +351,7 @@ def main():
                data="synthetic",
                config=dict(workload=desc, n_gaussians=int(n), views=len(cams), pixels=int(px),
                            channels=int(C), tile=args.tile, lds_batch=args.lds_batch,
-                           instances=int(n_inst), alpha_evaluations=int(ev),
+                           instances=int(n_inst), super_tile_entries=int(n_coarse), alpha_evaluations=int(ev),
                            blended_entries=int(blended), stage_ms=stage_ms),
                roofline=roofline, decode=dec, cpu_baseline=cpu)
     print(json.dumps(rec), flush=True)

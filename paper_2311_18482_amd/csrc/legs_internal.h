@@ -99,6 +99,7 @@ struct legs_sort_layout {
     int64_t clist_off;     // uint32 [4][ccap] coarse keys and positions, two buffers each
     int64_t ucnt_off;      // uint32 [ccap / unit + total_tiles][32] per-unit tile counts / offsets
     int64_t part_off;      // uint32 [LEGS_TILE_CHUNKS][total_tiles] partial tile-count grids
+    int64_t spart_off;     // uint32 [LEGS_TILE_CHUNKS][total_tiles] partial super-tile-count grids
     int64_t seg_off;       // uint32 [2][LEGS_SEG_MAX][256] segment digit counts and starts
     int64_t total;
 };
@@ -108,7 +109,7 @@ legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles = 0)
 #define LEGS_SORT_ITEMS 8
 #define LEGS_SORT_PART (LEGS_SORT_THREADS * LEGS_SORT_ITEMS)
 #define LEGS_SORT_MAX_PASSES 8
-#define LEGS_TILE_CHUNKS 128
+#define LEGS_TILE_CHUNKS 256
 #define LEGS_SEG_MAX 1024
 #define LEGS_COMPACT_UNIT 256
 // counter slots (u32) in the sort scratch's counter block: 0..15 sort passes

@@ -37,9 +37,8 @@ __device__ __forceinline__ void st_status(uint64_t *p, uint64_t v)
 
 // One workgroup: exclusive scan of counts[0..nb) into offsets[0..nb], total
 // in offsets[nb] and in *total (counts stay intact, so the binning can rerun).
-__global__ void __launch_bounds__(1024)
-k_scan_blocks(const uint64_t *__restrict__ counts, uint64_t *__restrict__ offsets, int64_t nb,
-              uint64_t *__restrict__ total)
+__device__ __forceinline__ void scan_blocks(const uint64_t *__restrict__ counts, uint64_t *__restrict__ offsets,
+                                            int64_t nb, uint64_t *__restrict__ total)
 {
     __shared__ uint64_t s_w[16];
     __shared__ uint64_t s_carry;
@@ -69,6 +68,27 @@ k_scan_blocks(const uint64_t *__restrict__ counts, uint64_t *__restrict__ offset
         offsets[nb] = s_carry;
         *total = s_carry;
     }
+}
+
+__global__ void __launch_bounds__(1024)
+k_scan_blocks(const uint64_t *__restrict__ counts, uint64_t *__restrict__ offsets, int64_t nb,
+              uint64_t *__restrict__ total)
+{
+    scan_blocks(counts, offsets, nb, total);
+}
+
+// Two independent scans, one workgroup each.
+struct ScanArgs {
+    const uint64_t *counts;
+    uint64_t *offsets;
+    int64_t nb;
+    uint64_t *total;
+};
+
+__global__ void __launch_bounds__(1024) k_scan_pair(ScanArgs a, ScanArgs b)
+{
+    const ScanArgs &x = blockIdx.x == 0 ? a : b;
+    scan_blocks(x.counts, x.offsets, x.nb, x.total);
 }
 
 // ---- emission -------------------------------------------------------------------
@@ -844,16 +864,18 @@ k_part_blocks(const uint64_t *__restrict__ goff, int64_t nblocks, int64_t parts_
     for (int64_t p = plo; p < phi; ++p) pstart[p] = (uint32_t)b;
 }
 
-// ---- per-tile counts of the depth-ordered instance stream ----------------------
+// ---- per-tile counts of the depth-ordered streams ------------------------------
 
-// The first `capacity` instances of the depth-ordered stream are counted per
-// tile on a 2D difference array (the tile grid of each view): +1 / -1 at the
-// corners of each G-view's tile rectangle, then prefix sums along the rows and
-// the columns. A G-view cut by the capacity contributes its first tiles in
-// row-major order (full rows plus one partial row). The counts give the
-// tile ranges and the digit histograms of the tile passes without reading
-// the instances.
-// +1 / -1 at the corners of a tile rectangle (view-local tile coordinates).
+// Two streams are counted per cell of a 2D difference array: the tile stream
+// (each G-view's tile rectangle, the first `capacity` instances kept) on the
+// tile grids of the views, and the coarse stream (each G-view's super-tile
+// rectangle, the first `ccap` kept) on the super-tile grids: +1 / -1 at the
+// corners of each rectangle, then prefix sums along the rows and the columns.
+// A G-view cut by its capacity contributes its first cells in row-major order
+// (full rows plus one partial row). The counts give the list ranges (and the
+// digit histograms of the coarse passes) without reading any instance. Every
+// kernel below handles both grids at once (grid 0: tiles, grid 1: super-tiles).
+// +1 / -1 at the corners of a rectangle (view-local cell coordinates).
 __device__ __forceinline__ void diff_rect(uint32_t *g, int W, int H, int x0, int x1, int y0, int y1)
 {
     atomicAdd(g + y0 * W + x0, 1u);
@@ -862,112 +884,136 @@ __device__ __forceinline__ void diff_rect(uint32_t *g, int W, int H, int x0, int
     if (x1 + 1 < W && y1 + 1 < H) atomicAdd(g + (y1 + 1) * W + x1 + 1, 1u);
 }
 
-constexpr int TILE_LDS_CELLS = 16384;   // views with at most this many tiles count in LDS
+// Adds a rectangle cut to its first `keep` cells.
+__device__ __forceinline__ void diff_rect_kept(uint32_t *g, int W, int H, int x0, int y0, int w, int h,
+                                               uint64_t keep)
+{
+    if (keep >= (uint64_t)w * (uint64_t)h) {
+        diff_rect(g, W, H, x0, x0 + w - 1, y0, y0 + h - 1);
+    } else {
+        const int full = (int)(keep / (uint64_t)w), rem = (int)(keep % (uint64_t)w);
+        if (full > 0) diff_rect(g, W, H, x0, x0 + w - 1, y0, y0 + full - 1);
+        if (rem > 0) diff_rect(g, W, H, x0, x0 + rem - 1, y0 + full, y0 + full);
+    }
+}
 
-// Rectangle of a record in view-local (super-)tile coordinates.
-struct Rect {
-    int x0, y0, w, h;
+constexpr int TILE_LDS_CELLS = 16384;   // tile grids with at most this many cells count in LDS
+constexpr int SUPER_LDS_CELLS = 4096;   // super-tile grids likewise
+
+// One of the two count grids.
+struct CountGrid {
+    const legs_view *views;   // the tile or super-tile views
+    uint32_t *count;          // [T] cells (at most T of them)
+    uint32_t *partial;        // [LEGS_TILE_CHUNKS][T] per-workgroup LDS grids
+    uint64_t *bsum;           // [tile_blocks + 1] sums of 1024 cells
+    uint64_t *boff;           // [tile_blocks + 2] their exclusive scan, total
+    uint32_t *ranges;         // [T][2]
+    const uint32_t *desc;     // digit layout of passes over these cells (NULL: none)
+    uint32_t *hist;           // digit histograms of those passes
 };
-__device__ __forceinline__ uint32_t rec_count(const FRec &r) { return (r.wh & 0xffffu) * (r.wh >> 16); }
-__device__ __forceinline__ uint32_t rec_count(const GRec &r) { return r.cnt; }
-__device__ __forceinline__ Rect rec_rect(const FRec &r, const legs_view &)
-{
-    return {(int)(r.xy & 0xffffu), (int)(r.xy >> 16), (int)(r.wh & 0xffffu), (int)(r.wh >> 16)};
-}
-__device__ __forceinline__ Rect rec_rect(const GRec &r, const legs_view &vw)
-{
-    const int local = (int)((int64_t)r.base - vw.tile_offset);
-    const int w = (int)(r.rwtx & 0xffffu);
-    return {local % vw.tiles_x, local / vw.tiles_x, w, (int)(r.cnt / (uint32_t)w)};
-}
 
 // Workgroup (c, v) adds the rectangles of view v's G-views in position blocks
-// c, c + gridDim.x, ... into an LDS copy of the view's tile grid and stores it
-// in partial[c] (views with more tiles than fit add straight into the global
-// grid with atomics); k_tile_merge then sums the partial grids. Hot corner
-// cells cost LDS atomics instead of global ones. With `cut`, the G-view whose
-// instances reach past the capacity stores its position and how many of its
-// tiles fit (at most one G-view does).
-template <typename R>
+// c, c + gridDim.x, ... to LDS copies of the view's tile and super-tile grids
+// and stores them in the partial grids of chunk c (grids with more cells than
+// fit add straight into the count arrays with atomics); k_count_merge then sums
+// the partial grids. Hot corner cells cost LDS atomics instead of global ones.
+// The G-view whose tile instances reach past the capacity stores its position
+// and how many of its tiles fit in cut (at most one G-view does).
 __global__ void __launch_bounds__(256)
-k_tile_corners(const R *__restrict__ recs, const uint64_t *__restrict__ goff,
-               const uint64_t *__restrict__ vrange, int64_t G,
-               const legs_view *__restrict__ views, int64_t capacity, int64_t total_tiles,
-               uint32_t *__restrict__ diff, uint32_t *__restrict__ partial, uint64_t *__restrict__ cut)
+k_count_corners(const FRec *__restrict__ frecs, const GRec *__restrict__ crecs,
+                const uint64_t *__restrict__ goff, const uint64_t *__restrict__ coff,
+                const uint64_t *__restrict__ vrange, int64_t G, int64_t capacity, int64_t ccap, int64_t T,
+                CountGrid g0, CountGrid g1, uint64_t *__restrict__ cut)
 {
     __shared__ uint32_t s_grid[TILE_LDS_CELLS];
-    __shared__ uint64_t s_start[257];
+    __shared__ uint32_t s_sgrid[SUPER_LDS_CELLS];
+    __shared__ uint64_t s_start[257], s_cstart[257];
     __shared__ uint64_t s_w[4];
     const int v = blockIdx.y;
-    const legs_view vw = views[v];
-    const int W = vw.tiles_x, H = vw.tiles_y;
-    const int ncell = W * H;
-    const bool lds = ncell <= TILE_LDS_CELLS;
-    uint32_t *g = lds ? s_grid : diff + vw.tile_offset;
+    const legs_view vw = g0.views[v], sw = g1.views[v];
+    const int W = vw.tiles_x, H = vw.tiles_y, SWd = sw.tiles_x, SH = sw.tiles_y;
+    const int ncell = W * H, nscell = SWd * SH;
+    const bool lds = ncell <= TILE_LDS_CELLS, slds = nscell <= SUPER_LDS_CELLS;
+    uint32_t *g = lds ? s_grid : g0.count + vw.tile_offset;
+    uint32_t *sg = slds ? s_sgrid : g1.count + sw.tile_offset;
     if (lds)
         for (int i = threadIdx.x; i < ncell; i += 256) s_grid[i] = 0u;
+    if (slds)
+        for (int i = threadIdx.x; i < nscell; i += 256) s_sgrid[i] = 0u;
     const int64_t p0 = (int64_t)vrange[2 * v], p1 = (int64_t)vrange[2 * v + 1];
     __syncthreads();
     if (p1 > p0) {
         for (int64_t b = p0 / 256 + blockIdx.x; b <= (p1 - 1) / 256; b += gridDim.x) {
             const int64_t pos = b * 256 + threadIdx.x;
-            // the whole block is scanned: its offset counts the positions of other views too
-            const R r = pos < G ? recs[pos] : R{0u, 0u, 0u, 0u};
-            block_scan_256<256>(rec_count(r), s_start, s_w);
-            const uint64_t off = goff[b] + s_start[threadIdx.x];
-            const uint32_t cnt = pos >= p0 && pos < p1 ? rec_count(r) : 0u;
-            if (cut && cnt && off <= (uint64_t)capacity && off + cnt > (uint64_t)capacity) {
-                cut[0] = (uint64_t)pos;
-                cut[1] = (uint64_t)capacity - off;
-            }
-            if (cnt && off < (uint64_t)capacity) {
-                const uint64_t keep = (uint64_t)capacity - off < cnt ? (uint64_t)capacity - off : cnt;
-                const Rect q = rec_rect(r, vw);
-                if (keep == cnt) {
-                    diff_rect(g, W, H, q.x0, q.x0 + q.w - 1, q.y0, q.y0 + q.h - 1);
-                } else {
-                    const int full = (int)(keep / (uint64_t)q.w), rem = (int)(keep % (uint64_t)q.w);
-                    if (full > 0) diff_rect(g, W, H, q.x0, q.x0 + q.w - 1, q.y0, q.y0 + full - 1);
-                    if (rem > 0) diff_rect(g, W, H, q.x0, q.x0 + rem - 1, q.y0 + full, q.y0 + full);
+            // the whole block is scanned: its offsets count the positions of other views too
+            const FRec f = pos < G ? frecs[pos] : FRec{0u, 0u, 0u, 0u};
+            const GRec r = pos < G ? crecs[pos] : GRec{0u, 0u, 0u, 0u};
+            const uint32_t fw = f.wh & 0xffffu, fh = f.wh >> 16;
+            block_scan_256<256>((uint64_t)fw * fh, s_start, s_w);
+            block_scan_256<256>(r.cnt, s_cstart, s_w);
+            if (pos >= p0 && pos < p1 && fw) {
+                const uint32_t cnt = fw * fh;
+                const uint64_t off = goff[b] + s_start[threadIdx.x];
+                if (off <= (uint64_t)capacity && off + cnt > (uint64_t)capacity) {
+                    cut[0] = (uint64_t)pos;
+                    cut[1] = (uint64_t)capacity - off;
+                }
+                if (off < (uint64_t)capacity)
+                    diff_rect_kept(g, W, H, (int)(f.xy & 0xffffu), (int)(f.xy >> 16), (int)fw, (int)fh,
+                                   (uint64_t)capacity - off);
+                const uint64_t co = coff[b] + s_cstart[threadIdx.x];
+                if (co < (uint64_t)ccap) {
+                    const int local = (int)((int64_t)r.base - sw.tile_offset);
+                    const int cw = (int)(r.rwtx & 0xffffu);
+                    diff_rect_kept(sg, SWd, SH, local % SWd, local / SWd, cw, (int)(r.cnt / (uint32_t)cw),
+                                   (uint64_t)ccap - co);
                 }
             }
             __syncthreads();
         }
     }
+    __syncthreads();
     if (lds) {
-        __syncthreads();
-        uint32_t *out = partial + (int64_t)blockIdx.x * total_tiles + vw.tile_offset;
+        uint32_t *out = g0.partial + (int64_t)blockIdx.x * T + vw.tile_offset;
         for (int i = threadIdx.x; i < ncell; i += 256) out[i] = s_grid[i];
     }
-}
-
-// Sum of the partial grids of views counted in LDS (the others already hold
-// their counts in diff). total_tiles may exceed the grid's cells (the
-// super-tile grids): cells past the last view are left alone.
-__global__ void __launch_bounds__(256)
-k_tile_merge(const uint32_t *__restrict__ partial, int nch, int64_t total_tiles,
-             const legs_view *__restrict__ views, int n_views, uint32_t *__restrict__ diff)
-{
-    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total_tiles; t += (int64_t)gridDim.x * 256) {
-        const legs_view &vw = views[legs_view_of_tile(views, n_views, t)];
-        const int64_t ncell = (int64_t)vw.tiles_x * vw.tiles_y;
-        if (ncell > TILE_LDS_CELLS || t - vw.tile_offset >= ncell) continue;
-        uint32_t acc = 0;
-#pragma unroll 8
-        for (int c = 0; c < nch; ++c) acc += partial[(int64_t)c * total_tiles + t];
-        diff[t] = acc;
+    if (slds) {
+        uint32_t *out = g1.partial + (int64_t)blockIdx.x * T + sw.tile_offset;
+        for (int i = threadIdx.x; i < nscell; i += 256) out[i] = s_sgrid[i];
     }
 }
 
-// Inclusive prefix sums along the tile rows of view blockIdx.y: one wave per row.
+// Sum of the partial grids of the grids counted in LDS (the others already
+// hold their counts). T may exceed a grid's cells (the super-tile grids):
+// cells past its last view are left alone.
 __global__ void __launch_bounds__(256)
-k_tile_rows(uint32_t *__restrict__ diff, const legs_view *__restrict__ views)
+k_count_merge(int nch, int64_t T, int n_views, CountGrid g0, CountGrid g1)
 {
-    const legs_view vw = views[blockIdx.y];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < 2 * T; i += (int64_t)gridDim.x * 256) {
+        const bool sup = i >= T;
+        const int64_t t = sup ? i - T : i;
+        const CountGrid &cg = sup ? g1 : g0;
+        const legs_view &vw = cg.views[legs_view_of_tile(cg.views, n_views, t)];
+        const int64_t ncell = (int64_t)vw.tiles_x * vw.tiles_y;
+        if (ncell > (sup ? SUPER_LDS_CELLS : TILE_LDS_CELLS) || t - vw.tile_offset >= ncell) continue;
+        uint32_t acc = 0;
+#pragma unroll 8
+        for (int c = 0; c < nch; ++c) acc += cg.partial[(int64_t)c * T + t];
+        cg.count[t] = acc;
+    }
+}
+
+// Inclusive prefix sums along the rows of view blockIdx.y of grid blockIdx.z:
+// one wave per row.
+__global__ void __launch_bounds__(256)
+k_count_rows(CountGrid g0, CountGrid g1)
+{
+    const CountGrid &cg = blockIdx.z ? g1 : g0;
+    const legs_view vw = cg.views[blockIdx.y];
     const int lane = legs_lane();
     const int row0 = blockIdx.x * 4 + (int)(threadIdx.x / LEGS_WAVE);
     for (int y = row0; y < vw.tiles_y; y += gridDim.x * 4) {
-        uint32_t *r = diff + vw.tile_offset + (int64_t)y * vw.tiles_x;
+        uint32_t *r = cg.count + vw.tile_offset + (int64_t)y * vw.tiles_x;
         uint32_t carry = 0;
         for (int x0 = 0; x0 < vw.tiles_x; x0 += LEGS_WAVE) {
             const int x = x0 + lane;
@@ -983,53 +1029,64 @@ k_tile_rows(uint32_t *__restrict__ diff, const legs_view *__restrict__ views)
     }
 }
 
-// Inclusive prefix sums down the tile columns of view blockIdx.y: one lane per column.
+// Inclusive prefix sums down the columns of view blockIdx.y of grid
+// blockIdx.z: one wave per column, 64 rows at a time.
 __global__ void __launch_bounds__(256)
-k_tile_cols(uint32_t *__restrict__ diff, const legs_view *__restrict__ views)
+k_count_cols(CountGrid g0, CountGrid g1)
 {
-    const legs_view vw = views[blockIdx.y];
-    for (int x = blockIdx.x * 256 + threadIdx.x; x < vw.tiles_x; x += gridDim.x * 256) {
-        uint32_t *col = diff + vw.tile_offset + x;
-        uint32_t acc = 0;
-        for (int y = 0; y < vw.tiles_y; ++y) {
-            acc += col[(int64_t)y * vw.tiles_x];
-            col[(int64_t)y * vw.tiles_x] = acc;
+    const CountGrid &cg = blockIdx.z ? g1 : g0;
+    const legs_view vw = cg.views[blockIdx.y];
+    const int lane = legs_lane();
+    const int col0 = blockIdx.x * 4 + (int)(threadIdx.x / LEGS_WAVE);
+    for (int x = col0; x < vw.tiles_x; x += gridDim.x * 4) {
+        uint32_t *col = cg.count + vw.tile_offset + x;
+        uint32_t carry = 0;
+        for (int y0 = 0; y0 < vw.tiles_y; y0 += LEGS_WAVE) {
+            const int y = y0 + lane;
+            uint32_t incl = y < vw.tiles_y ? col[(int64_t)y * vw.tiles_x] : 0u;
+#pragma unroll
+            for (int off = 1; off < LEGS_WAVE; off <<= 1) {
+                const uint32_t t = __shfl_up(incl, off, LEGS_WAVE);
+                if (lane >= off) incl += t;
+            }
+            if (y < vw.tiles_y) col[(int64_t)y * vw.tiles_x] = carry + incl;
+            carry += (uint32_t)__shfl((int)incl, LEGS_WAVE - 1, LEGS_WAVE);
         }
     }
 }
 
-// Sum of the tile counts of each block of 1024 tiles.
+// Sum of each block of 1024 cells of grid blockIdx.y.
 __global__ void __launch_bounds__(1024)
-k_tile_block_sums(const uint32_t *__restrict__ counts, int64_t total_tiles, uint64_t *__restrict__ sums)
+k_count_block_sums(int64_t T, CountGrid g0, CountGrid g1)
 {
+    const CountGrid &cg = blockIdx.y ? g1 : g0;
     __shared__ uint64_t s_w[16];
     const int64_t t = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-    uint64_t x = t < total_tiles ? counts[t] : 0u;
+    uint64_t x = t < T ? cg.count[t] : 0u;
 #pragma unroll
     for (int off = LEGS_WAVE / 2; off > 0; off >>= 1) x += __shfl_down(x, off, LEGS_WAVE);
     if (legs_lane() == 0) s_w[threadIdx.x / LEGS_WAVE] = x;
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint64_t s = 0;
-        for (int w = 0; w < 16; ++w) s += s_w[w];
-        sums[blockIdx.x] = s;
+        uint64_t sum = 0;
+        for (int w = 0; w < 16; ++w) sum += s_w[w];
+        cg.bsum[blockIdx.x] = sum;
     }
 }
 
-// Tile ranges [start, start + count) from the scanned counts and, with desc,
-// the digit histograms of the coarse passes over these ids.
+// List ranges [start, start + count) of the cells of grid blockIdx.y from the
+// scanned counts, and with desc the digit histograms of the passes over them.
 __global__ void __launch_bounds__(1024)
-k_tile_ranges(const uint32_t *__restrict__ counts, int64_t total_tiles,
-              const uint64_t *__restrict__ boff, const uint32_t *__restrict__ desc,
-              uint32_t *__restrict__ ranges, uint32_t *__restrict__ hist)
+k_count_ranges(int64_t T, CountGrid g0, CountGrid g1)
 {
-    const int npass = desc ? (int)desc[0] : 0;
+    const CountGrid &cg = blockIdx.y ? g1 : g0;
     __shared__ uint32_t s_h[4][256];
     __shared__ uint64_t s_w[16];
+    const int npass = cg.desc ? (int)cg.desc[0] : 0;
     for (int i = threadIdx.x; i < 4 * 256; i += 1024) (&s_h[0][0])[i] = 0;
     const int lane = legs_lane(), wave = threadIdx.x / LEGS_WAVE;
     const int64_t t = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-    const uint64_t x = t < total_tiles ? counts[t] : 0u;
+    const uint64_t x = t < T ? cg.count[t] : 0u;
     uint64_t incl = x;
 #pragma unroll
     for (int off = 1; off < LEGS_WAVE; off <<= 1) {
@@ -1040,18 +1097,19 @@ k_tile_ranges(const uint32_t *__restrict__ counts, int64_t total_tiles,
     __syncthreads();
     uint64_t wpre = 0;
     for (int w = 0; w < wave; ++w) wpre += s_w[w];
-    if (t < total_tiles) {
-        const uint64_t st = boff[blockIdx.x] + wpre + incl - x;
-        ranges[2 * t] = (uint32_t)st;
-        ranges[2 * t + 1] = (uint32_t)(st + x);
+    if (t < T) {
+        const uint64_t st = cg.boff[blockIdx.x] + wpre + incl - x;
+        cg.ranges[2 * t] = (uint32_t)st;
+        cg.ranges[2 * t + 1] = (uint32_t)(st + x);
         if (x)
             for (int p = 0; p < npass; ++p)
-                atomicAdd(&s_h[p][(uint32_t)(t >> desc[2 + 2 * p]) & ((1u << desc[3 + 2 * p]) - 1u)], (uint32_t)x);
+                atomicAdd(&s_h[p][(uint32_t)(t >> cg.desc[2 + 2 * p]) & ((1u << cg.desc[3 + 2 * p]) - 1u)],
+                          (uint32_t)x);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < npass * 256; i += 1024) {
         const uint32_t c = (&s_h[0][0])[i];
-        if (c) atomicAdd(&hist[i], c);
+        if (c) atomicAdd(&cg.hist[i], c);
     }
 }
 
@@ -1060,11 +1118,18 @@ k_tile_ranges(const uint32_t *__restrict__ counts, int64_t total_tiles,
 // Super-tile grids of the views (SX x SY tiles each, numbered after one
 // another like the tile grids) and the digit layout of the coarse passes:
 // ceil(bits / 8) passes over the bits of the super-tile id, split evenly.
-// One thread (n_views is small).
-__global__ void k_super_views(const legs_view *__restrict__ views, int n_views, legs_view *__restrict__ sv,
-                              uint32_t *__restrict__ desc)
+// The other threads clear the digit histograms and pass counters, the
+// capacity cut (no G-view cut) and the per-view position ranges.
+__global__ void __launch_bounds__(256)
+k_super_views(const legs_view *__restrict__ views, int n_views, legs_view *__restrict__ sv,
+              uint32_t *__restrict__ desc, uint32_t *__restrict__ hist, uint32_t *__restrict__ counters,
+              uint64_t *__restrict__ cut, uint64_t *__restrict__ vrange)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = threadIdx.x; i < LEGS_SORT_MAX_PASSES * 256; i += 256) hist[i] = 0u;
+    for (int i = threadIdx.x; i < 2 * n_views; i += 256) vrange[i] = 0u;
+    if (threadIdx.x < 16) counters[threadIdx.x] = 0u;
+    if (threadIdx.x < 2) cut[threadIdx.x] = ~0ull;
+    if (threadIdx.x != 0) return;
     int64_t off = 0;
     for (int v = 0; v < n_views; ++v) {
         legs_view w = views[v];
@@ -1397,9 +1462,9 @@ legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles)
     L.cparts = (L.ccap + LEGS_SORT_PART - 1) / LEGS_SORT_PART;
     const int64_t units = T > 0 ? L.ccap / LEGS_COMPACT_UNIT + T : 0;
     L.tcount_off = o; o = up(o + 4 * T);
+    L.scount_off = o; o = up(o + 4 * T);     // right after tcount: both are cleared at once
     L.tsum_off = o; o = up(o + 8 * (L.tile_blocks + 1));
     L.toff_off = o; o = up(o + 8 * (L.tile_blocks + 2));
-    L.scount_off = o; o = up(o + 4 * T);
     L.ssum_off = o; o = up(o + 8 * (L.tile_blocks + 1));
     L.soff_off = o; o = up(o + 8 * (L.tile_blocks + 2));
     L.cranges_off = o; o = up(o + 8 * T);
@@ -1409,6 +1474,7 @@ legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles)
     L.clist_off = o; o = up(o + 16 * L.ccap);
     L.ucnt_off = o; o = up(o + 4 * 32 * units);
     L.part_off = o; o = up(o + 4 * (int64_t)LEGS_TILE_CHUNKS * T);
+    L.spart_off = o; o = up(o + 4 * (int64_t)LEGS_TILE_CHUNKS * T);
     L.seg_off = o; o = up(o + (T > 0 ? 2 * 4 * (int64_t)LEGS_SEG_MAX * 256 : 0));
     L.total = o;
     return L;
@@ -1431,7 +1497,8 @@ struct SortScratch {
     int64_t parts;
     // depth-first binning
     int64_t tile_blocks, ccap, cparts;
-    uint32_t *tcount, *scount, *cranges, *uoff, *desc, *pstart, *clist, *ucnt, *partial, *seg_hist, *seg_off;
+    uint32_t *tcount, *scount, *cranges, *uoff, *desc, *pstart, *clist, *ucnt, *partial, *spartial, *seg_hist,
+        *seg_off;
     uint64_t *tsum, *toff, *ssum, *soff, *cut;
 };
 
@@ -1464,6 +1531,7 @@ SortScratch sort_scratch_at(void *base, int64_t capacity, int64_t total_tiles = 
     S.clist = u32(L.clist_off);
     S.ucnt = u32(L.ucnt_off);
     S.partial = u32(L.part_off);
+    S.spartial = u32(L.spart_off);
     S.seg_hist = u32(L.seg_off);
     S.seg_off = S.seg_hist + (int64_t)LEGS_SEG_MAX * 256;
     return S;
@@ -1589,17 +1657,16 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
         ccount = reinterpret_cast<uint64_t *>(ord + OL.ccount);
         uint64_t *vrange = reinterpret_cast<uint64_t *>(ord + OL.vrange);
         sviews = reinterpret_cast<legs_view *>(ord + OL.sviews);
-        hipLaunchKernelGGL(k_super_views, dim3(1), dim3(64), 0, s, views, n_views, sviews, S.desc);
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t *>(vrange),
-                           (int64_t)4 * n_views, 0u);
+        hipLaunchKernelGGL(k_super_views, dim3(1), dim3(256), 0, s, views, n_views, sviews, S.desc, S.hist,
+                           S.counters, S.cut, vrange);
         if (nblocks > 0)
             hipLaunchKernelGGL(k_sorted_records, dim3((unsigned)nblocks), dim3(LEGS_PROJ_BLOCK), 0, s,
                                perm, (gpass % 2 == 0) ? ok0 : ok1,
                                reinterpret_cast<const int4 *>(proj->box), proj->depth, proj->ntiles,
                                n, OL.G, views, sviews, o->tile, reinterpret_cast<FRec *>(ord + OL.frecs),
                                reinterpret_cast<GRec *>(ord + OL.crecs), vrange, bcounts, cbcounts);
-        hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, bcounts, offsets, nblocks, bins->count);
-        hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, cbcounts, coffsets, nblocks, ccount);
+        hipLaunchKernelGGL(k_scan_pair, dim3(2), dim3(1024), 0, s, ScanArgs{bcounts, offsets, nblocks, bins->count},
+                           ScanArgs{cbcounts, coffsets, nblocks, ccount});
     } else {
         // 1'. instance offsets in Gaussian order from the projection's block counts
         nblocks = ((n + LEGS_PROJ_BLOCK - 1) / LEGS_PROJ_BLOCK) * n_views;
@@ -1650,46 +1717,32 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     const GRec *crecs = reinterpret_cast<const GRec *>(ord + OL.crecs);
     const uint64_t *vrange = reinterpret_cast<const uint64_t *>(ord + OL.vrange);
     const int64_t T = total_tiles;
-    const int gT = grid_for(ctx, T, 256, 8);
     // enough workgroups per view to spread the G-views, at most LEGS_TILE_CHUNKS
-    int nch = (int)(((OL.G / (n_views > 0 ? n_views : 1)) + 8191) / 8192);
+    int nch = (int)(((OL.G / (n_views > 0 ? n_views : 1)) + 4095) / 4096);
     nch = nch < 1 ? 1 : (nch > LEGS_TILE_CHUNKS ? LEGS_TILE_CHUNKS : nch);
 
-    // 2. per-tile counts of the depth-ordered instance stream cut at the
-    //    capacity, the tile ranges, and the G-view the cut falls in
-    hipLaunchKernelGGL(k_sort_clear, dim3(1), dim3(256), 0, s, S.status, S.parts, 0, S.counters,
-                       S.hist, bins->count, bins->capacity);
-    hipLaunchKernelGGL(k_fill_u32, dim3(gT), dim3(256), 0, s, S.tcount, T, 0u);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t *>(S.cut), (int64_t)4,
-                       0xffffffffu);
+    // 2. per-cell counts of the tile stream (cut at the capacity) and of the
+    //    coarse stream (every G-view's super-tile rectangle, cut at the coarse
+    //    capacity, which holds every G-view the tile stream keeps): the tile
+    //    ranges, the super-tile list ranges, the digit histograms of the coarse
+    //    passes, and the G-view the tile cut falls in
+    CountGrid cg0{views, S.tcount, S.partial, S.tsum, S.toff, bins->ranges, nullptr, nullptr};
+    CountGrid cg1{sviews, S.scount, S.spartial, S.ssum, S.soff, S.cranges, S.desc, S.hist};
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(ctx, 2 * T, 256, 8)), dim3(256), 0, s, S.tcount,
+                       (int64_t)(S.scount - S.tcount) + T, 0u);
     LEGS_CHECK_LAUNCH(ctx);
-    hipLaunchKernelGGL((k_tile_corners<FRec>), dim3((unsigned)nch, (unsigned)n_views), dim3(256), 0, s, frecs,
-                       offsets, vrange, OL.G, views, bins->capacity, T, S.tcount, S.partial, S.cut);
-    hipLaunchKernelGGL(k_tile_merge, dim3(gT), dim3(256), 0, s, S.partial, nch, T, views, n_views, S.tcount);
-    hipLaunchKernelGGL(k_tile_rows, dim3(64, (unsigned)n_views), dim3(256), 0, s, S.tcount, views);
-    hipLaunchKernelGGL(k_tile_cols, dim3(8, (unsigned)n_views), dim3(256), 0, s, S.tcount, views);
-    hipLaunchKernelGGL(k_tile_block_sums, dim3((unsigned)S.tile_blocks), dim3(1024), 0, s, S.tcount, T, S.tsum);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, S.tsum, S.toff, S.tile_blocks,
-                       S.toff + S.tile_blocks + 1);
-    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)S.tile_blocks), dim3(1024), 0, s, S.tcount, T, S.toff,
-                       nullptr, bins->ranges, S.hist);
+    hipLaunchKernelGGL(k_count_corners, dim3((unsigned)nch, (unsigned)n_views), dim3(256), 0, s, frecs, crecs,
+                       offsets, coffsets, vrange, OL.G, bins->capacity, S.ccap, T, cg0, cg1, S.cut);
+    hipLaunchKernelGGL(k_count_merge, dim3(grid_for(ctx, 2 * T, 256, 8)), dim3(256), 0, s, nch, T, n_views, cg0,
+                       cg1);
+    hipLaunchKernelGGL(k_count_rows, dim3(64, (unsigned)n_views, 2), dim3(256), 0, s, cg0, cg1);
+    hipLaunchKernelGGL(k_count_cols, dim3(64, (unsigned)n_views, 2), dim3(256), 0, s, cg0, cg1);
+    hipLaunchKernelGGL(k_count_block_sums, dim3((unsigned)S.tile_blocks, 2), dim3(1024), 0, s, T, cg0, cg1);
+    hipLaunchKernelGGL(k_scan_pair, dim3(2), dim3(1024), 0, s,
+                       ScanArgs{S.tsum, S.toff, S.tile_blocks, S.toff + S.tile_blocks + 1},
+                       ScanArgs{S.ssum, S.soff, S.tile_blocks, S.soff + S.tile_blocks + 1});
+    hipLaunchKernelGGL(k_count_ranges, dim3((unsigned)S.tile_blocks, 2), dim3(1024), 0, s, T, cg0, cg1);
     LEGS_CHECK_LAUNCH(ctx);
-
-    // 3. the same on the super-tile grids for the coarse stream (every G-view's
-    //    super-tile rectangle, cut at the coarse capacity, which holds every
-    //    G-view the tile stream keeps): super-tile list ranges and the digit
-    //    histograms of the coarse passes
-    hipLaunchKernelGGL(k_fill_u32, dim3(gT), dim3(256), 0, s, S.scount, T, 0u);
-    hipLaunchKernelGGL((k_tile_corners<GRec>), dim3((unsigned)nch, (unsigned)n_views), dim3(256), 0, s, crecs,
-                       coffsets, vrange, OL.G, sviews, S.ccap, T, S.scount, S.partial, nullptr);
-    hipLaunchKernelGGL(k_tile_merge, dim3(gT), dim3(256), 0, s, S.partial, nch, T, sviews, n_views, S.scount);
-    hipLaunchKernelGGL(k_tile_rows, dim3(64, (unsigned)n_views), dim3(256), 0, s, S.scount, sviews);
-    hipLaunchKernelGGL(k_tile_cols, dim3(8, (unsigned)n_views), dim3(256), 0, s, S.scount, sviews);
-    hipLaunchKernelGGL(k_tile_block_sums, dim3((unsigned)S.tile_blocks), dim3(1024), 0, s, S.scount, T, S.ssum);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, S.ssum, S.soff, S.tile_blocks,
-                       S.soff + S.tile_blocks + 1);
-    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)S.tile_blocks), dim3(1024), 0, s, S.scount, T, S.soff,
-                       S.desc, S.cranges, S.hist);
     // passes for the most super-tiles there can be (one per tile); the ones
     // the actual count does not need return at once
     const int cpasses = (bits_for(T) + 7) / 8 > 0 ? (bits_for(T) + 7) / 8 : 1;
