@@ -98,6 +98,8 @@ struct legs_sort_layout {
     int64_t pstart_off;    // uint32 [cparts] first G-view block of each coarse partition
     int64_t clist_off;     // uint32 [4][ccap] coarse keys and positions, two buffers each
     int64_t ucnt_off;      // uint32 [ccap / unit + total_tiles][32] per-unit tile counts / offsets
+    int64_t udesc_off;     // [ccap / unit + total_tiles] 32-byte unit descriptors
+    int64_t cpay_off;      // [ccap] 16-byte tile records of the sorted coarse list
     int64_t part_off;      // uint32 [LEGS_TILE_CHUNKS][total_tiles] partial tile-count grids
     int64_t spart_off;     // uint32 [LEGS_TILE_CHUNKS][total_tiles] partial super-tile-count grids
     int64_t seg_off;       // uint32 [2][LEGS_SEG_MAX][256] segment digit counts and starts

@@ -276,6 +276,8 @@ struct TileEmit {
     const uint64_t *goff;      // [nblocks + 1]
     const uint32_t *pstart;    // [partitions]
     int64_t nblocks, G;
+    const FRec *frecs;         // with pay: the last coarse pass also writes
+    FRec *pay;                 // pay[i] = frecs[position of list entry i]
 };
 
 // Inclusive maximum over lanes 0..l of a wave (DPP row shifts, then the row
@@ -433,6 +435,7 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__res
            uint64_t *__restrict__ status, uint32_t *__restrict__ counter, TileEmit E,
            const uint32_t *__restrict__ seg_off)
 {
+    const bool payload = E.pay != nullptr && desc != nullptr && pass == (int)desc[0] - 1;
     if (desc) {
         shift = (int)desc[2 + 2 * pass];
         rb = (int)desc[3 + 2 * pass];
@@ -624,6 +627,11 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__res
                 if (gpos < (uint64_t)capacity) {
                     kout[gpos] = kk;
                     vout[gpos] = s_vals[k];
+                    // the partition's positions span a narrow window: these gathers stay in cache
+                    if (payload) {
+                        const uint32_t pv = s_vals[k];
+                        E.pay[gpos] = (int64_t)pv < E.G ? E.frecs[pv] : FRec{0u, 0u, 0u, 0u};
+                    }
                 }
             }
         }
@@ -1232,6 +1240,18 @@ __device__ __forceinline__ UnitCtx unit_ctx(uint32_t u, const uint32_t *__restri
     return c;
 }
 
+// Descriptor of every unit (its super-tile found by binary search over the
+// unit offsets), so that each compaction wave starts from one load.
+__global__ void __launch_bounds__(256)
+k_unit_desc(const uint32_t *__restrict__ uoff, int64_t n, const uint32_t *__restrict__ cranges,
+            const legs_view *__restrict__ sviews, const legs_view *__restrict__ views, int n_views,
+            UnitCtx *__restrict__ udesc)
+{
+    const uint32_t nunits = uoff[n];
+    for (uint32_t u = blockIdx.x * 256 + threadIdx.x; u < nunits; u += gridDim.x * 256)
+        udesc[u] = unit_ctx(u, uoff, n, cranges, sviews, views, n_views);
+}
+
 // Tiles of the super-tile at (tx0, ty0) that the record's rectangle covers:
 // bit (ty - ty0) * SX + (tx - tx0). The G-view at position cut[0] keeps only
 // its first cut[1] tiles in row-major order, the ones after it none (their
@@ -1270,9 +1290,8 @@ __device__ __forceinline__ uint32_t entry_mask(uint32_t pos, const FRec &r, cons
 // Counts of each of the 32 tiles in each unit: ucnt[u * 32 + b].
 __global__ void __launch_bounds__(256)
 k_compact_count(const uint32_t *__restrict__ clist0, const uint32_t *__restrict__ clist1,
-                const uint32_t *__restrict__ desc, const uint32_t *__restrict__ cranges,
-                const uint32_t *__restrict__ uoff, int64_t n, const legs_view *__restrict__ sviews,
-                const legs_view *__restrict__ views, int n_views, const FRec *__restrict__ frecs, int64_t G,
+                const uint32_t *__restrict__ desc, const uint32_t *__restrict__ uoff, int64_t n,
+                const UnitCtx *__restrict__ udesc, const FRec *__restrict__ pay, int64_t G,
                 const uint64_t *__restrict__ cut, uint32_t *__restrict__ ucnt)
 {
     // pass p of the coarse sort writes buffer p % 2
@@ -1283,7 +1302,7 @@ k_compact_count(const uint32_t *__restrict__ clist0, const uint32_t *__restrict_
     const uint32_t nw = gridDim.x * (256 / LEGS_WAVE);
     for (uint32_t u = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * (256 / LEGS_WAVE) + threadIdx.x / LEGS_WAVE));
          u < nunits; u += nw) {
-        const UnitCtx c = unit_ctx(u, uoff, n, cranges, sviews, views, n_views);
+        const UnitCtx c = udesc[u];
         uint32_t cnt[SUPER_TILES];
 #pragma unroll
         for (int b = 0; b < SUPER_TILES; ++b) cnt[b] = 0;
@@ -1292,7 +1311,7 @@ k_compact_count(const uint32_t *__restrict__ clist0, const uint32_t *__restrict_
             uint32_t m = 0;
             if (e < c.e1) {
                 const uint32_t pos = clist[e];
-                if ((int64_t)pos < G) m = entry_mask(pos, frecs[pos], c, cpos, ckeep);
+                if ((int64_t)pos < G) m = entry_mask(pos, pay[e], c, cpos, ckeep);
             }
 #pragma unroll
             for (int b = 0; b < SUPER_TILES; ++b) cnt[b] += (uint32_t)__popcll(legs_ballot((m >> b) & 1u));
@@ -1358,26 +1377,27 @@ k_compact_scan(const uint32_t *__restrict__ uoff, int64_t n, const legs_view *__
 // masks, one entry per lane and round of 64. Per tile, the entries covering
 // it get their rank among the unit's hits (ballot per round); their (id,
 // depth) pairs are placed in rank order in an LDS row of the wave, which is
-// then stored as one contiguous run of the tile's list with all lanes.
+// then stored as one contiguous run of the tile's list with all lanes. Four
+// tiles are staged per LDS round trip.
 __global__ void __launch_bounds__(256)
 k_compact_write(const uint32_t *__restrict__ clist0, const uint32_t *__restrict__ clist1,
-                const uint32_t *__restrict__ desc, const uint32_t *__restrict__ cranges,
-                const uint32_t *__restrict__ uoff, int64_t n, const legs_view *__restrict__ sviews,
-                const legs_view *__restrict__ views, int n_views, const FRec *__restrict__ frecs, int64_t G,
+                const uint32_t *__restrict__ desc, const uint32_t *__restrict__ uoff, int64_t n,
+                const UnitCtx *__restrict__ udesc, const FRec *__restrict__ pay, int64_t G,
                 const uint64_t *__restrict__ cut, const uint32_t *__restrict__ ucnt, int64_t capacity,
                 uint64_t *__restrict__ keys, uint32_t *__restrict__ ids)
 {
     constexpr int NQ = UNIT / LEGS_WAVE;
-    __shared__ uint2 s_run[256 / LEGS_WAVE][UNIT];   // (id, depth bits) of one tile's hits, in order
+    constexpr int TB = 4;                                   // tiles per LDS round trip
+    __shared__ uint2 s_run[256 / LEGS_WAVE][TB][UNIT];      // (id, depth bits) of the hits, in order
     const uint32_t *clist = ((desc[0] - 1u) & 1u) ? clist1 : clist0;
     const int lane = legs_lane(), wave = threadIdx.x / LEGS_WAVE;
-    uint2 *run = s_run[wave];
+    uint2(*run)[UNIT] = s_run[wave];
     const uint32_t nunits = uoff[n];
     const uint64_t cpos = cut[0], ckeep = cut[1];
     const uint32_t nw = gridDim.x * (256 / LEGS_WAVE);
     for (uint32_t u = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * (256 / LEGS_WAVE) + wave));
          u < nunits; u += nw) {
-        const UnitCtx c = unit_ctx(u, uoff, n, cranges, sviews, views, n_views);
+        const UnitCtx c = udesc[u];
         const uint32_t o = lane < SUPER_TILES ? ucnt[(int64_t)u * SUPER_TILES + lane] : 0u;
         uint32_t m[NQ];
         uint2 gd[NQ];
@@ -1389,32 +1409,42 @@ k_compact_write(const uint32_t *__restrict__ clist0, const uint32_t *__restrict_
             if (e < c.e1) {
                 const uint32_t pos = clist[e];
                 if ((int64_t)pos < G) {
-                    const FRec r = frecs[pos];
+                    const FRec r = pay[e];
                     m[q] = entry_mask(pos, r, c, cpos, ckeep);
                     gd[q] = make_uint2(r.gid, r.dbits);
                 }
             }
         }
         const int64_t tbase = c.toff + (int64_t)c.ty0 * c.tiles_x + c.tx0;
-        for (int b = 0; b < SUPER_TILES; ++b) {
-            uint32_t tot = 0;
+        for (int b0 = 0; b0 < SUPER_TILES; b0 += TB) {
+            uint32_t tot[TB];
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const uint64_t bal = legs_ballot((m[q] >> b) & 1u);
-                if ((m[q] >> b) & 1u)
-                    run[tot + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))] = gd[q];
-                tot += (uint32_t)__popcll(bal);
+            for (int bb = 0; bb < TB; ++bb) {
+                const int b = b0 + bb;
+                tot[bb] = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const uint64_t bal = legs_ballot((m[q] >> b) & 1u);
+                    if ((m[q] >> b) & 1u)
+                        run[bb][tot[bb] + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))] =
+                            gd[q];
+                    tot[bb] += (uint32_t)__popcll(bal);
+                }
             }
-            if (tot == 0) continue;
-            const uint32_t start = (uint32_t)__builtin_amdgcn_readlane((int)o, b);
-            const uint64_t tile = (uint64_t)(tbase + (int64_t)(b / SX) * c.tiles_x + b % SX);
-            for (uint32_t k = lane; k < tot; k += LEGS_WAVE) {
-                const uint2 v = run[k];
-                const int64_t at = (int64_t)start + k;
-                if (at < capacity) {
-                    keys[at] = (tile << 32) | v.y;
-                    ids[at] = v.x;
+#pragma unroll
+            for (int bb = 0; bb < TB; ++bb) {
+                if (tot[bb] == 0) continue;
+                const int b = b0 + bb;
+                const uint32_t start = (uint32_t)__builtin_amdgcn_readlane((int)o, b);
+                const uint64_t tile = (uint64_t)(tbase + (int64_t)(b / SX) * c.tiles_x + b % SX);
+                for (uint32_t k = lane; k < tot[bb]; k += LEGS_WAVE) {
+                    const uint2 v = run[bb][k];
+                    const int64_t at = (int64_t)start + k;
+                    if (at < capacity) {
+                        keys[at] = (tile << 32) | v.y;
+                        ids[at] = v.x;
+                    }
                 }
             }
         }
@@ -1473,6 +1503,8 @@ legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles)
     L.pstart_off = o; o = up(o + 4 * L.cparts);
     L.clist_off = o; o = up(o + 16 * L.ccap);
     L.ucnt_off = o; o = up(o + 4 * 32 * units);
+    L.udesc_off = o; o = up(o + 32 * units);
+    L.cpay_off = o; o = up(o + 16 * L.ccap);
     L.part_off = o; o = up(o + 4 * (int64_t)LEGS_TILE_CHUNKS * T);
     L.spart_off = o; o = up(o + 4 * (int64_t)LEGS_TILE_CHUNKS * T);
     L.seg_off = o; o = up(o + (T > 0 ? 2 * 4 * (int64_t)LEGS_SEG_MAX * 256 : 0));
@@ -1500,6 +1532,7 @@ struct SortScratch {
     uint32_t *tcount, *scount, *cranges, *uoff, *desc, *pstart, *clist, *ucnt, *partial, *spartial, *seg_hist,
         *seg_off;
     uint64_t *tsum, *toff, *ssum, *soff, *cut;
+    char *udesc, *cpay;
 };
 
 SortScratch sort_scratch_at(void *base, int64_t capacity, int64_t total_tiles = 0)
@@ -1530,6 +1563,8 @@ SortScratch sort_scratch_at(void *base, int64_t capacity, int64_t total_tiles = 
     S.pstart = u32(L.pstart_off);
     S.clist = u32(L.clist_off);
     S.ucnt = u32(L.ucnt_off);
+    S.udesc = b + L.udesc_off;
+    S.cpay = b + L.cpay_off;
     S.partial = u32(L.part_off);
     S.spartial = u32(L.spart_off);
     S.seg_hist = u32(L.seg_off);
@@ -1762,6 +1797,8 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     E.pstart = S.pstart;
     E.nblocks = nblocks;
     E.G = OL.G;
+    E.frecs = frecs;
+    E.pay = reinterpret_cast<FRec *>(S.cpay);
     const int nseg = (int)(ctx->num_cus * 2 < LEGS_SEG_MAX ? ctx->num_cus * 2 : LEGS_SEG_MAX);
     for (int p = 0; p < cpasses; ++p) {
         const int wo = p % 2, ri = 1 - wo;
@@ -1788,13 +1825,16 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     //    LEGS_COMPACT_UNIT list entries per wave
     const int64_t max_units = S.ccap / LEGS_COMPACT_UNIT + T;
     const int gu = grid_for(ctx, max_units, 256 / LEGS_WAVE, 8);
+    UnitCtx *udesc = reinterpret_cast<UnitCtx *>(S.udesc);
     hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, s, S.cranges, T, S.uoff);
-    hipLaunchKernelGGL(k_compact_count, dim3(gu), dim3(256), 0, s, cv[0], cv[1], S.desc, S.cranges, S.uoff, T,
-                       sviews, views, n_views, frecs, OL.G, S.cut, S.ucnt);
+    hipLaunchKernelGGL(k_unit_desc, dim3(grid_for(ctx, max_units, 256, 4)), dim3(256), 0, s, S.uoff, T, S.cranges,
+                       sviews, views, n_views, udesc);
+    hipLaunchKernelGGL(k_compact_count, dim3(gu), dim3(256), 0, s, cv[0], cv[1], S.desc, S.uoff, T, udesc, E.pay,
+                       OL.G, S.cut, S.ucnt);
     hipLaunchKernelGGL(k_compact_scan, dim3(grid_for(ctx, T, 256 / LEGS_WAVE, 4)), dim3(256), 0, s, S.uoff, T,
                        sviews, views, n_views, bins->ranges, S.ucnt);
-    hipLaunchKernelGGL(k_compact_write, dim3(gu), dim3(256), 0, s, cv[0], cv[1], S.desc, S.cranges, S.uoff, T,
-                       sviews, views, n_views, frecs, OL.G, S.cut, S.ucnt, bins->capacity, bins->keys, bins->ids);
+    hipLaunchKernelGGL(k_compact_write, dim3(gu), dim3(256), 0, s, cv[0], cv[1], S.desc, S.uoff, T, udesc, E.pay,
+                       OL.G, S.cut, S.ucnt, bins->capacity, bins->keys, bins->ids);
     LEGS_CHECK_LAUNCH(ctx);
     return LEGS_OK;
 }
