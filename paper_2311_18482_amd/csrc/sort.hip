@@ -268,35 +268,13 @@ struct FRec {
     uint32_t wh;     // rectangle width | height << 16 (0: culled)
 };
 
-// Inputs of the fused emission (the first coarse pass): the super-tile
-// records of the depth-ordered G-views, the instance offset of every 256 of
-// them and the first block of each partition.
-struct TileEmit {
-    const GRec *recs;
-    const uint64_t *goff;      // [nblocks + 1]
-    const uint32_t *pstart;    // [partitions]
-    int64_t nblocks, G;
-    const FRec *frecs;         // with pay: the last coarse pass also writes
-    FRec *pay;                 // pay[i] = frecs[position of list entry i]
+// The tile records the last coarse pass carries out with the sorted list:
+// pay[i] = frecs[position of list entry i] (positions >= G give zeros).
+struct CoarsePay {
+    const FRec *frecs;
+    FRec *pay;
+    int64_t G;
 };
-
-// Inclusive maximum over lanes 0..l of a wave (DPP row shifts, then the row
-// broadcasts of lanes 15 and 31).
-__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x)
-{
-    uint32_t t;
-#define LEGS_DPP_MAX(ctrl, rmask)                                                               \
-    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, ctrl, rmask, 0xF, false);             \
-    x = t > x ? t : x;
-    LEGS_DPP_MAX(0x111, 0xF)   // row_shr:1
-    LEGS_DPP_MAX(0x112, 0xF)   // row_shr:2
-    LEGS_DPP_MAX(0x114, 0xF)   // row_shr:4
-    LEGS_DPP_MAX(0x118, 0xF)   // row_shr:8
-    LEGS_DPP_MAX(0x142, 0xA)   // row_bcast:15 into rows 1 and 3
-    LEGS_DPP_MAX(0x143, 0xC)   // row_bcast:31 into rows 2 and 3
-#undef LEGS_DPP_MAX
-    return x;
-}
 
 // Exclusive scan over a block of T threads of one 64-bit value per thread
 // (threads >= 256 pass 0); s_start[0..256] receives the scan of the first
@@ -322,98 +300,6 @@ __device__ __forceinline__ void block_scan_256(uint64_t x, uint64_t *s_start, ui
     __syncthreads();
 }
 
-// LDS of the fused emission.
-struct EmitLds {
-    uint32_t rbase[256], rwtx[256], rg[256];
-    uint16_t own[LEGS_SORT_PART];
-    uint32_t omax[LEGS_SORT_THREADS / LEGS_WAVE];
-    uint64_t gscan[257];
-    uint64_t w64[LEGS_SORT_THREADS / LEGS_WAVE];
-};
-
-// Generates instances [base, base + nvalid) of the depth-ordered stream into
-// LDS slots 0 .. nvalid - 1 (super-tile key, position): instance e is
-// super-tile e - start of its G-view's rectangle, row-major. Each G-view marks
-// the first slot it fills and a running maximum over the slots gives every
-// slot its owner. Called by the whole workgroup.
-template <typename K>
-__device__ __forceinline__ void emit_partition(const TileEmit &E, int64_t part, int64_t base, int nvalid,
-                                               K *s_keys, uint32_t *s_vals, EmitLds &M)
-{
-    constexpr int T = LEGS_SORT_THREADS;
-    constexpr int NW = T / LEGS_WAVE;
-    constexpr int SPW = LEGS_SORT_PART / NW;   // partition slots per wave
-    const int tid = threadIdx.x, lane = legs_lane(), wave = tid / LEGS_WAVE;
-    for (int64_t b = E.pstart[part]; b < E.nblocks; ++b) {
-        const uint64_t ob = E.goff[b];
-        if (ob >= (uint64_t)(base + nvalid)) break;
-        const int64_t pos = b * 256 + tid;
-        uint32_t c = 0;
-        if (tid < 256 && pos < E.G) {
-            const GRec r = E.recs[pos];
-            c = r.cnt;
-            M.rbase[tid] = r.base;
-            M.rwtx[tid] = r.rwtx;
-            M.rg[tid] = r.gid;
-        }
-        block_scan_256<T>(c, M.gscan, M.w64);
-        const uint64_t tot = M.gscan[256];
-        const uint64_t lo = (uint64_t)base > ob ? (uint64_t)base - ob : 0;
-        const uint64_t hi = ((uint64_t)(base + nvalid) - ob) < tot ? (uint64_t)(base + nvalid) - ob : tot;
-        const int e_lo = (int)(ob + lo - (uint64_t)base), e_hi = (int)(ob + hi - (uint64_t)base);
-        // clear the slots of this block, mark each G-view's first slot; wave w
-        // owns slots [w SPW, (w + 1) SPW), lane-contiguous in chunks of 64
-#pragma unroll
-        for (int q = 0; q < SPW / LEGS_WAVE; ++q) {
-            const int e = wave * SPW + q * LEGS_WAVE + lane;
-            if (e >= e_lo && e < e_hi) M.own[e] = 0;
-        }
-        __syncthreads();
-        if (tid < 256 && c) {
-            const uint64_t st = M.gscan[tid];
-            const uint64_t first = st > lo ? st : lo;
-            if (first < hi && first < st + c) M.own[(int)(ob + first - (uint64_t)base)] = (uint16_t)(tid + 1);
-        }
-        __syncthreads();
-        // owner of each slot: running maximum of the marks (per-wave maxima
-        // first, then a DPP max-scan per chunk carried across chunks)
-        uint32_t wm = 0;
-#pragma unroll
-        for (int q = 0; q < SPW / LEGS_WAVE; ++q) {
-            const int e = wave * SPW + q * LEGS_WAVE + lane;
-            const uint32_t mk = (e >= e_lo && e < e_hi) ? (uint32_t)M.own[e] : 0u;
-            wm = mk > wm ? mk : wm;
-        }
-        wm = wave_incl_max(wm);
-        if (lane == LEGS_WAVE - 1) M.omax[wave] = wm;
-        __syncthreads();
-        uint32_t carry = 0;
-        for (int w = 0; w < wave; ++w) carry = M.omax[w] > carry ? M.omax[w] : carry;
-#pragma unroll
-        for (int q = 0; q < SPW / LEGS_WAVE; ++q) {
-            const int e = wave * SPW + q * LEGS_WAVE + lane;
-            const bool in = e >= e_lo && e < e_hi;
-            uint32_t own = wave_incl_max(in ? (uint32_t)M.own[e] : 0u);
-            own = own > carry ? own : carry;
-            carry = (uint32_t)__builtin_amdgcn_readlane((int)own, LEGS_WAVE - 1);
-            if (in) {
-                const int o = (int)own - 1;
-                const uint32_t local = (uint32_t)((uint64_t)base + (uint64_t)e - ob - M.gscan[o]);
-                const uint32_t rwtx = M.rwtx[o], rw = rwtx & 0xffffu, tx = rwtx >> 16;
-                // local / rw through a float reciprocal (local < 2^24, rw < 2^16:
-                // the estimate is off by at most a few units, fixed below)
-                uint32_t qq = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)rw));
-                int32_t rr = (int32_t)(local - qq * rw);
-                while (rr < 0) { --qq; rr += (int32_t)rw; }
-                while (rr >= (int32_t)rw) { ++qq; rr -= (int32_t)rw; }
-                s_keys[e] = (K)(M.rbase[o] + qq * tx + (uint32_t)rr);
-                s_vals[e] = M.rg[o];
-            }
-        }
-        __syncthreads();
-    }
-}
-
 // Digit layout of the coarse passes, decided on the device from the number of
 // super-tiles: desc[0] passes, desc[2 + 2p] and desc[3 + 2p] the shift and
 // width of pass p (width 0: the pass is not needed and returns at once).
@@ -421,21 +307,18 @@ constexpr int DESC_WORDS = 2 + 2 * LEGS_SORT_MAX_PASSES;
 
 // One onesweep pass over the digit of `rb` bits at `shift` of keys K with
 // 32-bit values (with desc, shift and width come from desc[2 + 2 pass ..]).
-// EMIT: the partition's (super-tile, position) pairs are generated from the
-// depth-ordered G-view records instead of read (instance e is super-tile
-// e - start of its G-view's rectangle, row-major): each G-view marks the
-// first partition slot it fills, and a running maximum over the slots gives
-// every slot its owner. SEG: workgroups walk fixed segments of partitions in
-// order from the segment digit starts instead of a decoupled look-back.
-template <typename K, bool EMIT, bool SEG>
+// SEG: workgroups walk fixed segments of partitions in order from the segment
+// digit starts instead of a decoupled look-back. With P.pay, the last pass
+// (desc) also writes the tile record of each entry's position.
+template <typename K, bool SEG>
 __global__ void __launch_bounds__(LEGS_SORT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__restrict__ kout,
            uint32_t *__restrict__ vout, const uint64_t *__restrict__ count, int64_t capacity, int pass,
            int shift, int rb, const uint32_t *__restrict__ desc, const uint32_t *__restrict__ digit_starts,
-           uint64_t *__restrict__ status, uint32_t *__restrict__ counter, TileEmit E,
+           uint64_t *__restrict__ status, uint32_t *__restrict__ counter, CoarsePay P,
            const uint32_t *__restrict__ seg_off)
 {
-    const bool payload = E.pay != nullptr && desc != nullptr && pass == (int)desc[0] - 1;
+    const bool payload = P.pay != nullptr && desc != nullptr && pass == (int)desc[0] - 1;
     if (desc) {
         shift = (int)desc[2 + 2 * pass];
         rb = (int)desc[3 + 2 * pass];
@@ -450,8 +333,7 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__res
     __shared__ uint32_t s_vals[PART];
     __shared__ uint32_t s_wh[NW][256];      // per-wave digit counts, then wave offsets
     __shared__ uint32_t s_lstart[256];      // block-local start of each digit
-    __shared__ uint64_t s_gstart[257];      // global position of LDS slot 0 of each digit;
-                                            // with EMIT first the G-view scan of a block
+    __shared__ uint64_t s_gstart[257];      // global position of LDS slot 0 of each digit
     __shared__ uint32_t s_tmp[NW];
     __shared__ uint64_t s_w64[NW];
     __shared__ int64_t s_part;
@@ -485,11 +367,6 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__res
         const int64_t nvalid64 = m - base < PART ? m - base : PART;
         const int nvalid = (int)nvalid64;
 
-        if constexpr (EMIT) {
-            __shared__ EmitLds s_emit;
-            emit_partition<K>(E, part, base, nvalid, s_keys, s_vals, s_emit);
-        }
-
         K key[ITEMS];
         uint32_t val[ITEMS];
         uint32_t rank[ITEMS];
@@ -498,19 +375,13 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__res
         for (int i = 0; i < ITEMS; ++i) {
             const int e = wave * LEGS_WAVE * ITEMS + i * LEGS_WAVE + lane;
             if (e < nvalid) {
-                if constexpr (EMIT) {
-                    key[i] = s_keys[e];
-                    val[i] = s_vals[e];
-                } else {
-                    key[i] = kin[base + e];
-                    val[i] = vin[base + e];
-                }
+                key[i] = kin[base + e];
+                val[i] = vin[base + e];
             } else {
                 key[i] = (K)~(K)0;
                 val[i] = 0;
             }
         }
-        if constexpr (EMIT) __syncthreads();   // the LDS arrays are reused by the scatter below
         // rank within the wave: peers with the same digit via 8 ballots
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
@@ -630,7 +501,7 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__res
                     // the partition's positions span a narrow window: these gathers stay in cache
                     if (payload) {
                         const uint32_t pv = s_vals[k];
-                        E.pay[gpos] = (int64_t)pv < E.G ? E.frecs[pv] : FRec{0u, 0u, 0u, 0u};
+                        P.pay[gpos] = (int64_t)pv < P.G ? P.frecs[pv] : FRec{0u, 0u, 0u, 0u};
                     }
                 }
             }
@@ -700,82 +571,6 @@ k_seg_scan(const uint32_t *__restrict__ seg_hist, int nseg, const uint32_t *__re
     uint32_t pre = digit_starts[pass * 256 + d];
     for (int w = 0; w < wave; ++w) pre += s_w[w];
     if (sg < nseg) seg_off[(int64_t)sg * 256 + d] = pre + incl - x;
-}
-
-// Counts of the low rb bits of the super-tile ids in segment blockIdx.x of the
-// depth-ordered coarse stream (the first coarse pass), from the G-view records
-// without generating the instances: every row of a rectangle covers
-// consecutive ids, i.e. a cyclic range of digits, added to a difference array
-// (full turns of 2^rb to every digit at once).
-__global__ void __launch_bounds__(256)
-k_tile_upsweep_emit(const uint64_t *__restrict__ count, int64_t capacity, TileEmit E,
-                    const uint32_t *__restrict__ desc, uint32_t *__restrict__ seg_hist)
-{
-    const int rb = (int)desc[3];    // the first pass sorts the low bits
-    const uint32_t nd = 1u << rb;
-    constexpr int PART = LEGS_SORT_PART;
-    __shared__ uint32_t s_d[257];
-    __shared__ uint32_t s_all;
-    __shared__ uint64_t s_start[257];
-    __shared__ uint64_t s_w[4];
-    const int tid = threadIdx.x;
-    for (int i = tid; i < 257; i += 256) s_d[i] = 0;
-    if (tid == 0) s_all = 0;
-    const uint64_t cnt = *count;
-    const int64_t m = (int64_t)(cnt < (uint64_t)capacity ? cnt : (uint64_t)capacity);
-    const int64_t parts = (m + PART - 1) / PART;
-    const int64_t per = (parts + gridDim.x - 1) / gridDim.x;
-    const int64_t p0 = (int64_t)blockIdx.x * per;
-    __syncthreads();
-    if (p0 < parts) {
-        const uint64_t s0 = (uint64_t)p0 * PART;
-        const uint64_t s1 = (uint64_t)((p0 + per) * PART < m ? (p0 + per) * PART : m);
-        for (int64_t b = E.pstart[p0]; b < E.nblocks; ++b) {
-            const uint64_t ob = E.goff[b];
-            if (ob >= s1) break;
-            const int64_t pos = b * 256 + tid;
-            const GRec r = pos < E.G ? E.recs[pos] : GRec{0u, 0u, 0u, 0u};
-            block_scan_256<256>(r.cnt, s_start, s_w);
-            const uint64_t st = ob + s_start[tid];
-            const uint64_t u0g = st > s0 ? st : s0, u1g = st + r.cnt < s1 ? st + r.cnt : s1;
-            if (r.cnt && u0g < u1g) {
-                const uint32_t rw = r.rwtx & 0xffffu, tx = r.rwtx >> 16;
-                const uint32_t u0 = (uint32_t)(u0g - st), u1 = (uint32_t)(u1g - st);   // [u0, u1) of the rectangle
-                for (uint32_t row = u0 / rw; row * rw < u1; ++row) {
-                    const uint32_t c0 = row * rw < u0 ? u0 - row * rw : 0u;
-                    const uint32_t c1 = (row + 1) * rw < u1 ? rw : u1 - row * rw;   // columns [c0, c1)
-                    const uint32_t a = (r.base + row * tx + c0) & (nd - 1u), len = c1 - c0;
-                    if (len >> rb) atomicAdd(&s_all, len >> rb);
-                    const uint32_t rem = len & (nd - 1u);
-                    if (rem) {
-                        atomicAdd(&s_d[a], 1u);
-                        if (a + rem <= nd) {
-                            atomicAdd(&s_d[a + rem], 0xffffffffu);
-                        } else {
-                            atomicAdd(&s_d[nd], 0xffffffffu);
-                            atomicAdd(&s_d[0], 1u);
-                            atomicAdd(&s_d[a + rem - nd], 0xffffffffu);
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    __syncthreads();
-    // inclusive prefix of the difference array over the 256 bytes
-    const int lane = legs_lane(), wave = tid / LEGS_WAVE;
-    uint32_t incl = s_d[tid];
-#pragma unroll
-    for (int off = 1; off < LEGS_WAVE; off <<= 1) {
-        const uint32_t y = __shfl_up(incl, off, LEGS_WAVE);
-        if (lane >= off) incl += y;
-    }
-    __shared__ uint32_t s_t[4];
-    if (lane == LEGS_WAVE - 1) s_t[wave] = incl;
-    __syncthreads();
-    for (int w = 0; w < wave; ++w) incl += s_t[w];
-    seg_hist[(int64_t)blockIdx.x * 256 + tid] = (uint32_t)tid < nd ? incl + s_all : 0u;
 }
 
 // ---- depth order of the G-views ---------------------------------------------------
@@ -858,18 +653,40 @@ k_sorted_records(const uint32_t *__restrict__ perm, const uint64_t *__restrict__
     }
 }
 
-// First block of 256 positions of every partition of the instance stream:
-// partition p starts in block b when goff[b] <= p * PART < goff[b + 1].
-__global__ void __launch_bounds__(256)
-k_part_blocks(const uint64_t *__restrict__ goff, int64_t nblocks, int64_t parts_cap,
-              uint32_t *__restrict__ pstart)
+// The coarse stream written out: each G-view's super-tile rectangle,
+// row-major, at its offset in the stream (the first ccap entries kept), key =
+// super-tile id, value = position. The block's entries are spread evenly over
+// its threads (consecutive threads, consecutive entries); each finds its
+// G-view by binary search over the block's scan in LDS.
+__global__ void __launch_bounds__(LEGS_PROJ_BLOCK)
+k_coarse_emit(const GRec *__restrict__ crecs, const uint64_t *__restrict__ coff, int64_t G, int64_t ccap,
+              uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
 {
-    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (b >= nblocks) return;
-    const int64_t plo = (int64_t)((goff[b] + LEGS_SORT_PART - 1) / LEGS_SORT_PART);
-    int64_t phi = (int64_t)((goff[b + 1] + LEGS_SORT_PART - 1) / LEGS_SORT_PART);
-    if (phi > parts_cap) phi = parts_cap;
-    for (int64_t p = plo; p < phi; ++p) pstart[p] = (uint32_t)b;
+    static_assert(LEGS_PROJ_BLOCK == 256, "offsets per block of 256 positions");
+    __shared__ uint64_t s_start[257];
+    __shared__ uint64_t s_w[4];
+    __shared__ uint32_t s_base[256], s_rwtx[256];
+    const int64_t pos0 = (int64_t)blockIdx.x * 256;
+    const GRec r = pos0 + threadIdx.x < G ? crecs[pos0 + threadIdx.x] : GRec{0u, 0u, 0u, 0u};
+    s_base[threadIdx.x] = r.base;
+    s_rwtx[threadIdx.x] = r.rwtx;
+    block_scan_256<256>(r.cnt, s_start, s_w);
+    const uint64_t o0 = coff[blockIdx.x];
+    const uint64_t tot = s_start[256];
+    const uint64_t lim = (uint64_t)ccap > o0 ? (uint64_t)ccap - o0 : 0u;
+    const uint32_t n = (uint32_t)(tot < lim ? tot : lim);
+    for (uint32_t e = threadIdx.x; e < n; e += 256) {
+        int lo = 0, hi = 255;   // the last G-view starting at or before e (it has entries)
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_start[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t k = e - (uint32_t)s_start[lo];
+        const uint32_t rw = s_rwtx[lo] & 0xffffu, stx = s_rwtx[lo] >> 16;
+        const uint32_t y = k / rw, x = k - y * rw;
+        keys[o0 + e] = s_base[lo] + y * stx + x;
+        vals[o0 + e] = (uint32_t)(pos0 + lo);
+    }
 }
 
 // ---- per-tile counts of the depth-ordered streams ------------------------------
@@ -991,9 +808,10 @@ k_count_corners(const FRec *__restrict__ frecs, const GRec *__restrict__ crecs,
     }
 }
 
-// Sum of the partial grids of the grids counted in LDS (the others already
-// hold their counts). T may exceed a grid's cells (the super-tile grids):
-// cells past its last view are left alone.
+// Adds the partial grids of the grids counted in LDS to the (cleared) counts:
+// chunk group blockIdx.y sums chunks blockIdx.y, blockIdx.y + gridDim.y, ...
+// of each cell. T may exceed a grid's cells (the super-tile grids): cells
+// past its last view are left alone.
 __global__ void __launch_bounds__(256)
 k_count_merge(int nch, int64_t T, int n_views, CountGrid g0, CountGrid g1)
 {
@@ -1005,9 +823,9 @@ k_count_merge(int nch, int64_t T, int n_views, CountGrid g0, CountGrid g1)
         const int64_t ncell = (int64_t)vw.tiles_x * vw.tiles_y;
         if (ncell > (sup ? SUPER_LDS_CELLS : TILE_LDS_CELLS) || t - vw.tile_offset >= ncell) continue;
         uint32_t acc = 0;
-#pragma unroll 8
-        for (int c = 0; c < nch; ++c) acc += cg.partial[(int64_t)c * T + t];
-        cg.count[t] = acc;
+#pragma unroll 4
+        for (int c = blockIdx.y; c < nch; c += gridDim.y) acc += cg.partial[(int64_t)c * T + t];
+        if (acc) atomicAdd(cg.count + t, acc);
     }
 }
 
@@ -1500,7 +1318,6 @@ legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles)
     L.cranges_off = o; o = up(o + 8 * T);
     L.uoff_off = o; o = up(o + 4 * (T + 1));
     L.desc_off = o; o = up(o + 256);
-    L.pstart_off = o; o = up(o + 4 * L.cparts);
     L.clist_off = o; o = up(o + 16 * L.ccap);
     L.ucnt_off = o; o = up(o + 4 * 32 * units);
     L.udesc_off = o; o = up(o + 32 * units);
@@ -1529,7 +1346,7 @@ struct SortScratch {
     int64_t parts;
     // depth-first binning
     int64_t tile_blocks, ccap, cparts;
-    uint32_t *tcount, *scount, *cranges, *uoff, *desc, *pstart, *clist, *ucnt, *partial, *spartial, *seg_hist,
+    uint32_t *tcount, *scount, *cranges, *uoff, *desc, *clist, *ucnt, *partial, *spartial, *seg_hist,
         *seg_off;
     uint64_t *tsum, *toff, *ssum, *soff, *cut;
     char *udesc, *cpay;
@@ -1560,7 +1377,6 @@ SortScratch sort_scratch_at(void *base, int64_t capacity, int64_t total_tiles = 
     S.uoff = u32(L.uoff_off);
     S.desc = u32(L.desc_off);
     S.cut = u64(L.desc_off + 128);
-    S.pstart = u32(L.pstart_off);
     S.clist = u32(L.clist_off);
     S.ucnt = u32(L.ucnt_off);
     S.udesc = b + L.udesc_off;
@@ -1593,10 +1409,10 @@ int32_t radix_passes(legs_ctx *ctx, const SortScratch &S, uint64_t *k0, uint32_t
     uint64_t *ka = k0, *kb = k1;
     uint32_t *va = v0, *vb = v1;
     for (int p = first; p < last; ++p) {
-        hipLaunchKernelGGL((k_onesweep<uint64_t, false, false>), dim3(gsort), dim3(LEGS_SORT_THREADS), 0, s,
+        hipLaunchKernelGGL((k_onesweep<uint64_t, false>), dim3(gsort), dim3(LEGS_SORT_THREADS), 0, s,
                            ka, va, kb, vb, count, capacity, p, 8 * p, 8, nullptr, S.starts,
                            S.status + (int64_t)(p - first) * S.parts * 256, S.counters + (p - first),
-                           TileEmit{}, nullptr);
+                           CoarsePay{}, nullptr);
         LEGS_CHECK_LAUNCH(ctx);
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
@@ -1768,8 +1584,8 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     LEGS_CHECK_LAUNCH(ctx);
     hipLaunchKernelGGL(k_count_corners, dim3((unsigned)nch, (unsigned)n_views), dim3(256), 0, s, frecs, crecs,
                        offsets, coffsets, vrange, OL.G, bins->capacity, S.ccap, T, cg0, cg1, S.cut);
-    hipLaunchKernelGGL(k_count_merge, dim3(grid_for(ctx, 2 * T, 256, 8)), dim3(256), 0, s, nch, T, n_views, cg0,
-                       cg1);
+    hipLaunchKernelGGL(k_count_merge, dim3((unsigned)((2 * T + 255) / 256), 8), dim3(256), 0, s, nch, T, n_views,
+                       cg0, cg1);
     hipLaunchKernelGGL(k_count_rows, dim3(64, (unsigned)n_views, 2), dim3(256), 0, s, cg0, cg1);
     hipLaunchKernelGGL(k_count_cols, dim3(64, (unsigned)n_views, 2), dim3(256), 0, s, cg0, cg1);
     hipLaunchKernelGGL(k_count_block_sums, dim3((unsigned)S.tile_blocks, 2), dim3(1024), 0, s, T, cg0, cg1);
@@ -1782,42 +1598,30 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     // the actual count does not need return at once
     const int cpasses = (bits_for(T) + 7) / 8 > 0 ? (bits_for(T) + 7) / 8 : 1;
     hipLaunchKernelGGL(k_digit_starts, dim3(cpasses), dim3(256), 0, s, S.hist, S.starts, 0);
-    if (nblocks > 0)
-        hipLaunchKernelGGL(k_part_blocks, dim3((unsigned)((nblocks + 255) / 256)), dim3(256), 0, s,
-                           coffsets, nblocks, S.cparts, S.pstart);
     LEGS_CHECK_LAUNCH(ctx);
 
-    // 4. coarse passes: stable counting sort of (super-tile, position) pairs,
-    //    the first generating them from the records; pass p writes buffer p % 2
+    // 4. coarse passes: the (super-tile, position) pairs written out in stream
+    //    order, then stable counting passes over the super-tile digits; pass p
+    //    reads buffer 1 - p % 2 and writes buffer p % 2, and the last one also
+    //    writes the tile record of each entry
     uint32_t *ck[2] = {S.clist, S.clist + S.ccap};
     uint32_t *cv[2] = {S.clist + 2 * S.ccap, S.clist + 3 * S.ccap};
-    TileEmit E;
-    E.recs = crecs;
-    E.goff = coffsets;
-    E.pstart = S.pstart;
-    E.nblocks = nblocks;
-    E.G = OL.G;
-    E.frecs = frecs;
-    E.pay = reinterpret_cast<FRec *>(S.cpay);
-    const int nseg = (int)(ctx->num_cus * 2 < LEGS_SEG_MAX ? ctx->num_cus * 2 : LEGS_SEG_MAX);
+    if (nblocks > 0)
+        hipLaunchKernelGGL(k_coarse_emit, dim3((unsigned)nblocks), dim3(LEGS_PROJ_BLOCK), 0, s, crecs, coffsets,
+                           OL.G, S.ccap, ck[1], cv[1]);
+    const CoarsePay P{frecs, reinterpret_cast<FRec *>(S.cpay), OL.G};
+    // one partition per segment up to LEGS_SEG_MAX segments (segments past the
+    // last partition return at once)
+    const int nseg = LEGS_SEG_MAX;
     for (int p = 0; p < cpasses; ++p) {
         const int wo = p % 2, ri = 1 - wo;
-        if (p == 0)
-            hipLaunchKernelGGL(k_tile_upsweep_emit, dim3(nseg), dim3(256), 0, s, ccount, S.ccap, E, S.desc,
-                               S.seg_hist);
-        else
-            hipLaunchKernelGGL(k_tile_upsweep, dim3(nseg), dim3(LEGS_SORT_THREADS), 0, s, ck[ri], ccount,
-                               S.ccap, S.desc, p, S.seg_hist);
+        hipLaunchKernelGGL(k_tile_upsweep, dim3(nseg), dim3(LEGS_SORT_THREADS), 0, s, ck[ri], ccount, S.ccap,
+                           S.desc, p, S.seg_hist);
         hipLaunchKernelGGL(k_seg_scan, dim3(256), dim3(LEGS_SEG_MAX), 0, s, S.seg_hist, nseg, S.starts, S.desc,
                            p, S.seg_off);
-        if (p == 0)
-            hipLaunchKernelGGL((k_onesweep<uint32_t, true, true>), dim3(nseg), dim3(LEGS_SORT_THREADS), 0, s,
-                               ck[ri], cv[ri], ck[wo], cv[wo], ccount, S.ccap, p, 0, 0, S.desc, S.starts, nullptr,
-                               nullptr, E, S.seg_off);
-        else
-            hipLaunchKernelGGL((k_onesweep<uint32_t, false, true>), dim3(nseg), dim3(LEGS_SORT_THREADS), 0, s,
-                               ck[ri], cv[ri], ck[wo], cv[wo], ccount, S.ccap, p, 0, 0, S.desc, S.starts, nullptr,
-                               nullptr, E, S.seg_off);
+        hipLaunchKernelGGL((k_onesweep<uint32_t, true>), dim3(nseg), dim3(LEGS_SORT_THREADS), 0, s, ck[ri], cv[ri],
+                           ck[wo], cv[wo], ccount, S.ccap, p, 0, 0, S.desc, S.starts, nullptr, nullptr, P,
+                           S.seg_off);
         LEGS_CHECK_LAUNCH(ctx);
     }
 
@@ -1829,11 +1633,11 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, s, S.cranges, T, S.uoff);
     hipLaunchKernelGGL(k_unit_desc, dim3(grid_for(ctx, max_units, 256, 4)), dim3(256), 0, s, S.uoff, T, S.cranges,
                        sviews, views, n_views, udesc);
-    hipLaunchKernelGGL(k_compact_count, dim3(gu), dim3(256), 0, s, cv[0], cv[1], S.desc, S.uoff, T, udesc, E.pay,
+    hipLaunchKernelGGL(k_compact_count, dim3(gu), dim3(256), 0, s, cv[0], cv[1], S.desc, S.uoff, T, udesc, P.pay,
                        OL.G, S.cut, S.ucnt);
     hipLaunchKernelGGL(k_compact_scan, dim3(grid_for(ctx, T, 256 / LEGS_WAVE, 4)), dim3(256), 0, s, S.uoff, T,
                        sviews, views, n_views, bins->ranges, S.ucnt);
-    hipLaunchKernelGGL(k_compact_write, dim3(gu), dim3(256), 0, s, cv[0], cv[1], S.desc, S.uoff, T, udesc, E.pay,
+    hipLaunchKernelGGL(k_compact_write, dim3(gu), dim3(256), 0, s, cv[0], cv[1], S.desc, S.uoff, T, udesc, P.pay,
                        OL.G, S.cut, S.ucnt, bins->capacity, bins->keys, bins->ids);
     LEGS_CHECK_LAUNCH(ctx);
     return LEGS_OK;
