@@ -1,21 +1,29 @@
-// Tile binning for the rasteriser (gfx950): instance scan, key emission, a
-// stable LSD onesweep radix sort of 64-bit (tile << 32 | depth bits) keys with
-// 32-bit Gaussian ids, and per-tile [start, end) ranges.
+// Tile binning for the rasteriser (gfx950): per-tile lists of (tile << 32 |
+// depth bits) keys and Gaussian ids, each list in depth order (ties by
+// Gaussian), and per-tile [start, end) ranges.
 //
-// Every kernel after the scan reads the instance count from device memory and
-// walks it with a fixed grid, so the whole chain can be captured in a HIP
-// graph without knowing the count on the host.
+// Depth-first path (default): the G-views are sorted once by (view, depth
+// bits) with a stable LSD onesweep radix sort; each G-view's rectangle of
+// 8 x 4-tile super-tiles is written out in that order and sorted stably by
+// super-tile id (reduce-then-scan counting passes); a compaction then splits
+// each super-tile's list into its 32 tile lists, writing every instance once,
+// at its final place. Per-cell counts of both streams come from 2D difference
+// grids over the rectangles, so ranges and offsets are known without reading
+// any instance. Full-sort path (LEGS_FLAG_FULL_SORT): every instance is
+// emitted in Gaussian order and all key digits are sorted over the instances.
 //
-// Onesweep (one pass per 8-bit digit): digit histograms for every pass come
-// from one upfront read of the keys; each pass then ranks a 4096-key
+// Every kernel after the scan reads its sizes from device memory and walks
+// them with a fixed grid, so the whole chain can be captured in a HIP graph
+// without knowing the counts on the host.
+//
+// Onesweep (one pass per digit of up to 8 bits): each pass ranks a 4096-key
 // partition per workgroup with wave64 ballots (stable: ties keep input order),
-// publishes per-digit partition counts, and resolves its global offsets by
-// decoupled look-back over earlier partitions. Partition ids are handed out
-// by an atomic counter in launch order, so every partition a workgroup waits
-// on belongs to a workgroup that is already running (forward progress without
-// relying on blockIdx scheduling order). Keys are first scattered into LDS in
-// digit order, then written out so consecutive lanes write consecutive
-// addresses within a digit run.
+// scatters the keys into LDS in digit order, and writes them out so that
+// consecutive lanes write consecutive addresses within a digit run. Global
+// digit offsets come either from a decoupled look-back over earlier
+// partitions (partition ids handed out by an atomic counter in launch order,
+// so every partition waited on belongs to a running workgroup) or, for the
+// segment passes, from per-segment digit counts scanned beforehand.
 #include "legs_internal.h"
 
 namespace {
