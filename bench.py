@@ -198,6 +198,9 @@ def main():
     ap.add_argument("--lds-batch", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-decode", action="store_true", help="skip the learned-vs-plain decode leg")
+    ap.add_argument("--eager", action="store_true",
+                    help="report the eagerly launched step instead of the replayed HIP graph of the step")
+    ap.add_argument("--persistent", action="store_true", help="persistent blend kernels (tiles from a counter)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain 1 GiB elementwise copy (torch.neg), "
                          "the reference dispatch that scales FETCH_SIZE / WRITE_SIZE to bytes")
@@ -212,7 +215,7 @@ def main():
 
     scene, cams, desc = workload(args.workload)
     log(f"workload {desc}")
-    o = R.opts(tile=args.tile, lds_batch=args.lds_batch)
+    o = R.opts(tile=args.tile, lds_batch=args.lds_batch, persistent=args.persistent)
     rast = R.Rasterizer(cams, o)
     dev = rast.ctx.device
     d = {k: torch.from_numpy(getattr(scene, k)).to(dev)
@@ -273,11 +276,42 @@ def main():
     per_step = np.array([evs[k][0].elapsed_time(evs[k][6]) for k in range(args.steps)])
     stage_ms = {s: float(np.median([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)]))
                 for i, s in enumerate(stages)}
-    ms = float(np.median(per_step))
+    eager_ms = float(np.median(per_step))
+    log(f"eager step {eager_ms:.3f} ms; stages (median ms): {json.dumps(stage_ms)}; wall {wall:.3f}s for "
+        f"{args.steps} steps; instances {n_inst}")
+
+    # The same step captured once as a HIP graph (every call is capturable: the
+    # binning reads its sizes on the device) and replayed: the timed steps below
+    # are graph launches, each doing the whole step's work; the per-stage times
+    # above come from the eager steps (events cannot sit inside a capture).
+    graph_ms = None
+    if not args.eager:
+        graph = R.Graph(rast.ctx)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with graph.capture():
+                step()
+        torch.cuda.current_stream().wait_stream(side)
+        for _ in range(args.warmup):
+            graph.launch()
+        torch.cuda.synchronize()
+        gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for e0, e1 in gev:
+            e0.record()
+            graph.launch()
+            e1.record()
+        torch.cuda.synchronize()
+        gwall = time.perf_counter() - t0
+        graph_ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in gev]))
+        assert int(bins.count.item()) <= bins.capacity, "instance list overflowed"
+        log(f"graph step {graph_ms:.3f} ms; wall {gwall:.3f}s for {args.steps} replays")
+    ms = eager_ms if graph_ms is None else graph_ms
     px = views.total_pixels
     value = px / (ms * 1e-3) / 1e6
-    log(f"stages (median ms): {json.dumps(stage_ms)}; wall {wall:.3f}s for {args.steps} steps; "
-        f"instances {n_inst}")
 
     # Algorithmic work per stage (section "Roofline" of the design notes):
     #  - bin_sort: bytes of emission, the onesweep passes and the ranges per instance;
@@ -352,7 +386,9 @@ def main():
                config=dict(workload=desc, n_gaussians=int(n), views=len(cams), pixels=int(px),
                            channels=int(C), tile=args.tile, lds_batch=args.lds_batch,
                            instances=int(n_inst), super_tile_entries=int(n_coarse), alpha_evaluations=int(ev),
-                           blended_entries=int(blended), stage_ms=stage_ms),
+                           blended_entries=int(blended), stage_ms=stage_ms,
+                           launch="eager" if graph_ms is None else "hip graph replay of the whole step",
+                           eager_ms_per_step=eager_ms, persistent_blend=bool(args.persistent)),
                roofline=roofline, decode=dec, cpu_baseline=cpu)
     print(json.dumps(rec), flush=True)
 
