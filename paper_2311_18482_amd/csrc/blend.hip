@@ -250,10 +250,9 @@ k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
         for (int c = 0; c < CP; ++c) acc[c] = 0.0f;
         float T = 1.0f;
         uint32_t lastpos = 0;
-        bool done = !inside;
-        uint64_t donemask = legs_ballot(done);
+        uint64_t donemask = legs_ballot(!inside);   // pixels that stopped (or lie off the image)
         for (uint32_t lo = ti.rs; lo < ti.re; lo += (uint32_t)B) {
-            if (__syncthreads_count(!done) == 0) break;
+            if (__syncthreads_count(l == 0 && ~donemask != 0) == 0) break;
             const int nb = (int)min((uint32_t)B, ti.re - lo);
             stage_batch<TILE, CP, NT>(P, ti.v, ti.tile_x0, ti.tile_y0, lo, nb, S);
             // 64 entries at a time: lane l computes the mask of this wave's 8 x 8
@@ -280,29 +279,28 @@ k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
                     const uint64_t act = (((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mhi, jl) << 32) |
                                           (uint32_t)__builtin_amdgcn_readlane((int)mlo, jl)) & ~donemask;
                     if (act == 0) continue;
-                    if ((act >> l) & 1ull) {
-                        const int j = c0 + jl;
-                        const float4 cn = S.c[j];
-                        const float dx = S.qx[j * NQ + qxi] - fx, dy = S.qy[j * NQ + qyi] - fy;
-                        float a, b, ep;
-                        bool clamped;
-                        falloff_dx(dx, cn.x, cn.y, a, b);
-                        const float alpha = falloff_alpha(a, b, dy, cn.z, cn.w, amax, ep, clamped);
-                        if (!(alpha < P.amin)) {
-                            const float Tn = T * (1.0f - alpha);
-                            if (Tn < P.tmin) {
-                                done = true;
-                            } else {
-                                const float wgt = alpha * T;
-                                const float *cj = S.ch + j * CP;
+                    // every lane evaluates (masked lanes would cost the same); only
+                    // the pixels of act may blend or stop
+                    const bool mine = (act >> l) & 1ull;
+                    const int j = c0 + jl;
+                    const float4 cn = S.c[j];
+                    const float dx = S.qx[j * NQ + qxi] - fx, dy = S.qy[j * NQ + qyi] - fy;
+                    float a, b, ep;
+                    bool clamped;
+                    falloff_dx(dx, cn.x, cn.y, a, b);
+                    const float alpha = falloff_alpha(a, b, dy, cn.z, cn.w, amax, ep, clamped);
+                    const float Tn = T * (1.0f - alpha);
+                    // lane masks straight from the compares (predicates 11 = unordered
+                    // or >=, i.e. !(alpha < amin); 4 = ordered <)
+                    donemask |= act & __builtin_amdgcn_fcmpf(alpha, P.amin, 11) & __builtin_amdgcn_fcmpf(Tn, P.tmin, 4);
+                    if (mine && !(alpha < P.amin) && !(Tn < P.tmin)) {
+                        const float wgt = alpha * T;
+                        const float *cj = S.ch + j * CP;
 #pragma unroll
-                                for (int c = 0; c < CP; ++c) acc[c] = fmaf(wgt, cj[c], acc[c]);
-                                T = Tn;
-                                lastpos = (lo - ti.rs) + (uint32_t)j + 1u;
-                            }
-                        }
+                        for (int c = 0; c < CP; ++c) acc[c] = fmaf(wgt, cj[c], acc[c]);
+                        T = Tn;
+                        lastpos = (lo - ti.rs) + (uint32_t)j + 1u;
                     }
-                    donemask = legs_ballot(done);
                     if (!~donemask) break;
                 }
             }
