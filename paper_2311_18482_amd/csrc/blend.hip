@@ -91,6 +91,16 @@ __device__ __forceinline__ float opaque_zero()
     return z;
 }
 
+// Two opaque zeros from one 64-bit move.
+__device__ __forceinline__ void opaque_zero2(float &a, float &b)
+{
+    double z;
+    asm volatile("v_mov_b64 %0, 0" : "=v"(z));
+    const uint64_t u = __builtin_bit_cast(uint64_t, z);
+    a = __builtin_bit_cast(float, (uint32_t)u);
+    b = __builtin_bit_cast(float, (uint32_t)(u >> 32));
+}
+
 __device__ __forceinline__ int sext8(uint32_t v, int sh) { return (int)(int8_t)((v >> sh) & 0xffu); }
 
 // LDS layout of one staged batch of B entries.
@@ -432,10 +442,13 @@ k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restr
                 for (int c = 0; c < CP; ++c) cv[c] = S.ch[j * CP + c];
                 // zeros the compiler cannot fold into the first band's arithmetic (a
                 // folded first band gives the skipped-band paths register copies)
-                float s0 = opaque_zero(), sy = opaque_zero(), syy = opaque_zero(), sop = opaque_zero();
+                float s0, sy, syy, sop;
+                opaque_zero2(s0, sy);
+                opaque_zero2(syy, sop);
                 float acc[NV];
 #pragma unroll
-                for (int c = 0; c < CP; ++c) acc[6 + c] = opaque_zero();
+                for (int c = 0; c + 1 < CP; c += 2) opaque_zero2(acc[6 + c], acc[7 + c]);
+                if constexpr (CP & 1) acc[6 + CP - 1] = opaque_zero();
                 bool any = false;
 #pragma unroll
                 for (int p = 0; p < PPL; ++p) {
@@ -488,7 +501,7 @@ k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restr
                 acc[4] = -0.5f * syy;
                 acc[5] = sop;
                 legs_tr::reduce<NV>(acc, l);
-                const uint32_t gid = S.id[j];
+                const uint32_t gid = (uint32_t)__builtin_amdgcn_readfirstlane((int)S.id[j]);   // scalar addressing
                 float *g2d = grad2d + 8 * ((int64_t)ti.v * P.n + gid);
                 float *dc = d_ch + (int64_t)gid * P.C;
 #pragma unroll
