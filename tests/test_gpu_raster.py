@@ -344,15 +344,31 @@ def test_autotune_returns_a_valid_setting(R):
     assert times[(best.tile, best.lds_batch)] == min(times.values())
 
 
-def test_depth_first_and_full_sort_lists_identical(R):
+def _super_tiles(cams, tile):
+    n = 0
+    for c in cams:
+        tx, ty = (c.width + tile - 1) // tile, (c.height + tile - 1) // tile
+        n += ((tx + 7) // 8) * ((ty + 3) // 4)
+    return n
+
+
+@pytest.mark.parametrize("rig", ["small", "wide"])
+def test_depth_first_and_full_sort_lists_identical(R, rig):
     """Sorting the depth digits per G-view before expansion gives the same
-    instance lists as sorting all eight key digits over the instances."""
+    instance lists as sorting all eight key digits over the instances. The
+    small rig has at most 256 super-tiles (one coarse pass), the wide one
+    more (two coarse passes)."""
     scene = synth.make_scene(80_000, 21, synth.VOL_CUBE, d_sem=8)
-    cams = synth.cameras_sphere(3, 121, 8.0, ((320, 240), (640, 360), (200, 150)))
+    if rig == "small":
+        cams = synth.cameras_sphere(3, 121, 8.0, ((320, 240), (640, 360), (200, 150)))
+        assert _super_tiles(cams, 8) <= 256 and _super_tiles(cams, 16) <= 256
+    else:
+        cams = synth.cameras_sphere(4, 121, 8.0, ((320, 240), (640, 360), (200, 150), (1280, 720)))
+        assert _super_tiles(cams, 8) > 256 and _super_tiles(cams, 16) > 256
     lists = []
     for full in (False, True):
         for tile in (8, 16):
-            note(f"full_sort={full} tile={tile}")
+            note(f"rig={rig} full_sort={full} tile={tile}")
             o = R.opts(tile=tile, full_sort=full)
             rast, d, proj, bins, out, T, last = run_forward(R, scene, cams, o)
             n_inst = int(bins.count.item())
