@@ -413,15 +413,6 @@ k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restr
         if (myL) atomicMax(&s_maxlast, myL);
         __syncthreads();
         const uint32_t maxL = min(s_maxlast, ti.re - ti.rs);
-        // deepest list position any pixel of each band still blends (wave-uniform)
-        uint32_t bandL[PPL];
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-            uint32_t x = L[p];
-#pragma unroll
-            for (int off = 1; off < LEGS_WAVE; off <<= 1) x = max(x, (uint32_t)__shfl_xor((int)x, off, LEGS_WAVE));
-            bandL[p] = (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
-        }
 
         for (uint32_t hi = maxL; hi > 0;) {
             const uint32_t lo_rel = hi > (uint32_t)B ? hi - (uint32_t)B : 0u;
@@ -452,11 +443,9 @@ k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restr
                 bool any = false;
 #pragma unroll
                 for (int p = 0; p < PPL; ++p) {
-                    // rows of band p: by0 + ROWSTEP p + [0, ROWSTEP); pixels of the band
-                    // stop before position bandL[p]
-                    if (pos >= bandL[p] || y1 < by0 + Shp::ROWSTEP * p ||
-                        y0 > by0 + Shp::ROWSTEP * p + Shp::ROWSTEP - 1)
-                        continue;
+                    // every band is evaluated (no uniform skips: the branches cost more
+                    // than the evaluations they save); the lanes outside the box or past
+                    // their pixel's last blended entry do not blend
                     const int ly = ly0 + Shp::ROWSTEP * p;
                     const bool inside = col_in && pos < L[p] && ly >= y0 && ly <= y1;
                     const float dy = S.qy[j * NQ + (ly >> 3)] - (float)(ly & 7);
