@@ -291,7 +291,7 @@ k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
                     if (act == 0) continue;
                     // every lane evaluates (masked lanes would cost the same); only
                     // the pixels of act may blend or stop
-                    const bool mine = (act >> l) & 1ull;
+                    const bool mine = __builtin_amdgcn_inverse_ballot_w64(act);   // lane l: bit l of act
                     const int j = c0 + jl;
                     const float4 cn = S.c[j];
                     const float dx = S.qx[j * NQ + qxi] - fx, dy = S.qy[j * NQ + qyi] - fy;
