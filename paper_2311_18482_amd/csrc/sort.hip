@@ -607,27 +607,28 @@ static_assert(SUPER_TILES == 32, "one mask bit per tile of a super-tile");
 // block of LEGS_PROJ_BLOCK positions.
 __global__ void __launch_bounds__(LEGS_PROJ_BLOCK)
 k_sorted_records(const uint32_t *__restrict__ perm, const uint64_t *__restrict__ okeys,
-                 const int4 *__restrict__ box, const float *__restrict__ depth,
-                 const uint32_t *__restrict__ ntiles, int64_t n, int64_t G,
-                 const legs_view *__restrict__ views, const legs_view *__restrict__ sviews, int tile,
+                 const int4 *__restrict__ box, int64_t n, int64_t G, const legs_view *__restrict__ sviews, int tile,
                  FRec *__restrict__ frecs, GRec *__restrict__ crecs, uint64_t *__restrict__ vrange,
                  uint64_t *__restrict__ block_counts, uint64_t *__restrict__ cblock_counts)
 {
     const int64_t pos = (int64_t)blockIdx.x * LEGS_PROJ_BLOCK + threadIdx.x;
     uint64_t c = 0, cc = 0;
     if (pos < G) {
-        const int64_t gv = perm[pos];
-        c = ntiles[gv];
+        // culled G-views (no tiles) carry the all-ones key and sort last; the key of a
+        // visible one holds its depth bits, and its tile count follows from its box,
+        // so the box is the only gather
+        const uint64_t key = okeys[pos];
         FRec f = {0u, 0u, 0u, 0u};
         GRec r = {(uint32_t)pos, 0u, 0u, 0u};
-        if (c) {
+        if (key != ~0ull) {
+            const int64_t gv = perm[pos];
             const int64_t v = gv / n;
             const int4 bx = box[gv];
-            const legs_view &vw = views[v];
             const legs_view &sw = sviews[v];
             const int tx0 = bx.x / tile, tx1 = bx.y / tile, ty0 = bx.z / tile, ty1 = bx.w / tile;
+            c = (uint64_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
             f.gid = (uint32_t)(gv - v * n);
-            f.dbits = __float_as_uint(depth[gv]);
+            f.dbits = (uint32_t)key;
             f.xy = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
             f.wh = (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)(ty1 - ty0 + 1) << 16);
             const int sx0 = tx0 / SX, sx1 = tx1 / SX, sy0 = ty0 / SY, sy1 = ty1 / SY;
@@ -636,7 +637,7 @@ k_sorted_records(const uint32_t *__restrict__ perm, const uint64_t *__restrict__
             r.rwtx = (uint32_t)(sx1 - sx0 + 1) | ((uint32_t)sw.tiles_x << 16);
             cc = r.cnt;
             // first and last position of each view (visible G-views sort by view)
-            const uint64_t kv = okeys[pos] >> 32;
+            const uint64_t kv = key >> 32;
             if (pos == 0 || (okeys[pos - 1] >> 32) != kv) vrange[2 * kv] = (uint64_t)pos;
             if (pos == G - 1 || (okeys[pos + 1] >> 32) != kv) vrange[2 * kv + 1] = (uint64_t)pos + 1;
         }
@@ -1521,8 +1522,8 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
         if (nblocks > 0)
             hipLaunchKernelGGL(k_sorted_records, dim3((unsigned)nblocks), dim3(LEGS_PROJ_BLOCK), 0, s,
                                perm, (gpass % 2 == 0) ? ok0 : ok1,
-                               reinterpret_cast<const int4 *>(proj->box), proj->depth, proj->ntiles,
-                               n, OL.G, views, sviews, o->tile, reinterpret_cast<FRec *>(ord + OL.frecs),
+                               reinterpret_cast<const int4 *>(proj->box), n, OL.G, sviews, o->tile,
+                               reinterpret_cast<FRec *>(ord + OL.frecs),
                                reinterpret_cast<GRec *>(ord + OL.crecs), vrange, bcounts, cbcounts);
         hipLaunchKernelGGL(k_scan_pair, dim3(2), dim3(1024), 0, s, ScanArgs{bcounts, offsets, nblocks, bins->count},
                            ScanArgs{cbcounts, coffsets, nblocks, ccount});
