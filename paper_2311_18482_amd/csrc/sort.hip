@@ -757,8 +757,11 @@ __global__ void __launch_bounds__(256)
 k_count_corners(const FRec *__restrict__ frecs, const GRec *__restrict__ crecs,
                 const uint64_t *__restrict__ goff, const uint64_t *__restrict__ coff,
                 const uint64_t *__restrict__ vrange, int64_t G, int64_t capacity, int64_t ccap, int64_t T,
+                const uint64_t *__restrict__ count, const uint64_t *__restrict__ ccount,
                 CountGrid g0, CountGrid g1, uint64_t *__restrict__ cut)
 {
+    // offsets inside the streams only matter when a stream overflows its capacity
+    const bool scan = *count > (uint64_t)capacity || *ccount > (uint64_t)ccap;
     __shared__ uint32_t s_grid[TILE_LDS_CELLS];
     __shared__ uint32_t s_sgrid[SUPER_LDS_CELLS];
     __shared__ uint64_t s_start[257], s_cstart[257];
@@ -783,11 +786,13 @@ k_count_corners(const FRec *__restrict__ frecs, const GRec *__restrict__ crecs,
             const FRec f = pos < G ? frecs[pos] : FRec{0u, 0u, 0u, 0u};
             const GRec r = pos < G ? crecs[pos] : GRec{0u, 0u, 0u, 0u};
             const uint32_t fw = f.wh & 0xffffu, fh = f.wh >> 16;
-            block_scan_256<256>((uint64_t)fw * fh, s_start, s_w);
-            block_scan_256<256>(r.cnt, s_cstart, s_w);
+            if (scan) {
+                block_scan_256<256>((uint64_t)fw * fh, s_start, s_w);
+                block_scan_256<256>(r.cnt, s_cstart, s_w);
+            }
             if (pos >= p0 && pos < p1 && fw) {
                 const uint32_t cnt = fw * fh;
-                const uint64_t off = goff[b] + s_start[threadIdx.x];
+                const uint64_t off = scan ? goff[b] + s_start[threadIdx.x] : 0u;
                 if (off <= (uint64_t)capacity && off + cnt > (uint64_t)capacity) {
                     cut[0] = (uint64_t)pos;
                     cut[1] = (uint64_t)capacity - off;
@@ -795,7 +800,7 @@ k_count_corners(const FRec *__restrict__ frecs, const GRec *__restrict__ crecs,
                 if (off < (uint64_t)capacity)
                     diff_rect_kept(g, W, H, (int)(f.xy & 0xffffu), (int)(f.xy >> 16), (int)fw, (int)fh,
                                    (uint64_t)capacity - off);
-                const uint64_t co = coff[b] + s_cstart[threadIdx.x];
+                const uint64_t co = scan ? coff[b] + s_cstart[threadIdx.x] : 0u;
                 if (co < (uint64_t)ccap) {
                     const int local = (int)((int64_t)r.base - sw.tile_offset);
                     const int cw = (int)(r.rwtx & 0xffffu);
@@ -803,7 +808,7 @@ k_count_corners(const FRec *__restrict__ frecs, const GRec *__restrict__ crecs,
                                    (uint64_t)ccap - co);
                 }
             }
-            __syncthreads();
+            if (scan) __syncthreads();   // s_start is rewritten by the next block's scan
         }
     }
     __syncthreads();
@@ -1592,7 +1597,8 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
                        (int64_t)(S.scount - S.tcount) + T, 0u);
     LEGS_CHECK_LAUNCH(ctx);
     hipLaunchKernelGGL(k_count_corners, dim3((unsigned)nch, (unsigned)n_views), dim3(256), 0, s, frecs, crecs,
-                       offsets, coffsets, vrange, OL.G, bins->capacity, S.ccap, T, cg0, cg1, S.cut);
+                       offsets, coffsets, vrange, OL.G, bins->capacity, S.ccap, T, bins->count, ccount, cg0, cg1,
+                       S.cut);
     hipLaunchKernelGGL(k_count_merge, dim3((unsigned)((2 * T + 255) / 256), 8), dim3(256), 0, s, nch, T, n_views,
                        cg0, cg1);
     hipLaunchKernelGGL(k_count_rows, dim3(64, (unsigned)n_views, 2), dim3(256), 0, s, cg0, cg1);
