@@ -172,11 +172,14 @@ k_emit(const int4 *__restrict__ box, const float *__restrict__ depth,
 constexpr int HIST_RUN = 16;  // keys per lane per block iteration
 
 // Digit histograms of passes [first, first + npass) in one read of the keys.
-// Loads are coalesced (lane l reads key base + 64 i + l); within each wave a
-// run of equal digits in consecutive lanes is counted with one LDS atomic by
-// its first lane (run starts from a ballot). Instance keys come in long runs
-// (every tile of one Gaussian shares its depth digits, consecutive tiles of a
-// row share the high tile digits), so hot digits no longer serialise.
+// Loads are coalesced (lane l reads key base + 64 i + l). RUNS: within each
+// wave a run of equal digits in consecutive lanes is counted with one LDS
+// atomic by its first lane (run starts from a ballot); instance keys come in
+// long runs (every tile of one Gaussian shares its depth digits, consecutive
+// tiles of a row share the high tile digits), so hot digits do not serialise.
+// Without RUNS (keys in no particular order, e.g. the G-view depth keys) the
+// keys of a lane are loaded at once and each digit is one LDS atomic.
+template <bool RUNS>
 __global__ void __launch_bounds__(256)
 k_histogram(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ count,
             int64_t capacity, int first, int npass, uint32_t *__restrict__ hist)
@@ -191,6 +194,20 @@ k_histogram(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ coun
     const int64_t chunk = (int64_t)256 * HIST_RUN;
     for (int64_t base = (int64_t)blockIdx.x * chunk; base < m; base += (int64_t)gridDim.x * chunk) {
         const int64_t wbase = base + (int64_t)wave * LEGS_WAVE * HIST_RUN;
+        if constexpr (!RUNS) {
+            uint64_t k[HIST_RUN];
+#pragma unroll
+            for (int i = 0; i < HIST_RUN; ++i) {
+                const int64_t idx = wbase + (int64_t)i * LEGS_WAVE + lane;
+                k[i] = idx < m ? keys[idx] : 0ull;
+            }
+#pragma unroll
+            for (int i = 0; i < HIST_RUN; ++i)
+                if (wbase + (int64_t)i * LEGS_WAVE + lane < m)
+                    for (int p = 0; p < npass; ++p)
+                        atomicAdd(&s_h[p][(uint32_t)(k[i] >> (8 * (first + p))) & 255u], 1u);
+            continue;
+        }
         for (int i = 0; i < HIST_RUN; ++i) {
             const int64_t idx = wbase + (int64_t)i * LEGS_WAVE + lane;
             const bool ok = idx < m;
@@ -1407,7 +1424,7 @@ SortScratch sort_scratch_at(void *base, int64_t capacity, int64_t total_tiles = 
 // (k0, v0) when last - first is even and in (k1, v1) otherwise.
 int32_t radix_passes(legs_ctx *ctx, const SortScratch &S, uint64_t *k0, uint32_t *v0,
                      uint64_t *k1, uint32_t *v1, const uint64_t *count, int64_t capacity,
-                     int first, int last, hipStream_t s)
+                     int first, int last, bool runs, hipStream_t s)
 {
     const int np = last - first;
     if (np <= 0) return LEGS_OK;
@@ -1415,8 +1432,12 @@ int32_t radix_passes(legs_ctx *ctx, const SortScratch &S, uint64_t *k0, uint32_t
     hipLaunchKernelGGL(k_sort_clear, dim3(gclear), dim3(256), 0, s, S.status, S.parts, np,
                        S.counters, S.hist, count, capacity);
     const int ghist = grid_for(ctx, capacity, 256 * HIST_RUN, 4);
-    hipLaunchKernelGGL(k_histogram, dim3(ghist), dim3(256), 0, s, k0, count, capacity, first, np,
-                       S.hist);
+    if (runs)
+        hipLaunchKernelGGL(k_histogram<true>, dim3(ghist), dim3(256), 0, s, k0, count, capacity, first, np,
+                           S.hist);
+    else
+        hipLaunchKernelGGL(k_histogram<false>, dim3(ghist), dim3(256), 0, s, k0, count, capacity, first, np,
+                           S.hist);
     hipLaunchKernelGGL(k_digit_starts, dim3(np), dim3(256), 0, s, S.hist, S.starts, first);
     LEGS_CHECK_LAUNCH(ctx);
     const int gsort = grid_for(ctx, capacity, LEGS_SORT_PART, 2);
@@ -1510,7 +1531,7 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
         const int gpass = (32 + bits_for(n_views) + 7) / 8;
         if (OL.G > 0) {
             const int32_t r = radix_passes(ctx, sort_scratch_at(ord + OL.sort, OL.G), ok0, ov0, ok1, ov1,
-                                           gcount, OL.G, 0, gpass, s);
+                                           gcount, OL.G, 0, gpass, false, s);
             if (r != LEGS_OK) return r;
         }
         perm = (gpass % 2 == 0) ? ov0 : ov1;
@@ -1566,7 +1587,7 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
             LEGS_CHECK_LAUNCH(ctx);
         }
         const int32_t r = radix_passes(ctx, S, k0, v0, k1, v1, bins->count, bins->capacity, 0,
-                                       passes, s);
+                                       passes, true, s);
         if (r != LEGS_OK) return r;
         const int gfill = grid_for(ctx, 2 * total_tiles, 256, 8);
         hipLaunchKernelGGL(k_fill_u32, dim3(gfill), dim3(256), 0, s, bins->ranges, 2 * total_tiles, 0u);
