@@ -73,7 +73,7 @@ def measured_traffic(stage, args):
     return rec["hbm_bytes_per_launch"]
 
 
-def decode_leg(log_fn):
+def decode_leg(log_fn, epochs=200):
     """Learned vs plain decode on the 32-view 1080p workload (Sec. 3.3 Eq. 4 plain
     codebook decode; Eq. 8/9 MLP decoder trained on the GPU by this library):
     render the 8-dim semantic maps of all views, label 10M pixels sampled from
@@ -114,7 +114,7 @@ def decode_leg(log_fn):
     ytr, _ = DEC.decode_plain(ctx, DEC.rowmajor_features(ftr), Pm, Cb)
     yev, _ = DEC.decode_plain(ctx, DEC.rowmajor_features(fev), Pm, Cb)
     ws, bs = synth.mlp_init((8, 64, 64, K), 4 + 403)
-    B, epochs, lr0 = 65536, 200, 1e-2
+    B, lr0 = 65536, 1e-2
     tr = DEC.MlpTrainer(ctx, DEC.mlp_pack(ws, bs), K, B, lr=lr0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -127,7 +127,7 @@ def decode_leg(log_fn):
         for i in range(0, n - B + 1, B):
             tr.step(DEC.rowmajor_features(fs[i:i + B]), ys[i:i + B])
             steps += 1
-        if ep % 50 == 49:
+        if ep % 50 == 49 or ep == epochs - 1:
             log_fn(f"decoder epoch {ep + 1}/{epochs}")
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
@@ -198,6 +198,8 @@ def main():
     ap.add_argument("--lds-batch", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-decode", action="store_true", help="skip the learned-vs-plain decode leg")
+    ap.add_argument("--decode-epochs", type=int, default=200,
+                    help="decoder training epochs of the decode leg (fewer only to profile its kernels)")
     ap.add_argument("--eager", action="store_true",
                     help="report the eagerly launched step instead of the replayed HIP graph of the step")
     ap.add_argument("--persistent", action="store_true", help="persistent blend kernels (tiles from a counter)")
@@ -371,7 +373,7 @@ def main():
         log("decode leg: render 32 views, label, train the decoder, time the decodes")
         del proj, bins, out, T, last, grad2d, d_ch, grads
         torch.cuda.empty_cache()
-        dec = decode_leg(log)
+        dec = decode_leg(log, epochs=args.decode_epochs)
         log(f"decode: {json.dumps(dec)}")
 
     cpu = None
