@@ -151,7 +151,7 @@ k_decode_plain(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps
                 const int k = 32 * b + drow(r, h);
                 const float sc = S[b][r] * s_inv[k] * inz;
                 S[b][r] = sc;
-                if (sc > best || (sc == best && k < bidx)) { best = sc; bidx = k; }
+                if (sc > best) { best = sc; bidx = k; }   // k increases along the loop: first wins ties
             }
         argmax_pair(best, bidx);
         if (valid) {
@@ -242,7 +242,7 @@ k_decode_folded(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t p
                 const int k = 32 * b + drow(r, h);
                 const float sc = S[b][r] * inz;
                 S[b][r] = sc;
-                if (sc > best || (sc == best && k < bidx)) { best = sc; bidx = k; }
+                if (sc > best) { best = sc; bidx = k; }   // k increases along the loop: first wins ties
             }
         argmax_pair(best, bidx);
         if (valid) {
@@ -283,7 +283,7 @@ k_decode_mlp(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
             for (int r = 0; r < 16; ++r) {
                 const int k = 32 * b + drow(r, h);
                 const float sc = S[b][r];
-                if (sc > best || (sc == best && k < bidx)) { best = sc; bidx = k; }
+                if (sc > best) { best = sc; bidx = k; }   // k increases along the loop: first wins ties
             }
         }
         argmax_pair(best, bidx);

@@ -106,8 +106,9 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds &L, const float *_
             ss = fmaf(v[e], v[e], ss);
         }
         const float nrm = sqrtf(ss);
+        const float inv = nrm > 0.0f ? 1.0f / nrm : 0.0f;   // one division, then products
 #pragma unroll
-        for (int e = 0; e < LEGS_MLP_IN; ++e) x[e] = (__bf16)(nrm > 0.0f ? v[e] / nrm : 0.0f);
+        for (int e = 0; e < LEGS_MLP_IN; ++e) x[e] = (__bf16)(v[e] * inv);
     }
     T.x = x;
 #pragma unroll
