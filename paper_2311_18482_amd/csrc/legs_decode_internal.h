@@ -39,6 +39,22 @@ struct MlpTile {
     legs_f32x16 z3[KB];     // logits, class 32 b + 8 (r / 4) + 4 (lane / 32) + r % 4
 };
 
+typedef __attribute__((ext_vector_type(2))) short legs_i16x2;
+
+// ReLU of 8 accumulator values as a bf16 fragment: rounding keeps the sign, so
+// rounding first and then taking the signed 16-bit max with 0 on packed pairs
+// gives the same bits as rounding max(z, 0) (-0 becomes +0 either way).
+__device__ __forceinline__ legs_bf16x8 relu_bf16x8(const legs_f32x16 &z, int first)
+{
+    legs_bf16x8 h;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) h[e] = (__bf16)z[first + e];
+    typedef __attribute__((ext_vector_type(8))) short i16x8;
+    i16x8 q = __builtin_bit_cast(i16x8, h);
+    q = __builtin_elementwise_max(q, (i16x8){0, 0, 0, 0, 0, 0, 0, 0});
+    return __builtin_bit_cast(legs_bf16x8, q);
+}
+
 // accumulator register r of lane half h holds row drow(r, h) of its 32-row block
 __device__ __forceinline__ int legs_drow(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
 // hidden unit fed by k-slot e of k-step ks (lane half h) when a 64-wide
@@ -119,9 +135,7 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds &L, const float *_
         T.z1[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.w1[mb * 64 + lane], x, a, 0, 0, 0);
     }
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) T.h1[ks][e] = (__bf16)fmaxf(T.z1[ks >> 1][8 * (ks & 1) + e], 0.0f);
+    for (int ks = 0; ks < 4; ++ks) T.h1[ks] = relu_bf16x8(T.z1[ks >> 1], 8 * (ks & 1));
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
         legs_f32x16 a;
@@ -133,9 +147,7 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds &L, const float *_
         T.z2[mb] = a;
     }
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) T.h2[ks][e] = (__bf16)fmaxf(T.z2[ks >> 1][8 * (ks & 1) + e], 0.0f);
+    for (int ks = 0; ks < 4; ++ks) T.h2[ks] = relu_bf16x8(T.z2[ks >> 1], 8 * (ks & 1));
 #pragma unroll
     for (int mb = 0; mb < KB; ++mb) {
         legs_f32x16 a;
