@@ -184,16 +184,25 @@ k_project(const float *__restrict__ mean, const float *__restrict__ log_scale,
 
 // ---- backward ---------------------------------------------------------------
 
-__global__ void __launch_bounds__(256)
-k_project_backward(const float *__restrict__ mean, const float *__restrict__ log_scale,
-                   const float *__restrict__ quat, const float *__restrict__ omega, int64_t n,
-                   const legs_view *__restrict__ views, int32_t n_views, legs_opts o,
-                   const uint32_t *__restrict__ ntiles, const float *__restrict__ grad2d,
-                   float *__restrict__ d_mean, float *__restrict__ d_log_scale,
-                   float *__restrict__ d_quat, float *__restrict__ d_omega)
+// Whether view v of Gaussian g received a gradient (it has tiles and a
+// non-zero screen-space gradient); the chain rule skips the other views.
+__device__ __forceinline__ bool view_has_grad(const uint32_t *__restrict__ ntiles,
+                                              const float *__restrict__ grad2d, int64_t gv)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n) return;
+    if (ntiles[gv] == 0) return false;
+    const float4 ga = *reinterpret_cast<const float4 *>(grad2d + 8 * gv);
+    const float2 gb = *reinterpret_cast<const float2 *>(grad2d + 8 * gv + 4);
+    return !(ga.x == 0.0f && ga.y == 0.0f && ga.z == 0.0f && ga.w == 0.0f && gb.x == 0.0f && gb.y == 0.0f);
+}
+
+// Chain rule of one Gaussian, summed over its views.
+__device__ __forceinline__ void project_backward_one(
+    const float *__restrict__ mean, const float *__restrict__ log_scale, const float *__restrict__ quat,
+    const float *__restrict__ omega, int64_t n, const legs_view *__restrict__ views, int32_t n_views,
+    const legs_opts &o, const uint32_t *__restrict__ ntiles, const float *__restrict__ grad2d,
+    float *__restrict__ d_mean, float *__restrict__ d_log_scale, float *__restrict__ d_quat,
+    float *__restrict__ d_omega, int64_t g)
+{
     double dmu[3] = {0, 0, 0}, dls[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dom = 0.0;
     bool any = false;
     for (int v = 0; v < n_views; ++v) {
@@ -298,6 +307,47 @@ k_project_backward(const float *__restrict__ mean, const float *__restrict__ log
     d_omega[g] += (float)dom;
 }
 
+constexpr int PB_PER_THREAD = 8;   // Gaussians checked per thread
+
+// Most Gaussians of a dense scene receive no gradient (culled or hidden), so
+// each workgroup first queues, in LDS, those of its 256 x PB_PER_THREAD that
+// have a view with a gradient (one ballot and one LDS atomic per wave), then
+// runs the chain rule over the queue with every lane busy.
+__global__ void __launch_bounds__(256)
+k_project_backward(const float *__restrict__ mean, const float *__restrict__ log_scale,
+                   const float *__restrict__ quat, const float *__restrict__ omega, int64_t n,
+                   const legs_view *__restrict__ views, int32_t n_views, legs_opts o,
+                   const uint32_t *__restrict__ ntiles, const float *__restrict__ grad2d,
+                   float *__restrict__ d_mean, float *__restrict__ d_log_scale,
+                   float *__restrict__ d_quat, float *__restrict__ d_omega)
+{
+    __shared__ uint32_t s_q[256 * PB_PER_THREAD];
+    __shared__ uint32_t s_n;
+    const int tid = threadIdx.x, lane = legs_lane();
+    if (tid == 0) s_n = 0;
+    __syncthreads();
+    const int64_t g0 = (int64_t)blockIdx.x * 256 * PB_PER_THREAD;
+#pragma unroll
+    for (int i = 0; i < PB_PER_THREAD; ++i) {
+        const int64_t g = g0 + (int64_t)i * 256 + tid;
+        bool act = false;
+        if (g < n)
+            for (int v = 0; v < n_views && !act; ++v) act = view_has_grad(ntiles, grad2d, (int64_t)v * n + g);
+        const uint64_t bal = legs_ballot(act);
+        uint32_t base = 0;
+        if (lane == 0 && bal) base = atomicAdd(&s_n, (uint32_t)__popcll(bal));
+        base = (uint32_t)__shfl((int)base, 0, LEGS_WAVE);
+        if (act)
+            s_q[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))] =
+                (uint32_t)(g - g0);
+    }
+    __syncthreads();
+    const uint32_t cnt = s_n;
+    for (uint32_t k = tid; k < cnt; k += 256)
+        project_backward_one(mean, log_scale, quat, omega, n, views, n_views, o, ntiles, grad2d, d_mean,
+                             d_log_scale, d_quat, d_omega, g0 + s_q[k]);
+}
+
 } // namespace
 
 int32_t legs_launch_project(legs_ctx *ctx, const float *mean, const float *log_scale,
@@ -326,7 +376,7 @@ int32_t legs_launch_project_backward(legs_ctx *ctx, const float *mean, const flo
                                      float *d_opacity_logit, hipStream_t s)
 {
     if (n == 0) return LEGS_OK;
-    const int64_t blocks = (n + 255) / 256;
+    const int64_t blocks = (n + 256 * PB_PER_THREAD - 1) / (256 * PB_PER_THREAD);
     hipLaunchKernelGGL(k_project_backward, dim3((unsigned)blocks), dim3(256), 0, s, mean,
                        log_scale, quat, opacity_logit, n, views, n_views, *o, proj->ntiles, grad2d,
                        d_mean, d_log_scale, d_quat, d_opacity_logit);
