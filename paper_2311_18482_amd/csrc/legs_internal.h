@@ -94,7 +94,6 @@ struct legs_sort_layout {
     int64_t uoff_off;      // uint32 [total_tiles + 1] first compaction unit of each super-tile
     int64_t desc_off;      // uint32 [32] coarse digit layout, then uint64 [2] capacity cut
     int64_t ccap;          // coarse list capacity: capacity + total_tiles
-    int64_t cparts;        // partitions of the coarse lists
     int64_t clist_off;     // uint32 [4][ccap] coarse keys and positions, two buffers each
     int64_t ucnt_off;      // uint32 [ccap / unit + total_tiles][32] per-unit tile counts / offsets
     int64_t udesc_off;     // [ccap / unit + total_tiles] 32-byte unit descriptors

@@ -328,7 +328,6 @@ __device__ __forceinline__ void block_scan_256(uint64_t x, uint64_t *s_start, ui
 // Digit layout of the coarse passes, decided on the device from the number of
 // super-tiles: desc[0] passes, desc[2 + 2p] and desc[3 + 2p] the shift and
 // width of pass p (width 0: the pass is not needed and returns at once).
-constexpr int DESC_WORDS = 2 + 2 * LEGS_SORT_MAX_PASSES;
 
 // One onesweep pass over the digit of `rb` bits at `shift` of keys K with
 // 32-bit values (with desc, shift and width come from desc[2 + 2 pass ..]).
@@ -539,7 +538,7 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__res
 // blockIdx.x (the same segments as the segment passes: per =
 // ceil(partitions / gridDim.x)).
 __global__ void __launch_bounds__(LEGS_SORT_THREADS)
-k_tile_upsweep(const uint32_t *__restrict__ kin, const uint64_t *__restrict__ count, int64_t capacity,
+k_coarse_upsweep(const uint32_t *__restrict__ kin, const uint64_t *__restrict__ count, int64_t capacity,
                const uint32_t *__restrict__ desc, int pass, uint32_t *__restrict__ seg_hist)
 {
     constexpr int T = LEGS_SORT_THREADS, PART = LEGS_SORT_PART, ITEMS = LEGS_SORT_ITEMS;
@@ -1338,7 +1337,6 @@ legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles)
     const int64_t T = total_tiles > 0 ? total_tiles : 0;   // the G-view sort needs none of these
     L.tile_blocks = (T + 1023) / 1024;
     L.ccap = T > 0 ? capacity + T : 0;
-    L.cparts = (L.ccap + LEGS_SORT_PART - 1) / LEGS_SORT_PART;
     const int64_t units = T > 0 ? L.ccap / LEGS_COMPACT_UNIT + T : 0;
     L.tcount_off = o; o = up(o + 4 * T);
     L.scount_off = o; o = up(o + 4 * T);     // right after tcount: both are cleared at once
@@ -1376,7 +1374,7 @@ struct SortScratch {
     uint64_t *status;
     int64_t parts;
     // depth-first binning
-    int64_t tile_blocks, ccap, cparts;
+    int64_t tile_blocks, ccap;
     uint32_t *tcount, *scount, *cranges, *uoff, *desc, *clist, *ucnt, *partial, *spartial, *seg_hist,
         *seg_off;
     uint64_t *tsum, *toff, *ssum, *soff, *cut;
@@ -1397,7 +1395,6 @@ SortScratch sort_scratch_at(void *base, int64_t capacity, int64_t total_tiles = 
     S.parts = L.parts;
     S.tile_blocks = L.tile_blocks;
     S.ccap = L.ccap;
-    S.cparts = L.cparts;
     S.tcount = u32(L.tcount_off);
     S.tsum = u64(L.tsum_off);
     S.toff = u64(L.toff_off);
@@ -1651,7 +1648,7 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     const int nseg = LEGS_SEG_MAX;
     for (int p = 0; p < cpasses; ++p) {
         const int wo = p % 2, ri = 1 - wo;
-        hipLaunchKernelGGL(k_tile_upsweep, dim3(nseg), dim3(LEGS_SORT_THREADS), 0, s, ck[ri], ccount, S.ccap,
+        hipLaunchKernelGGL(k_coarse_upsweep, dim3(nseg), dim3(LEGS_SORT_THREADS), 0, s, ck[ri], ccount, S.ccap,
                            S.desc, p, S.seg_hist);
         hipLaunchKernelGGL(k_seg_scan, dim3(256), dim3(LEGS_SEG_MAX), 0, s, S.seg_hist, nseg, S.starts, S.desc,
                            p, S.seg_off);
