@@ -83,13 +83,8 @@ struct legs_sort_layout {
     int64_t status_off;    // uint64 [8][parts][256] look-back status words
     int64_t parts;         // partitions at full capacity
     // depth-first binning only (total_tiles > 0):
-    int64_t tile_blocks;   // ceil(total_tiles / 1024)
     int64_t tcount_off;    // uint32 [total_tiles] per-tile instance counts
-    int64_t tsum_off;      // uint64 [tile_blocks + 1] per-1024-tile sums
-    int64_t toff_off;      // uint64 [tile_blocks + 2] their exclusive scan and total
     int64_t scount_off;    // uint32 [total_tiles] per-super-tile counts (fewer super-tiles than tiles)
-    int64_t ssum_off;      // uint64 [tile_blocks + 1]
-    int64_t soff_off;      // uint64 [tile_blocks + 2]
     int64_t cranges_off;   // uint32 [total_tiles][2] super-tile list ranges
     int64_t uoff_off;      // uint32 [total_tiles + 1] first compaction unit of each super-tile
     int64_t desc_off;      // uint32 [32] coarse digit layout, then uint64 [2] capacity cut

@@ -43,38 +43,90 @@ __device__ __forceinline__ void st_status(uint64_t *p, uint64_t v)
 
 // ---- scan of the per-block instance counts -----------------------------------
 
+// Inclusive sum over lanes 0..l of a wave (DPP row shifts, then the row
+// broadcasts of lanes 15 and 31).
+__device__ __forceinline__ uint32_t wave_incl_add(uint32_t x)
+{
+#define LEGS_DPP_ADD(ctrl, rmask) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, ctrl, rmask, 0xF, false);
+    LEGS_DPP_ADD(0x111, 0xF)   // row_shr:1
+    LEGS_DPP_ADD(0x112, 0xF)   // row_shr:2
+    LEGS_DPP_ADD(0x114, 0xF)   // row_shr:4
+    LEGS_DPP_ADD(0x118, 0xF)   // row_shr:8
+    LEGS_DPP_ADD(0x142, 0xA)   // row_bcast:15 into rows 1 and 3
+    LEGS_DPP_ADD(0x143, 0xC)   // row_bcast:31 into rows 2 and 3
+#undef LEGS_DPP_ADD
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_add(uint64_t x)
+{
+#pragma unroll
+    for (int off = 1; off < LEGS_WAVE; off <<= 1) {
+        const uint64_t y = __shfl_up(x, off, LEGS_WAVE);
+        if (legs_lane() >= off) x += y;
+    }
+    return x;
+}
+
+// One workgroup of 1024 threads: exclusive scan of x(i), i in [0, n), handed
+// to emit(i, exclusive prefix, x(i)); returns the total. A round covers ROWS *
+// 1024 values: wave w scans its ROWS * 64 consecutive values as ROWS coalesced
+// rows (all loads in flight together), then adds the sums of the waves before
+// it. ROWS keeps the 64-bit scan within the 128 registers a 1024-thread
+// workgroup allows.
+template <typename T, typename X, typename E, int ROWS = sizeof(T) == 8 ? 8 : 16>
+__device__ __forceinline__ T scan_rounds(int64_t n, X x, E emit)
+{
+    constexpr int NW = 1024 / LEGS_WAVE;
+    __shared__ T s_w[NW];
+    const int lane = legs_lane(), wave = threadIdx.x / LEGS_WAVE;
+    T carry = 0;
+    for (int64_t base = 0; base < n; base += (int64_t)ROWS * 1024) {
+        const int64_t w0 = base + (int64_t)wave * ROWS * LEGS_WAVE + lane;
+        T v[ROWS], e[ROWS];
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+            const int64_t i = w0 + j * LEGS_WAVE;
+            v[j] = i < n ? x(i) : (T)0;
+        }
+        T run = 0;
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+            const T incl = wave_incl_add(v[j]);
+            const T row = __shfl(incl, LEGS_WAVE - 1, LEGS_WAVE);
+            e[j] = run + incl - v[j];
+            run += row;
+        }
+        if (lane == 0) s_w[wave] = run;
+        __syncthreads();
+        T pre = carry, all = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const T t = s_w[w];
+            pre += w < wave ? t : (T)0;
+            all += t;
+        }
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+            const int64_t i = w0 + j * LEGS_WAVE;
+            if (i < n) emit(i, pre + e[j], v[j]);
+        }
+        carry += all;
+        __syncthreads();
+    }
+    return carry;
+}
+
 // One workgroup: exclusive scan of counts[0..nb) into offsets[0..nb], total
 // in offsets[nb] and in *total (counts stay intact, so the binning can rerun).
 __device__ __forceinline__ void scan_blocks(const uint64_t *__restrict__ counts, uint64_t *__restrict__ offsets,
                                             int64_t nb, uint64_t *__restrict__ total)
 {
-    __shared__ uint64_t s_w[16];
-    __shared__ uint64_t s_carry;
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    const int lane = legs_lane(), wave = threadIdx.x / LEGS_WAVE;
-    for (int64_t base = 0; base < nb; base += 1024) {
-        const int64_t i = base + threadIdx.x;
-        const uint64_t x = i < nb ? counts[i] : 0;
-        uint64_t incl = x;
-#pragma unroll
-        for (int off = 1; off < LEGS_WAVE; off <<= 1) {
-            const uint64_t y = __shfl_up(incl, off, LEGS_WAVE);
-            if (lane >= off) incl += y;
-        }
-        if (lane == LEGS_WAVE - 1) s_w[wave] = incl;
-        __syncthreads();
-        uint64_t wpre = 0;
-        for (int w = 0; w < wave; ++w) wpre += s_w[w];
-        const uint64_t carry = s_carry;
-        if (i < nb) offsets[i] = carry + wpre + incl - x;
-        __syncthreads();
-        if (threadIdx.x == 1023) s_carry = carry + wpre + incl;
-        __syncthreads();
-    }
+    const uint64_t t = scan_rounds<uint64_t>(
+        nb, [&](int64_t i) { return counts[i]; }, [&](int64_t i, uint64_t e, uint64_t) { offsets[i] = e; });
     if (threadIdx.x == 0) {
-        offsets[nb] = s_carry;
-        *total = s_carry;
+        offsets[nb] = t;
+        *total = t;
     }
 }
 
@@ -171,6 +223,21 @@ k_emit(const int4 *__restrict__ box, const float *__restrict__ depth,
 
 constexpr int HIST_RUN = 16;  // keys per lane per block iteration
 
+// Adds each valid lane's digit to an LDS histogram: the lanes holding the
+// first valid lane's digit add with one atomic, the others with one each, so
+// a wave of equal digits (the high digits of clustered keys) does not
+// serialise on one LDS address. Called by every lane of the wave.
+__device__ __forceinline__ void hist_add(uint32_t *h, uint32_t d, bool ok)
+{
+    const uint64_t valid = legs_ballot(ok);
+    if (valid == 0) return;
+    const int lead = __builtin_ctzll(valid);
+    const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d, lead);
+    const uint64_t same = legs_ballot(ok && d == d0);
+    if (ok && d != d0) atomicAdd(&h[d], 1u);
+    if (legs_lane() == lead) atomicAdd(&h[d0], (uint32_t)__popcll(same));
+}
+
 // Digit histograms of passes [first, first + npass) in one read of the keys.
 // Loads are coalesced (lane l reads key base + 64 i + l). RUNS: within each
 // wave a run of equal digits in consecutive lanes is counted with one LDS
@@ -178,7 +245,7 @@ constexpr int HIST_RUN = 16;  // keys per lane per block iteration
 // long runs (every tile of one Gaussian shares its depth digits, consecutive
 // tiles of a row share the high tile digits), so hot digits do not serialise.
 // Without RUNS (keys in no particular order, e.g. the G-view depth keys) the
-// keys of a lane are loaded at once and each digit is one LDS atomic.
+// keys of a lane are loaded at once and counted with hist_add.
 template <bool RUNS>
 __global__ void __launch_bounds__(256)
 k_histogram(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ count,
@@ -202,10 +269,11 @@ k_histogram(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ coun
                 k[i] = idx < m ? keys[idx] : 0ull;
             }
 #pragma unroll
-            for (int i = 0; i < HIST_RUN; ++i)
-                if (wbase + (int64_t)i * LEGS_WAVE + lane < m)
-                    for (int p = 0; p < npass; ++p)
-                        atomicAdd(&s_h[p][(uint32_t)(k[i] >> (8 * (first + p))) & 255u], 1u);
+            for (int i = 0; i < HIST_RUN; ++i) {
+                const bool ok = wbase + (int64_t)i * LEGS_WAVE + lane < m;
+                for (int p = 0; p < npass; ++p)
+                    hist_add(s_h[p], (uint32_t)(k[i] >> (8 * (first + p))) & 255u, ok);
+            }
             continue;
         }
         for (int i = 0; i < HIST_RUN; ++i) {
@@ -520,7 +588,7 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__res
                 const uint32_t d = (uint32_t)(kk >> shift) & dmask;
                 const uint64_t gpos = s_gstart[d] + (uint64_t)k;
                 if (gpos < (uint64_t)capacity) {
-                    kout[gpos] = kk;
+                    if (!payload) kout[gpos] = kk;   // the last coarse pass's keys are not read
                     vout[gpos] = s_vals[k];
                     // the partition's positions span a narrow window: these gathers stay in cache
                     if (payload) {
@@ -565,8 +633,7 @@ k_coarse_upsweep(const uint32_t *__restrict__ kin, const uint64_t *__restrict__ 
             k[q] = e < nvalid ? kin[base + e] : 0u;
         }
 #pragma unroll
-        for (int q = 0; q < ITEMS; ++q)
-            if (tid + q * T < nvalid) atomicAdd(&s_hist[(k[q] >> shift) & dmask], 1u);
+        for (int q = 0; q < ITEMS; ++q) hist_add(s_hist, (k[q] >> shift) & dmask, tid + q * T < nvalid);
     }
     __syncthreads();
     if (tid < 256) seg_hist[(int64_t)blockIdx.x * 256 + tid] = s_hist[tid];
@@ -617,6 +684,8 @@ k_order_keys(const uint32_t *__restrict__ ntiles, const float *__restrict__ dept
 // Super-tile edge in tiles: 8 x 4 tiles, one bit each of a 32-bit mask.
 constexpr int SX = 8, SY = 4, SUPER_TILES = SX * SY;
 static_assert(SUPER_TILES == 32, "one mask bit per tile of a super-tile");
+// Entries of the coarse lists per unit of the compaction (one wave each).
+constexpr int UNIT = LEGS_COMPACT_UNIT;
 
 // Tile and super-tile records and the per-view position ranges of the
 // depth-ordered G-views, and the tile and super-tile instance counts of each
@@ -755,8 +824,6 @@ struct CountGrid {
     const legs_view *views;   // the tile or super-tile views
     uint32_t *count;          // [T] cells (at most T of them)
     uint32_t *partial;        // [LEGS_TILE_CHUNKS][T] per-workgroup LDS grids
-    uint64_t *bsum;           // [tile_blocks + 1] sums of 1024 cells
-    uint64_t *boff;           // [tile_blocks + 2] their exclusive scan, total
     uint32_t *ranges;         // [T][2]
     const uint32_t *desc;     // digit layout of passes over these cells (NULL: none)
     uint32_t *hist;           // digit histograms of those passes
@@ -911,57 +978,58 @@ k_count_cols(CountGrid g0, CountGrid g1)
     }
 }
 
-// Sum of each block of 1024 cells of grid blockIdx.y.
-__global__ void __launch_bounds__(1024)
-k_count_block_sums(int64_t T, CountGrid g0, CountGrid g1)
+// Cell at position t of the list order: the cell itself, except for the
+// super-tile grid when its coarse passes take the top bits first and the low
+// byte last (desc[1] = S, the number of super-tiles): its lists are then
+// ordered by (low byte, id >> 8), and position t holds super-tile
+// 256 h + l with l, h from t (low bytes below S mod 256 hold one more id).
+__device__ __forceinline__ int64_t list_cell(int64_t t, const uint32_t *__restrict__ desc)
 {
-    const CountGrid &cg = blockIdx.y ? g1 : g0;
-    __shared__ uint64_t s_w[16];
-    const int64_t t = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-    uint64_t x = t < T ? cg.count[t] : 0u;
-#pragma unroll
-    for (int off = LEGS_WAVE / 2; off > 0; off >>= 1) x += __shfl_down(x, off, LEGS_WAVE);
-    if (legs_lane() == 0) s_w[threadIdx.x / LEGS_WAVE] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t sum = 0;
-        for (int w = 0; w < 16; ++w) sum += s_w[w];
-        cg.bsum[blockIdx.x] = sum;
+    const int64_t S = desc ? (int64_t)desc[1] : 0;
+    if (S <= 256 || t >= S) return t;
+    const int64_t hf = S >> 8, r = S & 255;
+    int64_t l, h;
+    if (t < r * (hf + 1)) {
+        l = t / (hf + 1);
+        h = t - l * (hf + 1);
+    } else {
+        const int64_t u = t - r * (hf + 1);
+        l = r + u / hf;
+        h = u - (l - r) * hf;
     }
+    return (h << 8) | l;
 }
 
-// List ranges [start, start + count) of the cells of grid blockIdx.y from the
-// scanned counts, and with desc the digit histograms of the passes over them.
+// List ranges [start, start + count) of every cell, one workgroup per grid:
+// grid 0's cells in order, grid 1's in list order (list_cell) with the digit
+// histograms of the coarse passes; a third workgroup numbers the units of the
+// super-tile lists, ceil(count / UNIT) per super-tile in id order (uoff[T] =
+// their number).
 __global__ void __launch_bounds__(1024)
-k_count_ranges(int64_t T, CountGrid g0, CountGrid g1)
+k_count_lists(int64_t T, CountGrid g0, CountGrid g1, uint32_t *__restrict__ uoff)
 {
-    const CountGrid &cg = blockIdx.y ? g1 : g0;
-    __shared__ uint32_t s_h[4][256];
-    __shared__ uint64_t s_w[16];
+    if (blockIdx.x == 2) {
+        const uint32_t t = scan_rounds<uint32_t>(
+            T, [&](int64_t c) { return (g1.count[c] + UNIT - 1) / UNIT; },
+            [&](int64_t c, uint32_t e, uint32_t) { uoff[c] = e; });
+        if (threadIdx.x == 0) uoff[T] = t;
+        return;
+    }
+    const CountGrid &cg = blockIdx.x ? g1 : g0;
+    __shared__ uint32_t s_h[LEGS_SORT_MAX_PASSES][256];
     const int npass = cg.desc ? (int)cg.desc[0] : 0;
-    for (int i = threadIdx.x; i < 4 * 256; i += 1024) (&s_h[0][0])[i] = 0;
-    const int lane = legs_lane(), wave = threadIdx.x / LEGS_WAVE;
-    const int64_t t = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-    const uint64_t x = t < T ? cg.count[t] : 0u;
-    uint64_t incl = x;
-#pragma unroll
-    for (int off = 1; off < LEGS_WAVE; off <<= 1) {
-        const uint64_t y = __shfl_up(incl, off, LEGS_WAVE);
-        if (lane >= off) incl += y;
-    }
-    if (lane == LEGS_WAVE - 1) s_w[wave] = incl;
+    for (int i = threadIdx.x; i < LEGS_SORT_MAX_PASSES * 256; i += 1024) (&s_h[0][0])[i] = 0;
     __syncthreads();
-    uint64_t wpre = 0;
-    for (int w = 0; w < wave; ++w) wpre += s_w[w];
-    if (t < T) {
-        const uint64_t st = cg.boff[blockIdx.x] + wpre + incl - x;
-        cg.ranges[2 * t] = (uint32_t)st;
-        cg.ranges[2 * t + 1] = (uint32_t)(st + x);
-        if (x)
-            for (int p = 0; p < npass; ++p)
-                atomicAdd(&s_h[p][(uint32_t)(t >> cg.desc[2 + 2 * p]) & ((1u << cg.desc[3 + 2 * p]) - 1u)],
-                          (uint32_t)x);
-    }
+    scan_rounds<uint32_t>(
+        T, [&](int64_t t) { return cg.count[list_cell(t, cg.desc)]; },
+        [&](int64_t t, uint32_t e, uint32_t x) {
+            const int64_t c = list_cell(t, cg.desc);
+            cg.ranges[2 * c] = e;
+            cg.ranges[2 * c + 1] = e + x;
+            if (x)
+                for (int p = 0; p < npass; ++p)
+                    atomicAdd(&s_h[p][(uint32_t)(c >> cg.desc[2 + 2 * p]) & ((1u << cg.desc[3 + 2 * p]) - 1u)], x);
+        });
     __syncthreads();
     for (int i = threadIdx.x; i < npass * 256; i += 1024) {
         const uint32_t c = (&s_h[0][0])[i];
@@ -973,7 +1041,9 @@ k_count_ranges(int64_t T, CountGrid g0, CountGrid g1)
 
 // Super-tile grids of the views (SX x SY tiles each, numbered after one
 // another like the tile grids) and the digit layout of the coarse passes:
-// ceil(bits / 8) passes over the bits of the super-tile id, split evenly.
+// ceil(bits / 8) passes over the bits of the super-tile id: one pass over the
+// whole id; two passes over the top bits, then the low byte (lists ordered
+// by (low byte, id >> 8), see list_cell); more, even digits from the lowest.
 // The other threads clear the digit histograms and pass counters, the
 // capacity cut (no G-view cut) and the per-view position ranges.
 __global__ void __launch_bounds__(256)
@@ -999,59 +1069,22 @@ k_super_views(const legs_view *__restrict__ views, int n_views, legs_view *__res
     while (bits < 32 && (1ll << bits) < off) ++bits;
     const int np = (bits + 7) / 8;
     desc[0] = (uint32_t)np;
-    desc[1] = 0u;
+    desc[1] = np == 2 ? (uint32_t)off : 0u;
     for (int p = 0, sh = 0; p < LEGS_SORT_MAX_PASSES; ++p) {
         const int w = p < np ? bits / np + (p < bits % np ? 1 : 0) : 0;
         desc[2 + 2 * p] = (uint32_t)sh;
         desc[3 + 2 * p] = (uint32_t)w;
         sh += w;
     }
-}
-
-// Inclusive sum over lanes 0..l of a wave (DPP row shifts, then the row
-// broadcasts of lanes 15 and 31).
-__device__ __forceinline__ uint32_t wave_incl_add(uint32_t x)
-{
-#define LEGS_DPP_ADD(ctrl, rmask) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, ctrl, rmask, 0xF, false);
-    LEGS_DPP_ADD(0x111, 0xF)   // row_shr:1
-    LEGS_DPP_ADD(0x112, 0xF)   // row_shr:2
-    LEGS_DPP_ADD(0x114, 0xF)   // row_shr:4
-    LEGS_DPP_ADD(0x118, 0xF)   // row_shr:8
-    LEGS_DPP_ADD(0x142, 0xA)   // row_bcast:15 into rows 1 and 3
-    LEGS_DPP_ADD(0x143, 0xC)   // row_bcast:31 into rows 2 and 3
-#undef LEGS_DPP_ADD
-    return x;
-}
-
-// Entries of the coarse lists per unit of the compaction (one wave each).
-constexpr int UNIT = LEGS_COMPACT_UNIT;
-
-// Units of the coarse lists: super-tile s's list [cranges[2s], cranges[2s+1])
-// is cut into ceil(length / UNIT) units; uoff[s] is the first unit of s and
-// uoff[n] the number of units. One workgroup.
-__global__ void __launch_bounds__(1024)
-k_units(const uint32_t *__restrict__ cranges, int64_t n, uint32_t *__restrict__ uoff)
-{
-    __shared__ uint32_t s_w[16];
-    const int lane = legs_lane(), wave = threadIdx.x / LEGS_WAVE;
-    uint32_t carry = 0;
-    for (int64_t s0 = 0; s0 < n; s0 += 1024) {
-        const int64_t st = s0 + threadIdx.x;
-        const uint32_t len = st < n ? cranges[2 * st + 1] - cranges[2 * st] : 0u;
-        const uint32_t u = (len + UNIT - 1) / UNIT;
-        const uint32_t incl = wave_incl_add(u);
-        if (lane == LEGS_WAVE - 1) s_w[wave] = incl;
-        __syncthreads();
-        uint32_t pre = 0, tot = 0;
-        for (int w = 0; w < 16; ++w) {
-            pre += w < wave ? s_w[w] : 0u;
-            tot += s_w[w];
-        }
-        if (st < n) uoff[st] = carry + pre + incl - u;
-        carry += tot;
-        __syncthreads();
+    if (np == 2) {
+        // top bits first, low byte last: the last pass then reads runs of 256
+        // consecutive super-tiles (one or two views), whose entries' positions
+        // are dense, so its record gathers stay local
+        desc[2] = 8u;
+        desc[3] = (uint32_t)(bits - 8);
+        desc[4] = 0u;
+        desc[5] = 8u;
     }
-    if (threadIdx.x == 0) uoff[n] = carry;
 }
 
 // What a wave needs of its unit: the list entries [e0, e1), the super-tile's
@@ -1335,15 +1368,10 @@ legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles)
     L.status_off = L.counter_off + 256;  // 64 counters
     int64_t o = up(L.status_off + 8 * (int64_t)LEGS_SORT_MAX_PASSES * L.parts * 256);
     const int64_t T = total_tiles > 0 ? total_tiles : 0;   // the G-view sort needs none of these
-    L.tile_blocks = (T + 1023) / 1024;
     L.ccap = T > 0 ? capacity + T : 0;
     const int64_t units = T > 0 ? L.ccap / LEGS_COMPACT_UNIT + T : 0;
     L.tcount_off = o; o = up(o + 4 * T);
     L.scount_off = o; o = up(o + 4 * T);     // right after tcount: both are cleared at once
-    L.tsum_off = o; o = up(o + 8 * (L.tile_blocks + 1));
-    L.toff_off = o; o = up(o + 8 * (L.tile_blocks + 2));
-    L.ssum_off = o; o = up(o + 8 * (L.tile_blocks + 1));
-    L.soff_off = o; o = up(o + 8 * (L.tile_blocks + 2));
     L.cranges_off = o; o = up(o + 8 * T);
     L.uoff_off = o; o = up(o + 4 * (T + 1));
     L.desc_off = o; o = up(o + 256);
@@ -1374,10 +1402,10 @@ struct SortScratch {
     uint64_t *status;
     int64_t parts;
     // depth-first binning
-    int64_t tile_blocks, ccap;
+    int64_t ccap;
     uint32_t *tcount, *scount, *cranges, *uoff, *desc, *clist, *ucnt, *partial, *spartial, *seg_hist,
         *seg_off;
-    uint64_t *tsum, *toff, *ssum, *soff, *cut;
+    uint64_t *cut;
     char *udesc, *cpay;
 };
 
@@ -1393,14 +1421,9 @@ SortScratch sort_scratch_at(void *base, int64_t capacity, int64_t total_tiles = 
     S.counters = u32(L.counter_off);
     S.status = u64(L.status_off);
     S.parts = L.parts;
-    S.tile_blocks = L.tile_blocks;
     S.ccap = L.ccap;
     S.tcount = u32(L.tcount_off);
-    S.tsum = u64(L.tsum_off);
-    S.toff = u64(L.toff_off);
     S.scount = u32(L.scount_off);
-    S.ssum = u64(L.ssum_off);
-    S.soff = u64(L.soff_off);
     S.cranges = u32(L.cranges_off);
     S.uoff = u32(L.uoff_off);
     S.desc = u32(L.desc_off);
@@ -1609,8 +1632,8 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     //    capacity, which holds every G-view the tile stream keeps): the tile
     //    ranges, the super-tile list ranges, the digit histograms of the coarse
     //    passes, and the G-view the tile cut falls in
-    CountGrid cg0{views, S.tcount, S.partial, S.tsum, S.toff, bins->ranges, nullptr, nullptr};
-    CountGrid cg1{sviews, S.scount, S.spartial, S.ssum, S.soff, S.cranges, S.desc, S.hist};
+    CountGrid cg0{views, S.tcount, S.partial, bins->ranges, nullptr, nullptr};
+    CountGrid cg1{sviews, S.scount, S.spartial, S.cranges, S.desc, S.hist};
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(ctx, 2 * T, 256, 8)), dim3(256), 0, s, S.tcount,
                        (int64_t)(S.scount - S.tcount) + T, 0u);
     LEGS_CHECK_LAUNCH(ctx);
@@ -1621,11 +1644,7 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
                        cg0, cg1);
     hipLaunchKernelGGL(k_count_rows, dim3(64, (unsigned)n_views, 2), dim3(256), 0, s, cg0, cg1);
     hipLaunchKernelGGL(k_count_cols, dim3(64, (unsigned)n_views, 2), dim3(256), 0, s, cg0, cg1);
-    hipLaunchKernelGGL(k_count_block_sums, dim3((unsigned)S.tile_blocks, 2), dim3(1024), 0, s, T, cg0, cg1);
-    hipLaunchKernelGGL(k_scan_pair, dim3(2), dim3(1024), 0, s,
-                       ScanArgs{S.tsum, S.toff, S.tile_blocks, S.toff + S.tile_blocks + 1},
-                       ScanArgs{S.ssum, S.soff, S.tile_blocks, S.soff + S.tile_blocks + 1});
-    hipLaunchKernelGGL(k_count_ranges, dim3((unsigned)S.tile_blocks, 2), dim3(1024), 0, s, T, cg0, cg1);
+    hipLaunchKernelGGL(k_count_lists, dim3(3), dim3(1024), 0, s, T, cg0, cg1, S.uoff);
     LEGS_CHECK_LAUNCH(ctx);
     // passes for the most super-tiles there can be (one per tile); the ones
     // the actual count does not need return at once
@@ -1663,7 +1682,6 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     const int64_t max_units = S.ccap / LEGS_COMPACT_UNIT + T;
     const int gu = grid_for(ctx, max_units, 256 / LEGS_WAVE, 8);
     UnitCtx *udesc = reinterpret_cast<UnitCtx *>(S.udesc);
-    hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, s, S.cranges, T, S.uoff);
     hipLaunchKernelGGL(k_unit_desc, dim3(grid_for(ctx, max_units, 256, 4)), dim3(256), 0, s, S.uoff, T, S.cranges,
                        sviews, views, n_views, udesc);
     hipLaunchKernelGGL(k_compact_count, dim3(gu), dim3(256), 0, s, cv[0], cv[1], S.desc, S.uoff, T, udesc, P.pay,
