@@ -77,6 +77,12 @@ typedef struct {
  * and each super-tile's list compacted into its tiles' lists. The lists are
  * identical. The depth-first binning needs capacity + total_tiles < 2^32. */
 #define LEGS_FLAG_FULL_SORT 2
+/* Blend kernels evaluate alpha at every pixel of each Gaussian's 3-sigma box.
+ * By default they skip the pixels outside the bounding box of the ellipse
+ * where opacity * exp(power) can reach alpha_min (widened for float32
+ * rounding): alpha stays below alpha_min there, so images, T_final, last and
+ * gradients are the same either way; only the work differs. */
+#define LEGS_FLAG_FULL_BOX 4
 
 /* Rasteriser options. Defaults (legs_opts_default): tile 16, lds_batch 256,
  * alpha_max 0.99, alpha_min 1/255, t_min 1e-4, lowpass 0.3 px^2, z_near 0.2,

@@ -19,6 +19,7 @@ LEGS_ERR_UNSUPPORTED = -4
 LEGS_MAX_CHANNELS = 64
 LEGS_FLAG_PERSISTENT = 1
 LEGS_FLAG_FULL_SORT = 2
+LEGS_FLAG_FULL_BOX = 4
 
 
 class LegsError(RuntimeError):

@@ -49,6 +49,7 @@ struct BlendParams {
     int C;
     int batch;
     float amax, amin, tmin;
+    bool reach;         // skip the pixels outside the reach of alpha_min (reach_box)
     uint32_t *counter;  // non-NULL: persistent launch, tiles taken from this counter
 };
 
@@ -102,6 +103,57 @@ __device__ __forceinline__ void opaque_zero2(float &a, float &b)
 }
 
 __device__ __forceinline__ int sext8(uint32_t v, int sh) { return (int)(int8_t)((v >> sh) & 0xffu); }
+
+// The pixels of a Gaussian's 3-sigma box where alpha can reach alpha_min,
+// from the staged values the blend kernels compute with: the scaled conic cs
+// (exponent in base 2: As dx^2 + Bs dx dy + Cs dy^2, opacity in w) and the
+// float32 offset (mx, my) of the mean from the centre of the tile's first
+// pixel. The box is cut to the bounding box of the ellipse where the exponent
+// is at least log2(alpha_min / opacity); every pixel outside it computes alpha
+// < alpha_min, so it neither blends nor stops there and the kernels skip it.
+// The ellipse is widened (the bound K by a relative 1e-3, by 1e-3 and by 1e-4
+// times kap = (1 + |rho|) / (1 - |rho|), rho the correlation of the form, a
+// bound on the sum of the exponent's absolute terms over its value; the half
+// widths by 0.5 % and by 0.01 pixel plus 1e-6 of the offset) so that neither
+// the few-ulp rounding of the kernels' exponent and exp2 nor the float32
+// arithmetic here (within 1e-3 relative while kap <= 1e4) can exclude a pixel
+// that reaches alpha_min. Very elongated ellipses (kap > 1e4) keep the whole
+// box. (x0, x1, y0, y1): the tile-relative inclusive box, tightened in place;
+// an empty result is (TILE, -1, TILE, -1).
+template <int TILE>
+__device__ __forceinline__ void reach_box(float4 cs, float mx, float my, float amin, int &x0, int &x1,
+                                          int &y0, int &y1)
+{
+    // the form a dx^2 + 2 h dx dy + c dy^2 <= K of the pixels that reach alpha_min
+    const float a = -cs.x, h = -0.5f * cs.y, c = -cs.z, op = cs.w;
+    if (amin > 0.0f && a > 0.0f && c > 0.0f) {
+        if (!(op >= amin)) {   // alpha <= opacity < alpha_min everywhere
+            x1 = x0 - 1;
+        } else {
+            const float r2 = (h * h) / (a * c);
+            const float rho = __builtin_sqrtf(r2);
+            if (rho < 0.9998f) {   // kap <= 1e4
+                const float kap = (1.0f + rho) / (1.0f - rho);
+                const float K = (__builtin_amdgcn_logf(op) - __builtin_amdgcn_logf(amin)) * 1.001f + 1e-3f +
+                                1e-4f * kap;
+                const float u = K / (1.0f - r2);
+                const float hw = __builtin_sqrtf(u / a) * 1.005f + 0.01f + 1e-6f * fabsf(mx);
+                const float hh = __builtin_sqrtf(u / c) * 1.005f + 0.01f + 1e-6f * fabsf(my);
+                // tile-relative pixel x has its centre mx - x from the mean
+                const float fx0 = ceilf(mx - hw), fx1 = floorf(mx + hw);
+                const float fy0 = ceilf(my - hh), fy1 = floorf(my + hh);
+                if (fx0 > (float)x0) x0 = fx0 > (float)x1 ? x1 + 1 : (int)fx0;
+                if (fx1 < (float)x1) x1 = fx1 < (float)x0 ? x0 - 1 : (int)fx1;
+                if (fy0 > (float)y0) y0 = fy0 > (float)y1 ? y1 + 1 : (int)fy0;
+                if (fy1 < (float)y1) y1 = fy1 < (float)y0 ? y0 - 1 : (int)fy1;
+            }
+        }
+    }
+    if (x0 > x1 || y0 > y1) {
+        x0 = y0 = TILE;
+        x1 = y1 = -1;
+    }
+}
 
 // LDS layout of one staged batch of B entries.
 template <int TILE, int CP>
@@ -187,6 +239,17 @@ __device__ __forceinline__ void stage_batch(const BlendParams &P, int v, int til
         }
     }
     __syncthreads();
+    if (P.reach) {
+        // the boxes cut to the reach of alpha_min, from the staged values
+        for (int k = tid; k < nb; k += NT) {
+            const uint32_t pk = S.box[k];
+            int x0 = sext8(pk, 0), x1 = sext8(pk, 8), y0 = sext8(pk, 16), y1 = sext8(pk, 24);
+            reach_box<TILE>(S.c[k], S.qx[k * NQ], S.qy[k * NQ], P.amin, x0, x1, y0, y1);
+            S.box[k] = (uint32_t)(x0 & 0xff) | ((uint32_t)(x1 & 0xff) << 8) | ((uint32_t)(y0 & 0xff) << 16) |
+                       ((uint32_t)(y1 & 0xff) << 24);
+        }
+        __syncthreads();
+    }
     if constexpr (!DIRECT) {
         for (int e = tid; e < nb * CP; e += NT) {
             const int k = e / CP, c = e - k * CP;
@@ -529,10 +592,15 @@ k_blend_count(BlendParams P, unsigned long long *__restrict__ counts)
             ++walked;
             const uint32_t gid = P.ids[k];
             const int64_t gv = (int64_t)ti.v * P.n + gid;
-            const int4 b = P.box[gv];
-            if (px < b.x || px > b.y || py < b.z || py > b.w) continue;
             const double2 m = P.mean2d[gv];
+            const int4 b = P.box[gv];
             const float4 cn = scale_conic(P.conic[gv]);
+            int x0 = min(max(b.x - ti.tile_x0, -1), TILE), x1 = min(max(b.y - ti.tile_x0, -1), TILE);
+            int y0 = min(max(b.z - ti.tile_y0, -1), TILE), y1 = min(max(b.w - ti.tile_y0, -1), TILE);
+            if (P.reach)
+                reach_box<TILE>(cn, (float)(m.x - ((double)ti.tile_x0 + 0.5)), (float)(m.y - ((double)ti.tile_y0 + 0.5)),
+                                P.amin, x0, x1, y0, y1);
+            if (lx < x0 || lx > x1 || ly < y0 || ly > y1) continue;
             const float dx = (float)(m.x - ((double)bx + 0.5)) - fx;
             const float dy = (float)(m.y - ((double)by + 0.5)) - fy;
             float fa, fb, ep;
@@ -652,6 +720,7 @@ BlendParams make_params(const legs_projected *proj, int64_t n, const legs_bins *
     P.amax = o->alpha_max;
     P.amin = o->alpha_min;
     P.tmin = o->t_min;
+    P.reach = (o->flags & LEGS_FLAG_FULL_BOX) == 0;
     return P;
 }
 

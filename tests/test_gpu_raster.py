@@ -176,6 +176,39 @@ def test_tile_and_batch_invariance(R):
                 assert np.array_equal(cur[0], ref[0]) and np.array_equal(cur[1], ref[1])
 
 
+def test_reach_cut_changes_no_result(R):
+    """Skipping the pixels outside the reach of alpha_min changes nothing:
+    images, final transmittance and last index are bit-identical to
+    evaluating the whole 3-sigma box (LEGS_FLAG_FULL_BOX), gradients agree to
+    float32 summation order, on a scene with near-threshold and transparent
+    opacities and strongly elongated Gaussians; only the work counts drop."""
+    scene = synth.make_scene(30_000, 19, synth.VOL_C2, d_sem=8)
+    scene.opacity_logit[::7] = -6.5                 # opacity 0.0015 < alpha_min
+    scene.opacity_logit[3::7] = -5.52               # opacity just above alpha_min
+    scene.log_scale[::5, 0] += 2.0                  # needles
+    scene.log_scale[1::5, 1] -= 1.5
+    cams = [synth.camera_front(320, 240, 300.0), synth.camera_front(150, 110, 140.0)]
+    G = synth.upstream_grads(cams, scene.n_channels, 210)
+    res = {}
+    for full in (False, True):
+        note(f"reach cut full_box={full}")
+        o = R.opts(full_box=full)
+        rast, d, proj, bins, out, T, last = run_forward(R, scene, cams, o)
+        grad2d, g, d_ch = run_backward(R, rast, d, proj, bins, T, last, G)
+        counts = R.render_counts(rast.ctx, proj, bins, rast.views, o)
+        res[full] = (out.cpu().numpy(), T.cpu().numpy(), last.cpu().numpy(), PT.gpu_grads_to_np(g, d_ch), counts)
+    a, b = res[False], res[True]
+    for i in range(3):
+        assert np.array_equal(a[i], b[i])
+    for k in a[3]:
+        x, y = a[3][k], b[3][k]
+        scale = np.abs(y).max() + 1e-30
+        assert np.abs(x - y).max() <= 1e-4 * scale, k
+    note(f"counts reach {a[4]} full box {b[4]}")
+    assert a[4][1] == b[4][1] and a[4][3] == b[4][3]
+    assert a[4][0] < 0.9 * b[4][0] and a[4][2] < 0.9 * b[4][2]
+
+
 def test_determinism_and_permutation(R):
     scene = synth.make_scene(40_000, 17, synth.VOL_C2, d_sem=8)
     cams = [synth.camera_front(300, 200, 280.0)]
@@ -386,10 +419,13 @@ def test_depth_first_and_full_sort_lists_identical(R, rig):
 def _expected_counts(proj_v, cam, ids, ranges, tile_offset, tile, amin, amax, tmin):
     """Per-pixel walk of the tile lists in FP64 (numpy over the pixels of one
     tile at a time): alpha evaluations of the forward, blended entries, alpha
-    evaluations of the backward and list positions walked."""
+    evaluations of the backward and list positions walked, with evaluations
+    counted inside the box, and inside the box cut to the bounding box of the
+    ellipse where opacity * exp(power) >= alpha_min (the reach)."""
     tx_n = (cam.width + tile - 1) // tile
     ty_n = (cam.height + tile - 1) // tile
     tot = np.zeros(4)
+    reach = np.zeros(4)
     for t in range(tx_n * ty_n):
         s, e = ranges[tile_offset + t]
         if e <= s:
@@ -403,6 +439,14 @@ def _expected_counts(proj_v, cam, ids, ranges, tile_offset, tile, amin, amax, tm
         inbox = ((p["valid"] != 0) & (px >= p["x0"]) & (px <= p["x1"]) & (py >= p["y0"])
                  & (py <= p["y1"]))
         dx, dy = p["mx"] - (px + 0.5), p["my"] - (py + 0.5)
+        # A dx^2 + 2 B dx dy + C dy^2 <= K, K = 2 ln(opacity / alpha_min): its
+        # bounding box has half widths sqrt(K C / det) and sqrt(K A / det)
+        K = 2.0 * np.log(np.maximum(p["sig"], 1e-300) / amin)
+        det = p["A"] * p["C"] - p["B"] ** 2
+        with np.errstate(invalid="ignore", divide="ignore"):
+            hw = np.sqrt(np.maximum(K, 0.0) * p["C"] / det)
+            hh = np.sqrt(np.maximum(K, 0.0) * p["A"] / det)
+        inreach = inbox & (K >= 0.0) & (np.abs(dx) <= hw) & (np.abs(dy) <= hh)
         power = np.minimum(-0.5 * (p["A"] * dx * dx + p["C"] * dy * dy) - p["B"] * dx * dy, 0.0)
         alpha = np.minimum(p["sig"] * np.exp(power), amax)
         blend = inbox & (alpha >= amin)
@@ -420,13 +464,19 @@ def _expected_counts(proj_v, cam, ids, ranges, tile_offset, tile, amin, amax, tm
         tot[1] += blended.sum()
         tot[2] += (inbox & (pos <= last[:, None])).sum()
         tot[3] += np.minimum(k_stop + 1, L).sum()
-    return tot
+        reach[0] += (inreach & (pos <= k_stop[:, None])).sum()
+        reach[2] += (inreach & (pos <= last[:, None])).sum()
+    reach[1], reach[3] = tot[1], tot[3]
+    return tot, reach
 
 
 def test_render_counts_match_a_per_pixel_walk(R):
-    """The work counts behind the blend kernels' ALU roofline equal a plain
+    """The work counts behind the blend kernels' ALU roofline against a plain
     per-pixel walk of the same lists (FP64; up to the rare decisions that FP32
-    and FP64 take differently)."""
+    and FP64 take differently): blended entries and list positions are equal;
+    alpha evaluations, which the kernels skip outside the reach of alpha_min,
+    lie between the walk's counts inside the exact reach and inside the full
+    box, and within 3 % of the former (the reach is widened for rounding)."""
     scene = synth.make_scene(20_000, 31, synth.VOL_C1, d_sem=8)
     cams = [synth.camera_front(256, 192, 240.0), synth.camera_front(200, 150, 190.0)]
     for tile in (8, 16):
@@ -435,14 +485,20 @@ def test_render_counts_match_a_per_pixel_walk(R):
         rast, d, proj, bins, out, T, last = run_forward(R, scene, cams, o)
         counts = R.render_counts(rast.ctx, proj, bins, rast.views, o)
         fwd = O.forward(scene, cams, PT.oracle_opts(o))
-        exp = np.zeros(4)
+        box, reach = np.zeros(4), np.zeros(4)
         for v, cam in enumerate(cams):
-            exp += _expected_counts(fwd["proj"][v], cam, fwd["ids"], fwd["ranges"],
-                                    fwd["offsets"][v], tile, o.alpha_min, o.alpha_max, o.t_min)
-        note(f"counts {counts} expected {exp.tolist()}")
-        assert exp[1] > 0 and exp[0] >= exp[2] >= exp[1]
-        for c, x in zip(counts, exp):
-            assert abs(c - x) <= 1e-4 * x + 2, (counts, exp)
+            b_, r_ = _expected_counts(fwd["proj"][v], cam, fwd["ids"], fwd["ranges"],
+                                      fwd["offsets"][v], tile, o.alpha_min, o.alpha_max, o.t_min)
+            box += b_
+            reach += r_
+        note(f"counts {counts} reach {reach.tolist()} box {box.tolist()}")
+        assert reach[1] > 0 and reach[0] >= reach[2] >= reach[1]
+        assert box[0] > 1.2 * reach[0]              # the cut matters on this scene
+        for q in (1, 3):
+            assert abs(counts[q] - reach[q]) <= 1e-4 * reach[q] + 2, (counts, reach)
+        for q in (0, 2):
+            tol = 1e-4 * reach[q] + 2
+            assert reach[q] - tol <= counts[q] <= min(box[q], 1.03 * reach[q]) + tol, (counts, reach, box)
 
 
 def _truncated_lists(fwd, cams, tile, n, capacity):
