@@ -297,8 +297,14 @@ __device__ __forceinline__ int64_t next_tile(const BlendParams &P, int64_t prev,
 
 // ---- forward ---------------------------------------------------------------------
 
+// Waves per SIMD the forward asks the register allocator for: 7 (the LDS limit
+// of a 256-entry batch at 16 x 16 tiles) where that costs at most a few spills
+// of loop invariants outside the visit loop (C <= 12), none elsewhere.
 template <int TILE, int CP>
-__global__ void __launch_bounds__(TILE *TILE)
+constexpr int fwd_waves() { return TILE == 16 && CP <= 12 ? 7 : 1; }
+
+template <int TILE, int CP>
+__global__ void __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(fwd_waves<TILE, CP>())))
 k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
             uint32_t *__restrict__ last)
 {
