@@ -487,11 +487,23 @@ k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restr
             const uint32_t lo_rel = hi > (uint32_t)B ? hi - (uint32_t)B : 0u;
             const int nb = (int)(hi - lo_rel);
             stage_batch<TILE, CP, NT>(P, ti.v, ti.tile_x0, ti.tile_y0, ti.rs + lo_rel, nb, S);
-            for (int j = nb - 1; j >= 0; --j) {
+            // 64 entries at a time, back to front: lane l tests entry c1 - 1 - l's
+            // box against this wave's block, and only the hits are visited
+            for (int c1 = nb; c1 > 0; c1 -= LEGS_WAVE) {
+              const int jl = c1 - 1 - l;
+              uint32_t pkl = 0;
+              bool hit = false;
+              if (jl >= 0) {
+                  pkl = S.box[jl];
+                  const int x0 = sext8(pkl, 0), x1 = sext8(pkl, 8), y0 = sext8(pkl, 16), y1 = sext8(pkl, 24);
+                  hit = !(x1 < bx0 || x0 > bx0 + Shp::SW - 1 || y1 < by0 || y0 > by0 + Shp::SH - 1);
+              }
+              for (uint64_t rel = legs_ballot(hit); rel; rel &= rel - 1) {
+                const int hl = (int)__builtin_ctzll(rel);           // the lowest lane: the last entry first
+                const int j = c1 - 1 - hl;
                 const uint32_t pos = lo_rel + (uint32_t)j;   // 0-based list position
-                const uint32_t pk = __builtin_amdgcn_readfirstlane(S.box[j]);
+                const uint32_t pk = (uint32_t)__builtin_amdgcn_readlane((int)pkl, hl);
                 const int x0 = sext8(pk, 0), x1 = sext8(pk, 8), y0 = sext8(pk, 16), y1 = sext8(pk, 24);
-                if (x1 < bx0 || x0 > bx0 + Shp::SW - 1 || y1 < by0 || y0 > by0 + Shp::SH - 1) continue;
                 const float4 cn = S.c[j];
                 const float dx = S.qx[j * NQ + qxi] - fx;   // constant over this lane's pixels
                 float fa, fb;
@@ -565,6 +577,7 @@ k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restr
 #pragma unroll
                 for (int r = 0; r < KF; ++r)
                     if (vok[r] && acc[r] != 0.0f) atomicAdd((vgeo[r] ? g2d : dc) + voff[r], acc[r]);
+              }
             }
             hi = lo_rel;
             __syncthreads();
