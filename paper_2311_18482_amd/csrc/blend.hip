@@ -360,7 +360,6 @@ k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
                     if (act == 0) continue;
                     // every lane evaluates (masked lanes would cost the same); only
                     // the pixels of act may blend or stop
-                    const bool mine = __builtin_amdgcn_inverse_ballot_w64(act);   // lane l: bit l of act
                     const int j = c0 + jl;
                     const float4 cn = S.c[j];
                     const float dx = S.qx[j * NQ + qxi] - fx, dy = S.qy[j * NQ + qyi] - fy;
@@ -370,9 +369,12 @@ k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
                     const float alpha = falloff_alpha(a, b, dy, cn.z, cn.w, amax, ep, clamped);
                     const float Tn = T * (1.0f - alpha);
                     // lane masks straight from the compares (predicates 11 = unordered
-                    // or >=, i.e. !(alpha < amin); 4 = ordered <)
-                    donemask |= act & __builtin_amdgcn_fcmpf(alpha, P.amin, 11) & __builtin_amdgcn_fcmpf(Tn, P.tmin, 4);
-                    if (mine && !(alpha < P.amin) && !(Tn < P.tmin)) {
+                    // or >=, i.e. !(alpha < amin); 4 = ordered <): the pixels of act
+                    // that reach alpha_min stop if Tn < t_min and blend otherwise
+                    const uint64_t reach = act & __builtin_amdgcn_fcmpf(alpha, P.amin, 11);
+                    const uint64_t stop = __builtin_amdgcn_fcmpf(Tn, P.tmin, 4);
+                    donemask |= reach & stop;
+                    if (__builtin_amdgcn_inverse_ballot_w64(reach & ~stop)) {
                         const float wgt = alpha * T;
                         const float *cj = S.ch + j * CP;
 #pragma unroll

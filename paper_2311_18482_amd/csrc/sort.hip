@@ -73,8 +73,9 @@ __device__ __forceinline__ uint64_t wave_incl_add(uint64_t x)
 // 1024 values: wave w scans its ROWS * 64 consecutive values as ROWS coalesced
 // rows (all loads in flight together), then adds the sums of the waves before
 // it. ROWS keeps the 64-bit scan within the 128 registers a 1024-thread
-// workgroup allows.
-template <typename T, typename X, typename E, int ROWS = sizeof(T) == 8 ? 8 : 16>
+// workgroup allows; the 32-bit scans (tile and unit counts, a few thousand
+// to tens of thousands) take shorter rounds.
+template <typename T, typename X, typename E, int ROWS = sizeof(T) == 8 ? 8 : 4>
 __device__ __forceinline__ T scan_rounds(int64_t n, X x, E emit)
 {
     constexpr int NW = 1024 / LEGS_WAVE;
@@ -271,8 +272,12 @@ k_histogram(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ coun
 #pragma unroll
             for (int i = 0; i < HIST_RUN; ++i) {
                 const bool ok = wbase + (int64_t)i * LEGS_WAVE + lane < m;
-                for (int p = 0; p < npass; ++p)
-                    hist_add(s_h[p], (uint32_t)(k[i] >> (8 * (first + p))) & 255u, ok);
+                for (int p = 0; p < npass; ++p) {
+                    // the low two bytes of a depth are spread, the higher ones cluster
+                    const uint32_t d = (uint32_t)(k[i] >> (8 * (first + p))) & 255u;
+                    if (first + p >= 2) hist_add(s_h[p], d, ok);
+                    else if (ok) atomicAdd(&s_h[p][d], 1u);
+                }
             }
             continue;
         }
