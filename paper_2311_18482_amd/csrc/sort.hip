@@ -648,13 +648,20 @@ k_coarse_upsweep(const uint32_t *__restrict__ kin, const uint64_t *__restrict__ 
 // counts of the segments before. One workgroup per digit, one thread per
 // segment (nseg <= LEGS_SEG_MAX).
 __global__ void __launch_bounds__(LEGS_SEG_MAX)
-k_seg_scan(const uint32_t *__restrict__ seg_hist, int nseg, const uint32_t *__restrict__ digit_starts,
+k_seg_scan(const uint32_t *__restrict__ seg_hist, int nseg, const uint32_t *__restrict__ hist,
            const uint32_t *__restrict__ desc, int pass, uint32_t *__restrict__ seg_off)
 {
     if (desc[3 + 2 * pass] == 0) return;
     __shared__ uint32_t s_w[LEGS_SEG_MAX / LEGS_WAVE];
+    __shared__ uint32_t s_d[256 / LEGS_WAVE];
     const int d = blockIdx.x, sg = threadIdx.x;
     const int lane = legs_lane(), wave = sg / LEGS_WAVE;
+    if (sg < 256) {   // the digit's global start: the pass's counts of the digits below it
+        uint32_t h = sg < d ? hist[pass * 256 + sg] : 0u;
+#pragma unroll
+        for (int off = LEGS_WAVE / 2; off > 0; off >>= 1) h += __shfl_xor(h, off, LEGS_WAVE);
+        if (lane == 0) s_d[wave] = h;
+    }
     const uint32_t x = sg < nseg ? seg_hist[(int64_t)sg * 256 + d] : 0u;
     uint32_t incl = x;
 #pragma unroll
@@ -664,7 +671,9 @@ k_seg_scan(const uint32_t *__restrict__ seg_hist, int nseg, const uint32_t *__re
     }
     if (lane == LEGS_WAVE - 1) s_w[wave] = incl;
     __syncthreads();
-    uint32_t pre = digit_starts[pass * 256 + d];
+    uint32_t pre = 0;
+#pragma unroll
+    for (int w = 0; w < 256 / LEGS_WAVE; ++w) pre += s_d[w];
     for (int w = 0; w < wave; ++w) pre += s_w[w];
     if (sg < nseg) seg_off[(int64_t)sg * 256 + d] = pre + incl - x;
 }
@@ -1050,12 +1059,17 @@ k_count_lists(int64_t T, CountGrid g0, CountGrid g1, uint32_t *__restrict__ uoff
 // whole id; two passes over the top bits, then the low byte (lists ordered
 // by (low byte, id >> 8), see list_cell); more, even digits from the lowest.
 // The other threads clear the digit histograms and pass counters, the
-// capacity cut (no G-view cut) and the per-view position ranges.
+// capacity cut (no G-view cut) and the per-view position ranges, and every
+// workgroup clears its share of the nclear cell counts at clear.
 __global__ void __launch_bounds__(256)
 k_super_views(const legs_view *__restrict__ views, int n_views, legs_view *__restrict__ sv,
               uint32_t *__restrict__ desc, uint32_t *__restrict__ hist, uint32_t *__restrict__ counters,
-              uint64_t *__restrict__ cut, uint64_t *__restrict__ vrange)
+              uint64_t *__restrict__ cut, uint64_t *__restrict__ vrange, uint32_t *__restrict__ clear,
+              int64_t nclear)
 {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nclear; i += (int64_t)gridDim.x * 256)
+        clear[i] = 0u;
+    if (blockIdx.x != 0) return;
     for (int i = threadIdx.x; i < LEGS_SORT_MAX_PASSES * 256; i += 256) hist[i] = 0u;
     for (int i = threadIdx.x; i < 2 * n_views; i += 256) vrange[i] = 0u;
     if (threadIdx.x < 16) counters[threadIdx.x] = 0u;
@@ -1568,8 +1582,10 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
         ccount = reinterpret_cast<uint64_t *>(ord + OL.ccount);
         uint64_t *vrange = reinterpret_cast<uint64_t *>(ord + OL.vrange);
         sviews = reinterpret_cast<legs_view *>(ord + OL.sviews);
-        hipLaunchKernelGGL(k_super_views, dim3(1), dim3(256), 0, s, views, n_views, sviews, S.desc, S.hist,
-                           S.counters, S.cut, vrange);
+        // also clears both grids' cell counts (adjacent) for the counting below
+        const int64_t nclear = (int64_t)(S.scount - S.tcount) + total_tiles;
+        hipLaunchKernelGGL(k_super_views, dim3(grid_for(ctx, nclear, 256, 8)), dim3(256), 0, s, views, n_views,
+                           sviews, S.desc, S.hist, S.counters, S.cut, vrange, S.tcount, nclear);
         if (nblocks > 0)
             hipLaunchKernelGGL(k_sorted_records, dim3((unsigned)nblocks), dim3(LEGS_PROJ_BLOCK), 0, s,
                                perm, (gpass % 2 == 0) ? ok0 : ok1,
@@ -1639,9 +1655,6 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     //    passes, and the G-view the tile cut falls in
     CountGrid cg0{views, S.tcount, S.partial, bins->ranges, nullptr, nullptr};
     CountGrid cg1{sviews, S.scount, S.spartial, S.cranges, S.desc, S.hist};
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(ctx, 2 * T, 256, 8)), dim3(256), 0, s, S.tcount,
-                       (int64_t)(S.scount - S.tcount) + T, 0u);
-    LEGS_CHECK_LAUNCH(ctx);
     hipLaunchKernelGGL(k_count_corners, dim3((unsigned)nch, (unsigned)n_views), dim3(256), 0, s, frecs, crecs,
                        offsets, coffsets, vrange, OL.G, bins->capacity, S.ccap, T, bins->count, ccount, cg0, cg1,
                        S.cut);
@@ -1654,8 +1667,6 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     // passes for the most super-tiles there can be (one per tile); the ones
     // the actual count does not need return at once
     const int cpasses = (bits_for(T) + 7) / 8 > 0 ? (bits_for(T) + 7) / 8 : 1;
-    hipLaunchKernelGGL(k_digit_starts, dim3(cpasses), dim3(256), 0, s, S.hist, S.starts, 0);
-    LEGS_CHECK_LAUNCH(ctx);
 
     // 4. coarse passes: the (super-tile, position) pairs written out in stream
     //    order, then stable counting passes over the super-tile digits; pass p
@@ -1674,7 +1685,7 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
         const int wo = p % 2, ri = 1 - wo;
         hipLaunchKernelGGL(k_coarse_upsweep, dim3(nseg), dim3(LEGS_SORT_THREADS), 0, s, ck[ri], ccount, S.ccap,
                            S.desc, p, S.seg_hist);
-        hipLaunchKernelGGL(k_seg_scan, dim3(256), dim3(LEGS_SEG_MAX), 0, s, S.seg_hist, nseg, S.starts, S.desc,
+        hipLaunchKernelGGL(k_seg_scan, dim3(256), dim3(LEGS_SEG_MAX), 0, s, S.seg_hist, nseg, S.hist, S.desc,
                            p, S.seg_off);
         hipLaunchKernelGGL((k_onesweep<uint32_t, true>), dim3(nseg), dim3(LEGS_SORT_THREADS), 0, s, ck[ri], cv[ri],
                            ck[wo], cv[wo], ccount, S.ccap, p, 0, 0, S.desc, S.starts, nullptr, nullptr, P,
