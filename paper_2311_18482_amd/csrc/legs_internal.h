@@ -78,7 +78,6 @@ int32_t legs_launch_blend_counts(legs_ctx *ctx, const legs_projected *proj, int6
 // Sort scratch layout (bytes), shared by the sizing function and the launcher.
 struct legs_sort_layout {
     int64_t hist_off;      // uint32 [8][256] digit histograms
-    int64_t start_off;     // uint32 [8][256] exclusive digit starts
     int64_t counter_off;   // uint32 [64] partition counters per pass, blend tile counters
     int64_t status_off;    // uint64 [8][parts][256] look-back status words
     int64_t parts;         // partitions at full capacity

@@ -304,27 +304,6 @@ k_histogram(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ coun
     }
 }
 
-// Exclusive scan of each pass's 256 digit counts (one workgroup per pass).
-__global__ void __launch_bounds__(256)
-k_digit_starts(const uint32_t *__restrict__ hist, uint32_t *__restrict__ starts, int first)
-{
-    const int p = first + blockIdx.x, d = threadIdx.x;
-    const int lane = legs_lane(), wave = d / LEGS_WAVE;
-    const uint32_t x = hist[p * 256 + d];
-    uint32_t incl = x;
-#pragma unroll
-    for (int off = 1; off < LEGS_WAVE; off <<= 1) {
-        const uint32_t y = __shfl_up(incl, off, LEGS_WAVE);
-        if (lane >= off) incl += y;
-    }
-    __shared__ uint32_t s_w[4];
-    if (lane == LEGS_WAVE - 1) s_w[wave] = incl;
-    __syncthreads();
-    uint32_t pre = 0;
-    for (int w = 0; w < wave; ++w) pre += s_w[w];
-    starts[p * 256 + d] = pre + incl - x;
-}
-
 // Zero the look-back status words of every pass and the partition counters,
 // only as far as the partitions this count needs.
 __global__ void __launch_bounds__(256)
@@ -411,7 +390,7 @@ template <typename K, bool SEG>
 __global__ void __launch_bounds__(LEGS_SORT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__restrict__ kout,
            uint32_t *__restrict__ vout, const uint64_t *__restrict__ count, int64_t capacity, int pass,
-           int shift, int rb, const uint32_t *__restrict__ desc, const uint32_t *__restrict__ digit_starts,
+           int shift, int rb, const uint32_t *__restrict__ desc, const uint32_t *__restrict__ digit_hist,
            uint64_t *__restrict__ status, uint32_t *__restrict__ counter, CoarsePay P,
            const uint32_t *__restrict__ seg_off)
 {
@@ -432,7 +411,6 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__res
     __shared__ uint32_t s_lstart[256];      // block-local start of each digit
     __shared__ uint64_t s_gstart[257];      // global position of LDS slot 0 of each digit
     __shared__ uint32_t s_tmp[NW];
-    __shared__ uint64_t s_w64[NW];
     __shared__ int64_t s_part;
 
     const uint64_t cnt = *count;
@@ -448,6 +426,24 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__res
     if constexpr (SEG) {
         per = (parts + gridDim.x - 1) / gridDim.x;
         if (tid < 256) s_run[tid] = seg_off[(int64_t)blockIdx.x * 256 + tid];
+    }
+    // look-back: the global start of every digit, an exclusive scan of the
+    // pass's digit counts
+    __shared__ uint32_t s_dstart[SEG ? 1 : 256];
+    if constexpr (!SEG) {
+        uint32_t h = 0, incl = 0;
+        if (tid < 256) {
+            h = digit_hist[pass * 256 + tid];
+            incl = wave_incl_add(h);
+            if (lane == LEGS_WAVE - 1) s_tmp[wave] = incl;
+        }
+        __syncthreads();
+        if (tid < 256) {
+            uint32_t pre = 0;
+            for (int w = 0; w < wave; ++w) pre += s_tmp[w];
+            s_dstart[tid] = pre + incl - h;
+        }
+        __syncthreads();
     }
     for (;;) {
         if constexpr (SEG) {
@@ -579,7 +575,7 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__res
                 }
                 st_status(status + part * 256 + d, FLAG_INC | (excl + t));
             }
-            s_gstart[d] = (uint64_t)digit_starts[pass * 256 + d] + excl - (uint64_t)lstart;
+            s_gstart[d] = (uint64_t)s_dstart[d] + excl - (uint64_t)lstart;
         }
         __syncthreads();
         // write out digit runs: consecutive lanes, consecutive addresses (positions
@@ -1382,8 +1378,7 @@ legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles)
     const int64_t parts = (capacity + LEGS_SORT_PART - 1) / LEGS_SORT_PART;
     L.parts = parts > 0 ? parts : 1;
     L.hist_off = 0;
-    L.start_off = L.hist_off + 4 * LEGS_SORT_MAX_PASSES * 256;
-    L.counter_off = L.start_off + 4 * LEGS_SORT_MAX_PASSES * 256;
+    L.counter_off = L.hist_off + 4 * LEGS_SORT_MAX_PASSES * 256;
     L.status_off = L.counter_off + 256;  // 64 counters
     int64_t o = up(L.status_off + 8 * (int64_t)LEGS_SORT_MAX_PASSES * L.parts * 256);
     const int64_t T = total_tiles > 0 ? total_tiles : 0;   // the G-view sort needs none of these
@@ -1417,7 +1412,7 @@ static int grid_for(legs_ctx *ctx, int64_t work, int per_block, int waves_per_cu
 namespace {
 
 struct SortScratch {
-    uint32_t *hist, *starts, *counters;
+    uint32_t *hist, *counters;
     uint64_t *status;
     int64_t parts;
     // depth-first binning
@@ -1436,7 +1431,6 @@ SortScratch sort_scratch_at(void *base, int64_t capacity, int64_t total_tiles = 
     auto u64 = [b](int64_t off) { return reinterpret_cast<uint64_t *>(b + off); };
     SortScratch S;
     S.hist = u32(L.hist_off);
-    S.starts = u32(L.start_off);
     S.counters = u32(L.counter_off);
     S.status = u64(L.status_off);
     S.parts = L.parts;
@@ -1477,14 +1471,13 @@ int32_t radix_passes(legs_ctx *ctx, const SortScratch &S, uint64_t *k0, uint32_t
     else
         hipLaunchKernelGGL(k_histogram<false>, dim3(ghist), dim3(256), 0, s, k0, count, capacity, first, np,
                            S.hist);
-    hipLaunchKernelGGL(k_digit_starts, dim3(np), dim3(256), 0, s, S.hist, S.starts, first);
     LEGS_CHECK_LAUNCH(ctx);
     const int gsort = grid_for(ctx, capacity, LEGS_SORT_PART, 2);
     uint64_t *ka = k0, *kb = k1;
     uint32_t *va = v0, *vb = v1;
     for (int p = first; p < last; ++p) {
         hipLaunchKernelGGL((k_onesweep<uint64_t, false>), dim3(gsort), dim3(LEGS_SORT_THREADS), 0, s,
-                           ka, va, kb, vb, count, capacity, p, 8 * p, 8, nullptr, S.starts,
+                           ka, va, kb, vb, count, capacity, p, 8 * p, 8, nullptr, S.hist,
                            S.status + (int64_t)(p - first) * S.parts * 256, S.counters + (p - first),
                            CoarsePay{}, nullptr);
         LEGS_CHECK_LAUNCH(ctx);
@@ -1688,7 +1681,7 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
         hipLaunchKernelGGL(k_seg_scan, dim3(256), dim3(LEGS_SEG_MAX), 0, s, S.seg_hist, nseg, S.hist, S.desc,
                            p, S.seg_off);
         hipLaunchKernelGGL((k_onesweep<uint32_t, true>), dim3(nseg), dim3(LEGS_SORT_THREADS), 0, s, ck[ri], cv[ri],
-                           ck[wo], cv[wo], ccount, S.ccap, p, 0, 0, S.desc, S.starts, nullptr, nullptr, P,
+                           ck[wo], cv[wo], ccount, S.ccap, p, 0, 0, S.desc, nullptr, nullptr, nullptr, P,
                            S.seg_off);
         LEGS_CHECK_LAUNCH(ctx);
     }
