@@ -239,15 +239,14 @@ __device__ __forceinline__ void hist_add(uint32_t *h, uint32_t d, bool ok)
     if (legs_lane() == lead) atomicAdd(&h[d0], (uint32_t)__popcll(same));
 }
 
-// Digit histograms of passes [first, first + npass) in one read of the keys.
-// Loads are coalesced (lane l reads key base + 64 i + l). RUNS: within each
-// wave a run of equal digits in consecutive lanes is counted with one LDS
-// atomic by its first lane (run starts from a ballot); instance keys come in
-// long runs (every tile of one Gaussian shares its depth digits, consecutive
-// tiles of a row share the high tile digits), so hot digits do not serialise.
-// Without RUNS (keys in no particular order, e.g. the G-view depth keys) the
-// keys of a lane are loaded at once and counted with hist_add.
-template <bool RUNS>
+// Digit histograms of passes [first, first + npass) in one read of the
+// instance keys. Loads are coalesced (lane l reads key base + 64 i + l).
+// Within each wave a run of equal digits in consecutive lanes is counted with
+// one LDS atomic by its first lane (run starts from a ballot); instance keys
+// come in long runs (every tile of one Gaussian shares its depth digits,
+// consecutive tiles of a row share the high tile digits), so hot digits do not
+// serialise. (The G-view depth keys are counted where they are made, in
+// k_order_keys.)
 __global__ void __launch_bounds__(256)
 k_histogram(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ count,
             int64_t capacity, int first, int npass, uint32_t *__restrict__ hist)
@@ -262,25 +261,6 @@ k_histogram(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ coun
     const int64_t chunk = (int64_t)256 * HIST_RUN;
     for (int64_t base = (int64_t)blockIdx.x * chunk; base < m; base += (int64_t)gridDim.x * chunk) {
         const int64_t wbase = base + (int64_t)wave * LEGS_WAVE * HIST_RUN;
-        if constexpr (!RUNS) {
-            uint64_t k[HIST_RUN];
-#pragma unroll
-            for (int i = 0; i < HIST_RUN; ++i) {
-                const int64_t idx = wbase + (int64_t)i * LEGS_WAVE + lane;
-                k[i] = idx < m ? keys[idx] : 0ull;
-            }
-#pragma unroll
-            for (int i = 0; i < HIST_RUN; ++i) {
-                const bool ok = wbase + (int64_t)i * LEGS_WAVE + lane < m;
-                for (int p = 0; p < npass; ++p) {
-                    // the low two bytes of a depth are spread, the higher ones cluster
-                    const uint32_t d = (uint32_t)(k[i] >> (8 * (first + p))) & 255u;
-                    if (first + p >= 2) hist_add(s_h[p], d, ok);
-                    else if (ok) atomicAdd(&s_h[p][d], 1u);
-                }
-            }
-            continue;
-        }
         for (int i = 0; i < HIST_RUN; ++i) {
             const int64_t idx = wbase + (int64_t)i * LEGS_WAVE + lane;
             const bool ok = idx < m;
@@ -311,7 +291,7 @@ k_sort_clear(uint64_t *__restrict__ status, int64_t parts_cap, int passes,
              uint32_t *__restrict__ counters, uint32_t *__restrict__ hist,
              const uint64_t *__restrict__ count, int64_t capacity)
 {
-    const uint64_t cnt = *count;
+    const uint64_t cnt = count ? *count : (uint64_t)capacity;   // NULL: the count is not known yet
     const int64_t m = (int64_t)(cnt < (uint64_t)capacity ? cnt : (uint64_t)capacity);
     const int64_t parts = (m + LEGS_SORT_PART - 1) / LEGS_SORT_PART;
     const int64_t per_pass = parts * 256;
@@ -677,18 +657,55 @@ k_seg_scan(const uint32_t *__restrict__ seg_hist, int nseg, const uint32_t *__re
 // ---- depth order of the G-views ---------------------------------------------------
 
 // key = (view << 32) | bits(depth) for visible G-views (culled ones sort last,
-// they emit nothing); value = G-view index. Also stores G for the sort.
+// they emit nothing); value = G-view index. Also stores G for the sort and
+// counts the digit histograms of its npass passes into hist (cleared before):
+// each workgroup takes chunks of HIST_RUN rows of 256 G-views, loads a
+// chunk's inputs at once, counts in LDS (hist_add for the clustered digits)
+// and flushes its counts once.
 __global__ void __launch_bounds__(256)
 k_order_keys(const uint32_t *__restrict__ ntiles, const float *__restrict__ depth, int64_t n,
              int64_t G, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-             uint64_t *__restrict__ gcount)
+             uint64_t *__restrict__ gcount, int npass, uint32_t *__restrict__ hist)
 {
-    const int64_t gv = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (gv == 0) *gcount = (uint64_t)G;
-    if (gv >= G) return;
-    const uint64_t v = (uint64_t)(gv / n);
-    keys[gv] = ntiles[gv] ? ((v << 32) | __float_as_uint(depth[gv])) : ~0ull;
-    vals[gv] = (uint32_t)gv;
+    __shared__ uint32_t s_h[LEGS_SORT_MAX_PASSES][256];
+    for (int i = threadIdx.x; i < LEGS_SORT_MAX_PASSES * 256; i += 256) (&s_h[0][0])[i] = 0;
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) *gcount = (uint64_t)G;
+    const bool narrow = G <= (int64_t)0xffffffffll;
+    const int64_t chunk = (int64_t)256 * HIST_RUN;
+    for (int64_t base = (int64_t)blockIdx.x * chunk; base < G; base += (int64_t)gridDim.x * chunk) {
+        uint32_t nt[HIST_RUN];
+        float dp[HIST_RUN];
+#pragma unroll
+        for (int i = 0; i < HIST_RUN; ++i) {
+            const int64_t gv = base + 256 * i + threadIdx.x;
+            nt[i] = gv < G ? ntiles[gv] : 0u;
+            dp[i] = gv < G ? depth[gv] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < HIST_RUN; ++i) {
+            const int64_t gv = base + 256 * i + threadIdx.x;
+            const bool ok = gv < G;
+            uint64_t key = ~0ull;
+            if (ok) {
+                const uint64_t v = narrow ? (uint64_t)((uint32_t)gv / (uint32_t)n) : (uint64_t)(gv / n);
+                if (nt[i]) key = (v << 32) | __float_as_uint(dp[i]);
+                keys[gv] = key;
+                vals[gv] = (uint32_t)gv;
+            }
+            for (int p = 0; p < npass; ++p) {
+                // the low two bytes of a depth are spread, the higher ones cluster
+                const uint32_t d = (uint32_t)(key >> (8 * p)) & 255u;
+                if (p >= 2) hist_add(s_h[p], d, ok);
+                else if (ok) atomicAdd(&s_h[p][d], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < npass * 256; i += 256) {
+        const uint32_t c = (&s_h[0][0])[i];
+        if (c) atomicAdd(&hist[i], c);
+    }
 }
 
 // Super-tile edge in tiles: 8 x 4 tiles, one bit each of a 32-bit mask.
@@ -1454,24 +1471,22 @@ SortScratch sort_scratch_at(void *base, int64_t capacity, int64_t total_tiles = 
 
 // LSD onesweep passes over digits [first, last) of (key, value) pairs; the
 // input is in (k0, v0) and the buffers ping-pong, so the result ends in
-// (k0, v0) when last - first is even and in (k1, v1) otherwise.
+// (k0, v0) when last - first is even and in (k1, v1) otherwise. Unless
+// prepared, the scratch is cleared and the digits counted here first.
 int32_t radix_passes(legs_ctx *ctx, const SortScratch &S, uint64_t *k0, uint32_t *v0,
                      uint64_t *k1, uint32_t *v1, const uint64_t *count, int64_t capacity,
-                     int first, int last, bool runs, hipStream_t s)
+                     int first, int last, bool prepared, hipStream_t s)
 {
     const int np = last - first;
     if (np <= 0) return LEGS_OK;
-    const int gclear = grid_for(ctx, S.parts * 256 * np, 256, 8);
-    hipLaunchKernelGGL(k_sort_clear, dim3(gclear), dim3(256), 0, s, S.status, S.parts, np,
-                       S.counters, S.hist, count, capacity);
-    const int ghist = grid_for(ctx, capacity, 256 * HIST_RUN, 4);
-    if (runs)
-        hipLaunchKernelGGL(k_histogram<true>, dim3(ghist), dim3(256), 0, s, k0, count, capacity, first, np,
-                           S.hist);
-    else
-        hipLaunchKernelGGL(k_histogram<false>, dim3(ghist), dim3(256), 0, s, k0, count, capacity, first, np,
-                           S.hist);
-    LEGS_CHECK_LAUNCH(ctx);
+    if (!prepared) {   // prepared: the caller cleared the scratch and counted the digits
+        const int gclear = grid_for(ctx, S.parts * 256 * np, 256, 8);
+        hipLaunchKernelGGL(k_sort_clear, dim3(gclear), dim3(256), 0, s, S.status, S.parts, np,
+                           S.counters, S.hist, count, capacity);
+        const int ghist = grid_for(ctx, capacity, 256 * HIST_RUN, 4);
+        hipLaunchKernelGGL(k_histogram, dim3(ghist), dim3(256), 0, s, k0, count, capacity, first, np, S.hist);
+        LEGS_CHECK_LAUNCH(ctx);
+    }
     const int gsort = grid_for(ctx, capacity, LEGS_SORT_PART, 2);
     uint64_t *ka = k0, *kb = k1;
     uint32_t *va = v0, *vb = v1;
@@ -1556,14 +1571,17 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
         uint64_t *ok0 = reinterpret_cast<uint64_t *>(ord + OL.k0), *ok1 = reinterpret_cast<uint64_t *>(ord + OL.k1);
         uint32_t *ov0 = reinterpret_cast<uint32_t *>(ord + OL.v0), *ov1 = reinterpret_cast<uint32_t *>(ord + OL.v1);
         uint64_t *gcount = reinterpret_cast<uint64_t *>(ord + OL.gcount);
-        if (OL.G > 0)
-            hipLaunchKernelGGL(k_order_keys, dim3((unsigned)((OL.G + 255) / 256)), dim3(256), 0, s,
-                               proj->ntiles, proj->depth, n, OL.G, ok0, ov0, gcount);
-        LEGS_CHECK_LAUNCH(ctx);
         const int gpass = (32 + bits_for(n_views) + 7) / 8;
         if (OL.G > 0) {
-            const int32_t r = radix_passes(ctx, sort_scratch_at(ord + OL.sort, OL.G), ok0, ov0, ok1, ov1,
-                                           gcount, OL.G, 0, gpass, false, s);
+            // clear the sort scratch for every G-view, then the keys with their
+            // digit counts, then the passes
+            const SortScratch GS = sort_scratch_at(ord + OL.sort, OL.G);
+            hipLaunchKernelGGL(k_sort_clear, dim3(grid_for(ctx, GS.parts * 256 * gpass, 256, 8)), dim3(256), 0, s,
+                               GS.status, GS.parts, gpass, GS.counters, GS.hist, nullptr, OL.G);
+            hipLaunchKernelGGL(k_order_keys, dim3(grid_for(ctx, OL.G, 256 * HIST_RUN, 4)), dim3(256), 0, s,
+                               proj->ntiles, proj->depth, n, OL.G, ok0, ov0, gcount, gpass, GS.hist);
+            LEGS_CHECK_LAUNCH(ctx);
+            const int32_t r = radix_passes(ctx, GS, ok0, ov0, ok1, ov1, gcount, OL.G, 0, gpass, true, s);
             if (r != LEGS_OK) return r;
         }
         perm = (gpass % 2 == 0) ? ov0 : ov1;
@@ -1621,7 +1639,7 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
             LEGS_CHECK_LAUNCH(ctx);
         }
         const int32_t r = radix_passes(ctx, S, k0, v0, k1, v1, bins->count, bins->capacity, 0,
-                                       passes, true, s);
+                                       passes, false, s);
         if (r != LEGS_OK) return r;
         const int gfill = grid_for(ctx, 2 * total_tiles, 256, 8);
         hipLaunchKernelGGL(k_fill_u32, dim3(gfill), dim3(256), 0, s, bins->ranges, 2 * total_tiles, 0u);
