@@ -297,30 +297,37 @@ __device__ __forceinline__ int64_t next_tile(const BlendParams &P, int64_t prev,
 
 // ---- forward ---------------------------------------------------------------------
 
-// Waves per SIMD the forward asks the register allocator for: 7 (the LDS limit
-// of a 256-entry batch at 16 x 16 tiles) where that costs at most a few spills
-// of loop invariants outside the visit loop (C <= 12), none elsewhere.
-template <int TILE, int CP>
-constexpr int fwd_waves() { return TILE == 16 && CP <= 12 ? 7 : 1; }
+// Waves per SIMD the forward asks the register allocator for, with up to 12
+// channels and 256-thread workgroups: the LDS limit of a 256-entry batch (7 at
+// 16 x 16 tiles, 6 for the 16 x 16 parts of 32 x 32 tiles), which costs at
+// most a few spills of loop invariants outside the visit loop; none elsewhere.
+template <int TILE, int CP, int SUB>
+constexpr int fwd_waves() { return SUB != 16 || CP > 12 ? 1 : (TILE == 16 ? 7 : 6); }
 
-template <int TILE, int CP>
-__global__ void __launch_bounds__(TILE *TILE) __attribute__((amdgpu_waves_per_eu(fwd_waves<TILE, CP>())))
+// SUB < TILE: each workgroup composites one SUB x SUB part of a tile over the
+// whole tile's list (one workgroup per part, one-per-tile launches only), so
+// a part stops as soon as its own pixels are done.
+template <int TILE, int CP, int SUB>
+__global__ void __launch_bounds__(SUB *SUB) __attribute__((amdgpu_waves_per_eu(fwd_waves<TILE, CP, SUB>())))
 k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
             uint32_t *__restrict__ last)
 {
-    constexpr int NT = TILE * TILE, NQ = TILE / 8;
+    constexpr int NT = SUB * SUB, NQ = TILE / 8, NS = TILE / SUB, QS = SUB / 8;
+    static_assert(NS * SUB == TILE, "parts tile the tile");
     extern __shared__ float4 s_dyn[];
     Stage<TILE, CP> S(s_dyn, P.batch);
     __shared__ int64_t s_tile;
     const int B = P.batch;
     const float amax = P.amax;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / LEGS_WAVE), l = threadIdx.x % LEGS_WAVE;
-    const int qxi = w % NQ, qyi = w / NQ;            // this wave's 8 x 8 quadrant
+    const int part = NS == 1 ? 0 : (int)(blockIdx.x % (NS * NS));
+    const int qxi = (part % NS) * QS + w % QS, qyi = (part / NS) * QS + w / QS;   // this wave's 8 x 8 quadrant
     const int qx0 = 8 * qxi, qy0 = 8 * qyi;
     const int lx = qx0 + (l & 7), ly = qy0 + (l >> 3);
     const float fx = (float)(l & 7), fy = (float)(l >> 3);
 
-    for (int64_t tile = next_tile(P, -1, &s_tile); tile < P.total_tiles; tile = next_tile(P, tile, &s_tile)) {
+    for (int64_t tile = NS == 1 ? next_tile(P, -1, &s_tile) : (int64_t)(blockIdx.x / (NS * NS));
+         tile < P.total_tiles; tile = NS == 1 ? next_tile(P, tile, &s_tile) : P.total_tiles) {
         const TileInfo ti = tile_info<TILE>(P, tile);
         const int px = ti.tile_x0 + lx, py = ti.tile_y0 + ly;
         const bool inside = px < ti.W && py < ti.H;
@@ -664,7 +671,11 @@ int32_t launch_tile_cp(legs_ctx *ctx, bool fwd, const BlendParams &P0, float *ou
     if (lds > 65536) return legs_set_error(ctx, LEGS_ERR_UNSUPPORTED, "LDS batch too large for C");
     int64_t grid = P.total_tiles;
     if (grid <= 0) return LEGS_OK;
-    const int threads = fwd ? TILE * TILE : BwdShape<TILE, CP>::NT;
+    // one-per-tile forward launches at 32-pixel tiles run a workgroup per 16 x 16 part
+    constexpr int SUB = TILE == 32 ? 16 : TILE;
+    const bool parts = fwd && SUB < TILE && !P.counter;
+    const int threads = fwd ? (parts ? SUB * SUB : TILE * TILE) : BwdShape<TILE, CP>::NT;
+    if (parts) grid *= (TILE / SUB) * (TILE / SUB);
     if (P.counter) {
         // enough workgroups to fill every CU several times; each loops over tiles
         const int64_t per_cu = threads >= 1024 ? 2 : (threads >= 256 ? 6 : 12);
@@ -672,8 +683,11 @@ int32_t launch_tile_cp(legs_ctx *ctx, bool fwd, const BlendParams &P0, float *ou
         grid = grid < cap ? grid : cap;
         hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, P.counter);
     }
-    if (fwd) {
-        hipLaunchKernelGGL((k_blend_fwd<TILE, CP>), dim3((unsigned)grid), dim3(threads), lds, s,
+    if (parts) {
+        hipLaunchKernelGGL((k_blend_fwd<TILE, CP, SUB>), dim3((unsigned)grid), dim3(threads), lds, s,
+                           P, out, Tf, last);
+    } else if (fwd) {
+        hipLaunchKernelGGL((k_blend_fwd<TILE, CP, TILE>), dim3((unsigned)grid), dim3(threads), lds, s,
                            P, out, Tf, last);
     } else {
         hipLaunchKernelGGL((k_blend_bwd<TILE, CP>), dim3((unsigned)grid), dim3(threads), lds, s,
