@@ -194,7 +194,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="1m_1080p")
-    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--tile", type=int, default=32)
     ap.add_argument("--lds-batch", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-decode", action="store_true", help="skip the learned-vs-plain decode leg")
