@@ -947,7 +947,7 @@ k_count_merge(int nch, int64_t T, int n_views, CountGrid g0, CountGrid g1)
         const int64_t ncell = (int64_t)vw.tiles_x * vw.tiles_y;
         if (ncell > (sup ? SUPER_LDS_CELLS : TILE_LDS_CELLS) || t - vw.tile_offset >= ncell) continue;
         uint32_t acc = 0;
-#pragma unroll 4
+#pragma unroll 8
         for (int c = blockIdx.y; c < nch; c += gridDim.y) acc += cg.partial[(int64_t)c * T + t];
         if (acc) atomicAdd(cg.count + t, acc);
     }
@@ -1669,7 +1669,7 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     hipLaunchKernelGGL(k_count_corners, dim3((unsigned)nch, (unsigned)n_views), dim3(256), 0, s, frecs, crecs,
                        offsets, coffsets, vrange, OL.G, bins->capacity, S.ccap, T, bins->count, ccount, cg0, cg1,
                        S.cut);
-    hipLaunchKernelGGL(k_count_merge, dim3((unsigned)((2 * T + 255) / 256), 8), dim3(256), 0, s, nch, T, n_views,
+    hipLaunchKernelGGL(k_count_merge, dim3((unsigned)((2 * T + 255) / 256), 32), dim3(256), 0, s, nch, T, n_views,
                        cg0, cg1);
     hipLaunchKernelGGL(k_count_rows, dim3(64, (unsigned)n_views, 2), dim3(256), 0, s, cg0, cg1);
     hipLaunchKernelGGL(k_count_cols, dim3(64, (unsigned)n_views, 2), dim3(256), 0, s, cg0, cg1);
