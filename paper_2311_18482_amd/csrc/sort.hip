@@ -953,52 +953,34 @@ k_count_merge(int nch, int64_t T, int n_views, CountGrid g0, CountGrid g1)
     }
 }
 
-// Inclusive prefix sums along the rows of view blockIdx.y of grid blockIdx.z:
-// one wave per row.
-__global__ void __launch_bounds__(256)
-k_count_rows(CountGrid g0, CountGrid g1)
+// Row, then column inclusive prefix sums of the difference grid of view
+// blockIdx.x in grid blockIdx.y (one workgroup per view and grid, a wave per
+// row or column), which turns the corner counts into per-cell counts.
+__global__ void __launch_bounds__(1024)
+k_count_prefix(CountGrid g0, CountGrid g1)
 {
-    const CountGrid &cg = blockIdx.z ? g1 : g0;
-    const legs_view vw = cg.views[blockIdx.y];
-    const int lane = legs_lane();
-    const int row0 = blockIdx.x * 4 + (int)(threadIdx.x / LEGS_WAVE);
-    for (int y = row0; y < vw.tiles_y; y += gridDim.x * 4) {
-        uint32_t *r = cg.count + vw.tile_offset + (int64_t)y * vw.tiles_x;
+    const CountGrid &cg = blockIdx.y ? g1 : g0;
+    const legs_view vw = cg.views[blockIdx.x];
+    const int lane = legs_lane(), wave = (int)(threadIdx.x / LEGS_WAVE);
+    constexpr int NW = 1024 / LEGS_WAVE;
+    uint32_t *base = cg.count + vw.tile_offset;
+    for (int y = wave; y < vw.tiles_y; y += NW) {
+        uint32_t *r = base + (int64_t)y * vw.tiles_x;
         uint32_t carry = 0;
         for (int x0 = 0; x0 < vw.tiles_x; x0 += LEGS_WAVE) {
             const int x = x0 + lane;
-            uint32_t incl = x < vw.tiles_x ? r[x] : 0u;
-#pragma unroll
-            for (int off = 1; off < LEGS_WAVE; off <<= 1) {
-                const uint32_t t = __shfl_up(incl, off, LEGS_WAVE);
-                if (lane >= off) incl += t;
-            }
+            uint32_t incl = wave_incl_add(x < vw.tiles_x ? r[x] : 0u);
             if (x < vw.tiles_x) r[x] = carry + incl;
             carry += (uint32_t)__shfl((int)incl, LEGS_WAVE - 1, LEGS_WAVE);
         }
     }
-}
-
-// Inclusive prefix sums down the columns of view blockIdx.y of grid
-// blockIdx.z: one wave per column, 64 rows at a time.
-__global__ void __launch_bounds__(256)
-k_count_cols(CountGrid g0, CountGrid g1)
-{
-    const CountGrid &cg = blockIdx.z ? g1 : g0;
-    const legs_view vw = cg.views[blockIdx.y];
-    const int lane = legs_lane();
-    const int col0 = blockIdx.x * 4 + (int)(threadIdx.x / LEGS_WAVE);
-    for (int x = col0; x < vw.tiles_x; x += gridDim.x * 4) {
-        uint32_t *col = cg.count + vw.tile_offset + x;
+    __syncthreads();   // the rows are done (and visible to the workgroup)
+    for (int x = wave; x < vw.tiles_x; x += NW) {
+        uint32_t *col = base + x;
         uint32_t carry = 0;
         for (int y0 = 0; y0 < vw.tiles_y; y0 += LEGS_WAVE) {
             const int y = y0 + lane;
-            uint32_t incl = y < vw.tiles_y ? col[(int64_t)y * vw.tiles_x] : 0u;
-#pragma unroll
-            for (int off = 1; off < LEGS_WAVE; off <<= 1) {
-                const uint32_t t = __shfl_up(incl, off, LEGS_WAVE);
-                if (lane >= off) incl += t;
-            }
+            uint32_t incl = wave_incl_add(y < vw.tiles_y ? col[(int64_t)y * vw.tiles_x] : 0u);
             if (y < vw.tiles_y) col[(int64_t)y * vw.tiles_x] = carry + incl;
             carry += (uint32_t)__shfl((int)incl, LEGS_WAVE - 1, LEGS_WAVE);
         }
@@ -1671,8 +1653,7 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
                        S.cut);
     hipLaunchKernelGGL(k_count_merge, dim3((unsigned)((2 * T + 255) / 256), 32), dim3(256), 0, s, nch, T, n_views,
                        cg0, cg1);
-    hipLaunchKernelGGL(k_count_rows, dim3(64, (unsigned)n_views, 2), dim3(256), 0, s, cg0, cg1);
-    hipLaunchKernelGGL(k_count_cols, dim3(64, (unsigned)n_views, 2), dim3(256), 0, s, cg0, cg1);
+    hipLaunchKernelGGL(k_count_prefix, dim3((unsigned)n_views, 2), dim3(1024), 0, s, cg0, cg1);
     hipLaunchKernelGGL(k_count_lists, dim3(3), dim3(1024), 0, s, T, cg0, cg1, S.uoff);
     LEGS_CHECK_LAUNCH(ctx);
     // passes for the most super-tiles there can be (one per tile); the ones
