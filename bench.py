@@ -208,7 +208,7 @@ def main():
                          "the reference dispatch that scales FETCH_SIZE / WRITE_SIZE to bytes")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the rasteriser would shard by view with one gradient all-reduce).", file=sys.stderr)
         sys.exit(2)
 

@@ -42,7 +42,7 @@ extern "C" {
 #define LEGS_ERR_ARG (-1)         /* invalid argument; nothing launched */
 #define LEGS_ERR_CAPACITY (-2)    /* instance list longer than its buffers */
 #define LEGS_ERR_HIP (-3)         /* a HIP runtime call failed */
-#define LEGS_ERR_UNSUPPORTED (-4) /* valid request this build does not serve */
+#define LEGS_ERR_UNSUPPORTED (-4) /* valid request the library does not serve */
 
 #define LEGS_MAX_CHANNELS 64
 #define LEGS_MAX_VIEWS 4096
