@@ -163,20 +163,76 @@ def decode_leg(log_fn, epochs=200):
                 ms=ms)
 
 
-def cpu_baseline(scene, cams, tile, budget_s=30.0):
+def _oracle_step(O, scene, cams, oo, G):
+    """One forward + backward of the oracle, stage by stage; returns seconds per stage."""
+    t = {}
+    t0 = time.perf_counter()
+    params = O.Params.from_scene(scene)
+    proj = O.project_views(params, cams, oo)
+    t["project"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    keys, ids, ranges = O.bin_lists(proj, cams, oo)
+    t["bin_sort"] = time.perf_counter() - t0
+    _, _, offsets, _ = O.view_tables(cams, oo.tile)
+    t0 = time.perf_counter()
+    for v, cam in enumerate(cams):
+        O.render_view(proj[v], cam, oo, scene.channels, ids, ranges, offsets[v])
+    t["blend_fwd"] = time.perf_counter() - t0
+    n, C = scene.channels.shape
+    dch = np.zeros((n, C))
+    acc = None
+    t["blend_bwd"] = t["project_bwd"] = 0.0
+    off = 0
+    for v, cam in enumerate(cams):
+        hw = cam.width * cam.height
+        t0 = time.perf_counter()
+        g2, dch = O.render_backward_view(proj[v], cam, oo, scene.channels, ids, ranges, offsets[v],
+                                         G[off:off + C * hw].reshape(C, hw), None, dch)
+        t["blend_bwd"] += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        acc = O.project_backward(params, cam, oo, g2, acc)
+        t["project_bwd"] += time.perf_counter() - t0
+        off += C * hw
+    return t
+
+
+def cpu_baseline(scene, cams, tile):
     """The FP64 oracle as it stands, on this host's cores: one full forward +
-    backward of the same workload (projection, lists, blending, backward)."""
+    backward of the same workload (projection, lists, blending, backward) on
+    every thread OpenMP gives it, then a single-thread run of the same step on
+    the central quarter of the image rows (a 1920x270 crop of the same camera:
+    all Gaussians projected, the crop's lists blended), both with per-stage
+    times."""
     import synth
     from oracle import oracle as O
     oo = O.make_opts(tile)
-    t0 = time.perf_counter()
-    fwd = O.forward(scene, cams, oo)
-    G = synth.upstream_grads(cams, scene.n_channels, 200).astype(np.float64)
-    O.backward(scene, cams, oo, fwd, G)
-    dt = time.perf_counter() - t0
     px = sum(c.width * c.height for c in cams)
-    return dict(value=px / dt / 1e6, unit="Mpixels/s", cores=O.threads(), kind="oracle",
-                sample=f"one full forward+backward step of the same workload ({px} px), {dt:.1f} s")
+    G = synth.upstream_grads(cams, scene.n_channels, 200).astype(np.float64)
+    nth = O.threads()
+    st = _oracle_step(O, scene, cams, oo, G)
+    dt = sum(st.values())
+    # single thread on a crop: rows [H/2 - H/8, H/2 + H/8) of each view
+    crop = []
+    for c in cams:
+        h = c.height // 4
+        y0 = (c.height - h) // 2
+        crop.append(synth.Camera(c.width, h, c.fx, c.fy, c.cx, c.cy - y0, c.R, c.t))
+    cpx = sum(c.width * c.height for c in crop)
+    Gc = synth.upstream_grads(crop, scene.n_channels, 201).astype(np.float64)
+    O.set_threads(1)
+    try:
+        st1 = _oracle_step(O, scene, crop, oo, Gc)
+    finally:
+        O.set_threads(nth)
+    dt1 = sum(st1.values())
+    return dict(value=px / dt / 1e6, unit="Mpixels/s", cores=nth, kind="oracle",
+                sample=f"one full forward+backward step of the same workload ({px} px), {dt:.1f} s on {nth} "
+                       f"threads",
+                stage_s=st,
+                single_thread=dict(value=cpx / dt1 / 1e6, unit="Mpixels/s", cores=1,
+                                   sample=f"one forward+backward step of the same scene and camera cropped to "
+                                          f"the central quarter of its rows ({cpx} px), {dt1:.1f} s",
+                                   stage_s=st1))
 
 
 def coarse_entries(proj, tile, sx=8, sy=4):
@@ -186,6 +242,155 @@ def coarse_entries(proj, tile, sx=8, sy=4):
     vis = proj.ntiles.cpu().numpy() > 0
     tx0, tx1, ty0, ty1 = (box[vis, k] // tile for k in range(4))
     return int(((tx1 // sx - tx0 // sx + 1) * (ty1 // sy - ty0 // sy + 1)).sum())
+
+
+class StepRunner:
+    """Buffers and the captured HIP graph of one forward + backward step
+    (project -> bin/sort -> blend forward -> gradient clear -> blend backward
+    -> project backward) for a scene and a camera rig, inputs resident in HBM.
+    Every kernel of the step is the library's (the gradient buffers are
+    cleared by legs_clear)."""
+
+    STAGES = ("project", "bin_sort", "blend_fwd", "zero", "blend_bwd", "project_bwd")
+
+    def __init__(self, R, scene, cams, o, G, dev):
+        import torch
+        self.R, self.o = R, o
+        self.rast = R.Rasterizer(cams, o)
+        ctx, views = self.rast.ctx, self.rast.views
+        self.d = {k: torch.from_numpy(getattr(scene, k)).to(dev)
+                  for k in ("mean", "log_scale", "quat", "opacity_logit", "channels")}
+        n, C = scene.channels.shape
+        self.n, self.C = n, C
+        self.proj = R.ProjectedBuf(n, views.n_views, dev)
+        R.project(ctx, self.d["mean"], self.d["log_scale"], self.d["quat"], self.d["opacity_logit"], views, o,
+                  out=self.proj)
+        bins = R.bin_sort(ctx, self.proj, views, o)            # sizes the lists once (host read-back)
+        self.n_inst = bins.n_instances
+        del bins
+        self.bins = R.BinsBuf(int(self.n_inst * 1.05) + 4096, views.total_tiles, dev)
+        self.out = torch.empty(C * views.total_pixels, dtype=torch.float32, device=dev)
+        self.T = torch.empty(views.total_pixels, dtype=torch.float32, device=dev)
+        self.last = torch.empty(views.total_pixels, dtype=torch.int32, device=dev)
+        self.G = G
+        # every gradient buffer is a slice of one flat allocation, cleared by one fill per step
+        gshapes = {"grad2d": (n * views.n_views, 8), "d_ch": (n, C)}
+        gshapes.update({k: tuple(self.d[k].shape) for k in ("mean", "log_scale", "quat", "opacity_logit")})
+        self.gflat = torch.zeros(sum(int(np.prod(sh)) for sh in gshapes.values()), dtype=torch.float32, device=dev)
+        self.gv, at = {}, 0
+        for k, sh in gshapes.items():
+            self.gv[k] = self.gflat[at:at + int(np.prod(sh))].view(sh)
+            at += int(np.prod(sh))
+        self.graph = None
+
+    def step(self, ev=None):
+        R, ctx, views, o, d = self.R, self.rast.ctx, self.rast.views, self.o, self.d
+
+        def mark(i):
+            if ev is not None:
+                ev[i].record()
+        mark(0)
+        R.project(ctx, d["mean"], d["log_scale"], d["quat"], d["opacity_logit"], views, o, out=self.proj)
+        mark(1)
+        R.bin_sort(ctx, self.proj, views, o, self.bins, sync_count=False)
+        mark(2)
+        R.render_forward(ctx, self.proj, self.bins, views, d["channels"], o, self.out, self.T, self.last)
+        mark(3)
+        R.clear(ctx, self.gflat)
+        mark(4)
+        R.render_backward(ctx, self.proj, self.bins, views, d["channels"], o, self.T, self.last, self.G,
+                          self.gv["grad2d"], self.gv["d_ch"])
+        mark(5)
+        grads = {k: self.gv[k] for k in ("mean", "log_scale", "quat", "opacity_logit")}
+        R.project_backward(ctx, d["mean"], d["log_scale"], d["quat"], d["opacity_logit"], views, o, self.proj,
+                           self.gv["grad2d"], grads)
+        mark(6)
+
+    def time_eager(self, steps, warmup):
+        import torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        assert int(self.bins.count.item()) <= self.bins.capacity, "instance list overflowed"
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            self.step(evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per_step = np.array([evs[k][0].elapsed_time(evs[k][6]) for k in range(steps)])
+        stage_ms = {s_: float(np.median([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
+                    for i, s_ in enumerate(self.STAGES)}
+        return float(np.median(per_step)), stage_ms, wall
+
+    def time_graph(self, steps, warmup):
+        """The same step captured once as a HIP graph (every call is capturable:
+        the binning reads its sizes on the device) and replayed: each timed
+        step is one graph launch doing the whole step's work."""
+        import torch
+        if self.graph is None:
+            self.graph = self.R.Graph(self.rast.ctx)
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                with self.graph.capture():
+                    self.step()
+            torch.cuda.current_stream().wait_stream(side)
+        for _ in range(warmup):
+            self.graph.launch()
+        torch.cuda.synchronize()
+        gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for e0, e1 in gev:
+            e0.record()
+            self.graph.launch()
+            e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        assert int(self.bins.count.item()) <= self.bins.capacity, "instance list overflowed"
+        return float(np.median([e0.elapsed_time(e1) for e0, e1 in gev])), wall
+
+
+def c3_leg(log_fn, steps, warmup):
+    """The 16-view batch: 1M Gaussians seen by 16 cameras of uneven resolution
+    on the r=8 sphere, forward + backward of all views per step. The
+    autotuner sweeps tile {8, 16, 32} x LDS batch {64, 128, 256}; the chosen
+    setting is then timed as a replayed HIP graph with the blend kernels
+    launched one workgroup per tile and as persistent launches."""
+    import torch
+    import synth
+    from paper_2311_18482_amd import raster as R
+    scene, cams = synth.workload_c3()
+    dev = torch.device("cuda:0")
+    C = scene.n_channels
+    G = torch.from_numpy(synth.upstream_grads(cams, C, 203)).to(dev)
+    d = {k: torch.from_numpy(getattr(scene, k)).to(dev)
+         for k in ("mean", "log_scale", "quat", "opacity_logit", "channels")}
+    ctx = R.Context(0)
+    log_fn("c3: autotune over tile x LDS batch")
+    best, table = R.autotune(ctx, d["mean"], d["log_scale"], d["quat"], d["opacity_logit"], d["channels"], cams,
+                             R.opts(persistent=True), d_out=G, reps=2)
+    del d
+    torch.cuda.empty_cache()
+    px = sum(c.width * c.height for c in cams)
+    res = dict(workload="1M Gaussians in [-4,4]^3, 16 views of uneven resolution on the r=8 sphere, C=12",
+               views=len(cams), pixels=int(px), resolutions=[[c.width, c.height] for c in cams],
+               autotune=dict(ms={f"tile{t}_batch{b}": v for (t, b), v in table.items()},
+                             best=dict(tile=int(best.tile), lds_batch=int(best.lds_batch))))
+    for persistent in (False, True):
+        o = R.opts(tile=best.tile, lds_batch=best.lds_batch, persistent=persistent)
+        run = StepRunner(R, scene, cams, o, G, dev)
+        eager_ms, stage_ms, _ = run.time_eager(steps, warmup)
+        graph_ms, _ = run.time_graph(steps, warmup)
+        key = "persistent" if persistent else "one_workgroup_per_tile"
+        res[key] = dict(ms_per_step=graph_ms, mpx_s=px / (graph_ms * 1e-3) / 1e6, eager_ms_per_step=eager_ms,
+                        stage_ms=stage_ms, instances=int(run.n_inst))
+        log_fn(f"c3 {key}: {json.dumps(res[key])}")
+        del run
+        torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -198,6 +403,7 @@ def main():
     ap.add_argument("--lds-batch", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-decode", action="store_true", help="skip the learned-vs-plain decode leg")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 16-view batch leg")
     ap.add_argument("--decode-epochs", type=int, default=200,
                     help="decoder training epochs of the decode leg (fewer only to profile its kernels)")
     ap.add_argument("--eager", action="store_true",
@@ -218,98 +424,17 @@ def main():
     scene, cams, desc = workload(args.workload)
     log(f"workload {desc}")
     o = R.opts(tile=args.tile, lds_batch=args.lds_batch, persistent=args.persistent)
-    rast = R.Rasterizer(cams, o)
-    dev = rast.ctx.device
-    d = {k: torch.from_numpy(getattr(scene, k)).to(dev)
-         for k in ("mean", "log_scale", "quat", "opacity_logit", "channels")}
+    dev = torch.device("cuda:0")
     n, C = scene.channels.shape
-    views = rast.views
-    proj = R.ProjectedBuf(n, views.n_views, dev)
-    R.project(rast.ctx, d["mean"], d["log_scale"], d["quat"], d["opacity_logit"], views, o, out=proj)
-    bins = R.bin_sort(rast.ctx, proj, views, o)           # sizes the lists once (host read-back)
-    n_inst = bins.n_instances
-    bins = R.BinsBuf(int(n_inst * 1.05) + 4096, views.total_tiles, dev)
-    out = torch.empty(C * views.total_pixels, dtype=torch.float32, device=dev)
-    T = torch.empty(views.total_pixels, dtype=torch.float32, device=dev)
-    last = torch.empty(views.total_pixels, dtype=torch.int32, device=dev)
     G = torch.from_numpy(__import__("synth").upstream_grads(cams, C, 200)).to(dev)
-    # every gradient buffer is a slice of one flat allocation, cleared by one fill per step
-    gshapes = {"grad2d": (n * views.n_views, 8), "d_ch": (n, C)}
-    gshapes.update({k: tuple(d[k].shape) for k in ("mean", "log_scale", "quat", "opacity_logit")})
-    gflat = torch.zeros(sum(int(np.prod(sh)) for sh in gshapes.values()), dtype=torch.float32, device=dev)
-    gviews, at = {}, 0
-    for k, sh in gshapes.items():
-        gviews[k] = gflat[at:at + int(np.prod(sh))].view(sh)
-        at += int(np.prod(sh))
-    grad2d, d_ch = gviews["grad2d"], gviews["d_ch"]
-    grads = {k: gviews[k] for k in ("mean", "log_scale", "quat", "opacity_logit")}
-    stages = ("project", "bin_sort", "blend_fwd", "zero", "blend_bwd", "project_bwd")
-
-    def step(ev=None):
-        def mark(i):
-            if ev is not None:
-                ev[i].record()
-        mark(0)
-        R.project(rast.ctx, d["mean"], d["log_scale"], d["quat"], d["opacity_logit"], views, o, out=proj)
-        mark(1)
-        R.bin_sort(rast.ctx, proj, views, o, bins, sync_count=False)
-        mark(2)
-        R.render_forward(rast.ctx, proj, bins, views, d["channels"], o, out, T, last)
-        mark(3)
-        gflat.zero_()
-        mark(4)
-        R.render_backward(rast.ctx, proj, bins, views, d["channels"], o, T, last, G, grad2d, d_ch)
-        mark(5)
-        R.project_backward(rast.ctx, d["mean"], d["log_scale"], d["quat"], d["opacity_logit"],
-                           views, o, proj, grad2d, grads)
-        mark(6)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    assert int(bins.count.item()) <= bins.capacity, "instance list overflowed"
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    per_step = np.array([evs[k][0].elapsed_time(evs[k][6]) for k in range(args.steps)])
-    stage_ms = {s: float(np.median([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)]))
-                for i, s in enumerate(stages)}
-    eager_ms = float(np.median(per_step))
+    run = StepRunner(R, scene, cams, o, G, dev)
+    rast, views, proj, bins, n_inst = run.rast, run.rast.views, run.proj, run.bins, run.n_inst
+    eager_ms, stage_ms, wall = run.time_eager(args.steps, args.warmup)
     log(f"eager step {eager_ms:.3f} ms; stages (median ms): {json.dumps(stage_ms)}; wall {wall:.3f}s for "
         f"{args.steps} steps; instances {n_inst}")
-
-    # The same step captured once as a HIP graph (every call is capturable: the
-    # binning reads its sizes on the device) and replayed: the timed steps below
-    # are graph launches, each doing the whole step's work; the per-stage times
-    # above come from the eager steps (events cannot sit inside a capture).
     graph_ms = None
     if not args.eager:
-        graph = R.Graph(rast.ctx)
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            with graph.capture():
-                step()
-        torch.cuda.current_stream().wait_stream(side)
-        for _ in range(args.warmup):
-            graph.launch()
-        torch.cuda.synchronize()
-        gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for e0, e1 in gev:
-            e0.record()
-            graph.launch()
-            e1.record()
-        torch.cuda.synchronize()
-        gwall = time.perf_counter() - t0
-        graph_ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in gev]))
-        assert int(bins.count.item()) <= bins.capacity, "instance list overflowed"
+        graph_ms, gwall = run.time_graph(args.steps, args.warmup)
         log(f"graph step {graph_ms:.3f} ms; wall {gwall:.3f}s for {args.steps} replays")
     ms = eager_ms if graph_ms is None else graph_ms
     px = views.total_pixels
@@ -323,7 +448,9 @@ def main():
     #    once, outside the timed steps).
     ev, blended, ev_bwd, _walked = R.render_counts(rast.ctx, proj, bins, views, o)
     G_views = n * views.n_views
-    gpasses = (32 + max(1, int(np.ceil(np.log2(max(views.n_views, 1))))) + 7) // 8
+    # depth passes of the G-view sort: 8-bit digits over the 32 depth bits and
+    # the view bits, ceil(log2(views)) (none for one view)
+    gpasses = (32 + int(np.ceil(np.log2(views.n_views))) + 7) // 8
     n_coarse = coarse_entries(proj, args.tile)
     work = {
         "project": ("hbm", G_views * (44 + 16 + 16 + 16 + 4 + 4)),
@@ -368,11 +495,17 @@ def main():
         log("copy calibration: 1 GiB read, 1 GiB written (neg kernel)")
         del src, dst
 
+    del run, rast, proj, bins
+    torch.cuda.empty_cache()
+    c3 = None
+    if not args.no_c3 and args.workload == "1m_1080p":
+        log("16-view leg: autotune, then one-workgroup-per-tile and persistent blend launches")
+        c3 = c3_leg(log, max(5, args.steps // 2), 2)
+        torch.cuda.empty_cache()
+
     dec = None
     if not args.no_decode and args.workload == "1m_1080p":
         log("decode leg: render 32 views, label, train the decoder, time the decodes")
-        del proj, bins, out, T, last, grad2d, d_ch, grads
-        torch.cuda.empty_cache()
         dec = decode_leg(log, epochs=args.decode_epochs)
         log(f"decode: {json.dumps(dec)}")
 
@@ -391,7 +524,7 @@ def main():
                            blended_entries=int(blended), stage_ms=stage_ms,
                            launch="eager" if graph_ms is None else "hip graph replay of the whole step",
                            eager_ms_per_step=eager_ms, persistent_blend=bool(args.persistent)),
-               roofline=roofline, decode=dec, cpu_baseline=cpu)
+               roofline=roofline, c3=c3, decode=dec, cpu_baseline=cpu)
     print(json.dumps(rec), flush=True)
 
 

@@ -320,6 +320,13 @@ int32_t legs_l1_loss_grad(legs_ctx *ctx, const float *out, const float *target,
                           int32_t C, int32_t n_fit, float lambda_u, float *d_out, float *loss,
                           void *stream);
 
+/* Zero `bytes` bytes (a multiple of 4, 4-byte aligned) of device memory with a
+ * kernel (a kernel node under graph capture, never a memset node): clears the
+ * accumulated (+=) gradient outputs of legs_render_backward and
+ * legs_project_backward before a step. LEGS_ERR_ARG on a bad size or
+ * pointer. */
+int32_t legs_clear(legs_ctx *ctx, void *dev, int64_t bytes, void *stream);
+
 /* ---- runtime: graph capture and autotuning -------------------------------- */
 
 typedef struct legs_graph legs_graph;

@@ -682,3 +682,13 @@ int32_t oracle_threads(void)
     return 1;
 #endif
 }
+
+/* Threads used by the parallel loops above from now on (timing runs only). */
+void oracle_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -74,6 +74,8 @@ def lib():
         L.oracle_project_backward.restype = None
         L.oracle_threads.argtypes = []
         L.oracle_threads.restype = i32
+        L.oracle_set_threads.argtypes = [i32]
+        L.oracle_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -219,6 +221,10 @@ def project_backward(params: Params, cam, opts, grad2d, acc=None):
 
 def threads() -> int:
     return int(lib().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().oracle_set_threads(int(n))
 
 
 # ---- whole-pipeline helpers --------------------------------------------------

@@ -103,6 +103,7 @@ _SIGS = {
     "legs_mlp_train_step": (I32, [P, P, I64, I64, I64, P, I32, P, P, P, P, I32, ct.c_float,
                                   ct.c_float, ct.c_float, ct.c_float, P, P, P]),
     "legs_l1_loss_grad": (I32, [P, P, P, P, I32, I64, I32, I32, ct.c_float, P, P, P]),
+    "legs_clear": (I32, [P, P, I64, P]),
     "legs_capture_begin": (I32, [P, P]),
     "legs_capture_end": (I32, [P, P, ct.POINTER(P)]),
     "legs_graph_launch": (I32, [P, P, P]),

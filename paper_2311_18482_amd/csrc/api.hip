@@ -414,4 +414,14 @@ int32_t legs_l1_loss_grad(legs_ctx *ctx, const float *out, const float *target,
                                     lambda_u, d_out, loss, (hipStream_t)stream);
 }
 
+int32_t legs_clear(legs_ctx *ctx, void *dev, int64_t bytes, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (bytes < 0 || (bytes & 3)) return legs_set_error(ctx, LEGS_ERR_ARG, "bytes must be a non-negative multiple of 4");
+    if (bytes > 0 && (!dev || (reinterpret_cast<uintptr_t>(dev) & 3)))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "NULL or unaligned buffer");
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_clear(ctx, dev, bytes / 4, (hipStream_t)stream);
+}
+
 } // extern "C"

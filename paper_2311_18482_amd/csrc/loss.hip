@@ -48,7 +48,31 @@ k_l1(const float *__restrict__ out, const float *__restrict__ tgt, const legs_vi
 
 __global__ void k_zero1(float *p) { *p = 0.0f; }
 
+// Zero n 32-bit words (16-byte stores where aligned; a kernel, so it records
+// as a kernel node under graph capture).
+__global__ void __launch_bounds__(256)
+k_clear(uint32_t *__restrict__ p, int64_t n)
+{
+    const int64_t n4 = (reinterpret_cast<uintptr_t>(p) & 15) == 0 ? n / 4 : 0;
+    uint4 *q = reinterpret_cast<uint4 *>(p);
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride) q[i] = make_uint4(0, 0, 0, 0);
+    for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
 } // namespace
+
+int32_t legs_launch_clear(legs_ctx *ctx, void *dev, int64_t words, hipStream_t s)
+{
+    if (words <= 0) return LEGS_OK;
+    int64_t g = (words / 4 + 255) / 256;
+    const int64_t cap = (int64_t)ctx->num_cus * 8;
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_clear, dim3((unsigned)g), dim3(256), 0, s, static_cast<uint32_t *>(dev), words);
+    LEGS_CHECK_LAUNCH(ctx);
+    return LEGS_OK;
+}
 
 int32_t legs_launch_l1_loss_grad(legs_ctx *ctx, const float *out, const float *target,
                                  const legs_view *views, int32_t n_views, int64_t total_pixels,

@@ -179,9 +179,10 @@ extern "C" int32_t legs_autotune(legs_ctx *ctx, const float *mean, const float *
                 if (rc == LEGS_OK) rc = legs_bin_sort(ctx, &proj, n, views, n_views, total_tiles, &o, &bins, nullptr, stream);
                 if (rc == LEGS_OK) rc = legs_render_forward(ctx, &proj, n, &bins, views, n_views, total_tiles, channels, C, &o, out, Tf, last, stream);
                 if (rc == LEGS_OK && d_out) {
-                    hipMemsetAsync(g2, 0, sizeof(float) * 8 * G, s);
-                    hipMemsetAsync(dch, 0, sizeof(float) * n * C, s);
-                    rc = legs_render_backward(ctx, &proj, n, &bins, views, n_views, total_tiles, channels, C, &o, Tf, last, d_out, g2, dch, stream);
+                    rc = legs_clear(ctx, g2, (int64_t)sizeof(float) * 8 * G, stream);
+                    if (rc == LEGS_OK) rc = legs_clear(ctx, dch, (int64_t)sizeof(float) * n * C, stream);
+                    if (rc == LEGS_OK)
+                        rc = legs_render_backward(ctx, &proj, n, &bins, views, n_views, total_tiles, channels, C, &o, Tf, last, d_out, g2, dch, stream);
                     if (rc == LEGS_OK)
                         rc = legs_project_backward(ctx, mean, log_scale, quat, opacity_logit, n, views, n_views, &o, &proj, g2, dmu, dls, dq, dom, stream);
                 }

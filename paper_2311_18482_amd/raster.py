@@ -202,6 +202,13 @@ def render_backward(ctx: Context, proj: ProjectedBuf, bins: BinsBuf, views: View
     return grad2d, d_channels
 
 
+def clear(ctx: Context, t):
+    """Zero a contiguous device tensor with the library's fill kernel."""
+    assert t.is_cuda and t.is_contiguous()
+    ctx.check(L.lib().legs_clear(ctx.handle, _p(t), t.numel() * t.element_size(), _stream()))
+    return t
+
+
 def render_counts(ctx: Context, proj: ProjectedBuf, bins: BinsBuf, views: Views, o: L.Opts):
     """(forward alpha evaluations, blended entries, backward alpha evaluations,
     list positions walked) for these lists."""
@@ -230,13 +237,19 @@ def project_backward(ctx: Context, mean, log_scale, quat, opacity_logit, views: 
 
 
 class Rasterizer:
-    """Holds a context, a view table and options; reuses bin buffers."""
+    """Holds a context, a view table and options.
+
+    forward() reuses one set of bin buffers: its lists are overwritten by the
+    next forward(). The autograd path (rasterize) instead takes a set of its
+    own for every call and returns it to a pool when its backward has been
+    enqueued, so several renders may be alive before any backward runs."""
 
     def __init__(self, cams, o: L.Opts | None = None, device: int = 0):
         self.ctx = Context(device)
         self.o = o if o is not None else opts()
         self.views = views_build(cams, self.o, self.ctx.device)
         self.bins = None
+        self._pool = []
 
     def forward(self, mean, log_scale, quat, opacity_logit, channels):
         proj = project(self.ctx, mean, log_scale, quat, opacity_logit, self.views, self.o)
@@ -244,14 +257,26 @@ class Rasterizer:
         out, T, last = render_forward(self.ctx, proj, self.bins, self.views, channels, self.o)
         return proj, self.bins, out, T, last
 
+    def forward_owned(self, mean, log_scale, quat, opacity_logit, channels):
+        """Like forward(), with bin buffers that belong to the caller until
+        it hands them back with release()."""
+        proj = project(self.ctx, mean, log_scale, quat, opacity_logit, self.views, self.o)
+        bins = bin_sort(self.ctx, proj, self.views, self.o, self._pool.pop() if self._pool else None)
+        out, T, last = render_forward(self.ctx, proj, bins, self.views, channels, self.o)
+        return proj, bins, out, T, last
+
+    def release(self, bins):
+        self._pool.append(bins)
+
 
 class RasterizeFn(torch.autograd.Function):
     """out (planar, views concatenated), T_final = rasterize(...).
-    Saves only the projected records, the tile lists, T_final and last."""
+    Saves only the projected records, the tile lists, T_final and last; each
+    call holds its own tile lists until its backward."""
 
     @staticmethod
     def forward(fctx, mean, log_scale, quat, opacity_logit, channels, rast: Rasterizer):
-        proj, bins, out, T, last = rast.forward(mean, log_scale, quat, opacity_logit, channels)
+        proj, bins, out, T, last = rast.forward_owned(mean, log_scale, quat, opacity_logit, channels)
         fctx.rast, fctx.proj, fctx.bins = rast, proj, bins
         fctx.save_for_backward(mean, log_scale, quat, opacity_logit, channels, T, last)
         fctx.mark_non_differentiable(T)
@@ -265,6 +290,9 @@ class RasterizeFn(torch.autograd.Function):
                                        d_out)
         g = project_backward(r.ctx, mean, log_scale, quat, opacity_logit, r.views, r.o, fctx.proj,
                              grad2d)
+        # the lists are no longer read after the kernels enqueued above (same stream)
+        r.release(fctx.bins)
+        fctx.bins = None
         return g["mean"], g["log_scale"], g["quat"], g["opacity_logit"], d_ch, None
 
 

@@ -9,12 +9,14 @@ Comparison rules
     such a pixel also passes if it matches the oracle with that decision
     inverted (up to the first four ambiguous events, any combination);
   - gradients: per Gaussian and parameter group,
-    ||g - g_ref|| <= 1e-3 * max(||g_ref||, 1e-2 * RMS of the group), with the
-    oracle replaying each pixel along the branch the GPU took. The floor keeps
-    the bound meaningful for gradients that are a near-cancellation by
-    construction (e.g. the quaternion gradient of a nearly isotropic Gaussian,
-    where float32 rounding of its conic gradients is amplified by the ratio of
-    the two scales); the global relative error of each group is reported too.
+    ||g - g_ref|| <= 1e-3 * max(||g_ref||, f * RMS of the group) with
+    f = 1e-3 (f = 1e-2 for the quaternion), the oracle replaying each pixel
+    along the branch the GPU took, and ||G - G_ref|| / ||G_ref|| <= 1e-5 over
+    the whole group. The quaternion's larger floor covers a cancellation by
+    construction: the quaternion gradient of a nearly isotropic Gaussian is a
+    difference of nearly equal terms (it vanishes for an isotropic one), so
+    float32 rounding of its conic gradients, amplified by the ratio of the
+    two scales, dominates it.
 """
 from __future__ import annotations
 
@@ -144,11 +146,20 @@ def gpu_grads_to_np(grads, d_ch):
     return out
 
 
-def compare_grads(g, ref, n, tol=1e-3, groups=GROUPS, subset=None, floor=1e-2):
+FLOOR = {"quat": 1e-2}
+FLOOR_DEFAULT = 1e-3
+
+
+def group_floor(grp):
+    return FLOOR.get(grp, FLOOR_DEFAULT)
+
+
+def compare_grads(g, ref, n, tol=1e-3, groups=GROUPS, subset=None, floor=None, global_tol=1e-5):
     """Per-Gaussian group check; returns worst ratio err / bound and the
-    global relative error per group."""
+    global relative error per group (asserted <= global_tol unless None)."""
     worst = {}
     for grp in groups:
+        fl = group_floor(grp) if floor is None else floor
         a = np.asarray(g[grp], np.float64).reshape(n, -1)
         r = np.asarray(ref[grp], np.float64).reshape(n, -1)
         if subset is not None:
@@ -156,7 +167,7 @@ def compare_grads(g, ref, n, tol=1e-3, groups=GROUPS, subset=None, floor=1e-2):
         nz = np.abs(r).sum(axis=1) > 0
         rms = np.sqrt(np.mean(r[nz] ** 2)) if nz.any() else 0.0
         err = np.linalg.norm(a - r, axis=1)
-        bound = tol * np.maximum(np.linalg.norm(r, axis=1), floor * rms)
+        bound = tol * np.maximum(np.linalg.norm(r, axis=1), fl * rms)
         bad = err > bound
         if nz.any() or bad.any():
             k = int(np.argmax(err / np.maximum(bound, 1e-300)))
@@ -165,4 +176,6 @@ def compare_grads(g, ref, n, tol=1e-3, groups=GROUPS, subset=None, floor=1e-2):
                               worst_norm_over_rms=float(np.linalg.norm(r[k]) / max(rms, 1e-300)))
         assert not bad.any(), (f"{grp}: {int(bad.sum())} of {len(a)} Gaussians exceed tolerance; "
                                f"worst {worst[grp]}")
+        if global_tol is not None and grp in worst:
+            assert worst[grp]["global_rel"] <= global_tol, (grp, worst[grp])
     return worst

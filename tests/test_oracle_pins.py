@@ -277,14 +277,16 @@ def np_project(params, cam, lowpass=H_LOWPASS, z_near=0.2, guard=1.3):
     return dict(mx=mx, my=my, Q=Q, r=r, sig=sig, valid=valid, depth32=z.astype(np.float32))
 
 
-def np_render(params, channels, cam):
+def np_render(params, channels, cam, return_last=False):
     """Per pixel, over ALL Gaussians ordered by (depth32 bits, id): the
-    front-to-back rule written out directly."""
+    front-to-back rule written out directly. With return_last, also the id of
+    the last Gaussian blended at each pixel (-1 if none)."""
     P = np_project(params, cam)
     order = np.lexsort((np.arange(params.n), P["depth32"].view(np.uint32)))
     C = channels.shape[1]
     out = np.zeros((C, cam.height, cam.width))
     Tf = np.ones((cam.height, cam.width))
+    last_id = np.full((cam.height, cam.width), -1, np.int64)
     ch = channels.astype(np.float64)
     for j in range(cam.height):
         for i in range(cam.width):
@@ -306,8 +308,11 @@ def np_render(params, channels, cam):
                     break
                 acc += a * T * ch[g]
                 T *= (1 - a)
+                last_id[j, i] = g
             out[:, j, i] = acc
             Tf[j, i] = T
+    if return_last:
+        return out, Tf, last_id
     return out, Tf
 
 
@@ -638,3 +643,197 @@ def test_l1_loss_gradient_fd():
         lp, _ = D.l1_loss_grad(out + e, tgt, cams, C, ds)
         lm, _ = D.l1_loss_grad(out - e, tgt, cams, C, ds)
         assert grad[k] == pytest.approx((lp - lm) / 2e-6, rel=1e-6, abs=1e-9)
+
+
+def _guard_band_scene(seed, n_out=40, n_in=300):
+    """Gaussians whose means lie outside the guard band (|x/z| > 1.3 W / (2 f))
+    but whose footprints still reach the image, mixed with ordinary ones."""
+    rng = np.random.default_rng(seed)
+    z = rng.uniform(2.5, 4.0, n_out)
+    u = rng.uniform(0.68, 0.85, n_out) * rng.choice([-1.0, 1.0], n_out)
+    v = rng.uniform(-0.3, 0.3, n_out)
+    out_mean = np.stack([u * z, v * z, z], 1)
+    inner = synth.make_scene(n_in, seed + 1, synth.VOL_C1, d_sem=2)
+    q = rng.normal(size=(n_out, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    return synth.Scene(
+        np.concatenate([out_mean.astype(np.float32), inner.mean]),
+        np.concatenate([rng.normal(-1.0, 0.2, (n_out, 3)).astype(np.float32), inner.log_scale]),
+        np.concatenate([q.astype(np.float32), inner.quat]),
+        np.concatenate([rng.normal(0.0, 1.0, n_out).astype(np.float32), inner.opacity_logit]),
+        np.concatenate([rng.normal(0.0, 1.0, (n_out, inner.n_channels)).astype(np.float32),
+                        inner.channels]), 2)
+
+
+def test_guard_band_backward_matches_finite_differences(oracle_lib):
+    """The Jacobian of a Gaussian outside the guard band is evaluated at the
+    clamped point (x/z held at the limit), so its derivative with respect to the
+    camera-space x or y is zero and only z moves it. The oracle's analytic
+    gradient of such Gaussians (mean, log-scale, quaternion, opacity, channels)
+    agrees with float64 central finite differences of the rendered loss."""
+    scene = _guard_band_scene(91)
+    cams = [synth.camera_front(96, 96, 96.0)]
+    opts = O.make_opts(16)
+    f = O.forward(scene, cams, opts)
+    P = f["proj"][0]
+    G = synth.upstream_grads(cams, scene.n_channels, 291)
+    b = O.backward(scene, cams, opts, f, G)
+    blended = set(fd.blended_gaussians(b).tolist())
+    clamped = [g for g in range(40) if P["valid"][g] and (P["clampx"][g] or P["clampy"][g])
+               and g in blended]
+    assert len(clamped) >= 20
+    groups = ("mean", "log_scale", "quat", "opacity_logit", "channels")
+    ids = np.array(sorted(blended))
+    rms = {g: np.sqrt(np.mean(b[g].reshape(scene.n, -1)[ids] ** 2)) for g in groups}
+    n_valid = 0
+    for g in clamped[:10]:
+        r = fd.fd_gaussian(f["params"], scene.channels, cams, opts, f["proj"], G, g)
+        for grp in groups:
+            vals, ok = r[grp]
+            an = b[grp].reshape(scene.n, -1)[g]
+            n_valid += int(ok.sum())
+            err = _group_err(an[ok], vals[ok], 1e-3 * rms[grp])
+            assert err < 1e-5, (g, grp, err)
+    assert n_valid >= 10 * 14
+
+
+def test_l1_loss_closed_form_values():
+    """Constant maps give the loss in closed form: with |out - target| = d on
+    every fitted channel and a rendered uncertainty u in each remaining
+    channel, each view contributes d + lambda_u * u per uncertainty channel,
+    and dL/dout = sign(out - target) / (n_fit H W) or lambda_u / (H W)."""
+    cams = [synth.camera_front(7, 5, 7.0), synth.camera_front(3, 4, 3.0)]
+    C, ds = 7, 3                        # RGB + 3 semantic + 1 uncertainty
+    n_fit = 3 + ds
+    parts_o, parts_t, want_g = [], [], []
+    rng = np.random.default_rng(12)
+    for cam in cams:
+        hw = cam.width * cam.height
+        t = rng.normal(0, 1, (C, hw))
+        sign = rng.choice([-1.0, 1.0], (C, hw))
+        o = t + 0.375 * sign
+        o[n_fit:] = 0.625
+        parts_o.append(o.reshape(-1))
+        parts_t.append(t.reshape(-1))
+        g = np.concatenate([sign[:n_fit] / (n_fit * hw), np.full((C - n_fit, hw), 2.0 / hw)])
+        want_g.append(g.reshape(-1))
+    loss, grad = D.l1_loss_grad(np.concatenate(parts_o), np.concatenate(parts_t), cams, C, ds,
+                                lambda_u=2.0)
+    assert loss == pytest.approx(len(cams) * (0.375 + 2.0 * 0.625), rel=1e-14)
+    assert np.allclose(grad, np.concatenate(want_g), rtol=1e-15, atol=0)
+    # equal maps: no L1 term and a zero sign gradient
+    o = np.concatenate(parts_t).copy()
+    loss0, grad0 = D.l1_loss_grad(o, o, cams, C, ds, lambda_u=0.0)
+    assert loss0 == 0.0 and not grad0.any()
+
+
+def _tile_positions(items, tile_of_pixel):
+    """Position of each Gaussian in each tile's list, from brute-force lists."""
+    pos = {}
+    k_in_tile = {}
+    for t, _, g in items:
+        k = k_in_tile.get(t, 0)
+        pos[(t, g)] = k
+        k_in_tile[t] = k + 1
+    return pos
+
+
+def test_last_index_multi_entry_brute_force(oracle_lib):
+    """`last` = 1 + the tile-list position of the last Gaussian blended at a
+    pixel. A direct per-pixel walk over all Gaussians (depth order) names that
+    Gaussian; its position in the brute-force tile list gives the expected
+    value, on a scene dense enough that many pixels blend several entries and
+    some stop."""
+    scene = synth.make_scene(150, 33, synth.VOL_C1, d_sem=1)
+    scene.opacity_logit[:] += 2.0
+    cam = synth.camera_front(40, 32, 40.0)
+    for tile in (8, 16):
+        opts = O.make_opts(tile)
+        f = O.forward(scene, [cam], opts)
+        r = f["views"][0]
+        params = O.Params.from_scene(scene)
+        _, _, last_id = np_render(params, scene.channels, cam, return_last=True)
+        items, _ = brute_force_lists(f["proj"], [cam], tile)
+        pos = _tile_positions(items, None)
+        tiles_x = (cam.width + tile - 1) // tile
+        want = np.zeros(cam.width * cam.height, np.int64)
+        for j in range(cam.height):
+            for i in range(cam.width):
+                g = last_id[j, i]
+                if g >= 0:
+                    want[j * cam.width + i] = 1 + pos[((j // tile) * tiles_x + i // tile, g)]
+        assert np.array_equal(r["last"], want)
+        assert (want > 1).mean() > 0.5 and want.max() > 10
+
+
+def test_ambiguous_stop_flip_and_backward_replay(oracle_lib):
+    """Two Gaussians with opacity above alpha_max centred on one pixel: both
+    clamp to 0.99, so after the second T (1 - alpha) = 1e-4 up to rounding,
+    the stop rule's threshold. The oracle flags the decision ambiguous; with
+    it inverted the second Gaussian stops unblended. The backward along the
+    inverted branch equals the backward of the same scene with t_min nudged
+    so that the stop happens without inversion (and, for the skip rule, with
+    alpha_min nudged), so a flip mask replays exactly the other decision."""
+    cam = synth.camera_front(64, 64, 64.0)
+    opts = O.make_opts(16)
+    # centred on pixel (32, 32); opacities above 0.99 only within half a pixel
+    # of the centre, so the centre is the only pixel where both clamp
+    c = 1.5 / 64
+    sc = scene_from([[c, c, 3.0], [c * 4 / 3, c * 4 / 3, 4.0]], [[-1.0] * 3, [-0.9] * 3],
+                    [[1, 0, 0, 0]] * 2, [5.5, 5.0], [[1.0, 0.5], [0.25, 2.0]])
+    f = O.forward(sc, [cam], opts)
+    P = f["proj"][0]
+    assert P["mx"][0] == pytest.approx(32.5, abs=1e-12) and P["mx"][1] == pytest.approx(32.5, abs=1e-12)
+    lin = 32 * 64 + 32
+    r0 = O.render_view(P, cam, opts, sc.channels, f["ids"], f["ranges"], 0, pix=[lin])
+    r1 = O.render_view(P, cam, opts, sc.channels, f["ids"], f["ranges"], 0, pix=[lin], flip_mask=[1])
+    assert r0["n_amb"][0] == 1
+    a = 0.99
+    # without the flip both blend (T'= (1 - 0.99)^2 rounds above 1e-4 in float64)
+    assert r0["last"][0] == 2 and r0["out"][0, 0] == pytest.approx(a * 1.0 + a * (1 - a) * 0.25, rel=1e-12)
+    assert r0["T"][0] == pytest.approx((1 - a) ** 2, rel=1e-12)
+    assert r1["last"][0] == 1 and r1["out"][0, 0] == pytest.approx(a, rel=1e-12)
+    assert r1["T"][0] == pytest.approx(1 - a, rel=1e-12)
+    # backward replay of the flipped branch = backward with the stop taken naturally
+    G = synth.upstream_grads([cam], 2, 17).astype(np.float64)
+    fm = np.zeros(64 * 64, np.uint32)
+    fm[lin] = 1
+    b_flip = O.backward(sc, [cam], opts, f, G, flip_masks=[fm])
+    o2 = O.make_opts(16)
+    o2.t_min = 1.0000001e-4
+    f2 = O.forward(sc, [cam], o2)
+    assert f2["views"][0]["last"][lin] == 1
+    b_nat = O.backward(sc, [cam], o2, f2, G)
+    b_plain = O.backward(sc, [cam], opts, f, G)
+    for grp in ("mean", "log_scale", "quat", "opacity_logit", "channels"):
+        assert np.allclose(b_flip[grp], b_nat[grp], rtol=1e-12, atol=1e-15), grp
+    assert not np.allclose(b_flip["channels"], b_plain["channels"])
+
+
+def test_skip_flip_backward_replay(oracle_lib):
+    """A Gaussian whose alpha at one pixel sits at 1/255 within the ambiguity
+    margin: the backward along the inverted skip decision equals the backward
+    with alpha_min nudged so that the other decision is taken naturally."""
+    cam = synth.camera_front(64, 64, 64.0)
+    opts = O.make_opts(16)
+    s0 = 1.0 / 255.0
+    omega = np.float32(np.log(s0 / (1 - s0)))
+    sig = 1.0 / (1.0 + np.exp(-float(omega)))
+    sc = scene_from([[1.5 / 64, 1.5 / 64, 3.0], [0.1, 0.05, 2.5]], [[-1.0] * 3, [-1.6, -1.2, -1.4]],
+                    [[1, 0, 0, 0], [0.9, 0.2, -0.1, 0.3]], [omega, 0.3], [[2.0, 1.0], [0.5, -1.0]])
+    f = O.forward(sc, [cam], opts)
+    lin = 32 * 64 + 32
+    G = synth.upstream_grads([cam], 2, 18).astype(np.float64)
+    fm = np.zeros(64 * 64, np.uint32)
+    fm[lin] = 1
+    r = O.render_view(f["proj"][0], cam, opts, sc.channels, f["ids"], f["ranges"], 0, pix=[lin])
+    assert r["n_amb"][0] == 1
+    b_flip = O.backward(sc, [cam], opts, f, G, flip_masks=[fm])
+    o2 = O.make_opts(16)
+    # move alpha_min across alpha so that the natural decision is the inverted one
+    o2.alpha_min = sig * (1 + 1e-9) if sig >= s0 else sig * (1 - 1e-9)
+    o2.eps_alpha = 1e-12
+    f2 = O.forward(sc, [cam], o2)
+    b_nat = O.backward(sc, [cam], o2, f2, G)
+    for grp in ("mean", "log_scale", "quat", "opacity_logit", "channels"):
+        assert np.allclose(b_flip[grp], b_nat[grp], rtol=1e-10, atol=1e-15), grp
