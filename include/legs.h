@@ -67,9 +67,11 @@ typedef struct {
     int64_t pixel_offset; /* first pixel of this view in the concatenated planes */
 } legs_view;
 
-/* Blend kernels as one persistent launch per call (workgroups take tiles from
- * an atomic counter in the sort scratch until every tile of every view is
- * done) instead of one workgroup per tile. Results are identical. */
+/* Blend kernels as one persistent launch per call over the tiles of every
+ * view: the launch first orders all tiles by decreasing list length (the
+ * heaviest first), then workgroups take tiles from that queue through an
+ * atomic counter in the sort scratch until it is empty, instead of one
+ * workgroup per tile. Results are identical. */
 #define LEGS_FLAG_PERSISTENT 1
 /* Bin with all 8-bit digits of the 64-bit keys sorted over the instances
  * (6 passes at 8160 tiles) instead of the depth-first binning: the G-views

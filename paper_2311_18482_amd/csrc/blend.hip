@@ -51,6 +51,7 @@ struct BlendParams {
     float amax, amin, tmin;
     bool reach;         // skip the pixels outside the reach of alpha_min (reach_box)
     uint32_t *counter;  // non-NULL: persistent launch, tiles taken from this counter
+    const uint32_t *order;  // persistent launch: the tiles in decreasing order of list length
 };
 
 // The conic (A, B, C) is staged scaled by (-log2(e)/2, -log2(e), -log2(e)/2),
@@ -282,11 +283,15 @@ __device__ __forceinline__ TileInfo tile_info(const BlendParams &P, int64_t tile
     return t;
 }
 
-// Next tile of this workgroup: one tile per workgroup, or from the persistent counter.
+// Next tile of this workgroup: one tile per workgroup, or the next entry of
+// the heaviest-first tile order from the persistent counter.
 __device__ __forceinline__ int64_t next_tile(const BlendParams &P, int64_t prev, int64_t *s_tile)
 {
     if (P.counter) {
-        if (threadIdx.x == 0) *s_tile = (int64_t)atomicAdd(P.counter, 1u);
+        if (threadIdx.x == 0) {
+            const uint32_t i = atomicAdd(P.counter, 1u);
+            *s_tile = (int64_t)i < P.total_tiles ? (int64_t)P.order[i] : P.total_tiles;
+        }
         __syncthreads();
         const int64_t t = *s_tile;
         __syncthreads();
@@ -656,7 +661,47 @@ k_blend_count(BlendParams P, unsigned long long *__restrict__ counts)
 
 __global__ void k_zero_counts(unsigned long long *c) { c[threadIdx.x] = 0ull; }
 
-__global__ void k_zero_counter(uint32_t *c) { *c = 0u; }
+// Work bucket of a tile list of length n: 0 for an empty list, otherwise
+// 1 + 4 floor(log2 n) + the two bits below the leading one (quarter octaves).
+__device__ __forceinline__ int length_bucket(uint32_t n)
+{
+    if (n == 0) return 0;
+    const int lz = 31 - __builtin_clz(n);
+    const int q = lz >= 2 ? (int)((n >> (lz - 2)) & 3u) : (lz == 1 ? (int)((n & 1u) << 1) : 0);
+    return 1 + 4 * lz + q;
+}
+
+constexpr int ORDER_BUCKETS = 1 + 4 * 32;
+
+// The persistent blend launches' tile queue: every tile of every view in
+// decreasing order of list length (longest-processing-time first, at quarter-
+// octave resolution; order inside a bucket is arbitrary), and the queue
+// counter reset. One workgroup; a kernel, so it records under graph capture.
+__global__ void __launch_bounds__(1024)
+k_tile_order(const uint32_t *__restrict__ ranges, int64_t T, uint32_t *__restrict__ order,
+             uint32_t *__restrict__ counter)
+{
+    __shared__ uint32_t cnt[ORDER_BUCKETS];
+    for (int b = threadIdx.x; b < ORDER_BUCKETS; b += blockDim.x) cnt[b] = 0u;
+    if (threadIdx.x == 0) *counter = 0u;
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < T; t += blockDim.x)
+        atomicAdd(&cnt[length_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int b = ORDER_BUCKETS - 1; b >= 0; --b) {
+            const uint32_t c = cnt[b];
+            cnt[b] = s;
+            s += c;
+        }
+    }
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < T; t += blockDim.x) {
+        const uint32_t pos = atomicAdd(&cnt[length_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
+        order[pos] = (uint32_t)t;
+    }
+}
 
 template <int TILE, int CP>
 int32_t launch_tile_cp(legs_ctx *ctx, bool fwd, const BlendParams &P0, float *out, float *Tf,
@@ -681,7 +726,8 @@ int32_t launch_tile_cp(legs_ctx *ctx, bool fwd, const BlendParams &P0, float *ou
         const int64_t per_cu = threads >= 1024 ? 2 : (threads >= 256 ? 6 : 12);
         const int64_t cap = (int64_t)ctx->num_cus * per_cu;
         grid = grid < cap ? grid : cap;
-        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, P.counter);
+        hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, P.ranges, P.total_tiles,
+                           const_cast<uint32_t *>(P.order), P.counter);
     }
     if (parts) {
         hipLaunchKernelGGL((k_blend_fwd<TILE, CP, SUB>), dim3((unsigned)grid), dim3(threads), lds, s,
@@ -736,9 +782,13 @@ BlendParams make_params(const legs_projected *proj, int64_t n, const legs_bins *
 {
     BlendParams P;
     P.counter = nullptr;
+    P.order = nullptr;
     if (o->flags & LEGS_FLAG_PERSISTENT) {
-        const legs_sort_layout Ls = legs_sort_layout_for(bins->capacity);
+        const legs_sort_layout Ls = legs_sort_layout_for(bins->capacity, total_tiles);
         P.counter = reinterpret_cast<uint32_t *>(static_cast<char *>(bins->scratch) + Ls.counter_off) + slot;
+        // every persistent launch rebuilds the queue before it starts, so the
+        // backward does not depend on a persistent forward having run
+        P.order = reinterpret_cast<const uint32_t *>(static_cast<char *>(bins->scratch) + Ls.order_off);
     }
     P.mean2d = reinterpret_cast<const double2 *>(proj->mean2d);
     P.conic = reinterpret_cast<const float4 *>(proj->conic);

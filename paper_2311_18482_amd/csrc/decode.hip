@@ -272,7 +272,9 @@ k_decode_mlp(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
     for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < tiles; tile += stride) {
         const int64_t p = tile * 32 + (lane & 31);
         const bool valid = p < P;
-        mlp_tile_forward<KB>(L, feat, p, valid, cs, ps, T);
+        int off = 0;
+        asm volatile("" : "+s"(off));   // fragments are re-read from LDS every tile
+        mlp_tile_forward<KB>(L, feat, p, valid, cs, ps, T, off);
         float best = -INFINITY;
         int bidx = 0x7fffffff;
         f32x16 S[KB];
@@ -290,6 +292,93 @@ k_decode_mlp(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
         if (valid) {
             if (h == 0) top1[p] = bidx;
             if (probs) write_softmax<KB>(S, best, h, p, probs);
+        }
+    }
+}
+
+// Top-1 only: NT 32-pixel tiles per wave at once (each weight fragment read
+// from LDS feeds NT MFMAs), logits consumed block by block. Per block a lane
+// takes the maximum of its 16 logits; when it beats the running maximum, the
+// class is the first position of that maximum in the block (KEEP: the
+// block's logits are kept and searched once at the end; otherwise the
+// position is found per block). Either way the result is the first maximum
+// along increasing class index.
+template <int KB, int NT, bool VEC8, bool KEEP>
+__global__ void __launch_bounds__(256)
+k_decode_mlp_top1(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
+                  const float *__restrict__ params, int32_t *__restrict__ top1)
+{
+    __shared__ MlpLds L;
+    mlp_stage_weights<KB>(params, L);
+    __syncthreads();
+    const int lane = legs_lane(), wave = threadIdx.x / LEGS_WAVE, h = lane >> 5;
+    const int64_t groups = (P + 32 * NT - 1) / (32 * NT);
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    for (int64_t g = (int64_t)blockIdx.x * 4 + wave; g < groups; g += stride) {
+        int off = 0;
+        asm volatile("" : "+s"(off));   // fragments are re-read from LDS every group
+        legs_bf16x8 x[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int64_t p = (g * NT + t) * 32 + (lane & 31);
+            float v[LEGS_MLP_IN];
+            if (h == 0 && p < P) {
+                if constexpr (VEC8) {
+                    const float4 a = reinterpret_cast<const float4 *>(feat)[2 * p];
+                    const float4 b = reinterpret_cast<const float4 *>(feat)[2 * p + 1];
+                    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+                    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < LEGS_MLP_IN; ++e) v[e] = ldfeat(feat, p, e, cs, ps);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < LEGS_MLP_IN; ++e) v[e] = 0.0f;
+            }
+            x[t] = mlp_input(v, h);
+        }
+        legs_bf16x8 h2[NT][4];
+        mlp_hidden<NT>(L, off, x, h2);
+        float best[NT];
+        int sb[NT];                       // KEEP: block of the maximum; else its class
+        f32x16 kept[KEEP ? NT : 1];
+#pragma unroll
+        for (int mb = 0; mb < KB; ++mb) {
+            f32x16 z[NT];
+            mlp_logits_block<NT>(L, off, mb, h2, z);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                float m = z[t][0];
+#pragma unroll
+                for (int r = 1; r < 16; ++r) m = fmaxf(m, z[t][r]);
+                const bool upd = mb == 0 || m > best[t];
+                best[t] = upd ? m : best[t];
+                if constexpr (KEEP) {
+                    sb[t] = upd ? mb : sb[t];
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) kept[t][r] = upd ? z[t][r] : kept[t][r];
+                } else {
+                    int pos = 15;
+#pragma unroll
+                    for (int r = 14; r >= 0; --r) pos = z[t][r] == m ? r : pos;
+                    sb[t] = upd ? 32 * mb + drow(pos, h) : sb[t];
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            int k = sb[t];
+            if constexpr (KEEP) {
+                int pos = 15;
+#pragma unroll
+                for (int r = 14; r >= 0; --r) pos = kept[t][r] == best[t] ? r : pos;
+                k = 32 * sb[t] + drow(pos, h);
+            }
+            float bv = best[t];
+            argmax_pair(bv, k);
+            const int64_t p = (g * NT + t) * 32 + (lane & 31);
+            if (h == 0 && p < P) top1[p] = k;
         }
     }
 }
@@ -350,12 +439,28 @@ int32_t legs_launch_decode_mlp(legs_ctx *ctx, const float *feat, int64_t P, int6
                                int32_t *top1, hipStream_t s)
 {
     if (P == 0) return LEGS_OK;
-    const int grid = decode_grid(ctx, P, 32 * 4);
-    switch (K) {
-    case 32: hipLaunchKernelGGL(k_decode_mlp<1>, dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, probs, top1); break;
-    case 64: hipLaunchKernelGGL(k_decode_mlp<2>, dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, probs, top1); break;
-    case 128: hipLaunchKernelGGL(k_decode_mlp<4>, dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, probs, top1); break;
-    default: return legs_set_error(ctx, LEGS_ERR_ARG, "K must be 32, 64 or 128");
+    if (K != 32 && K != 64 && K != 128) return legs_set_error(ctx, LEGS_ERR_ARG, "K must be 32, 64 or 128");
+    if (probs) {
+        const int grid = decode_grid(ctx, P, 32 * 4);
+        switch (K) {
+        case 32: hipLaunchKernelGGL(k_decode_mlp<1>, dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, probs, top1); break;
+        case 64: hipLaunchKernelGGL(k_decode_mlp<2>, dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, probs, top1); break;
+        default: hipLaunchKernelGGL(k_decode_mlp<4>, dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, probs, top1); break;
+        }
+    } else {
+        constexpr int NT = 2;
+        constexpr bool KEEP = true;
+        const int grid = decode_grid(ctx, P, 32 * NT * 4);
+        const bool vec8 = cs == 1 && ps == LEGS_MLP_IN && (reinterpret_cast<uintptr_t>(feat) & 15) == 0;
+#define LEGS_MLP_TOP1(KB)                                                                             \
+        if (vec8) hipLaunchKernelGGL((k_decode_mlp_top1<KB, NT, true, KEEP>), dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, top1); \
+        else hipLaunchKernelGGL((k_decode_mlp_top1<KB, NT, false, KEEP>), dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, top1);
+        switch (K) {
+        case 32: LEGS_MLP_TOP1(1) break;
+        case 64: LEGS_MLP_TOP1(2) break;
+        default: LEGS_MLP_TOP1(4) break;
+        }
+#undef LEGS_MLP_TOP1
     }
     LEGS_CHECK_LAUNCH(ctx);
     return LEGS_OK;

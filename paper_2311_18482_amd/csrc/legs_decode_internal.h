@@ -20,21 +20,29 @@
 typedef __attribute__((ext_vector_type(8))) __bf16 legs_bf16x8;
 typedef __attribute__((ext_vector_type(16))) float legs_f32x16;
 
-// Per-lane MFMA fragments of every layer (bf16x8 = 16 bytes per lane) and
-// the biases in accumulator layout [block][lane half][register].
+// Per-lane MFMA fragments of every layer (bf16x8 = 16 bytes per lane), in LDS.
+//   w1[mb]        layer 1, block mb: k-slots 0..7 (lower lane half) = W1 row,
+//                 k-slots 8..10 (upper half) = the bias b1 split into three
+//                 bf16 parts, rest 0
+//   w2, w3        layers 2 and 3, [block][k-step]
+//   bb2, bb3      the biases of layers 2 and 3 as an A operand: k-slots 8..10
+//                 = the three bf16 parts of the bias, rest 0
+// The three parts hi = bf16(b), mid = bf16(b - hi), lo = bf16(b - hi - mid)
+// sum to b exactly (8 + 8 + 8 significant bits cover float32's 24), so an
+// MFMA against the "bias ones" B operand (k-slots 8..10 = 1) yields the
+// float32 bias in every accumulator row: the biases cost no registers, no
+// VALU work and one 1 KB fragment per block.
 struct MlpLds {
     legs_bf16x8 w1[2 * 64];
     legs_bf16x8 w2[2 * 4 * 64];
     legs_bf16x8 w3[4 * 4 * 64];
-    float b1[2 * 2 * 16];
-    float b2[2 * 2 * 16];
-    float b3[4 * 2 * 16];
+    legs_bf16x8 bb2[2 * 64];
+    legs_bf16x8 bb3[4 * 64];
 };
 
 template <int KB>
 struct MlpTile {
-    legs_bf16x8 x;          // bf16 input (k-slots of the lower half)
-    legs_f32x16 z1[2], z2[2];
+    legs_bf16x8 x;          // bf16 input (k-slots of the lower half), bias ones (upper half)
     legs_bf16x8 h1[4], h2[4];
     legs_f32x16 z3[KB];     // logits, class 32 b + 8 (r / 4) + 4 (lane / 32) + r % 4
 };
@@ -70,6 +78,27 @@ __device__ __forceinline__ float legs_ldfeat(const float *__restrict__ f, int64_
     return f[(int64_t)c * cs + p * ps];
 }
 
+// The B operand of the bias MFMAs (and the upper half of layer 1's input):
+// k-slots 8..10 = 1 in the upper lane half, 0 elsewhere.
+__device__ __forceinline__ legs_bf16x8 mlp_bias_ones(int h)
+{
+    legs_bf16x8 o = {};
+    if (h) {
+        o[0] = (__bf16)1.0f;
+        o[1] = (__bf16)1.0f;
+        o[2] = (__bf16)1.0f;
+    }
+    return o;
+}
+
+__device__ __forceinline__ void legs_split3(float b, __bf16 &hi, __bf16 &mid, __bf16 &lo)
+{
+    hi = (__bf16)b;
+    const float r1 = b - (float)hi;
+    mid = (__bf16)r1;
+    lo = (__bf16)(r1 - (float)mid);
+}
+
 template <int KB>
 __device__ __forceinline__ void mlp_stage_weights(const float *__restrict__ params, MlpLds &L)
 {
@@ -84,7 +113,13 @@ __device__ __forceinline__ void mlp_stage_weights(const float *__restrict__ para
     for (int i = tid; i < 2 * 64 * 8; i += nt) {
         const int e = i & 7, l = (i >> 3) & 63, mb = i >> 9;
         const int row = 32 * mb + (l & 31), hh = l >> 5;
-        w1[i] = (__bf16)(hh == 0 ? W1[row * LEGS_MLP_IN + e] : 0.0f);
+        if (hh == 0) {
+            w1[i] = (__bf16)W1[row * LEGS_MLP_IN + e];
+        } else {
+            __bf16 p[3];
+            legs_split3(b1[row], p[0], p[1], p[2]);
+            w1[i] = e < 3 ? p[e] : (__bf16)0.0f;
+        }
     }
     for (int i = tid; i < 2 * 4 * 64 * 8; i += nt) {
         const int e = i & 7, l = (i >> 3) & 63, ks = (i >> 9) & 3, mb = i >> 11;
@@ -94,69 +129,135 @@ __device__ __forceinline__ void mlp_stage_weights(const float *__restrict__ para
         const int e = i & 7, l = (i >> 3) & 63, ks = (i >> 9) & 3, mb = i >> 11;
         w3[i] = (__bf16)W3[(32 * mb + (l & 31)) * LEGS_MLP_H + legs_khid(ks, l >> 5, e)];
     }
-    for (int i = tid; i < 2 * 2 * 16; i += nt) {
-        const int r = i & 15, hh = (i >> 4) & 1, mb = i >> 5;
-        L.b1[i] = b1[32 * mb + legs_drow(r, hh)];
-        L.b2[i] = b2[32 * mb + legs_drow(r, hh)];
-    }
-    for (int i = tid; i < KB * 2 * 16; i += nt) {
-        const int r = i & 15, hh = (i >> 4) & 1, mb = i >> 5;
-        L.b3[i] = b3[32 * mb + legs_drow(r, hh)];
+    __bf16 *bb2 = reinterpret_cast<__bf16 *>(L.bb2);
+    __bf16 *bb3 = reinterpret_cast<__bf16 *>(L.bb3);
+    for (int i = tid; i < (2 + KB) * 64 * 8; i += nt) {
+        const int e = i & 7, l = (i >> 3) & 63, mb = i >> 9;
+        const bool second = mb < 2;
+        const int blk = second ? mb : mb - 2;
+        const float b = second ? b2[32 * blk + (l & 31)] : b3[32 * blk + (l & 31)];
+        __bf16 p[3];
+        legs_split3(b, p[0], p[1], p[2]);
+        const __bf16 v = ((l >> 5) == 1 && e < 3) ? p[e] : (__bf16)0.0f;
+        if (second) bb2[(blk * 64 + l) * 8 + e] = v;
+        else bb3[(blk * 64 + l) * 8 + e] = v;
     }
 }
 
-// Forward of one 32-pixel tile (pixel p = 32 tile + lane % 32).
-template <int KB>
-__device__ __forceinline__ void mlp_tile_forward(const MlpLds &L, const float *__restrict__ feat,
-                                                 int64_t p, bool valid, int64_t cs, int64_t ps,
-                                                 MlpTile<KB> &T)
+__device__ __forceinline__ legs_f32x16 legs_mfma(legs_bf16x8 a, legs_bf16x8 b, legs_f32x16 c)
 {
-    const int lane = __lane_id(), h = lane >> 5;
-    legs_bf16x8 x = {};
-    if (h == 0 && valid) {
-        // the feature divided by its Euclidean norm (zero stays zero)
-        float v[LEGS_MLP_IN], ss = 0.0f;
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// Input fragment of one pixel: the feature divided by its Euclidean norm (a
+// zero feature stays zero), bf16, in the lower lane half; the bias ones in
+// the upper half. v: the pixel's 8 features (read by the lower half only).
+__device__ __forceinline__ legs_bf16x8 mlp_input(const float (&v)[LEGS_MLP_IN], int h)
+{
+    legs_bf16x8 x = mlp_bias_ones(h);
+    if (h == 0) {
+        float ss = 0.0f;
 #pragma unroll
-        for (int e = 0; e < LEGS_MLP_IN; ++e) {
-            v[e] = legs_ldfeat(feat, p, e, cs, ps);
-            ss = fmaf(v[e], v[e], ss);
-        }
+        for (int e = 0; e < LEGS_MLP_IN; ++e) ss = fmaf(v[e], v[e], ss);
         const float nrm = sqrtf(ss);
         const float inv = nrm > 0.0f ? 1.0f / nrm : 0.0f;   // one division, then products
 #pragma unroll
         for (int e = 0; e < LEGS_MLP_IN; ++e) x[e] = (__bf16)(v[e] * inv);
     }
-    T.x = x;
+    return x;
+}
+
+// Hidden layers of NT 32-pixel tiles at once: every weight fragment read from
+// LDS feeds NT independent MFMAs. lds_off is an opaque zero the caller
+// refreshes per iteration so that the compiler keeps the fragments in LDS
+// rather than in registers.
+template <int NT>
+__device__ __forceinline__ void mlp_hidden(const MlpLds &L, int lds_off, const legs_bf16x8 (&x)[NT],
+                                           legs_bf16x8 (&h2)[NT][4])
+{
+    const int lane = __lane_id() + lds_off;
+    const legs_bf16x8 ones = mlp_bias_ones(__lane_id() >> 5);
+    legs_bf16x8 h1[NT][4];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
-        legs_f32x16 a;
+        const legs_bf16x8 a = L.w1[mb * 64 + lane];
+        legs_f32x16 z[NT];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) a[r] = L.b1[(mb * 2 + h) * 16 + r];
-        T.z1[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.w1[mb * 64 + lane], x, a, 0, 0, 0);
+        for (int t = 0; t < NT; ++t) z[t] = legs_mfma(a, x[t], (legs_f32x16){});
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            h1[t][2 * mb] = relu_bf16x8(z[t], 0);
+            h1[t][2 * mb + 1] = relu_bf16x8(z[t], 8);
+        }
     }
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) T.h1[ks] = relu_bf16x8(T.z1[ks >> 1], 8 * (ks & 1));
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
-        legs_f32x16 a;
+        const legs_f32x16 cb = legs_mfma(L.bb2[mb * 64 + lane], ones, (legs_f32x16){});
+        legs_f32x16 z[NT];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) a[r] = L.b2[(mb * 2 + h) * 16 + r];
+        for (int ks = 0; ks < 4; ++ks) {
+            const legs_bf16x8 a = L.w2[(mb * 4 + ks) * 64 + lane];
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks)
-            a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.w2[(mb * 4 + ks) * 64 + lane], T.h1[ks], a, 0, 0, 0);
-        T.z2[mb] = a;
+            for (int t = 0; t < NT; ++t) z[t] = legs_mfma(a, h1[t][ks], ks == 0 ? cb : z[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            h2[t][2 * mb] = relu_bf16x8(z[t], 0);
+            h2[t][2 * mb + 1] = relu_bf16x8(z[t], 8);
+        }
     }
+}
+
+// Logit block mb (32 classes) of NT tiles.
+template <int NT>
+__device__ __forceinline__ void mlp_logits_block(const MlpLds &L, int lds_off, int mb, const legs_bf16x8 (&h2)[NT][4],
+                                                 legs_f32x16 (&z)[NT])
+{
+    const int lane = __lane_id() + lds_off;
+    const legs_f32x16 cb = legs_mfma(L.bb3[mb * 64 + lane], mlp_bias_ones(__lane_id() >> 5), (legs_f32x16){});
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) T.h2[ks] = relu_bf16x8(T.z2[ks >> 1], 8 * (ks & 1));
+    for (int ks = 0; ks < 4; ++ks) {
+        const legs_bf16x8 a = L.w3[(mb * 4 + ks) * 64 + lane];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) z[t] = legs_mfma(a, h2[t][ks], ks == 0 ? cb : z[t]);
+    }
+}
+
+// Forward of one 32-pixel tile keeping every activation (training, and the
+// decode that writes probabilities). pixel p = 32 tile + lane % 32.
+template <int KB>
+__device__ __forceinline__ void mlp_tile_forward(const MlpLds &L, const float *__restrict__ feat,
+                                                 int64_t p, bool valid, int64_t cs, int64_t ps,
+                                                 MlpTile<KB> &T, int lds_off = 0)
+{
+    const int h = __lane_id() >> 5;
+    float v[LEGS_MLP_IN];
+#pragma unroll
+    for (int e = 0; e < LEGS_MLP_IN; ++e) v[e] = (h == 0 && valid) ? legs_ldfeat(feat, p, e, cs, ps) : 0.0f;
+    legs_bf16x8 x[1] = {mlp_input(v, h)};
+    T.x = x[0];
+    const int lane = __lane_id() + lds_off;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+        const legs_f32x16 z = legs_mfma(L.w1[mb * 64 + lane], x[0], (legs_f32x16){});
+        T.h1[2 * mb] = relu_bf16x8(z, 0);
+        T.h1[2 * mb + 1] = relu_bf16x8(z, 8);
+    }
+    const legs_bf16x8 ones = mlp_bias_ones(h);
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+        legs_f32x16 z = legs_mfma(L.bb2[mb * 64 + lane], ones, (legs_f32x16){});
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) z = legs_mfma(L.w2[(mb * 4 + ks) * 64 + lane], T.h1[ks], z);
+        T.h2[2 * mb] = relu_bf16x8(z, 0);
+        T.h2[2 * mb + 1] = relu_bf16x8(z, 8);
+    }
+    legs_bf16x8 h2[1][4] = {{T.h2[0], T.h2[1], T.h2[2], T.h2[3]}};
 #pragma unroll
     for (int mb = 0; mb < KB; ++mb) {
-        legs_f32x16 a;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) a[r] = L.b3[(mb * 2 + h) * 16 + r];
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks)
-            a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.w3[(mb * 4 + ks) * 64 + lane], T.h2[ks], a, 0, 0, 0);
-        T.z3[mb] = a;
+        legs_f32x16 z[1];
+        mlp_logits_block<1>(L, lds_off, mb, h2, z);
+        T.z3[mb] = z[0];
     }
 }
 

@@ -95,6 +95,7 @@ struct legs_sort_layout {
     int64_t part_off;      // uint32 [LEGS_TILE_CHUNKS][total_tiles] partial tile-count grids
     int64_t spart_off;     // uint32 [LEGS_TILE_CHUNKS][total_tiles] partial super-tile-count grids
     int64_t seg_off;       // uint32 [2][LEGS_SEG_MAX][256] segment digit counts and starts
+    int64_t order_off;     // uint32 [total_tiles] tiles by decreasing list length (persistent blending)
     int64_t total;
 };
 legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles = 0);

@@ -1395,6 +1395,7 @@ legs_sort_layout legs_sort_layout_for(int64_t capacity, int64_t total_tiles)
     L.part_off = o; o = up(o + 4 * (int64_t)LEGS_TILE_CHUNKS * T);
     L.spart_off = o; o = up(o + 4 * (int64_t)LEGS_TILE_CHUNKS * T);
     L.seg_off = o; o = up(o + (T > 0 ? 2 * 4 * (int64_t)LEGS_SEG_MAX * 256 : 0));
+    L.order_off = o; o = up(o + 4 * T);
     L.total = o;
     return L;
 }

@@ -79,7 +79,13 @@ def test_mlp_decode(ctx, DEC, K):
     params = DEC.mlp_pack(ws, bs).cuda()
     top, pr = DEC.decode_mlp(ctx, DEC.rowmajor_features(torch.from_numpy(f).cuda()), params, K, probs=True)
     torch.cuda.synchronize()
+    # the top-1-only kernel (logits consumed block by block), row-major and planar input
+    fd_ = torch.from_numpy(f).cuda()
+    top_r, _ = DEC.decode_mlp(ctx, DEC.rowmajor_features(fd_), params, K)
+    top_p, _ = DEC.decode_mlp(ctx, (fd_.t().contiguous(), n, n, 1), params, K)
+    torch.cuda.synchronize()
     top, pr = top.cpu().numpy(), pr.cpu().numpy()
+    assert np.array_equal(top_r.cpu().numpy(), top) and np.array_equal(top_p.cpu().numpy(), top)
     p_ref = D.softmax(ref["logits"])
     ok = ~ref["ambiguous"]
     assert ok.mean() > 0.5, ok.mean()
