@@ -262,18 +262,27 @@ int32_t legs_decode_folded(legs_ctx *ctx, const float *feat, int64_t P, int64_t 
                            int64_t p_stride, const float *folded, int32_t K, float *probs,
                            int32_t *top1, void *stream);
 
-/* Learned decode softmax(D_MLP(f / |f|)), D_MLP = 8 -> 64 -> 64 -> K
- * per-pixel linear layers with ReLU (1x1 convolutions, the pattern of
- * Table 3) applied to the feature divided by its Euclidean norm (a zero
- * feature stays zero; the codes depend only on the direction). params are
- * float32 masters packed W1 [64][8], b1 [64], W2 [64][64], b2 [64],
+/* Learned decode softmax(D_MLP(R_s)) of Sec. 3.4.1, Eq. 8 (and the
+ * supplementary inference equation), D_MLP = 8 -> 64 -> 64 -> K per-pixel
+ * linear layers with ReLU (1x1 convolutions, the pattern of Table 3). params
+ * are float32 masters packed W1 [64][8], b1 [64], W2 [64][64], b2 [64],
  * W3 [K][64], b3 [K]; weights, input and hidden activations are rounded to
- * bf16 (nearest even), accumulation and biases are float32. Training
- * (legs_mlp_grad, legs_mlp_train_step) uses the same forward. */
+ * bf16 (nearest even), accumulation and biases are float32.
+ * mlp_flags: LEGS_MLP_NORMALIZE_INPUT feeds the decoder the feature divided
+ * by its Euclidean norm (a zero feature stays zero) instead of the feature
+ * itself: the plain decode's codes (Eq. 4's cosine search) depend only on the
+ * feature's direction, and a decoder given the direction reaches 99 % top-1
+ * agreement with them where one given the raw feature does not (this is a
+ * reading beyond Eq. 8, which applies the decoder to R_s directly). Every
+ * call that runs the decoder (decode, gradient, training step, semantic loss)
+ * takes the same flags, and the same parameters must be used with the same
+ * flags. Unknown bits: LEGS_ERR_ARG. With probs == NULL only top1 is written
+ * (a kernel that never holds all K logits). */
+#define LEGS_MLP_NORMALIZE_INPUT 1
 int64_t legs_mlp_param_count(int32_t K);
 int32_t legs_decode_mlp(legs_ctx *ctx, const float *feat, int64_t P, int64_t c_stride,
-                        int64_t p_stride, const float *params, int32_t K, float *probs,
-                        int32_t *top1, void *stream);
+                        int64_t p_stride, const float *params, int32_t K, int32_t mlp_flags,
+                        float *probs, int32_t *top1, void *stream);
 
 /* Gradient of the mean cross-entropy (Eq. 9) of B pixels against labels
  * [B] int32 in [0, K): grad [legs_mlp_param_count(K)] is overwritten, loss [1]
@@ -281,8 +290,29 @@ int32_t legs_decode_mlp(legs_ctx *ctx, const float *feat, int64_t P, int64_t c_s
  * workspace: legs_mlp_workspace_bytes(B, K) bytes of device memory. */
 int64_t legs_mlp_workspace_bytes(int64_t B, int32_t K);
 int32_t legs_mlp_grad(legs_ctx *ctx, const float *feat, int64_t B, int64_t c_stride,
-                      int64_t p_stride, const int32_t *labels, int32_t K, const float *params,
-                      void *workspace, float *grad, float *loss, void *stream);
+                      int64_t p_stride, const int32_t *labels, int32_t K, int32_t mlp_flags,
+                      const float *params, void *workspace, float *grad, float *loss, void *stream);
+
+/* Semantic loss of Sec. 3.4.2 over the P pixels of one view (Eqs. 10-12):
+ *   L_CE = sum_px CE(softmax(D_MLP(R_s)), M) (1 - R_u) / (H W),
+ *   L_u  = sum_px R_u / (H W),   L_s = lambda_CE L_CE + lambda_u L_u,
+ * with D_MLP the decoder of legs_decode_mlp (same params and mlp_flags),
+ * labels = M [P] int32 in [0, K) and inv_hw = 1 / (H W). feat = R_s is read
+ * like the decode calls (c_stride, p_stride); ru [P] = R_u (contiguous, e.g.
+ * the uncertainty plane of legs_render_forward's output). Writes
+ * d_feat = dL_s/dR_s (element (p, c) at d_feat[c * d_c_stride + p * d_p_stride],
+ * e.g. into the semantic planes of the d_out handed to legs_render_backward)
+ * and d_ru [P] = dL_s/dR_u = (lambda_u - lambda_CE CE_p) / (H W); accumulates
+ * (+=) the decoder's parameter gradient into grad [legs_mlp_param_count(K)]
+ * and L_s into loss [1] (the caller zeroes both; one call per view).
+ * workspace: legs_mlp_workspace_bytes(P, K) bytes. Straight-through for the
+ * bf16 roundings. */
+int32_t legs_semantic_loss_grad(legs_ctx *ctx, const float *feat, const float *ru, int64_t P,
+                                int64_t c_stride, int64_t p_stride, const int32_t *labels,
+                                int32_t K, int32_t mlp_flags, const float *params, float lambda_ce,
+                                float lambda_u, float inv_hw, void *workspace, float *grad,
+                                float *d_feat, int64_t d_c_stride, int64_t d_p_stride, float *d_ru,
+                                float *loss, void *stream);
 
 /* ---- optimisation (Sec. 4: Adam, lr 1e-3, betas (0.9, 0.999)) ------------- */
 
@@ -309,9 +339,10 @@ int32_t legs_adam(legs_ctx *ctx, const legs_adam_group *groups, int32_t n_groups
 /* One decoder training step: legs_mlp_grad, then legs_adam on params with
  * moment buffers m, v [legs_mlp_param_count(K)]; grad is scratch. */
 int32_t legs_mlp_train_step(legs_ctx *ctx, const float *feat, int64_t B, int64_t c_stride,
-                            int64_t p_stride, const int32_t *labels, int32_t K, float *params,
-                            float *m, float *v, float *grad, int32_t step, float lr, float beta1,
-                            float beta2, float eps, void *workspace, float *loss, void *stream);
+                            int64_t p_stride, const int32_t *labels, int32_t K, int32_t mlp_flags,
+                            float *params, float *m, float *v, float *grad, int32_t step, float lr,
+                            float beta1, float beta2, float eps, void *workspace, float *loss,
+                            void *stream);
 
 /* Per view: mean |out - target| over the first n_fit channels (RGB and s_G)
  * plus lambda_u times the mean of the remaining channels (R_u, Eq. 11),

@@ -53,11 +53,13 @@ def decode_plain(feat, proj, codebook):
     return probs, top1
 
 
-def mlp_forward(feat, weights, biases, amb_tol=2e-6):
+def mlp_forward(feat, weights, biases, amb_tol=2e-6, normalize=True):
     """Per-pixel MLP with ReLU between layers. weights[l] is [out, in] (float32
-    master), biases[l] [out] (float32). The feature is first divided by its
-    Euclidean norm (a zero feature stays zero): the codes it is trained to
-    predict depend only on the feature's direction (cosine scores, Eq. 4).
+    master), biases[l] [out] (float32). With normalize (the default) the
+    feature is first divided by its Euclidean norm (a zero feature stays
+    zero): the codes it is trained to predict depend only on the feature's
+    direction (cosine scores, Eq. 4); without it the decoder sees R_s itself,
+    as Eq. 8 writes it.
     Returns a dict with the bf16-rounded input, pre-activations z_l,
     post-activations h_l and float64 logits.
 
@@ -66,8 +68,11 @@ def mlp_forward(feat, weights, biases, amb_tol=2e-6):
     ~1e-7 relative) may round such a value to the other neighbour, so those
     pixels are checked only loosely against an implementation in float32."""
     f = np.asarray(feat, np.float32).astype(np.float64)
-    nrm = np.sqrt(np.sum(f * f, axis=1, keepdims=True))
-    u = np.where(nrm > 0.0, f / np.where(nrm > 0.0, nrm, 1.0), 0.0)
+    if normalize:
+        nrm = np.sqrt(np.sum(f * f, axis=1, keepdims=True))
+        u = np.where(nrm > 0.0, f / np.where(nrm > 0.0, nrm, 1.0), 0.0)
+    else:
+        u = f
     x = bf16(u)
     hs = [x]
     zs = []
@@ -93,10 +98,10 @@ def softmax(z):
     return e / e.sum(axis=1, keepdims=True)
 
 
-def mlp_grads(feat, labels, weights, biases):
+def mlp_grads(feat, labels, weights, biases, normalize=True):
     """Mean cross-entropy over the batch and its gradients w.r.t. every weight
     and bias (straight-through for the bf16 roundings)."""
-    fw = mlp_forward(feat, weights, biases)
+    fw = mlp_forward(feat, weights, biases, normalize=normalize)
     B = feat.shape[0]
     p = softmax(fw["logits"])
     y = np.asarray(labels, np.int64)
@@ -153,3 +158,58 @@ def l1_loss_grad(out_flat, target_flat, cams, n_channels, d_sem, lambda_u=1.0):
             g[c] = lambda_u / hw
         off += n_channels * hw
     return loss, grad
+
+
+def semantic_loss_grad(feat, ru, labels, weights, biases, inv_hw, lambda_ce=1.0, lambda_u=1.0,
+                       round_bf16=True, normalize=True):
+    """Semantic loss of Sec. 3.4.2 for the pixels of one view and its gradients:
+      L_CE = sum_px CE(softmax(D_MLP(R_s)), M) (1 - R_u) / (H W)      (Eq. 10)
+      L_u  = sum_px R_u / (H W)                                        (Eq. 11)
+      L_s  = lambda_CE L_CE + lambda_u L_u                             (Eq. 12)
+    feat [P, 8] = R_s, ru [P] = R_u, labels [P] = M (code indices), inv_hw =
+    1 / (H W) of the view. The decoder is mlp_forward's (input divided by its
+    norm, bf16 roundings emulated unless round_bf16 is False). Gradients pass
+    straight through the roundings. Returns dict with loss, ce [P],
+    d_feat [P, 8] = dL_s/dR_s, d_ru [P] = dL_s/dR_u, gW, gb (lists per layer)."""
+    f = np.asarray(feat).astype(np.float64)     # float32 maps promote exactly
+    u_r = np.asarray(ru).astype(np.float64)
+    y = np.asarray(labels, np.int64)
+    P = f.shape[0]
+    nrm = np.sqrt(np.sum(f * f, axis=1, keepdims=True))
+    u = np.where(nrm > 0.0, f / np.where(nrm > 0.0, nrm, 1.0), 0.0) if normalize else f
+    rnd = bf16 if round_bf16 else (lambda a: np.asarray(a, np.float64))
+    h = rnd(u)
+    hs, zs, Ws = [h], [], []
+    L = len(weights)
+    for l in range(L):
+        W = rnd(np.asarray(weights[l], np.float32).astype(np.float64))
+        b = np.asarray(biases[l], np.float32).astype(np.float64)
+        Ws.append(W)
+        z = h @ W.T + b
+        zs.append(z)
+        if l < L - 1:
+            h = rnd(np.maximum(z, 0.0))
+            hs.append(h)
+    p = softmax(zs[-1])
+    ce = -np.log(p[np.arange(P), y])
+    wpx = lambda_ce * (1.0 - u_r) * inv_hw                # weight of each pixel's CE
+    loss = float(np.sum(wpx * ce) + lambda_u * inv_hw * np.sum(u_r))
+    d_ru = (-lambda_ce * ce + lambda_u) * inv_hw
+    dz = p.copy()
+    dz[np.arange(P), y] -= 1.0
+    dz *= wpx[:, None]
+    gW, gb = [None] * L, [None] * L
+    for l in range(L - 1, -1, -1):
+        gW[l] = dz.T @ hs[l]
+        gb[l] = dz.sum(axis=0)
+        dh = dz @ Ws[l]
+        if l > 0:
+            dz = dh * (zs[l - 1] > 0.0)
+    # dh is now dL/d(decoder input); a normalised input f / |f| has the
+    # Jacobian (I - u u^T) / |f| (zero for a zero feature)
+    if normalize:
+        d_feat = np.where(nrm > 0.0,
+                          (dh - np.sum(dh * u, axis=1, keepdims=True) * u) / np.where(nrm > 0.0, nrm, 1.0), 0.0)
+    else:
+        d_feat = dh
+    return dict(loss=loss, ce=ce, d_feat=d_feat, d_ru=d_ru, gW=gW, gb=gb)

@@ -487,18 +487,25 @@ double oracle_render_region(int64_t n, const oproj_t *pv, const ocam_t *cam, con
  * and channel gradients dch[n][C] (summed over views by repeated calls).
  * out_c = sum_k alpha_k T_k ch_kc with T_k = prod_{j<k} (1 - alpha_j), so
  * d out_c / d alpha_k = T_k ch_kc - (sum_{j>k} alpha_j T_j ch_jc) / (1 - alpha_k). */
+/* mag2d [n][6] and magch [n][C] (optional, accumulated like grad2d and dch):
+ * the same sums with every term replaced by its magnitude (|G_c|, |ch| and the
+ * absolute values of the power's derivatives), i.e. sum |term| for each
+ * gradient: the scale of the rounding error of any floating-point evaluation
+ * of these sums. */
 void oracle_render_backward(int64_t n, const oproj_t *pv, const ocam_t *cam, const oopts_t *o,
                             const double *ch, int32_t C, const uint32_t *ids,
                             const uint32_t *ranges, int64_t tile_offset, const double *G,
-                            const uint32_t *flip_mask, double *grad2d, double *dch)
+                            const uint32_t *flip_mask, double *grad2d, double *dch,
+                            double *mag2d, double *magch)
 {
     const int64_t HW = (int64_t)cam->W * cam->H;
     int nth = 1;
 #ifdef _OPENMP
     nth = omp_get_max_threads();
 #endif
-    double *priv2 = (double *)calloc((size_t)nth * (size_t)n * 6, sizeof(double));
-    double *privc = (double *)calloc((size_t)nth * (size_t)n * (size_t)C, sizeof(double));
+    const int want_mag = mag2d != NULL && magch != NULL;
+    double *priv2 = (double *)calloc((size_t)nth * (size_t)n * 6 * (want_mag ? 2 : 1), sizeof(double));
+    double *privc = (double *)calloc((size_t)nth * (size_t)n * (size_t)C * (want_mag ? 2 : 1), sizeof(double));
 #pragma omp parallel
     {
         int tid = 0;
@@ -507,9 +514,11 @@ void oracle_render_backward(int64_t n, const oproj_t *pv, const ocam_t *cam, con
 #endif
         double *g2 = priv2 + (size_t)tid * (size_t)n * 6;
         double *gc = privc + (size_t)tid * (size_t)n * (size_t)C;
+        double *m2 = want_mag ? priv2 + ((size_t)nth + (size_t)tid) * (size_t)n * 6 : NULL;
+        double *mc = want_mag ? privc + ((size_t)nth + (size_t)tid) * (size_t)n * (size_t)C : NULL;
         int64_t cap = 0;
         oblend_t *rec = NULL;
-        double *suffix = NULL;
+        double *suffix = NULL, *suffix_abs = NULL;
 #pragma omp for schedule(dynamic, 256)
         for (int64_t q = 0; q < HW; ++q) {
             const int i = (int)(q % cam->W), j = (int)(q / cam->W);
@@ -519,6 +528,7 @@ void oracle_render_backward(int64_t n, const oproj_t *pv, const ocam_t *cam, con
                 cap = len;
                 rec = (oblend_t *)realloc(rec, sizeof(oblend_t) * (size_t)cap);
                 suffix = (double *)realloc(suffix, sizeof(double) * (size_t)cap * (size_t)C);
+                if (want_mag) suffix_abs = (double *)realloc(suffix_abs, sizeof(double) * (size_t)cap * (size_t)C);
             }
             double acc[64];
             double T; int64_t l, nr;
@@ -533,15 +543,28 @@ void oracle_render_backward(int64_t n, const oproj_t *pv, const ocam_t *cam, con
                 for (int cc = 0; cc < C; ++cc)
                     suffix[k * C + cc] = suffix[(k + 1) * C + cc] + e->alpha * e->T * cg[cc];
             }
+            if (want_mag) {
+                for (int cc = 0; cc < C; ++cc) suffix_abs[(nr - 1) * C + cc] = 0.0;
+                for (int64_t k = nr - 2; k >= 0; --k) {
+                    const oblend_t *e = rec + k + 1;
+                    const double *cg = ch + (int64_t)e->g * C;
+                    for (int cc = 0; cc < C; ++cc)
+                        suffix_abs[k * C + cc] = suffix_abs[(k + 1) * C + cc] + e->alpha * e->T * fabs(cg[cc]);
+                }
+            }
             for (int64_t k = 0; k < nr; ++k) {
                 const oblend_t *e = rec + k;
                 const oproj_t *p = pv + e->g;
                 const double *cg = ch + (int64_t)e->g * C;
-                double dalpha = 0.0;
+                double dalpha = 0.0, dalpha_abs = 0.0;
                 for (int cc = 0; cc < C; ++cc) {
                     const double Gc = G[(int64_t)cc * HW + q];
                     gc[(int64_t)e->g * C + cc] += e->alpha * e->T * Gc;
                     dalpha += Gc * (e->T * cg[cc] - suffix[k * C + cc] / (1.0 - e->alpha));
+                    if (want_mag) {
+                        mc[(int64_t)e->g * C + cc] += e->alpha * e->T * fabs(Gc);
+                        dalpha_abs += fabs(Gc) * (e->T * fabs(cg[cc]) + suffix_abs[k * C + cc] / (1.0 - e->alpha));
+                    }
                 }
                 if (e->clamped) continue;
                 double *d = g2 + (int64_t)e->g * 6;
@@ -549,22 +572,39 @@ void oracle_render_backward(int64_t n, const oproj_t *pv, const ocam_t *cam, con
                 const double dpow = dalpha * p->sig * e->ep;
                 const double dx = e->dx, dy = e->dy;
                 const double raw = -0.5 * (p->A * dx * dx + p->C * dy * dy) - p->B * dx * dy;
+                if (want_mag) m2[(int64_t)e->g * 6 + 5] += dalpha_abs * e->ep;
                 if (raw > 0.0) continue;                /* power clamped at 0 */
                 d[0] += dpow * (-(p->A * dx + p->B * dy));
                 d[1] += dpow * (-(p->B * dx + p->C * dy));
                 d[2] += dpow * (-0.5 * dx * dx);
                 d[3] += dpow * (-dx * dy);
                 d[4] += dpow * (-0.5 * dy * dy);
+                if (want_mag) {
+                    double *mm = m2 + (int64_t)e->g * 6;
+                    const double ap = dalpha_abs * p->sig * e->ep;
+                    mm[0] += ap * (fabs(p->A * dx) + fabs(p->B * dy));
+                    mm[1] += ap * (fabs(p->B * dx) + fabs(p->C * dy));
+                    mm[2] += ap * 0.5 * dx * dx;
+                    mm[3] += ap * fabs(dx * dy);
+                    mm[4] += ap * 0.5 * dy * dy;
+                }
             }
         }
         free(rec);
         free(suffix);
+        free(suffix_abs);
     }
     for (int t = 0; t < nth; ++t) {
         const double *g2 = priv2 + (size_t)t * (size_t)n * 6;
         const double *gc = privc + (size_t)t * (size_t)n * (size_t)C;
         for (int64_t x = 0; x < n * 6; ++x) grad2d[x] += g2[x];
         for (int64_t x = 0; x < n * C; ++x) dch[x] += gc[x];
+        if (want_mag) {
+            const double *m2 = priv2 + ((size_t)nth + (size_t)t) * (size_t)n * 6;
+            const double *mc = privc + ((size_t)nth + (size_t)t) * (size_t)n * (size_t)C;
+            for (int64_t x = 0; x < n * 6; ++x) mag2d[x] += m2[x];
+            for (int64_t x = 0; x < n * C; ++x) magch[x] += mc[x];
+        }
     }
     free(priv2);
     free(privc);

@@ -67,7 +67,7 @@ def lib():
                                            i32, i32, i32, P, P, P, P]
         L.oracle_render_region.restype = ct.c_double
         L.oracle_render_backward.argtypes = [i64, P, ct.POINTER(OCam), ct.POINTER(OOpts), P, i32, P,
-                                             P, i64, P, P, P, P]
+                                             P, i64, P, P, P, P, P, P]
         L.oracle_render_backward.restype = None
         L.oracle_project_backward.argtypes = [i64, P, P, P, P, ct.POINTER(OCam), ct.POINTER(OOpts),
                                               P, P, P, P, P]
@@ -188,8 +188,11 @@ def render_region(proj_v, cam, opts, channels, x0, y0, w, h, G=None):
 
 
 def render_backward_view(proj_v, cam, opts, channels, ids, ranges, tile_offset, G_view,
-                         flip_mask=None, dch=None):
-    """Returns (grad2d [n, 6] for this view, dch [n, C] accumulated)."""
+                         flip_mask=None, dch=None, mag=None):
+    """Returns (grad2d [n, 6] for this view, dch [n, C] accumulated). mag
+    (optional dict with "g2" [n, 6] and "channels" [n, C]) receives the
+    magnitude sums sum |term| of those gradients (g2 overwritten, channels
+    accumulated)."""
     ch = np.ascontiguousarray(channels, np.float64)
     n, C = ch.shape
     c = make_cam(cam)
@@ -200,8 +203,13 @@ def render_backward_view(proj_v, cam, opts, channels, ids, ranges, tile_offset, 
     fm = None if flip_mask is None else np.ascontiguousarray(flip_mask, np.uint32)
     pv = np.ascontiguousarray(proj_v)
     idv = np.ascontiguousarray(ids if len(ids) else np.zeros(1, np.uint32))
+    m2 = mc = None
+    if mag is not None:
+        mag["g2"] = m2 = np.zeros((n, 6))
+        mc = mag.setdefault("channels", np.zeros((n, C)))
     lib().oracle_render_backward(n, _p(pv), ct.byref(c), ct.byref(opts), _p(ch), C, _p(idv),
-                                 _p(ranges), int(tile_offset), _p(Gd), _p(fm), _p(g2), _p(dch))
+                                 _p(ranges), int(tile_offset), _p(Gd), _p(fm), _p(g2), _p(dch),
+                                 _p(m2), _p(mc))
     return g2, dch
 
 
@@ -243,13 +251,28 @@ def forward(scene, cams, opts, params: Params | None = None):
                 views=views)
 
 
-def backward(scene, cams, opts, fwd, G_flat, flip_masks=None):
-    """Gradients of sum(G * out) w.r.t. every per-Gaussian parameter (float64)."""
+GEO_GROUPS = ("mean", "log_scale", "quat", "opacity_logit")
+
+
+def backward(scene, cams, opts, fwd, G_flat, flip_masks=None, magnitudes=False):
+    """Gradients of sum(G * out) w.r.t. every per-Gaussian parameter (float64).
+
+    With magnitudes, also acc["mag"]: for every gradient entry the scale of
+    the rounding error of a floating-point evaluation of it. The blend sums
+    are the only long sums of the gradient (every other step is a fixed short
+    formula), so this is sum |term| of the per-view screen-space and channel
+    sums, carried to the per-Gaussian groups through the magnitude of the
+    projection's chain rule: for each view and screen-space component k,
+    |J e_k| (the chain rule applied to a unit gradient in k) times the
+    magnitude sum of component k."""
     params = fwd["params"]
     n, C = scene.channels.shape
     dch = np.zeros((n, C))
     acc = None
     grad2d_all = []
+    mag = dict(channels=np.zeros((n, C))) if magnitudes else None
+    mags = {k: 0.0 for k in GEO_GROUPS}
+    mag2d_all = []
     off = 0
     for v, cam in enumerate(cams):
         hw = cam.width * cam.height
@@ -257,9 +280,19 @@ def backward(scene, cams, opts, fwd, G_flat, flip_masks=None):
         off += C * hw
         fm = None if flip_masks is None else flip_masks[v]
         g2, dch = render_backward_view(fwd["proj"][v], cam, opts, scene.channels, fwd["ids"],
-                                       fwd["ranges"], fwd["offsets"][v], Gv, fm, dch)
+                                       fwd["ranges"], fwd["offsets"][v], Gv, fm, dch, mag)
         grad2d_all.append(g2)
         acc = project_backward(params, cam, opts, g2, acc)
+        if magnitudes:
+            mag2d_all.append(mag["g2"])
+            for k in range(6):
+                unit = np.zeros((n, 6))
+                unit[:, k] = 1.0
+                col = project_backward(params, cam, opts, unit)
+                for grp in GEO_GROUPS:
+                    mags[grp] = mags[grp] + np.abs(col[grp]) * mag["g2"][:, k].reshape((n,) + (1,) * (col[grp].ndim - 1))
     acc["channels"] = dch
     acc["grad2d"] = np.stack(grad2d_all, axis=0)
+    if magnitudes:
+        acc["mag"] = dict(mags, channels=mag["channels"], grad2d=np.stack(mag2d_all, axis=0))
     return acc

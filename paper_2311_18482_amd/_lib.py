@@ -20,6 +20,7 @@ LEGS_MAX_CHANNELS = 64
 LEGS_FLAG_PERSISTENT = 1
 LEGS_FLAG_FULL_SORT = 2
 LEGS_FLAG_FULL_BOX = 4
+LEGS_MLP_NORMALIZE_INPUT = 1
 
 
 class LegsError(RuntimeError):
@@ -95,12 +96,14 @@ _SIGS = {
     "legs_decode_fold": (I32, [P, P, I32, P, I32, P, P]),
     "legs_decode_folded": (I32, [P, P, I64, I64, I64, P, I32, P, P, P]),
     "legs_mlp_param_count": (I64, [I32]),
-    "legs_decode_mlp": (I32, [P, P, I64, I64, I64, P, I32, P, P, P]),
+    "legs_decode_mlp": (I32, [P, P, I64, I64, I64, P, I32, I32, P, P, P]),
     "legs_mlp_workspace_bytes": (I64, [I64, I32]),
-    "legs_mlp_grad": (I32, [P, P, I64, I64, I64, P, I32, P, P, P, P, P]),
+    "legs_mlp_grad": (I32, [P, P, I64, I64, I64, P, I32, I32, P, P, P, P, P]),
+    "legs_semantic_loss_grad": (I32, [P, P, P, I64, I64, I64, P, I32, I32, P, ct.c_float, ct.c_float,
+                                      ct.c_float, P, P, P, I64, I64, P, P, P]),
     "legs_adam": (I32, [P, ct.POINTER(AdamGroup), I32, I32, ct.c_float, ct.c_float, ct.c_float,
                         ct.c_float, P]),
-    "legs_mlp_train_step": (I32, [P, P, I64, I64, I64, P, I32, P, P, P, P, I32, ct.c_float,
+    "legs_mlp_train_step": (I32, [P, P, I64, I64, I64, P, I32, I32, P, P, P, P, I32, ct.c_float,
                                   ct.c_float, ct.c_float, ct.c_float, P, P, P]),
     "legs_l1_loss_grad": (I32, [P, P, P, P, I32, I64, I32, I32, ct.c_float, P, P, P]),
     "legs_clear": (I32, [P, P, I64, P]),

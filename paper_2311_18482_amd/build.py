@@ -30,13 +30,21 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=o
          "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
+# Per-source additions. The decoders keep MFMA accumulators in ordinary VGPRs
+# (the VGPR form of the MFMA instructions that gfx950 has): their results are
+# read by VALU code right away (ReLU and bf16 packing, the argmax), which from
+# accumulation registers would cost one extra move per value.
+EXTRA = {"decode.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+         "mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
 def _compile(src, verbose):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -326,15 +326,22 @@ int64_t legs_mlp_param_count(int32_t K)
     return LEGS_MLP_NPARAMS(K / 32);
 }
 
+static int32_t check_mlp_flags(legs_ctx *ctx, int32_t mlp_flags)
+{
+    if (mlp_flags & ~LEGS_MLP_NORMALIZE_INPUT) return legs_set_error(ctx, LEGS_ERR_ARG, "unknown mlp_flags bits");
+    return LEGS_OK;
+}
+
 int32_t legs_decode_mlp(legs_ctx *ctx, const float *feat, int64_t P, int64_t c_stride,
-                        int64_t p_stride, const float *params, int32_t K, float *probs,
-                        int32_t *top1, void *stream)
+                        int64_t p_stride, const float *params, int32_t K, int32_t mlp_flags,
+                        float *probs, int32_t *top1, void *stream)
 {
     if (!ctx) return LEGS_ERR_ARG;
     LEGS_TRY(check_feat(ctx, feat, P, c_stride, p_stride, K, top1));
+    LEGS_TRY(check_mlp_flags(ctx, mlp_flags));
     if (!params) return legs_set_error(ctx, LEGS_ERR_ARG, "NULL params");
     LEGS_TRY(use_device(ctx));
-    return legs_launch_decode_mlp(ctx, feat, P, c_stride, p_stride, params, K, probs, top1,
+    return legs_launch_decode_mlp(ctx, feat, P, c_stride, p_stride, params, K, mlp_flags, probs, top1,
                                   (hipStream_t)stream);
 }
 
@@ -345,18 +352,44 @@ int64_t legs_mlp_workspace_bytes(int64_t B, int32_t K)
 }
 
 int32_t legs_mlp_grad(legs_ctx *ctx, const float *feat, int64_t B, int64_t c_stride,
-                      int64_t p_stride, const int32_t *labels, int32_t K, const float *params,
-                      void *workspace, float *grad, float *loss, void *stream)
+                      int64_t p_stride, const int32_t *labels, int32_t K, int32_t mlp_flags,
+                      const float *params, void *workspace, float *grad, float *loss, void *stream)
 {
     if (!ctx) return LEGS_ERR_ARG;
+    LEGS_TRY(check_mlp_flags(ctx, mlp_flags));
     if (B < 0 || B > (1ll << 31)) return legs_set_error(ctx, LEGS_ERR_ARG, "B out of range");
     if (K != 32 && K != 64 && K != 128) return legs_set_error(ctx, LEGS_ERR_ARG, "K must be 32, 64 or 128");
     if (!params || !grad || !loss || (B > 0 && (!feat || !labels || !workspace)))
         return legs_set_error(ctx, LEGS_ERR_ARG, "NULL argument");
     if (c_stride < 0 || p_stride < 0) return legs_set_error(ctx, LEGS_ERR_ARG, "negative stride");
     LEGS_TRY(use_device(ctx));
-    return legs_launch_mlp_grad(ctx, feat, B, c_stride, p_stride, labels, K, params,
+    return legs_launch_mlp_grad(ctx, feat, B, c_stride, p_stride, labels, K, mlp_flags, params,
                                 static_cast<float *>(workspace), grad, loss, (hipStream_t)stream);
+}
+
+int32_t legs_semantic_loss_grad(legs_ctx *ctx, const float *feat, const float *ru, int64_t P,
+                                int64_t c_stride, int64_t p_stride, const int32_t *labels,
+                                int32_t K, int32_t mlp_flags, const float *params, float lambda_ce,
+                                float lambda_u, float inv_hw, void *workspace, float *grad,
+                                float *d_feat, int64_t d_c_stride, int64_t d_p_stride, float *d_ru,
+                                float *loss, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (P < 0 || P > (1ll << 31)) return legs_set_error(ctx, LEGS_ERR_ARG, "P out of range");
+    if (K != 32 && K != 64 && K != 128) return legs_set_error(ctx, LEGS_ERR_ARG, "K must be 32, 64 or 128");
+    LEGS_TRY(check_mlp_flags(ctx, mlp_flags));
+    if (!params || !grad || !loss ||
+        (P > 0 && (!feat || !ru || !labels || !workspace || !d_feat || !d_ru)))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "NULL argument");
+    if (c_stride < 0 || p_stride < 0 || d_c_stride < 0 || d_p_stride < 0)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "negative stride");
+    if (!(inv_hw >= 0.0f) || !(lambda_ce >= 0.0f) || !(lambda_u >= 0.0f))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "negative or NaN weight");
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_semantic_loss_grad(ctx, feat, ru, P, c_stride, p_stride, labels, K, mlp_flags,
+                                          params, lambda_ce, lambda_u, inv_hw,
+                                          static_cast<float *>(workspace), grad, d_feat, d_c_stride,
+                                          d_p_stride, d_ru, loss, (hipStream_t)stream);
 }
 
 int32_t legs_adam(legs_ctx *ctx, const legs_adam_group *groups, int32_t n_groups, int32_t step,
@@ -380,12 +413,13 @@ int32_t legs_adam(legs_ctx *ctx, const legs_adam_group *groups, int32_t n_groups
 }
 
 int32_t legs_mlp_train_step(legs_ctx *ctx, const float *feat, int64_t B, int64_t c_stride,
-                            int64_t p_stride, const int32_t *labels, int32_t K, float *params,
-                            float *m, float *v, float *grad, int32_t step, float lr, float beta1,
-                            float beta2, float eps, void *workspace, float *loss, void *stream)
+                            int64_t p_stride, const int32_t *labels, int32_t K, int32_t mlp_flags,
+                            float *params, float *m, float *v, float *grad, int32_t step, float lr,
+                            float beta1, float beta2, float eps, void *workspace, float *loss,
+                            void *stream)
 {
-    LEGS_TRY(legs_mlp_grad(ctx, feat, B, c_stride, p_stride, labels, K, params, workspace, grad,
-                           loss, stream));
+    LEGS_TRY(legs_mlp_grad(ctx, feat, B, c_stride, p_stride, labels, K, mlp_flags, params, workspace,
+                           grad, loss, stream));
     legs_adam_group g;
     g.param = params;
     g.grad = grad;

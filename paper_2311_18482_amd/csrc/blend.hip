@@ -300,6 +300,23 @@ __device__ __forceinline__ int64_t next_tile(const BlendParams &P, int64_t prev,
     return prev < 0 ? (int64_t)blockIdx.x : P.total_tiles;
 }
 
+// Next forward work item: one per workgroup, or the next queue position from
+// the persistent counter (items / parts of one tile = one queue entry).
+__device__ __forceinline__ int64_t next_item(const BlendParams &P, int64_t prev, int64_t items, int64_t *s_item)
+{
+    if (P.counter) {
+        if (threadIdx.x == 0) {
+            const uint32_t i = atomicAdd(P.counter, 1u);
+            *s_item = (int64_t)i < items ? (int64_t)i : items;
+        }
+        __syncthreads();
+        const int64_t t = *s_item;
+        __syncthreads();
+        return t;
+    }
+    return prev < 0 ? (int64_t)blockIdx.x : items;
+}
+
 // ---- forward ---------------------------------------------------------------------
 
 // Waves per SIMD the forward asks the register allocator for, with up to 12
@@ -325,14 +342,18 @@ k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
     const int B = P.batch;
     const float amax = P.amax;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / LEGS_WAVE), l = threadIdx.x % LEGS_WAVE;
-    const int part = NS == 1 ? 0 : (int)(blockIdx.x % (NS * NS));
-    const int qxi = (part % NS) * QS + w % QS, qyi = (part / NS) * QS + w / QS;   // this wave's 8 x 8 quadrant
-    const int qx0 = 8 * qxi, qy0 = 8 * qyi;
-    const int lx = qx0 + (l & 7), ly = qy0 + (l >> 3);
     const float fx = (float)(l & 7), fy = (float)(l >> 3);
-
-    for (int64_t tile = NS == 1 ? next_tile(P, -1, &s_tile) : (int64_t)(blockIdx.x / (NS * NS));
-         tile < P.total_tiles; tile = NS == 1 ? next_tile(P, tile, &s_tile) : P.total_tiles) {
+    // work items: (tile, part) pairs, the parts of a tile consecutive; one
+    // item per workgroup, or the persistent queue (heaviest tiles first)
+    constexpr int NP = NS * NS;
+    const int64_t items = P.total_tiles * NP;
+    for (int64_t item = next_item(P, -1, items, &s_tile); item < items; item = next_item(P, item, items, &s_tile)) {
+        const int64_t q = item / NP;
+        const int part = (int)(item - q * NP);
+        const int64_t tile = P.counter ? (int64_t)P.order[q] : q;
+        const int qxi = (part % NS) * QS + w % QS, qyi = (part / NS) * QS + w / QS;   // this wave's 8 x 8 quadrant
+        const int qx0 = 8 * qxi, qy0 = 8 * qyi;
+        const int lx = qx0 + (l & 7), ly = qy0 + (l >> 3);
         const TileInfo ti = tile_info<TILE>(P, tile);
         const int px = ti.tile_x0 + lx, py = ti.tile_y0 + ly;
         const bool inside = px < ti.W && py < ti.H;
@@ -716,9 +737,10 @@ int32_t launch_tile_cp(legs_ctx *ctx, bool fwd, const BlendParams &P0, float *ou
     if (lds > 65536) return legs_set_error(ctx, LEGS_ERR_UNSUPPORTED, "LDS batch too large for C");
     int64_t grid = P.total_tiles;
     if (grid <= 0) return LEGS_OK;
-    // one-per-tile forward launches at 32-pixel tiles run a workgroup per 16 x 16 part
+    // forward launches at 32-pixel tiles run a workgroup per 16 x 16 part (a
+    // part is a work item of its own, persistent or not)
     constexpr int SUB = TILE == 32 ? 16 : TILE;
-    const bool parts = fwd && SUB < TILE && !P.counter;
+    const bool parts = fwd && SUB < TILE;
     const int threads = fwd ? (parts ? SUB * SUB : TILE * TILE) : BwdShape<TILE, CP>::NT;
     if (parts) grid *= (TILE / SUB) * (TILE / SUB);
     if (P.counter) {

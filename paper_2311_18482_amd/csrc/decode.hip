@@ -256,7 +256,7 @@ k_decode_folded(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t p
 
 namespace {
 
-template <int KB>
+template <int KB, bool NORM>
 __global__ void __launch_bounds__(256)
 k_decode_mlp(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
              const float *__restrict__ params, float *__restrict__ probs,
@@ -274,7 +274,7 @@ k_decode_mlp(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
         const bool valid = p < P;
         int off = 0;
         asm volatile("" : "+s"(off));   // fragments are re-read from LDS every tile
-        mlp_tile_forward<KB>(L, feat, p, valid, cs, ps, T, off);
+        mlp_tile_forward<KB, NORM>(L, feat, p, valid, cs, ps, T, off);
         float best = -INFINITY;
         int bidx = 0x7fffffff;
         f32x16 S[KB];
@@ -303,7 +303,7 @@ k_decode_mlp(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
 // block's logits are kept and searched once at the end; otherwise the
 // position is found per block). Either way the result is the first maximum
 // along increasing class index.
-template <int KB, int NT, bool VEC8, bool KEEP>
+template <int KB, int NT, bool VEC8, bool KEEP, bool NORM>
 __global__ void __launch_bounds__(256)
 k_decode_mlp_top1(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
                   const float *__restrict__ params, int32_t *__restrict__ top1)
@@ -336,7 +336,7 @@ k_decode_mlp_top1(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t
 #pragma unroll
                 for (int e = 0; e < LEGS_MLP_IN; ++e) v[e] = 0.0f;
             }
-            x[t] = mlp_input(v, h);
+            x[t] = mlp_input<NORM>(v, h);
         }
         legs_bf16x8 h2[NT][4];
         mlp_hidden<NT>(L, off, x, h2);
@@ -435,31 +435,38 @@ int32_t legs_launch_decode_folded(legs_ctx *ctx, const float *feat, int64_t P, i
 }
 
 int32_t legs_launch_decode_mlp(legs_ctx *ctx, const float *feat, int64_t P, int64_t cs,
-                               int64_t ps, const float *params, int32_t K, float *probs,
-                               int32_t *top1, hipStream_t s)
+                               int64_t ps, const float *params, int32_t K, int32_t mlp_flags,
+                               float *probs, int32_t *top1, hipStream_t s)
 {
     if (P == 0) return LEGS_OK;
     if (K != 32 && K != 64 && K != 128) return legs_set_error(ctx, LEGS_ERR_ARG, "K must be 32, 64 or 128");
+    const bool norm = (mlp_flags & LEGS_MLP_NORMALIZE_INPUT) != 0;
     if (probs) {
         const int grid = decode_grid(ctx, P, 32 * 4);
+#define LEGS_MLP_ALL(KB)                                                                                     \
+        if (norm) hipLaunchKernelGGL((k_decode_mlp<KB, true>), dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, probs, top1); \
+        else hipLaunchKernelGGL((k_decode_mlp<KB, false>), dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, probs, top1);
         switch (K) {
-        case 32: hipLaunchKernelGGL(k_decode_mlp<1>, dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, probs, top1); break;
-        case 64: hipLaunchKernelGGL(k_decode_mlp<2>, dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, probs, top1); break;
-        default: hipLaunchKernelGGL(k_decode_mlp<4>, dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, probs, top1); break;
+        case 32: LEGS_MLP_ALL(1) break;
+        case 64: LEGS_MLP_ALL(2) break;
+        default: LEGS_MLP_ALL(4) break;
         }
+#undef LEGS_MLP_ALL
     } else {
         constexpr int NT = 2;
         constexpr bool KEEP = true;
         const int grid = decode_grid(ctx, P, 32 * NT * 4);
         const bool vec8 = cs == 1 && ps == LEGS_MLP_IN && (reinterpret_cast<uintptr_t>(feat) & 15) == 0;
-#define LEGS_MLP_TOP1(KB)                                                                             \
-        if (vec8) hipLaunchKernelGGL((k_decode_mlp_top1<KB, NT, true, KEEP>), dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, top1); \
-        else hipLaunchKernelGGL((k_decode_mlp_top1<KB, NT, false, KEEP>), dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, top1);
+#define LEGS_MLP_TOP1(KB, NORM)                                                                       \
+        if (vec8) hipLaunchKernelGGL((k_decode_mlp_top1<KB, NT, true, KEEP, NORM>), dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, top1); \
+        else hipLaunchKernelGGL((k_decode_mlp_top1<KB, NT, false, KEEP, NORM>), dim3(grid), dim3(256), 0, s, feat, P, cs, ps, params, top1);
+#define LEGS_MLP_TOP1N(KB) if (norm) { LEGS_MLP_TOP1(KB, true) } else { LEGS_MLP_TOP1(KB, false) }
         switch (K) {
-        case 32: LEGS_MLP_TOP1(1) break;
-        case 64: LEGS_MLP_TOP1(2) break;
-        default: LEGS_MLP_TOP1(4) break;
+        case 32: LEGS_MLP_TOP1N(1) break;
+        case 64: LEGS_MLP_TOP1N(2) break;
+        default: LEGS_MLP_TOP1N(4) break;
         }
+#undef LEGS_MLP_TOP1N
 #undef LEGS_MLP_TOP1
     }
     LEGS_CHECK_LAUNCH(ctx);

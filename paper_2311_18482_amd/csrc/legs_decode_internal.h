@@ -54,13 +54,18 @@ typedef __attribute__((ext_vector_type(2))) short legs_i16x2;
 // gives the same bits as rounding max(z, 0) (-0 becomes +0 either way).
 __device__ __forceinline__ legs_bf16x8 relu_bf16x8(const legs_f32x16 &z, int first)
 {
-    legs_bf16x8 h;
+    typedef __attribute__((ext_vector_type(2))) float f32x2;
+    typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+    typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+    u32x4 w;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) h[e] = (__bf16)z[first + e];
-    typedef __attribute__((ext_vector_type(8))) short i16x8;
-    i16x8 q = __builtin_bit_cast(i16x8, h);
-    q = __builtin_elementwise_max(q, (i16x8){0, 0, 0, 0, 0, 0, 0, 0});
-    return __builtin_bit_cast(legs_bf16x8, q);
+    for (int j = 0; j < 4; ++j) {
+        // one v_cvt_pk_bf16_f32 per pair, one v_pk_max_i16 per pair
+        const f32x2 v = {z[first + 2 * j], z[first + 2 * j + 1]};
+        const legs_i16x2 q = __builtin_bit_cast(legs_i16x2, __builtin_convertvector(v, bf16x2));
+        w[j] = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(q, (legs_i16x2){0, 0}));
+    }
+    return __builtin_bit_cast(legs_bf16x8, w);
 }
 
 // accumulator register r of lane half h holds row drow(r, h) of its 32-row block
@@ -149,20 +154,24 @@ __device__ __forceinline__ legs_f32x16 legs_mfma(legs_bf16x8 a, legs_bf16x8 b, l
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-// Input fragment of one pixel: the feature divided by its Euclidean norm (a
-// zero feature stays zero), bf16, in the lower lane half; the bias ones in
-// the upper half. v: the pixel's 8 features (read by the lower half only).
+// Input fragment of one pixel: the feature (NORM: divided by its Euclidean
+// norm, a zero feature staying zero), bf16, in the lower lane half; the bias
+// ones in the upper half. v: the pixel's 8 features (read by the lower half).
+template <bool NORM>
 __device__ __forceinline__ legs_bf16x8 mlp_input(const float (&v)[LEGS_MLP_IN], int h)
 {
     legs_bf16x8 x = mlp_bias_ones(h);
     if (h == 0) {
-        float ss = 0.0f;
+        float inv = 1.0f;
+        if constexpr (NORM) {
+            float ss = 0.0f;
 #pragma unroll
-        for (int e = 0; e < LEGS_MLP_IN; ++e) ss = fmaf(v[e], v[e], ss);
-        const float nrm = sqrtf(ss);
-        const float inv = nrm > 0.0f ? 1.0f / nrm : 0.0f;   // one division, then products
+            for (int e = 0; e < LEGS_MLP_IN; ++e) ss = fmaf(v[e], v[e], ss);
+            const float nrm = sqrtf(ss);
+            inv = nrm > 0.0f ? 1.0f / nrm : 0.0f;   // one division, then products
+        }
 #pragma unroll
-        for (int e = 0; e < LEGS_MLP_IN; ++e) x[e] = (__bf16)(v[e] * inv);
+        for (int e = 0; e < LEGS_MLP_IN; ++e) x[e] = (__bf16)(NORM ? v[e] * inv : v[e]);
     }
     return x;
 }
@@ -225,7 +234,7 @@ __device__ __forceinline__ void mlp_logits_block(const MlpLds &L, int lds_off, i
 
 // Forward of one 32-pixel tile keeping every activation (training, and the
 // decode that writes probabilities). pixel p = 32 tile + lane % 32.
-template <int KB>
+template <int KB, bool NORM>
 __device__ __forceinline__ void mlp_tile_forward(const MlpLds &L, const float *__restrict__ feat,
                                                  int64_t p, bool valid, int64_t cs, int64_t ps,
                                                  MlpTile<KB> &T, int lds_off = 0)
@@ -234,7 +243,7 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds &L, const float *_
     float v[LEGS_MLP_IN];
 #pragma unroll
     for (int e = 0; e < LEGS_MLP_IN; ++e) v[e] = (h == 0 && valid) ? legs_ldfeat(feat, p, e, cs, ps) : 0.0f;
-    legs_bf16x8 x[1] = {mlp_input(v, h)};
+    legs_bf16x8 x[1] = {mlp_input<NORM>(v, h)};
     T.x = x[0];
     const int lane = __lane_id() + lds_off;
 #pragma unroll
@@ -271,12 +280,18 @@ int32_t legs_launch_decode_folded(legs_ctx *ctx, const float *feat, int64_t P, i
                                   int64_t ps, const float *folded, int32_t K, float *probs,
                                   int32_t *top1, hipStream_t s);
 int32_t legs_launch_decode_mlp(legs_ctx *ctx, const float *feat, int64_t P, int64_t cs,
-                               int64_t ps, const float *params, int32_t K, float *probs,
-                               int32_t *top1, hipStream_t s);
+                               int64_t ps, const float *params, int32_t K, int32_t mlp_flags,
+                               float *probs, int32_t *top1, hipStream_t s);
 int64_t legs_mlp_workspace_floats(int64_t B, int32_t K);
 int32_t legs_launch_mlp_grad(legs_ctx *ctx, const float *feat, int64_t B, int64_t cs, int64_t ps,
-                             const int32_t *labels, int32_t K, const float *params,
+                             const int32_t *labels, int32_t K, int32_t mlp_flags, const float *params,
                              float *workspace, float *grad, float *loss, hipStream_t s);
+int32_t legs_launch_semantic_loss_grad(legs_ctx *ctx, const float *feat, const float *ru, int64_t P,
+                                       int64_t cs, int64_t ps, const int32_t *labels, int32_t K,
+                                       int32_t mlp_flags, const float *params, float lambda_ce,
+                                       float lambda_u, float inv_hw, float *workspace, float *grad,
+                                       float *d_feat, int64_t dcs, int64_t dps, float *d_ru,
+                                       float *loss, hipStream_t s);
 int32_t legs_launch_adam(legs_ctx *ctx, const legs_adam_group *groups, int32_t n_groups,
                          int32_t step, float lr, float beta1, float beta2, float eps, hipStream_t s);
 int32_t legs_launch_clear(legs_ctx *ctx, void *dev, int64_t words, hipStream_t s);

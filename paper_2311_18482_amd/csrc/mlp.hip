@@ -21,11 +21,21 @@ namespace {
 
 constexpr int WS_X = 0, WS_H1 = 8, WS_H2 = 72, WS_DZ1 = 136, WS_DZ2 = 200, WS_DZ3 = 264;
 
-template <int KB>
+// Per-pixel weighting of the cross-entropy. ru == NULL: the mean over the
+// batch (Eq. 9). Otherwise the uncertainty-weighted loss of Eqs. 10-12:
+// pixel p's CE is weighted by lce (1 - ru[p]) inv_hw, the loss gains
+// lu ru[p] inv_hw, and d_ru[p] = (lu - lce CE_p) inv_hw.
+struct CeWeights {
+    const float *ru;
+    float *d_ru;
+    float lce, lu, inv_hw;
+};
+
+template <int KB, bool NORM>
 __global__ void __launch_bounds__(256)
 k_mlp_fwd(const float *__restrict__ feat, int64_t B, int64_t cs, int64_t ps,
           const int32_t *__restrict__ labels, const float *__restrict__ params,
-          float *__restrict__ ws, float *__restrict__ loss)
+          float *__restrict__ ws, float *__restrict__ loss, CeWeights cw)
 {
     constexpr int K = 32 * KB;
     constexpr int WS = WS_DZ3 + K;
@@ -41,7 +51,7 @@ k_mlp_fwd(const float *__restrict__ feat, int64_t B, int64_t cs, int64_t ps,
     for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < tiles; tile += stride) {
         const int64_t p = tile * 32 + (lane & 31);
         const bool valid = p < B;
-        mlp_tile_forward<KB>(L, feat, p, valid, cs, ps, T);
+        mlp_tile_forward<KB, NORM>(L, feat, p, valid, cs, ps, T);
         float mx = -INFINITY;
 #pragma unroll
         for (int b = 0; b < KB; ++b)
@@ -58,6 +68,12 @@ k_mlp_fwd(const float *__restrict__ feat, int64_t B, int64_t cs, int64_t ps,
         const int y = labels[p];
         float *w = ws + p * WS;
         const float inv = 1.0f / sum;
+        float wpx = invB;
+        if (cw.ru) {
+            const float ru = cw.ru[p];
+            wpx = cw.lce * (1.0f - ru) * cw.inv_hw;
+            if (h == 0) lsum += cw.lu * ru * cw.inv_hw;
+        }
 #pragma unroll
         for (int b = 0; b < KB; ++b)
 #pragma unroll
@@ -68,8 +84,12 @@ k_mlp_fwd(const float *__restrict__ feat, int64_t B, int64_t cs, int64_t ps,
                 for (int i = 0; i < 4; ++i) {
                     const int k = 32 * b + 8 * j + 4 * h + i;
                     const float pr = __expf(T.z3[b][4 * j + i] - mx) * inv;
-                    dv[i] = (pr - (k == y ? 1.0f : 0.0f)) * invB;
-                    if (k == y) lsum += (mx + __logf(sum) - T.z3[b][4 * j + i]) * invB;
+                    dv[i] = (pr - (k == y ? 1.0f : 0.0f)) * wpx;
+                    if (k == y) {
+                        const float ce = mx + __logf(sum) - T.z3[b][4 * j + i];
+                        lsum += ce * wpx;
+                        if (cw.ru) cw.d_ru[p] = (cw.lu - cw.lce * ce) * cw.inv_hw;
+                    }
                 }
                 *reinterpret_cast<float4 *>(w + WS_DZ3 + 32 * b + 8 * j + 4 * h) = d;
             }
@@ -102,18 +122,31 @@ k_mlp_fwd(const float *__restrict__ feat, int64_t B, int64_t cs, int64_t ps,
 
 // dz2 and dz1 per pixel (straight-through the bf16 rounding; ReLU gate from
 // the stored activation, which is positive exactly when z > 0).
-template <int KB>
+// Input gradient request: d_feat (NULL: none) receives dL/d(feature) at
+// d_feat[c * dcs + p * dps]; with NORM the decoder input was f / |f| and its
+// Jacobian (I - u u^T) / |f| (u = f / |f|, from the feature re-read here) is
+// applied, straight through the bf16 rounding of the input.
+struct InputGrad {
+    const float *feat;
+    int64_t cs, ps;
+    float *d_feat;
+    int64_t dcs, dps;
+};
+
+template <int KB, bool NORM>
 __global__ void __launch_bounds__(256)
-k_mlp_act(int64_t B, const float *__restrict__ params, float *__restrict__ ws)
+k_mlp_act(int64_t B, const float *__restrict__ params, float *__restrict__ ws, InputGrad ig)
 {
     constexpr int K = 32 * KB;
     constexpr int WS = WS_DZ3 + K;
     constexpr int H = LEGS_MLP_H;
     __shared__ float s_W3[K * H];
     __shared__ float s_W2[H * H];
-    const float *W2 = params + LEGS_MLP_OFF_W2, *W3 = params + LEGS_MLP_OFF_W3;
+    __shared__ float s_W1[H * LEGS_MLP_IN];
+    const float *W1 = params + LEGS_MLP_OFF_W1, *W2 = params + LEGS_MLP_OFF_W2, *W3 = params + LEGS_MLP_OFF_W3;
     for (int i = threadIdx.x; i < K * H; i += blockDim.x) s_W3[i] = (float)(__bf16)W3[i];
     for (int i = threadIdx.x; i < H * H; i += blockDim.x) s_W2[i] = (float)(__bf16)W2[i];
+    for (int i = threadIdx.x; i < H * LEGS_MLP_IN; i += blockDim.x) s_W1[i] = (float)(__bf16)W1[i];
     __syncthreads();
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < B;
          p += (int64_t)gridDim.x * blockDim.x) {
@@ -149,9 +182,37 @@ k_mlp_act(int64_t B, const float *__restrict__ params, float *__restrict__ ws)
 #pragma unroll
         for (int i4 = 0; i4 < H; i4 += 4) {
             const float4 hv = *reinterpret_cast<const float4 *>(w + WS_H1 + i4);
-            *reinterpret_cast<float4 *>(w + WS_DZ1 + i4) =
-                make_float4(hv.x > 0.0f ? e[i4 + 0] : 0.0f, hv.y > 0.0f ? e[i4 + 1] : 0.0f,
-                            hv.z > 0.0f ? e[i4 + 2] : 0.0f, hv.w > 0.0f ? e[i4 + 3] : 0.0f);
+            e[i4 + 0] = hv.x > 0.0f ? e[i4 + 0] : 0.0f;
+            e[i4 + 1] = hv.y > 0.0f ? e[i4 + 1] : 0.0f;
+            e[i4 + 2] = hv.z > 0.0f ? e[i4 + 2] : 0.0f;
+            e[i4 + 3] = hv.w > 0.0f ? e[i4 + 3] : 0.0f;
+            *reinterpret_cast<float4 *>(w + WS_DZ1 + i4) = make_float4(e[i4], e[i4 + 1], e[i4 + 2], e[i4 + 3]);
+        }
+        if (ig.d_feat) {
+            float dx[LEGS_MLP_IN];
+#pragma unroll
+            for (int c = 0; c < LEGS_MLP_IN; ++c) dx[c] = 0.0f;
+#pragma unroll
+            for (int i = 0; i < H; ++i)
+#pragma unroll
+                for (int c = 0; c < LEGS_MLP_IN; ++c) dx[c] += e[i] * s_W1[i * LEGS_MLP_IN + c];
+            if constexpr (NORM) {
+                float f[LEGS_MLP_IN], ss = 0.0f;
+#pragma unroll
+                for (int c = 0; c < LEGS_MLP_IN; ++c) {
+                    f[c] = legs_ldfeat(ig.feat, p, c, ig.cs, ig.ps);
+                    ss = fmaf(f[c], f[c], ss);
+                }
+                const float nrm = sqrtf(ss);
+                const float inv = nrm > 0.0f ? 1.0f / nrm : 0.0f;
+                float ud = 0.0f;
+#pragma unroll
+                for (int c = 0; c < LEGS_MLP_IN; ++c) ud += f[c] * inv * dx[c];
+#pragma unroll
+                for (int c = 0; c < LEGS_MLP_IN; ++c) dx[c] = (dx[c] - ud * (f[c] * inv)) * inv;
+            }
+#pragma unroll
+            for (int c = 0; c < LEGS_MLP_IN; ++c) ig.d_feat[(int64_t)c * ig.dcs + p * ig.dps] = dx[c];
         }
     }
 }
@@ -218,36 +279,37 @@ k_zero_f32(float *__restrict__ p, int64_t n)
 
 int64_t legs_mlp_workspace_floats(int64_t B, int32_t K) { return B * (WS_DZ3 + (int64_t)K); }
 
-int32_t legs_launch_mlp_grad(legs_ctx *ctx, const float *feat, int64_t B, int64_t cs, int64_t ps,
-                             const int32_t *labels, int32_t K, const float *params,
-                             float *workspace, float *grad, float *loss, hipStream_t s)
+namespace {
+
+// Forward with dz3, hidden-layer backward (and the input gradient), weight
+// gradients (accumulated into grad with float atomics).
+int32_t mlp_train_kernels(legs_ctx *ctx, const float *feat, int64_t B, int64_t cs, int64_t ps,
+                          const int32_t *labels, int32_t K, int32_t mlp_flags, const float *params,
+                          float *workspace, float *grad, float *loss, const CeWeights &cw,
+                          const InputGrad &ig, hipStream_t s)
 {
     const int KB = K / 32;
-    const int64_t np = LEGS_MLP_NPARAMS(KB);
-    hipLaunchKernelGGL(k_zero_f32, dim3(64), dim3(256), 0, s, grad, np);
-    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, s, loss, (int64_t)1);
-    LEGS_CHECK_LAUNCH(ctx);
     if (B == 0) return LEGS_OK;
     int64_t g = (B + 127) / 128;
     const int64_t cap = (int64_t)ctx->num_cus * 8;
     if (g > cap) g = cap;
     const int64_t ga = ((B + 255) / 256) < cap ? (B + 255) / 256 : cap;
-    switch (KB) {
-    case 1:
-        hipLaunchKernelGGL(k_mlp_fwd<1>, dim3((unsigned)g), dim3(256), 0, s, feat, B, cs, ps, labels, params, workspace, loss);
-        hipLaunchKernelGGL(k_mlp_act<1>, dim3((unsigned)ga), dim3(256), 0, s, B, params, workspace);
-        break;
-    case 2:
-        hipLaunchKernelGGL(k_mlp_fwd<2>, dim3((unsigned)g), dim3(256), 0, s, feat, B, cs, ps, labels, params, workspace, loss);
-        hipLaunchKernelGGL(k_mlp_act<2>, dim3((unsigned)ga), dim3(256), 0, s, B, params, workspace);
-        break;
-    case 4:
-        hipLaunchKernelGGL(k_mlp_fwd<4>, dim3((unsigned)g), dim3(256), 0, s, feat, B, cs, ps, labels, params, workspace, loss);
-        hipLaunchKernelGGL(k_mlp_act<4>, dim3((unsigned)ga), dim3(256), 0, s, B, params, workspace);
-        break;
-    default:
-        return legs_set_error(ctx, LEGS_ERR_ARG, "K must be 32, 64 or 128");
+    const bool norm = (mlp_flags & LEGS_MLP_NORMALIZE_INPUT) != 0;
+#define LEGS_MLP_TRAIN(KBV)                                                                                         \
+    if (norm) {                                                                                                     \
+        hipLaunchKernelGGL((k_mlp_fwd<KBV, true>), dim3((unsigned)g), dim3(256), 0, s, feat, B, cs, ps, labels, params, workspace, loss, cw); \
+        hipLaunchKernelGGL((k_mlp_act<KBV, true>), dim3((unsigned)ga), dim3(256), 0, s, B, params, workspace, ig); \
+    } else {                                                                                                        \
+        hipLaunchKernelGGL((k_mlp_fwd<KBV, false>), dim3((unsigned)g), dim3(256), 0, s, feat, B, cs, ps, labels, params, workspace, loss, cw); \
+        hipLaunchKernelGGL((k_mlp_act<KBV, false>), dim3((unsigned)ga), dim3(256), 0, s, B, params, workspace, ig); \
     }
+    switch (KB) {
+    case 1: LEGS_MLP_TRAIN(1) break;
+    case 2: LEGS_MLP_TRAIN(2) break;
+    case 4: LEGS_MLP_TRAIN(4) break;
+    default: return legs_set_error(ctx, LEGS_ERR_ARG, "K must be 32, 64 or 128");
+    }
+#undef LEGS_MLP_TRAIN
     LEGS_CHECK_LAUNCH(ctx);
     const int WS = WS_DZ3 + K;
     const unsigned chunks = (unsigned)((B + WG_CHUNK - 1) / WG_CHUNK);
@@ -263,6 +325,33 @@ int32_t legs_launch_mlp_grad(legs_ctx *ctx, const float *feat, int64_t B, int64_
                        B, workspace, WS, WS_DZ1, H, WS_X, LEGS_MLP_IN, grad + LEGS_MLP_OFF_W1, grad + LEGS_MLP_OFF_B1);
     LEGS_CHECK_LAUNCH(ctx);
     return LEGS_OK;
+}
+
+} // namespace
+
+int32_t legs_launch_mlp_grad(legs_ctx *ctx, const float *feat, int64_t B, int64_t cs, int64_t ps,
+                             const int32_t *labels, int32_t K, int32_t mlp_flags, const float *params,
+                             float *workspace, float *grad, float *loss, hipStream_t s)
+{
+    const int64_t np = LEGS_MLP_NPARAMS(K / 32);
+    hipLaunchKernelGGL(k_zero_f32, dim3(64), dim3(256), 0, s, grad, np);
+    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, s, loss, (int64_t)1);
+    LEGS_CHECK_LAUNCH(ctx);
+    const CeWeights cw = {nullptr, nullptr, 1.0f, 0.0f, 0.0f};
+    const InputGrad ig = {nullptr, 0, 0, nullptr, 0, 0};
+    return mlp_train_kernels(ctx, feat, B, cs, ps, labels, K, mlp_flags, params, workspace, grad, loss, cw, ig, s);
+}
+
+int32_t legs_launch_semantic_loss_grad(legs_ctx *ctx, const float *feat, const float *ru, int64_t P,
+                                       int64_t cs, int64_t ps, const int32_t *labels, int32_t K,
+                                       int32_t mlp_flags, const float *params, float lambda_ce,
+                                       float lambda_u, float inv_hw, float *workspace, float *grad,
+                                       float *d_feat, int64_t dcs, int64_t dps, float *d_ru,
+                                       float *loss, hipStream_t s)
+{
+    const CeWeights cw = {ru, d_ru, lambda_ce, lambda_u, inv_hw};
+    const InputGrad ig = {feat, cs, ps, d_feat, dcs, dps};
+    return mlp_train_kernels(ctx, feat, P, cs, ps, labels, K, mlp_flags, params, workspace, grad, loss, cw, ig, s);
 }
 
 // ---- fused Adam over parameter groups -------------------------------------------

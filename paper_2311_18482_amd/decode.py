@@ -79,21 +79,27 @@ def mlp_pack(ws, bs):
     return torch.cat(parts)
 
 
-def decode_mlp(ctx: Context, f, params, K, probs=False, top1=None):
+def mlp_flags(normalize: bool) -> int:
+    return L.LEGS_MLP_NORMALIZE_INPUT if normalize else 0
+
+
+def decode_mlp(ctx: Context, f, params, K, probs=False, top1=None, normalize=True):
     tp, P, cs, ps = _feat_args(f)
     if top1 is None:
         top1 = torch.empty(max(P, 1), dtype=torch.int32, device=ctx.device)
     pr = torch.empty((P, K), dtype=torch.float32, device=ctx.device) if probs else None
-    ctx.check(L.lib().legs_decode_mlp(ctx.handle, tp, P, cs, ps, _p(params), K, _p(pr), _p(top1),
-                                      _stream()))
+    ctx.check(L.lib().legs_decode_mlp(ctx.handle, tp, P, cs, ps, _p(params), K, mlp_flags(normalize),
+                                      _p(pr), _p(top1), _stream()))
     return top1[:P], pr
 
 
 class MlpTrainer:
     """Decoder parameters, Adam moments and scratch for legs_mlp_train_step."""
 
-    def __init__(self, ctx: Context, params, K, batch, lr=1e-3, betas=(0.9, 0.999), eps=1e-8):
+    def __init__(self, ctx: Context, params, K, batch, lr=1e-3, betas=(0.9, 0.999), eps=1e-8,
+                 normalize=True):
         self.ctx, self.K, self.lr, self.betas, self.eps = ctx, K, lr, betas, eps
+        self.flags = mlp_flags(normalize)
         self.params = params.to(ctx.device).contiguous().clone()
         n = mlp_param_count(K)
         assert self.params.numel() == n
@@ -110,7 +116,7 @@ class MlpTrainer:
         tp, P, cs, ps = _feat_args(f)
         assert P <= self.batch
         self.ctx.check(L.lib().legs_mlp_grad(self.ctx.handle, tp, P, cs, ps, _p(labels), self.K,
-                                             _p(self.params), _p(self.ws), _p(self.grad),
+                                             self.flags, _p(self.params), _p(self.ws), _p(self.grad),
                                              _p(self.loss), _stream()))
         return self.grad, self.loss
 
@@ -119,10 +125,29 @@ class MlpTrainer:
         assert P <= self.batch
         self.step_count += 1
         self.ctx.check(L.lib().legs_mlp_train_step(
-            self.ctx.handle, tp, P, cs, ps, _p(labels), self.K, _p(self.params), _p(self.m),
+            self.ctx.handle, tp, P, cs, ps, _p(labels), self.K, self.flags, _p(self.params), _p(self.m),
             _p(self.v), _p(self.grad), self.step_count, self.lr, self.betas[0], self.betas[1],
             self.eps, _p(self.ws), _p(self.loss), _stream()))
         return self.loss
+
+
+def semantic_loss_grad(ctx: Context, f, ru, labels, params, K, inv_hw, workspace, grad, d_feat, d_ru, loss,
+                       lambda_ce=1.0, lambda_u=1.0, normalize=True):
+    """Eqs. 10-12 over the pixels of one view (legs_semantic_loss_grad).
+    f: feature argument like the decode calls; d_feat: (tensor, c_stride,
+    p_stride) receiving dL_s/dR_s; ru, d_ru: [P] tensors; grad and loss are
+    accumulated."""
+    tp, P, cs, ps = _feat_args(f)
+    dt, dcs, dps = d_feat
+    ctx.check(L.lib().legs_semantic_loss_grad(ctx.handle, tp, _p(ru), P, cs, ps, _p(labels), K,
+                                              mlp_flags(normalize), _p(params), lambda_ce, lambda_u, inv_hw,
+                                              _p(workspace), _p(grad), _p(dt), int(dcs), int(dps), _p(d_ru),
+                                              _p(loss), _stream()))
+
+
+def workspace(ctx: Context, P, K):
+    nbytes = int(L.lib().legs_mlp_workspace_bytes(P, K))
+    return torch.empty(max(nbytes, 4), dtype=torch.uint8, device=ctx.device)
 
 
 def adam(ctx: Context, groups, step, lr=1e-3, betas=(0.9, 0.999), eps=1e-8):

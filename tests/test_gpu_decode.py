@@ -70,19 +70,20 @@ def test_plain_and_folded_decode(ctx, DEC, K, Dm):
     assert np.abs(pr.cpu().numpy() - probs_ref).max() < 1e-5
 
 
-@pytest.mark.parametrize("K", [128, 64, 32])
-def test_mlp_decode(ctx, DEC, K):
+@pytest.mark.parametrize("K,normalize", [(128, True), (64, True), (32, True), (128, False)])
+def test_mlp_decode(ctx, DEC, K, normalize):
     n = 5000 + 17
     f = features(n, 20 + K)
     ws, bs = synth.mlp_init((8, 64, 64, K), 30 + K)
-    ref = D.mlp_forward(f, ws, bs)
+    ref = D.mlp_forward(f, ws, bs, normalize=normalize)
     params = DEC.mlp_pack(ws, bs).cuda()
-    top, pr = DEC.decode_mlp(ctx, DEC.rowmajor_features(torch.from_numpy(f).cuda()), params, K, probs=True)
+    top, pr = DEC.decode_mlp(ctx, DEC.rowmajor_features(torch.from_numpy(f).cuda()), params, K, probs=True,
+                             normalize=normalize)
     torch.cuda.synchronize()
     # the top-1-only kernel (logits consumed block by block), row-major and planar input
     fd_ = torch.from_numpy(f).cuda()
-    top_r, _ = DEC.decode_mlp(ctx, DEC.rowmajor_features(fd_), params, K)
-    top_p, _ = DEC.decode_mlp(ctx, (fd_.t().contiguous(), n, n, 1), params, K)
+    top_r, _ = DEC.decode_mlp(ctx, DEC.rowmajor_features(fd_), params, K, normalize=normalize)
+    top_p, _ = DEC.decode_mlp(ctx, (fd_.t().contiguous(), n, n, 1), params, K, normalize=normalize)
     torch.cuda.synchronize()
     top, pr = top.cpu().numpy(), pr.cpu().numpy()
     assert np.array_equal(top_r.cpu().numpy(), top) and np.array_equal(top_p.cpu().numpy(), top)
@@ -100,14 +101,15 @@ def test_mlp_decode(ctx, DEC, K):
     assert (top == t_ref).mean() > 0.995
 
 
-def test_mlp_gradient_and_train_step(ctx, DEC):
+@pytest.mark.parametrize("normalize", [True, False])
+def test_mlp_gradient_and_train_step(ctx, DEC, normalize):
     K, B = 128, 6000
     f = features(B, 40)
     rng = np.random.default_rng(41)
     y = rng.integers(0, K, B).astype(np.int32)
     ws, bs = synth.mlp_init((8, 64, 64, K), 42)
-    loss_ref, gW, gb = D.mlp_grads(f, y, ws, bs)
-    tr = DEC.MlpTrainer(ctx, DEC.mlp_pack(ws, bs), K, B)
+    loss_ref, gW, gb = D.mlp_grads(f, y, ws, bs, normalize=normalize)
+    tr = DEC.MlpTrainer(ctx, DEC.mlp_pack(ws, bs), K, B, normalize=normalize)
     fd_ = torch.from_numpy(f).cuda()
     yd = torch.from_numpy(y).cuda()
     grad, loss = tr.grad_only(DEC.rowmajor_features(fd_), yd)

@@ -64,12 +64,16 @@ def full_check(R, scene, cams, tile=16, batch=256, grads=True, seed_g=200):
     G = synth.upstream_grads(cams, scene.n_channels, seed_g)
     note("backward")
     grad2d, g, d_ch = run_backward(R, rast, d, proj, bins, T, last, G)
-    ref = O.backward(scene, cams, oo, fwd, G.astype(np.float64), flip_masks=masks)
-    # per-G-view screen-space gradients
+    ref = O.backward(scene, cams, oo, fwd, G.astype(np.float64), flip_masks=masks, magnitudes=True)
+    # per-G-view screen-space gradients: an intermediate mixing units (mean,
+    # conic and opacity gradients), whose largest entries are conic gradients
+    # of the smallest Gaussians, sums with cancellation: its global error is
+    # bounded at 3e-5
     g2 = grad2d.cpu().numpy()[:, :6].astype(np.float64)
     ref2 = ref["grad2d"].reshape(-1, 6)
-    PT.compare_grads({"g2": g2}, {"g2": ref2}, g2.shape[0], groups=("g2",))
-    worst = PT.compare_grads(PT.gpu_grads_to_np(g, d_ch), ref, scene.n)
+    PT.compare_grads({"g2": g2}, {"g2": ref2}, g2.shape[0], groups=("g2",), global_tol=3e-5,
+                     mag={"g2": ref["mag"]["grad2d"].reshape(-1, 6)})
+    worst = PT.compare_grads(PT.gpu_grads_to_np(g, d_ch), ref, scene.n, mag=ref["mag"])
     note(f"gradient worst ratios {worst}")
     return stats
 
@@ -133,9 +137,9 @@ def test_c2_forward_backward_and_fd(R):
     G = synth.upstream_grads(cams, scene.n_channels, 202)
     note("c2 backward")
     grad2d, g, d_ch = run_backward(R, rast, d, proj, bins, T, last, G)
-    ref = O.backward(scene, cams, oo, fwd, G.astype(np.float64), flip_masks=masks)
+    ref = O.backward(scene, cams, oo, fwd, G.astype(np.float64), flip_masks=masks, magnitudes=True)
     gg = PT.gpu_grads_to_np(g, d_ch)
-    worst = PT.compare_grads(gg, ref, scene.n)
+    worst = PT.compare_grads(gg, ref, scene.n, mag=ref["mag"])
     note(f"c2 gradient worst ratios {worst}")
     # central finite differences on 64 seeded Gaussians blended somewhere: 8
     # outside the guard band (Jacobian at the clamped point), 8 with radius in
@@ -247,10 +251,10 @@ def test_autograd_two_renders_one_loss(R):
         _, _, _, _, o2, T2, l2 = run_forward(R, sc, cams, o)
         assert torch.equal(out.detach(), o2)
         masks, _ = PT.compare_render(o2, T2, l2, sc, cams, oo, fwd)
-        ref = O.backward(sc, cams, oo, fwd, G.astype(np.float64), flip_masks=masks)
+        ref = O.backward(sc, cams, oo, fwd, G.astype(np.float64), flip_masks=masks, magnitudes=True)
         got = {k: p[k].grad.cpu().numpy().astype(np.float64) for k in ("mean", "log_scale", "quat", "opacity_logit")}
         got["channels"] = p["channels"].grad.cpu().numpy().astype(np.float64)
-        PT.compare_grads(got, ref, sc.n)
+        PT.compare_grads(got, ref, sc.n, mag=ref["mag"])
 
 
 def test_tile_and_batch_invariance(R):
@@ -520,9 +524,9 @@ def test_persistent_graph_six_views_matches_oracle(R):
         PT.compare_bins(bins, fwd)
         masks, stats = PT.compare_render(out, T, last, scene, cams, oo, fwd)
         if ref is None:
-            ref = O.backward(scene, cams, oo, fwd, G.astype(np.float64), flip_masks=masks)
+            ref = O.backward(scene, cams, oo, fwd, G.astype(np.float64), flip_masks=masks, magnitudes=True)
         got = PT.gpu_grads_to_np(grads, d_ch)
-        worst = PT.compare_grads(got, ref, n)
+        worst = PT.compare_grads(got, ref, n, mag=ref["mag"])
         note(f"replay {rep}: {stats} {worst}")
 
 

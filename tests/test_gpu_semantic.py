@@ -1,0 +1,140 @@
+"""GPU parity of the semantic objective of Sec. 3.4.2 (Eqs. 10-12: the
+uncertainty-weighted cross-entropy of the decoded rendered features, the
+uncertainty regulariser and their sum) against the FP64 oracle, and of its
+gradients flowing through the rasteriser into s_G and u."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import decode as D
+from oracle import oracle as O
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2311_18482_amd import raster
+    assert torch.cuda.is_available()
+    return raster.Context(0)
+
+
+@pytest.mark.parametrize("K,normalize", [(128, True), (64, False)])
+def test_semantic_loss_matches_oracle(ctx, K, normalize):
+    from paper_2311_18482_amd import decode as DEC
+    rng = np.random.default_rng(70 + K)
+    P = 7000 + 13
+    f = rng.normal(0, 1, (P, 8)).astype(np.float32)
+    ru = rng.uniform(0, 1, P).astype(np.float32)
+    ru[:50] = 1.0                                 # fully uncertain pixels: no CE term
+    y = rng.integers(0, K, P).astype(np.int32)
+    ws, bs = synth.mlp_init((8, 64, 64, K), 71)
+    inv_hw = 1.0 / P
+    ref = D.semantic_loss_grad(f, ru, y, ws, bs, inv_hw, 1.0, 1.0, normalize=normalize)
+    amb = D.mlp_forward(f, ws, bs, normalize=normalize)["ambiguous"]
+    params = DEC.mlp_pack(ws, bs).cuda()
+    grad = torch.zeros_like(params)
+    loss = torch.zeros(1, device="cuda")
+    fd_ = torch.from_numpy(f).cuda()
+    d_feat = torch.full((P, 8), 7.0, device="cuda")
+    d_ru = torch.full((P,), 7.0, device="cuda")
+    ws_ = DEC.workspace(ctx, P, K)
+    DEC.semantic_loss_grad(ctx, DEC.rowmajor_features(fd_), torch.from_numpy(ru).cuda(), torch.from_numpy(y).cuda(),
+                           params, K, inv_hw, ws_, grad, (d_feat, 1, 8), d_ru, loss, normalize=normalize)
+    torch.cuda.synchronize()
+    assert loss.item() == pytest.approx(ref["loss"], rel=1e-5)
+    ok = ~amb
+    assert ok.mean() > 0.5
+    dr = d_ru.cpu().numpy().astype(np.float64)
+    assert np.allclose(dr[ok], ref["d_ru"][ok], rtol=1e-4, atol=1e-6 * inv_hw)
+    df = d_feat.cpu().numpy().astype(np.float64)
+    err = np.linalg.norm(df - ref["d_feat"], axis=1)
+    scale = np.linalg.norm(ref["d_feat"], axis=1)
+    rms = np.sqrt(np.mean(scale ** 2))
+    assert (err[ok] <= 1e-3 * np.maximum(scale[ok], 1e-3 * rms)).all()
+    assert (df[:50] == 0.0).all()
+    g = grad.cpu().numpy().astype(np.float64)
+    off = 0
+    for w, b in zip(ref["gW"], ref["gb"]):
+        for part in (w.reshape(-1), b):
+            seg = g[off:off + part.size]
+            assert np.linalg.norm(seg - part) <= 2e-3 * np.linalg.norm(part), off
+            off += part.size
+    # a second call accumulates the parameter gradient and the loss
+    DEC.semantic_loss_grad(ctx, DEC.rowmajor_features(fd_), torch.from_numpy(ru).cuda(), torch.from_numpy(y).cuda(),
+                           params, K, inv_hw, ws_, grad, (d_feat, 1, 8), d_ru, loss, normalize=normalize)
+    torch.cuda.synchronize()
+    assert loss.item() == pytest.approx(2 * ref["loss"], rel=1e-5)
+    assert np.allclose(grad.cpu().numpy(), 2 * g, rtol=1e-5, atol=1e-9)
+
+
+def test_semantic_gradients_reach_features_and_uncertainty(ctx):
+    """Render, decode and score the semantic maps of two views, write dL_s/dR_s
+    and dL_s/dR_u into the semantic and uncertainty planes of dL/d(out), and
+    run the rasteriser's backward: the semantic-channel and uncertainty
+    gradients of the Gaussians (and their geometry gradients) match the
+    oracle's chain of the same steps, and they are not zero."""
+    from paper_2311_18482_amd import raster as R, decode as DEC
+    scene = synth.make_scene(6000, 72, synth.VOL_C1, d_sem=8)
+    C = scene.n_channels
+    cams = [synth.camera_front(96, 80, 96.0), synth.camera_front(64, 64, 60.0)]
+    K = 64
+    ws, bs = synth.mlp_init((8, 64, 64, K), 73)
+    o = R.opts(tile=16, lds_batch=128)
+    oo = PT.oracle_opts(o)
+    rast = R.Rasterizer(cams, o)
+    d = PT.to_dev(scene)
+    proj, bins, out, T, last = rast.forward(d["mean"], d["log_scale"], d["quat"], d["opacity_logit"], d["channels"])
+    params = DEC.mlp_pack(ws, bs).cuda()
+    grad = torch.zeros_like(params)
+    loss = torch.zeros(1, device="cuda")
+    d_out = torch.zeros_like(out)
+    rng = np.random.default_rng(74)
+    labels = [torch.from_numpy(rng.integers(0, K, c.width * c.height).astype(np.int32)).cuda() for c in cams]
+    for v, cam in enumerate(cams):
+        hw = cam.width * cam.height
+        base = C * rast.views.pixel_offsets[v]
+        feat = (out[base + 3 * hw:], hw, hw, 1)
+        ws_ = DEC.workspace(ctx, hw, K)
+        DEC.semantic_loss_grad(ctx, feat, out[base + (C - 1) * hw:base + C * hw], labels[v], params, K, 1.0 / hw,
+                               ws_, grad, (d_out[base + 3 * hw:], hw, 1), d_out[base + (C - 1) * hw:base + C * hw],
+                               loss)
+    grad2d, d_ch = R.render_backward(rast.ctx, proj, bins, rast.views, d["channels"], o, T, last, d_out)
+    g = R.project_backward(rast.ctx, d["mean"], d["log_scale"], d["quat"], d["opacity_logit"], rast.views, o, proj,
+                           grad2d)
+    torch.cuda.synchronize()
+    # the oracle chain: render, semantic loss per view on the oracle's maps
+    fwd = O.forward(scene, cams, oo)
+    masks, _ = PT.compare_render(out, T, last, scene, cams, oo, fwd)
+    dref = np.zeros(out.numel())
+    lref = 0.0
+    off = 0
+    for v, cam in enumerate(cams):
+        hw = cam.width * cam.height
+        r = fwd["views"][v]["out"]
+        s = D.semantic_loss_grad(r[3:11].T, r[C - 1], labels[v].cpu().numpy(), ws, bs, 1.0 / hw, 1.0, 1.0)
+        lref += s["loss"]
+        dref[off + 3 * hw:off + 11 * hw] = s["d_feat"].T.reshape(-1)
+        dref[off + (C - 1) * hw:off + C * hw] = s["d_ru"]
+        off += C * hw
+    assert loss.item() == pytest.approx(lref, rel=1e-4)
+    dg = d_out.cpu().numpy().astype(np.float64)
+    assert np.abs(dg - dref).max() <= 1e-3 * np.abs(dref).max()
+    # the rasteriser's backward of the GPU's dL/d(out), along the GPU's branches
+    ref = O.backward(scene, cams, oo, fwd, dg, flip_masks=masks, magnitudes=True)
+    got = PT.gpu_grads_to_np(g, d_ch)
+    PT.compare_grads(got, ref, scene.n, mag=ref["mag"])
+    dch = got["channels"]
+    assert np.abs(dch[:, 3:11]).max() > 0 and np.abs(dch[:, C - 1]).max() > 0
+    assert not dch[:, :3].any()                   # no RGB term in L_s
+    note(f"semantic loss {loss.item():.6f}; |dL/ds_G| max {np.abs(dch[:, 3:11]).max():.3e}, "
+         f"|dL/du| max {np.abs(dch[:, C - 1]).max():.3e}")

@@ -573,6 +573,23 @@ def _torch_mlp(torch, x, ws, bs):
     return h
 
 
+def test_raw_input_decoder_matches_torch():
+    """Without the input normalisation the decoder is Eq. 8 applied to R_s."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(12)
+    x = rng.normal(0, 1, (300, 8)).astype(np.float32)
+    ws, bs = synth.mlp_init((8, 64, 64, 64), 13)
+    fw = D.mlp_forward(x, ws, bs, normalize=False)
+    h = torch.from_numpy(D.bf16(x.astype(np.float64)))
+    for l, (W, b) in enumerate(zip(ws, bs)):
+        h = torch.nn.functional.linear(h, torch.from_numpy(D.bf16(W.astype(np.float64))),
+                                       torch.from_numpy(b.astype(np.float64)))
+        if l < 2:
+            h = torch.from_numpy(D.bf16(torch.relu(h).numpy()))
+    assert np.allclose(fw["logits"], h.numpy(), rtol=1e-12, atol=1e-13)
+    assert not np.allclose(fw["logits"], D.mlp_forward(x, ws, bs)["logits"])
+
+
 def test_mlp_forward_and_grads_match_torch():
     torch = pytest.importorskip("torch")
     rng = np.random.default_rng(2)
@@ -837,3 +854,103 @@ def test_skip_flip_backward_replay(oracle_lib):
     b_nat = O.backward(sc, [cam], o2, f2, G)
     for grp in ("mean", "log_scale", "quat", "opacity_logit", "channels"):
         assert np.allclose(b_flip[grp], b_nat[grp], rtol=1e-10, atol=1e-15), grp
+
+
+# ------------------------------------------------------- semantic loss (Eqs. 10-12)
+
+def _torch_semantic(torch, f, ru, y, ws, bs, inv_hw, lam_ce, lam_u, round_bf16, normalize=True):
+    """The same loss written with torch ops, differentiated by autograd
+    (straight-through roundings via the detach trick)."""
+    ft = torch.tensor(f.astype(np.float64), requires_grad=True)
+    rt = torch.tensor(ru.astype(np.float64), requires_grad=True)
+    Wt = [torch.tensor(D.bf16(w.astype(np.float64)) if round_bf16 else w.astype(np.float64), requires_grad=True)
+          for w in ws]
+    bt = [torch.tensor(b.astype(np.float64), requires_grad=True) for b in bs]
+
+    def st(x):
+        return x + (torch.from_numpy(D.bf16(x.detach().numpy())) - x).detach() if round_bf16 else x
+    h = st(torch.nn.functional.normalize(ft, dim=1) if normalize else ft)
+    for l, (W, b) in enumerate(zip(Wt, bt)):
+        h = torch.nn.functional.linear(h, W, b)
+        if l < len(Wt) - 1:
+            h = st(torch.relu(h))
+    ce = torch.nn.functional.cross_entropy(h, torch.from_numpy(y.astype(np.int64)), reduction="none")
+    loss = lam_ce * (ce * (1.0 - rt)).sum() * inv_hw + lam_u * rt.sum() * inv_hw
+    loss.backward()
+    return loss.item(), ft.grad.numpy(), rt.grad.numpy(), [w.grad.numpy() for w in Wt], [b.grad.numpy() for b in bt]
+
+
+@pytest.mark.parametrize("round_bf16,normalize", [(True, True), (False, True), (True, False)])
+def test_semantic_loss_matches_torch_autograd(round_bf16, normalize):
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(8)
+    P, K = 400, 64
+    f = rng.normal(0, 1, (P, 8)).astype(np.float32)
+    ru = rng.uniform(0, 1, P).astype(np.float32)
+    y = rng.integers(0, K, P)
+    ws, bs = synth.mlp_init((8, 64, 64, K), 9)
+    inv_hw = 1.0 / 517.0
+    r = D.semantic_loss_grad(f, ru, y, ws, bs, inv_hw, 1.0, 1.0, round_bf16=round_bf16, normalize=normalize)
+    lt, gf, gr, gW, gb = _torch_semantic(torch, f, ru, y, ws, bs, inv_hw, 1.0, 1.0, round_bf16, normalize)
+    assert r["loss"] == pytest.approx(lt, rel=1e-12)
+    assert np.allclose(r["d_feat"], gf, rtol=1e-9, atol=1e-15)
+    assert np.allclose(r["d_ru"], gr, rtol=1e-12, atol=1e-16)
+    for l in range(3):
+        assert np.allclose(r["gW"][l], gW[l], rtol=1e-9, atol=1e-15)
+        assert np.allclose(r["gb"][l], gb[l], rtol=1e-9, atol=1e-15)
+
+
+def test_semantic_loss_special_cases_and_fd():
+    """R_u = 0 reduces L_CE to the plain mean cross-entropy (Eq. 9 with H W
+    pixels), whose gradients mlp_grads gives; R_u = 1 removes every CE term,
+    leaving L_u alone; dL/dR_u is exact in closed form ((lambda_u - lambda_CE
+    CE) / (H W), L is linear in R_u); and without the roundings the feature
+    gradient matches central finite differences."""
+    rng = np.random.default_rng(10)
+    P, K = 300, 32
+    f = rng.normal(0, 1, (P, 8)).astype(np.float32)
+    y = rng.integers(0, K, P)
+    ws, bs = synth.mlp_init((8, 64, 64, K), 11)
+    r0 = D.semantic_loss_grad(f, np.zeros(P), y, ws, bs, 1.0 / P, 1.0, 1.0)
+    l2, gW, gb = D.mlp_grads(f, y, ws, bs)
+    assert r0["loss"] == pytest.approx(l2, rel=1e-12)
+    for l in range(3):
+        assert np.allclose(r0["gW"][l], gW[l], rtol=1e-12, atol=1e-16)
+        assert np.allclose(r0["gb"][l], gb[l], rtol=1e-12, atol=1e-16)
+    r1 = D.semantic_loss_grad(f, np.ones(P), y, ws, bs, 1.0 / P, 1.0, 0.5)
+    assert r1["loss"] == pytest.approx(0.5, rel=1e-14)
+    assert not r1["d_feat"].any() and all(not g.any() for g in r1["gW"])
+    ru = rng.uniform(0, 1, P)
+    r = D.semantic_loss_grad(f, ru, y, ws, bs, 1.0 / 777.0, 2.0, 0.25, round_bf16=False)
+    assert np.allclose(r["d_ru"], (0.25 - 2.0 * r["ce"]) / 777.0, rtol=1e-14)
+    ff = f.astype(np.float64)
+    for p, c in zip(rng.integers(0, P, 20), rng.integers(0, 8, 20)):
+        hstep = 1e-4
+        fp, fm = ff.copy(), ff.copy()
+        fp[p, c] += hstep
+        fm[p, c] -= hstep
+        lp = D.semantic_loss_grad(fp.astype(np.float64), ru, y, ws, bs, 1.0 / 777.0, 2.0, 0.25, False)["loss"]
+        lm = D.semantic_loss_grad(fm.astype(np.float64), ru, y, ws, bs, 1.0 / 777.0, 2.0, 0.25, False)["loss"]
+        assert r["d_feat"][p, c] == pytest.approx((lp - lm) / (2 * hstep), rel=1e-5, abs=1e-10)
+
+
+def test_gradient_magnitude_sums(oracle_lib):
+    """The magnitude sums behind the float32-aware gradient bound bound the
+    gradients they belong to (|sum t| <= sum |t|, and through the chain
+    rule's magnitude), and equal them when no term cancels: a positive
+    upstream gradient on positive channels gives channel-gradient terms
+    alpha T G > 0 only."""
+    scene = synth.make_scene(800, 92, synth.VOL_C1, d_sem=2)
+    cams = [synth.camera_front(64, 56, 64.0), synth.camera_front(48, 48, 50.0)]
+    opts = O.make_opts(16)
+    f = O.forward(scene, cams, opts)
+    G = synth.upstream_grads(cams, scene.n_channels, 93).astype(np.float64)
+    b = O.backward(scene, cams, opts, f, G, magnitudes=True)
+    m = b["mag"]
+    for grp in ("mean", "log_scale", "quat", "opacity_logit", "channels"):
+        assert (np.abs(b[grp]) <= m[grp] * (1 + 1e-12) + 1e-300).all(), grp
+        assert (m[grp] > 0).any()
+    assert (np.abs(b["grad2d"]) <= m["grad2d"] * (1 + 1e-12) + 1e-300).all()
+    bp = O.backward(scene, cams, opts, f, np.abs(G), magnitudes=True)
+    pos = scene.channels >= 0
+    assert np.allclose(bp["channels"][pos], bp["mag"]["channels"][pos], rtol=1e-12, atol=0)
