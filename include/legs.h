@@ -332,16 +332,18 @@ typedef struct {
 
 /* m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
  * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps); one launch
- * over every group (groups is a host array of n_groups <= 8). */
+ * over every group (groups is a host array of n_groups <= 8). The betas are
+ * doubles: 1 - b and the bias corrections are formed in double and rounded
+ * once to float (so b2 = 0.999 gives 1 - b2 = float(0.001)). */
 int32_t legs_adam(legs_ctx *ctx, const legs_adam_group *groups, int32_t n_groups, int32_t step,
-                  float lr, float beta1, float beta2, float eps, void *stream);
+                  float lr, double beta1, double beta2, float eps, void *stream);
 
 /* One decoder training step: legs_mlp_grad, then legs_adam on params with
  * moment buffers m, v [legs_mlp_param_count(K)]; grad is scratch. */
 int32_t legs_mlp_train_step(legs_ctx *ctx, const float *feat, int64_t B, int64_t c_stride,
                             int64_t p_stride, const int32_t *labels, int32_t K, int32_t mlp_flags,
                             float *params, float *m, float *v, float *grad, int32_t step, float lr,
-                            float beta1, float beta2, float eps, void *workspace, float *loss,
+                            double beta1, double beta2, float eps, void *workspace, float *loss,
                             void *stream);
 
 /* Per view: mean |out - target| over the first n_fit channels (RGB and s_G)

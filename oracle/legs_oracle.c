@@ -491,12 +491,18 @@ double oracle_render_region(int64_t n, const oproj_t *pv, const ocam_t *cam, con
  * the same sums with every term replaced by its magnitude (|G_c|, |ch| and the
  * absolute values of the power's derivatives), i.e. sum |term| for each
  * gradient: the scale of the rounding error of any floating-point evaluation
- * of these sums. */
+ * of these sums. Every term of a pixel is weighted by 1 + mag_cond * S with
+ * S = sum over the pixel's blended entries of 1 / (1 - alpha): a rounding
+ * error e in alpha changes 1 - alpha by the relative amount
+ * e alpha / (1 - alpha), and the transmittance T = prod (1 - alpha) and the
+ * suffix behind an entry, which every term of the pixel uses, collect these
+ * relative errors over the list, so S is the condition number of the
+ * pixel's terms with respect to the rounding of its alphas. */
 void oracle_render_backward(int64_t n, const oproj_t *pv, const ocam_t *cam, const oopts_t *o,
                             const double *ch, int32_t C, const uint32_t *ids,
                             const uint32_t *ranges, int64_t tile_offset, const double *G,
                             const uint32_t *flip_mask, double *grad2d, double *dch,
-                            double *mag2d, double *magch)
+                            double *mag2d, double *magch, double mag_cond)
 {
     const int64_t HW = (int64_t)cam->W * cam->H;
     int nth = 1;
@@ -543,7 +549,11 @@ void oracle_render_backward(int64_t n, const oproj_t *pv, const ocam_t *cam, con
                 for (int cc = 0; cc < C; ++cc)
                     suffix[k * C + cc] = suffix[(k + 1) * C + cc] + e->alpha * e->T * cg[cc];
             }
+            double wmag = 1.0;
             if (want_mag) {
+                double S = 0.0;
+                for (int64_t k = 0; k < nr; ++k) S += 1.0 / (1.0 - rec[k].alpha);
+                wmag = 1.0 + mag_cond * S;
                 for (int cc = 0; cc < C; ++cc) suffix_abs[(nr - 1) * C + cc] = 0.0;
                 for (int64_t k = nr - 2; k >= 0; --k) {
                     const oblend_t *e = rec + k + 1;
@@ -562,8 +572,8 @@ void oracle_render_backward(int64_t n, const oproj_t *pv, const ocam_t *cam, con
                     gc[(int64_t)e->g * C + cc] += e->alpha * e->T * Gc;
                     dalpha += Gc * (e->T * cg[cc] - suffix[k * C + cc] / (1.0 - e->alpha));
                     if (want_mag) {
-                        mc[(int64_t)e->g * C + cc] += e->alpha * e->T * fabs(Gc);
-                        dalpha_abs += fabs(Gc) * (e->T * fabs(cg[cc]) + suffix_abs[k * C + cc] / (1.0 - e->alpha));
+                        mc[(int64_t)e->g * C + cc] += wmag * e->alpha * e->T * fabs(Gc);
+                        dalpha_abs += wmag * fabs(Gc) * (e->T * fabs(cg[cc]) + suffix_abs[k * C + cc] / (1.0 - e->alpha));
                     }
                 }
                 if (e->clamped) continue;

@@ -67,7 +67,7 @@ def lib():
                                            i32, i32, i32, P, P, P, P]
         L.oracle_render_region.restype = ct.c_double
         L.oracle_render_backward.argtypes = [i64, P, ct.POINTER(OCam), ct.POINTER(OOpts), P, i32, P,
-                                             P, i64, P, P, P, P, P, P]
+                                             P, i64, P, P, P, P, P, P, ct.c_double]
         L.oracle_render_backward.restype = None
         L.oracle_project_backward.argtypes = [i64, P, P, P, P, ct.POINTER(OCam), ct.POINTER(OOpts),
                                               P, P, P, P, P]
@@ -188,11 +188,13 @@ def render_region(proj_v, cam, opts, channels, x0, y0, w, h, G=None):
 
 
 def render_backward_view(proj_v, cam, opts, channels, ids, ranges, tile_offset, G_view,
-                         flip_mask=None, dch=None, mag=None):
+                         flip_mask=None, dch=None, mag=None, mag_cond=0.0):
     """Returns (grad2d [n, 6] for this view, dch [n, C] accumulated). mag
     (optional dict with "g2" [n, 6] and "channels" [n, C]) receives the
     magnitude sums sum |term| of those gradients (g2 overwritten, channels
-    accumulated)."""
+    accumulated), each pixel's terms weighted by 1 + mag_cond * S, S the sum of
+    1 / (1 - alpha) over the pixel's blended entries (how strongly rounding
+    errors of the alphas reach the pixel's terms through T and the suffix)."""
     ch = np.ascontiguousarray(channels, np.float64)
     n, C = ch.shape
     c = make_cam(cam)
@@ -209,7 +211,7 @@ def render_backward_view(proj_v, cam, opts, channels, ids, ranges, tile_offset, 
         mc = mag.setdefault("channels", np.zeros((n, C)))
     lib().oracle_render_backward(n, _p(pv), ct.byref(c), ct.byref(opts), _p(ch), C, _p(idv),
                                  _p(ranges), int(tile_offset), _p(Gd), _p(fm), _p(g2), _p(dch),
-                                 _p(m2), _p(mc))
+                                 _p(m2), _p(mc), float(mag_cond))
     return g2, dch
 
 
@@ -254,7 +256,7 @@ def forward(scene, cams, opts, params: Params | None = None):
 GEO_GROUPS = ("mean", "log_scale", "quat", "opacity_logit")
 
 
-def backward(scene, cams, opts, fwd, G_flat, flip_masks=None, magnitudes=False):
+def backward(scene, cams, opts, fwd, G_flat, flip_masks=None, magnitudes=False, mag_cond=0.0):
     """Gradients of sum(G * out) w.r.t. every per-Gaussian parameter (float64).
 
     With magnitudes, also acc["mag"]: for every gradient entry the scale of
@@ -264,7 +266,8 @@ def backward(scene, cams, opts, fwd, G_flat, flip_masks=None, magnitudes=False):
     sums, carried to the per-Gaussian groups through the magnitude of the
     projection's chain rule: for each view and screen-space component k,
     |J e_k| (the chain rule applied to a unit gradient in k) times the
-    magnitude sum of component k."""
+    magnitude sum of component k. mag_cond weights each pixel's terms as in
+    render_backward_view."""
     params = fwd["params"]
     n, C = scene.channels.shape
     dch = np.zeros((n, C))
@@ -280,7 +283,7 @@ def backward(scene, cams, opts, fwd, G_flat, flip_masks=None, magnitudes=False):
         off += C * hw
         fm = None if flip_masks is None else flip_masks[v]
         g2, dch = render_backward_view(fwd["proj"][v], cam, opts, scene.channels, fwd["ids"],
-                                       fwd["ranges"], fwd["offsets"][v], Gv, fm, dch, mag)
+                                       fwd["ranges"], fwd["offsets"][v], Gv, fm, dch, mag, mag_cond)
         grad2d_all.append(g2)
         acc = project_backward(params, cam, opts, g2, acc)
         if magnitudes:

@@ -101,10 +101,10 @@ _SIGS = {
     "legs_mlp_grad": (I32, [P, P, I64, I64, I64, P, I32, I32, P, P, P, P, P]),
     "legs_semantic_loss_grad": (I32, [P, P, P, I64, I64, I64, P, I32, I32, P, ct.c_float, ct.c_float,
                                       ct.c_float, P, P, P, I64, I64, P, P, P]),
-    "legs_adam": (I32, [P, ct.POINTER(AdamGroup), I32, I32, ct.c_float, ct.c_float, ct.c_float,
+    "legs_adam": (I32, [P, ct.POINTER(AdamGroup), I32, I32, ct.c_float, ct.c_double, ct.c_double,
                         ct.c_float, P]),
     "legs_mlp_train_step": (I32, [P, P, I64, I64, I64, P, I32, I32, P, P, P, P, I32, ct.c_float,
-                                  ct.c_float, ct.c_float, ct.c_float, P, P, P]),
+                                  ct.c_double, ct.c_double, ct.c_float, P, P, P]),
     "legs_l1_loss_grad": (I32, [P, P, P, P, I32, I64, I32, I32, ct.c_float, P, P, P]),
     "legs_clear": (I32, [P, P, I64, P]),
     "legs_capture_begin": (I32, [P, P]),

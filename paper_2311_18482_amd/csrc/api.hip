@@ -393,13 +393,13 @@ int32_t legs_semantic_loss_grad(legs_ctx *ctx, const float *feat, const float *r
 }
 
 int32_t legs_adam(legs_ctx *ctx, const legs_adam_group *groups, int32_t n_groups, int32_t step,
-                  float lr, float beta1, float beta2, float eps, void *stream)
+                  float lr, double beta1, double beta2, float eps, void *stream)
 {
     if (!ctx) return LEGS_ERR_ARG;
     if (!groups || n_groups < 1 || n_groups > LEGS_ADAM_MAX_GROUPS)
         return legs_set_error(ctx, LEGS_ERR_ARG, "n_groups out of [1, %d]", LEGS_ADAM_MAX_GROUPS);
     if (step < 1) return legs_set_error(ctx, LEGS_ERR_ARG, "step must be >= 1");
-    if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f))
+    if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps >= 0.f))
         return legs_set_error(ctx, LEGS_ERR_ARG, "bad Adam hyper-parameters");
     for (int k = 0; k < n_groups; ++k) {
         const legs_adam_group &g = groups[k];
@@ -415,7 +415,7 @@ int32_t legs_adam(legs_ctx *ctx, const legs_adam_group *groups, int32_t n_groups
 int32_t legs_mlp_train_step(legs_ctx *ctx, const float *feat, int64_t B, int64_t c_stride,
                             int64_t p_stride, const int32_t *labels, int32_t K, int32_t mlp_flags,
                             float *params, float *m, float *v, float *grad, int32_t step, float lr,
-                            float beta1, float beta2, float eps, void *workspace, float *loss,
+                            double beta1, double beta2, float eps, void *workspace, float *loss,
                             void *stream)
 {
     LEGS_TRY(legs_mlp_grad(ctx, feat, B, c_stride, p_stride, labels, K, mlp_flags, params, workspace,

@@ -293,7 +293,7 @@ int32_t legs_launch_semantic_loss_grad(legs_ctx *ctx, const float *feat, const f
                                        float *d_feat, int64_t dcs, int64_t dps, float *d_ru,
                                        float *loss, hipStream_t s);
 int32_t legs_launch_adam(legs_ctx *ctx, const legs_adam_group *groups, int32_t n_groups,
-                         int32_t step, float lr, float beta1, float beta2, float eps, hipStream_t s);
+                         int32_t step, float lr, double beta1, double beta2, float eps, hipStream_t s);
 int32_t legs_launch_clear(legs_ctx *ctx, void *dev, int64_t words, hipStream_t s);
 int32_t legs_launch_l1_loss_grad(legs_ctx *ctx, const float *out, const float *target,
                                  const legs_view *views, int32_t n_views, int64_t total_pixels,

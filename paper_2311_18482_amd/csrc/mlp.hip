@@ -362,7 +362,9 @@ struct AdamArgs {
     legs_adam_group g[LEGS_ADAM_MAX_GROUPS];
     int64_t start[LEGS_ADAM_MAX_GROUPS + 1];
     int n_groups;
-    float lr, b1, b2, eps, c1, c2;  // c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t)
+    // omb = 1 - b rounded once from double (1 - 0.999f would be 1.3e-5 off
+    // 0.001); c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t)
+    float lr, b1, b2, omb1, omb2, eps, c1, c2;
 };
 
 __global__ void __launch_bounds__(256)
@@ -375,8 +377,8 @@ k_adam(AdamArgs A)
         const legs_adam_group &G = A.g[k];
         const int64_t j = i - A.start[k];
         const float g = G.grad[j];
-        const float m = A.b1 * G.m[j] + (1.0f - A.b1) * g;
-        const float v = A.b2 * G.v[j] + (1.0f - A.b2) * g * g;
+        const float m = A.b1 * G.m[j] + A.omb1 * g;
+        const float v = A.b2 * G.v[j] + A.omb2 * g * g;
         G.m[j] = m;
         G.v[j] = v;
         float p = G.param[j] - A.lr * (m * A.c1) / (sqrtf(v * A.c2) + A.eps);
@@ -389,7 +391,7 @@ k_adam(AdamArgs A)
 } // namespace
 
 int32_t legs_launch_adam(legs_ctx *ctx, const legs_adam_group *groups, int32_t n_groups,
-                         int32_t step, float lr, float beta1, float beta2, float eps, hipStream_t s)
+                         int32_t step, float lr, double beta1, double beta2, float eps, hipStream_t s)
 {
     AdamArgs A;
     A.n_groups = n_groups;
@@ -398,9 +400,11 @@ int32_t legs_launch_adam(legs_ctx *ctx, const legs_adam_group *groups, int32_t n
         A.g[k] = groups[k];
         A.start[k + 1] = A.start[k] + groups[k].n;
     }
-    A.lr = lr; A.b1 = beta1; A.b2 = beta2; A.eps = eps;
-    A.c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)step)));
-    A.c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)step)));
+    A.lr = lr; A.eps = eps;
+    A.b1 = (float)beta1; A.b2 = (float)beta2;
+    A.omb1 = (float)(1.0 - beta1); A.omb2 = (float)(1.0 - beta2);
+    A.c1 = (float)(1.0 / (1.0 - pow(beta1, (double)step)));
+    A.c2 = (float)(1.0 / (1.0 - pow(beta2, (double)step)));
     const int64_t total = A.start[n_groups];
     if (total == 0) return LEGS_OK;
     int64_t g = (total + 255) / 256;

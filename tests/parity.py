@@ -161,7 +161,18 @@ def group_floor(grp):
     return FLOOR.get(grp, FLOOR_DEFAULT)
 
 
+# Rounding-error model of a float32 evaluation of the gradient sums, in units
+# of the oracle's magnitude sums (sum |term|, each pixel's terms weighted by
+# 1 + MAG_COND * S with S = sum 1 / (1 - alpha) over its blended entries).
+# A term's own float32 arithmetic and the summation of up to ~1e5 terms per
+# Gaussian (wave reductions, then atomics) stay within MAG_KAPPA = 3e-5 (about
+# 250 float32 half-ulps) of sum |term|. The transmittance and the suffix are
+# products over the list: a rounding error of a few half-ulps in alpha_j moves
+# them by about 5 u / (1 - alpha_j) relative, u = 2^-24, so a pixel's terms
+# carry up to about 5 u S relative error; MAG_KAPPA * MAG_COND = 1e-6 (about
+# 16 u) covers that with a factor of 3 to spare.
 MAG_KAPPA = 3e-5
+MAG_COND = 1.0 / 30.0
 
 
 def compare_grads(g, ref, n, tol=1e-3, groups=GROUPS, subset=None, floor=None, global_tol=1e-5, mag=None):
@@ -189,7 +200,9 @@ def compare_grads(g, ref, n, tol=1e-3, groups=GROUPS, subset=None, floor=None, g
             k = int(np.argmax(err / np.maximum(bound, 1e-300)))
             worst[grp] = dict(ratio=float(err[k] / max(bound[k], 1e-300)),
                               global_rel=float(np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-300)),
-                              worst_norm_over_rms=float(np.linalg.norm(r[k]) / max(rms, 1e-300)))
+                              worst_norm_over_rms=float(np.linalg.norm(r[k]) / max(rms, 1e-300)),
+                              index=int(k), err=float(err[k]), norm=float(np.linalg.norm(r[k])),
+                              mag_norm=None if m is None else float(np.linalg.norm(m[k])))
         assert not bad.any(), (f"{grp}: {int(bad.sum())} of {len(a)} Gaussians exceed tolerance; "
                                f"worst {worst[grp]}")
         if global_tol is not None and grp in worst:

@@ -130,7 +130,7 @@ def test_semantic_gradients_reach_features_and_uncertainty(ctx):
     dg = d_out.cpu().numpy().astype(np.float64)
     assert np.abs(dg - dref).max() <= 1e-3 * np.abs(dref).max()
     # the rasteriser's backward of the GPU's dL/d(out), along the GPU's branches
-    ref = O.backward(scene, cams, oo, fwd, dg, flip_masks=masks, magnitudes=True)
+    ref = O.backward(scene, cams, oo, fwd, dg, flip_masks=masks, magnitudes=True, mag_cond=PT.MAG_COND)
     got = PT.gpu_grads_to_np(g, d_ch)
     PT.compare_grads(got, ref, scene.n, mag=ref["mag"])
     dch = got["channels"]

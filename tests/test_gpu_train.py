@@ -58,7 +58,7 @@ def test_training_step_matches_oracle():
     assert np.allclose(d_out[~near], G_ref[~near], rtol=1e-6, atol=0)     # float32 1 / count
     note(f"render {stats}; {int(near.sum())} loss elements at their target")
     # gradients: the oracle backward of the same dL/dout, along the GPU's branches
-    ref = O.backward(scene, cams, oo, fwd, d_out, flip_masks=masks, magnitudes=True)
+    ref = O.backward(scene, cams, oo, fwd, d_out, flip_masks=masks, magnitudes=True, mag_cond=PT.MAG_COND)
     # Adam's first step from zero moments: m = (1 - b1) g, v = (1 - b2) g^2,
     # p -= lr g / (|g| + eps), then u clamped to [0, 1]
     got_g = {k: ts.g[k].cpu().numpy().astype(np.float64) for k in GROUPS}
