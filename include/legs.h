@@ -314,6 +314,25 @@ int32_t legs_semantic_loss_grad(legs_ctx *ctx, const float *feat, const float *r
                                 float *d_feat, int64_t d_c_stride, int64_t d_p_stride, float *d_ru,
                                 float *loss, void *stream);
 
+/* legs_semantic_loss_grad without a workspace argument, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc). It allocates nothing: its
+ * workspace is a fixed array of 25,690,112 bytes inside the library's device
+ * code, one per GPU, held from the first legs_create on that GPU until the
+ * process ends. P <= LEGS_NOALLOC_MAX_PIXELS, else LEGS_ERR_ARG (nothing
+ * launched); the loss and the decoder gradient accumulate, so a larger view
+ * is processed in chunks of at most that many pixels, each call given the
+ * whole view's inv_hw. All calls on one GPU share the array: calls that
+ * overlap in time on one GPU (several streams or threads) race and must be
+ * serialised by the caller. Arguments and results as legs_semantic_loss_grad. */
+#define LEGS_NOALLOC_MAX_PIXELS 16384
+int32_t legs_semantic_loss_grad_noalloc(legs_ctx *ctx, const float *feat, const float *ru, int64_t P,
+                                        int64_t c_stride, int64_t p_stride, const int32_t *labels,
+                                        int32_t K, int32_t mlp_flags, const float *params,
+                                        float lambda_ce, float lambda_u, float inv_hw, float *grad,
+                                        float *d_feat, int64_t d_c_stride, int64_t d_p_stride,
+                                        float *d_ru, float *loss, void *stream);
+
 /* ---- optimisation (Sec. 4: Adam, lr 1e-3, betas (0.9, 0.999)) ------------- */
 
 /* One parameter group of a fused Adam step (all device pointers, n floats).

@@ -101,6 +101,8 @@ _SIGS = {
     "legs_mlp_grad": (I32, [P, P, I64, I64, I64, P, I32, I32, P, P, P, P, P]),
     "legs_semantic_loss_grad": (I32, [P, P, P, I64, I64, I64, P, I32, I32, P, ct.c_float, ct.c_float,
                                       ct.c_float, P, P, P, I64, I64, P, P, P]),
+    "legs_semantic_loss_grad_noalloc": (I32, [P, P, P, I64, I64, I64, P, I32, I32, P, ct.c_float,
+                                              ct.c_float, ct.c_float, P, P, I64, I64, P, P, P]),
     "legs_adam": (I32, [P, ct.POINTER(AdamGroup), I32, I32, ct.c_float, ct.c_double, ct.c_double,
                         ct.c_float, P]),
     "legs_mlp_train_step": (I32, [P, P, I64, I64, I64, P, I32, I32, P, P, P, P, I32, ct.c_float,

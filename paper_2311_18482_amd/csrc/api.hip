@@ -5,8 +5,47 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
+#include <mutex>
+
 #include "legs_internal.h"
 #include "legs_decode_internal.h"
+
+// Workspace of legs_semantic_loss_grad_noalloc: LEGS_NOALLOC_MAX_PIXELS rows of
+// the decoder-training workspace at the largest K (25,690,112 bytes). Every GPU
+// that loads the library holds its own copy until the process ends. In host
+// code `scratch` is only a stand-in for the symbol: the device address of a
+// GPU's copy comes from hipGetSymbolAddress with that GPU current, once per
+// device (in legs_create), and only that address is handed to kernels.
+static __device__ __align__(256) float scratch[(size_t)LEGS_NOALLOC_MAX_PIXELS * LEGS_MLP_WS_PER_PIXEL(128)];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+std::atomic<float *> g_scratch[kScratchDevices];
+
+int32_t scratch_setup(legs_ctx *ctx)
+{
+    if (ctx->device >= kScratchDevices)
+        return legs_set_error(ctx, LEGS_ERR_UNSUPPORTED, "device %d beyond the %d with a scratch table",
+                              ctx->device, kScratchDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[ctx->device].load()) return LEGS_OK;
+    int prev = -1;
+    LEGS_CHECK_HIP(ctx, hipGetDevice(&prev));
+    LEGS_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    LEGS_CHECK_HIP(ctx, hipSetDevice(prev));
+    if (e != hipSuccess || !p)
+        return legs_set_error(ctx, LEGS_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s",
+                              ctx->device, hipGetErrorString(e));
+    g_scratch[ctx->device].store(static_cast<float *>(p));
+    return LEGS_OK;
+}
+
+} // namespace
 
 int32_t legs_set_error(legs_ctx *ctx, int32_t code, const char *fmt, ...)
 {
@@ -102,6 +141,12 @@ int32_t legs_create(int32_t device, legs_ctx **out)
     c->device = device;
     c->num_cus = prop.multiProcessorCount;
     c->err[0] = 0;
+    const int32_t rc = scratch_setup(c);
+    if (rc != LEGS_OK) {
+        fprintf(stderr, "legs_create: %s\n", c->err);
+        delete c;
+        return rc;
+    }
     *out = c;
     return LEGS_OK;
 }
@@ -390,6 +435,28 @@ int32_t legs_semantic_loss_grad(legs_ctx *ctx, const float *feat, const float *r
                                           params, lambda_ce, lambda_u, inv_hw,
                                           static_cast<float *>(workspace), grad, d_feat, d_c_stride,
                                           d_p_stride, d_ru, loss, (hipStream_t)stream);
+}
+
+int32_t legs_semantic_loss_grad_noalloc(legs_ctx *ctx, const float *feat, const float *ru, int64_t P,
+                                        int64_t c_stride, int64_t p_stride, const int32_t *labels,
+                                        int32_t K, int32_t mlp_flags, const float *params,
+                                        float lambda_ce, float lambda_u, float inv_hw, float *grad,
+                                        float *d_feat, int64_t d_c_stride, int64_t d_p_stride,
+                                        float *d_ru, float *loss, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (P > LEGS_NOALLOC_MAX_PIXELS)
+        return legs_set_error(ctx, LEGS_ERR_ARG,
+                              "P = %lld exceeds LEGS_NOALLOC_MAX_PIXELS (%d); process the view in chunks",
+                              (long long)P, LEGS_NOALLOC_MAX_PIXELS);
+    float *ws = ctx->device < kScratchDevices ? g_scratch[ctx->device].load() : nullptr;
+    if (!ws) return legs_set_error(ctx, LEGS_ERR_HIP, "no scratch address for device %d", ctx->device);
+    // Every workspace element the kernels read is written earlier in the same
+    // call (forward rows, then the hidden-layer gradients), so the array needs
+    // no clearing between calls.
+    return legs_semantic_loss_grad(ctx, feat, ru, P, c_stride, p_stride, labels, K, mlp_flags, params,
+                                   lambda_ce, lambda_u, inv_hw, ws, grad, d_feat, d_c_stride,
+                                   d_p_stride, d_ru, loss, stream);
 }
 
 int32_t legs_adam(legs_ctx *ctx, const legs_adam_group *groups, int32_t n_groups, int32_t step,

@@ -16,6 +16,8 @@
 #define LEGS_MLP_OFF_W3 (LEGS_MLP_OFF_B2 + LEGS_MLP_H)
 #define LEGS_MLP_OFF_B3(KB) (LEGS_MLP_OFF_W3 + 32 * (KB) * LEGS_MLP_H)
 #define LEGS_MLP_NPARAMS(KB) (LEGS_MLP_OFF_B3(KB) + 32 * (KB))
+// Training workspace per pixel (floats): X 8 | H1 64 | H2 64 | DZ1 64 | DZ2 64 | DZ3 K
+#define LEGS_MLP_WS_PER_PIXEL(K) (264 + (K))
 
 typedef __attribute__((ext_vector_type(8))) __bf16 legs_bf16x8;
 typedef __attribute__((ext_vector_type(16))) float legs_f32x16;

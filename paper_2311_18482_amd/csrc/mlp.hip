@@ -20,6 +20,7 @@
 namespace {
 
 constexpr int WS_X = 0, WS_H1 = 8, WS_H2 = 72, WS_DZ1 = 136, WS_DZ2 = 200, WS_DZ3 = 264;
+static_assert(WS_DZ3 + 128 == LEGS_MLP_WS_PER_PIXEL(128), "workspace layout");
 
 // Per-pixel weighting of the cross-entropy. ru == NULL: the mean over the
 // batch (Eq. 9). Otherwise the uncertainty-weighted loss of Eqs. 10-12:

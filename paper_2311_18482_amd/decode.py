@@ -145,6 +145,22 @@ def semantic_loss_grad(ctx: Context, f, ru, labels, params, K, inv_hw, workspace
                                               _p(loss), _stream()))
 
 
+def semantic_loss_grad_noalloc(ctx: Context, f, ru, labels, params, K, inv_hw, grad, d_feat, d_ru, loss,
+                               lambda_ce=1.0, lambda_u=1.0, normalize=True):
+    """semantic_loss_grad without a workspace (legs_semantic_loss_grad_noalloc):
+    the library's own fixed per-GPU array serves as workspace; at most
+    max_noalloc_pixels() pixels per call."""
+    tp, P, cs, ps = _feat_args(f)
+    dt, dcs, dps = d_feat
+    ctx.check(L.lib().legs_semantic_loss_grad_noalloc(ctx.handle, tp, _p(ru), P, cs, ps, _p(labels), K,
+                                                      mlp_flags(normalize), _p(params), lambda_ce, lambda_u,
+                                                      inv_hw, _p(grad), _p(dt), int(dcs), int(dps), _p(d_ru),
+                                                      _p(loss), _stream()))
+
+
+NOALLOC_MAX_PIXELS = 16384      # LEGS_NOALLOC_MAX_PIXELS of include/legs.h
+
+
 def workspace(ctx: Context, P, K):
     nbytes = int(L.lib().legs_mlp_workspace_bytes(P, K))
     return torch.empty(max(nbytes, 4), dtype=torch.uint8, device=ctx.device)
