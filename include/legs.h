@@ -284,6 +284,34 @@ int32_t legs_decode_mlp(legs_ctx *ctx, const float *feat, int64_t P, int64_t c_s
                         int64_t p_stride, const float *params, int32_t K, int32_t mlp_flags,
                         float *probs, int32_t *top1, void *stream);
 
+/* Decoder of Table 3 (supplementary implementation details): D_MLP = 1x1
+ * convolutions 8 -> 128 -> 256 -> N with ReLU between them, N (the size of
+ * the discrete feature space) 32, 64 or 128; M_infer = softmax(D_MLP(R_s))
+ * per pixel (supplementary inference equation). params: float32 masters
+ * [legs_dmlp_param_count(N)] packed W1 [128][8], b1 [128], W2 [256][128],
+ * b2 [256], W3 [N][256], b3 [N]; weights, input and hidden activations are
+ * rounded to bf16 (nearest even), biases and accumulation are float32.
+ * feat is read as in legs_decode_mlp; mlp_flags as there (0 = Eq. 8 as
+ * written). Outputs (each nullable, at least one): probs [P][N] float32
+ * (16-byte aligned), probs_f16 [P][N] IEEE half (8-byte aligned; the same
+ * probabilities rounded to nearest, the input of legs_language_features),
+ * top1 [P] int32 (lowest index on ties). With only top1 requested the kernel
+ * never holds all N logits. */
+int64_t legs_dmlp_param_count(int32_t N);
+int32_t legs_decode_dmlp(legs_ctx *ctx, const float *feat, int64_t P, int64_t c_stride, int64_t p_stride,
+                         const float *params, int32_t N, int32_t mlp_flags, float *probs, uint16_t *probs_f16,
+                         int32_t *top1, void *stream);
+
+/* Language feature map F = M_infer S (supplementary inference equation):
+ * probs_f16 [P][N] the half-precision distribution from legs_decode_dmlp
+ * (16-byte aligned), S [N][d] float32 the quantised language features (the
+ * discrete feature space), d a multiple of 32 up to 4096. F is written planar,
+ * F[c * P + p] for feature dimension c and pixel p, as float32 (out_f16 = 0)
+ * or IEEE half (out_f16 = 1). S is rounded to half inside (|S| < 65504);
+ * products are accumulated in float32 on FP16 MFMA. */
+int32_t legs_language_features(legs_ctx *ctx, const uint16_t *probs_f16, int64_t P, int32_t N,
+                               const float *S, int32_t d, int32_t out_f16, void *F, void *stream);
+
 /* Gradient of the mean cross-entropy (Eq. 9) of B pixels against labels
  * [B] int32 in [0, K): grad [legs_mlp_param_count(K)] is overwritten, loss [1]
  * receives the mean loss. Straight-through for the bf16 roundings.

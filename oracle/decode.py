@@ -92,6 +92,60 @@ def mlp_forward(feat, weights, biases, amb_tol=2e-6, normalize=True):
     return dict(x=x, hs=hs, zs=zs, logits=zs[-1], ambiguous=amb)
 
 
+def mlp_branches(feat_row, weights, biases, normalize=True, amb_tol=2e-6, max_states=64):
+    """Every logit vector a float32 evaluation of mlp_forward can produce for
+    one pixel: wherever a value that is rounded to bf16 (the input, each
+    hidden activation) lies within a relative amb_tol of a rounding midpoint,
+    both neighbours are followed. Returns (list of logits, complete) with
+    complete False when more than max_states branches would arise (the list
+    then holds the branches of the first ambiguous values only)."""
+    f = np.asarray(feat_row, np.float32).astype(np.float64)[None, :]
+    if normalize:
+        nrm = np.sqrt(np.sum(f * f))
+        u = f / nrm if nrm > 0.0 else np.zeros_like(f)
+    else:
+        u = f
+    complete = True
+
+    def roundings(v):
+        nonlocal complete
+        lo, hi = bf16(v * (1 - amb_tol)), bf16(v * (1 + amb_tol))
+        base = bf16(v)
+        amb = np.nonzero(lo != hi)[1] if v.ndim == 2 else np.nonzero(lo != hi)[0]
+        outs = [base]
+        for j in amb:
+            alt = []
+            for o in outs:
+                for cand in (lo[..., j], hi[..., j]):
+                    if cand != o[..., j]:
+                        q = o.copy()
+                        q[..., j] = cand
+                        alt.append(q)
+            if len(outs) + len(alt) > max_states:
+                complete = False
+                break
+            outs += alt
+        return outs
+
+    states = roundings(u)
+    L = len(weights)
+    Ws = [bf16(np.asarray(w, np.float32).astype(np.float64)) for w in weights]
+    bs = [np.asarray(b, np.float32).astype(np.float64) for b in biases]
+    for l in range(L):
+        nxt = []
+        for h in states:
+            z = h @ Ws[l].T + bs[l]
+            if l < L - 1:
+                nxt += roundings(np.maximum(z, 0.0))
+            else:
+                nxt.append(z[0])
+        if len(nxt) > max_states:
+            complete = False
+            nxt = nxt[:max_states]
+        states = nxt
+    return states, complete
+
+
 def softmax(z):
     z = z - z.max(axis=1, keepdims=True)
     e = np.exp(z)

@@ -437,6 +437,43 @@ int32_t legs_semantic_loss_grad(legs_ctx *ctx, const float *feat, const float *r
                                           d_p_stride, d_ru, loss, (hipStream_t)stream);
 }
 
+int64_t legs_dmlp_param_count(int32_t N)
+{
+    return (N == 32 || N == 64 || N == 128) ? (int64_t)LEGS_DMLP_NPARAMS(N / 32) : -1;
+}
+
+int32_t legs_decode_dmlp(legs_ctx *ctx, const float *feat, int64_t P, int64_t c_stride, int64_t p_stride,
+                         const float *params, int32_t N, int32_t mlp_flags, float *probs, uint16_t *probs_f16,
+                         int32_t *top1, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (P < 0 || P > (1ll << 40)) return legs_set_error(ctx, LEGS_ERR_ARG, "P out of range");
+    if (N != 32 && N != 64 && N != 128) return legs_set_error(ctx, LEGS_ERR_ARG, "N must be 32, 64 or 128");
+    LEGS_TRY(check_mlp_flags(ctx, mlp_flags));
+    if (!params || (P > 0 && !feat)) return legs_set_error(ctx, LEGS_ERR_ARG, "NULL argument");
+    if (!probs && !probs_f16 && !top1) return legs_set_error(ctx, LEGS_ERR_ARG, "no output requested");
+    if (c_stride < 0 || p_stride < 0) return legs_set_error(ctx, LEGS_ERR_ARG, "negative stride");
+    if ((reinterpret_cast<uintptr_t>(probs) & 15) || (reinterpret_cast<uintptr_t>(probs_f16) & 7))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "probs must be 16-byte and probs_f16 8-byte aligned");
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_decode_dmlp(ctx, feat, P, c_stride, p_stride, params, N, mlp_flags, probs, probs_f16,
+                                   top1, (hipStream_t)stream);
+}
+
+int32_t legs_language_features(legs_ctx *ctx, const uint16_t *probs_f16, int64_t P, int32_t N,
+                               const float *S, int32_t d, int32_t out_f16, void *F, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (P < 0 || P > (1ll << 40)) return legs_set_error(ctx, LEGS_ERR_ARG, "P out of range");
+    if (N != 32 && N != 64 && N != 128) return legs_set_error(ctx, LEGS_ERR_ARG, "N must be 32, 64 or 128");
+    if (d < 32 || d > 4096 || d % 32) return legs_set_error(ctx, LEGS_ERR_ARG, "d must be a multiple of 32 in [32, 4096]");
+    if (!S || (P > 0 && (!probs_f16 || !F))) return legs_set_error(ctx, LEGS_ERR_ARG, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(probs_f16) & 15)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "probs_f16 must be 16-byte aligned");
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_language_features(ctx, probs_f16, P, N, S, d, out_f16, F, (hipStream_t)stream);
+}
+
 int32_t legs_semantic_loss_grad_noalloc(legs_ctx *ctx, const float *feat, const float *ru, int64_t P,
                                         int64_t c_stride, int64_t p_stride, const int32_t *labels,
                                         int32_t K, int32_t mlp_flags, const float *params,

@@ -16,6 +16,18 @@
 #define LEGS_MLP_OFF_W3 (LEGS_MLP_OFF_B2 + LEGS_MLP_H)
 #define LEGS_MLP_OFF_B3(KB) (LEGS_MLP_OFF_W3 + 32 * (KB) * LEGS_MLP_H)
 #define LEGS_MLP_NPARAMS(KB) (LEGS_MLP_OFF_B3(KB) + 32 * (KB))
+// Decoder of Table 3: 8 -> 128 -> 256 -> N; float32 masters packed as
+// W1 [128][8], b1 [128], W2 [256][128], b2 [256], W3 [N][256], b3 [N].
+#define LEGS_DMLP_H1 128
+#define LEGS_DMLP_H2 256
+#define LEGS_DMLP_OFF_W1 0
+#define LEGS_DMLP_OFF_B1 (LEGS_DMLP_H1 * LEGS_MLP_IN)
+#define LEGS_DMLP_OFF_W2 (LEGS_DMLP_OFF_B1 + LEGS_DMLP_H1)
+#define LEGS_DMLP_OFF_B2 (LEGS_DMLP_OFF_W2 + LEGS_DMLP_H2 * LEGS_DMLP_H1)
+#define LEGS_DMLP_OFF_W3 (LEGS_DMLP_OFF_B2 + LEGS_DMLP_H2)
+#define LEGS_DMLP_OFF_B3(KB) (LEGS_DMLP_OFF_W3 + 32 * (KB) * LEGS_DMLP_H2)
+#define LEGS_DMLP_NPARAMS(KB) (LEGS_DMLP_OFF_B3(KB) + 32 * (KB))
+
 // Training workspace per pixel (floats): X 8 | H1 64 | H2 64 | DZ1 64 | DZ2 64 | DZ3 K
 #define LEGS_MLP_WS_PER_PIXEL(K) (264 + (K))
 
@@ -284,6 +296,11 @@ int32_t legs_launch_decode_folded(legs_ctx *ctx, const float *feat, int64_t P, i
 int32_t legs_launch_decode_mlp(legs_ctx *ctx, const float *feat, int64_t P, int64_t cs,
                                int64_t ps, const float *params, int32_t K, int32_t mlp_flags,
                                float *probs, int32_t *top1, hipStream_t s);
+int32_t legs_launch_decode_dmlp(legs_ctx *ctx, const float *feat, int64_t P, int64_t cs, int64_t ps,
+                                const float *params, int32_t N, int32_t mlp_flags, float *probs,
+                                uint16_t *probs16, int32_t *top1, hipStream_t s);
+int32_t legs_launch_language_features(legs_ctx *ctx, const uint16_t *probs16, int64_t P, int32_t N,
+                                      const float *S, int32_t d, int32_t out_f16, void *F, hipStream_t s);
 int64_t legs_mlp_workspace_floats(int64_t B, int32_t K);
 int32_t legs_launch_mlp_grad(legs_ctx *ctx, const float *feat, int64_t B, int64_t cs, int64_t ps,
                              const int32_t *labels, int32_t K, int32_t mlp_flags, const float *params,

@@ -93,6 +93,37 @@ def decode_mlp(ctx: Context, f, params, K, probs=False, top1=None, normalize=Tru
     return top1[:P], pr
 
 
+def dmlp_param_count(N):
+    return int(L.lib().legs_dmlp_param_count(N))
+
+
+def decode_dmlp(ctx: Context, f, params, N, probs=False, probs_f16=False, top1=True, normalize=False):
+    """Table 3 decoder (legs_decode_dmlp). Returns (top1 [P] int32 or None,
+    probs [P][N] float32 or None, probs_f16 [P][N] float16 or None)."""
+    tp, P, cs, ps = _feat_args(f)
+    dev = ctx.device
+    t1 = torch.empty(max(P, 1), dtype=torch.int32, device=dev) if top1 else None
+    pr = torch.empty((P, N), dtype=torch.float32, device=dev) if probs else None
+    p16 = torch.empty((P, N), dtype=torch.float16, device=dev) if probs_f16 else None
+    ctx.check(L.lib().legs_decode_dmlp(ctx.handle, tp, P, cs, ps, _p(params), N, mlp_flags(normalize),
+                                       _p(pr), _p(p16), _p(t1), _stream()))
+    return (t1[:P] if t1 is not None else None), pr, p16
+
+
+def language_features(ctx: Context, probs_f16, S, out_f16=False, F=None):
+    """F = M S planar [d][P] (legs_language_features); probs_f16 [P][N]
+    float16, S [N][d] float32."""
+    assert probs_f16.dtype == torch.float16 and probs_f16.is_contiguous()
+    assert S.dtype == torch.float32 and S.is_contiguous()
+    P, N = probs_f16.shape
+    d = S.shape[1]
+    if F is None:
+        F = torch.empty((d, P), dtype=torch.float16 if out_f16 else torch.float32, device=ctx.device)
+    ctx.check(L.lib().legs_language_features(ctx.handle, _p(probs_f16), P, N, _p(S), d, int(bool(out_f16)),
+                                             _p(F), _stream()))
+    return F
+
+
 class MlpTrainer:
     """Decoder parameters, Adam moments and scratch for legs_mlp_train_step."""
 

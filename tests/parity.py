@@ -208,3 +208,36 @@ def compare_grads(g, ref, n, tol=1e-3, groups=GROUPS, subset=None, floor=None, g
         if global_tol is not None and grp in worst:
             assert worst[grp]["global_rel"] <= global_tol, (grp, worst[grp])
     return worst
+
+
+def check_mlp_probs(pr_gpu, feat, ws, bs, normalize, tol=2e-5, max_unresolved_frac=0.002):
+    """GPU decoder probabilities [P][N] against the oracle. A pixel none of
+    whose bf16-rounded values lies near a rounding midpoint must be within tol
+    of the oracle's softmax; every other pixel within tol of the softmax of
+    one of its rounding branches (oracle.decode.mlp_branches), which fixes the
+    logits used for it. Pixels with more ambiguous values than the branch
+    enumeration follows (at most max_unresolved_frac of them) are left out.
+    Returns (logits [P][N] of the matched branches, resolved mask, number of
+    ambiguous pixels)."""
+    from oracle import decode as D
+    ref = D.mlp_forward(feat, ws, bs, normalize=normalize)
+    logits = ref["logits"].copy()
+    M = D.softmax(logits)
+    ok = ~ref["ambiguous"]
+    err = np.abs(pr_gpu - M).max(axis=1)
+    assert (err[ok] < tol).all(), (int((err[ok] >= tol).sum()), float(err[ok].max()))
+    resolved = ok.copy()
+    unresolved = 0
+    for i in np.nonzero(~ok)[0]:
+        br, complete = D.mlp_branches(feat[i], ws, bs, normalize=normalize)
+        errs = [np.abs(pr_gpu[i] - D.softmax(b[None])[0]).max() for b in br]
+        k = int(np.argmin(errs))
+        if errs[k] < tol:
+            logits[i] = br[k]
+            resolved[i] = True
+        else:
+            assert not complete, (i, errs[k])
+            unresolved += 1
+    assert unresolved <= max_unresolved_frac * len(feat), unresolved
+    return logits, resolved, int((~ok).sum())
+

@@ -66,6 +66,30 @@ def test_feature_map_limits():
     assert (np.abs(r3["F"]) <= r3["F_abs"] + 1e-15).all()
 
 
+def test_rounding_branches():
+    """A pixel with no value near a bf16 midpoint has one branch, the oracle's
+    logits; an input exactly at a midpoint gives two branches whose inputs
+    are the two bf16 neighbours (first-layer logits differ by W1 times one
+    bf16 ulp in that input)."""
+    rng = np.random.default_rng(140)
+    ws, bs = synth.mlp_init((8, 128, 256, 32), 141)
+    for _ in range(20):
+        x = rng.normal(0, 1, (1, 8)).astype(np.float32)
+        fw = D.mlp_forward(x, ws, bs, normalize=False)
+        br, ok = D.mlp_branches(x[0], ws, bs, normalize=False)
+        assert ok
+        if not fw["ambiguous"][0]:
+            assert len(br) == 1 and np.array_equal(br[0], fw["logits"][0])
+        else:
+            assert len(br) >= 2 and any(np.array_equal(b, fw["logits"][0]) for b in br)
+    x = np.zeros((1, 8), np.float32)
+    x[0, 3] = np.float32(1.0 + 2.0 ** -8)           # halfway between 1 and 1 + 2^-7
+    br, ok = D.mlp_branches(x[0], ws[:1], bs[:1], normalize=False)
+    assert ok and len(br) == 2
+    W = D.bf16(ws[0].astype(np.float64))
+    assert np.allclose(np.abs(br[0] - br[1]), np.abs(W[:, 3]) * 2.0 ** -7, rtol=1e-12, atol=0)
+
+
 # ------------------------------------------------------------ quantisation
 
 def _hybrid(K, N, dc, dd, seed):
