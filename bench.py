@@ -172,6 +172,178 @@ def decode_leg(log_fn, epochs=200):
                 learned_over_folded=mpx["learned"] / mpx["folded"], ms=ms)
 
 
+BF16_MFMA_PEAK_TFLOPS = 2500.0    # dense bf16 / fp16 MFMA
+
+
+def _timer(reps=5):
+    import torch
+
+    def tm(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+    return tm
+
+
+def language_leg(log_fn):
+    """Rows beyond the rasteriser, each on its own synthetic input of the
+    paper's shapes (random-init weights; what is timed is the kernel work):
+      paper_decoder  Table 3 decoder 8-128-256-128 over four 1920x1080 views of
+                     8-d rendered features (top-1 only, and the fp16
+                     distribution M_infer), then F = M_infer S with S 128 x 512
+                     (supplementary inference equations), F planar float32 / half;
+      quantize       1M hybrid features (512 CLIP + 384 DINO dims, half) against
+                     a 128-code feature space: Eqs. 4-7 with the gradient;
+      smooth         L_smo (Eqs. 13-14) with every gradient over the 1M Gaussians
+                     of the 1080p scene."""
+    import torch
+    import synth
+    from paper_2311_18482_amd import raster as R, decode as DEC
+    dev = torch.device("cuda:0")
+    ctx = R.Context(0)
+    tm = _timer()
+    res = {}
+    # --- Table 3 decoder and F = M S
+    P, N, d = 4 * 1920 * 1080, 128, 512
+    g = torch.Generator(device=dev).manual_seed(190)
+    feat = torch.randn((P, 8), generator=g, device=dev)
+    ws, bs = synth.mlp_init((8, 128, 256, N), 191)
+    params = DEC.mlp_pack(ws, bs).to(dev)
+    S = torch.from_numpy(synth.codebook(N, d, 192)).to(dev)
+    fr = DEC.rowmajor_features(feat)
+    top1 = torch.empty(P, dtype=torch.int32, device=dev)
+    p16 = torch.empty((P, N), dtype=torch.float16, device=dev)
+    F32 = torch.empty((d, P), dtype=torch.float32, device=dev)
+    lib = __import__("paper_2311_18482_amd._lib", fromlist=["lib"]).lib()
+    st = R._stream()
+
+    def dec_top1():
+        ctx.check(lib.legs_decode_dmlp(ctx.handle, R._p(feat), P, 1, 8, R._p(params), N, 0, None, None,
+                                       R._p(top1), st))
+
+    def dec_probs():
+        ctx.check(lib.legs_decode_dmlp(ctx.handle, R._p(feat), P, 1, 8, R._p(params), N, 0, None, R._p(p16),
+                                       R._p(top1), st))
+    ms_t = tm(dec_top1)
+    ms_p = tm(dec_probs)
+    ms_f = tm(lambda: DEC.language_features(ctx, p16, S, F=F32))
+    F16 = F32.view(torch.float16)[: d * P].view(d, P)
+    ms_h = tm(lambda: DEC.language_features(ctx, p16, S, out_f16=True, F=F16))
+    flop_px = 2 * (8 * 128 + 128 * 256 + 256 * N)
+    fbytes = lambda ob: P * (N * 2 * ((d + 255) // 256) + d * ob)
+    res["paper_decoder"] = dict(
+        workload=f"Table 3 decoder 8-128-256-{N} (bf16) on {P} px (4 views 1920x1080) of N(0,1) features; "
+                 f"F = M S with S {N} x {d}",
+        pixels=P, ms=dict(top1=ms_t, probs_f16=ms_p, features_f32=ms_f, features_f16=ms_h),
+        mpx_s=dict(top1=P / ms_t / 1e3, probs_f16=P / ms_p / 1e3, features_f32=P / ms_f / 1e3),
+        roofline=dict(decoder=dict(bound="mfma", unit="TFLOP/s", achieved=P * flop_px / ms_t / 1e9,
+                                   peak=BF16_MFMA_PEAK_TFLOPS,
+                                   frac=P * flop_px / ms_t / 1e9 / BF16_MFMA_PEAK_TFLOPS,
+                                   flop_per_px=flop_px),
+                      features_f32=dict(bound="hbm", unit="GB/s", achieved=fbytes(4) / ms_f / 1e6, peak=HBM_PEAK_GBS,
+                                        frac=fbytes(4) / ms_f / 1e6 / HBM_PEAK_GBS, bytes_per_px=fbytes(4) / P),
+                      features_f16=dict(bound="hbm", unit="GB/s", achieved=fbytes(2) / ms_h / 1e6, peak=HBM_PEAK_GBS,
+                                        frac=fbytes(2) / ms_h / 1e6 / HBM_PEAK_GBS, bytes_per_px=fbytes(2) / P)))
+    log_fn(f"paper decoder: {json.dumps(res['paper_decoder'])}")
+    del feat, top1, p16, F32, F16
+    torch.cuda.empty_cache()
+    # --- quantisation
+    K, N, dc, dd = 1 << 20, 128, 512, 384
+    d = dc + dd
+    rng = np.random.default_rng(193)
+    Sq = rng.normal(0, 1, (N, d)).astype(np.float32)
+    Ft = (torch.from_numpy(Sq).to(dev)[torch.randint(0, N, (K,), generator=g, device=dev)] +
+          1.5 * torch.randn((K, d), generator=g, device=dev)).half().contiguous()
+    Sd = torch.from_numpy(Sq).to(dev)
+    wsq = torch.empty(int(lib.legs_quantize_workspace_bytes(K, N, d)), dtype=torch.uint8, device=dev)
+    ms_a = tm(lambda: DEC.quantize(ctx, Ft, Sd, dc, grad=False, workspace=wsq))
+    ms_g = tm(lambda: DEC.quantize(ctx, Ft, Sd, dc, grad=True, workspace=wsq))
+    fl = 2 * K * N * d
+    res["quantize"] = dict(
+        workload=f"{K} hybrid features ({dc} CLIP + {dd} DINO dims, half) scattered around a {N}-code space; "
+                 f"lambda_DINO = lambda_lb = 0.5, lambda_cos = 1",
+        features=K, ms=dict(assign=ms_a, assign_and_grad=ms_g),
+        mfeat_s=dict(assign=K / ms_a / 1e3, assign_and_grad=K / ms_g / 1e3),
+        roofline=dict(assign=dict(bound="hbm", unit="GB/s", achieved=K * d * 2 / ms_a / 1e6, peak=HBM_PEAK_GBS,
+                                  frac=K * d * 2 / ms_a / 1e6 / HBM_PEAK_GBS, bytes_per_feature=d * 2,
+                                  mfma_frac=fl / ms_a / 1e9 / BF16_MFMA_PEAK_TFLOPS),
+                      assign_and_grad=dict(bound="hbm", unit="GB/s", achieved=2 * K * d * 2 / ms_g / 1e6,
+                                           peak=HBM_PEAK_GBS, frac=2 * K * d * 2 / ms_g / 1e6 / HBM_PEAK_GBS,
+                                           bytes_per_feature=2 * d * 2,
+                                           mfma_frac=3 * fl / ms_g / 1e9 / BF16_MFMA_PEAK_TFLOPS)))
+    log_fn(f"quantize: {json.dumps(res['quantize'])}")
+    del Ft, Sd, wsq
+    torch.cuda.empty_cache()
+    # --- smoothing
+    scene, _ = synth.workload_1m_1080p()
+    n, C = scene.channels.shape
+    mean = torch.from_numpy(scene.mean).to(dev)
+    chans = torch.from_numpy(scene.channels).to(dev)
+    ws3, bs3 = synth.mlp_init((3, 128, 128, 128, 8), 194)
+    sp = torch.cat([torch.from_numpy(np.concatenate([W.reshape(-1), b])) for W, b in zip(ws3, bs3)]).to(dev)
+    grad = torch.zeros_like(sp)
+    dch = torch.zeros_like(chans)
+    loss = torch.zeros(1, device=dev)
+    wss = DEC.smooth_workspace(ctx, n)
+    ms_s = tm(lambda: DEC.smooth_loss_grad(ctx, mean, chans, 3, C - 1, sp, grad, dch, loss, workspace=wss))
+    flop_g = 2 * (3 * 128 + 2 * 128 * 128 + 128 * 8) * 3       # forward, input-side backward, weight gradient
+    res["smooth"] = dict(
+        workload=f"L_smo and its gradients over {n} Gaussians (the 1080p scene), MLP 3-128-128-128-8 bf16",
+        gaussians=int(n), ms=ms_s, mgauss_s=n / ms_s / 1e3,
+        roofline=dict(bound="mfma", unit="TFLOP/s", achieved=n * flop_g / ms_s / 1e9, peak=BF16_MFMA_PEAK_TFLOPS,
+                      frac=n * flop_g / ms_s / 1e9 / BF16_MFMA_PEAK_TFLOPS, flop_per_gaussian=flop_g))
+    log_fn(f"smooth: {json.dumps(res['smooth'])}")
+    return res
+
+
+def c5_leg(log_fn, steps, warmup):
+    """One optimisation step of every per-Gaussian parameter (render, L1 +
+    L_u, backward, fused Adam) at 3M Gaussians x 4 views 1920x1080, C = 20,
+    replayed as one HIP graph."""
+    import torch
+    import synth
+    from paper_2311_18482_amd import raster as R
+    from paper_2311_18482_amd.train import TrainStep
+    dev = torch.device("cuda:0")
+    scene, cams = synth.workload_c5()
+    n, C = scene.channels.shape
+    d_sem = C - 4
+    target = torch.from_numpy(synth.targets_l1(cams, C, d_sem, 205)).to(dev)
+    params = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in
+              (("mean", scene.mean), ("log_scale", scene.log_scale), ("quat", scene.quat),
+               ("opacity_logit", scene.opacity_logit), ("channels", scene.channels))}
+    torch.cuda.reset_peak_memory_stats()
+    ts = TrainStep(cams, params, target, d_sem, o=R.opts(tile=32, lds_batch=256))
+    for _ in range(warmup):
+        ts.step()
+    torch.cuda.synchronize()
+    g = ts.capture(step_number=warmup + 1)
+    g.launch()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    px = sum(c.width * c.height for c in cams)
+    res = dict(workload=f"{n} Gaussians in [-4,4]^3, {len(cams)} views 1920x1080, C={C} (RGB + {d_sem} sem + u); "
+                        f"per-view L1 + L_u, Adam on all {n * (11 + C)} floats",
+               ms_per_step=ms, mpx_s=px / ms / 1e3, instances=int(ts.bins.count.item()),
+               overflowed=bool(ts.overflowed()), peak_mem_gib=torch.cuda.max_memory_allocated() / 2 ** 30)
+    log_fn(f"c5: {json.dumps(res)}")
+    return res
+
+
 def _oracle_step(O, scene, cams, oo, G):
     """One forward + backward of the oracle, stage by stage; returns seconds per stage."""
     t = {}
@@ -401,6 +573,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-decode", action="store_true", help="skip the learned-vs-plain decode leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the 16-view batch leg")
+    ap.add_argument("--no-language", action="store_true",
+                    help="skip the Table 3 decoder / feature map, quantisation and smoothing legs")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 3M-Gaussian training-step leg")
     ap.add_argument("--decode-epochs", type=int, default=200,
                     help="decoder training epochs of the decode leg (fewer only to profile its kernels)")
     ap.add_argument("--eager", action="store_true",
@@ -506,6 +681,18 @@ def main():
         dec = decode_leg(log, epochs=args.decode_epochs)
         log(f"decode: {json.dumps(dec)}")
 
+    lang = None
+    if not args.no_language and args.workload == "1m_1080p":
+        log("language legs: Table 3 decoder and F, quantisation, smoothing")
+        lang = language_leg(log)
+        torch.cuda.empty_cache()
+
+    c5 = None
+    if not args.no_c5 and args.workload == "1m_1080p":
+        log("c5 leg: training step at 3M Gaussians x 4 views")
+        c5 = c5_leg(log, max(5, args.steps // 2), 2)
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
@@ -521,7 +708,7 @@ def main():
                            blended_entries=int(blended), stage_ms=stage_ms,
                            launch="eager" if graph_ms is None else "hip graph replay of the whole step",
                            eager_ms_per_step=eager_ms, persistent_blend=bool(args.persistent)),
-               roofline=roofline, c3=c3, decode=dec, cpu_baseline=cpu)
+               roofline=roofline, c3=c3, decode=dec, language=lang, c5=c5, cpu_baseline=cpu)
     print(json.dumps(rec), flush=True)
 
 

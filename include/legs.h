@@ -312,6 +312,57 @@ int32_t legs_decode_dmlp(legs_ctx *ctx, const float *feat, int64_t P, int64_t c_
 int32_t legs_language_features(legs_ctx *ctx, const uint16_t *probs_f16, int64_t P, int32_t N,
                                const float *S, int32_t d, int32_t out_f16, void *F, void *stream);
 
+/* Quantisation of K hybrid language features into the discrete feature space
+ * S (Sec. 3.3) and its optimisation objective:
+ *   D_ij = cos(F_i^CLIP, f_j^CLIP) + lambda_dino cos(F_i^DINO, f_j^DINO)  (Eq. 4)
+ *   index_i = argmax_j D_ij (lowest j on ties); F^_i = f_index_i         (Eq. 5)
+ *   L_cos = mean_i [(1 - cos(F_i^C, F^_i^C)) + lambda_dino (1 - cos(F_i^D, F^_i^D))]  (Eq. 6)
+ *   r = histogram(index) / K, p = mean_i softmax_j(D_ij), L_lb = sum_j r_j p_j
+ *                                            (Eq. 7, supplementary load balancing)
+ *   L_q = lambda_cos L_cos + lambda_lb L_lb
+ * feat [K][d] IEEE half (16-byte aligned, K >= 1), columns [0, d_clip) the CLIP part
+ * and [d_clip, d) the DINO part; S [N][d] float32 (16-byte aligned), rounded
+ * to half for every use; N 32, 64 or 128; d and d_clip multiples of 128
+ * (d <= 8192). Outputs (overwritten): index [K] int32, counts [N] uint32 (the
+ * histogram, r = counts / K), prob_mean [N] float32 (p; nullable), losses [3]
+ * float32 = (L_cos, L_lb, L_q) (nullable), grad [N][d] float32 = dL_q/dS
+ * (nullable: no gradient pass), straight through the half rounding of S;
+ * the index and r are piecewise constant (no gradient). A zero part of a
+ * feature or code has cosine 0. workspace: legs_quantize_workspace_bytes(K,
+ * N, d) bytes (16-byte aligned). Dot products accumulate in float32 on FP16
+ * MFMA; features whose two best distances lie within float32 rounding of each
+ * other may take either index. */
+int64_t legs_quantize_workspace_bytes(int64_t K, int32_t N, int32_t d);
+int32_t legs_quantize(legs_ctx *ctx, const uint16_t *feat, int64_t K, int32_t d, int32_t d_clip,
+                      const float *S, int32_t N, float lambda_dino, float lambda_cos, float lambda_lb,
+                      void *workspace, int32_t *index, uint32_t *counts, float *prob_mean, float *losses,
+                      float *grad, void *stream);
+
+/* Adaptive spatial smoothing of the semantic features (Sec. 3.4.2, Eqs.
+ * 13-14, Table 4): s_MLP = MLP(PE(p)) with PE configuration 0 (the position
+ * itself) and MLP 3 -> 128 -> 128 -> 128 -> 8 (ReLU after the first three
+ * layers), and
+ *   L_smo = lambda_smo mean_g [ |s_MLP - s_G*| + max(u_G*, w_s) |s_MLP* - s_G| ]
+ * (unsquared Euclidean norms, * = stop gradient). mean [n][3] are the
+ * Gaussian positions (inputs only: this loss moves no position), channels
+ * [n][C] the per-Gaussian channels with s_G at [sem_channel, sem_channel + 8)
+ * and u at u_channel. params: float32 masters [legs_smooth_param_count()]
+ * packed W1 [128][3], b1 [128], W2 [128][128], b2, W3 [128][128], b3,
+ * W4 [8][128], b4 [8]; weights and hidden activations are rounded to bf16,
+ * the position enters unrounded, accumulation is float32 (the backward's
+ * upstream gradients are carried as two bf16 parts, 16 significant bits).
+ * Accumulates (+=): loss [1] += L_smo, grad [legs_smooth_param_count()] +=
+ * dL_smo/dparams, d_channels [n][C] += dL_smo/ds_G in the s_G columns (u gets
+ * no gradient). A Gaussian with s_MLP = s_G adds nothing. workspace:
+ * legs_smooth_workspace_bytes(n) bytes (16-byte aligned), which on return
+ * holds the bf16 hidden activations (unit-major planes) of the forward pass. */
+int64_t legs_smooth_param_count(void);
+int64_t legs_smooth_workspace_bytes(int64_t n);
+int32_t legs_smooth_loss_grad(legs_ctx *ctx, const float *mean, const float *channels, int32_t C,
+                              int32_t sem_channel, int32_t u_channel, int64_t n, const float *params,
+                              float w_s, float lambda_smo, void *workspace, float *grad, float *d_channels,
+                              float *loss, void *stream);
+
 /* Gradient of the mean cross-entropy (Eq. 9) of B pixels against labels
  * [B] int32 in [0, K): grad [legs_mlp_param_count(K)] is overwritten, loss [1]
  * receives the mean loss. Straight-through for the bf16 roundings.

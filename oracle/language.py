@@ -52,7 +52,7 @@ def _unit_rows(X):
     return X / np.where(n > 0.0, n, 1.0)[:, None], n
 
 
-def quantize(F, S, d_clip, lambda_dino=0.5, lambda_cos=1.0, lambda_lb=0.5):
+def quantize(F, S, d_clip, lambda_dino=0.5, lambda_cos=1.0, lambda_lb=0.5, m=None):
     """F [K, d] hybrid features (columns [0, d_clip) CLIP, the rest DINO),
     S [N, d] the discrete feature space with the same split.
 
@@ -64,7 +64,9 @@ def quantize(F, S, d_clip, lambda_dino=0.5, lambda_cos=1.0, lambda_lb=0.5):
     L_q = lambda_cos L_cos + lambda_lb L_lb
 
     The gradient is with respect to S (the optimised feature space); the
-    argmax and therefore r are piecewise constant (no gradient). A zero row
+    argmax and therefore r are piecewise constant (no gradient). m (optional)
+    replaces the argmax (to follow another evaluation's choice among
+    near-equal distances). A zero row
     (feature or code part) has cosine 0 and no gradient through it.
     Returns dict with D, cos_c, cos_d, m, r, p, L_cos, L_lb, L_q, dD (dL_q/dD),
     grad [N, d] and margin (top-1 minus top-2 of each row of D)."""
@@ -79,7 +81,7 @@ def quantize(F, S, d_clip, lambda_dino=0.5, lambda_cos=1.0, lambda_lb=0.5):
     cos_c = Fc @ Sc.T
     cos_d = Fd @ Sd.T
     D = cos_c + lambda_dino * cos_d
-    m = np.argmax(D, axis=1)
+    m = np.argmax(D, axis=1) if m is None else np.asarray(m, np.int64)
     srt = np.sort(D, axis=1)
     margin = srt[:, -1] - srt[:, -2] if N > 1 else np.full(K, np.inf)
     rows = np.arange(K)
@@ -117,12 +119,14 @@ def positional_encoding(pos, n_freq):
     return np.concatenate(parts, axis=1)
 
 
-def smooth_forward(pos, weights, biases, n_freq=0, round_bf16=True):
+def smooth_forward(pos, weights, biases, n_freq=0, round_bf16=True, hidden=None):
     """s_MLP = MLP(PE(p)) (Eq. 13): fully connected layers with ReLU between
     them (Table 4: PE -> 128 -> 128 -> 128 -> 8). Weights and the hidden
     activations are rounded to bf16 (round_bf16); the encoded position enters
-    the first layer unrounded. Returns dict with hs (layer inputs), zs
-    (pre-activations) and out (float64)."""
+    the first layer unrounded. hidden (optional): the hidden activations to
+    use instead of the computed ones (another evaluation's rounding choices);
+    the pre-activations are still computed from the previous layer's.
+    Returns dict with hs (layer inputs), zs (pre-activations) and out (float64)."""
     rnd = bf16 if round_bf16 else (lambda a: np.asarray(a, np.float64))
     h = positional_encoding(np.asarray(pos, np.float32), n_freq)
     hs, zs = [h], []
@@ -133,20 +137,22 @@ def smooth_forward(pos, weights, biases, n_freq=0, round_bf16=True):
         z = h @ W.T + b
         zs.append(z)
         if l < L - 1:
-            h = rnd(np.maximum(z, 0.0))
+            h = rnd(np.maximum(z, 0.0)) if hidden is None else np.asarray(hidden[l], np.float64)
             hs.append(h)
     return dict(hs=hs, zs=zs, out=zs[-1])
 
 
-def smoothing_loss_grad(pos, s_g, u, weights, biases, w_s=0.1, n_freq=0, round_bf16=True):
+def smoothing_loss_grad(pos, s_g, u, weights, biases, w_s=0.1, n_freq=0, round_bf16=True, hidden=None):
     """Adaptive spatial smoothing loss (Eq. 14) averaged over the Gaussians:
       L_smo = mean_g [ |s_MLP - s_G*|_2 + max(u_G*, w_s) |s_MLP* - s_G|_2 ]
     (* = stop gradient; unsquared Euclidean norms). The positions are inputs,
     not optimised by this loss. Gradients: the first term reaches the MLP, the
     second reaches s_G; u gets none. A Gaussian with s_MLP = s_G contributes
-    zero loss and zero gradient.
+    zero loss and zero gradient. hidden: as in smooth_forward. The ReLU gate
+    of a unit is open where its (rounded) activation is positive, which is
+    where its pre-activation is.
     Returns dict with loss, s_mlp, d_sg [n, d_s], gW, gb (lists per layer)."""
-    fw = smooth_forward(pos, weights, biases, n_freq, round_bf16)
+    fw = smooth_forward(pos, weights, biases, n_freq, round_bf16, hidden)
     sg = np.asarray(s_g, np.float64)
     uu = np.asarray(u, np.float64)
     n = sg.shape[0]
@@ -165,5 +171,5 @@ def smoothing_loss_grad(pos, s_g, u, weights, biases, w_s=0.1, n_freq=0, round_b
         gb[l] = dz.sum(axis=0)
         if l > 0:
             W = rnd(np.asarray(weights[l], np.float32).astype(np.float64))
-            dz = (dz @ W) * (fw["zs"][l - 1] > 0.0)
-    return dict(loss=loss, s_mlp=fw["out"], d_sg=d_sg, gW=gW, gb=gb, norm=nrm)
+            dz = (dz @ W) * (fw["hs"][l] > 0.0)
+    return dict(loss=loss, s_mlp=fw["out"], d_sg=d_sg, gW=gW, gb=gb, norm=nrm, hs=fw["hs"], zs=fw["zs"])

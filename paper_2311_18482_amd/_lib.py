@@ -99,6 +99,12 @@ _SIGS = {
     "legs_decode_mlp": (I32, [P, P, I64, I64, I64, P, I32, I32, P, P, P]),
     "legs_mlp_workspace_bytes": (I64, [I64, I32]),
     "legs_dmlp_param_count": (I64, [I32]),
+    "legs_smooth_param_count": (I64, []),
+    "legs_smooth_workspace_bytes": (I64, [I64]),
+    "legs_smooth_loss_grad": (I32, [P, P, P, I32, I32, I32, I64, P, ct.c_float, ct.c_float, P, P, P, P, P]),
+    "legs_quantize_workspace_bytes": (I64, [I64, I32, I32]),
+    "legs_quantize": (I32, [P, P, I64, I32, I32, P, I32, ct.c_float, ct.c_float, ct.c_float, P, P, P, P, P,
+                            P, P]),
     "legs_decode_dmlp": (I32, [P, P, I64, I64, I64, P, I32, I32, P, P, P, P]),
     "legs_language_features": (I32, [P, P, I64, I32, P, I32, I32, P, P]),
     "legs_mlp_grad": (I32, [P, P, I64, I64, I64, P, I32, I32, P, P, P, P, P]),

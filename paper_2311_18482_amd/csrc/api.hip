@@ -474,6 +474,50 @@ int32_t legs_language_features(legs_ctx *ctx, const uint16_t *probs_f16, int64_t
     return legs_launch_language_features(ctx, probs_f16, P, N, S, d, out_f16, F, (hipStream_t)stream);
 }
 
+int32_t legs_quantize(legs_ctx *ctx, const uint16_t *feat, int64_t K, int32_t d, int32_t d_clip,
+                      const float *S, int32_t N, float lambda_dino, float lambda_cos, float lambda_lb,
+                      void *workspace, int32_t *index, uint32_t *counts, float *prob_mean, float *losses,
+                      float *grad, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (K < 1 || K > (1ll << 31) - 256) return legs_set_error(ctx, LEGS_ERR_ARG, "K out of [1, 2^31 - 256]");
+    if (N != 32 && N != 64 && N != 128) return legs_set_error(ctx, LEGS_ERR_ARG, "N must be 32, 64 or 128");
+    if (d < 128 || d > 8192 || d % 128 || d_clip < 0 || d_clip > d || d_clip % 128)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "d and d_clip must be multiples of 128, 0 <= d_clip <= d <= 8192");
+    if (!S || !workspace || !counts || !feat || !index)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "NULL argument");
+    if ((reinterpret_cast<uintptr_t>(feat) | reinterpret_cast<uintptr_t>(S) |
+         reinterpret_cast<uintptr_t>(workspace)) & 15)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "feat, S and workspace must be 16-byte aligned");
+    if (!(lambda_dino >= 0.f) || !(lambda_cos >= 0.f) || !(lambda_lb >= 0.f))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "negative or NaN weight");
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_quantize(ctx, feat, K, d, d_clip, S, N, lambda_dino, lambda_cos, lambda_lb, workspace,
+                                index, counts, prob_mean, losses, grad, (hipStream_t)stream);
+}
+
+int64_t legs_smooth_param_count(void) { return LEGS_SMOOTH_NPARAMS; }
+
+int32_t legs_smooth_loss_grad(legs_ctx *ctx, const float *mean, const float *channels, int32_t C,
+                              int32_t sem_channel, int32_t u_channel, int64_t n, const float *params,
+                              float w_s, float lambda_smo, void *workspace, float *grad, float *d_channels,
+                              float *loss, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (n < 0 || n > (1ll << 31) - 64) return legs_set_error(ctx, LEGS_ERR_ARG, "n out of range");
+    if (C < 1 || C > LEGS_MAX_CHANNELS || sem_channel < 0 || sem_channel + LEGS_SMOOTH_OUT > C ||
+        u_channel < 0 || u_channel >= C)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "channel layout out of range");
+    if (!params || !grad || !loss || (n > 0 && (!mean || !channels || !workspace || !d_channels)))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(workspace) & 15)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "workspace must be 16-byte aligned");
+    if (!(w_s >= 0.f) || !(lambda_smo >= 0.f)) return legs_set_error(ctx, LEGS_ERR_ARG, "negative or NaN weight");
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_smooth(ctx, mean, channels, C, sem_channel, u_channel, n, params, w_s, lambda_smo,
+                              workspace, grad, d_channels, loss, (hipStream_t)stream);
+}
+
 int32_t legs_semantic_loss_grad_noalloc(legs_ctx *ctx, const float *feat, const float *ru, int64_t P,
                                         int64_t c_stride, int64_t p_stride, const int32_t *labels,
                                         int32_t K, int32_t mlp_flags, const float *params,

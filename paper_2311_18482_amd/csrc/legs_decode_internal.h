@@ -28,6 +28,20 @@
 #define LEGS_DMLP_OFF_B3(KB) (LEGS_DMLP_OFF_W3 + 32 * (KB) * LEGS_DMLP_H2)
 #define LEGS_DMLP_NPARAMS(KB) (LEGS_DMLP_OFF_B3(KB) + 32 * (KB))
 
+// Smoothing MLP of Table 4: 3 -> 128 -> 128 -> 128 -> 8; float32 masters packed
+// W1 [128][3], b1 [128], W2 [128][128], b2, W3 [128][128], b3, W4 [8][128], b4 [8].
+#define LEGS_SMOOTH_H 128
+#define LEGS_SMOOTH_OUT 8
+#define LEGS_SMOOTH_OFF_W1 0
+#define LEGS_SMOOTH_OFF_B1 (LEGS_SMOOTH_OFF_W1 + LEGS_SMOOTH_H * 3)
+#define LEGS_SMOOTH_OFF_W2 (LEGS_SMOOTH_OFF_B1 + LEGS_SMOOTH_H)
+#define LEGS_SMOOTH_OFF_B2 (LEGS_SMOOTH_OFF_W2 + LEGS_SMOOTH_H * LEGS_SMOOTH_H)
+#define LEGS_SMOOTH_OFF_W3 (LEGS_SMOOTH_OFF_B2 + LEGS_SMOOTH_H)
+#define LEGS_SMOOTH_OFF_B3 (LEGS_SMOOTH_OFF_W3 + LEGS_SMOOTH_H * LEGS_SMOOTH_H)
+#define LEGS_SMOOTH_OFF_W4 (LEGS_SMOOTH_OFF_B3 + LEGS_SMOOTH_H)
+#define LEGS_SMOOTH_OFF_B4 (LEGS_SMOOTH_OFF_W4 + LEGS_SMOOTH_OUT * LEGS_SMOOTH_H)
+#define LEGS_SMOOTH_NPARAMS (LEGS_SMOOTH_OFF_B4 + LEGS_SMOOTH_OUT)
+
 // Training workspace per pixel (floats): X 8 | H1 64 | H2 64 | DZ1 64 | DZ2 64 | DZ3 K
 #define LEGS_MLP_WS_PER_PIXEL(K) (264 + (K))
 
@@ -301,6 +315,15 @@ int32_t legs_launch_decode_dmlp(legs_ctx *ctx, const float *feat, int64_t P, int
                                 uint16_t *probs16, int32_t *top1, hipStream_t s);
 int32_t legs_launch_language_features(legs_ctx *ctx, const uint16_t *probs16, int64_t P, int32_t N,
                                       const float *S, int32_t d, int32_t out_f16, void *F, hipStream_t s);
+int64_t legs_smooth_workspace_bytes(int64_t n);
+int32_t legs_launch_smooth(legs_ctx *ctx, const float *mean, const float *channels, int32_t C, int32_t sem,
+                           int32_t uch, int64_t n, const float *params, float w_s, float lambda_smo,
+                           void *workspace, float *grad, float *d_channels, float *loss, hipStream_t s);
+int64_t legs_quantize_workspace_bytes(int64_t K, int32_t N, int32_t d);
+int32_t legs_launch_quantize(legs_ctx *ctx, const uint16_t *feat, int64_t K, int32_t d, int32_t dC,
+                             const float *S, int32_t N, float lam_d, float lam_cos, float lam_lb,
+                             void *workspace, int32_t *index, uint32_t *counts, float *prob_mean,
+                             float *losses, float *grad, hipStream_t s);
 int64_t legs_mlp_workspace_floats(int64_t B, int32_t K);
 int32_t legs_launch_mlp_grad(legs_ctx *ctx, const float *feat, int64_t B, int64_t cs, int64_t ps,
                              const int32_t *labels, int32_t K, int32_t mlp_flags, const float *params,

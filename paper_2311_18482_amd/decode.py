@@ -124,6 +124,55 @@ def language_features(ctx: Context, probs_f16, S, out_f16=False, F=None):
     return F
 
 
+def quantize(ctx: Context, feat, S, d_clip, lambda_dino=0.5, lambda_cos=1.0, lambda_lb=0.5, grad=True,
+             workspace=None):
+    """Codebook quantisation (legs_quantize). feat [K][d] float16, S [N][d]
+    float32. Returns dict with index [K] int32, counts [N] int32 (uint32
+    bits), prob_mean [N], losses [3] = (L_cos, L_lb, L_q) and grad [N][d]
+    (None without the gradient pass)."""
+    assert feat.dtype == torch.float16 and feat.is_contiguous() and S.dtype == torch.float32
+    K, d = feat.shape
+    N = S.shape[0]
+    dev = ctx.device
+    if workspace is None:
+        workspace = torch.empty(max(int(L.lib().legs_quantize_workspace_bytes(K, N, d)), 16), dtype=torch.uint8,
+                                device=dev)
+    out = dict(index=torch.empty(max(K, 1), dtype=torch.int32, device=dev),
+               counts=torch.empty(N, dtype=torch.int32, device=dev),
+               prob_mean=torch.empty(N, dtype=torch.float32, device=dev),
+               losses=torch.empty(3, dtype=torch.float32, device=dev),
+               grad=torch.empty((N, d), dtype=torch.float32, device=dev) if grad else None)
+    ctx.check(L.lib().legs_quantize(ctx.handle, _p(feat), K, d, int(d_clip), _p(S), N, float(lambda_dino),
+                                    float(lambda_cos), float(lambda_lb), _p(workspace), _p(out["index"]),
+                                    _p(out["counts"]), _p(out["prob_mean"]), _p(out["losses"]), _p(out["grad"]),
+                                    _stream()))
+    out["index"] = out["index"][:K]
+    return out
+
+
+def smooth_param_count():
+    return int(L.lib().legs_smooth_param_count())
+
+
+def smooth_workspace(ctx: Context, n):
+    return torch.empty(max(int(L.lib().legs_smooth_workspace_bytes(n)), 16), dtype=torch.uint8, device=ctx.device)
+
+
+def smooth_loss_grad(ctx: Context, mean, channels, sem_channel, u_channel, params, grad, d_channels, loss,
+                     w_s=0.1, lambda_smo=1.0, workspace=None):
+    """Adaptive spatial smoothing loss and gradients (legs_smooth_loss_grad);
+    loss, grad and d_channels are accumulated. Returns the workspace (which
+    holds the bf16 hidden activations, unit-major, rows padded to a multiple
+    of 64 Gaussians)."""
+    n, C = channels.shape
+    if workspace is None:
+        workspace = smooth_workspace(ctx, n)
+    ctx.check(L.lib().legs_smooth_loss_grad(ctx.handle, _p(mean), _p(channels), C, int(sem_channel), int(u_channel),
+                                            n, _p(params), float(w_s), float(lambda_smo), _p(workspace), _p(grad),
+                                            _p(d_channels), _p(loss), _stream()))
+    return workspace
+
+
 class MlpTrainer:
     """Decoder parameters, Adam moments and scratch for legs_mlp_train_step."""
 

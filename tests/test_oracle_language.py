@@ -289,3 +289,27 @@ def test_smoothing_closed_forms_and_stop_gradient_routing():
         sm[g, c] -= h
         f2 = lambda s: np.mean(wgt * np.linalg.norm(r["s_mlp"] - s, axis=1))
         assert r["d_sg"][g, c] == pytest.approx((f2(sp) - f2(sm)) / (2 * h), rel=1e-6, abs=1e-12)
+
+
+def test_smoothing_follows_given_activations():
+    """Given its own hidden activations the smoothing loss is unchanged; given
+    one activation moved by a bf16 ulp it equals a fresh evaluation of the
+    layers above from that activation."""
+    rng = np.random.default_rng(134)
+    ws, bs = synth.mlp_init((3, 128, 128, 128, 8), 135)
+    pos = rng.uniform(-4, 4, (40, 3)).astype(np.float32)
+    sg = rng.normal(0, 1, (40, 8))
+    u = rng.uniform(0, 1, 40)
+    r = LG.smoothing_loss_grad(pos, sg, u, ws, bs)
+    r2 = LG.smoothing_loss_grad(pos, sg, u, ws, bs, hidden=r["hs"][1:])
+    assert r2["loss"] == r["loss"] and np.array_equal(r2["d_sg"], r["d_sg"])
+    assert all(np.array_equal(a, b) for a, b in zip(r["gW"], r2["gW"]))
+    hid = [h.copy() for h in r["hs"][1:]]
+    g, k = 7, int(np.argmax(hid[2][7]))
+    hid[2][g, k] = D.bf16(hid[2][g, k] * (1 + 2.0 ** -7))          # one ulp up
+    r3 = LG.smoothing_loss_grad(pos, sg, u, ws, bs, hidden=hid)
+    W4 = D.bf16(ws[3].astype(np.float64))
+    out = hid[2] @ W4.T + bs[3].astype(np.float64)
+    assert np.allclose(r3["s_mlp"], out, rtol=1e-14, atol=1e-14)
+    assert not np.allclose(r3["s_mlp"][g], r["s_mlp"][g], rtol=1e-9, atol=0)
+
