@@ -235,7 +235,7 @@ def language_leg(log_fn):
     ms_t = tm(dec_top1)
     ms_p = tm(dec_probs)
     ms_f = tm(lambda: DEC.language_features(ctx, p16, S, F=F32))
-    F16 = F32.view(torch.float16)[: d * P].view(d, P)
+    F16 = F32.view(-1).view(torch.float16)[: d * P].view(d, P)
     ms_h = tm(lambda: DEC.language_features(ctx, p16, S, out_f16=True, F=F16))
     flop_px = 2 * (8 * 128 + 128 * 256 + 256 * N)
     fbytes = lambda ob: P * (N * 2 * ((d + 255) // 256) + d * ob)

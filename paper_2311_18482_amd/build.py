@@ -35,7 +35,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=o
 # read by VALU code right away (ReLU and bf16 packing, the argmax), which from
 # accumulation registers would cost one extra move per value.
 EXTRA = {"decode.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
-         "mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+         "mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+         "language.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+         "smooth.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def sources():

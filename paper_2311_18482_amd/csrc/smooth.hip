@@ -18,13 +18,14 @@
 //
 //  k_smooth_fwd_bwd  per 32-Gaussian tile (two per wave): forward, loss,
 //                    dL/ds_G (accumulated into the channel gradient), and
-//                    dz of every layer; writes the hidden activations and the
-//                    split dz unit-major ([unit][Gaussian], 64-byte runs per
-//                    half wave) into the workspace.
+//                    dz of every layer; writes the bf16 hidden activations and
+//                    the float32 dz unit-major ([unit][Gaussian], 64- and
+//                    128-byte runs per half wave) into the workspace.
 //  k_smooth_wgrad    dW_l = sum_g dz_l h_(l-1)^T and db_l = sum_g dz_l: the
 //                    Gaussians are the MFMA contraction, read straight from
 //                    the unit-major planes (8 consecutive Gaussians of one
-//                    unit = one 16-byte fragment); split over Gaussian chunks
+//                    unit = one 16-byte fragment; dz split into two bf16 parts
+//                    as it is loaded); split over Gaussian chunks
 //                    (x) and layers (y), float atomics into the gradient.
 #include "legs_internal.h"
 #include "legs_decode_internal.h"
@@ -134,7 +135,7 @@ struct SmoothArgs {
     float w_s, inv_n;             // inv_n = lambda_smo / n
     float *d_ch, *loss;
     __bf16 *X, *H1, *H2, *H3;     // [16][Gp], [128][Gp] x 3
-    __bf16 *D1, *D2, *D3, *D4;    // split dz: [2][rows][Gp] (hi plane, then lo plane)
+    float *D1, *D2, *D3, *D4;     // dz: [rows][Gp] float32
 };
 
 // Hidden-layer step: acc of block mb from B fragments x[NT][KS] and A
@@ -292,16 +293,13 @@ k_smooth_fwd_bwd(SmoothArgs A)
             }
         }
         // backward through the layers: dz_l split into hi and lo bf16 parts
-        auto put_dz = [&](__bf16 *plane, int rows, const f32x16 &z, int mb, int t) {
+        auto put_dz = [&](float *plane, int rows, const f32x16 &z, int mb, int t) {
             if (gi[t] >= A.Gp) return;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int u = 32 * mb + legs_drow(r, h);
                 if (u >= rows) continue;
-                const float v = valid[t] ? z[r] : 0.0f;
-                const __bf16 a = (__bf16)v;
-                store_plane(plane, A.Gp, u, gi[t], a);
-                store_plane(plane + (int64_t)rows * A.Gp, A.Gp, u, gi[t], (__bf16)(v - (float)a));
+                plane[(int64_t)u * A.Gp + gi[t]] = valid[t] ? z[r] : 0.0f;
             }
         };
 #pragma unroll
@@ -328,7 +326,7 @@ k_smooth_fwd_bwd(SmoothArgs A)
                     for (int r = 0; r < 16; ++r)
                         if (!((float)hf[t][2 * mb + (r >> 3)][r & 7] > 0.0f)) dz[t][mb][r] = 0.0f;
         };
-        auto back = [&](const bf16x8 *__restrict__ T, __bf16 *plane) {
+        auto back = [&](const bf16x8 *__restrict__ T, float *plane) {
 #pragma unroll
             for (int t = 0; t < SNT; ++t)
 #pragma unroll
@@ -376,46 +374,61 @@ k_smooth_wgrad(SmoothArgs A, float *__restrict__ grad)
 {
     const int layer = blockIdx.y;
     const int lane = __lane_id(), wave = threadIdx.x / LEGS_WAVE, h = lane >> 5;
-    const __bf16 *Dp = layer == 0 ? A.D1 : layer == 1 ? A.D2 : layer == 2 ? A.D3 : A.D4;
+    const float *Dp = layer == 0 ? A.D1 : layer == 1 ? A.D2 : layer == 2 ? A.D3 : A.D4;
     const __bf16 *Bp = layer == 0 ? A.X : layer == 1 ? A.H1 : layer == 2 ? A.H2 : A.H3;
     const int M = layer == 3 ? LEGS_SMOOTH_OUT : SH;          // rows of D
     const int Kb = layer == 0 ? 16 : SH;                      // rows of B
     const int MB = (M + 31) / 32, NB = (Kb + 31) / 32;
-    // blocks (mb, nb) dealt to the 4 waves
-    const int nblk = MB * NB;
+    // wave w owns the 32 rows of block w of D against every block of B, so
+    // each fragment of D is loaded once and each of B once per wave
+    if (wave >= MB) return;
+    const int mb = wave, m = 32 * mb + (lane & 31);
     const int64_t g0 = (int64_t)blockIdx.x * WG_CHUNK_G;
     const int64_t g1 = min(g0 + (int64_t)WG_CHUNK_G, A.Gp);
-    const __bf16 *Dlo = Dp + (int64_t)M * A.Gp;
-    for (int blk = wave; blk < nblk; blk += 4) {
-        const int mb = blk / NB, nb = blk % NB;
-        const int m = 32 * mb + (lane & 31), k = 32 * nb + (lane & 31);
-        f32x16 acc = {};
-        float dbs = 0.0f;
-        for (int64_t g = g0; g < g1; g += 16) {
-            const int64_t gg = g + 8 * h;
-            bf16x8 ah = {}, al = {}, b = {};
-            if (m < M) {
-                ah = *reinterpret_cast<const bf16x8 *>(Dp + (int64_t)m * A.Gp + gg);
-                al = *reinterpret_cast<const bf16x8 *>(Dlo + (int64_t)m * A.Gp + gg);
-            }
-            if (k < Kb) b = *reinterpret_cast<const bf16x8 *>(Bp + (int64_t)k * A.Gp + gg);
-            acc = legs_mfma(al, b, legs_mfma(ah, b, acc));
-            if (nb == 0) {
+    const float *Drow = Dp + (int64_t)m * A.Gp + 8 * h;
+    const __bf16 *Bq[4];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) dbs += (float)ah[e] + (float)al[e];
+    for (int nb = 0; nb < 4; ++nb) Bq[nb] = Bp + (int64_t)(32 * nb + (lane & 31)) * A.Gp + 8 * h;
+    const bool mrow = m < M;
+    bool krow[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) krow[nb] = nb < NB && 32 * nb + (lane & 31) < Kb;
+    f32x16 acc[4] = {};
+    float dbs = 0.0f;
+#pragma unroll 2
+    for (int64_t g = g0; g < g1; g += 16) {
+        bf16x8 ah = {}, al = {}, b[4];
+        if (mrow) {                 // dz as hi + lo bf16 parts (16 significant bits)
+            const float4 v0 = *reinterpret_cast<const float4 *>(Drow + g);
+            const float4 v1 = *reinterpret_cast<const float4 *>(Drow + g + 4);
+            const float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                ah[e] = (__bf16)v[e];
+                al[e] = (__bf16)(v[e] - (float)ah[e]);
             }
         }
-        // bias gradient: rows m of this block, both lane halves
-        if (nb == 0 && layer != 0) {
-            dbs += __shfl_xor(dbs, 32, LEGS_WAVE);
-            float *db = grad + (layer == 1 ? LEGS_SMOOTH_OFF_B2 : layer == 2 ? LEGS_SMOOTH_OFF_B3 : LEGS_SMOOTH_OFF_B4);
-            if (h == 0 && m < M && dbs != 0.0f) atomicAdd(db + m, dbs);
-        }
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) b[nb] = krow[nb] ? *reinterpret_cast<const bf16x8 *>(Bq[nb] + g) : (bf16x8){};
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+            if (nb < NB) acc[nb] = legs_mfma(al, b[nb], legs_mfma(ah, b[nb], acc[nb]));
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dbs += (float)ah[e] + (float)al[e];
+    }
+    if (layer != 0) {                                           // bias gradient of rows m
+        dbs += __shfl_xor(dbs, 32, LEGS_WAVE);
+        float *db = grad + (layer == 1 ? LEGS_SMOOTH_OFF_B2 : layer == 2 ? LEGS_SMOOTH_OFF_B3 : LEGS_SMOOTH_OFF_B4);
+        if (h == 0 && mrow && dbs != 0.0f) atomicAdd(db + m, dbs);
+    }
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        if (nb >= NB) continue;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int row = 32 * mb + legs_drow(r, h);
             const int col = 32 * nb + (lane & 31);
-            const float v = acc[r];
+            const float v = acc[nb][r];
             if (row >= M || col >= Kb || v == 0.0f) continue;
             if (layer == 0) {
                 if (col < 9) atomicAdd(grad + LEGS_SMOOTH_OFF_W1 + row * 3 + col % 3, v);
@@ -442,7 +455,7 @@ SmoothLayout smooth_layout(int64_t n)
     L.H1 = o; o += SH * plane;
     L.H2 = o; o += SH * plane;
     L.H3 = o; o += SH * plane;
-    L.D1 = o; o += 2 * SH * plane;
+    L.D1 = o; o += 2 * SH * plane;            // float32 rows: twice a bf16 row
     L.D2 = o; o += 2 * SH * plane;
     L.D3 = o; o += 2 * SH * plane;
     L.D4 = o; o += 2 * LEGS_SMOOTH_OUT * plane;
@@ -478,10 +491,10 @@ int32_t legs_launch_smooth(legs_ctx *ctx, const float *mean, const float *channe
     A.H1 = reinterpret_cast<__bf16 *>(ws + Lw.H1);
     A.H2 = reinterpret_cast<__bf16 *>(ws + Lw.H2);
     A.H3 = reinterpret_cast<__bf16 *>(ws + Lw.H3);
-    A.D1 = reinterpret_cast<__bf16 *>(ws + Lw.D1);
-    A.D2 = reinterpret_cast<__bf16 *>(ws + Lw.D2);
-    A.D3 = reinterpret_cast<__bf16 *>(ws + Lw.D3);
-    A.D4 = reinterpret_cast<__bf16 *>(ws + Lw.D4);
+    A.D1 = reinterpret_cast<float *>(ws + Lw.D1);
+    A.D2 = reinterpret_cast<float *>(ws + Lw.D2);
+    A.D3 = reinterpret_cast<float *>(ws + Lw.D3);
+    A.D4 = reinterpret_cast<float *>(ws + Lw.D4);
     int64_t blocks = (Lw.Gp + 32 * SNT * 4 - 1) / (32 * SNT * 4);
     if (blocks > ctx->num_cus) blocks = ctx->num_cus;
     hipLaunchKernelGGL(k_smooth_fwd_bwd, dim3((unsigned)blocks), dim3(256), 0, s, A);
