@@ -454,7 +454,7 @@ template <int TILE, int CP> struct BwdShape {
 // (mean offset and conic) are summed per lane as moments of (dx, dy) and
 // turned into gradients once per Gaussian (the map is linear).
 template <int TILE, int CP>
-__global__ void __launch_bounds__((BwdShape<TILE, CP>::NT))
+__global__ void __launch_bounds__((BwdShape<TILE, CP>::NT), 4)
 k_blend_bwd(BlendParams P, const float *__restrict__ Tf, const uint32_t *__restrict__ last,
             const float *__restrict__ d_out, float *__restrict__ grad2d, float *__restrict__ d_ch)
 {
