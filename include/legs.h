@@ -396,7 +396,7 @@ int32_t legs_semantic_loss_grad(legs_ctx *ctx, const float *feat, const float *r
 /* legs_semantic_loss_grad without a workspace argument, for callers that
  * cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc). It allocates nothing: its
- * workspace is a fixed array of 25,690,112 bytes inside the library's device
+ * workspace is a fixed array of 21,495,808 bytes inside the library's device
  * code, one per GPU, held from the first legs_create on that GPU until the
  * process ends. P <= LEGS_NOALLOC_MAX_PIXELS, else LEGS_ERR_ARG (nothing
  * launched); the loss and the decoder gradient accumulate, so a larger view

@@ -12,7 +12,7 @@
 #include "legs_decode_internal.h"
 
 // Workspace of legs_semantic_loss_grad_noalloc: LEGS_NOALLOC_MAX_PIXELS rows of
-// the decoder-training workspace at the largest K (25,690,112 bytes). Every GPU
+// the decoder-training workspace at the largest K (21,495,808 bytes). Every GPU
 // that loads the library holds its own copy until the process ends. In host
 // code `scratch` is only a stand-in for the symbol: the device address of a
 // GPU's copy comes from hipGetSymbolAddress with that GPU current, once per

@@ -42,8 +42,9 @@
 #define LEGS_SMOOTH_OFF_B4 (LEGS_SMOOTH_OFF_W4 + LEGS_SMOOTH_OUT * LEGS_SMOOTH_H)
 #define LEGS_SMOOTH_NPARAMS (LEGS_SMOOTH_OFF_B4 + LEGS_SMOOTH_OUT)
 
-// Training workspace per pixel (floats): X 8 | H1 64 | H2 64 | DZ1 64 | DZ2 64 | DZ3 K
-#define LEGS_MLP_WS_PER_PIXEL(K) (264 + (K))
+// Training workspace per pixel, in floats: X (16 bf16) 8 | H1, H2 (64 bf16) 32 each |
+// DZ1, DZ2 (float) 64 each | DZ3 (float) K
+#define LEGS_MLP_WS_PER_PIXEL(K) (200 + (K))
 
 typedef __attribute__((ext_vector_type(8))) __bf16 legs_bf16x8;
 typedef __attribute__((ext_vector_type(16))) float legs_f32x16;

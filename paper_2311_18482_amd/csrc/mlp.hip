@@ -1,26 +1,37 @@
 // Training of the MLP decoder (gfx950): Eq. 9 cross-entropy against code
-// index labels, gradients by the chain rule, and the fused Adam update of
-// Sec. 4 (Adam, betas (0.9, 0.999)) used for both the decoder and the
-// per-Gaussian parameters.
+// index labels (or the uncertainty-weighted loss of Eqs. 10-12), gradients by
+// the chain rule, and the fused Adam update of Sec. 4 (Adam, betas (0.9,
+// 0.999)) used for both the decoder and the per-Gaussian parameters.
 //
-// The forward pass is the inference tile routine (BF16 MFMA, FP32
-// accumulation), so training sees exactly the activations inference produces.
-// Backward runs in FP32 and passes straight through the bf16 roundings:
-//   k_mlp_fwd     logits, softmax, dz3 = (p - onehot) / B, loss; stores the
-//                 bf16 input and hidden activations (as floats) per pixel
-//   k_mlp_act     dh2 = W3^T dz3, dz2 = dh2 * [z2 > 0], dh1 = W2^T dz2,
-//                 dz1 = dh1 * [z1 > 0] (one thread per pixel, weights in LDS)
-//   k_mlp_wgrad   dW = dZ^T H and db = sum dZ for each layer: split-K over
-//                 pixel chunks, 4x4 register tiles per thread, one float
-//                 atomic per weight per chunk
-// Workspace per pixel (floats): X 8 | H1 64 | H2 64 | DZ1 64 | DZ2 64 | DZ3 K.
+// Every contraction runs on v_mfma_f32_32x32x16_bf16 with float32 accumulation:
+//   k_mlp_fb     per 32-pixel tile: the inference forward (so training sees
+//                exactly the activations inference produces), softmax, CE,
+//                dz3 = (p - onehot) w_p, then the backward through the layers
+//                (dh2 = W3^T dz3, dz2 = dh2 [h2 > 0], dh1 = W2^T dz2, dz1 =
+//                dh1 [h1 > 0], and the input gradient W1^T dz1) with the
+//                upstream gradient split into two bf16 parts (hi + lo, 16
+//                significant bits) and the W^T fragments in LDS next to the
+//                forward ones; straight through the bf16 roundings. Writes
+//                the layer inputs (bf16) and the dz (float32) unit-major
+//                ([unit][pixel]) into the workspace.
+//   k_mlp_wg     dW_l = sum_p dz_l h_(l-1)^T and db_l = sum_p dz_l: the pixels
+//                are the MFMA contraction, read straight from the unit-major
+//                planes (8 consecutive pixels of one unit = one fragment; dz
+//                split into bf16 hi + lo as it is loaded); split over pixel
+//                chunks (x) and layers (y), float atomics into the gradient.
+// Workspace, Bp = B rounded up to 64 pixels: X [16][Bp] bf16 (the decoder
+// input, then a row of ones), H1, H2 [64][Bp] bf16, DZ1, DZ2 [64][Bp] and
+// DZ3 [K][Bp] float32: 200 + K floats per pixel.
 #include "legs_internal.h"
 #include "legs_decode_internal.h"
 
 namespace {
 
-constexpr int WS_X = 0, WS_H1 = 8, WS_H2 = 72, WS_DZ1 = 136, WS_DZ2 = 200, WS_DZ3 = 264;
-static_assert(WS_DZ3 + 128 == LEGS_MLP_WS_PER_PIXEL(128), "workspace layout");
+typedef legs_f32x16 f32x16;
+typedef legs_bf16x8 bf16x8;
+
+constexpr int MH = LEGS_MLP_H;                     // 64 hidden units
+static_assert(LEGS_MLP_WS_PER_PIXEL(0) == 8 + 32 + 32 + 64 + 64, "workspace layout");
 
 // Per-pixel weighting of the cross-entropy. ru == NULL: the mean over the
 // batch (Eq. 9). Otherwise the uncertainty-weighted loss of Eqs. 10-12:
@@ -32,241 +43,317 @@ struct CeWeights {
     float lce, lu, inv_hw;
 };
 
+// Input gradient request: d_feat (NULL: none) receives dL/d(feature) at
+// d_feat[c * dcs + p * dps]; with NORM the decoder input was f / |f| and its
+// Jacobian (I - u u^T) / |f| (u = f / |f|) is applied, straight through the
+// bf16 rounding of the input.
+struct InputGrad {
+    float *d_feat;
+    int64_t dcs, dps;
+};
+
+struct MlpPlanes {
+    int64_t Bp;
+    __bf16 *X, *H1, *H2;
+    float *D1, *D2, *D3;
+};
+
+MlpPlanes mlp_planes(void *ws, int64_t B, int32_t K)
+{
+    MlpPlanes P;
+    P.Bp = (B + 63) / 64 * 64;
+    char *c = static_cast<char *>(ws);
+    P.X = reinterpret_cast<__bf16 *>(c);                  c += 16 * P.Bp * 2;
+    P.H1 = reinterpret_cast<__bf16 *>(c);                 c += MH * P.Bp * 2;
+    P.H2 = reinterpret_cast<__bf16 *>(c);                 c += MH * P.Bp * 2;
+    P.D1 = reinterpret_cast<float *>(c);                  c += MH * P.Bp * 4;
+    P.D2 = reinterpret_cast<float *>(c);                  c += MH * P.Bp * 4;
+    P.D3 = reinterpret_cast<float *>(c);
+    return P;
+}
+
+// W^T fragments of the backward: (block, k-step, lane, e) = row 32 block +
+// lane % 32 of W^T (a unit of the layer below), column legs_khid(k-step,
+// lane / 32, e) (a unit of the layer above).
+template <int KB>
+struct MlpBwdLds {
+    bf16x8 t3[2 * 2 * KB * 64];     // W3^T: 64 rows x K
+    bf16x8 t2[2 * 4 * 64];          // W2^T: 64 x 64
+    bf16x8 t1[4 * 64];              // W1^T: 8 rows (block padded to 32) x 64
+};
+
+template <int KB>
+__device__ __forceinline__ void mlp_stage_bwd(const float *__restrict__ params, MlpBwdLds<KB> &T)
+{
+    const float *W1 = params + LEGS_MLP_OFF_W1, *W2 = params + LEGS_MLP_OFF_W2, *W3 = params + LEGS_MLP_OFF_W3;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    constexpr int S3 = 2 * KB;
+    for (int i = tid; i < 2 * S3 * 64 * 8; i += nt) {
+        const int e = i & 7, l = (i >> 3) & 63, ks = (i >> 9) % S3, mb = (i >> 9) / S3;
+        reinterpret_cast<__bf16 *>(T.t3)[i] = (__bf16)W3[legs_khid(ks, l >> 5, e) * MH + 32 * mb + (l & 31)];
+    }
+    for (int i = tid; i < 2 * 4 * 64 * 8; i += nt) {
+        const int e = i & 7, l = (i >> 3) & 63, ks = (i >> 9) & 3, mb = i >> 11;
+        reinterpret_cast<__bf16 *>(T.t2)[i] = (__bf16)W2[legs_khid(ks, l >> 5, e) * MH + 32 * mb + (l & 31)];
+    }
+    for (int i = tid; i < 4 * 64 * 8; i += nt) {
+        const int e = i & 7, l = (i >> 3) & 63, ks = i >> 9;
+        const int row = l & 31;
+        reinterpret_cast<__bf16 *>(T.t1)[i] =
+            row < LEGS_MLP_IN ? (__bf16)W1[legs_khid(ks, l >> 5, e) * LEGS_MLP_IN + row] : (__bf16)0.0f;
+    }
+}
+
+__device__ __forceinline__ void split8(const f32x16 &z, int first, bf16x8 &hi, bf16x8 &lo)
+{
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const __bf16 a = (__bf16)z[first + e];
+        hi[e] = a;
+        lo[e] = (__bf16)(z[first + e] - (float)a);
+    }
+}
+
 template <int KB, bool NORM>
 __global__ void __launch_bounds__(256)
-k_mlp_fwd(const float *__restrict__ feat, int64_t B, int64_t cs, int64_t ps,
-          const int32_t *__restrict__ labels, const float *__restrict__ params,
-          float *__restrict__ ws, float *__restrict__ loss, CeWeights cw)
+k_mlp_fb(const float *__restrict__ feat, int64_t B, int64_t cs, int64_t ps, const int32_t *__restrict__ labels,
+         const float *__restrict__ params, MlpPlanes W, float *__restrict__ loss, CeWeights cw, InputGrad ig)
 {
     constexpr int K = 32 * KB;
-    constexpr int WS = WS_DZ3 + K;
     __shared__ MlpLds L;
+    __shared__ MlpBwdLds<KB> T;
     mlp_stage_weights<KB>(params, L);
+    mlp_stage_bwd<KB>(params, T);
     __syncthreads();
     const int lane = __lane_id(), wave = threadIdx.x / LEGS_WAVE, h = lane >> 5;
-    const int64_t tiles = (B + 31) / 32;
+    const int64_t tiles = W.Bp / 32;
     const int64_t stride = (int64_t)gridDim.x * 4;
     const float invB = 1.0f / (float)B;
     float lsum = 0.0f;
-    MlpTile<KB> T;
+    MlpTile<KB> F;
     for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < tiles; tile += stride) {
+        int off = 0;
+        asm volatile("" : "+s"(off));   // fragments are re-read from LDS every tile
+        const int ln = lane + off;
         const int64_t p = tile * 32 + (lane & 31);
         const bool valid = p < B;
-        mlp_tile_forward<KB, NORM>(L, feat, p, valid, cs, ps, T);
+        mlp_tile_forward<KB, NORM>(L, feat, p, valid, cs, ps, F, off);
+        // softmax over the pixel's K logits (this lane and its partner)
         float mx = -INFINITY;
 #pragma unroll
         for (int b = 0; b < KB; ++b)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) mx = fmaxf(mx, T.z3[b][r]);
+            for (int r = 0; r < 16; ++r) mx = fmaxf(mx, F.z3[b][r]);
         mx = fmaxf(mx, __shfl_xor(mx, 32, LEGS_WAVE));
         float sum = 0.0f;
 #pragma unroll
         for (int b = 0; b < KB; ++b)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) sum += __expf(T.z3[b][r] - mx);
+            for (int r = 0; r < 16; ++r) sum += __expf(F.z3[b][r] - mx);
         sum += __shfl_xor(sum, 32, LEGS_WAVE);
-        if (!valid) continue;
-        const int y = labels[p];
-        float *w = ws + p * WS;
         const float inv = 1.0f / sum;
-        float wpx = invB;
-        if (cw.ru) {
+        const int y = valid ? labels[p] : -1;
+        float wpx = valid ? invB : 0.0f;
+        if (cw.ru && valid) {
             const float ru = cw.ru[p];
             wpx = cw.lce * (1.0f - ru) * cw.inv_hw;
             if (h == 0) lsum += cw.lu * ru * cw.inv_hw;
         }
+        // dz3 in place of the logits: (p - onehot) w_p; the loss and dL/dR_u
 #pragma unroll
         for (int b = 0; b < KB; ++b)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                float4 d;
-                float *dv = &d.x;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int k = 32 * b + 8 * j + 4 * h + i;
-                    const float pr = __expf(T.z3[b][4 * j + i] - mx) * inv;
-                    dv[i] = (pr - (k == y ? 1.0f : 0.0f)) * wpx;
-                    if (k == y) {
-                        const float ce = mx + __logf(sum) - T.z3[b][4 * j + i];
-                        lsum += ce * wpx;
-                        if (cw.ru) cw.d_ru[p] = (cw.lu - cw.lce * ce) * cw.inv_hw;
-                    }
+            for (int r = 0; r < 16; ++r) {
+                const int k = 32 * b + legs_drow(r, h);
+                const float pr = __expf(F.z3[b][r] - mx) * inv;
+                if (k == y) {
+                    const float ce = mx + __logf(sum) - F.z3[b][r];
+                    lsum += ce * wpx;
+                    if (cw.ru) cw.d_ru[p] = (cw.lu - cw.lce * ce) * cw.inv_hw;
                 }
-                *reinterpret_cast<float4 *>(w + WS_DZ3 + 32 * b + 8 * j + 4 * h) = d;
+                F.z3[b][r] = (pr - (k == y ? 1.0f : 0.0f)) * wpx;
             }
-        // bf16 activations (as floats) in feature order
+        // layer inputs to the workspace (unit-major): X rows 0..7 the bf16
+        // input, row 8 ones (the bias column of layer 1), rows 9..15 zero
+        if (h == 0) {
+            const __bf16 z0 = (__bf16)0.0f;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) W.X[(int64_t)e * W.Bp + p] = valid ? F.x[e] : z0;
+            W.X[8 * W.Bp + p] = valid ? (__bf16)1.0f : z0;
+#pragma unroll
+            for (int e = 9; e < 16; ++e) W.X[(int64_t)e * W.Bp + p] = z0;
+        }
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int f0 = legs_khid(ks, h, 4 * q);
-                float4 a, c;
-                a.x = (float)T.h1[ks][4 * q + 0]; a.y = (float)T.h1[ks][4 * q + 1];
-                a.z = (float)T.h1[ks][4 * q + 2]; a.w = (float)T.h1[ks][4 * q + 3];
-                c.x = (float)T.h2[ks][4 * q + 0]; c.y = (float)T.h2[ks][4 * q + 1];
-                c.z = (float)T.h2[ks][4 * q + 2]; c.w = (float)T.h2[ks][4 * q + 3];
-                *reinterpret_cast<float4 *>(w + WS_H1 + f0) = a;
-                *reinterpret_cast<float4 *>(w + WS_H2 + f0) = c;
+            for (int e = 0; e < 8; ++e) {
+                const int64_t o = (int64_t)legs_khid(ks, h, e) * W.Bp + p;
+                W.H1[o] = valid ? F.h1[ks][e] : (__bf16)0.0f;
+                W.H2[o] = valid ? F.h2[ks][e] : (__bf16)0.0f;
             }
-        if (h == 0) {
-            float4 a, c;
-            a.x = (float)T.x[0]; a.y = (float)T.x[1]; a.z = (float)T.x[2]; a.w = (float)T.x[3];
-            c.x = (float)T.x[4]; c.y = (float)T.x[5]; c.z = (float)T.x[6]; c.w = (float)T.x[7];
-            *reinterpret_cast<float4 *>(w + WS_X) = a;
-            *reinterpret_cast<float4 *>(w + WS_X + 4) = c;
+#pragma unroll
+        for (int b = 0; b < KB; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) W.D3[(int64_t)(32 * b + legs_drow(r, h)) * W.Bp + p] = F.z3[b][r];
+        // dh2 = W3^T dz3 (two blocks of 32 hidden units), gated by h2 > 0
+        bf16x8 bh[2 * KB], bl[2 * KB];
+#pragma unroll
+        for (int b = 0; b < KB; ++b) {
+            split8(F.z3[b], 0, bh[2 * b], bl[2 * b]);
+            split8(F.z3[b], 8, bh[2 * b + 1], bl[2 * b + 1]);
+        }
+        f32x16 dz[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            f32x16 acc = {};
+#pragma unroll
+            for (int ks = 0; ks < 2 * KB; ++ks) {
+                const bf16x8 a = T.t3[(mb * 2 * KB + ks) * 64 + ln];
+                acc = legs_mfma(a, bl[ks], legs_mfma(a, bh[ks], acc));
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (!((float)F.h2[2 * mb + (r >> 3)][r & 7] > 0.0f)) acc[r] = 0.0f;
+            dz[mb] = acc;
+        }
+        // dz2 stored; dh1 = W2^T dz2 gated by h1 > 0
+        bf16x8 ch[4], cl[4];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) W.D2[(int64_t)(32 * mb + legs_drow(r, h)) * W.Bp + p] = dz[mb][r];
+            split8(dz[mb], 0, ch[2 * mb], cl[2 * mb]);
+            split8(dz[mb], 8, ch[2 * mb + 1], cl[2 * mb + 1]);
+        }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            f32x16 acc = {};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const bf16x8 a = T.t2[(mb * 4 + ks) * 64 + ln];
+                acc = legs_mfma(a, cl[ks], legs_mfma(a, ch[ks], acc));
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (!((float)F.h1[2 * mb + (r >> 3)][r & 7] > 0.0f)) acc[r] = 0.0f;
+            dz[mb] = acc;
+        }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) W.D1[(int64_t)(32 * mb + legs_drow(r, h)) * W.Bp + p] = dz[mb][r];
+        }
+        if (ig.d_feat) {
+            // dx = W1^T dz1: inputs 4 h + r in registers r = 0..3
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) {
+                split8(dz[mb], 0, ch[2 * mb], cl[2 * mb]);
+                split8(dz[mb], 8, ch[2 * mb + 1], cl[2 * mb + 1]);
+            }
+            f32x16 acc = {};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const bf16x8 a = T.t1[ks * 64 + ln];
+                acc = legs_mfma(a, cl[ks], legs_mfma(a, ch[ks], acc));
+            }
+            float dx[4] = {acc[0], acc[1], acc[2], acc[3]};
+            if constexpr (NORM) {
+                float f[4], ss = 0.0f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    f[r] = valid ? legs_ldfeat(feat, p, 4 * h + r, cs, ps) : 0.0f;
+                    ss = fmaf(f[r], f[r], ss);
+                }
+                ss += __shfl_xor(ss, 32, LEGS_WAVE);
+                const float nrm = sqrtf(ss);
+                const float iv = nrm > 0.0f ? 1.0f / nrm : 0.0f;
+                float ud = 0.0f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ud += f[r] * iv * dx[r];
+                ud += __shfl_xor(ud, 32, LEGS_WAVE);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) dx[r] = (dx[r] - ud * (f[r] * iv)) * iv;
+            }
+            if (valid) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ig.d_feat[(int64_t)(4 * h + r) * ig.dcs + p * ig.dps] = dx[r];
+            }
         }
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, LEGS_WAVE);
+    for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, LEGS_WAVE);
     if (lane == 0 && lsum != 0.0f) atomicAdd(loss, lsum);
 }
 
-// dz2 and dz1 per pixel (straight-through the bf16 rounding; ReLU gate from
-// the stored activation, which is positive exactly when z > 0).
-// Input gradient request: d_feat (NULL: none) receives dL/d(feature) at
-// d_feat[c * dcs + p * dps]; with NORM the decoder input was f / |f| and its
-// Jacobian (I - u u^T) / |f| (u = f / |f|, from the feature re-read here) is
-// applied, straight through the bf16 rounding of the input.
-struct InputGrad {
-    const float *feat;
-    int64_t cs, ps;
-    float *d_feat;
-    int64_t dcs, dps;
-};
+// dW[m][k] += sum_p (dz_hi + dz_lo)[m][p] B[k][p] over the pixels of this
+// workgroup's chunk, db[m] += sum_p dz[m][p]. Layer (blockIdx.y): 0: DZ1 x X
+// (rows 0..7 the input, row 8 ones -> b1), 1: DZ2 x H1, 2: DZ3 x H2. Wave w
+// owns the 32 rows of block w of dz against every block of B.
+constexpr int MLP_WG_CHUNK = 4096;
 
-template <int KB, bool NORM>
 __global__ void __launch_bounds__(256)
-k_mlp_act(int64_t B, const float *__restrict__ params, float *__restrict__ ws, InputGrad ig)
+k_mlp_wg(MlpPlanes W, int K, float *__restrict__ grad)
 {
-    constexpr int K = 32 * KB;
-    constexpr int WS = WS_DZ3 + K;
-    constexpr int H = LEGS_MLP_H;
-    __shared__ float s_W3[K * H];
-    __shared__ float s_W2[H * H];
-    __shared__ float s_W1[H * LEGS_MLP_IN];
-    const float *W1 = params + LEGS_MLP_OFF_W1, *W2 = params + LEGS_MLP_OFF_W2, *W3 = params + LEGS_MLP_OFF_W3;
-    for (int i = threadIdx.x; i < K * H; i += blockDim.x) s_W3[i] = (float)(__bf16)W3[i];
-    for (int i = threadIdx.x; i < H * H; i += blockDim.x) s_W2[i] = (float)(__bf16)W2[i];
-    for (int i = threadIdx.x; i < H * LEGS_MLP_IN; i += blockDim.x) s_W1[i] = (float)(__bf16)W1[i];
-    __syncthreads();
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < B;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        float *w = ws + p * WS;
-        float d[H];
+    const int layer = blockIdx.y;
+    const int lane = __lane_id(), wave = threadIdx.x / LEGS_WAVE, h = lane >> 5;
+    const float *Dp = layer == 0 ? W.D1 : layer == 1 ? W.D2 : W.D3;
+    const __bf16 *Bp = layer == 0 ? W.X : layer == 1 ? W.H1 : W.H2;
+    const int M = layer == 2 ? K : MH;
+    const int Kb = layer == 0 ? 16 : MH;
+    const int MB = M / 32, NB = (Kb + 31) / 32;
+    if (wave >= MB) return;
+    const int mb = wave, m = 32 * mb + (lane & 31);
+    const int64_t g0 = (int64_t)blockIdx.x * MLP_WG_CHUNK;
+    const int64_t g1 = min(g0 + (int64_t)MLP_WG_CHUNK, W.Bp);
+    const float *Drow = Dp + (int64_t)m * W.Bp + 8 * h;
+    const __bf16 *Bq0 = Bp + (int64_t)(lane & 31) * W.Bp + 8 * h;
+    const __bf16 *Bq1 = Bp + (int64_t)(32 + (lane & 31)) * W.Bp + 8 * h;
+    const bool k0 = (lane & 31) < Kb, k1 = NB > 1;
+    f32x16 acc[2] = {};
+    float dbs = 0.0f;
+#pragma unroll 2
+    for (int64_t g = g0; g < g1; g += 16) {
+        const float4 v0 = *reinterpret_cast<const float4 *>(Drow + g);
+        const float4 v1 = *reinterpret_cast<const float4 *>(Drow + g + 4);
+        const float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        bf16x8 ah, al;
 #pragma unroll
-        for (int j = 0; j < H; ++j) d[j] = 0.0f;
-        for (int k4 = 0; k4 < K; k4 += 4) {
-            const float4 dz = *reinterpret_cast<const float4 *>(w + WS_DZ3 + k4);
-            const float *dzv = &dz.x;
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < H; ++j) d[j] += dzv[i] * s_W3[(k4 + i) * H + j];
+        for (int e = 0; e < 8; ++e) {
+            ah[e] = (__bf16)v[e];
+            al[e] = (__bf16)(v[e] - (float)ah[e]);
+            dbs += v[e];
         }
-#pragma unroll
-        for (int j4 = 0; j4 < H; j4 += 4) {
-            const float4 hv = *reinterpret_cast<const float4 *>(w + WS_H2 + j4);
-            d[j4 + 0] = hv.x > 0.0f ? d[j4 + 0] : 0.0f;
-            d[j4 + 1] = hv.y > 0.0f ? d[j4 + 1] : 0.0f;
-            d[j4 + 2] = hv.z > 0.0f ? d[j4 + 2] : 0.0f;
-            d[j4 + 3] = hv.w > 0.0f ? d[j4 + 3] : 0.0f;
-            *reinterpret_cast<float4 *>(w + WS_DZ2 + j4) =
-                make_float4(d[j4 + 0], d[j4 + 1], d[j4 + 2], d[j4 + 3]);
+        const bf16x8 b0 = k0 ? *reinterpret_cast<const bf16x8 *>(Bq0 + g) : (bf16x8){};
+        acc[0] = legs_mfma(al, b0, legs_mfma(ah, b0, acc[0]));
+        if (k1) {
+            const bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(Bq1 + g);
+            acc[1] = legs_mfma(al, b1, legs_mfma(ah, b1, acc[1]));
         }
-        float e[H];
+    }
+    const int KB = K / 32;
+    if (layer != 0) {                                   // row sums: the bias gradient
+        dbs += __shfl_xor(dbs, 32, LEGS_WAVE);
+        float *db = grad + (layer == 1 ? LEGS_MLP_OFF_B2 : LEGS_MLP_OFF_B3(KB));
+        if (h == 0 && dbs != 0.0f) atomicAdd(db + m, dbs);
+    }
 #pragma unroll
-        for (int i = 0; i < H; ++i) e[i] = 0.0f;
+    for (int nb = 0; nb < 2; ++nb) {
+        if (nb >= NB) continue;
 #pragma unroll
-        for (int j = 0; j < H; ++j)
-#pragma unroll
-            for (int i = 0; i < H; ++i) e[i] += d[j] * s_W2[j * H + i];
-#pragma unroll
-        for (int i4 = 0; i4 < H; i4 += 4) {
-            const float4 hv = *reinterpret_cast<const float4 *>(w + WS_H1 + i4);
-            e[i4 + 0] = hv.x > 0.0f ? e[i4 + 0] : 0.0f;
-            e[i4 + 1] = hv.y > 0.0f ? e[i4 + 1] : 0.0f;
-            e[i4 + 2] = hv.z > 0.0f ? e[i4 + 2] : 0.0f;
-            e[i4 + 3] = hv.w > 0.0f ? e[i4 + 3] : 0.0f;
-            *reinterpret_cast<float4 *>(w + WS_DZ1 + i4) = make_float4(e[i4], e[i4 + 1], e[i4 + 2], e[i4 + 3]);
-        }
-        if (ig.d_feat) {
-            float dx[LEGS_MLP_IN];
-#pragma unroll
-            for (int c = 0; c < LEGS_MLP_IN; ++c) dx[c] = 0.0f;
-#pragma unroll
-            for (int i = 0; i < H; ++i)
-#pragma unroll
-                for (int c = 0; c < LEGS_MLP_IN; ++c) dx[c] += e[i] * s_W1[i * LEGS_MLP_IN + c];
-            if constexpr (NORM) {
-                float f[LEGS_MLP_IN], ss = 0.0f;
-#pragma unroll
-                for (int c = 0; c < LEGS_MLP_IN; ++c) {
-                    f[c] = legs_ldfeat(ig.feat, p, c, ig.cs, ig.ps);
-                    ss = fmaf(f[c], f[c], ss);
-                }
-                const float nrm = sqrtf(ss);
-                const float inv = nrm > 0.0f ? 1.0f / nrm : 0.0f;
-                float ud = 0.0f;
-#pragma unroll
-                for (int c = 0; c < LEGS_MLP_IN; ++c) ud += f[c] * inv * dx[c];
-#pragma unroll
-                for (int c = 0; c < LEGS_MLP_IN; ++c) dx[c] = (dx[c] - ud * (f[c] * inv)) * inv;
+        for (int r = 0; r < 16; ++r) {
+            const int row = 32 * mb + legs_drow(r, h);
+            const int col = 32 * nb + (lane & 31);
+            const float x = acc[nb][r];
+            if (col >= Kb || x == 0.0f) continue;
+            if (layer == 0) {
+                if (col < LEGS_MLP_IN) atomicAdd(grad + LEGS_MLP_OFF_W1 + row * LEGS_MLP_IN + col, x);
+                else if (col == LEGS_MLP_IN) atomicAdd(grad + LEGS_MLP_OFF_B1 + row, x);
+            } else {
+                const int o = layer == 1 ? LEGS_MLP_OFF_W2 : LEGS_MLP_OFF_W3;
+                atomicAdd(grad + o + row * MH + col, x);
             }
-#pragma unroll
-            for (int c = 0; c < LEGS_MLP_IN; ++c) ig.d_feat[(int64_t)c * ig.dcs + p * ig.dps] = dx[c];
         }
     }
-}
-
-// out[m][n] += sum_p A[p][m] * Bm[p][n] for m < Ma, n < Nb, plus
-// bias[m] += sum_p A[p][m] (a virtual column of ones). Grid: x = pixel chunk,
-// y = 64 x 64 output tile (the bias tile is the extra column block).
-constexpr int WG_CHUNK = 512;
-constexpr int WG_SUB = 32;
-
-__global__ void __launch_bounds__(256)
-k_mlp_wgrad(int64_t B, const float *__restrict__ ws, int WS, int offA, int Ma, int offB, int Nb,
-            float *__restrict__ out, float *__restrict__ bias)
-{
-    __shared__ float sA[WG_SUB][64];
-    __shared__ float sB[WG_SUB][65];
-    const int tiles_n = (Nb + 1 + 63) / 64;
-    const int tm = blockIdx.y / tiles_n, tn = blockIdx.y % tiles_n;
-    const int m0 = tm * 64, n0 = tn * 64;
-    const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
-    float acc[4][4] = {};
-    const int64_t p0 = (int64_t)blockIdx.x * WG_CHUNK;
-    const int64_t p1 = p0 + WG_CHUNK < B ? p0 + WG_CHUNK : B;
-    for (int64_t ps = p0; ps < p1; ps += WG_SUB) {
-        for (int i = tid; i < WG_SUB * 64; i += 256) {
-            const int q = i / 64, c = i % 64;
-            const int64_t p = ps + q;
-            const int m = m0 + c, n = n0 + c;
-            sA[q][c] = (p < p1 && m < Ma) ? ws[p * WS + offA + m] : 0.0f;
-            sB[q][c] = (p < p1) ? (n < Nb ? ws[p * WS + offB + n] : (n == Nb ? 1.0f : 0.0f)) : 0.0f;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int q = 0; q < WG_SUB; ++q) {
-            float a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) { a[i] = sA[q][ty * 4 + i]; b[i] = sB[q][tx * 4 + i]; }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int m = m0 + ty * 4 + i, n = n0 + tx * 4 + j;
-            if (m >= Ma || acc[i][j] == 0.0f) continue;
-            if (n < Nb) atomicAdd(out + (int64_t)m * Nb + n, acc[i][j]);
-            else if (n == Nb) atomicAdd(bias + m, acc[i][j]);
-        }
 }
 
 __global__ void __launch_bounds__(256)
@@ -278,12 +365,15 @@ k_zero_f32(float *__restrict__ p, int64_t n)
 
 } // namespace
 
-int64_t legs_mlp_workspace_floats(int64_t B, int32_t K) { return B * (WS_DZ3 + (int64_t)K); }
+int64_t legs_mlp_workspace_floats(int64_t B, int32_t K)
+{
+    return (B + 63) / 64 * 64 * (int64_t)LEGS_MLP_WS_PER_PIXEL(K);
+}
 
 namespace {
 
-// Forward with dz3, hidden-layer backward (and the input gradient), weight
-// gradients (accumulated into grad with float atomics).
+// Forward and backward through the layers, then the weight gradients
+// (accumulated into grad with float atomics).
 int32_t mlp_train_kernels(legs_ctx *ctx, const float *feat, int64_t B, int64_t cs, int64_t ps,
                           const int32_t *labels, int32_t K, int32_t mlp_flags, const float *params,
                           float *workspace, float *grad, float *loss, const CeWeights &cw,
@@ -291,19 +381,16 @@ int32_t mlp_train_kernels(legs_ctx *ctx, const float *feat, int64_t B, int64_t c
 {
     const int KB = K / 32;
     if (B == 0) return LEGS_OK;
-    int64_t g = (B + 127) / 128;
-    const int64_t cap = (int64_t)ctx->num_cus * 8;
+    const MlpPlanes W = mlp_planes(workspace, B, K);
+    int64_t g = (W.Bp / 32 + 3) / 4;
+    const int64_t cap = (int64_t)ctx->num_cus * 2;
     if (g > cap) g = cap;
-    const int64_t ga = ((B + 255) / 256) < cap ? (B + 255) / 256 : cap;
     const bool norm = (mlp_flags & LEGS_MLP_NORMALIZE_INPUT) != 0;
 #define LEGS_MLP_TRAIN(KBV)                                                                                         \
-    if (norm) {                                                                                                     \
-        hipLaunchKernelGGL((k_mlp_fwd<KBV, true>), dim3((unsigned)g), dim3(256), 0, s, feat, B, cs, ps, labels, params, workspace, loss, cw); \
-        hipLaunchKernelGGL((k_mlp_act<KBV, true>), dim3((unsigned)ga), dim3(256), 0, s, B, params, workspace, ig); \
-    } else {                                                                                                        \
-        hipLaunchKernelGGL((k_mlp_fwd<KBV, false>), dim3((unsigned)g), dim3(256), 0, s, feat, B, cs, ps, labels, params, workspace, loss, cw); \
-        hipLaunchKernelGGL((k_mlp_act<KBV, false>), dim3((unsigned)ga), dim3(256), 0, s, B, params, workspace, ig); \
-    }
+    if (norm) hipLaunchKernelGGL((k_mlp_fb<KBV, true>), dim3((unsigned)g), dim3(256), 0, s, feat, B, cs, ps, labels, \
+                                 params, W, loss, cw, ig);                                                           \
+    else hipLaunchKernelGGL((k_mlp_fb<KBV, false>), dim3((unsigned)g), dim3(256), 0, s, feat, B, cs, ps, labels,    \
+                            params, W, loss, cw, ig);
     switch (KB) {
     case 1: LEGS_MLP_TRAIN(1) break;
     case 2: LEGS_MLP_TRAIN(2) break;
@@ -312,18 +399,8 @@ int32_t mlp_train_kernels(legs_ctx *ctx, const float *feat, int64_t B, int64_t c
     }
 #undef LEGS_MLP_TRAIN
     LEGS_CHECK_LAUNCH(ctx);
-    const int WS = WS_DZ3 + K;
-    const unsigned chunks = (unsigned)((B + WG_CHUNK - 1) / WG_CHUNK);
-    const int H = LEGS_MLP_H;
-    // layer 3: dW3 [K][64] from DZ3 x H2, db3
-    hipLaunchKernelGGL(k_mlp_wgrad, dim3(chunks, (unsigned)(((K + 63) / 64) * ((H + 1 + 63) / 64))), dim3(256), 0, s,
-                       B, workspace, WS, WS_DZ3, K, WS_H2, H, grad + LEGS_MLP_OFF_W3, grad + LEGS_MLP_OFF_B3(KB));
-    // layer 2: dW2 [64][64] from DZ2 x H1, db2
-    hipLaunchKernelGGL(k_mlp_wgrad, dim3(chunks, (unsigned)((H + 1 + 63) / 64)), dim3(256), 0, s,
-                       B, workspace, WS, WS_DZ2, H, WS_H1, H, grad + LEGS_MLP_OFF_W2, grad + LEGS_MLP_OFF_B2);
-    // layer 1: dW1 [64][8] from DZ1 x X, db1
-    hipLaunchKernelGGL(k_mlp_wgrad, dim3(chunks, 1), dim3(256), 0, s,
-                       B, workspace, WS, WS_DZ1, H, WS_X, LEGS_MLP_IN, grad + LEGS_MLP_OFF_W1, grad + LEGS_MLP_OFF_B1);
+    const dim3 gw((unsigned)((W.Bp + MLP_WG_CHUNK - 1) / MLP_WG_CHUNK), 3);
+    hipLaunchKernelGGL(k_mlp_wg, gw, dim3(256), 0, s, W, K, grad);
     LEGS_CHECK_LAUNCH(ctx);
     return LEGS_OK;
 }
@@ -339,7 +416,7 @@ int32_t legs_launch_mlp_grad(legs_ctx *ctx, const float *feat, int64_t B, int64_
     hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, s, loss, (int64_t)1);
     LEGS_CHECK_LAUNCH(ctx);
     const CeWeights cw = {nullptr, nullptr, 1.0f, 0.0f, 0.0f};
-    const InputGrad ig = {nullptr, 0, 0, nullptr, 0, 0};
+    const InputGrad ig = {nullptr, 0, 0};
     return mlp_train_kernels(ctx, feat, B, cs, ps, labels, K, mlp_flags, params, workspace, grad, loss, cw, ig, s);
 }
 
@@ -351,7 +428,7 @@ int32_t legs_launch_semantic_loss_grad(legs_ctx *ctx, const float *feat, const f
                                        float *loss, hipStream_t s)
 {
     const CeWeights cw = {ru, d_ru, lambda_ce, lambda_u, inv_hw};
-    const InputGrad ig = {feat, cs, ps, d_feat, dcs, dps};
+    const InputGrad ig = {d_feat, dcs, dps};
     return mlp_train_kernels(ctx, feat, P, cs, ps, labels, K, mlp_flags, params, workspace, grad, loss, cw, ig, s);
 }
 
