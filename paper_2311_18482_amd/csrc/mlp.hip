@@ -289,10 +289,8 @@ k_mlp_fb(const float *__restrict__ feat, int64_t B, int64_t cs, int64_t ps, cons
 // workgroup's chunk, db[m] += sum_p dz[m][p]. Layer (blockIdx.y): 0: DZ1 x X
 // (rows 0..7 the input, row 8 ones -> b1), 1: DZ2 x H1, 2: DZ3 x H2. Wave w
 // owns the 32 rows of block w of dz against every block of B.
-constexpr int MLP_WG_CHUNK = 4096;
-
 __global__ void __launch_bounds__(256)
-k_mlp_wg(MlpPlanes W, int K, float *__restrict__ grad)
+k_mlp_wg(MlpPlanes W, int K, int64_t chunk, float *__restrict__ grad)
 {
     const int layer = blockIdx.y;
     const int lane = __lane_id(), wave = threadIdx.x / LEGS_WAVE, h = lane >> 5;
@@ -303,8 +301,8 @@ k_mlp_wg(MlpPlanes W, int K, float *__restrict__ grad)
     const int MB = M / 32, NB = (Kb + 31) / 32;
     if (wave >= MB) return;
     const int mb = wave, m = 32 * mb + (lane & 31);
-    const int64_t g0 = (int64_t)blockIdx.x * MLP_WG_CHUNK;
-    const int64_t g1 = min(g0 + (int64_t)MLP_WG_CHUNK, W.Bp);
+    const int64_t g0 = (int64_t)blockIdx.x * chunk;
+    const int64_t g1 = min(g0 + chunk, W.Bp);
     const float *Drow = Dp + (int64_t)m * W.Bp + 8 * h;
     const __bf16 *Bq0 = Bp + (int64_t)(lane & 31) * W.Bp + 8 * h;
     const __bf16 *Bq1 = Bp + (int64_t)(32 + (lane & 31)) * W.Bp + 8 * h;
@@ -399,8 +397,11 @@ int32_t mlp_train_kernels(legs_ctx *ctx, const float *feat, int64_t B, int64_t c
     }
 #undef LEGS_MLP_TRAIN
     LEGS_CHECK_LAUNCH(ctx);
-    const dim3 gw((unsigned)((W.Bp + MLP_WG_CHUNK - 1) / MLP_WG_CHUNK), 3);
-    hipLaunchKernelGGL(k_mlp_wg, gw, dim3(256), 0, s, W, K, grad);
+    // pixel chunks of 256 to 4096 (a multiple of 64), about 256 per layer
+    int64_t chunk = (W.Bp / 256 + 63) / 64 * 64;
+    chunk = chunk < 256 ? 256 : (chunk > 4096 ? 4096 : chunk);
+    const dim3 gw((unsigned)((W.Bp + chunk - 1) / chunk), 3);
+    hipLaunchKernelGGL(k_mlp_wg, gw, dim3(256), 0, s, W, K, chunk, grad);
     LEGS_CHECK_LAUNCH(ctx);
     return LEGS_OK;
 }
