@@ -92,13 +92,16 @@ def mlp_forward(feat, weights, biases, amb_tol=2e-6, normalize=True):
     return dict(x=x, hs=hs, zs=zs, logits=zs[-1], ambiguous=amb)
 
 
-def mlp_branches(feat_row, weights, biases, normalize=True, amb_tol=2e-6, max_states=64):
+def mlp_branches(feat_row, weights, biases, normalize=True, amb_tol=2e-6, max_states=64,
+                 return_hidden=False):
     """Every logit vector a float32 evaluation of mlp_forward can produce for
     one pixel: wherever a value that is rounded to bf16 (the input, each
     hidden activation) lies within a relative amb_tol of a rounding midpoint,
     both neighbours are followed. Returns (list of logits, complete) with
     complete False when more than max_states branches would arise (the list
-    then holds the branches of the first ambiguous values only)."""
+    then holds the branches of the first ambiguous values only). With
+    return_hidden, also the rounded layer inputs [x, h1, ...] of each branch
+    (a third list, same order)."""
     f = np.asarray(feat_row, np.float32).astype(np.float64)[None, :]
     if normalize:
         nrm = np.sqrt(np.sum(f * f))
@@ -127,23 +130,26 @@ def mlp_branches(feat_row, weights, biases, normalize=True, amb_tol=2e-6, max_st
             outs += alt
         return outs
 
-    states = roundings(u)
+    states = [(h, [h[0]]) for h in roundings(u)]
     L = len(weights)
     Ws = [bf16(np.asarray(w, np.float32).astype(np.float64)) for w in weights]
     bs = [np.asarray(b, np.float32).astype(np.float64) for b in biases]
     for l in range(L):
         nxt = []
-        for h in states:
+        for h, trail in states:
             z = h @ Ws[l].T + bs[l]
             if l < L - 1:
-                nxt += roundings(np.maximum(z, 0.0))
+                nxt += [(q, trail + [q[0]]) for q in roundings(np.maximum(z, 0.0))]
             else:
-                nxt.append(z[0])
+                nxt.append((z[0], trail))
         if len(nxt) > max_states:
             complete = False
             nxt = nxt[:max_states]
         states = nxt
-    return states, complete
+    logits = [z for z, _ in states]
+    if return_hidden:
+        return logits, complete, [trail for _, trail in states]
+    return logits, complete
 
 
 def softmax(z):
@@ -152,10 +158,27 @@ def softmax(z):
     return e / e.sum(axis=1, keepdims=True)
 
 
-def mlp_grads(feat, labels, weights, biases, normalize=True):
+def _follow(fw, hidden, weights, biases):
+    """Replace the rounded layer inputs of a forward pass by given ones
+    (another evaluation's rounding choices: hidden = [x, h1, h2, ...]) and
+    recompute every pre-activation from them in float64."""
+    hs = [np.asarray(h, np.float64) for h in hidden]
+    zs = []
+    for l in range(len(weights)):
+        W = bf16(np.asarray(weights[l], np.float32).astype(np.float64))
+        zs.append(hs[l] @ W.T + np.asarray(biases[l], np.float32).astype(np.float64))
+    return dict(fw, x=hs[0], hs=hs, zs=zs, logits=zs[-1])
+
+
+def mlp_grads(feat, labels, weights, biases, normalize=True, hidden=None):
     """Mean cross-entropy over the batch and its gradients w.r.t. every weight
-    and bias (straight-through for the bf16 roundings)."""
+    and bias (straight-through for the bf16 roundings). hidden (optional): the
+    decoder input and hidden activations to follow ([x, h1, h2]) instead of
+    this forward's roundings; a ReLU gate is open where its activation is
+    positive, which is where its pre-activation is."""
     fw = mlp_forward(feat, weights, biases, normalize=normalize)
+    if hidden is not None:
+        fw = _follow(fw, hidden, weights, biases)
     B = feat.shape[0]
     p = softmax(fw["logits"])
     y = np.asarray(labels, np.int64)
@@ -173,7 +196,7 @@ def mlp_grads(feat, labels, weights, biases, normalize=True):
         if l > 0:
             W = bf16(np.asarray(weights[l], np.float32).astype(np.float64))
             dh = dz @ W
-            dz = dh * (fw["zs"][l - 1] > 0.0)
+            dz = dh * (fw["hs"][l] > 0.0)
     return loss, gW, gb
 
 
@@ -215,7 +238,7 @@ def l1_loss_grad(out_flat, target_flat, cams, n_channels, d_sem, lambda_u=1.0):
 
 
 def semantic_loss_grad(feat, ru, labels, weights, biases, inv_hw, lambda_ce=1.0, lambda_u=1.0,
-                       round_bf16=True, normalize=True):
+                       round_bf16=True, normalize=True, hidden=None):
     """Semantic loss of Sec. 3.4.2 for the pixels of one view and its gradients:
       L_CE = sum_px CE(softmax(D_MLP(R_s)), M) (1 - R_u) / (H W)      (Eq. 10)
       L_u  = sum_px R_u / (H W)                                        (Eq. 11)
@@ -223,8 +246,11 @@ def semantic_loss_grad(feat, ru, labels, weights, biases, inv_hw, lambda_ce=1.0,
     feat [P, 8] = R_s, ru [P] = R_u, labels [P] = M (code indices), inv_hw =
     1 / (H W) of the view. The decoder is mlp_forward's (input divided by its
     norm, bf16 roundings emulated unless round_bf16 is False). Gradients pass
-    straight through the roundings. Returns dict with loss, ce [P],
-    d_feat [P, 8] = dL_s/dR_s, d_ru [P] = dL_s/dR_u, gW, gb (lists per layer)."""
+    straight through the roundings. hidden (optional): the rounded decoder
+    input and hidden activations to follow ([x, h1, ...], another
+    evaluation's rounding choices) instead of this forward's. Returns dict
+    with loss, ce [P], d_feat [P, 8] = dL_s/dR_s, d_ru [P] = dL_s/dR_u, gW, gb
+    (lists per layer)."""
     f = np.asarray(feat).astype(np.float64)     # float32 maps promote exactly
     u_r = np.asarray(ru).astype(np.float64)
     y = np.asarray(labels, np.int64)
@@ -244,6 +270,9 @@ def semantic_loss_grad(feat, ru, labels, weights, biases, inv_hw, lambda_ce=1.0,
         if l < L - 1:
             h = rnd(np.maximum(z, 0.0))
             hs.append(h)
+    if hidden is not None:
+        hs = [np.asarray(v, np.float64) for v in hidden]
+        zs = [hs[l] @ Ws[l].T + np.asarray(biases[l], np.float32).astype(np.float64) for l in range(L)]
     p = softmax(zs[-1])
     ce = -np.log(p[np.arange(P), y])
     wpx = lambda_ce * (1.0 - u_r) * inv_hw                # weight of each pixel's CE
@@ -258,7 +287,7 @@ def semantic_loss_grad(feat, ru, labels, weights, biases, inv_hw, lambda_ce=1.0,
         gb[l] = dz.sum(axis=0)
         dh = dz @ Ws[l]
         if l > 0:
-            dz = dh * (zs[l - 1] > 0.0)
+            dz = dh * (hs[l] > 0.0)            # ReLU gate: open where its activation is positive
     # dh is now dL/d(decoder input); a normalised input f / |f| has the
     # Jacobian (I - u u^T) / |f| (zero for a zero feature)
     if normalize:

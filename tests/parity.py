@@ -210,7 +210,8 @@ def compare_grads(g, ref, n, tol=1e-3, groups=GROUPS, subset=None, floor=None, g
     return worst
 
 
-def check_mlp_probs(pr_gpu, feat, ws, bs, normalize, tol=2e-5, max_unresolved_frac=0.002):
+def check_mlp_probs(pr_gpu, feat, ws, bs, normalize, tol=2e-5, max_unresolved_frac=0.002,
+                    hidden_out=None):
     """GPU decoder probabilities [P][N] against the oracle. A pixel none of
     whose bf16-rounded values lies near a rounding midpoint must be within tol
     of the oracle's softmax; every other pixel within tol of the softmax of
@@ -218,10 +219,14 @@ def check_mlp_probs(pr_gpu, feat, ws, bs, normalize, tol=2e-5, max_unresolved_fr
     logits used for it. Pixels with more ambiguous values than the branch
     enumeration follows (at most max_unresolved_frac of them) are left out.
     Returns (logits [P][N] of the matched branches, resolved mask, number of
-    ambiguous pixels)."""
+    ambiguous pixels). With hidden_out a list, it receives the oracle's
+    rounded layer inputs [x, h1, ...] ([P][width] each) of the matched
+    branches (the plain forward's where a pixel is unresolved)."""
     from oracle import decode as D
     ref = D.mlp_forward(feat, ws, bs, normalize=normalize)
     logits = ref["logits"].copy()
+    if hidden_out is not None:
+        hidden_out[:] = [h.copy() for h in ref["hs"]]
     M = D.softmax(logits)
     ok = ~ref["ambiguous"]
     err = np.abs(pr_gpu - M).max(axis=1)
@@ -229,12 +234,15 @@ def check_mlp_probs(pr_gpu, feat, ws, bs, normalize, tol=2e-5, max_unresolved_fr
     resolved = ok.copy()
     unresolved = 0
     for i in np.nonzero(~ok)[0]:
-        br, complete = D.mlp_branches(feat[i], ws, bs, normalize=normalize)
+        br, complete, hid = D.mlp_branches(feat[i], ws, bs, normalize=normalize, return_hidden=True)
         errs = [np.abs(pr_gpu[i] - D.softmax(b[None])[0]).max() for b in br]
         k = int(np.argmin(errs))
         if errs[k] < tol:
             logits[i] = br[k]
             resolved[i] = True
+            if hidden_out is not None:
+                for h, v in zip(hidden_out, hid[k]):
+                    h[i] = v
         else:
             assert not complete, (i, errs[k])
             unresolved += 1

@@ -5,14 +5,22 @@ Plain decode: Sec. 3.3 Eq. 4 (cosine max-similarity over S); learned decode:
 Eq. 8 and the supplementary inference equation; training: Eq. 9 with Adam
 (Sec. 4); loss: per-view L1 plus the L_u regulariser of Eq. 11.
 """
+import sys
+
 import numpy as np
 import pytest
 import torch
 
 import synth
 from oracle import decode as D
+from tests import parity as PT
 
 pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
 
 
 @pytest.fixture(scope="module")
@@ -75,7 +83,7 @@ def test_mlp_decode(ctx, DEC, K, normalize):
     n = 5000 + 17
     f = features(n, 20 + K)
     ws, bs = synth.mlp_init((8, 64, 64, K), 30 + K)
-    ref = D.mlp_forward(f, ws, bs, normalize=normalize)
+    note(f"decode_mlp K={K} normalize={normalize}")
     params = DEC.mlp_pack(ws, bs).cuda()
     top, pr = DEC.decode_mlp(ctx, DEC.rowmajor_features(torch.from_numpy(f).cuda()), params, K, probs=True,
                              normalize=normalize)
@@ -87,18 +95,15 @@ def test_mlp_decode(ctx, DEC, K, normalize):
     torch.cuda.synchronize()
     top, pr = top.cpu().numpy(), pr.cpu().numpy()
     assert np.array_equal(top_r.cpu().numpy(), top) and np.array_equal(top_p.cpu().numpy(), top)
-    p_ref = D.softmax(ref["logits"])
-    ok = ~ref["ambiguous"]
-    assert ok.mean() > 0.5, ok.mean()
-    # non-ambiguous pixels: identical bf16 activations, float32 vs float64 sums only
-    s = np.sort(ref["logits"][ok], axis=1)
-    clear = (s[:, -1] - s[:, -2]) > 1e-4 * (np.abs(s[:, -1]) + 1)
-    t_ref = np.argmax(ref["logits"], axis=1)
-    assert np.array_equal(top[ok][clear], t_ref[ok][clear])
-    assert np.abs(pr[ok] - p_ref[ok]).max() < 2e-5
-    # ambiguous pixels differ by at most a few bf16 ulps in some hidden unit
-    assert np.abs(pr[~ok] - p_ref[~ok]).max() < 2e-2
-    assert (top == t_ref).mean() > 0.995
+    # pixels with no bf16 rounding near a midpoint: the oracle's own forward;
+    # the others: the oracle branch whose roundings the kernel took
+    logits, resolved, n_amb = PT.check_mlp_probs(pr.astype(np.float64), f, ws, bs, normalize)
+    assert n_amb < n // 2, n_amb
+    s = np.sort(logits, axis=1)
+    clear = resolved & ((s[:, -1] - s[:, -2]) > 1e-4 * (np.abs(s[:, -1]) + 1))
+    assert np.array_equal(top[clear], np.argmax(logits, axis=1)[clear])
+    assert clear.mean() > 0.99, clear.mean()
+    note(f"ambiguous pixels {n_amb}, resolved {int(resolved.sum())} of {n}")
 
 
 @pytest.mark.parametrize("normalize", [True, False])
@@ -108,22 +113,35 @@ def test_mlp_gradient_and_train_step(ctx, DEC, normalize):
     rng = np.random.default_rng(41)
     y = rng.integers(0, K, B).astype(np.int32)
     ws, bs = synth.mlp_init((8, 64, 64, K), 42)
-    loss_ref, gW, gb = D.mlp_grads(f, y, ws, bs, normalize=normalize)
+    note(f"mlp train K={K} B={B} normalize={normalize}")
     tr = DEC.MlpTrainer(ctx, DEC.mlp_pack(ws, bs), K, B, normalize=normalize)
     fd_ = torch.from_numpy(f).cuda()
     yd = torch.from_numpy(y).cuda()
     grad, loss = tr.grad_only(DEC.rowmajor_features(fd_), yd)
+    # the training forward is the decoder's: its probabilities name the
+    # rounding branch each pixel took, and the oracle's gradient follows the
+    # oracle's activations of that branch
+    _, pr = DEC.decode_mlp(ctx, DEC.rowmajor_features(fd_), tr.params, K, probs=True, normalize=normalize)
     torch.cuda.synchronize()
+    hid = []
+    _, resolved, n_amb = PT.check_mlp_probs(pr.cpu().numpy().astype(np.float64), f, ws, bs, normalize,
+                                            hidden_out=hid)
+    loss_ref, gW, gb = D.mlp_grads(f, y, ws, bs, normalize=normalize, hidden=hid)
     g = grad.cpu().numpy().astype(np.float64)
     ref = np.concatenate([np.concatenate([w.reshape(-1), b]) for w, b in zip(gW, gb)])
-    assert abs(loss.item() - loss_ref) < 1e-5 * abs(loss_ref)
-    off = 0
+    assert abs(loss.item() - loss_ref) < 1e-6 * abs(loss_ref), (loss.item(), loss_ref)
+    # float32 sums of split-bf16 (16 significant bits) upstream gradients
+    # times exact bf16 operands: each segment within 3e-5 of its norm
+    off, worst = 0, 0.0
     for w, b in zip(gW, gb):
         for part in (w.reshape(-1), b):
             seg = g[off:off + part.size]
-            assert np.linalg.norm(seg - part) <= 1e-3 * np.linalg.norm(part), off
+            r = np.linalg.norm(seg - part) / np.linalg.norm(part)
+            worst = max(worst, r)
+            assert r <= 3e-5, (off, r)
             off += part.size
     assert off == g.size
+    note(f"ambiguous {n_amb}, resolved {int(resolved.sum())} of {B}; worst segment error {worst:.2e}")
     # one full step (gradient + Adam) vs the oracle's Adam on the oracle gradient
     p0 = DEC.mlp_pack(ws, bs).numpy().astype(np.float64)
     tr.step(DEC.rowmajor_features(fd_), yd)

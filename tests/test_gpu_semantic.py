@@ -39,8 +39,7 @@ def test_semantic_loss_matches_oracle(ctx, K, normalize):
     y = rng.integers(0, K, P).astype(np.int32)
     ws, bs = synth.mlp_init((8, 64, 64, K), 71)
     inv_hw = 1.0 / P
-    ref = D.semantic_loss_grad(f, ru, y, ws, bs, inv_hw, 1.0, 1.0, normalize=normalize)
-    amb = D.mlp_forward(f, ws, bs, normalize=normalize)["ambiguous"]
+    note(f"semantic loss K={K} normalize={normalize} P={P}")
     params = DEC.mlp_pack(ws, bs).cuda()
     grad = torch.zeros_like(params)
     loss = torch.zeros(1, device="cuda")
@@ -50,25 +49,36 @@ def test_semantic_loss_matches_oracle(ctx, K, normalize):
     ws_ = DEC.workspace(ctx, P, K)
     DEC.semantic_loss_grad(ctx, DEC.rowmajor_features(fd_), torch.from_numpy(ru).cuda(), torch.from_numpy(y).cuda(),
                            params, K, inv_hw, ws_, grad, (d_feat, 1, 8), d_ru, loss, normalize=normalize)
+    # the loss kernel's forward is the decoder's: its probabilities name the
+    # rounding branch of each pixel, and the oracle follows its own
+    # activations of that branch
+    _, pr = DEC.decode_mlp(ctx, DEC.rowmajor_features(fd_), params, K, probs=True, normalize=normalize)
     torch.cuda.synchronize()
-    assert loss.item() == pytest.approx(ref["loss"], rel=1e-5)
-    ok = ~amb
-    assert ok.mean() > 0.5
+    hid = []
+    _, resolved, n_amb = PT.check_mlp_probs(pr.cpu().numpy().astype(np.float64), f, ws, bs, normalize,
+                                            hidden_out=hid)
+    ref = D.semantic_loss_grad(f, ru, y, ws, bs, inv_hw, 1.0, 1.0, normalize=normalize, hidden=hid)
+    assert loss.item() == pytest.approx(ref["loss"], rel=1e-6)
     dr = d_ru.cpu().numpy().astype(np.float64)
-    assert np.allclose(dr[ok], ref["d_ru"][ok], rtol=1e-4, atol=1e-6 * inv_hw)
+    assert np.allclose(dr[resolved], ref["d_ru"][resolved], rtol=1e-5, atol=1e-6 * inv_hw)
     df = d_feat.cpu().numpy().astype(np.float64)
     err = np.linalg.norm(df - ref["d_feat"], axis=1)
     scale = np.linalg.norm(ref["d_feat"], axis=1)
     rms = np.sqrt(np.mean(scale ** 2))
-    assert (err[ok] <= 1e-3 * np.maximum(scale[ok], 1e-3 * rms)).all()
+    rel = err / np.maximum(scale, 1e-3 * rms)
+    assert (rel[resolved] <= 1e-4).all(), float(rel[resolved].max())
     assert (df[:50] == 0.0).all()
     g = grad.cpu().numpy().astype(np.float64)
-    off = 0
+    off, worst = 0, 0.0
     for w, b in zip(ref["gW"], ref["gb"]):
         for part in (w.reshape(-1), b):
             seg = g[off:off + part.size]
-            assert np.linalg.norm(seg - part) <= 2e-3 * np.linalg.norm(part), off
+            r = np.linalg.norm(seg - part) / np.linalg.norm(part)
+            worst = max(worst, r)
+            assert r <= 3e-5, (off, r)
             off += part.size
+    note(f"ambiguous {n_amb}, resolved {int(resolved.sum())} of {P}; d_feat worst {rel[resolved].max():.2e}, "
+         f"parameter gradient worst segment {worst:.2e}")
     # a second call accumulates the parameter gradient and the loss
     DEC.semantic_loss_grad(ctx, DEC.rowmajor_features(fd_), torch.from_numpy(ru).cuda(), torch.from_numpy(y).cuda(),
                            params, K, inv_hw, ws_, grad, (d_feat, 1, 8), d_ru, loss, normalize=normalize)

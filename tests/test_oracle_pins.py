@@ -880,6 +880,86 @@ def _torch_semantic(torch, f, ru, y, ws, bs, inv_hw, lam_ce, lam_u, round_bf16, 
     return loss.item(), ft.grad.numpy(), rt.grad.numpy(), [w.grad.numpy() for w in Wt], [b.grad.numpy() for b in bt]
 
 
+def test_rounding_branches_and_followed_gradients():
+    """mlp_branches: the first branch of a pixel is the plain forward; every
+    branch rounds each value (the normalised input, each hidden activation
+    computed from the branch's previous layer) to one of its two bf16
+    neighbours, and differs from round-to-nearest only where the value lies
+    within amb_tol of a rounding midpoint; its logits are the forward of its
+    own activations. Following a branch's activations (hidden=) gives the
+    straight-through gradients torch autograd computes with the roundings
+    forced to those values, for mlp_grads (Eq. 9) and semantic_loss_grad
+    (Eqs. 10-12)."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(14)
+    P, K, tol = 400, 32, 2e-6
+    f = rng.normal(0, 1, (P, 8)).astype(np.float32)
+    ru = rng.uniform(0, 1, P)
+    y = rng.integers(0, K, P)
+    ws, bs = synth.mlp_init((8, 64, 64, K), 15)
+    fw = D.mlp_forward(f, ws, bs, amb_tol=tol)
+    amb = np.nonzero(fw["ambiguous"])[0]
+    assert len(amb) >= 5
+    Wb = [D.bf16(w.astype(np.float64)) for w in ws]
+    b64 = [b.astype(np.float64) for b in bs]
+    hid = [h.copy() for h in fw["hs"]]
+    moved = 0
+    for i in amb:
+        lg, complete, trails = D.mlp_branches(f[i], ws, bs, amb_tol=tol, return_hidden=True)
+        assert complete and len(lg) >= 2 and len(trails) == len(lg)
+        assert all(np.array_equal(a, b[i]) for a, b in zip(trails[0], fw["hs"]))
+        u = f[i].astype(np.float64) / np.linalg.norm(f[i].astype(np.float64))
+        for z, tr in zip(lg, trails):
+            assert np.allclose(z, tr[-1] @ Wb[-1].T + b64[-1], rtol=0, atol=1e-12)
+            for l, h in enumerate(tr):
+                v = u if l == 0 else np.maximum(tr[l - 1] @ Wb[l - 1].T + b64[l - 1], 0.0)
+                lo, hi = D.bf16(v * (1 - tol)), D.bf16(v * (1 + tol))
+                near = lo != hi
+                assert np.array_equal(h[~near], D.bf16(v)[~near])
+                assert ((h[near] == lo[near]) | (h[near] == hi[near])).all()
+        for l, h in enumerate(trails[-1]):
+            hid[l][i] = h
+        moved += any(not np.array_equal(a, b) for a, b in zip(trails[-1], trails[0]))
+    assert moved == len(amb)
+
+    def forced(normalize):
+        ft = torch.tensor(f.astype(np.float64), requires_grad=True)
+        Wt = [torch.tensor(w, requires_grad=True) for w in Wb]
+        bt = [torch.tensor(b, requires_grad=True) for b in b64]
+
+        def force(x, v):
+            return x + (torch.from_numpy(v) - x).detach()
+        h = force(torch.nn.functional.normalize(ft, dim=1) if normalize else ft, hid[0])
+        for l, (W, b) in enumerate(zip(Wt, bt)):
+            h = torch.nn.functional.linear(h, W, b)
+            if l < len(Wt) - 1:
+                h = force(torch.relu(h), hid[l + 1])
+        return ft, Wt, bt, h
+    ft, Wt, bt, z = forced(True)
+    loss = torch.nn.functional.cross_entropy(z, torch.from_numpy(y))
+    loss.backward()
+    l2, gW, gb = D.mlp_grads(f, y, ws, bs, hidden=hid)
+    assert l2 == pytest.approx(loss.item(), rel=1e-12)
+    for l in range(3):
+        assert np.allclose(gW[l], Wt[l].grad.numpy(), rtol=1e-10, atol=1e-14)
+        assert np.allclose(gb[l], bt[l].grad.numpy(), rtol=1e-10, atol=1e-14)
+    plain = D.mlp_grads(f, y, ws, bs)
+    assert not np.allclose(plain[1][0], gW[0], rtol=1e-12, atol=0)      # the branches matter
+    ft, Wt, bt, z = forced(True)
+    rt = torch.tensor(ru, requires_grad=True)
+    inv_hw = 1.0 / 613.0
+    ce = torch.nn.functional.cross_entropy(z, torch.from_numpy(y), reduction="none")
+    sl = 1.5 * (ce * (1.0 - rt)).sum() * inv_hw + 0.5 * rt.sum() * inv_hw
+    sl.backward()
+    r = D.semantic_loss_grad(f, ru, y, ws, bs, inv_hw, 1.5, 0.5, hidden=hid)
+    assert r["loss"] == pytest.approx(sl.item(), rel=1e-12)
+    assert np.allclose(r["d_feat"], ft.grad.numpy(), rtol=1e-9, atol=1e-15)
+    assert np.allclose(r["d_ru"], rt.grad.numpy(), rtol=1e-12, atol=1e-16)
+    for l in range(3):
+        assert np.allclose(r["gW"][l], Wt[l].grad.numpy(), rtol=1e-9, atol=1e-15)
+        assert np.allclose(r["gb"][l], bt[l].grad.numpy(), rtol=1e-9, atol=1e-15)
+
+
 @pytest.mark.parametrize("round_bf16,normalize", [(True, True), (False, True), (True, False)])
 def test_semantic_loss_matches_torch_autograd(round_bf16, normalize):
     torch = pytest.importorskip("torch")
