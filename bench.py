@@ -321,7 +321,7 @@ def c5_leg(log_fn, steps, warmup):
               (("mean", scene.mean), ("log_scale", scene.log_scale), ("quat", scene.quat),
                ("opacity_logit", scene.opacity_logit), ("channels", scene.channels))}
     torch.cuda.reset_peak_memory_stats()
-    ts = TrainStep(cams, params, target, d_sem, o=R.opts(tile=32, lds_batch=256))
+    ts = TrainStep(cams, params, target, d_sem, o=R.opts(tile=32, lds_batch=256, ids_only=True))
     for _ in range(warmup):
         ts.step()
     torch.cuda.synchronize()
@@ -540,7 +540,7 @@ def c3_leg(log_fn, steps, warmup):
     ctx = R.Context(0)
     log_fn("c3: autotune over tile x LDS batch")
     best, table = R.autotune(ctx, d["mean"], d["log_scale"], d["quat"], d["opacity_logit"], d["channels"], cams,
-                             R.opts(persistent=True), d_out=G, reps=2)
+                             R.opts(persistent=True, ids_only=True), d_out=G, reps=2)
     del d
     torch.cuda.empty_cache()
     px = sum(c.width * c.height for c in cams)
@@ -549,7 +549,7 @@ def c3_leg(log_fn, steps, warmup):
                autotune=dict(ms={f"tile{t}_batch{b}": v for (t, b), v in table.items()},
                              best=dict(tile=int(best.tile), lds_batch=int(best.lds_batch))))
     for persistent in (False, True):
-        o = R.opts(tile=best.tile, lds_batch=best.lds_batch, persistent=persistent)
+        o = R.opts(tile=best.tile, lds_batch=best.lds_batch, persistent=persistent, ids_only=True)
         run = StepRunner(R, scene, cams, o, G, dev)
         eager_ms, stage_ms, _ = run.time_eager(steps, warmup)
         graph_ms, _ = run.time_graph(steps, warmup)
@@ -595,7 +595,9 @@ def main():
 
     scene, cams, desc = workload(args.workload)
     log(f"workload {desc}")
-    o = R.opts(tile=args.tile, lds_batch=args.lds_batch, persistent=args.persistent)
+    # the blend kernels read the tile lists' ids and ranges; the 64-bit keys are
+    # not written (LEGS_FLAG_IDS_ONLY)
+    o = R.opts(tile=args.tile, lds_batch=args.lds_batch, persistent=args.persistent, ids_only=True)
     dev = torch.device("cuda:0")
     n, C = scene.channels.shape
     G = torch.from_numpy(__import__("synth").upstream_grads(cams, C, 200)).to(dev)
@@ -630,8 +632,8 @@ def main():
         # records (36 B read, 32 B written), the cell counts (32 B) and the coarse
         # emission (16 B); per super-tile entry: the coarse pass writes 8 B, the
         # compaction reads the list and the tile record twice (40 B); per
-        # instance: the compaction writes 12 B
-        "bin_sort": ("hbm", G_views * (24 * gpasses + 68 + 32 + 16) + n_coarse * 48 + n_inst * 12),
+        # instance: the compaction writes the 4 B id (no key: ids only)
+        "bin_sort": ("hbm", G_views * (24 * gpasses + 68 + 32 + 16) + n_coarse * 48 + n_inst * 4),
         "project_bwd": ("hbm", G_views * (44 + 32 + 44 + 4)),
         "blend_fwd": ("alu", ev * FLOPS_EVAL + blended * (4 + 2 * C)),
         "blend_bwd": ("alu", ev_bwd * FLOPS_EVAL + blended * (40 + 7 * C)),

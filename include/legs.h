@@ -85,6 +85,11 @@ typedef struct {
  * rounding): alpha stays below alpha_min there, so images, T_final, last and
  * gradients are the same either way; only the work differs. */
 #define LEGS_FLAG_FULL_BOX 4
+/* Depth-first binning writes the per-tile lists of Gaussian ids and the
+ * ranges only, not the 64-bit keys (the blend kernels read ids and ranges):
+ * bins->keys is left as it was. The lists and ranges are the same. The
+ * full-sort binning sorts the keys themselves and ignores this flag. */
+#define LEGS_FLAG_IDS_ONLY 8
 
 /* Rasteriser options. Defaults (legs_opts_default): tile 16, lds_batch 256,
  * alpha_max 0.99, alpha_min 1/255, t_min 1e-4, lowpass 0.3 px^2, z_near 0.2,

@@ -20,6 +20,7 @@ LEGS_MAX_CHANNELS = 64
 LEGS_FLAG_PERSISTENT = 1
 LEGS_FLAG_FULL_SORT = 2
 LEGS_FLAG_FULL_BOX = 4
+LEGS_FLAG_IDS_ONLY = 8
 LEGS_MLP_NORMALIZE_INPUT = 1
 
 

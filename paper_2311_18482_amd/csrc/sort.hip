@@ -286,25 +286,38 @@ k_histogram(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ coun
 
 // Zero the look-back status words of every pass and the partition counters,
 // only as far as the partitions this count needs.
-__global__ void __launch_bounds__(256)
-k_sort_clear(uint64_t *__restrict__ status, int64_t parts_cap, int passes,
-             uint32_t *__restrict__ counters, uint32_t *__restrict__ hist,
-             const uint64_t *__restrict__ count, int64_t capacity)
+struct SortClearArgs {
+    uint64_t *status;
+    int64_t parts_cap;
+    int passes;
+    uint32_t *counters, *hist;
+    const uint64_t *count;   // NULL: the count is not known yet (capacity is used)
+    int64_t capacity;
+};
+
+// The share of workgroup `block` of `blocks`.
+__device__ __forceinline__ void sort_clear_part(const SortClearArgs &a, int64_t block, int64_t blocks)
 {
-    const uint64_t cnt = count ? *count : (uint64_t)capacity;   // NULL: the count is not known yet
-    const int64_t m = (int64_t)(cnt < (uint64_t)capacity ? cnt : (uint64_t)capacity);
+    if (a.passes <= 0) return;
+    const uint64_t cnt = a.count ? *a.count : (uint64_t)a.capacity;
+    const int64_t m = (int64_t)(cnt < (uint64_t)a.capacity ? cnt : (uint64_t)a.capacity);
     const int64_t parts = (m + LEGS_SORT_PART - 1) / LEGS_SORT_PART;
     const int64_t per_pass = parts * 256;
-    const int64_t tot = per_pass * passes;
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < tot; i += stride) {
+    const int64_t tot = per_pass * a.passes;
+    const int64_t stride = blocks * 256;
+    for (int64_t i = block * 256 + threadIdx.x; i < tot; i += stride) {
         const int64_t p = i / per_pass, r = i - p * per_pass;
-        status[p * parts_cap * 256 + r] = 0;
+        a.status[p * a.parts_cap * 256 + r] = 0;
     }
-    if (blockIdx.x == 0) {
-        if (threadIdx.x < 16) counters[threadIdx.x] = 0;
-        for (int i = threadIdx.x; i < LEGS_SORT_MAX_PASSES * 256; i += 256) hist[i] = 0;
+    if (block == 0 && a.counters) {
+        if (threadIdx.x < 16) a.counters[threadIdx.x] = 0;
+        for (int i = threadIdx.x; i < LEGS_SORT_MAX_PASSES * 256; i += 256) a.hist[i] = 0;
     }
+}
+
+__global__ void __launch_bounds__(256) k_sort_clear(SortClearArgs a)
+{
+    sort_clear_part(a, blockIdx.x, gridDim.x);
 }
 
 // Super-tile record of a depth-ordered position: what the coarse pass needs
@@ -659,32 +672,35 @@ k_seg_scan(const uint32_t *__restrict__ seg_hist, int nseg, const uint32_t *__re
 // key = (view << 32) | bits(depth) for visible G-views (culled ones sort last,
 // they emit nothing); value = G-view index. Also stores G for the sort and
 // counts the digit histograms of its npass passes into hist (cleared before):
-// each workgroup takes chunks of HIST_RUN rows of 256 G-views, loads a
-// chunk's inputs at once, counts in LDS (hist_add for the clustered digits)
-// and flushes its counts once.
-__global__ void __launch_bounds__(256)
+// each workgroup takes chunks of ORDER_RUN rows of ORDER_THREADS G-views,
+// loads a chunk's inputs at once, counts in LDS (hist_add for the clustered
+// digits) and flushes its counts once.
+constexpr int ORDER_THREADS = 1024, ORDER_RUN = 4;   // measured: 4 waves per SIMD beat 1 (256 x 16)
+
+__global__ void __launch_bounds__(ORDER_THREADS)
 k_order_keys(const uint32_t *__restrict__ ntiles, const float *__restrict__ depth, int64_t n,
              int64_t G, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
              uint64_t *__restrict__ gcount, int npass, uint32_t *__restrict__ hist)
 {
+    constexpr int NT = ORDER_THREADS, RUN = ORDER_RUN;
     __shared__ uint32_t s_h[LEGS_SORT_MAX_PASSES][256];
-    for (int i = threadIdx.x; i < LEGS_SORT_MAX_PASSES * 256; i += 256) (&s_h[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < LEGS_SORT_MAX_PASSES * 256; i += NT) (&s_h[0][0])[i] = 0;
     __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) *gcount = (uint64_t)G;
     const bool narrow = G <= (int64_t)0xffffffffll;
-    const int64_t chunk = (int64_t)256 * HIST_RUN;
+    const int64_t chunk = (int64_t)NT * RUN;
     for (int64_t base = (int64_t)blockIdx.x * chunk; base < G; base += (int64_t)gridDim.x * chunk) {
-        uint32_t nt[HIST_RUN];
-        float dp[HIST_RUN];
+        uint32_t nt[RUN];
+        float dp[RUN];
 #pragma unroll
-        for (int i = 0; i < HIST_RUN; ++i) {
-            const int64_t gv = base + 256 * i + threadIdx.x;
+        for (int i = 0; i < RUN; ++i) {
+            const int64_t gv = base + NT * i + threadIdx.x;
             nt[i] = gv < G ? ntiles[gv] : 0u;
             dp[i] = gv < G ? depth[gv] : 0.0f;
         }
 #pragma unroll
-        for (int i = 0; i < HIST_RUN; ++i) {
-            const int64_t gv = base + 256 * i + threadIdx.x;
+        for (int i = 0; i < RUN; ++i) {
+            const int64_t gv = base + NT * i + threadIdx.x;
             const bool ok = gv < G;
             uint64_t key = ~0ull;
             if (ok) {
@@ -702,7 +718,7 @@ k_order_keys(const uint32_t *__restrict__ ntiles, const float *__restrict__ dept
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < npass * 256; i += 256) {
+    for (int i = threadIdx.x; i < npass * 256; i += NT) {
         const uint32_t c = (&s_h[0][0])[i];
         if (c) atomicAdd(&hist[i], c);
     }
@@ -1056,20 +1072,30 @@ k_count_lists(int64_t T, CountGrid g0, CountGrid g1, uint32_t *__restrict__ uoff
 // The other threads clear the digit histograms and pass counters, the
 // capacity cut (no G-view cut) and the per-view position ranges, and every
 // workgroup clears its share of the nclear cell counts at clear.
-__global__ void __launch_bounds__(256)
-k_super_views(const legs_view *__restrict__ views, int n_views, legs_view *__restrict__ sv,
-              uint32_t *__restrict__ desc, uint32_t *__restrict__ hist, uint32_t *__restrict__ counters,
-              uint64_t *__restrict__ cut, uint64_t *__restrict__ vrange, uint32_t *__restrict__ clear,
-              int64_t nclear)
+struct SuperViewArgs {
+    const legs_view *views;
+    int n_views;
+    legs_view *sv;
+    uint32_t *desc, *hist, *counters;
+    uint64_t *cut, *vrange;
+    uint32_t *clear;
+    int64_t nclear;
+};
+
+// The share of workgroup `block` of `blocks`.
+__device__ __forceinline__ void super_views_part(const SuperViewArgs &a, int64_t block, int64_t blocks)
 {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nclear; i += (int64_t)gridDim.x * 256)
-        clear[i] = 0u;
-    if (blockIdx.x != 0) return;
-    for (int i = threadIdx.x; i < LEGS_SORT_MAX_PASSES * 256; i += 256) hist[i] = 0u;
-    for (int i = threadIdx.x; i < 2 * n_views; i += 256) vrange[i] = 0u;
-    if (threadIdx.x < 16) counters[threadIdx.x] = 0u;
-    if (threadIdx.x < 2) cut[threadIdx.x] = ~0ull;
+    for (int64_t i = block * 256 + threadIdx.x; i < a.nclear; i += blocks * 256) a.clear[i] = 0u;
+    if (block != 0) return;
+    for (int i = threadIdx.x; i < LEGS_SORT_MAX_PASSES * 256; i += 256) a.hist[i] = 0u;
+    for (int i = threadIdx.x; i < 2 * a.n_views; i += 256) a.vrange[i] = 0u;
+    if (threadIdx.x < 16) a.counters[threadIdx.x] = 0u;
+    if (threadIdx.x < 2) a.cut[threadIdx.x] = ~0ull;
     if (threadIdx.x != 0) return;
+    const int n_views = a.n_views;
+    const legs_view *views = a.views;
+    legs_view *sv = a.sv;
+    uint32_t *desc = a.desc;
     int64_t off = 0;
     for (int v = 0; v < n_views; ++v) {
         legs_view w = views[v];
@@ -1099,6 +1125,16 @@ k_super_views(const legs_view *__restrict__ views, int n_views, legs_view *__res
         desc[4] = 0u;
         desc[5] = 8u;
     }
+}
+
+// The set-up of the depth-first binning in one launch: the G-view sort's
+// scratch cleared (sort_clear_part) and the super-tile views with the
+// clears of the counting and coarse scratch (super_views_part, whose
+// single-workgroup part goes to the last workgroup).
+__global__ void __launch_bounds__(256) k_bin_setup(SortClearArgs a, SuperViewArgs b)
+{
+    sort_clear_part(a, blockIdx.x, gridDim.x);
+    super_views_part(b, gridDim.x - 1 - blockIdx.x, gridDim.x);
 }
 
 // What a wave needs of its unit: the list entries [e0, e1), the super-tile's
@@ -1272,8 +1308,8 @@ k_compact_scan(const uint32_t *__restrict__ uoff, int64_t n, const legs_view *__
 // masks, one entry per lane and round of 64. Per tile, the entries covering
 // it get their rank among the unit's hits (ballot per round); their (id,
 // depth) pairs are placed in rank order in an LDS row of the wave, which is
-// then stored as one contiguous run of the tile's list with all lanes. Four
-// tiles are staged per LDS round trip.
+// then stored as one contiguous run of the tile's list with all lanes (ids,
+// and the keys unless keys is NULL). Four tiles are staged per LDS round trip.
 __global__ void __launch_bounds__(256)
 k_compact_write(const uint32_t *__restrict__ clist0, const uint32_t *__restrict__ clist1,
                 const uint32_t *__restrict__ desc, const uint32_t *__restrict__ uoff, int64_t n,
@@ -1337,7 +1373,7 @@ k_compact_write(const uint32_t *__restrict__ clist0, const uint32_t *__restrict_
                     const uint2 v = run[bb][k];
                     const int64_t at = (int64_t)start + k;
                     if (at < capacity) {
-                        keys[at] = (tile << 32) | v.y;
+                        if (keys) keys[at] = (tile << 32) | v.y;
                         ids[at] = v.x;
                     }
                 }
@@ -1464,8 +1500,8 @@ int32_t radix_passes(legs_ctx *ctx, const SortScratch &S, uint64_t *k0, uint32_t
     if (np <= 0) return LEGS_OK;
     if (!prepared) {   // prepared: the caller cleared the scratch and counted the digits
         const int gclear = grid_for(ctx, S.parts * 256 * np, 256, 8);
-        hipLaunchKernelGGL(k_sort_clear, dim3(gclear), dim3(256), 0, s, S.status, S.parts, np,
-                           S.counters, S.hist, count, capacity);
+        hipLaunchKernelGGL(k_sort_clear, dim3(gclear), dim3(256), 0, s,
+                           SortClearArgs{S.status, S.parts, np, S.counters, S.hist, count, capacity});
         const int ghist = grid_for(ctx, capacity, 256 * HIST_RUN, 4);
         hipLaunchKernelGGL(k_histogram, dim3(ghist), dim3(256), 0, s, k0, count, capacity, first, np, S.hist);
         LEGS_CHECK_LAUNCH(ctx);
@@ -1555,13 +1591,28 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
         uint32_t *ov0 = reinterpret_cast<uint32_t *>(ord + OL.v0), *ov1 = reinterpret_cast<uint32_t *>(ord + OL.v1);
         uint64_t *gcount = reinterpret_cast<uint64_t *>(ord + OL.gcount);
         const int gpass = (32 + bits_for(n_views) + 7) / 8;
-        if (OL.G > 0) {
-            // clear the sort scratch for every G-view, then the keys with their
-            // digit counts, then the passes
+        uint64_t *vrange = reinterpret_cast<uint64_t *>(ord + OL.vrange);
+        sviews = reinterpret_cast<legs_view *>(ord + OL.sviews);
+        {
+            // one set-up launch: the G-view sort scratch cleared for every G-view,
+            // the super-tile views, and the clears of the counting and coarse
+            // scratch (both grids' cell counts are adjacent)
             const SortScratch GS = sort_scratch_at(ord + OL.sort, OL.G);
-            hipLaunchKernelGGL(k_sort_clear, dim3(grid_for(ctx, GS.parts * 256 * gpass, 256, 8)), dim3(256), 0, s,
-                               GS.status, GS.parts, gpass, GS.counters, GS.hist, nullptr, OL.G);
-            hipLaunchKernelGGL(k_order_keys, dim3(grid_for(ctx, OL.G, 256 * HIST_RUN, 4)), dim3(256), 0, s,
+            const SortClearArgs ca = OL.G > 0 ? SortClearArgs{GS.status, GS.parts, gpass, GS.counters, GS.hist,
+                                                              nullptr, OL.G}
+                                              : SortClearArgs{nullptr, 0, 0, nullptr, nullptr, nullptr, 0};
+            const int64_t nclear = (int64_t)(S.scount - S.tcount) + total_tiles;
+            const SuperViewArgs sa{views, n_views, sviews, S.desc, S.hist, S.counters, S.cut, vrange, S.tcount,
+                                   nclear};
+            const int g0 = OL.G > 0 ? grid_for(ctx, GS.parts * 256 * gpass, 256, 8) : 1;
+            const int g1 = grid_for(ctx, nclear, 256, 8);
+            hipLaunchKernelGGL(k_bin_setup, dim3(g0 > g1 ? g0 : g1), dim3(256), 0, s, ca, sa);
+        }
+        if (OL.G > 0) {
+            // the keys with their digit counts, then the passes
+            const SortScratch GS = sort_scratch_at(ord + OL.sort, OL.G);
+            hipLaunchKernelGGL(k_order_keys, dim3(grid_for(ctx, OL.G, ORDER_THREADS * ORDER_RUN, 4)),
+                               dim3(ORDER_THREADS), 0, s,
                                proj->ntiles, proj->depth, n, OL.G, ok0, ov0, gcount, gpass, GS.hist);
             LEGS_CHECK_LAUNCH(ctx);
             const int32_t r = radix_passes(ctx, GS, ok0, ov0, ok1, ov1, gcount, OL.G, 0, gpass, true, s);
@@ -1574,12 +1625,6 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
         offsets = reinterpret_cast<uint64_t *>(ord + OL.offsets);
         coffsets = reinterpret_cast<uint64_t *>(ord + OL.coffsets);
         ccount = reinterpret_cast<uint64_t *>(ord + OL.ccount);
-        uint64_t *vrange = reinterpret_cast<uint64_t *>(ord + OL.vrange);
-        sviews = reinterpret_cast<legs_view *>(ord + OL.sviews);
-        // also clears both grids' cell counts (adjacent) for the counting below
-        const int64_t nclear = (int64_t)(S.scount - S.tcount) + total_tiles;
-        hipLaunchKernelGGL(k_super_views, dim3(grid_for(ctx, nclear, 256, 8)), dim3(256), 0, s, views, n_views,
-                           sviews, S.desc, S.hist, S.counters, S.cut, vrange, S.tcount, nclear);
         if (nblocks > 0)
             hipLaunchKernelGGL(k_sorted_records, dim3((unsigned)nblocks), dim3(LEGS_PROJ_BLOCK), 0, s,
                                perm, (gpass % 2 == 0) ? ok0 : ok1,
@@ -1698,7 +1743,8 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
     hipLaunchKernelGGL(k_compact_scan, dim3(grid_for(ctx, T, 256 / LEGS_WAVE, 4)), dim3(256), 0, s, S.uoff, T,
                        sviews, views, n_views, bins->ranges, S.ucnt);
     hipLaunchKernelGGL(k_compact_write, dim3(gu), dim3(256), 0, s, cv[0], cv[1], S.desc, S.uoff, T, udesc, P.pay,
-                       OL.G, S.cut, S.ucnt, bins->capacity, bins->keys, bins->ids);
+                       OL.G, S.cut, S.ucnt, bins->capacity,
+                       (o->flags & LEGS_FLAG_IDS_ONLY) ? nullptr : bins->keys, bins->ids);
     LEGS_CHECK_LAUNCH(ctx);
     return LEGS_OK;
 }

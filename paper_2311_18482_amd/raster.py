@@ -24,12 +24,13 @@ def _stream(device=None):
 
 
 def opts(tile=16, lds_batch=256, alpha_max=0.99, alpha_min=1.0 / 255.0, t_min=1e-4,
-         lowpass=0.3, z_near=0.2, guard=1.3, persistent=False, full_sort=False, full_box=False) -> L.Opts:
+         lowpass=0.3, z_near=0.2, guard=1.3, persistent=False, full_sort=False, full_box=False,
+         ids_only=False) -> L.Opts:
     o = L.Opts()
     L.lib().legs_opts_default(ct.byref(o))
     o.tile, o.lds_batch = int(tile), int(lds_batch)
     o.flags = ((L.LEGS_FLAG_PERSISTENT if persistent else 0) | (L.LEGS_FLAG_FULL_SORT if full_sort else 0)
-               | (L.LEGS_FLAG_FULL_BOX if full_box else 0))
+               | (L.LEGS_FLAG_FULL_BOX if full_box else 0) | (L.LEGS_FLAG_IDS_ONLY if ids_only else 0))
     o.alpha_max, o.alpha_min, o.t_min = alpha_max, alpha_min, t_min
     o.lowpass, o.z_near, o.guard = lowpass, z_near, guard
     return o

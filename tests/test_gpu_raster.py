@@ -590,6 +590,21 @@ def test_depth_first_and_full_sort_lists_identical(R, rig):
         assert a[0] == b[0]
         for x, y in zip(a[1:], b[1:]):
             assert np.array_equal(x, y)
+    # ids only: the same lists, ranges and images; the keys left as they were
+    for tile, keys, ids, ranges, img in lists[:2]:
+        note(f"rig={rig} ids_only tile={tile}")
+        o = R.opts(tile=tile, ids_only=True)
+        rast, d, proj, bins, out, T, last = run_forward(R, scene, cams, o)
+        n_inst = int(bins.count.item())
+        assert n_inst == len(ids)
+        assert np.array_equal(bins.ids[:n_inst].cpu().numpy(), ids)
+        assert np.array_equal(bins.ranges.cpu().numpy(), ranges)
+        assert np.array_equal(out.cpu().numpy(), img)
+        bins.keys.fill_(0x5A5A5A5A5A5A5A5A)
+        R.bin_sort(rast.ctx, proj, rast.views, o, bins)
+        torch.cuda.synchronize()
+        assert (bins.keys == 0x5A5A5A5A5A5A5A5A).all()
+        assert np.array_equal(bins.ids[:n_inst].cpu().numpy(), ids)
 
 
 def _expected_counts(proj_v, cam, ids, ranges, tile_offset, tile, amin, amax, tmin):
