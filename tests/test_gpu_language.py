@@ -94,3 +94,49 @@ def test_language_features_match_oracle(ctx, N, d, out_f16):
     tol = (2.0 ** -10 + 2e-5) * o["F_abs"] + N * 2.0 ** -25 * np.abs(S).max() + (bound if out_f16 else 0.0)
     assert (np.abs(Fg - o["F"])[~amb] <= tol[~amb]).all()
     note(f"max rel err vs exact {float((np.abs(Fg - o['F']) / np.maximum(o['F_abs'], 1e-30))[~amb].max()):.3g}")
+
+
+def test_paper_decoder_and_features_at_bench_size(ctx):
+    """The Table 3 decoder and F = M S at the size the bench times them (four
+    1920x1080 views of 8-d rendered features, N = 128, d = 512, float32 F),
+    in the same launch configurations: both decode kernels agree on every
+    pixel's top-1, both precisions come from one probability, and 4000
+    sampled pixels (the first, the ragged last 40, random ones) match the
+    oracle: the decoder by rounding-branch replay, their F columns within the
+    bounds of the small-size test."""
+    from paper_2311_18482_amd import decode as DEC
+    P, N, d = 4 * 1920 * 1080, 128, 512
+    f = features(P, 190)
+    ws, bs = synth.mlp_init((8, 128, 256, N), 191)
+    S = synth.codebook(N, d, 192)
+    params = DEC.mlp_pack(ws, bs).cuda()
+    fd = torch.from_numpy(f).cuda()
+    note(f"decode_dmlp + language_features at P={P} N={N} d={d}")
+    t_only, _, _ = DEC.decode_dmlp(ctx, DEC.rowmajor_features(fd), params, N)
+    t1, pr, p16 = DEC.decode_dmlp(ctx, DEC.rowmajor_features(fd), params, N, probs=True, probs_f16=True)
+    Fg = DEC.language_features(ctx, p16, torch.from_numpy(S).cuda())
+    torch.cuda.synchronize()
+    assert torch.equal(t_only, t1)
+    assert torch.equal(p16, pr.half())
+    rng = np.random.default_rng(193)
+    idx = np.unique(np.concatenate([[0], np.arange(P - 40, P), rng.integers(0, P, 4000)]))
+    it = torch.from_numpy(idx).cuda()
+    prs = pr[it].cpu().numpy().astype(np.float64)
+    t1s = t1[it].cpu().numpy()
+    Fs = Fg[:, it].t().cpu().numpy().astype(np.float64)
+    M16 = p16[it].float().cpu().numpy().astype(np.float64)
+    del pr, p16, Fg
+    logits, resolved, n_amb = PT.check_mlp_probs(prs, f[idx], ws, bs, False)
+    s = np.sort(logits, axis=1)
+    clear = resolved & ((s[:, -1] - s[:, -2]) > 1e-4 * (np.abs(s[:, -1]) + 1))
+    assert np.array_equal(t1s[clear], np.argmax(logits, axis=1)[clear])
+    assert clear.mean() > 0.99, clear.mean()
+    S16 = S.astype(np.float16).astype(np.float64)
+    ref = M16 @ S16
+    bound = N * 2.0 ** -24 * (M16 @ np.abs(S16)) + 1e-30
+    assert (np.abs(Fs - ref) <= bound).all(), float((np.abs(Fs - ref) / bound).max())
+    o = LG.language_features(f[idx], ws, bs, S)
+    amb = o["ambiguous"]
+    tol = (2.0 ** -10 + 2e-5) * o["F_abs"] + N * 2.0 ** -25 * np.abs(S).max()
+    assert (np.abs(Fs - o["F"])[~amb] <= tol[~amb]).all()
+    note(f"sampled {len(idx)} of {P}: ambiguous {n_amb}, resolved {int(resolved.sum())}")

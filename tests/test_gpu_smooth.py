@@ -13,7 +13,12 @@ from oracle import language as LG
 
 pytestmark = pytest.mark.gpu
 
-KAPPA = 3e-5          # float32 sums of ~1e4 terms and the 16-bit split of dz, in units of sum |term|
+
+def kappa(n):
+    """Error allowance of the weight-gradient sums in units of sum |term|:
+    float32 sums within a workgroup's chunk of 4096 Gaussians and the 16-bit
+    split of dz (3e-5), plus one float32 atomic per chunk."""
+    return 3e-5 + -(-n // 4096) * 2.0 ** -24
 
 
 def note(msg):
@@ -61,8 +66,10 @@ def check_activations(pos, ws, bs, hid):
     return n_amb
 
 
-@pytest.mark.parametrize("n", [20000 + 13, 777])
+@pytest.mark.parametrize("n", [20000 + 13, 777, 1_000_000])
 def test_smoothing_matches_oracle(ctx, n):
+    """The last size is the bench's (the 1M Gaussians of the 1080p scene), in
+    its launch configuration."""
     from paper_2311_18482_amd import decode as DEC
     rng = np.random.default_rng(180 + n)
     C, sem, uch = 12, 3, 11
@@ -88,7 +95,9 @@ def test_smoothing_matches_oracle(ctx, n):
     # everything else along the GPU's activations
     sg, u = chans[:, sem:sem + 8], chans[:, uch]
     r = LG.smoothing_loss_grad(pos, sg, u, ws, bs, w_s=0.1, hidden=hid)
-    assert loss.item() == pytest.approx(lam * r["loss"], rel=1e-5)
+    # the loss is one float32 atomic per wave (64 Gaussians): a random walk of
+    # about sqrt(n / 64) roundings of 2^-24 (under 1e-5 up to ~1e5 Gaussians)
+    assert loss.item() == pytest.approx(lam * r["loss"], rel=1e-5 + 4.0 * np.sqrt(n / 64) * 2.0 ** -24)
     after = d_ch.cpu().numpy().astype(np.float64)
     dch = after - d0
     # the accumulated channel gradient is stored in float32: 2^-24 of the sum per element
@@ -104,7 +113,7 @@ def test_smoothing_matches_oracle(ctx, n):
     err = np.linalg.norm(dch[:, sem:sem + 8] - lam * r["d_sg"], axis=1)
     assert (err <= lam * wgt / n * du + 1e-6 * lam * wgt / n + store).all()
     # MLP gradients: errors of dz4 (as above) carried down the layers, plus
-    # KAPPA sum |term| of each product
+    # kappa(n) sum |term| of each product
     g = grad.cpu().numpy().astype(np.float64)
     Wb = [D.bf16(w.astype(np.float64)) for w in ws]
     e = (lam / n * du)[:, None] * np.ones((1, 8))             # |error| of dz4 per Gaussian and output
@@ -115,9 +124,9 @@ def test_smoothing_matches_oracle(ctx, n):
     for l in range(3, -1, -1):
         gW = g[offs[l]:offs[l] + sizes[l][0] * sizes[l][1]].reshape(sizes[l])
         gb = g[offs[l] + sizes[l][0] * sizes[l][1]:offs[l + 1]]
-        bound = e.T @ np.abs(hs[l]) + KAPPA * (dz.T @ np.abs(hs[l])) + 1e-12
+        bound = e.T @ np.abs(hs[l]) + kappa(n) * (dz.T @ np.abs(hs[l])) + 1e-12
         assert (np.abs(gW - lam * r["gW"][l]) <= bound).all(), (l, float((np.abs(gW - lam * r["gW"][l]) / bound).max()))
-        bb = e.sum(axis=0) + KAPPA * dz.sum(axis=0) + 1e-12
+        bb = e.sum(axis=0) + kappa(n) * dz.sum(axis=0) + 1e-12
         assert (np.abs(gb - lam * r["gb"][l]) <= bb).all(), (l, float((np.abs(gb - lam * r["gb"][l]) / bb).max()))
         if l > 0:
             gate = hs[l] > 0
