@@ -106,6 +106,59 @@ def test_mlp_decode(ctx, DEC, K, normalize):
     note(f"ambiguous pixels {n_amb}, resolved {int(resolved.sum())} of {n}")
 
 
+def test_decodes_at_bench_size(ctx, DEC):
+    """The decodes the bench times, at its size (32 views of 1920x1080 8-d
+    features: 66.4M pixels, K = 128, codebook 128 x 512, projection 512 x 8)
+    in the same launches (top-1 only): the learned decode with normalised and
+    raw input, the direct and the folded plain decode. 4000 sampled pixels
+    (the first, the ragged last 40, random ones) against the oracle: the
+    plain decodes' top-1 outside a 1e-5 cosine margin; the learned decode's
+    top-1 is the oracle's argmax where no bf16 value lies near a rounding
+    midpoint (outside a 1e-4 logit margin), and elsewhere the argmax of one
+    of the pixel's rounding branches."""
+    P, K, Dm = 32 * 1920 * 1080, 128, 512
+    f = features(P, 80)
+    ws, bs = synth.mlp_init((8, 64, 64, K), 81)
+    Pm = synth.projection(Dm, 8, 82)
+    Cb = synth.codebook(K, Dm, 83)
+    fd_ = torch.from_numpy(f).cuda()
+    params = DEC.mlp_pack(ws, bs).cuda()
+    Pd, Cd = torch.from_numpy(Pm).cuda(), torch.from_numpy(Cb).cuda()
+    note(f"decodes at P={P} K={K}")
+    fr = DEC.rowmajor_features(fd_)
+    tops = {}
+    for normalize in (True, False):
+        t, _ = DEC.decode_mlp(ctx, fr, params, K, normalize=normalize)
+        tops[normalize] = t
+    t_plain, _ = DEC.decode_plain(ctx, fr, Pd, Cd)
+    t_fold, _ = DEC.decode_folded(ctx, fr, DEC.decode_fold(ctx, Pd, Cd), K)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(84)
+    idx = np.unique(np.concatenate([[0], np.arange(P - 40, P), rng.integers(0, P, 4000)]))
+    it = torch.from_numpy(idx).cuda()
+    fs = f[idx]
+    # plain decodes
+    _, top_ref = D.decode_plain(fs, Pm, Cb)
+    z = fs.astype(np.float64) @ Pm.astype(np.float64).T
+    cos = (z @ Cb.astype(np.float64).T) / np.maximum(np.linalg.norm(z, axis=1, keepdims=True), 1e-300)
+    for t in (t_plain, t_fold):
+        amb = check_top1(t[it].cpu().numpy(), cos, top_ref, 1e-5)
+        assert amb < len(idx) // 100
+    # learned decodes
+    for normalize, t in tops.items():
+        tg = t[it].cpu().numpy()
+        fw = D.mlp_forward(fs, ws, bs, normalize=normalize)
+        s = np.sort(fw["logits"], axis=1)
+        clear = ~fw["ambiguous"] & ((s[:, -1] - s[:, -2]) > 1e-4 * (np.abs(s[:, -1]) + 1))
+        assert np.array_equal(tg[clear], np.argmax(fw["logits"], axis=1)[clear])
+        assert clear.mean() > 0.9, clear.mean()
+        for i in np.nonzero(fw["ambiguous"])[0]:
+            br, complete = D.mlp_branches(fs[i], ws, bs, normalize=normalize)
+            if complete:
+                assert tg[i] in {int(np.argmax(b)) for b in br}, i
+        note(f"normalize={normalize}: ambiguous {int(fw['ambiguous'].sum())} of {len(idx)} sampled")
+
+
 @pytest.mark.parametrize("normalize", [True, False])
 def test_mlp_gradient_and_train_step(ctx, DEC, normalize):
     K, B = 128, 6000
