@@ -51,6 +51,10 @@ typedef struct {
     double t_min;     /* 1e-4 */
     double eps_alpha; /* relative margin below which a skip decision is ambiguous */
     double eps_t;     /* relative margin below which a stop decision is ambiguous */
+    double eps_alpha_mag; /* added to eps_alpha per unit of the exponent's magnitude sum
+                             (0.5 |A dx^2| + |B dx dy| + 0.5 |C dy^2|): rounding the
+                             terms of a strongly cancelling exponent moves alpha by
+                             that sum times a few ulps, not by |power| times them */
     int32_t tile;     /* tile edge in pixels */
     int32_t pad;
 } oopts_t;
@@ -274,7 +278,9 @@ static inline uint64_t fnv(uint64_t h, uint64_t v)
 
 /* Blend pixel (i, j) over `list` (Gaussian ids in order). Decisions whose
  * relative margin to the 1/255 skip or the 1e-4 stop threshold is below eps are
- * counted as ambiguous events; bit e of flip_mask inverts the e-th such event.
+ * counted as ambiguous events (for the skip, eps grows with the magnitude sum
+ * of the exponent's terms: eps_alpha_mag); bit e of flip_mask inverts the
+ * e-th such event.
  * rec (optional, capacity len) receives the blended entries in order. */
 static void blend_pixel(int i, int j, const uint32_t *list, int64_t len, const oproj_t *P,
                         const double *ch, int C, const oopts_t *o, uint32_t flip_mask,
@@ -302,7 +308,8 @@ static void blend_pixel(int i, int j, const uint32_t *list, int64_t len, const o
         int skip = alpha < o->alpha_min;
         double m = fabs(alpha - o->alpha_min) / o->alpha_min;
         if (m < mm) mm = m;
-        if (m < o->eps_alpha) {
+        const double mag = 0.5 * (fabs(p->A * dx * dx) + fabs(p->C * dy * dy)) + fabs(p->B * dx * dy);
+        if (m < o->eps_alpha + o->eps_alpha_mag * mag) {
             if (ev < 32 && ((flip_mask >> ev) & 1u)) skip = !skip;
             ++ev;
         }

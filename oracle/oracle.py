@@ -28,8 +28,8 @@ class OCam(ct.Structure):
 class OOpts(ct.Structure):
     _fields_ = [("lowpass", ct.c_double), ("z_near", ct.c_double), ("guard", ct.c_double),
                 ("alpha_max", ct.c_double), ("alpha_min", ct.c_double), ("t_min", ct.c_double),
-                ("eps_alpha", ct.c_double), ("eps_t", ct.c_double), ("tile", ct.c_int32),
-                ("pad", ct.c_int32)]
+                ("eps_alpha", ct.c_double), ("eps_t", ct.c_double), ("eps_alpha_mag", ct.c_double),
+                ("tile", ct.c_int32), ("pad", ct.c_int32)]
 
 
 PROJ_DTYPE = np.dtype([
@@ -89,8 +89,9 @@ def make_cam(cam) -> OCam:
     return OCam(W, H, fx, fy, cx, cy, (ct.c_double * 9)(*R), (ct.c_double * 3)(*t))
 
 
-def make_opts(tile=16, lowpass=0.3, z_near=0.2, guard=1.3, eps_alpha=1e-5, eps_t=1e-4) -> OOpts:
-    return OOpts(lowpass, z_near, guard, ALPHA_MAX, ALPHA_MIN, T_MIN, eps_alpha, eps_t, int(tile), 0)
+def make_opts(tile=16, lowpass=0.3, z_near=0.2, guard=1.3, eps_alpha=1e-5, eps_t=1e-4,
+              eps_alpha_mag=0.0) -> OOpts:
+    return OOpts(lowpass, z_near, guard, ALPHA_MAX, ALPHA_MIN, T_MIN, eps_alpha, eps_t, eps_alpha_mag, int(tile), 0)
 
 
 class Params:

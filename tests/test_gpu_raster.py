@@ -470,19 +470,13 @@ def test_graph_replay(R):
         PT.compare_grads(got, want, n, tol=1e-4)
 
 
-def test_persistent_graph_six_views_matches_oracle(R):
-    """A captured forward + backward step over 6 views of uneven resolution
-    with both blend kernels launched persistently (one queue of every view's
-    tiles, heaviest first), replayed several times with eager work and
-    synchronisation in between: every replay matches the oracle (lists
-    bit-exact, images, T and last under the ambiguity rule, per-Gaussian
-    gradients within the gradient bound)."""
-    scene = synth.make_scene(60_000, 24, synth.VOL_CUBE, d_sem=8)
-    sizes = ((320, 240), (200, 150), (480, 270), (256, 256), (160, 120), (400, 300))
-    cams = synth.cameras_sphere(6, 124, 8.0, (320, 240))
-    for c, (w, h) in zip(cams, sizes):
-        c.width, c.height, c.fx, c.fy, c.cx, c.cy = w, h, float(w), float(w), w / 2.0, h / 2.0
-    o = R.opts(tile=16, lds_batch=128, persistent=True)
+def graph_replays_match_oracle(R, scene, cams, o, reps, seed_g):
+    """Captures one forward + backward step (project, bin, blend forward,
+    gradient clear, blend backward, project backward) as a HIP graph and
+    replays it reps times with eager work and synchronisation in between;
+    every replay matches the oracle (lists bit-exact, images, T and last
+    under the ambiguity rule, per-Gaussian gradients within the gradient
+    bound)."""
     oo = PT.oracle_opts(o)
     rast = R.Rasterizer(cams, o)
     d = PT.to_dev(scene)
@@ -495,7 +489,7 @@ def test_persistent_graph_six_views_matches_oracle(R):
     out = torch.empty(C * views.total_pixels, device="cuda")
     T = torch.empty(views.total_pixels, device="cuda")
     last = torch.empty(views.total_pixels, dtype=torch.int32, device="cuda")
-    G = synth.upstream_grads(cams, C, 224)
+    G = synth.upstream_grads(cams, C, seed_g)
     Gd = torch.from_numpy(G).cuda()
     gflat = torch.zeros(n * views.n_views * 8 + n * (C + 11), device="cuda")
     grad2d = gflat[:n * views.n_views * 8].view(-1, 8)
@@ -522,21 +516,54 @@ def test_persistent_graph_six_views_matches_oracle(R):
     torch.cuda.current_stream().wait_stream(side)
     fwd = O.forward(scene, cams, oo)
     ref = None
-    for rep in range(3):
+    for rep in range(reps):
         out.fill_(-1.0)
         T.fill_(-1.0)
         d_ch.fill_(123.0)
         torch.cuda.synchronize()
         g.launch()
         torch.cuda.synchronize()
-        note(f"six-view persistent graph replay {rep}")
-        PT.compare_bins(bins, fwd)
+        note(f"{len(cams)}-view graph replay {rep} (tile {o.tile}, batch {o.lds_batch}, flags {o.flags})")
+        PT.compare_bins(bins, fwd, ids_only=bool(o.flags & R.L.LEGS_FLAG_IDS_ONLY))
         masks, stats = PT.compare_render(out, T, last, scene, cams, oo, fwd)
         if ref is None:
-            ref = O.backward(scene, cams, oo, fwd, G.astype(np.float64), flip_masks=masks, magnitudes=True, mag_cond=PT.MAG_COND)
+            ref = O.backward(scene, cams, oo, fwd, G.astype(np.float64), flip_masks=masks, magnitudes=True,
+                             mag_cond=PT.MAG_COND)
         got = PT.gpu_grads_to_np(grads, d_ch)
         worst = PT.compare_grads(got, ref, n, mag=ref["mag"])
         note(f"replay {rep}: {stats} {worst}")
+
+
+def test_persistent_graph_six_views_matches_oracle(R):
+    """A captured forward + backward step over 6 views of uneven resolution
+    with both blend kernels launched persistently (one queue of every view's
+    tiles, heaviest first), replayed several times: every replay matches the
+    oracle."""
+    scene = synth.make_scene(60_000, 24, synth.VOL_CUBE, d_sem=8)
+    sizes = ((320, 240), (200, 150), (480, 270), (256, 256), (160, 120), (400, 300))
+    cams = synth.cameras_sphere(6, 124, 8.0, (320, 240))
+    for c, (w, h) in zip(cams, sizes):
+        c.width, c.height, c.fx, c.fy, c.cx, c.cy = w, h, float(w), float(w), w / 2.0, h / 2.0
+    graph_replays_match_oracle(R, scene, cams, R.opts(tile=16, lds_batch=128, persistent=True), 3, 224)
+
+
+@pytest.mark.timeout(1200)
+def test_c3_sixteen_views_autotuned_persistent_graph(R):
+    """The 16-view batch as the bench times it: 1M Gaussians, 16 views of
+    uneven resolution on the r=8 sphere, the autotuner's choice of tile and
+    LDS batch, both blend kernels persistent, ids-only binning, the step
+    captured and replayed: every replay against the oracle."""
+    scene, cams = synth.workload_c3()
+    d = PT.to_dev(scene)
+    G = torch.from_numpy(synth.upstream_grads(cams, scene.n_channels, 203)).cuda()
+    ctx = R.Context(0)
+    best, table = R.autotune(ctx, d["mean"], d["log_scale"], d["quat"], d["opacity_logit"], d["channels"], cams,
+                             R.opts(persistent=True, ids_only=True), d_out=G, reps=1)
+    del d, G
+    torch.cuda.empty_cache()
+    note(f"c3 autotune: best tile {best.tile} batch {best.lds_batch}")
+    o = R.opts(tile=best.tile, lds_batch=best.lds_batch, persistent=True, ids_only=True)
+    graph_replays_match_oracle(R, scene, cams, o, 2, 203)
 
 
 def test_autotune_returns_a_valid_setting(R):

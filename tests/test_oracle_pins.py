@@ -455,6 +455,43 @@ def test_ambiguous_skip_flip(oracle_lib):
     assert skipped["out"][0, 0] == 0.0 and skipped["T"][0] == 1.0 and skipped["last"][0] == 0
 
 
+def test_skip_window_grows_with_exponent_magnitude(oracle_lib):
+    """The skip decision counts as ambiguous within eps_alpha (relative) of
+    1/255, widened by eps_alpha_mag per unit of the exponent's magnitude sum
+    0.5 |A dx^2| + |B dx dy| + 0.5 |C dy^2|. A needle-shaped footprint (terms
+    of ~1188 cancelling to a power of -5.2) with alpha 2e-5 below 1/255 is
+    ambiguous only with the widening; a round footprint at the same alpha and
+    power (magnitude sum 5.2) is not ambiguous either way. Both are skipped."""
+    cam = synth.camera_front(64, 64, 64.0)
+    sc = scene_from([[1.5 / 64, 1.5 / 64, 3.0]], [[-1.0] * 3], [[1, 0, 0, 0]], [0.0], [[2.0]])
+    f = O.forward(sc, [cam], O.make_opts(16))
+    lin = 32 * 64 + 32
+    dx, dy = 10.0, -9.9
+    target = (1.0 / 255.0) * (1.0 - 2e-5)
+    got = {}
+    for name in ("needle", "round"):
+        rec = f["proj"][0].copy()
+        if name == "needle":
+            A = C = 12.0
+            B = (0.5 * (A * dx * dx + C * dy * dy) - 5.2) / (-dx * dy)
+            assert A * C - B * B > 0.0
+        else:
+            A = C = 10.4 / (dx * dx + dy * dy)
+            B = 0.0
+        power = -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy
+        assert power == pytest.approx(-5.2, rel=1e-12)
+        rec["mx"], rec["my"] = 32.5 + dx, 32.5 + dy
+        rec["A"], rec["B"], rec["C"] = A, B, C
+        rec["sig"] = target / np.exp(power)
+        rec["x0"], rec["x1"], rec["y0"], rec["y1"] = 0, 63, 0, 63
+        for widen in (False, True):
+            opts = O.make_opts(16, eps_alpha_mag=16 * 2.0 ** -24 if widen else 0.0)
+            r = O.render_view(rec, cam, opts, sc.channels, f["ids"], f["ranges"], 0, pix=[lin])
+            got[(name, widen)] = int(r["n_amb"][0])
+            assert r["out"][0, 0] == 0.0 and r["T"][0] == 1.0
+    assert got == {("needle", False): 0, ("needle", True): 1, ("round", False): 0, ("round", True): 0}
+
+
 # ------------------------------------------------------------------ backward
 
 def _group_err(an, ref, floor):
