@@ -415,12 +415,12 @@ def coarse_entries(proj, tile, sx=8, sy=4):
 
 class StepRunner:
     """Buffers and the captured HIP graph of one forward + backward step
-    (project -> bin/sort -> blend forward -> gradient clear -> blend backward
-    -> project backward) for a scene and a camera rig, inputs resident in HBM.
-    Every kernel of the step is the library's (the gradient buffers are
-    cleared by legs_clear)."""
+    (project -> bin/sort -> blend forward -> blend backward -> project
+    backward) for a scene and a camera rig, inputs resident in HBM. Every
+    kernel of the step is the library's; the blend forward also zeroes the
+    gradient buffers the backward accumulates into (legs_render_forward_zero)."""
 
-    STAGES = ("project", "bin_sort", "blend_fwd", "zero", "blend_bwd", "project_bwd")
+    STAGES = ("project", "bin_sort", "blend_fwd", "blend_bwd", "project_bwd")
 
     def __init__(self, R, scene, cams, o, G, dev):
         import torch
@@ -442,7 +442,7 @@ class StepRunner:
         self.T = torch.empty(views.total_pixels, dtype=torch.float32, device=dev)
         self.last = torch.empty(views.total_pixels, dtype=torch.int32, device=dev)
         self.G = G
-        # every gradient buffer is a slice of one flat allocation, cleared by one fill per step
+        # every gradient buffer is a slice of one flat allocation, zeroed by the forward launch
         gshapes = {"grad2d": (n * views.n_views, 8), "d_ch": (n, C)}
         gshapes.update({k: tuple(self.d[k].shape) for k in ("mean", "log_scale", "quat", "opacity_logit")})
         self.gflat = torch.zeros(sum(int(np.prod(sh)) for sh in gshapes.values()), dtype=torch.float32, device=dev)
@@ -463,17 +463,16 @@ class StepRunner:
         mark(1)
         R.bin_sort(ctx, self.proj, views, o, self.bins, sync_count=False)
         mark(2)
-        R.render_forward(ctx, self.proj, self.bins, views, d["channels"], o, self.out, self.T, self.last)
+        R.render_forward(ctx, self.proj, self.bins, views, d["channels"], o, self.out, self.T, self.last,
+                         zero=self.gflat)
         mark(3)
-        R.clear(ctx, self.gflat)
-        mark(4)
         R.render_backward(ctx, self.proj, self.bins, views, d["channels"], o, self.T, self.last, self.G,
                           self.gv["grad2d"], self.gv["d_ch"])
-        mark(5)
+        mark(4)
         grads = {k: self.gv[k] for k in ("mean", "log_scale", "quat", "opacity_logit")}
         R.project_backward(ctx, d["mean"], d["log_scale"], d["quat"], d["opacity_logit"], views, o, self.proj,
                            self.gv["grad2d"], grads)
-        mark(6)
+        mark(5)
 
     def time_eager(self, steps, warmup):
         import torch
@@ -481,14 +480,14 @@ class StepRunner:
             self.step()
         torch.cuda.synchronize()
         assert int(self.bins.count.item()) <= self.bins.capacity, "instance list overflowed"
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(steps)]
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(steps):
             self.step(evs[k])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        per_step = np.array([evs[k][0].elapsed_time(evs[k][6]) for k in range(steps)])
+        per_step = np.array([evs[k][0].elapsed_time(evs[k][5]) for k in range(steps)])
         stage_ms = {s_: float(np.median([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
                     for i, s_ in enumerate(self.STAGES)}
         return float(np.median(per_step)), stage_ms, wall

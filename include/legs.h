@@ -210,6 +210,20 @@ int32_t legs_render_forward(legs_ctx *ctx, const legs_projected *proj, int64_t n
                             const legs_opts *opts, float *out, float *T_final, uint32_t *last,
                             void *stream);
 
+/* legs_render_forward that also sets the zero_bytes bytes at zero (device
+ * memory, 16-byte aligned, zero_bytes a multiple of 4) to 0 in the same
+ * launch: each workgroup stores its share before compositing, so the stores
+ * drain while the ALU-bound compositing runs instead of costing a launch and
+ * a pass of their own. Meant for the gradient buffers that the following
+ * legs_render_backward and legs_project_backward accumulate into; the range
+ * must not overlap any buffer the compositing reads or writes (the result is
+ * then undefined). LEGS_ERR_ARG for a misaligned pointer or a bad size. */
+int32_t legs_render_forward_zero(legs_ctx *ctx, const legs_projected *proj, int64_t n,
+                                 const legs_bins *bins, const legs_view *views_dev, int32_t n_views,
+                                 int64_t total_tiles, const float *channels, int32_t C,
+                                 const legs_opts *opts, float *out, float *T_final, uint32_t *last,
+                                 void *zero, int64_t zero_bytes, void *stream);
+
 /* Gradient of a loss with dL/d(out) = d_out (planar like out) through the
  * compositing, replaying each pixel back to front from (T_final, last).
  * Accumulates (+=) into grad2d [G][8] = d(mx, my, A, B, C, opacity, -, -)

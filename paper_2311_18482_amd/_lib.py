@@ -87,6 +87,8 @@ _SIGS = {
                             ct.POINTER(Bins), ct.POINTER(I64), P]),
     "legs_render_forward": (I32, [P, ct.POINTER(Projected), I64, ct.POINTER(Bins), P, I32, I64, P,
                                   I32, ct.POINTER(Opts), P, P, P, P]),
+    "legs_render_forward_zero": (I32, [P, ct.POINTER(Projected), I64, ct.POINTER(Bins), P, I32, I64, P,
+                                       I32, ct.POINTER(Opts), P, P, P, P, I64, P]),
     "legs_render_backward": (I32, [P, ct.POINTER(Projected), I64, ct.POINTER(Bins), P, I32, I64,
                                    P, I32, ct.POINTER(Opts), P, P, P, P, P, P]),
     "legs_render_counts": (I32, [P, ct.POINTER(Projected), I64, ct.POINTER(Bins), P, I32, I64,

@@ -256,7 +256,32 @@ int32_t legs_render_forward(legs_ctx *ctx, const legs_projected *proj, int64_t n
     LEGS_TRY(check_views(ctx, views_dev, n_views));
     LEGS_TRY(use_device(ctx));
     return legs_launch_blend_forward(ctx, proj, n, bins, views_dev, n_views, total_tiles, channels,
-                                     C, opts, out, T_final, last, (hipStream_t)stream);
+                                     C, opts, out, T_final, last, nullptr, 0, (hipStream_t)stream);
+}
+
+int32_t legs_render_forward_zero(legs_ctx *ctx, const legs_projected *proj, int64_t n,
+                                 const legs_bins *bins, const legs_view *views_dev, int32_t n_views,
+                                 int64_t total_tiles, const float *channels, int32_t C,
+                                 const legs_opts *opts, float *out, float *T_final, uint32_t *last,
+                                 void *zero, int64_t zero_bytes, void *stream)
+{
+    if (!ctx) return LEGS_ERR_ARG;
+    if (!proj_ok(proj) || !bins_ok(bins)) return legs_set_error(ctx, LEGS_ERR_ARG, "incomplete buffers");
+    if (C < 1 || C > LEGS_MAX_CHANNELS) return legs_set_error(ctx, LEGS_ERR_ARG, "C out of range");
+    if ((n > 0 && !channels) || !out || !T_final || !last)
+        return legs_set_error(ctx, LEGS_ERR_ARG, "NULL output or channels");
+    if (total_tiles < 1 || total_tiles >= (1ll << 32))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "total_tiles out of range");
+    if (zero_bytes < 0 || zero_bytes % 4 != 0 || (zero_bytes > 0 && !zero) ||
+        (reinterpret_cast<uintptr_t>(zero) & 15) != 0)
+        return legs_set_error(ctx, LEGS_ERR_ARG,
+                              "legs_render_forward_zero: zero must be 16-byte aligned and zero_bytes a "
+                              "non-negative multiple of 4");
+    LEGS_TRY(check_opts(ctx, opts));
+    LEGS_TRY(check_views(ctx, views_dev, n_views));
+    LEGS_TRY(use_device(ctx));
+    return legs_launch_blend_forward(ctx, proj, n, bins, views_dev, n_views, total_tiles, channels,
+                                     C, opts, out, T_final, last, zero, zero_bytes, (hipStream_t)stream);
 }
 
 int32_t legs_render_backward(legs_ctx *ctx, const legs_projected *proj, int64_t n,

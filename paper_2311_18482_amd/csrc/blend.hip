@@ -52,6 +52,9 @@ struct BlendParams {
     bool reach;         // skip the pixels outside the reach of alpha_min (reach_box)
     uint32_t *counter;  // non-NULL: persistent launch, tiles taken from this counter
     const uint32_t *order;  // persistent launch: the tiles in decreasing order of list length
+    float4 *zero4;      // forward: zero_n4 float4 and then zero_tail floats to set to 0 (NULL: none)
+    int64_t zero_n4;
+    int zero_tail;
 };
 
 // The conic (A, B, C) is staged scaled by (-log2(e)/2, -log2(e), -log2(e)/2),
@@ -342,6 +345,15 @@ k_blend_fwd(BlendParams P, float *__restrict__ out, float *__restrict__ Tf,
     const int B = P.batch;
     const float amax = P.amax;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / LEGS_WAVE), l = threadIdx.x % LEGS_WAVE;
+    if (P.zero4) {
+        // the zeroing asked for with the compositing: each workgroup stores its
+        // grid-stride share before its first item (the stores drain while the
+        // ALU-bound compositing runs)
+        for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < P.zero_n4; i += (int64_t)gridDim.x * NT)
+            P.zero4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (blockIdx.x == 0 && (int)threadIdx.x < P.zero_tail)
+            reinterpret_cast<float *>(P.zero4 + P.zero_n4)[threadIdx.x] = 0.0f;
+    }
     const float fx = (float)(l & 7), fy = (float)(l >> 3);
     // work items: (tile, part) pairs, the parts of a tile consecutive; one
     // item per workgroup, or the persistent queue (heaviest tiles first)
@@ -805,6 +817,9 @@ BlendParams make_params(const legs_projected *proj, int64_t n, const legs_bins *
     BlendParams P;
     P.counter = nullptr;
     P.order = nullptr;
+    P.zero4 = nullptr;
+    P.zero_n4 = 0;
+    P.zero_tail = 0;
     if (o->flags & LEGS_FLAG_PERSISTENT) {
         const legs_sort_layout Ls = legs_sort_layout_for(bins->capacity, total_tiles);
         P.counter = reinterpret_cast<uint32_t *>(static_cast<char *>(bins->scratch) + Ls.counter_off) + slot;
@@ -837,10 +852,16 @@ int32_t legs_launch_blend_forward(legs_ctx *ctx, const legs_projected *proj, int
                                   const legs_bins *bins, const legs_view *views, int32_t n_views,
                                   int64_t total_tiles, const float *channels, int32_t C,
                                   const legs_opts *o, float *out, float *T_final, uint32_t *last,
-                                  hipStream_t s)
+                                  void *zero, int64_t zero_bytes, hipStream_t s)
 {
-    const BlendParams P = make_params(proj, n, bins, views, n_views, total_tiles, channels, C, o,
-                                      LEGS_BLEND_COUNTER_FWD);
+    BlendParams P = make_params(proj, n, bins, views, n_views, total_tiles, channels, C, o,
+                                LEGS_BLEND_COUNTER_FWD);
+    if (zero && zero_bytes >= 4) {
+        const int64_t words = zero_bytes / 4;
+        P.zero4 = static_cast<float4 *>(zero);
+        P.zero_n4 = words / 4;
+        P.zero_tail = (int)(words % 4);
+    }
     return launch(ctx, true, P, out, T_final, last, nullptr, nullptr, nullptr, nullptr, nullptr,
                   o->tile, s);
 }

@@ -62,7 +62,7 @@ int32_t legs_launch_blend_forward(legs_ctx *ctx, const legs_projected *proj, int
                                   const legs_bins *bins, const legs_view *views, int32_t n_views,
                                   int64_t total_tiles, const float *channels, int32_t C,
                                   const legs_opts *o, float *out, float *T_final, uint32_t *last,
-                                  hipStream_t s);
+                                  void *zero, int64_t zero_bytes, hipStream_t s);
 int32_t legs_launch_blend_backward(legs_ctx *ctx, const legs_projected *proj, int64_t n,
                                    const legs_bins *bins, const legs_view *views, int32_t n_views,
                                    int64_t total_tiles, const float *channels, int32_t C,

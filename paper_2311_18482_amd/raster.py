@@ -169,7 +169,9 @@ def bin_sort(ctx: Context, proj: ProjectedBuf, views: Views, o: L.Opts,
 
 
 def render_forward(ctx: Context, proj: ProjectedBuf, bins: BinsBuf, views: Views, channels,
-                   o: L.Opts, out=None, T=None, last=None):
+                   o: L.Opts, out=None, T=None, last=None, zero=None):
+    """legs_render_forward; with zero (a contiguous device tensor), the same
+    launch also sets zero to 0 (legs_render_forward_zero)."""
     assert channels.is_cuda and channels.dtype == torch.float32 and channels.is_contiguous()
     n, C = channels.shape
     device = channels.device
@@ -180,9 +182,16 @@ def render_forward(ctx: Context, proj: ProjectedBuf, bins: BinsBuf, views: Views
     if last is None:
         last = torch.empty(views.total_pixels, dtype=torch.int32, device=device)
     ps, bs = proj.struct(), bins.struct()
-    ctx.check(L.lib().legs_render_forward(ctx.handle, ct.byref(ps), n, ct.byref(bs), _p(views.dev),
-                                          views.n_views, views.total_tiles, _p(channels), C,
-                                          ct.byref(o), _p(out), _p(T), _p(last), _stream()))
+    if zero is None:
+        ctx.check(L.lib().legs_render_forward(ctx.handle, ct.byref(ps), n, ct.byref(bs), _p(views.dev),
+                                              views.n_views, views.total_tiles, _p(channels), C,
+                                              ct.byref(o), _p(out), _p(T), _p(last), _stream()))
+    else:
+        assert zero.is_cuda and zero.is_contiguous()
+        ctx.check(L.lib().legs_render_forward_zero(ctx.handle, ct.byref(ps), n, ct.byref(bs), _p(views.dev),
+                                                   views.n_views, views.total_tiles, _p(channels), C,
+                                                   ct.byref(o), _p(out), _p(T), _p(last), _p(zero),
+                                                   zero.numel() * zero.element_size(), _stream()))
     return out, T, last
 
 

@@ -3,12 +3,13 @@ library's calls (argument marshalling and buffer ownership only; every step
 runs in the HIP kernels behind include/legs.h).
 
   render   project -> bin/sort -> blend forward of every view (Sec. 3.1 Eq. 1,
-           with R_s and R_u of Sec. 3.4)
+           with R_s and R_u of Sec. 3.4); the forward launch also zeroes the
+           gradient buffers (legs_render_forward_zero)
   loss     per view, mean |out - target| over RGB and s_G plus lambda_u times
            the mean rendered uncertainty (the L_u regulariser of Eq. 11),
            and dL/d(out) (legs_l1_loss_grad)
-  backward clear the gradients, blend backward from (T_final, last), projection
-           backward (legs_clear, legs_render_backward, legs_project_backward)
+  backward blend backward from (T_final, last), projection backward
+           (legs_render_backward, legs_project_backward)
   update   one fused Adam launch over means, log-scales, quaternions, opacity
            logits and channels, the uncertainty clamped to [0, 1] (Sec. 4:
            Adam, lr 1e-3, betas (0.9, 0.999); u in [0, 1] of Sec. 3.4.2)
@@ -58,7 +59,7 @@ class TrainStep:
         self.d_out = torch.empty(C * px, dtype=torch.float32, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         G = n * views.n_views
-        # gradients: one allocation (one clear per step)
+        # gradients: one allocation (zeroed once per step by the forward launch)
         sizes = {"grad2d": 8 * G, "channels": n * C, "mean": 3 * n, "log_scale": 3 * n, "quat": 4 * n,
                  "opacity_logit": n}
         self.gflat = torch.zeros(sum(sizes.values()), dtype=torch.float32, device=dev)
@@ -88,9 +89,10 @@ class TrainStep:
         ctx, views, o, p = self.rast.ctx, self.rast.views, self.rast.o, self.p
         R.project(ctx, p["mean"], p["log_scale"], p["quat"], p["opacity_logit"], views, o, out=self.proj)
         R.bin_sort(ctx, self.proj, views, o, self.bins, sync_count=False)
-        R.render_forward(ctx, self.proj, self.bins, views, p["channels"], o, self.out, self.T, self.last)
+        # the forward launch also zeroes the gradients the backward accumulates into
+        R.render_forward(ctx, self.proj, self.bins, views, p["channels"], o, self.out, self.T, self.last,
+                         zero=self.gflat)
         _l1(ctx, self.out, self.target, views, self.C, self.n_fit, self.lambda_u, self.d_out, self.loss)
-        R.clear(ctx, self.gflat)
         R.render_backward(ctx, self.proj, self.bins, views, p["channels"], o, self.T, self.last, self.d_out,
                           self.g["grad2d"], self.g["channels"])
         R.project_backward(ctx, p["mean"], p["log_scale"], p["quat"], p["opacity_logit"], views, o, self.proj,

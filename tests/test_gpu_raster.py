@@ -382,6 +382,32 @@ def test_autograd_function(R):
     PT.compare_grads(got, PT.gpu_grads_to_np(g, d_ch), scene.n, tol=1e-4)
 
 
+@pytest.mark.parametrize("persistent", [False, True])
+def test_forward_zero_matches_and_zeroes(R, persistent):
+    """legs_render_forward_zero composites exactly like legs_render_forward
+    (out, T and last bit-identical, one workgroup per tile and persistent) and
+    sets the whole given range to 0 (a float count that leaves a 3-float tail
+    after the float4 stores), nothing past it; it rejects a misaligned range
+    and a byte count that is not a multiple of 4."""
+    scene, cams = synth.workload_c1()
+    o = R.opts(tile=32, lds_batch=128, persistent=persistent)
+    rast, d, proj, bins, out, T, last = run_forward(R, scene, cams, o)
+    n_zero = 1_000_003
+    buf = torch.full((n_zero + 8,), 7.0, device="cuda")
+    out2, T2, last2 = (torch.full_like(out, -1.0), torch.full_like(T, -1.0), torch.full_like(last, -1))
+    R.render_forward(rast.ctx, proj, bins, rast.views, d["channels"], o, out2, T2, last2, zero=buf[:n_zero])
+    torch.cuda.synchronize()
+    assert torch.equal(out2, out) and torch.equal(T2, T) and torch.equal(last2, last)
+    assert (buf[:n_zero] == 0.0).all() and (buf[n_zero:] == 7.0).all()
+    with pytest.raises(RuntimeError):
+        R.render_forward(rast.ctx, proj, bins, rast.views, d["channels"], o, out2, T2, last2, zero=buf[1:101])
+    with pytest.raises(RuntimeError):
+        R.render_forward(rast.ctx, proj, bins, rast.views, d["channels"], o, out2, T2, last2,
+                         zero=buf.view(torch.uint8)[:7])
+    torch.cuda.synchronize()
+    assert (buf[n_zero:] == 7.0).all()
+
+
 def test_persistent_launch_matches(R):
     """One persistent launch over the tiles of several uneven views gives the
     same images, T and last as one workgroup per tile (bit for bit: each pixel
