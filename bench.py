@@ -160,7 +160,19 @@ def decode_leg(log_fn, epochs=200):
           "learned_raw_input": tm(lambda: DEC.decode_mlp(ctx, f_all, tr_raw.params, K, top1=top1, normalize=False)),
           "plain": tm(lambda: DEC.decode_plain(ctx, f_all, Pm, Cb)),
           "folded": tm(lambda: DEC.decode_folded(ctx, f_all, folded, K))}
+    # the full distribution as well (float32 softmax of every class, with the top-1)
+    probs = torch.empty((P, K), dtype=torch.float32, device=dev)
+    lib = __import__("paper_2311_18482_amd._lib", fromlist=["lib"])
+    st = R._stream()
+
+    def learned_probs():
+        ctx.check(lib.lib().legs_decode_mlp(ctx.handle, R._p(fall), P, 1, 8, R._p(tr.params), K,
+                                            lib.LEGS_MLP_NORMALIZE_INPUT, R._p(probs), R._p(top1), st))
+    ms["learned_probs"] = tm(learned_probs)
+    del probs
+    torch.cuda.empty_cache()
     mpx = {k: P / (v * 1e-3) / 1e6 for k, v in ms.items()}
+    probs_bytes = P * (8 * 4 + K * 4 + 4)        # features read, float32 distribution and top-1 written
     return dict(workload="1M Gaussians, 32 views 1920x1080 (C=12, 8-dim semantic maps), codebook "
                          "128 x 512, projection 512 x 8, decoder 8-64-64-128 bf16 on the L2-normalised "
                          "rendered feature (top-1 output)",
@@ -169,7 +181,13 @@ def decode_leg(log_fn, epochs=200):
                 learned_mpx_s=mpx["learned"], learned_raw_input_mpx_s=mpx["learned_raw_input"],
                 plain_mpx_s=mpx["plain"], folded_mpx_s=mpx["folded"],
                 learned_over_plain=mpx["learned"] / mpx["plain"],
-                learned_over_folded=mpx["learned"] / mpx["folded"], ms=ms)
+                learned_over_folded=mpx["learned"] / mpx["folded"],
+                learned_probs_mpx_s=mpx["learned_probs"],
+                learned_probs_roofline=dict(bound="hbm", unit="GB/s", bytes_per_px=8 * 4 + K * 4 + 4,
+                                            achieved=probs_bytes / (ms["learned_probs"] * 1e-3) / 1e9,
+                                            peak=HBM_PEAK_GBS,
+                                            frac=probs_bytes / (ms["learned_probs"] * 1e-3) / 1e9 / HBM_PEAK_GBS),
+                ms=ms)
 
 
 BF16_MFMA_PEAK_TFLOPS = 2500.0    # dense bf16 / fp16 MFMA
@@ -396,12 +414,29 @@ def cpu_baseline(scene, cams, tile):
     finally:
         O.set_threads(nth)
     dt1 = sum(st1.values())
+    # the oracle's decodes (Eq. 4 plain, Eq. 8 learned with the bf16 roundings
+    # emulated; numpy, its BLAS on this host's threads) on a pixel sample
+    from oracle import decode as D
+    npx = 200_000
+    fs = np.random.default_rng(400).normal(0, 1, (npx, 8)).astype(np.float32)
+    Pm, Cb = synth.projection(512, 8, 404), synth.codebook(128, 512, 405)
+    ws, bs = synth.mlp_init((8, 64, 64, 128), 407)
+    t0 = time.perf_counter()
+    D.decode_plain(fs, Pm, Cb)
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    np.argmax(D.mlp_forward(fs, ws, bs)["logits"], axis=1)
+    t_learned = time.perf_counter() - t0
+    decode = dict(sample=f"{npx} pixels of 8-d features, codebook 128 x 512, decoder 8-64-64-128",
+                  plain_mpx_s=npx / t_plain / 1e6, learned_mpx_s=npx / t_learned / 1e6,
+                  plain_s=t_plain, learned_s=t_learned)
     return dict(value=px / dt / 1e6, unit="Mpixels/s", cores=nth, kind="oracle",
                 sample=f"one full forward+backward step of the same workload ({px} px), {dt:.1f} s on {nth} "
                        f"threads",
                 stage_s=st,
                 single_thread=dict(value=px / dt1 / 1e6, unit="Mpixels/s", cores=1,
-                                   sample=f"the same step on one thread, {dt1:.1f} s", stage_s=st1))
+                                   sample=f"the same step on one thread, {dt1:.1f} s", stage_s=st1),
+                decode=decode)
 
 
 def coarse_entries(proj, tile, sx=8, sy=4):

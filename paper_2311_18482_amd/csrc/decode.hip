@@ -47,31 +47,51 @@ __device__ __forceinline__ void argmax_pair(float &best, int &bidx)
     if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
 }
 
+// Staged row of write_softmax: 32 codes of one pixel plus 4 floats of padding
+// (the 16-byte stores of one lane half then fall on distinct banks).
+constexpr int SROW = 36;
+
 // Softmax over the pixel's K scores held as KB blocks of 16 registers in this
-// lane and its partner; writes probs[p][K] (float4 per 4 consecutive codes).
+// lane and its partner (exp taken once per score, in place); writes
+// probs[p][K] for the wave's 32 pixels p0 .. p0 + 31 (those below P). Each
+// block of 32 codes goes through this wave's LDS tile stage[32][SROW] and
+// leaves as runs of 128 contiguous bytes per pixel (8 pixels per store
+// instruction) instead of 32-byte pieces of 32 rows. Called by the whole wave.
 template <int KB>
-__device__ __forceinline__ void write_softmax(const f32x16 (&s)[KB], float mx, int h, int64_t p,
-                                              float *__restrict__ probs)
+__device__ __forceinline__ void write_softmax(f32x16 (&s)[KB], float mx, int h, int64_t p0, int64_t P,
+                                              float *__restrict__ probs, float *stage)
 {
     float sum = 0.0f;
 #pragma unroll
     for (int b = 0; b < KB; ++b)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) sum += __expf(s[b][r] - mx);
+        for (int r = 0; r < 16; ++r) {
+            s[b][r] = __expf(s[b][r] - mx);
+            sum += s[b][r];
+        }
     sum += __shfl_xor(sum, 32, LEGS_WAVE);
     const float inv = 1.0f / sum;
-    float *row = probs + p * (int64_t)(32 * KB);
+    const int lane = legs_lane(), px = lane & 31;
+    const int rr = lane >> 3, c4 = (lane & 7) * 4;      // read-back: row rr + 8 q, codes c4 .. c4 + 3
 #pragma unroll
-    for (int b = 0; b < KB; ++b)
+    for (int b = 0; b < KB; ++b) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            float4 v;
-            v.x = __expf(s[b][4 * j + 0] - mx) * inv;
-            v.y = __expf(s[b][4 * j + 1] - mx) * inv;
-            v.z = __expf(s[b][4 * j + 2] - mx) * inv;
-            v.w = __expf(s[b][4 * j + 3] - mx) * inv;
-            *reinterpret_cast<float4 *>(row + 32 * b + 8 * j + 4 * h) = v;
+        for (int j = 0; j < 4; ++j)
+            *reinterpret_cast<float4 *>(stage + px * SROW + 8 * j + 4 * h) =
+                make_float4(s[b][4 * j] * inv, s[b][4 * j + 1] * inv, s[b][4 * j + 2] * inv, s[b][4 * j + 3] * inv);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = rr + 8 * q;
+            const float4 v = *reinterpret_cast<const float4 *>(stage + row * SROW + c4);
+            if (p0 + row < P) *reinterpret_cast<float4 *>(probs + (p0 + row) * (int64_t)(32 * KB) + 32 * b + c4) = v;
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();   // the tile's reads are done before the next block is staged
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
 }
 
 // ---- plain decode (direct) --------------------------------------------------------
@@ -90,6 +110,7 @@ k_decode_plain(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps
     __shared__ float s_P[LEGS_DECODE_MAXD * LEGS_DECODE_DIN];
     __shared__ float s_cb[K * CPAD];
     __shared__ float s_inv[K];
+    __shared__ __align__(16) float s_stage[NW][32 * SROW];
     const int tid = threadIdx.x, lane = legs_lane(), wave = tid / LEGS_WAVE, h = lane >> 5;
     for (int i = tid; i < D * LEGS_DECODE_DIN; i += PLAIN_THREADS) s_P[i] = proj[i];
     // inverse code norms
@@ -154,10 +175,8 @@ k_decode_plain(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps
                 if (sc > best) { best = sc; bidx = k; }   // k increases along the loop: first wins ties
             }
         argmax_pair(best, bidx);
-        if (valid) {
-            if (h == 0) top1[p] = bidx;
-            if (probs) write_softmax<KB>(S, best, h, p, probs);
-        }
+        if (valid && h == 0) top1[p] = bidx;
+        if (probs) write_softmax<KB>(S, best, h, tile * 32, P, probs, s_stage[wave]);
     }
 }
 
@@ -197,6 +216,7 @@ k_decode_folded(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t p
     constexpr int DI = LEGS_DECODE_DIN;
     __shared__ float s_M[K * DI];
     __shared__ float s_Q[DI * DI];
+    __shared__ __align__(16) float s_stage[4][32 * SROW];
     const int tid = threadIdx.x, lane = legs_lane(), wave = tid / LEGS_WAVE, h = lane >> 5;
     for (int i = tid; i < K * DI; i += 256) s_M[i] = folded[i];
     if (tid < DI * DI) s_Q[tid] = folded[K * DI + tid];
@@ -245,10 +265,8 @@ k_decode_folded(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t p
                 if (sc > best) { best = sc; bidx = k; }   // k increases along the loop: first wins ties
             }
         argmax_pair(best, bidx);
-        if (valid) {
-            if (h == 0) top1[p] = bidx;
-            if (probs) write_softmax<KB>(S, best, h, p, probs);
-        }
+        if (valid && h == 0) top1[p] = bidx;
+        if (probs) write_softmax<KB>(S, best, h, tile * 32, P, probs, s_stage[wave]);
     }
 }
 
@@ -257,12 +275,13 @@ k_decode_folded(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t p
 namespace {
 
 template <int KB, bool NORM>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_decode_mlp(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
              const float *__restrict__ params, float *__restrict__ probs,
              int32_t *__restrict__ top1)
 {
     __shared__ MlpLds L;
+    __shared__ __align__(16) float s_stage[4][32 * SROW];
     mlp_stage_weights<KB>(params, L);
     __syncthreads();
     const int lane = legs_lane(), wave = threadIdx.x / LEGS_WAVE, h = lane >> 5;
@@ -289,10 +308,8 @@ k_decode_mlp(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
             }
         }
         argmax_pair(best, bidx);
-        if (valid) {
-            if (h == 0) top1[p] = bidx;
-            if (probs) write_softmax<KB>(S, best, h, p, probs);
-        }
+        if (valid && h == 0) top1[p] = bidx;
+        if (probs) write_softmax<KB>(S, best, h, tile * 32, P, probs, s_stage[wave]);
     }
 }
 
