@@ -312,7 +312,7 @@ int32_t legs_decode_mlp(legs_ctx *ctx, const float *feat, int64_t P, int64_t c_s
  * rounded to bf16 (nearest even), biases and accumulation are float32.
  * feat is read as in legs_decode_mlp; mlp_flags as there (0 = Eq. 8 as
  * written). Outputs (each nullable, at least one): probs [P][N] float32
- * (16-byte aligned), probs_f16 [P][N] IEEE half (8-byte aligned; the same
+ * (16-byte aligned), probs_f16 [P][N] IEEE half (16-byte aligned; the same
  * probabilities rounded to nearest, the input of legs_language_features),
  * top1 [P] int32 (lowest index on ties). With only top1 requested the kernel
  * never holds all N logits. */

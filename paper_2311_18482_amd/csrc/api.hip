@@ -478,8 +478,8 @@ int32_t legs_decode_dmlp(legs_ctx *ctx, const float *feat, int64_t P, int64_t c_
     if (!params || (P > 0 && !feat)) return legs_set_error(ctx, LEGS_ERR_ARG, "NULL argument");
     if (!probs && !probs_f16 && !top1) return legs_set_error(ctx, LEGS_ERR_ARG, "no output requested");
     if (c_stride < 0 || p_stride < 0) return legs_set_error(ctx, LEGS_ERR_ARG, "negative stride");
-    if ((reinterpret_cast<uintptr_t>(probs) & 15) || (reinterpret_cast<uintptr_t>(probs_f16) & 7))
-        return legs_set_error(ctx, LEGS_ERR_ARG, "probs must be 16-byte and probs_f16 8-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(probs) & 15) || (reinterpret_cast<uintptr_t>(probs_f16) & 15))
+        return legs_set_error(ctx, LEGS_ERR_ARG, "probs and probs_f16 must be 16-byte aligned");
     LEGS_TRY(use_device(ctx));
     return legs_launch_decode_dmlp(ctx, feat, P, c_stride, p_stride, params, N, mlp_flags, probs, probs_f16,
                                    top1, (hipStream_t)stream);

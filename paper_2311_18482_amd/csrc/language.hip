@@ -229,6 +229,21 @@ k_dmlp_top1(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
 // Full distribution: all N logits of NT tiles kept, softmax, then the
 // requested outputs: probs [P][N] float32, probs16 [P][N] float16 (the same
 // float32 probability rounded to nearest), top1 [P].
+// The distribution leaves through a 2.5 KB LDS tile per wave (the weights fill
+// 144 KB): 32 codes x 32 pixels as halves (rows of PROW16), or 16 codes x 32
+// pixels as floats (rows of PROW32), stored back as 64-byte runs per pixel
+// instead of 8- or 16-byte pieces of 32 rows. The rows are padded so that a
+// lane half's stores fall on distinct banks.
+constexpr int PROW16 = 40, PROW32 = 20;   // 80-byte rows either way: 32 x 80 = 2560 bytes per wave
+
+// LDS writes of this wave are done before its reads (and reads before the next writes).
+__device__ __forceinline__ void stage_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int KB, int NT, bool VEC8, bool NORM>
 __global__ void __launch_bounds__(256)
 k_dmlp_probs(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
@@ -237,6 +252,7 @@ k_dmlp_probs(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
 {
     constexpr int N = 32 * KB;
     __shared__ DmlpLds<KB> L;
+    __shared__ __align__(16) float s_stage[4][32 * PROW32];
     dmlp_stage<KB>(params, L);
     __syncthreads();
     const int lane = __lane_id(), wave = threadIdx.x / LEGS_WAVE, h = lane >> 5;
@@ -269,27 +285,58 @@ k_dmlp_probs(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
 #pragma unroll
             for (int b = 0; b < KB; ++b)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) sum += __expf(z[b][t][r] - best);
+                for (int r = 0; r < 16; ++r) {
+                    z[b][t][r] = __expf(z[b][t][r] - best);
+                    sum += z[b][t][r];
+                }
             sum += __shfl_xor(sum, 32, LEGS_WAVE);
             const float inv = 1.0f / sum;
-            if (p >= P) continue;
-            if (top1 && h == 0) top1[p] = bidx;
+            if (top1 && h == 0 && p < P) top1[p] = bidx;
+            const int64_t p0 = (g * NT + t) * 32;
+            float *st = s_stage[wave];
 #pragma unroll
-            for (int b = 0; b < KB; ++b)
+            for (int b = 0; b < KB; ++b) {
+                if (probs16) {
+                    // 32 codes of 32 pixels as halves: rows of PROW16 halves
+                    _Float16 *st16 = reinterpret_cast<_Float16 *>(st);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    float4 v;
-                    v.x = __expf(z[b][t][4 * j + 0] - best) * inv;
-                    v.y = __expf(z[b][t][4 * j + 1] - best) * inv;
-                    v.z = __expf(z[b][t][4 * j + 2] - best) * inv;
-                    v.w = __expf(z[b][t][4 * j + 3] - best) * inv;
-                    const int64_t o = p * N + 32 * b + 8 * j + 4 * h;
-                    if (probs) *reinterpret_cast<float4 *>(probs + o) = v;
-                    if (probs16) {
-                        f16x4 q = {(_Float16)v.x, (_Float16)v.y, (_Float16)v.z, (_Float16)v.w};
-                        *reinterpret_cast<f16x4 *>(probs16 + o) = q;
+                    for (int j = 0; j < 4; ++j) {
+                        const f16x4 q = {(_Float16)(z[b][t][4 * j] * inv), (_Float16)(z[b][t][4 * j + 1] * inv),
+                                         (_Float16)(z[b][t][4 * j + 2] * inv), (_Float16)(z[b][t][4 * j + 3] * inv)};
+                        *reinterpret_cast<f16x4 *>(st16 + (lane & 31) * PROW16 + 8 * j + 4 * h) = q;
+                    }
+                    stage_sync();
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int row = (lane >> 2) + 16 * q, c8 = (lane & 3) * 8;
+                        const f16x8 v = *reinterpret_cast<const f16x8 *>(st16 + row * PROW16 + c8);
+                        if (p0 + row < P) *reinterpret_cast<f16x8 *>(probs16 + (p0 + row) * N + 32 * b + c8) = v;
+                    }
+                    stage_sync();
+                }
+                if (probs) {
+                    // two halves of 16 codes as floats: rows of PROW32 floats
+#pragma unroll
+                    for (int half = 0; half < 2; ++half) {
+#pragma unroll
+                        for (int jj = 0; jj < 2; ++jj) {
+                            const int j = 2 * half + jj;
+                            *reinterpret_cast<float4 *>(st + (lane & 31) * PROW32 + 8 * jj + 4 * h) =
+                                make_float4(z[b][t][4 * j] * inv, z[b][t][4 * j + 1] * inv, z[b][t][4 * j + 2] * inv,
+                                            z[b][t][4 * j + 3] * inv);
+                        }
+                        stage_sync();
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) {
+                            const int row = (lane >> 2) + 16 * q, c4 = (lane & 3) * 4;
+                            const float4 v = *reinterpret_cast<const float4 *>(st + row * PROW32 + c4);
+                            if (p0 + row < P)
+                                *reinterpret_cast<float4 *>(probs + (p0 + row) * N + 32 * b + 16 * half + c4) = v;
+                        }
+                        stage_sync();
                     }
                 }
+            }
         }
     }
 }
