@@ -374,7 +374,10 @@ int32_t legs_quantize(legs_ctx *ctx, const uint16_t *feat, int64_t K, int32_t d,
  * dL_smo/dparams, d_channels [n][C] += dL_smo/ds_G in the s_G columns (u gets
  * no gradient). A Gaussian with s_MLP = s_G adds nothing. workspace:
  * legs_smooth_workspace_bytes(n) bytes (16-byte aligned), which on return
- * holds the bf16 hidden activations (unit-major planes) of the forward pass. */
+ * holds the bf16 hidden activations of the forward pass: with Gp = n rounded
+ * up to a multiple of 64, a 16-row input plane (16 Gp bf16) and then the
+ * planes of h1, h2 and h3 (128 Gp bf16 each), every plane blocked by 64
+ * Gaussians ([Gp / 64][rows][64], zero for the padding Gaussians). */
 int64_t legs_smooth_param_count(void);
 int64_t legs_smooth_workspace_bytes(int64_t n);
 int32_t legs_smooth_loss_grad(legs_ctx *ctx, const float *mean, const float *channels, int32_t C,

@@ -19,11 +19,13 @@
 //  k_smooth_fwd_bwd  per 32-Gaussian tile (two per wave): forward, loss,
 //                    dL/ds_G (accumulated into the channel gradient), and
 //                    dz of every layer; writes the bf16 hidden activations and
-//                    the float32 dz unit-major ([unit][Gaussian], 64- and
-//                    128-byte runs per half wave) into the workspace.
+//                    the float32 dz into the workspace planes, each lane's rows
+//                    transposed across its quad of lanes first so that one
+//                    store covers 4 Gaussians of a unit (8 bytes bf16, 16
+//                    bytes float32).
 //  k_smooth_wgrad    dW_l = sum_g dz_l h_(l-1)^T and db_l = sum_g dz_l: the
 //                    Gaussians are the MFMA contraction, read straight from
-//                    the unit-major planes (8 consecutive Gaussians of one
+//                    the planes (8 consecutive Gaussians of one
 //                    unit = one 16-byte fragment; dz split into two bf16 parts
 //                    as it is loaded); split over Gaussian chunks
 //                    (x) and layers (y), float atomics into the gradient.
@@ -127,6 +129,14 @@ __device__ __forceinline__ void split_bf16x8(const f32x16 &z, int first, bf16x8 
     }
 }
 
+// Workspace planes are blocked by 64 Gaussians: block b holds [rows][64]
+// (rows x 64 Gaussians, unit-major inside the block), so the forward writes
+// and the weight gradient reads whole blocks. Offset of (row, Gaussian g):
+__device__ __forceinline__ int64_t plane_at(int64_t g, int rows, int row)
+{
+    return ((g >> 6) * rows + row) * 64 + (g & 63);
+}
+
 struct SmoothArgs {
     const float *mean, *ch;
     int32_t C, sem, uch;
@@ -134,8 +144,8 @@ struct SmoothArgs {
     const float *params;
     float w_s, inv_n;             // inv_n = lambda_smo / n
     float *d_ch, *loss;
-    __bf16 *X, *H1, *H2, *H3;     // [16][Gp], [128][Gp] x 3
-    float *D1, *D2, *D3, *D4;     // dz: [rows][Gp] float32
+    __bf16 *X, *H1, *H2, *H3;     // 16 and 128 (x 3) rows, blocked (plane_at)
+    float *D1, *D2, *D3, *D4;     // dz: 128 (x 3) and 8 rows float32, blocked
 };
 
 // Hidden-layer step: acc of block mb from B fragments x[NT][KS] and A
@@ -153,9 +163,90 @@ __device__ __forceinline__ void layer_block(const bf16x8 *__restrict__ wA, const
     }
 }
 
-__device__ __forceinline__ void store_plane(__bf16 *__restrict__ plane, int64_t Gp, int unit, int64_t g, __bf16 v)
+__device__ __forceinline__ void store_plane(__bf16 *__restrict__ plane, int rows, int unit, int64_t g, __bf16 v)
 {
-    plane[(int64_t)unit * Gp + g] = v;
+    plane[plane_at(g, rows, unit)] = v;
+}
+
+// Exchanges within each quad of lanes (DPP quad_perm [1,0,3,2] and [2,3,0,1]).
+__device__ __forceinline__ uint32_t quad_xor1(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t quad_xor2(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+}
+
+// The lanes of a quad (i = lane & 3, one Gaussian each) hold 4 rows of a plane
+// as a[0..3]; afterwards lane i holds row i of the quad's Gaussians 0..3.
+// Two rounds: halves across lanes i ^ 2, then single values across i ^ 1.
+__device__ __forceinline__ void quad_transpose32(uint32_t (&a)[4], bool b0, bool b1)
+{
+    uint32_t s0 = b1 ? a[0] : a[2], s1 = b1 ? a[1] : a[3];
+    uint32_t r0 = quad_xor2(s0), r1 = quad_xor2(s1);
+    a[0] = b1 ? r0 : a[0];
+    a[1] = b1 ? r1 : a[1];
+    a[2] = b1 ? a[2] : r0;
+    a[3] = b1 ? a[3] : r1;
+    s0 = b0 ? a[0] : a[1];
+    s1 = b0 ? a[2] : a[3];
+    r0 = quad_xor1(s0);
+    r1 = quad_xor1(s1);
+    a[0] = b0 ? r0 : a[0];
+    a[2] = b0 ? r1 : a[2];
+    a[1] = b0 ? a[1] : r0;
+    a[3] = b0 ? a[3] : r1;
+}
+
+// The same for 4 bf16 rows packed in two words (d0 = rows 0, 1; d1 = rows 2,
+// 3): afterwards d0 = row i of Gaussians 0, 1 and d1 = row i of Gaussians 2, 3.
+// psel picks the halves of the last round: 0x05040100 (own low, partner's low)
+// on even lanes, 0x03020706 (partner's high, own high) on odd ones.
+__device__ __forceinline__ void quad_transpose16(uint32_t &d0, uint32_t &d1, bool b1, uint32_t psel)
+{
+    const uint32_t r = quad_xor2(b1 ? d0 : d1);
+    d0 = b1 ? r : d0;
+    d1 = b1 ? d1 : r;
+    d0 = __builtin_amdgcn_perm(quad_xor1(d0), d0, psel);
+    d1 = __builtin_amdgcn_perm(quad_xor1(d1), d1, psel);
+}
+
+// One k-step of a bf16 activation (units legs_khid(ks, h, 0..7) of this
+// lane's Gaussian, zero for padding Gaussians) into its plane (SH rows):
+// transposed across the quad, lane i writes units khid(ks, h, i) and
+// khid(ks, h, 4 + i) of the quad's 4 Gaussians (from g0), 8 bytes each.
+__device__ __forceinline__ void store_act_quad(__bf16 *__restrict__ plane, int ks, int h, int qi,
+                                               int64_t g0, const bf16x8 &v, bool valid, bool b1, uint32_t psel)
+{
+    typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+    const u32x4 w = __builtin_bit_cast(u32x4, v);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        uint32_t d0 = valid ? w[2 * half] : 0u, d1 = valid ? w[2 * half + 1] : 0u;
+        quad_transpose16(d0, d1, b1, psel);
+        *reinterpret_cast<uint2 *>(plane + plane_at(g0, SH, legs_khid(ks, h, 4 * half + qi))) = make_uint2(d0, d1);
+    }
+}
+
+// Quads 0 .. NQ-1 of an accumulator block (rows 32 mb + 8 q + 4 h + 0..3 of
+// this lane's Gaussian) into a float32 plane of `rows` rows: lane i of each quad
+// writes row 32 mb + 8 q + 4 h + i of the quad's 4 Gaussians, 16 bytes.
+template <int NQ>
+__device__ __forceinline__ void store_dz_quads(float *__restrict__ plane, int rows, int mb, int h, int qi,
+                                               int64_t g0, const f32x16 &z, bool b0, bool b1)
+{
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        uint32_t a[4];
+#pragma unroll
+        // (__builtin_bit_cast of an ext_vector element reads element 0 with this
+        // compiler; __float_as_uint takes the element's value)
+        for (int k = 0; k < 4; ++k) a[k] = __float_as_uint(z[4 * q + k]);
+        quad_transpose32(a, b0, b1);
+        *reinterpret_cast<uint4 *>(plane + plane_at(g0, rows, 32 * mb + 8 * q + 4 * h + qi)) =
+            make_uint4(a[0], a[1], a[2], a[3]);
+    }
 }
 
 __global__ void __launch_bounds__(256)
@@ -165,6 +256,10 @@ k_smooth_fwd_bwd(SmoothArgs A)
     smooth_stage(A.params, L);
     __syncthreads();
     const int lane = __lane_id(), wave = threadIdx.x / LEGS_WAVE, h = lane >> 5;
+    // position in the lane's quad for the transposed plane stores
+    const int qi = lane & 3;
+    const bool qb0 = (lane & 1) != 0, qb1 = (lane & 2) != 0;
+    const uint32_t psel = qb0 ? 0x03020706u : 0x05040100u;
     const int64_t groups = (A.n + 32 * SNT - 1) / (32 * SNT);
     const int64_t stride = (int64_t)gridDim.x * 4;
     float lsum = 0.0f;
@@ -208,7 +303,7 @@ k_smooth_fwd_bwd(SmoothArgs A)
                     __bf16 w = z0;
                     if (r < 9) w = valid[t] ? s[r % 3][r / 3] : z0;
                     else if (r == 9) w = valid[t] ? one : z0;
-                    store_plane(A.X, A.Gp, r, gi[t], w);
+                    store_plane(A.X, 16, r, gi[t], w);
                 }
             }
         }
@@ -246,20 +341,15 @@ k_smooth_fwd_bwd(SmoothArgs A)
         }
         f32x16 s4[SNT];
         layer_block<SK>(L.w4, L.bb4, 0, ln, h3, s4);
-        // hidden activations to the workspace (unit-major)
+        // hidden activations to the workspace, 4 Gaussians per store
 #pragma unroll
         for (int t = 0; t < SNT; ++t) {
-            if (gi[t] >= A.Gp) continue;
 #pragma unroll
-            for (int ks = 0; ks < SK; ++ks)
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int u = legs_khid(ks, h, e);
-                    const __bf16 z0 = (__bf16)0.0f;
-                    store_plane(A.H1, A.Gp, u, gi[t], valid[t] ? h1[t][ks][e] : z0);
-                    store_plane(A.H2, A.Gp, u, gi[t], valid[t] ? h2[t][ks][e] : z0);
-                    store_plane(A.H3, A.Gp, u, gi[t], valid[t] ? h3[t][ks][e] : z0);
-                }
+            for (int ks = 0; ks < SK; ++ks) {
+                store_act_quad(A.H1, ks, h, qi, gi[t] - qi, h1[t][ks], valid[t], qb1, psel);
+                store_act_quad(A.H2, ks, h, qi, gi[t] - qi, h2[t][ks], valid[t], qb1, psel);
+                store_act_quad(A.H3, ks, h, qi, gi[t] - qi, h3[t][ks], valid[t], qb1, psel);
+            }
         }
         // loss and dz4: outputs 4 h + r in registers r = 0..3
         f32x16 dz4[SNT];
@@ -292,18 +382,11 @@ k_smooth_fwd_bwd(SmoothArgs A)
                 drow[r] += -wgt * diff[r] * inv;
             }
         }
-        // backward through the layers: dz_l split into hi and lo bf16 parts
-        auto put_dz = [&](float *plane, int rows, const f32x16 &z, int mb, int t) {
-            if (gi[t] >= A.Gp) return;
+        // backward through the layers: dz_l split into hi and lo bf16 parts.
+        // dz is exactly zero for padding Gaussians (dz4 is, and every lower dz
+        // is a product with it), so the planes hold zeros there.
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int u = 32 * mb + legs_drow(r, h);
-                if (u >= rows) continue;
-                plane[(int64_t)u * A.Gp + gi[t]] = valid[t] ? z[r] : 0.0f;
-            }
-        };
-#pragma unroll
-        for (int t = 0; t < SNT; ++t) put_dz(A.D4, LEGS_SMOOTH_OUT, dz4[t], 0, t);
+        for (int t = 0; t < SNT; ++t) store_dz_quads<1>(A.D4, LEGS_SMOOTH_OUT, 0, h, qi, gi[t] - qi, dz4[t], qb0, qb1);
         // dh3 = W4^T dz4 (one k-step: outputs 0..7 in slots 0..3 of both halves)
         bf16x8 bh[SNT][SK], bl[SNT][SK];
 #pragma unroll
@@ -331,7 +414,7 @@ k_smooth_fwd_bwd(SmoothArgs A)
             for (int t = 0; t < SNT; ++t)
 #pragma unroll
                 for (int mb = 0; mb < SB; ++mb) {
-                    put_dz(plane, SH, dz[t][mb], mb, t);
+                    store_dz_quads<4>(plane, SH, mb, h, qi, gi[t] - qi, dz[t][mb], qb0, qb1);
                     split_bf16x8(dz[t][mb], 0, bh[t][2 * mb], bl[t][2 * mb]);
                     split_bf16x8(dz[t][mb], 8, bh[t][2 * mb + 1], bl[t][2 * mb + 1]);
                 }
@@ -385,10 +468,6 @@ k_smooth_wgrad(SmoothArgs A, float *__restrict__ grad)
     const int mb = wave, m = 32 * mb + (lane & 31);
     const int64_t g0 = (int64_t)blockIdx.x * WG_CHUNK_G;
     const int64_t g1 = min(g0 + (int64_t)WG_CHUNK_G, A.Gp);
-    const float *Drow = Dp + (int64_t)m * A.Gp + 8 * h;
-    const __bf16 *Bq[4];
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb) Bq[nb] = Bp + (int64_t)(32 * nb + (lane & 31)) * A.Gp + 8 * h;
     const bool mrow = m < M;
     bool krow[4];
 #pragma unroll
@@ -399,8 +478,9 @@ k_smooth_wgrad(SmoothArgs A, float *__restrict__ grad)
     for (int64_t g = g0; g < g1; g += 16) {
         bf16x8 ah = {}, al = {}, b[4];
         if (mrow) {                 // dz as hi + lo bf16 parts (16 significant bits)
-            const float4 v0 = *reinterpret_cast<const float4 *>(Drow + g);
-            const float4 v1 = *reinterpret_cast<const float4 *>(Drow + g + 4);
+            const float *Drow = Dp + plane_at(g, M, m) + 8 * h;
+            const float4 v0 = *reinterpret_cast<const float4 *>(Drow);
+            const float4 v1 = *reinterpret_cast<const float4 *>(Drow + 4);
             const float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -409,7 +489,9 @@ k_smooth_wgrad(SmoothArgs A, float *__restrict__ grad)
             }
         }
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) b[nb] = krow[nb] ? *reinterpret_cast<const bf16x8 *>(Bq[nb] + g) : (bf16x8){};
+        for (int nb = 0; nb < 4; ++nb)
+            b[nb] = krow[nb] ? *reinterpret_cast<const bf16x8 *>(Bp + plane_at(g, Kb, 32 * nb + (lane & 31)) + 8 * h)
+                             : (bf16x8){};
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb)
             if (nb < NB) acc[nb] = legs_mfma(al, b[nb], legs_mfma(ah, b[nb], acc[nb]));

@@ -34,12 +34,15 @@ def ctx():
 
 
 def planes(ws, n, Gp):
-    """The bf16 hidden activations h1, h2, h3 from the workspace ([unit][Gp] each after the 16-row input plane)."""
+    """The bf16 hidden activations h1, h2, h3 from the workspace: after the
+    16-row input plane, three 128-row planes, each blocked by 64 Gaussians
+    ([Gp / 64][128 units][64 Gaussians]). Returned [n][128] each."""
     b = ws.view(torch.bfloat16)
     out = []
     for k in range(3):
         off = 16 * Gp + k * 128 * Gp
-        out.append(b[off:off + 128 * Gp].view(128, Gp)[:, :n].t().float().cpu().numpy().astype(np.float64))
+        blk = b[off:off + 128 * Gp].view(Gp // 64, 128, 64)
+        out.append(blk.permute(0, 2, 1).reshape(Gp, 128)[:n].float().cpu().numpy().astype(np.float64))
     return out
 
 
