@@ -19,16 +19,15 @@
 //  k_smooth_fwd_bwd  per 32-Gaussian tile (two per wave): forward, loss,
 //                    dL/ds_G (accumulated into the channel gradient), and
 //                    dz of every layer; writes the bf16 hidden activations and
-//                    the float32 dz into the workspace planes, each lane's rows
-//                    transposed across its quad of lanes first so that one
-//                    store covers 4 Gaussians of a unit (8 bytes bf16, 16
-//                    bytes float32).
+//                    dz (as its two bf16 parts) into the workspace planes in
+//                    the weight gradient's operand order, each lane's 8 rows
+//                    transposed across its group of 8 lanes first so that one
+//                    16-byte store is one operand fragment.
 //  k_smooth_wgrad    dW_l = sum_g dz_l h_(l-1)^T and db_l = sum_g dz_l: the
-//                    Gaussians are the MFMA contraction, read straight from
-//                    the planes (8 consecutive Gaussians of one
-//                    unit = one 16-byte fragment; dz split into two bf16 parts
-//                    as it is loaded); split over Gaussian chunks
-//                    (x) and layers (y), float atomics into the gradient.
+//                    Gaussians are the MFMA contraction, each operand one
+//                    16-byte load (a wave's load of a 128-row plane is 1 KB
+//                    contiguous); split over Gaussian chunks (x) and layers
+//                    (y), float atomics into the gradient.
 #include "legs_internal.h"
 #include "legs_decode_internal.h"
 
@@ -129,12 +128,17 @@ __device__ __forceinline__ void split_bf16x8(const f32x16 &z, int first, bf16x8 
     }
 }
 
-// Workspace planes are blocked by 64 Gaussians: block b holds [rows][64]
-// (rows x 64 Gaussians, unit-major inside the block), so the forward writes
-// and the weight gradient reads whole blocks. Offset of (row, Gaussian g):
-__device__ __forceinline__ int64_t plane_at(int64_t g, int rows, int row)
+// Workspace planes are kept in the operand order of the weight-gradient
+// MFMAs: Gaussians in steps of 16, rows in blocks of RW = min(R, 32) (R = 8,
+// 16 or a multiple of 32); in the chunk of (step, block), slot
+// j = row % 32 + RW ((g % 16) / 8) holds Gaussians 16 step + 8 ((g % 16) / 8)
+// .. + 7 of that row, 16 bytes, which is what lane j of a 32 x 32 x 16 MFMA
+// takes. A 128-row chunk is 64 slots in lane order (1 KB). Element offset of
+// the fragment of (row, Gaussians g .. g + 7), g a multiple of 8:
+__device__ __forceinline__ int64_t frag_at(int64_t g, int R, int row)
 {
-    return ((g >> 6) * rows + row) * 64 + (g & 63);
+    const int RW = R < 32 ? R : 32, RB = (R + 31) / 32;
+    return ((((g >> 4) * RB + row / 32) * (2 * RW)) + row % 32 + RW * ((g >> 3) & 1)) * 8;
 }
 
 struct SmoothArgs {
@@ -144,8 +148,8 @@ struct SmoothArgs {
     const float *params;
     float w_s, inv_n;             // inv_n = lambda_smo / n
     float *d_ch, *loss;
-    __bf16 *X, *H1, *H2, *H3;     // 16 and 128 (x 3) rows, blocked (plane_at)
-    float *D1, *D2, *D3, *D4;     // dz: 128 (x 3) and 8 rows float32, blocked
+    __bf16 *X, *H1, *H2, *H3;     // 16 and 128 (x 3) rows, fragment order (frag_at)
+    __bf16 *D1, *D2, *D3, *D4;    // dz: hi plane then lo plane, 128 (x 3) and 8 rows
 };
 
 // Hidden-layer step: acc of block mb from B fragments x[NT][KS] and A
@@ -163,90 +167,55 @@ __device__ __forceinline__ void layer_block(const bf16x8 *__restrict__ wA, const
     }
 }
 
-__device__ __forceinline__ void store_plane(__bf16 *__restrict__ plane, int rows, int unit, int64_t g, __bf16 v)
+// DPP moves: lanes enabled by BANK (banks of 4 lanes in each row of 16)
+// read src from the lane CTRL names, the others keep old.
+template <int CTRL, int BANK>
+__device__ __forceinline__ uint32_t dpp_move(uint32_t old, uint32_t src)
 {
-    plane[plane_at(g, rows, unit)] = v;
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, CTRL, 0xF, BANK, false);
 }
 
-// Exchanges within each quad of lanes (DPP quad_perm [1,0,3,2] and [2,3,0,1]).
-__device__ __forceinline__ uint32_t quad_xor1(uint32_t v)
+// 8 x 8 transpose of bf16 values across each group of 8 lanes (i = lane & 7):
+// lane i holds 8 values of one row, element e in half e % 2 of word e / 2;
+// afterwards lane i holds element i of the 8 lanes' rows, in lane order.
+// Three rounds, each keeping one half of the current chunk size and taking
+// the partner's other half: words 0-1 / 2-3 across lanes i ^ 4 (DPP row
+// shifts by 4 into the banks that need them), words across i ^ 2, halves of
+// each word across i ^ 1 (v_perm with psel = 0x05040100 on even lanes: own
+// low, partner's low; 0x03020706 on odd lanes: partner's high, own high).
+__device__ __forceinline__ void oct_transpose(uint32_t (&w)[4], bool b1, uint32_t psel)
 {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
-}
-__device__ __forceinline__ uint32_t quad_xor2(uint32_t v)
-{
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
-}
-
-// The lanes of a quad (i = lane & 3, one Gaussian each) hold 4 rows of a plane
-// as a[0..3]; afterwards lane i holds row i of the quad's Gaussians 0..3.
-// Two rounds: halves across lanes i ^ 2, then single values across i ^ 1.
-__device__ __forceinline__ void quad_transpose32(uint32_t (&a)[4], bool b0, bool b1)
-{
-    uint32_t s0 = b1 ? a[0] : a[2], s1 = b1 ? a[1] : a[3];
-    uint32_t r0 = quad_xor2(s0), r1 = quad_xor2(s1);
-    a[0] = b1 ? r0 : a[0];
-    a[1] = b1 ? r1 : a[1];
-    a[2] = b1 ? a[2] : r0;
-    a[3] = b1 ? a[3] : r1;
-    s0 = b0 ? a[0] : a[1];
-    s1 = b0 ? a[2] : a[3];
-    r0 = quad_xor1(s0);
-    r1 = quad_xor1(s1);
-    a[0] = b0 ? r0 : a[0];
-    a[2] = b0 ? r1 : a[2];
-    a[1] = b0 ? a[1] : r0;
-    a[3] = b0 ? a[3] : r1;
+    const uint32_t n0 = dpp_move<0x114, 0xA>(w[0], w[2]);   // lanes 4-7: lane i - 4's words 2, 3
+    const uint32_t n1 = dpp_move<0x114, 0xA>(w[1], w[3]);
+    const uint32_t n2 = dpp_move<0x104, 0x5>(w[2], w[0]);   // lanes 0-3: lane i + 4's words 0, 1
+    const uint32_t n3 = dpp_move<0x104, 0x5>(w[3], w[1]);
+    // every exchange runs on all lanes before the selects: a DPP move inside
+    // one arm of a conditional would run under a partial exec mask and read
+    // lanes that are switched off
+    const uint32_t p0 = dpp_move<0x4E, 0xF>(0u, n0), p1 = dpp_move<0x4E, 0xF>(0u, n1);
+    const uint32_t p2 = dpp_move<0x4E, 0xF>(0u, n2), p3 = dpp_move<0x4E, 0xF>(0u, n3);
+    w[0] = b1 ? p1 : n0;
+    w[1] = b1 ? n1 : p0;
+    w[2] = b1 ? p3 : n2;
+    w[3] = b1 ? n3 : p2;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = __builtin_amdgcn_perm(dpp_move<0xB1, 0xF>(0u, w[k]), w[k], psel);
 }
 
-// The same for 4 bf16 rows packed in two words (d0 = rows 0, 1; d1 = rows 2,
-// 3): afterwards d0 = row i of Gaussians 0, 1 and d1 = row i of Gaussians 2, 3.
-// psel picks the halves of the last round: 0x05040100 (own low, partner's low)
-// on even lanes, 0x03020706 (partner's high, own high) on odd ones.
-__device__ __forceinline__ void quad_transpose16(uint32_t &d0, uint32_t &d1, bool b1, uint32_t psel)
-{
-    const uint32_t r = quad_xor2(b1 ? d0 : d1);
-    d0 = b1 ? r : d0;
-    d1 = b1 ? d1 : r;
-    d0 = __builtin_amdgcn_perm(quad_xor1(d0), d0, psel);
-    d1 = __builtin_amdgcn_perm(quad_xor1(d1), d1, psel);
-}
-
-// One k-step of a bf16 activation (units legs_khid(ks, h, 0..7) of this
-// lane's Gaussian, zero for padding Gaussians) into its plane (SH rows):
-// transposed across the quad, lane i writes units khid(ks, h, i) and
-// khid(ks, h, 4 + i) of the quad's 4 Gaussians (from g0), 8 bytes each.
-__device__ __forceinline__ void store_act_quad(__bf16 *__restrict__ plane, int ks, int h, int qi,
-                                               int64_t g0, const bf16x8 &v, bool valid, bool b1, uint32_t psel)
+// Eight rows (row(e), e = 0..7) of this lane's Gaussian into a plane of R
+// rows in fragment order: transposed across the lane's group of 8 (Gaussians
+// g0 .. g0 + 7), lane i stores row(i) of those Gaussians, one 16-byte
+// fragment; rows at or past R are not stored.
+template <typename RowOf>
+__device__ __forceinline__ void store_rows8(__bf16 *__restrict__ plane, int R, int64_t g0, bf16x8 v, RowOf row_of,
+                                            int i8, bool b1, uint32_t psel)
 {
     typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
-    const u32x4 w = __builtin_bit_cast(u32x4, v);
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        uint32_t d0 = valid ? w[2 * half] : 0u, d1 = valid ? w[2 * half + 1] : 0u;
-        quad_transpose16(d0, d1, b1, psel);
-        *reinterpret_cast<uint2 *>(plane + plane_at(g0, SH, legs_khid(ks, h, 4 * half + qi))) = make_uint2(d0, d1);
-    }
-}
-
-// Quads 0 .. NQ-1 of an accumulator block (rows 32 mb + 8 q + 4 h + 0..3 of
-// this lane's Gaussian) into a float32 plane of `rows` rows: lane i of each quad
-// writes row 32 mb + 8 q + 4 h + i of the quad's 4 Gaussians, 16 bytes.
-template <int NQ>
-__device__ __forceinline__ void store_dz_quads(float *__restrict__ plane, int rows, int mb, int h, int qi,
-                                               int64_t g0, const f32x16 &z, bool b0, bool b1)
-{
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        uint32_t a[4];
-#pragma unroll
-        // (__builtin_bit_cast of an ext_vector element reads element 0 with this
-        // compiler; __float_as_uint takes the element's value)
-        for (int k = 0; k < 4; ++k) a[k] = __float_as_uint(z[4 * q + k]);
-        quad_transpose32(a, b0, b1);
-        *reinterpret_cast<uint4 *>(plane + plane_at(g0, rows, 32 * mb + 8 * q + 4 * h + qi)) =
-            make_uint4(a[0], a[1], a[2], a[3]);
-    }
+    const u32x4 x = __builtin_bit_cast(u32x4, v);
+    uint32_t w[4] = {x[0], x[1], x[2], x[3]};
+    oct_transpose(w, b1, psel);
+    const int row = row_of(i8);
+    if (row < R) *reinterpret_cast<uint4 *>(plane + frag_at(g0, R, row)) = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
 __global__ void __launch_bounds__(256)
@@ -256,10 +225,10 @@ k_smooth_fwd_bwd(SmoothArgs A)
     smooth_stage(A.params, L);
     __syncthreads();
     const int lane = __lane_id(), wave = threadIdx.x / LEGS_WAVE, h = lane >> 5;
-    // position in the lane's quad for the transposed plane stores
-    const int qi = lane & 3;
-    const bool qb0 = (lane & 1) != 0, qb1 = (lane & 2) != 0;
-    const uint32_t psel = qb0 ? 0x03020706u : 0x05040100u;
+    // position in the lane's group of 8 for the transposed plane stores
+    const int i8 = lane & 7;
+    const bool b1 = (lane & 2) != 0;
+    const uint32_t psel = (lane & 1) ? 0x03020706u : 0x05040100u;
     const int64_t groups = (A.n + 32 * SNT - 1) / (32 * SNT);
     const int64_t stride = (int64_t)gridDim.x * 4;
     float lsum = 0.0f;
@@ -295,17 +264,13 @@ k_smooth_fwd_bwd(SmoothArgs A)
             }
             x[t][0] = v;
             // layer-1 input plane for the weight gradient: rows 0..8 the split
-            // coordinates (part-major), row 9 ones, rows 10..15 zero
-            if (h == 0 && gi[t] < A.Gp) {
-                const __bf16 z0 = (__bf16)0.0f, one = (__bf16)1.0f;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    __bf16 w = z0;
-                    if (r < 9) w = valid[t] ? s[r % 3][r / 3] : z0;
-                    else if (r == 9) w = valid[t] ? one : z0;
-                    store_plane(A.X, 16, r, gi[t], w);
-                }
+            // coordinates (part-major), row 9 ones (zero for padding
+            // Gaussians), rows 10..15 zero; lane half h holds rows 8 h .. 8 h + 7
+            if (h == 1) {
+                v[1] = valid[t] ? (__bf16)1.0f : (__bf16)0.0f;
+                v[2] = v[3] = (__bf16)0.0f;
             }
+            store_rows8(A.X, 16, gi[t] - i8, v, [h](int i) { return 8 * h + i; }, i8, b1, psel);
         }
         // forward
         bf16x8 h1[SNT][SK], h2[SNT][SK], h3[SNT][SK];
@@ -341,14 +306,16 @@ k_smooth_fwd_bwd(SmoothArgs A)
         }
         f32x16 s4[SNT];
         layer_block<SK>(L.w4, L.bb4, 0, ln, h3, s4);
-        // hidden activations to the workspace, 4 Gaussians per store
+        // hidden activations to the workspace (zero for padding Gaussians)
 #pragma unroll
         for (int t = 0; t < SNT; ++t) {
 #pragma unroll
             for (int ks = 0; ks < SK; ++ks) {
-                store_act_quad(A.H1, ks, h, qi, gi[t] - qi, h1[t][ks], valid[t], qb1, psel);
-                store_act_quad(A.H2, ks, h, qi, gi[t] - qi, h2[t][ks], valid[t], qb1, psel);
-                store_act_quad(A.H3, ks, h, qi, gi[t] - qi, h3[t][ks], valid[t], qb1, psel);
+                const auto unit = [ks, h](int i) { return legs_khid(ks, h, i); };
+                const bf16x8 z8 = {};
+                store_rows8(A.H1, SH, gi[t] - i8, valid[t] ? h1[t][ks] : z8, unit, i8, b1, psel);
+                store_rows8(A.H2, SH, gi[t] - i8, valid[t] ? h2[t][ks] : z8, unit, i8, b1, psel);
+                store_rows8(A.H3, SH, gi[t] - i8, valid[t] ? h3[t][ks] : z8, unit, i8, b1, psel);
             }
         }
         // loss and dz4: outputs 4 h + r in registers r = 0..3
@@ -382,15 +349,19 @@ k_smooth_fwd_bwd(SmoothArgs A)
                 drow[r] += -wgt * diff[r] * inv;
             }
         }
-        // backward through the layers: dz_l split into hi and lo bf16 parts.
-        // dz is exactly zero for padding Gaussians (dz4 is, and every lower dz
-        // is a product with it), so the planes hold zeros there.
-#pragma unroll
-        for (int t = 0; t < SNT; ++t) store_dz_quads<1>(A.D4, LEGS_SMOOTH_OUT, 0, h, qi, gi[t] - qi, dz4[t], qb0, qb1);
+        // backward through the layers: dz_l split into hi and lo bf16 parts,
+        // which are also what the planes keep (hi plane, then lo plane). dz is
+        // exactly zero for padding Gaussians (dz4 is, and every lower dz is a
+        // product with it), so the planes hold zeros there.
         // dh3 = W4^T dz4 (one k-step: outputs 0..7 in slots 0..3 of both halves)
         bf16x8 bh[SNT][SK], bl[SNT][SK];
 #pragma unroll
-        for (int t = 0; t < SNT; ++t) split_bf16x8(dz4[t], 0, bh[t][0], bl[t][0]);
+        for (int t = 0; t < SNT; ++t) {
+            split_bf16x8(dz4[t], 0, bh[t][0], bl[t][0]);
+            const auto out = [h](int i) { return legs_khid(0, h, i); };   // outputs 4 h + i for i < 4
+            store_rows8(A.D4, LEGS_SMOOTH_OUT, gi[t] - i8, bh[t][0], out, i8, b1, psel);
+            store_rows8(A.D4 + LEGS_SMOOTH_OUT * A.Gp, LEGS_SMOOTH_OUT, gi[t] - i8, bl[t][0], out, i8, b1, psel);
+        }
         f32x16 dz[SNT][SB];
 #pragma unroll
         for (int mb = 0; mb < SB; ++mb) {
@@ -409,14 +380,20 @@ k_smooth_fwd_bwd(SmoothArgs A)
                     for (int r = 0; r < 16; ++r)
                         if (!((float)hf[t][2 * mb + (r >> 3)][r & 7] > 0.0f)) dz[t][mb][r] = 0.0f;
         };
-        auto back = [&](const bf16x8 *__restrict__ T, float *plane) {
+        auto back = [&](const bf16x8 *__restrict__ T, __bf16 *plane) {
 #pragma unroll
             for (int t = 0; t < SNT; ++t)
 #pragma unroll
                 for (int mb = 0; mb < SB; ++mb) {
-                    store_dz_quads<4>(plane, SH, mb, h, qi, gi[t] - qi, dz[t][mb], qb0, qb1);
                     split_bf16x8(dz[t][mb], 0, bh[t][2 * mb], bl[t][2 * mb]);
                     split_bf16x8(dz[t][mb], 8, bh[t][2 * mb + 1], bl[t][2 * mb + 1]);
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) {   // rows legs_khid(2 mb + k, h, .)
+                        const int ks = 2 * mb + k;
+                        const auto row = [ks, h](int i) { return legs_khid(ks, h, i); };
+                        store_rows8(plane, SH, gi[t] - i8, bh[t][ks], row, i8, b1, psel);
+                        store_rows8(plane + SH * A.Gp, SH, gi[t] - i8, bl[t][ks], row, i8, b1, psel);
+                    }
                 }
             if (!T) return;
 #pragma unroll
@@ -457,11 +434,12 @@ k_smooth_wgrad(SmoothArgs A, float *__restrict__ grad)
 {
     const int layer = blockIdx.y;
     const int lane = __lane_id(), wave = threadIdx.x / LEGS_WAVE, h = lane >> 5;
-    const float *Dp = layer == 0 ? A.D1 : layer == 1 ? A.D2 : layer == 2 ? A.D3 : A.D4;
+    const __bf16 *Dh = layer == 0 ? A.D1 : layer == 1 ? A.D2 : layer == 2 ? A.D3 : A.D4;
     const __bf16 *Bp = layer == 0 ? A.X : layer == 1 ? A.H1 : layer == 2 ? A.H2 : A.H3;
     const int M = layer == 3 ? LEGS_SMOOTH_OUT : SH;          // rows of D
     const int Kb = layer == 0 ? 16 : SH;                      // rows of B
     const int MB = (M + 31) / 32, NB = (Kb + 31) / 32;
+    const __bf16 *Dl = Dh + (int64_t)M * A.Gp;                 // lo parts after the hi plane
     // wave w owns the 32 rows of block w of D against every block of B, so
     // each fragment of D is loaded once and each of B once per wave
     if (wave >= MB) return;
@@ -476,21 +454,16 @@ k_smooth_wgrad(SmoothArgs A, float *__restrict__ grad)
     float dbs = 0.0f;
 #pragma unroll 2
     for (int64_t g = g0; g < g1; g += 16) {
+        // this lane's operands: Gaussians g + 8 h .. + 7 (16-byte fragments)
+        const int64_t gl = g + 8 * h;
         bf16x8 ah = {}, al = {}, b[4];
         if (mrow) {                 // dz as hi + lo bf16 parts (16 significant bits)
-            const float *Drow = Dp + plane_at(g, M, m) + 8 * h;
-            const float4 v0 = *reinterpret_cast<const float4 *>(Drow);
-            const float4 v1 = *reinterpret_cast<const float4 *>(Drow + 4);
-            const float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                ah[e] = (__bf16)v[e];
-                al[e] = (__bf16)(v[e] - (float)ah[e]);
-            }
+            ah = *reinterpret_cast<const bf16x8 *>(Dh + frag_at(gl, M, m));
+            al = *reinterpret_cast<const bf16x8 *>(Dl + frag_at(gl, M, m));
         }
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb)
-            b[nb] = krow[nb] ? *reinterpret_cast<const bf16x8 *>(Bp + plane_at(g, Kb, 32 * nb + (lane & 31)) + 8 * h)
+            b[nb] = krow[nb] ? *reinterpret_cast<const bf16x8 *>(Bp + frag_at(gl, Kb, 32 * nb + (lane & 31)))
                              : (bf16x8){};
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb)
@@ -573,10 +546,10 @@ int32_t legs_launch_smooth(legs_ctx *ctx, const float *mean, const float *channe
     A.H1 = reinterpret_cast<__bf16 *>(ws + Lw.H1);
     A.H2 = reinterpret_cast<__bf16 *>(ws + Lw.H2);
     A.H3 = reinterpret_cast<__bf16 *>(ws + Lw.H3);
-    A.D1 = reinterpret_cast<float *>(ws + Lw.D1);
-    A.D2 = reinterpret_cast<float *>(ws + Lw.D2);
-    A.D3 = reinterpret_cast<float *>(ws + Lw.D3);
-    A.D4 = reinterpret_cast<float *>(ws + Lw.D4);
+    A.D1 = reinterpret_cast<__bf16 *>(ws + Lw.D1);
+    A.D2 = reinterpret_cast<__bf16 *>(ws + Lw.D2);
+    A.D3 = reinterpret_cast<__bf16 *>(ws + Lw.D3);
+    A.D4 = reinterpret_cast<__bf16 *>(ws + Lw.D4);
     int64_t blocks = (Lw.Gp + 32 * SNT * 4 - 1) / (32 * SNT * 4);
     if (blocks > ctx->num_cus) blocks = ctx->num_cus;
     hipLaunchKernelGGL(k_smooth_fwd_bwd, dim3((unsigned)blocks), dim3(256), 0, s, A);

@@ -35,14 +35,15 @@ def ctx():
 
 def planes(ws, n, Gp):
     """The bf16 hidden activations h1, h2, h3 from the workspace: after the
-    16-row input plane, three 128-row planes, each blocked by 64 Gaussians
-    ([Gp / 64][128 units][64 Gaussians]). Returned [n][128] each."""
+    16-row input plane, three 128-row planes in the weight gradient's operand
+    order ([Gp / 16 steps][4 row blocks][2 Gaussian halves][32 rows][8
+    Gaussians]: row 32 b + r, Gaussian 16 s + 8 k + e). Returned [n][128]."""
     b = ws.view(torch.bfloat16)
     out = []
     for k in range(3):
         off = 16 * Gp + k * 128 * Gp
-        blk = b[off:off + 128 * Gp].view(Gp // 64, 128, 64)
-        out.append(blk.permute(0, 2, 1).reshape(Gp, 128)[:n].float().cpu().numpy().astype(np.float64))
+        f = b[off:off + 128 * Gp].view(Gp // 16, 4, 2, 32, 8)
+        out.append(f.permute(0, 2, 4, 1, 3).reshape(Gp, 128)[:n].float().cpu().numpy().astype(np.float64))
     return out
 
 
