@@ -313,11 +313,18 @@ def language_leg(log_fn):
     wss = DEC.smooth_workspace(ctx, n)
     ms_s = tm(lambda: DEC.smooth_loss_grad(ctx, mean, chans, 3, C - 1, sp, grad, dch, loss, workspace=wss))
     flop_g = 2 * (3 * 128 + 2 * 128 * 128 + 128 * 8) * 3       # forward, input-side backward, weight gradient
+    # HBM bytes per Gaussian: the workspace planes written by the forward and
+    # read by the weight gradient (x 16 rows, h1-h3 128 rows bf16, dz1-dz3 128
+    # rows and dz4 8 rows as two bf16 parts), position and s_G, u read, and the
+    # read-modify-write of the 8 channel-gradient floats
+    planes_b = 16 * 2 + 3 * 128 * 2 + 3 * 128 * 4 + 8 * 4
+    bytes_g = 2 * planes_b + 12 + 9 * 4 + 2 * 8 * 4
     res["smooth"] = dict(
         workload=f"L_smo and its gradients over {n} Gaussians (the 1080p scene), MLP 3-128-128-128-8 bf16",
         gaussians=int(n), ms=ms_s, mgauss_s=n / ms_s / 1e3,
-        roofline=dict(bound="mfma", unit="TFLOP/s", achieved=n * flop_g / ms_s / 1e9, peak=BF16_MFMA_PEAK_TFLOPS,
-                      frac=n * flop_g / ms_s / 1e9 / BF16_MFMA_PEAK_TFLOPS, flop_per_gaussian=flop_g))
+        roofline=dict(bound="hbm", unit="GB/s", achieved=n * bytes_g / ms_s / 1e6, peak=HBM_PEAK_GBS,
+                      frac=n * bytes_g / ms_s / 1e6 / HBM_PEAK_GBS, bytes_per_gaussian=bytes_g,
+                      mfma_frac=n * flop_g / ms_s / 1e9 / BF16_MFMA_PEAK_TFLOPS, flop_per_gaussian=flop_g))
     log_fn(f"smooth: {json.dumps(res['smooth'])}")
     return res
 

@@ -175,6 +175,14 @@ __device__ __forceinline__ uint32_t dpp_move(uint32_t old, uint32_t src)
     return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, CTRL, 0xF, BANK, false);
 }
 
+// A DPP move that writes every lane (its source lane always exists): no old
+// value to keep, so no register to initialise first.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_all(uint32_t src)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)src, CTRL, 0xF, 0xF, false);
+}
+
 // 8 x 8 transpose of bf16 values across each group of 8 lanes (i = lane & 7):
 // lane i holds 8 values of one row, element e in half e % 2 of word e / 2;
 // afterwards lane i holds element i of the 8 lanes' rows, in lane order.
@@ -192,14 +200,14 @@ __device__ __forceinline__ void oct_transpose(uint32_t (&w)[4], bool b1, uint32_
     // every exchange runs on all lanes before the selects: a DPP move inside
     // one arm of a conditional would run under a partial exec mask and read
     // lanes that are switched off
-    const uint32_t p0 = dpp_move<0x4E, 0xF>(0u, n0), p1 = dpp_move<0x4E, 0xF>(0u, n1);
-    const uint32_t p2 = dpp_move<0x4E, 0xF>(0u, n2), p3 = dpp_move<0x4E, 0xF>(0u, n3);
+    const uint32_t p0 = dpp_all<0x4E>(n0), p1 = dpp_all<0x4E>(n1);
+    const uint32_t p2 = dpp_all<0x4E>(n2), p3 = dpp_all<0x4E>(n3);
     w[0] = b1 ? p1 : n0;
     w[1] = b1 ? n1 : p0;
     w[2] = b1 ? p3 : n2;
     w[3] = b1 ? n3 : p2;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] = __builtin_amdgcn_perm(dpp_move<0xB1, 0xF>(0u, w[k]), w[k], psel);
+    for (int k = 0; k < 4; ++k) w[k] = __builtin_amdgcn_perm(dpp_all<0xB1>(w[k]), w[k], psel);
 }
 
 // Eight rows (row(e), e = 0..7) of this lane's Gaussian into a plane of R
