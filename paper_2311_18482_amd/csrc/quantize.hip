@@ -10,10 +10,12 @@
 //  k_quant_prep      S once per call into the LDS image of each 128-dimension
 //                    chunk (A-operand fragments, code rows x dimensions), and
 //                    1 / |S_j| of both parts.
-//  k_quant_pass      one workgroup of 4 waves per CU, 256 features per round
-//                    (two 32-feature tiles per wave, sharing every codebook
-//                    fragment read from LDS): for each chunk the image is copied into
-//                    one of two LDS buffers while the other feeds the MFMAs;
+//  k_quant_pass      one workgroup of 4 waves per CU, 32-feature tiles (two
+//                    per wave at N = 32, sharing every codebook fragment read
+//                    from LDS): the codebook image of each chunk and every
+//                    wave's feature fragments stream straight into one of two
+//                    LDS buffers (global_load_lds, no registers) while the
+//                    other feeds the MFMAs;
 //                    the 32 x N dot products of each part stay in registers
 //                    (transposed: codes x features), the feature norms are
 //                    summed from the same B fragments. Then per feature the
@@ -50,9 +52,18 @@ constexpr float WSCALE = 1024.0f;
 constexpr int QTHREADS = 256;      // 4 waves, one per SIMD
 constexpr int QGROUP = 256;        // feature padding of the half weights W^C, W^D
 // 32-feature tiles per wave (every codebook fragment read from LDS feeds QNT
-// MFMAs): two up to N = 64, one at N = 128 (whose 2 x 128 accumulators fill
-// the register file)
-template <int KB> constexpr int qnt() { return KB == 4 ? 1 : 2; }
+// MFMAs): two at N = 32, one from N = 64 (the LDS holds two chunks of the
+// codebook image and of every wave's feature fragments)
+template <int KB> constexpr int qnt() { return KB == 1 ? 2 : 1; }
+
+// 16 bytes per lane from global memory straight into LDS (gfx950
+// global_load_lds_dwordx4): lane l's bytes land at lds + 16 l; lds is the
+// same for the whole wave. Completion: s_waitcnt vmcnt(0) of this wave, then
+// a barrier for the other waves' reads.
+__device__ __forceinline__ void global_to_lds(const void *src, void *lds)
+{
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+}
 
 __device__ __forceinline__ f32x16 mfma16(f16x8 a, f16x8 b, f32x16 c)
 {
@@ -121,14 +132,12 @@ __device__ __forceinline__ void half_wave_sums(float (&v)[V], float *dst, CodeOf
 {
     const int lane = __lane_id();
     legs_tr::run<4, V, V>(v, lane);
-    int idx[V];
-#pragma unroll
-    for (int i = 0; i < V; ++i) idx[i] = i;
-    legs_tr::index_run<4, V, V>(idx, lane);
     constexpr int R = legs_tr::final_k(V, 5);
 #pragma unroll
-    for (int k = 0; k < R; ++k)
-        if (idx[k] >= 0 && v[k] != 0.0f) atomicAdd(dst + code_of(idx[k]), v[k]);
+    for (int k = 0; k < R; ++k) {
+        const int ix = legs_tr::src_index<4, V>(k, lane);
+        if (ix >= 0 && v[k] != 0.0f) atomicAdd(dst + code_of(ix), v[k]);
+    }
 }
 
 template <int KB, bool GRAD>
@@ -138,7 +147,8 @@ k_quant_pass(QuantArgs A)
     constexpr int N = 32 * KB, NF = KB * 8 * 64, PER = NF / QTHREADS;
     constexpr int QNT = qnt<KB>(), ROUND = QTHREADS / LEGS_WAVE * 32 * QNT;   // features per round
     static_assert(NF % QTHREADS == 0, "fragments per thread");
-    __shared__ f16x8 frag[2][NF];
+    __shared__ f16x8 frag[2][NF];                                    // codebook chunk images
+    __shared__ f16x8 feat[2][QTHREADS / LEGS_WAVE][QNT][8 * LEGS_WAVE];  // each wave's feature fragments
     __shared__ float s_inv[2][N];
     __shared__ float s_ab[2 * N];         // psum | col^C then col^D
     __shared__ uint32_t s_cnt[N];
@@ -174,18 +184,24 @@ k_quant_pass(QuantArgs A)
 #pragma unroll
             for (int mb = 0; mb < KB; ++mb) { ac[t][mb] = (f32x16){}; ad[t][mb] = (f32x16){}; }
         float ssc[QNT] = {}, ssd[QNT] = {};
-        __syncthreads();                              // the previous round's readers are done
+        // the fragments of chunk ch into LDS buffer ch & 1: the codebook image
+        // in 1 KB pieces (wave w copies pieces w, w + 4, ...) and this wave's
+        // feature fragments (lane l of k-step ks: feature l % 32, dimensions
+        // 128 ch + 16 ks + 8 (l / 32) .. + 7; padding features read row 0 and
+        // are zeroed when read back)
+        auto issue = [&](int ch) {
+            const int b = ch & 1;
+            for (int p = wave; p < NF / LEGS_WAVE; p += QTHREADS / LEGS_WAVE)
+                global_to_lds(A.img + (int64_t)ch * NF + p * LEGS_WAVE + lane, &frag[b][p * LEGS_WAVE]);
 #pragma unroll
-        for (int q = 0; q < PER; ++q) frag[0][tid + q * QTHREADS] = A.img[tid + q * QTHREADS];
-        __syncthreads();
-        // chunks [0, nchC) accumulate the CLIP dot products, the rest the DINO ones
+            for (int t = 0; t < QNT; ++t)
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks)
+                    global_to_lds(frow[t] + ch * QCH + 16 * ks, &feat[b][wave][t][ks * LEGS_WAVE]);
+        };
         auto chunk = [&](int ch, f32x16 (&acc)[QNT][KB], float (&ss)[QNT]) {
-            f16x8 nx[PER];
-            if (ch + 1 < nch) {
-#pragma unroll
-                for (int q = 0; q < PER; ++q) nx[q] = A.img[(int64_t)(ch + 1) * NF + tid + q * QTHREADS];
-            }
             const f16x8 *fr = frag[ch & 1];
+            const f16x8 (*fb)[8 * LEGS_WAVE] = feat[ch & 1][wave];
             // software pipeline: the fragments of k-step ks + 1 are read while
             // the MFMAs of ks run; a scheduling barrier per k-step keeps the
             // compiler from hoisting every read of the chunk (registers)
@@ -193,8 +209,7 @@ k_quant_pass(QuantArgs A)
 #pragma unroll
             for (int mb = 0; mb < KB; ++mb) a[mb] = fr[mb * 8 * 64 + lane];
 #pragma unroll
-            for (int t = 0; t < QNT; ++t)
-                b[t] = valid[t] ? *reinterpret_cast<const f16x8 *>(frow[t] + ch * QCH) : (f16x8){};
+            for (int t = 0; t < QNT; ++t) b[t] = valid[t] ? fb[t][lane] : (f16x8){};
 #pragma unroll
             for (int ks = 0; ks < 8; ++ks) {
                 f16x8 an[KB], bn[QNT];
@@ -202,9 +217,7 @@ k_quant_pass(QuantArgs A)
 #pragma unroll
                     for (int mb = 0; mb < KB; ++mb) an[mb] = fr[(mb * 8 + ks + 1) * 64 + lane];
 #pragma unroll
-                    for (int t = 0; t < QNT; ++t)
-                        bn[t] = valid[t] ? *reinterpret_cast<const f16x8 *>(frow[t] + ch * QCH + 16 * (ks + 1))
-                                         : (f16x8){};
+                    for (int t = 0; t < QNT; ++t) bn[t] = valid[t] ? fb[t][(ks + 1) * 64 + lane] : (f16x8){};
                 }
 #pragma unroll
                 for (int mb = 0; mb < KB; ++mb)
@@ -222,16 +235,23 @@ k_quant_pass(QuantArgs A)
                     for (int t = 0; t < QNT; ++t) b[t] = bn[t];
                 }
             }
-            if (ch + 1 < nch) {
-#pragma unroll
-                for (int q = 0; q < PER; ++q) frag[(ch + 1) & 1][tid + q * QTHREADS] = nx[q];
-            }
-            __syncthreads();
         };
+        // chunk ch + 1 loads while chunk ch computes; the wait and barrier
+        // before each chunk make its fragments visible and free the other
+        // buffer (read by chunk ch - 1) for the next loads
+        auto step = [&](int ch, f32x16 (&acc)[QNT][KB], float (&ss)[QNT]) {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            if (ch + 1 < nch) issue(ch + 1);
+            chunk(ch, acc, ss);
+        };
+        __syncthreads();                              // the previous round's readers are done
+        issue(0);
+        // chunks [0, nchC) accumulate the CLIP dot products, the rest the DINO ones
 #pragma unroll 1
-        for (int ch = 0; ch < nchC; ++ch) chunk(ch, ac, ssc);
+        for (int ch = 0; ch < nchC; ++ch) step(ch, ac, ssc);
 #pragma unroll 1
-        for (int ch = nchC; ch < nch; ++ch) chunk(ch, ad, ssd);
+        for (int ch = nchC; ch < nch; ++ch) step(ch, ad, ssd);
 #pragma unroll
         for (int t = 0; t < QNT; ++t) {
             const int64_t i = ii[t];
@@ -296,11 +316,17 @@ k_quant_pass(QuantArgs A)
                 rs += __shfl_xor(rs, 32, LEGS_WAVE);
                 rs *= isum;
                 const float scale = (float)A.K * WSCALE;
+                // column i of W^C, W^D at row j = 32 mb + 8 (r / 4) + (r % 4) + 4 h:
+                // a per-lane base (rows 4 h) plus a row offset uniform over the
+                // wave, so no per-register 64-bit addresses stay live
+                _Float16 *wch = A.Wc + i + (int64_t)(4 * h) * A.Kp;
+                _Float16 *wdh = A.Wd + i + (int64_t)(4 * h) * A.Kp;
 #pragma unroll
                 for (int mb = 0; mb < KB; ++mb)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const int j = 32 * mb + legs_drow(r, h);
+                        const int64_t jrow = (int64_t)(32 * mb + 8 * (r >> 2) + (r & 3)) * A.Kp;
                         const float c = ac[t][mb][r], e = ad[t][mb][r];
                         const float s = __expf(c + A.lam_d * e - best) * isum;
                         float gj = A.lam_lb * invK * s * (s_r[j] - rs);
@@ -308,8 +334,8 @@ k_quant_pass(QuantArgs A)
                         if (!vt) gj = 0.0f;
                         ac[t][mb][r] = gj * c;                 // column-sum terms, in place
                         ad[t][mb][r] = A.lam_d * gj * e;
-                        A.Wc[(int64_t)j * A.Kp + i] = (_Float16)(scale * gj);
-                        A.Wd[(int64_t)j * A.Kp + i] = (_Float16)(scale * A.lam_d * gj);
+                        wch[jrow] = (_Float16)(scale * gj);
+                        wdh[jrow] = (_Float16)(scale * A.lam_d * gj);
                     }
                 auto code = [h](int v) { return 32 * (v >> 4) + legs_drow(v & 15, h); };
                 {

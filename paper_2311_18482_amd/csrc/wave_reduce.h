@@ -120,6 +120,26 @@ __device__ __forceinline__ void index_run(int (&idx)[N], int lane)
     }
 }
 
+// The value index that slot q of the final registers holds after the stages
+// S .. 0 over K values (-1: none), walking the stages backwards from the
+// last: the closed form of index_run for one slot, with no array of indices.
+template <int S, int K>
+__device__ __forceinline__ int src_index(int q, int lane)
+{
+    if constexpr (S < 0) {
+        return q;
+    } else {
+        const int p = src_index<S - 1, next_k(K)>(q, lane);   // slot after stage S
+        constexpr int H = K / 2;
+        const bool hi = (lane >> S) & 1;
+        if (p < 0) return -1;
+        if constexpr (K & 1) {
+            if (p == H) return hi ? -1 : K - 1;
+        }
+        return p + (hi ? H : 0);
+    }
+}
+
 // Value index of each final register in this lane (-1: a zero or a duplicate).
 template <int N>
 __device__ __forceinline__ void index(int (&idx)[N], int lane)
