@@ -297,9 +297,11 @@ k_quant_pass(QuantArgs A)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const float c = ac[t][mb][r], e = ad[t][mb][r];
-                        if (vt && 32 * mb + legs_drow(r, h) == bidx) lcos += (1.0f - c) + A.lam_d * (1.0f - e);
                         sv[mb * 16 + r] = vt ? __expf(c + A.lam_d * e - best) * isum : 0.0f;
                     }
+                // the cosine loss of the assigned code: (1 - cos^C) + lambda (1 - cos^D)
+                // = (1 + lambda) - D at the maximum, which is best
+                if (vt && h == 0) lcos += (1.0f + A.lam_d) - best;
                 half_wave_sums<KB * 16>(sv, s_ab, [h](int v) { return 32 * (v >> 4) + legs_drow(v & 15, h); });
                 if (vt && h == 0) {
                     A.index[i] = bidx;
