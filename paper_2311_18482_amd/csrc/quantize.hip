@@ -24,20 +24,24 @@
 //                    indices, sum of the softmax (the mean selection
 //                    probability), cosine loss. GRAD: dL_q/dD_j with the final
 //                    histogram, written (scaled by 2^10 K) as half weights
-//                    W^C, W^D [N][Kp] with 1 / |F_i| of both parts, and the
-//                    column sums
-//                    sum_i dL/dD_ij cos_ij per part. Column sums over the 32
+//                    W^C, W^D (N x Kp, in the weight gradient's MFMA operand
+//                    order: one 16-byte fragment per lane after an 8 x 8 lane
+//                    transpose) with 1 / |F_i| of both parts, and the column
+//                    sums sum_i dL/dD_ij cos_ij per part. Column sums over the 32
 //                    features of a wave go through a transpose reduction
 //                    (five lane-bit stages) before the LDS and global atomics.
 //  k_quant_wgrad     sum_i W_ij F_ic / |F_i| for every code j and dimension c:
-//                    FP16 MFMA with the features as the contraction, the
-//                    unit feature rows staged through LDS transposed
-//                    (dimension-major) in steps of 64, split over feature ranges (x) and 128-dimension
-//                    chunks (y), float atomics into the gradient.
+//                    FP16 MFMA with the features as the contraction (the
+//                    weight fragments 1 KB contiguous per wave), the unit
+//                    feature rows staged through LDS transposed
+//                    (dimension-major) in steps of 64, split over feature
+//                    ranges (x) and 128-dimension chunks (y), float atomics
+//                    into the gradient.
 //  k_quant_finish    the gradient's second term, the losses, r and p.
 #include "legs_internal.h"
 #include "legs_decode_internal.h"
 #include "wave_reduce.h"
+#include "lane_transpose.h"
 
 namespace {
 
@@ -63,6 +67,14 @@ template <int KB> constexpr int qnt() { return KB == 1 ? 2 : 1; }
 __device__ __forceinline__ void global_to_lds(const void *src, void *lds)
 {
     __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+}
+
+// Two floats as a word of halves (round to nearest), a in the low half.
+__device__ __forceinline__ uint32_t pack_half2(float a, float b)
+{
+    typedef __attribute__((ext_vector_type(2))) _Float16 f16x2;
+    const f16x2 v = {(_Float16)a, (_Float16)b};
+    return __builtin_bit_cast(uint32_t, v);
 }
 
 __device__ __forceinline__ f32x16 mfma16(f16x8 a, f16x8 b, f32x16 c)
@@ -120,7 +132,8 @@ struct QuantArgs {
     uint32_t *counts;           // [N]
     float *psum;                // [N] sum of softmax over features
     float *lsum;                // [1] cosine-loss sum
-    _Float16 *Wc, *Wd;          // [N][Kp] half weights 2^10 K dL/dD (lambda_dino K dL/dD for DINO)
+    _Float16 *Wc, *Wd;          // N x Kp half weights 2^10 K dL/dD (lambda_dino K dL/dD for DINO) in
+                                // MFMA operand order (legs_lt::frag_at, codes as rows, features as columns)
     float *invF;                // [2][Kp] 1 / |F_i| of both parts (0 past K)
     float *col;                 // [2][N]
 };
@@ -154,6 +167,10 @@ k_quant_pass(QuantArgs A)
     __shared__ uint32_t s_cnt[N];
     __shared__ float s_r[N];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5;
+    // position in the lane's group of 8 for the transposed weight stores
+    const int i8 = lane & 7;
+    const bool b1 = (lane & 2) != 0;
+    const uint32_t psel = (lane & 1) ? 0x03020706u : 0x05040100u;
     const float invK = 1.0f / (float)A.K;
     for (int j = tid; j < N; j += QTHREADS) {
         s_inv[0][j] = A.invS[j];
@@ -318,26 +335,42 @@ k_quant_pass(QuantArgs A)
                 rs += __shfl_xor(rs, 32, LEGS_WAVE);
                 rs *= isum;
                 const float scale = (float)A.K * WSCALE;
-                // column i of W^C, W^D at row j = 32 mb + 8 (r / 4) + (r % 4) + 4 h:
-                // a per-lane base (rows 4 h) plus a row offset uniform over the
-                // wave, so no per-register 64-bit addresses stay live
-                _Float16 *wch = A.Wc + i + (int64_t)(4 * h) * A.Kp;
-                _Float16 *wdh = A.Wd + i + (int64_t)(4 * h) * A.Kp;
+                // W^C, W^D in the weight gradient's operand order: the 8 codes
+                // r = 8 k .. 8 k + 7 of block mb of this lane's feature,
+                // transposed across its group of 8 lanes (8 consecutive
+                // features), are one 16-byte fragment per lane
+                const int64_t i0 = i - i8;
 #pragma unroll
                 for (int mb = 0; mb < KB; ++mb)
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int j = 32 * mb + legs_drow(r, h);
-                        const int64_t jrow = (int64_t)(32 * mb + 8 * (r >> 2) + (r & 3)) * A.Kp;
-                        const float c = ac[t][mb][r], e = ad[t][mb][r];
-                        const float s = __expf(c + A.lam_d * e - best) * isum;
-                        float gj = A.lam_lb * invK * s * (s_r[j] - rs);
-                        if (j == m) gj -= A.lam_cos * invK;
-                        if (!vt) gj = 0.0f;
-                        ac[t][mb][r] = gj * c;                 // column-sum terms, in place
-                        ad[t][mb][r] = A.lam_d * gj * e;
-                        wch[jrow] = (_Float16)(scale * gj);
-                        wdh[jrow] = (_Float16)(scale * A.lam_d * gj);
+                    for (int k = 0; k < 2; ++k) {
+                        uint32_t wc[4], wd[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            float gv[2];
+#pragma unroll
+                            for (int u = 0; u < 2; ++u) {
+                                const int r = 8 * k + 2 * q + u;
+                                const int j = 32 * mb + legs_drow(r, h);
+                                const float c = ac[t][mb][r], e = ad[t][mb][r];
+                                const float s = __expf(c + A.lam_d * e - best) * isum;
+                                float gj = A.lam_lb * invK * s * (s_r[j] - rs);
+                                if (j == m) gj -= A.lam_cos * invK;
+                                if (!vt) gj = 0.0f;
+                                ac[t][mb][r] = gj * c;         // column-sum terms, in place
+                                ad[t][mb][r] = A.lam_d * gj * e;
+                                gv[u] = gj;
+                            }
+                            wc[q] = pack_half2(scale * gv[0], scale * gv[1]);
+                            wd[q] = pack_half2(scale * A.lam_d * gv[0], scale * A.lam_d * gv[1]);
+                        }
+                        legs_lt::oct_transpose(wc, b1, psel);
+                        legs_lt::oct_transpose(wd, b1, psel);
+                        // lane i8 now holds code 32 mb + drow(8 k + i8, h) of features i0 .. i0 + 7
+                        const int row = 32 * mb + 16 * k + 8 * (i8 >> 2) + 4 * h + (i8 & 3);
+                        const int64_t off = legs_lt::frag_at(i0, N, row);
+                        *reinterpret_cast<uint4 *>(A.Wc + off) = make_uint4(wc[0], wc[1], wc[2], wc[3]);
+                        *reinterpret_cast<uint4 *>(A.Wd + off) = make_uint4(wd[0], wd[1], wd[2], wd[3]);
                     }
                 auto code = [h](int v) { return 32 * (v >> 4) + legs_drow(v & 15, h); };
                 {
@@ -411,7 +444,9 @@ k_quant_wgrad(const _Float16 *__restrict__ F, int64_t K, int64_t Kp, int d, int 
 #pragma unroll
         for (int ks = 0; ks < WG_FEAT / 16; ++ks) {
             const int64_t ia = s0 + 16 * ks + 8 * h;
-            const f16x8 a = ia < x1 ? *reinterpret_cast<const f16x8 *>(W + (int64_t)(32 * mb + (lane & 31)) * Kp + ia)
+            // operand order: the wave's fragments of (code block mb, features
+            // s0 + 16 ks ..) are 1 KB contiguous
+            const f16x8 a = ia < x1 ? *reinterpret_cast<const f16x8 *>(W + legs_lt::frag_at(ia, N, 32 * mb + (lane & 31)))
                                     : (f16x8){};
 #pragma unroll
             for (int q = 0; q < DB; ++q) {

@@ -30,6 +30,7 @@
 //                    (y), float atomics into the gradient.
 #include "legs_internal.h"
 #include "legs_decode_internal.h"
+#include "lane_transpose.h"
 
 namespace {
 
@@ -129,17 +130,10 @@ __device__ __forceinline__ void split_bf16x8(const f32x16 &z, int first, bf16x8 
 }
 
 // Workspace planes are kept in the operand order of the weight-gradient
-// MFMAs: Gaussians in steps of 16, rows in blocks of RW = min(R, 32) (R = 8,
-// 16 or a multiple of 32); in the chunk of (step, block), slot
-// j = row % 32 + RW ((g % 16) / 8) holds Gaussians 16 step + 8 ((g % 16) / 8)
-// .. + 7 of that row, 16 bytes, which is what lane j of a 32 x 32 x 16 MFMA
-// takes. A 128-row chunk is 64 slots in lane order (1 KB). Element offset of
-// the fragment of (row, Gaussians g .. g + 7), g a multiple of 8:
-__device__ __forceinline__ int64_t frag_at(int64_t g, int R, int row)
-{
-    const int RW = R < 32 ? R : 32, RB = (R + 31) / 32;
-    return ((((g >> 4) * RB + row / 32) * (2 * RW)) + row % 32 + RW * ((g >> 3) & 1)) * 8;
-}
+// MFMAs (legs_lt::frag_at with the Gaussians as the columns), so a forward
+// store is one 16-byte fragment and a weight-gradient load of a 128-row plane
+// is 1 KB contiguous per wave.
+using legs_lt::frag_at;
 
 struct SmoothArgs {
     const float *mean, *ch;
@@ -167,49 +161,6 @@ __device__ __forceinline__ void layer_block(const bf16x8 *__restrict__ wA, const
     }
 }
 
-// DPP moves: lanes enabled by BANK (banks of 4 lanes in each row of 16)
-// read src from the lane CTRL names, the others keep old.
-template <int CTRL, int BANK>
-__device__ __forceinline__ uint32_t dpp_move(uint32_t old, uint32_t src)
-{
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, CTRL, 0xF, BANK, false);
-}
-
-// A DPP move that writes every lane (its source lane always exists): no old
-// value to keep, so no register to initialise first.
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_all(uint32_t src)
-{
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)src, CTRL, 0xF, 0xF, false);
-}
-
-// 8 x 8 transpose of bf16 values across each group of 8 lanes (i = lane & 7):
-// lane i holds 8 values of one row, element e in half e % 2 of word e / 2;
-// afterwards lane i holds element i of the 8 lanes' rows, in lane order.
-// Three rounds, each keeping one half of the current chunk size and taking
-// the partner's other half: words 0-1 / 2-3 across lanes i ^ 4 (DPP row
-// shifts by 4 into the banks that need them), words across i ^ 2, halves of
-// each word across i ^ 1 (v_perm with psel = 0x05040100 on even lanes: own
-// low, partner's low; 0x03020706 on odd lanes: partner's high, own high).
-__device__ __forceinline__ void oct_transpose(uint32_t (&w)[4], bool b1, uint32_t psel)
-{
-    const uint32_t n0 = dpp_move<0x114, 0xA>(w[0], w[2]);   // lanes 4-7: lane i - 4's words 2, 3
-    const uint32_t n1 = dpp_move<0x114, 0xA>(w[1], w[3]);
-    const uint32_t n2 = dpp_move<0x104, 0x5>(w[2], w[0]);   // lanes 0-3: lane i + 4's words 0, 1
-    const uint32_t n3 = dpp_move<0x104, 0x5>(w[3], w[1]);
-    // every exchange runs on all lanes before the selects: a DPP move inside
-    // one arm of a conditional would run under a partial exec mask and read
-    // lanes that are switched off
-    const uint32_t p0 = dpp_all<0x4E>(n0), p1 = dpp_all<0x4E>(n1);
-    const uint32_t p2 = dpp_all<0x4E>(n2), p3 = dpp_all<0x4E>(n3);
-    w[0] = b1 ? p1 : n0;
-    w[1] = b1 ? n1 : p0;
-    w[2] = b1 ? p3 : n2;
-    w[3] = b1 ? n3 : p2;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] = __builtin_amdgcn_perm(dpp_all<0xB1>(w[k]), w[k], psel);
-}
-
 // Eight rows (row(e), e = 0..7) of this lane's Gaussian into a plane of R
 // rows in fragment order: transposed across the lane's group of 8 (Gaussians
 // g0 .. g0 + 7), lane i stores row(i) of those Gaussians, one 16-byte
@@ -221,7 +172,7 @@ __device__ __forceinline__ void store_rows8(__bf16 *__restrict__ plane, int R, i
     typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
     const u32x4 x = __builtin_bit_cast(u32x4, v);
     uint32_t w[4] = {x[0], x[1], x[2], x[3]};
-    oct_transpose(w, b1, psel);
+    legs_lt::oct_transpose(w, b1, psel);
     const int row = row_of(i8);
     if (row < R) *reinterpret_cast<uint4 *>(plane + frag_at(g0, R, row)) = make_uint4(w[0], w[1], w[2], w[3]);
 }
