@@ -408,7 +408,6 @@ k_quant_pass(QuantArgs A)
 // dimensions of chunk blockIdx.y; wave w computes code block w % KB and
 // 4 / (4 / KB) dimension blocks.
 constexpr int WG_FEAT = 64;          // features per LDS step
-constexpr int WG_TPAD = 72;          // halves per dimension row of the transposed tile (bank spread)
 
 template <int KB>
 __global__ void __launch_bounds__(256)
@@ -417,8 +416,11 @@ k_quant_wgrad(const _Float16 *__restrict__ F, int64_t K, int64_t Kp, int d, int 
               const float *__restrict__ invS, float *__restrict__ grad)
 {
     constexpr int N = 32 * KB, WPB = 4 / KB, DB = 4 / WPB;   // waves per code block, dim blocks per wave
-    __shared__ _Float16 tile[QCH * WG_TPAD];
+    __shared__ f16x8 tile[WG_FEAT / 16][QCH / 32][64];   // B fragments of a step: [k-step][dim block][lane]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5;
+    const int i8 = lane & 7;
+    const bool b1 = (lane & 2) != 0;
+    const uint32_t psel = (lane & 1) ? 0x03020706u : 0x05040100u;
     const int mb = wave % KB, db0 = (wave / KB) * DB;
     const int c0 = blockIdx.y * QCH;
     const bool clip = c0 < dC;
@@ -429,32 +431,61 @@ k_quant_wgrad(const _Float16 *__restrict__ F, int64_t K, int64_t Kp, int d, int 
     f32x16 acc[DB];
 #pragma unroll
     for (int q = 0; q < DB; ++q) acc[q] = (f32x16){};
-    for (int64_t s0 = x0; s0 < x1; s0 += WG_FEAT) {
-        __syncthreads();
-        // stage features [s0, s0 + 64) x dimensions [c0, c0 + 128), transposed
-        for (int q = tid; q < WG_FEAT * (QCH / 8); q += 256) {
-            const int fi = q / (QCH / 8), c8 = (q % (QCH / 8)) * 8;
-            const int64_t ii = s0 + fi;
-            f16x8 v = (ii < K) ? *reinterpret_cast<const f16x8 *>(F + ii * d + c0 + c8) : (f16x8){};
-            const float sc = ii < K ? iF[ii] : 0.0f;       // unit feature rows of this part
+    // the next step's feature rows, their norms and this wave's weight
+    // fragments are loaded into registers while the current step computes
+    f16x8 fv[4], wa[WG_FEAT / 16];
+    float fsc[4];
+    auto load_step = [&](int64_t s0) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) tile[(c8 + e) * WG_TPAD + fi] = (_Float16)((float)v[e] * sc);
+        for (int it = 0; it < 4; ++it) {
+            const int u = 4 * wave + it;
+            const int64_t ii = s0 + 8 * (u >> 1) + i8;
+            const int c8 = 64 * (u & 1) + 8 * (lane >> 3);
+            fv[it] = ii < K ? *reinterpret_cast<const f16x8 *>(F + ii * d + c0 + c8) : (f16x8){};
+            fsc[it] = ii < K ? iF[ii] : 0.0f;               // unit feature rows of this part
         }
-        __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < WG_FEAT / 16; ++ks) {
-            const int64_t ia = s0 + 16 * ks + 8 * h;
             // operand order: the wave's fragments of (code block mb, features
             // s0 + 16 ks ..) are 1 KB contiguous
-            const f16x8 a = ia < x1 ? *reinterpret_cast<const f16x8 *>(W + legs_lt::frag_at(ia, N, 32 * mb + (lane & 31)))
-                                    : (f16x8){};
+            const int64_t ia = s0 + 16 * ks + 8 * h;
+            wa[ks] = ia < x1 ? *reinterpret_cast<const f16x8 *>(W + legs_lt::frag_at(ia, N, 32 * mb + (lane & 31)))
+                             : (f16x8){};
+        }
+    };
+    if (x0 < x1) load_step(x0);
+    for (int64_t s0 = x0; s0 < x1; s0 += WG_FEAT) {
+        __syncthreads();                                   // the previous step's readers are done
+        // stage features [s0, s0 + 64) x dimensions [c0, c0 + 128) as B
+        // fragments: 16 units of 8 features x 64 dimensions, four per wave;
+        // lane l holds dimensions 8 (l / 8) .. + 7 (of the unit's half) of
+        // feature l % 8 (of the unit's block of 8), scales the row to unit
+        // length, and the transpose across its group of 8 lanes leaves it
+        // dimension 8 (l / 8) + l % 8 of the 8 features: one fragment
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int u = 4 * wave + it, fb = u >> 1;
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                w[q] = pack_half2((float)fv[it][2 * q] * fsc[it], (float)fv[it][2 * q + 1] * fsc[it]);
+            legs_lt::oct_transpose(w, b1, psel);
+            const int c = 64 * (u & 1) + 8 * (lane >> 3) + i8;   // the dimension this lane now holds
+            tile[fb >> 1][c >> 5][(c & 31) + 32 * (fb & 1)] =
+                __builtin_bit_cast(f16x8, make_uint4(w[0], w[1], w[2], w[3]));
+        }
+        f16x8 a[WG_FEAT / 16];
+#pragma unroll
+        for (int ks = 0; ks < WG_FEAT / 16; ++ks) a[ks] = wa[ks];
+        if (s0 + WG_FEAT < x1) load_step(s0 + WG_FEAT);
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < WG_FEAT / 16; ++ks)
 #pragma unroll
             for (int q = 0; q < DB; ++q) {
-                const int c = 32 * (db0 + q) + (lane & 31);
-                const f16x8 b = *reinterpret_cast<const f16x8 *>(tile + c * WG_TPAD + 16 * ks + 8 * h);
-                acc[q] = mfma16(a, b, acc[q]);
+                const f16x8 b = tile[ks][db0 + q][lane];     // dimension 32 (db0 + q) + lane % 32
+                acc[q] = mfma16(a[ks], b, acc[q]);
             }
-        }
     }
     const float invK = 1.0f / ((float)K * WSCALE);
     const float *is = invS + (clip ? 0 : N);
