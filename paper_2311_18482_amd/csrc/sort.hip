@@ -388,6 +388,7 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__res
            const uint32_t *__restrict__ seg_off)
 {
     const bool payload = P.pay != nullptr && desc != nullptr && pass == (int)desc[0] - 1;
+    const bool has_vals = vin != nullptr;   // no values: they travel in the key's low bits
     if (desc) {
         shift = (int)desc[2 + 2 * pass];
         rb = (int)desc[3 + 2 * pass];
@@ -462,7 +463,7 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__res
             const int e = wave * LEGS_WAVE * ITEMS + i * LEGS_WAVE + lane;
             if (e < nvalid) {
                 key[i] = kin[base + e];
-                val[i] = vin[base + e];
+                val[i] = has_vals ? vin[base + e] : 0u;
             } else {
                 key[i] = (K)~(K)0;
                 val[i] = 0;
@@ -532,7 +533,7 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__res
                 const uint32_t d = (uint32_t)(key[i] >> shift) & dmask;
                 const uint32_t pos = s_lstart[d] + s_wh[wave][d] + rank[i];
                 s_keys[pos] = key[i];
-                s_vals[pos] = val[i];
+                if (has_vals) s_vals[pos] = val[i];
             }
         }
         // global start of each digit run: the segment's running start, or a
@@ -583,7 +584,7 @@ k_onesweep(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__res
                 const uint64_t gpos = s_gstart[d] + (uint64_t)k;
                 if (gpos < (uint64_t)capacity) {
                     if (!payload) kout[gpos] = kk;   // the last coarse pass's keys are not read
-                    vout[gpos] = s_vals[k];
+                    if (has_vals) vout[gpos] = s_vals[k];
                     // the partition's positions span a narrow window: these gathers stay in cache
                     if (payload) {
                         const uint32_t pv = s_vals[k];
@@ -670,7 +671,9 @@ k_seg_scan(const uint32_t *__restrict__ seg_hist, int nseg, const uint32_t *__re
 // ---- depth order of the G-views ---------------------------------------------------
 
 // key = (view << 32) | bits(depth) for visible G-views (culled ones sort last,
-// they emit nothing); value = G-view index. Also stores G for the sort and
+// they emit nothing); value = G-view index. With vbits > 0 the value travels
+// in the key's low bits, (key << vbits) | index (culled: all ones), and the
+// digits of the passes start at bit vbits. Also stores G for the sort and
 // counts the digit histograms of its npass passes into hist (cleared before):
 // each workgroup takes chunks of ORDER_RUN rows of ORDER_THREADS G-views,
 // loads a chunk's inputs at once, counts in LDS (hist_add for the clustered
@@ -680,7 +683,7 @@ constexpr int ORDER_THREADS = 1024, ORDER_RUN = 4;   // measured: 4 waves per SI
 __global__ void __launch_bounds__(ORDER_THREADS)
 k_order_keys(const uint32_t *__restrict__ ntiles, const float *__restrict__ depth, int64_t n,
              int64_t G, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-             uint64_t *__restrict__ gcount, int npass, uint32_t *__restrict__ hist)
+             uint64_t *__restrict__ gcount, int npass, uint32_t *__restrict__ hist, int vbits)
 {
     constexpr int NT = ORDER_THREADS, RUN = ORDER_RUN;
     __shared__ uint32_t s_h[LEGS_SORT_MAX_PASSES][256];
@@ -706,12 +709,16 @@ k_order_keys(const uint32_t *__restrict__ ntiles, const float *__restrict__ dept
             if (ok) {
                 const uint64_t v = narrow ? (uint64_t)((uint32_t)gv / (uint32_t)n) : (uint64_t)(gv / n);
                 if (nt[i]) key = (v << 32) | __float_as_uint(dp[i]);
+                if (vbits > 0) {
+                    if (nt[i]) key = (key << vbits) | (uint64_t)gv;
+                } else {
+                    vals[gv] = (uint32_t)gv;
+                }
                 keys[gv] = key;
-                vals[gv] = (uint32_t)gv;
             }
             for (int p = 0; p < npass; ++p) {
                 // the low two bytes of a depth are spread, the higher ones cluster
-                const uint32_t d = (uint32_t)(key >> (8 * p)) & 255u;
+                const uint32_t d = (uint32_t)(key >> (vbits + 8 * p)) & 255u;
                 if (p >= 2) hist_add(s_h[p], d, ok);
                 else if (ok) atomicAdd(&s_h[p][d], 1u);
             }
@@ -734,7 +741,7 @@ constexpr int UNIT = LEGS_COMPACT_UNIT;
 // depth-ordered G-views, and the tile and super-tile instance counts of each
 // block of LEGS_PROJ_BLOCK positions.
 __global__ void __launch_bounds__(LEGS_PROJ_BLOCK)
-k_sorted_records(const uint32_t *__restrict__ perm, const uint64_t *__restrict__ okeys,
+k_sorted_records(const uint32_t *__restrict__ perm, const uint64_t *__restrict__ okeys, int vbits,
                  const int4 *__restrict__ box, int64_t n, int64_t G, const legs_view *__restrict__ sviews, int tile,
                  FRec *__restrict__ frecs, GRec *__restrict__ crecs, uint64_t *__restrict__ vrange,
                  uint64_t *__restrict__ block_counts, uint64_t *__restrict__ cblock_counts)
@@ -745,11 +752,12 @@ k_sorted_records(const uint32_t *__restrict__ perm, const uint64_t *__restrict__
         // culled G-views (no tiles) carry the all-ones key and sort last; the key of a
         // visible one holds its depth bits, and its tile count follows from its box,
         // so the box is the only gather
-        const uint64_t key = okeys[pos];
+        const uint64_t packed = okeys[pos];
+        const uint64_t key = packed >> vbits;      // (view << 32) | depth bits
         FRec f = {0u, 0u, 0u, 0u};
         GRec r = {(uint32_t)pos, 0u, 0u, 0u};
-        if (key != ~0ull) {
-            const int64_t gv = perm[pos];
+        if (packed != ~0ull) {
+            const int64_t gv = vbits > 0 ? (int64_t)(packed & ((1ull << vbits) - 1)) : (int64_t)perm[pos];
             const int64_t v = gv / n;
             const int4 bx = box[gv];
             const legs_view &sw = sviews[v];
@@ -766,8 +774,8 @@ k_sorted_records(const uint32_t *__restrict__ perm, const uint64_t *__restrict__
             cc = r.cnt;
             // first and last position of each view (visible G-views sort by view)
             const uint64_t kv = key >> 32;
-            if (pos == 0 || (okeys[pos - 1] >> 32) != kv) vrange[2 * kv] = (uint64_t)pos;
-            if (pos == G - 1 || (okeys[pos + 1] >> 32) != kv) vrange[2 * kv + 1] = (uint64_t)pos + 1;
+            if (pos == 0 || ((okeys[pos - 1] >> vbits) >> 32) != kv) vrange[2 * kv] = (uint64_t)pos;
+            if (pos == G - 1 || ((okeys[pos + 1] >> vbits) >> 32) != kv) vrange[2 * kv + 1] = (uint64_t)pos + 1;
         }
         frecs[pos] = f;
         crecs[pos] = r;
@@ -1494,7 +1502,7 @@ SortScratch sort_scratch_at(void *base, int64_t capacity, int64_t total_tiles = 
 // prepared, the scratch is cleared and the digits counted here first.
 int32_t radix_passes(legs_ctx *ctx, const SortScratch &S, uint64_t *k0, uint32_t *v0,
                      uint64_t *k1, uint32_t *v1, const uint64_t *count, int64_t capacity,
-                     int first, int last, bool prepared, hipStream_t s)
+                     int first, int last, bool prepared, hipStream_t s, int shift0 = 0)
 {
     const int np = last - first;
     if (np <= 0) return LEGS_OK;
@@ -1511,7 +1519,7 @@ int32_t radix_passes(legs_ctx *ctx, const SortScratch &S, uint64_t *k0, uint32_t
     uint32_t *va = v0, *vb = v1;
     for (int p = first; p < last; ++p) {
         hipLaunchKernelGGL((k_onesweep<uint64_t, false>), dim3(gsort), dim3(LEGS_SORT_THREADS), 0, s,
-                           ka, va, kb, vb, count, capacity, p, 8 * p, 8, nullptr, S.hist,
+                           ka, va, kb, vb, count, capacity, p, shift0 + 8 * p, 8, nullptr, S.hist,
                            S.status + (int64_t)(p - first) * S.parts * 256, S.counters + (p - first),
                            CoarsePay{}, nullptr);
         LEGS_CHECK_LAUNCH(ctx);
@@ -1591,6 +1599,10 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
         uint32_t *ov0 = reinterpret_cast<uint32_t *>(ord + OL.v0), *ov1 = reinterpret_cast<uint32_t *>(ord + OL.v1);
         uint64_t *gcount = reinterpret_cast<uint64_t *>(ord + OL.gcount);
         const int gpass = (32 + bits_for(n_views) + 7) / 8;
+        // the G-view index in the key's low bits when the digits still fit in
+        // 64 bits: the passes move 8 bytes per G-view instead of 12
+        const int vb = bits_for(OL.G);
+        const int vbits = (vb > 0 && vb + 8 * gpass <= 64) ? vb : 0;
         uint64_t *vrange = reinterpret_cast<uint64_t *>(ord + OL.vrange);
         sviews = reinterpret_cast<legs_view *>(ord + OL.sviews);
         {
@@ -1613,12 +1625,15 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
             const SortScratch GS = sort_scratch_at(ord + OL.sort, OL.G);
             hipLaunchKernelGGL(k_order_keys, dim3(grid_for(ctx, OL.G, ORDER_THREADS * ORDER_RUN, 4)),
                                dim3(ORDER_THREADS), 0, s,
-                               proj->ntiles, proj->depth, n, OL.G, ok0, ov0, gcount, gpass, GS.hist);
+                               proj->ntiles, proj->depth, n, OL.G, ok0, ov0, gcount, gpass, GS.hist, vbits);
             LEGS_CHECK_LAUNCH(ctx);
-            const int32_t r = radix_passes(ctx, GS, ok0, ov0, ok1, ov1, gcount, OL.G, 0, gpass, true, s);
+            const int32_t r = vbits > 0
+                                  ? radix_passes(ctx, GS, ok0, nullptr, ok1, nullptr, gcount, OL.G, 0, gpass, true, s,
+                                                 vbits)
+                                  : radix_passes(ctx, GS, ok0, ov0, ok1, ov1, gcount, OL.G, 0, gpass, true, s);
             if (r != LEGS_OK) return r;
         }
-        perm = (gpass % 2 == 0) ? ov0 : ov1;
+        perm = vbits > 0 ? nullptr : (gpass % 2 == 0) ? ov0 : ov1;
         nblocks = OL.nbs;
         uint64_t *bcounts = reinterpret_cast<uint64_t *>(ord + OL.bcounts);
         uint64_t *cbcounts = reinterpret_cast<uint64_t *>(ord + OL.cbcounts);
@@ -1627,7 +1642,7 @@ int32_t legs_launch_bin_sort(legs_ctx *ctx, const legs_projected *proj, int64_t 
         ccount = reinterpret_cast<uint64_t *>(ord + OL.ccount);
         if (nblocks > 0)
             hipLaunchKernelGGL(k_sorted_records, dim3((unsigned)nblocks), dim3(LEGS_PROJ_BLOCK), 0, s,
-                               perm, (gpass % 2 == 0) ? ok0 : ok1,
+                               perm, (gpass % 2 == 0) ? ok0 : ok1, vbits,
                                reinterpret_cast<const int4 *>(proj->box), n, OL.G, sviews, o->tile,
                                reinterpret_cast<FRec *>(ord + OL.frecs),
                                reinterpret_cast<GRec *>(ord + OL.crecs), vrange, bcounts, cbcounts);
