@@ -666,15 +666,20 @@ def main():
     # depth passes of the G-view sort: 8-bit digits over the 32 depth bits and
     # the view bits, ceil(log2(views)) (none for one view)
     gpasses = (32 + int(np.ceil(np.log2(views.n_views))) + 7) // 8
+    # bytes per G-view and pass: the G-view index travels in the key's low bits
+    # (8 B each way) when the index and the digits fit in 64 bits, else a
+    # separate 4 B id follows the 8 B key
+    gbits = int(np.ceil(np.log2(G_views))) if G_views > 1 else 0
+    pass_b = 16 if 0 < gbits and gbits + 8 * gpasses <= 64 else 24
     n_coarse = coarse_entries(proj, args.tile)
     work = {
         "project": ("hbm", G_views * (44 + 16 + 16 + 16 + 4 + 4)),
-        # per G-view: the depth sort (8 + 4 B keys and ids per pass each way), the
-        # records (36 B read, 32 B written), the cell counts (32 B) and the coarse
-        # emission (16 B); per super-tile entry: the coarse pass writes 8 B, the
-        # compaction reads the list and the tile record twice (40 B); per
-        # instance: the compaction writes the 4 B id (no key: ids only)
-        "bin_sort": ("hbm", G_views * (24 * gpasses + 68 + 32 + 16) + n_coarse * 48 + n_inst * 4),
+        # per G-view: the depth sort (pass_b per pass), the records (36 B read,
+        # 32 B written), the cell counts (32 B) and the coarse emission (16 B);
+        # per super-tile entry: the coarse pass writes 8 B, the compaction reads
+        # the list and the tile record twice (40 B); per instance: the
+        # compaction writes the 4 B id (no key: ids only)
+        "bin_sort": ("hbm", G_views * (pass_b * gpasses + 68 + 32 + 16) + n_coarse * 48 + n_inst * 4),
         "project_bwd": ("hbm", G_views * (44 + 32 + 44 + 4)),
         "blend_fwd": ("alu", ev * FLOPS_EVAL + blended * (4 + 2 * C)),
         "blend_bwd": ("alu", ev_bwd * FLOPS_EVAL + blended * (40 + 7 * C)),
