@@ -99,6 +99,26 @@ def test_ragged_multiview(R):
         full_check(R, scene, cams, tile=tile, batch=128)
 
 
+def test_many_views_index_apart_from_depth_keys(R):
+    """520 small views: the G-view depth keys need 6 digit passes (10 view bits
+    above the 32 depth bits) and the G-view index 17 bits, more than 64 in all,
+    so the index travels in an array of its own beside the keys (the depth
+    sort's other path; every other scene packs it into the keys' low bits)."""
+    scene = synth.make_scene(200, 12, synth.VOL_C1, d_sem=8)
+    rng = np.random.default_rng(520)
+    cams = []
+    for v in range(520):
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        Rv, tv = synth.look_at(tuple(np.array([0.0, 0.0, 4.0]) + 6.0 * u), target=(0.0, 0.0, 4.0))
+        w, h = 16 + v % 5, 12 + v % 3
+        cams.append(synth.Camera(w, h, 18.0, 18.0, w / 2, h / 2, Rv, tv))
+    G = 200 * len(cams)
+    gpass = (32 + int(np.ceil(np.log2(len(cams)))) + 7) // 8
+    assert int(np.ceil(np.log2(G))) + 8 * gpass > 64
+    full_check(R, scene, cams, tile=8, batch=64)
+
+
 def test_uncommon_channel_counts(R):
     for d_sem in (0, 5, 16, 30):
         scene = synth.make_scene(3000, 13 + d_sem, synth.VOL_C1, d_sem=d_sem)
