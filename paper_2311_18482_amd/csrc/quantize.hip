@@ -60,6 +60,28 @@ constexpr int QGROUP = 256;        // feature padding of the half weights W^C, W
 // codebook image and of every wave's feature fragments)
 template <int KB> constexpr int qnt() { return KB == 1 ? 2 : 1; }
 
+// s_waitcnt vmcnt(N) (expcnt and lgkmcnt not waited for).
+template <int N>
+__device__ __forceinline__ void vm_wait()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Workgroup barrier for the double-buffered chunks: this wave's LDS reads
+// are complete (lgkmcnt 0) and the compiler keeps memory operations on their
+// side of it, but the next chunk's loads in flight are not waited for (the
+// fence of a __syncthreads() would wait for every load). Each wave waits for
+// its own loads of a buffer (vm_wait) before the barrier that precedes the
+// buffer's reads.
+__device__ __forceinline__ void ring_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(0xC07F);       // lgkmcnt(0); vmcnt, expcnt not waited for
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // 16 bytes per lane from global memory straight into LDS (gfx950
 // global_load_lds_dwordx4): lane l's bytes land at lds + 16 l; lds is the
 // same for the whole wave. Completion: s_waitcnt vmcnt(0) of this wave, then
@@ -160,8 +182,12 @@ k_quant_pass(QuantArgs A)
     constexpr int N = 32 * KB, NF = KB * 8 * 64, PER = NF / QTHREADS;
     constexpr int QNT = qnt<KB>(), ROUND = QTHREADS / LEGS_WAVE * 32 * QNT;   // features per round
     static_assert(NF % QTHREADS == 0, "fragments per thread");
-    __shared__ f16x8 frag[2][NF];                                    // codebook chunk images
-    __shared__ f16x8 feat[2][QTHREADS / LEGS_WAVE][QNT][8 * LEGS_WAVE];  // each wave's feature fragments
+    // two LDS buffers, each the codebook image of a chunk and every wave's
+    // feature fragments; distinct arrays, so that the compiler can tell the
+    // reads of one buffer from the loads still landing in the other
+    constexpr int FEF = QTHREADS / LEGS_WAVE * QNT * 8 * LEGS_WAVE;
+    __shared__ f16x8 frag0[NF], frag1[NF];
+    __shared__ f16x8 feat0[FEF], feat1[FEF];
     __shared__ float s_inv[2][N];
     __shared__ float s_ab[2 * N];         // psum | col^C then col^D
     __shared__ uint32_t s_cnt[N];
@@ -206,19 +232,17 @@ k_quant_pass(QuantArgs A)
         // feature fragments (lane l of k-step ks: feature l % 32, dimensions
         // 128 ch + 16 ks + 8 (l / 32) .. + 7; padding features read row 0 and
         // are zeroed when read back)
-        auto issue = [&](int ch) {
-            const int b = ch & 1;
+        auto issue = [&](int ch, f16x8 *fg, f16x8 *fe) {
             for (int p = wave; p < NF / LEGS_WAVE; p += QTHREADS / LEGS_WAVE)
-                global_to_lds(A.img + (int64_t)ch * NF + p * LEGS_WAVE + lane, &frag[b][p * LEGS_WAVE]);
+                global_to_lds(A.img + (int64_t)ch * NF + p * LEGS_WAVE + lane, fg + p * LEGS_WAVE);
 #pragma unroll
             for (int t = 0; t < QNT; ++t)
 #pragma unroll
                 for (int ks = 0; ks < 8; ++ks)
-                    global_to_lds(frow[t] + ch * QCH + 16 * ks, &feat[b][wave][t][ks * LEGS_WAVE]);
+                    global_to_lds(frow[t] + ch * QCH + 16 * ks, fe + ((wave * QNT + t) * 8 + ks) * LEGS_WAVE);
         };
-        auto chunk = [&](int ch, f32x16 (&acc)[QNT][KB], float (&ss)[QNT]) {
-            const f16x8 *fr = frag[ch & 1];
-            const f16x8 (*fb)[8 * LEGS_WAVE] = feat[ch & 1][wave];
+        auto chunk = [&](const f16x8 *fr, const f16x8 *fe, f32x16 (&acc)[QNT][KB], float (&ss)[QNT]) {
+            const f16x8(*fb)[8 * LEGS_WAVE] = reinterpret_cast<const f16x8(*)[8 * LEGS_WAVE]>(fe + wave * QNT * 8 * LEGS_WAVE);
             // software pipeline: the fragments of k-step ks + 1 are read while
             // the MFMAs of ks run; a scheduling barrier per k-step keeps the
             // compiler from hoisting every read of the chunk (registers)
@@ -253,22 +277,61 @@ k_quant_pass(QuantArgs A)
                 }
             }
         };
-        // chunk ch + 1 loads while chunk ch computes; the wait and barrier
-        // before each chunk make its fragments visible and free the other
-        // buffer (read by chunk ch - 1) for the next loads
-        auto step = [&](int ch, f32x16 (&acc)[QNT][KB], float (&ss)[QNT]) {
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            __syncthreads();
-            if (ch + 1 < nch) issue(ch + 1);
-            chunk(ch, acc, ss);
+        // chunk ch + 1 loads while chunk ch computes: the wait for this wave's
+        // loads and the barrier before each chunk make its fragments visible
+        // and free the other buffer (read by chunk ch - 1) for the next loads.
+        // The loop takes two chunks per iteration, even ones in buffer 0 and
+        // odd ones in buffer 1, so that every read and every load has its
+        // buffer fixed at compile time; the last chunk reloads itself into
+        // the other buffer (an unconditional load keeps the compiler's own
+        // wait away from the reads). One set of accumulators serves the part
+        // being summed: at chunk nchC the CLIP sums move to ac.
+        f32x16 acc[QNT][KB];
+        float ss[QNT];
+#pragma unroll
+        for (int t = 0; t < QNT; ++t) {
+            ss[t] = 0.0f;
+#pragma unroll
+            for (int mb = 0; mb < KB; ++mb) acc[t][mb] = (f32x16){};
+        }
+        auto part_switch = [&](int ch) {
+            if (ch != nchC) return;
+#pragma unroll
+            for (int t = 0; t < QNT; ++t) {
+                ssc[t] = ss[t];
+                ss[t] = 0.0f;
+#pragma unroll
+                for (int mb = 0; mb < KB; ++mb) {
+                    ac[t][mb] = acc[t][mb];
+                    acc[t][mb] = (f32x16){};
+                }
+            }
         };
+        vm_wait<0>();                                 // the previous round's stores
         __syncthreads();                              // the previous round's readers are done
-        issue(0);
-        // chunks [0, nchC) accumulate the CLIP dot products, the rest the DINO ones
+        issue(0, frag0, feat0);
 #pragma unroll 1
-        for (int ch = 0; ch < nchC; ++ch) step(ch, ac, ssc);
-#pragma unroll 1
-        for (int ch = nchC; ch < nch; ++ch) step(ch, ad, ssd);
+        for (int ch = 0; ch < nch; ch += 2) {
+            part_switch(ch);
+            vm_wait<0>();
+            ring_barrier();
+            issue(ch + 1 < nch ? ch + 1 : ch, frag1, feat1);
+            chunk(frag0, feat0, acc, ss);
+            if (ch + 1 < nch) {
+                part_switch(ch + 1);
+                vm_wait<0>();
+                ring_barrier();
+                issue(ch + 2 < nch ? ch + 2 : ch + 1, frag0, feat0);
+                chunk(frag1, feat1, acc, ss);
+            }
+        }
+        if (nchC == nch) part_switch(nch);             // no DINO chunks: ad stays zero
+#pragma unroll
+        for (int t = 0; t < QNT; ++t) {
+            ssd[t] = ss[t];
+#pragma unroll
+            for (int mb = 0; mb < KB; ++mb) ad[t][mb] = acc[t][mb];
+        }
 #pragma unroll
         for (int t = 0; t < QNT; ++t) {
             const int64_t i = ii[t];
