@@ -518,7 +518,7 @@ k_quant_wgrad(const _Float16 *__restrict__ F, int64_t K, int64_t Kp, int d, int 
     };
     if (x0 < x1) load_step(x0);
     for (int64_t s0 = x0; s0 < x1; s0 += WG_FEAT) {
-        __syncthreads();                                   // the previous step's readers are done
+        ring_barrier();                                    // the previous step's readers are done
         // stage features [s0, s0 + 64) x dimensions [c0, c0 + 128) as B
         // fragments: 16 units of 8 features x 64 dimensions, four per wave;
         // lane l holds dimensions 8 (l / 8) .. + 7 (of the unit's half) of
@@ -541,7 +541,8 @@ k_quant_wgrad(const _Float16 *__restrict__ F, int64_t K, int64_t Kp, int d, int 
 #pragma unroll
         for (int ks = 0; ks < WG_FEAT / 16; ++ks) a[ks] = wa[ks];
         if (s0 + WG_FEAT < x1) load_step(s0 + WG_FEAT);
-        __syncthreads();
+        ring_barrier();                                    // the staged fragments (LDS only: the
+                                                           // loads just issued stay in flight)
 #pragma unroll
         for (int ks = 0; ks < WG_FEAT / 16; ++ks)
 #pragma unroll
