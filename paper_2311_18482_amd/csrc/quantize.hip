@@ -282,9 +282,10 @@ k_quant_pass(QuantArgs A)
         // and free the other buffer (read by chunk ch - 1) for the next loads.
         // The loop takes two chunks per iteration, even ones in buffer 0 and
         // odd ones in buffer 1, so that every read and every load has its
-        // buffer fixed at compile time; the last chunk reloads itself into
-        // the other buffer (an unconditional load keeps the compiler's own
-        // wait away from the reads). One set of accumulators serves the part
+        // buffer fixed at compile time. In the gradient pass the last chunk
+        // reloads itself into the other buffer: there a conditional load made
+        // the compiler wait before the reads (and spill); the assign pass
+        // loads only what it reads. One set of accumulators serves the part
         // being summed: at chunk nchC the CLIP sums move to ac.
         f32x16 acc[QNT][KB];
         float ss[QNT];
@@ -315,13 +316,13 @@ k_quant_pass(QuantArgs A)
             part_switch(ch);
             vm_wait<0>();
             ring_barrier();
-            issue(ch + 1 < nch ? ch + 1 : ch, frag1, feat1);
+            if (GRAD || ch + 1 < nch) issue(ch + 1 < nch ? ch + 1 : ch, frag1, feat1);
             chunk(frag0, feat0, acc, ss);
             if (ch + 1 < nch) {
                 part_switch(ch + 1);
                 vm_wait<0>();
                 ring_barrier();
-                issue(ch + 2 < nch ? ch + 2 : ch + 1, frag0, feat0);
+                if (GRAD || ch + 2 < nch) issue(ch + 2 < nch ? ch + 2 : ch + 1, frag0, feat0);
                 chunk(frag1, feat1, acc, ss);
             }
         }
