@@ -175,8 +175,12 @@ __device__ __forceinline__ void argmax_pair(float &best, int &bidx)
 // Top-1 only: logits consumed block by block (each lane keeps the block
 // holding its running maximum and searches it once at the end: the first
 // maximum along increasing class index).
+// Row-major input (VEC8): eight waves per workgroup. The weight fragments fill
+// the LDS (one workgroup per CU) and such a wave fits in 256 registers, so two
+// waves share each SIMD (MFMAs of one beside the other's conversions and
+// argmax). The strided input's addressing would spill there: four waves.
 template <int KB, int NT, bool VEC8, bool NORM>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(VEC8 ? 512 : 256)
 k_dmlp_top1(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
             const float *__restrict__ params, int32_t *__restrict__ top1)
 {
@@ -184,9 +188,10 @@ k_dmlp_top1(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
     dmlp_stage<KB>(params, L);
     __syncthreads();
     const int lane = __lane_id(), wave = threadIdx.x / LEGS_WAVE, h = lane >> 5;
+    const int nw = blockDim.x / LEGS_WAVE;
     const int64_t groups = (P + 32 * NT - 1) / (32 * NT);
-    const int64_t stride = (int64_t)gridDim.x * 4;
-    for (int64_t g = (int64_t)blockIdx.x * 4 + wave; g < groups; g += stride) {
+    const int64_t stride = (int64_t)gridDim.x * nw;
+    for (int64_t g = (int64_t)blockIdx.x * nw + wave; g < groups; g += stride) {
         int off = 0;
         asm volatile("" : "+s"(off));
         legs_bf16x8 x[NT];
@@ -449,8 +454,9 @@ int32_t legs_launch_decode_dmlp(legs_ctx *ctx, const float *feat, int64_t P, int
 #undef LEGS_DMLP_P
     } else {
         constexpr int NT = 2;
-        const int grid = dmlp_grid(ctx, P, 32 * NT * 4, 1);
-#define LEGS_DMLP_T(KB, V, NM) hipLaunchKernelGGL((k_dmlp_top1<KB, NT, V, NM>), dim3(grid), dim3(256), 0, s, \
+        const int threads = vec8 ? 512 : 256;      // k_dmlp_top1's workgroup for each input layout
+        const int grid = dmlp_grid(ctx, P, 32 * NT * (threads / LEGS_WAVE), 1);
+#define LEGS_DMLP_T(KB, V, NM) hipLaunchKernelGGL((k_dmlp_top1<KB, NT, V, NM>), dim3(grid), dim3(threads), 0, s, \
                                                    feat, P, cs, ps, params, top1)
 #define LEGS_DMLP_TN(KB) if (vec8) { if (norm) LEGS_DMLP_T(KB, true, true); else LEGS_DMLP_T(KB, true, false); } \
                          else { if (norm) LEGS_DMLP_T(KB, false, true); else LEGS_DMLP_T(KB, false, false); }
