@@ -376,8 +376,12 @@ int32_t legs_quantize(legs_ctx *ctx, const uint16_t *feat, int64_t K, int32_t d,
  * legs_smooth_workspace_bytes(n) bytes (16-byte aligned), which on return
  * holds the bf16 hidden activations of the forward pass: with Gp = n rounded
  * up to a multiple of 64, a 16-row input plane (16 Gp bf16) and then the
- * planes of h1, h2 and h3 (128 Gp bf16 each), every plane blocked by 64
- * Gaussians ([Gp / 64][rows][64], zero for the padding Gaussians). */
+ * planes of h1, h2 and h3 (128 Gp bf16 each), followed by the backward's
+ * pre-activation gradients of layers 1-3 and of the output layer, each as a
+ * hi and a lo bf16 plane. A plane of R rows is in MFMA operand order:
+ * [Gp / 16][ceil(R / 32)][2][min(R, 32)][8], i.e. Gaussian g, row r at
+ * (g / 16, r / 32, (g / 8) % 2, r % 32, g % 8); the padding Gaussians are
+ * zero in the input and hidden planes. */
 int64_t legs_smooth_param_count(void);
 int64_t legs_smooth_workspace_bytes(int64_t n);
 int32_t legs_smooth_loss_grad(legs_ctx *ctx, const float *mean, const float *channels, int32_t C,

@@ -469,7 +469,7 @@ SmoothLayout smooth_layout(int64_t n)
     L.H1 = o; o += SH * plane;
     L.H2 = o; o += SH * plane;
     L.H3 = o; o += SH * plane;
-    L.D1 = o; o += 2 * SH * plane;            // float32 rows: twice a bf16 row
+    L.D1 = o; o += 2 * SH * plane;            // hi and lo bf16 planes
     L.D2 = o; o += 2 * SH * plane;
     L.D3 = o; o += 2 * SH * plane;
     L.D4 = o; o += 2 * LEGS_SMOOTH_OUT * plane;

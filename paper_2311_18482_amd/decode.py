@@ -162,8 +162,9 @@ def smooth_loss_grad(ctx: Context, mean, channels, sem_channel, u_channel, param
                      w_s=0.1, lambda_smo=1.0, workspace=None):
     """Adaptive spatial smoothing loss and gradients (legs_smooth_loss_grad);
     loss, grad and d_channels are accumulated. Returns the workspace (which
-    holds the bf16 hidden activations in blocks of 64 Gaussians, [rows][64]
-    per block, Gaussians padded to a multiple of 64)."""
+    holds the bf16 input and hidden activations, Gaussians padded to a
+    multiple of 64, each R-row plane in MFMA operand order
+    [Gp / 16][ceil(R / 32)][2][min(R, 32)][8])."""
     n, C = channels.shape
     if workspace is None:
         workspace = smooth_workspace(ctx, n)
