@@ -256,7 +256,7 @@ def language_leg(log_fn):
     F16 = F32.view(-1).view(torch.float16)[: d * P].view(d, P)
     ms_h = tm(lambda: DEC.language_features(ctx, p16, S, out_f16=True, F=F16))
     flop_px = 2 * (8 * 128 + 128 * 256 + 256 * N)
-    fbytes = lambda ob: P * (N * 2 * ((d + 255) // 256) + d * ob)
+    fbytes = lambda ob: P * (N * 2 * ((d + 511) // 512) + d * ob)   # M read once per 512-dimension chunk
     res["paper_decoder"] = dict(
         workload=f"Table 3 decoder 8-128-256-{N} (bf16) on {P} px (4 views 1920x1080) of N(0,1) features; "
                  f"F = M S with S {N} x {d}",

@@ -348,7 +348,7 @@ k_dmlp_probs(const float *__restrict__ feat, int64_t P, int64_t cs, int64_t ps,
 
 // ---- F = M S ------------------------------------------------------------------------
 
-constexpr int FCHUNK = 256;               // feature dimensions per workgroup
+constexpr int FCHUNK = 512;               // feature dimensions per workgroup (d = 512: M read once)
 constexpr int FBLK = FCHUNK / 32;
 
 template <int KB>
@@ -362,12 +362,19 @@ __device__ __forceinline__ f32x16 mfma16(f16x8 a, f16x8 b, f32x16 c)
 }
 
 // Grid: x = pixel groups (grid-stride), y = chunk of FCHUNK feature
-// dimensions. B operand of k-step ks for pixel p = lane % 32: classes
-// 16 ks + 8 (lane / 32) + e, one 16-byte load from the row M[p].
+// dimensions. A group is 32 NT consecutive pixels whose NT tiles interleave:
+// column c of tile t is pixel 32 NT g + NT c + t, so each lane ends with NT
+// neighbouring pixels of every output row and stores them as one vector (a
+// half-wave writes 32 NT contiguous elements of a row of F; with one pixel per
+// lane, half F took 2-byte stores and ran 25 % slower). B operand of
+// k-step ks for pixel p: classes 16 ks + 8 (lane / 32) + e, one 16-byte load
+// from the row M[p]. Sixteen waves per workgroup: the S fragments of 512
+// dimensions fill the LDS (one workgroup per CU) and a wave fits in 128
+// registers. vec: P % NT == 0 and F 16-byte aligned, else element stores.
 template <int KB, int NT, bool OUT16>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_lang_features(const _Float16 *__restrict__ M, int64_t P, const float *__restrict__ S, int d,
-                void *__restrict__ F)
+                void *__restrict__ F, int vec)
 {
     constexpr int N = 32 * KB, KS = 2 * KB;
     __shared__ FeatLds<KB> L;
@@ -384,15 +391,16 @@ k_lang_features(const _Float16 *__restrict__ M, int64_t P, const float *__restri
     }
     __syncthreads();
     const int lane = __lane_id(), wave = threadIdx.x / LEGS_WAVE, h = lane >> 5;
+    const int nw = blockDim.x / LEGS_WAVE;
     const int64_t groups = (P + 32 * NT - 1) / (32 * NT);
-    const int64_t stride = (int64_t)gridDim.x * 4;
-    for (int64_t g = (int64_t)blockIdx.x * 4 + wave; g < groups; g += stride) {
+    const int64_t stride = (int64_t)gridDim.x * nw;
+    for (int64_t g = (int64_t)blockIdx.x * nw + wave; g < groups; g += stride) {
         int off = 0;
         asm volatile("" : "+s"(off));
         f16x8 b[NT][KS];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int64_t p = (g * NT + t) * 32 + (lane & 31);
+            const int64_t p = g * NT * 32 + NT * (lane & 31) + t;
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
                 b[t][ks] = p < P ? *reinterpret_cast<const f16x8 *>(M + p * N + 16 * ks + 8 * h) : (f16x8){};
@@ -406,14 +414,32 @@ k_lang_features(const _Float16 *__restrict__ M, int64_t P, const float *__restri
                 for (int t = 0; t < NT; ++t) acc[t] = mfma16(a, b[t][ks], ks == 0 ? (f32x16){} : acc[t]);
             }
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int64_t p = (g * NT + t) * 32 + (lane & 31);
-                if (p >= P) continue;
+            for (int r = 0; r < 16; ++r) {
+                const int64_t p0 = g * NT * 32 + NT * (lane & 31);
+                const int64_t o = (int64_t)(d0 + 32 * db + legs_drow(r, h)) * P + p0;
+                if (vec) {
+                    if (p0 < P) {
+                        if constexpr (OUT16) {
+                            typedef _Float16 hv __attribute__((ext_vector_type(NT)));
+                            hv v;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int64_t o = (int64_t)(d0 + 32 * db + legs_drow(r, h)) * P + p;
-                    if constexpr (OUT16) reinterpret_cast<_Float16 *>(F)[o] = (_Float16)acc[t][r];
-                    else reinterpret_cast<float *>(F)[o] = acc[t][r];
+                            for (int t = 0; t < NT; ++t) v[t] = (_Float16)acc[t][r];
+                            *reinterpret_cast<hv *>(reinterpret_cast<_Float16 *>(F) + o) = v;
+                        } else {
+                            typedef float fv __attribute__((ext_vector_type(NT)));
+                            fv v;
+#pragma unroll
+                            for (int t = 0; t < NT; ++t) v[t] = acc[t][r];
+                            *reinterpret_cast<fv *>(reinterpret_cast<float *>(F) + o) = v;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        if (p0 + t >= P) break;
+                        if constexpr (OUT16) reinterpret_cast<_Float16 *>(F)[o + t] = (_Float16)acc[t][r];
+                        else reinterpret_cast<float *>(F)[o + t] = acc[t][r];
+                    }
                 }
             }
         }
@@ -476,12 +502,13 @@ int32_t legs_launch_language_features(legs_ctx *ctx, const uint16_t *probs16, in
                                       const float *S, int32_t d, int32_t out_f16, void *F, hipStream_t s)
 {
     if (P == 0) return LEGS_OK;
-    constexpr int NT = 4;
-    const int gx = dmlp_grid(ctx, P, 32 * NT * 4, 2);
+    constexpr int NT = 2;
+    const int gx = dmlp_grid(ctx, P, 32 * NT * 16, 1);
     const dim3 grid((unsigned)gx, (unsigned)((d + FCHUNK - 1) / FCHUNK));
     const _Float16 *M = reinterpret_cast<const _Float16 *>(probs16);
-#define LEGS_FEAT(KB) if (out_f16) hipLaunchKernelGGL((k_lang_features<KB, NT, true>), grid, dim3(256), 0, s, M, P, S, d, F); \
-                      else hipLaunchKernelGGL((k_lang_features<KB, NT, false>), grid, dim3(256), 0, s, M, P, S, d, F)
+    const int vec = P % NT == 0 && (reinterpret_cast<uintptr_t>(F) & 15) == 0;
+#define LEGS_FEAT(KB) if (out_f16) hipLaunchKernelGGL((k_lang_features<KB, NT, true>), grid, dim3(1024), 0, s, M, P, S, d, F, vec); \
+                      else hipLaunchKernelGGL((k_lang_features<KB, NT, false>), grid, dim3(1024), 0, s, M, P, S, d, F, vec)
     switch (N) {
     case 32: LEGS_FEAT(1); break;
     case 64: LEGS_FEAT(2); break;

@@ -62,23 +62,30 @@ def test_paper_decoder_matches_oracle(ctx, N, normalize):
     note(f"ambiguous pixels {n_amb}, resolved {int(resolved.sum())} of {n}")
 
 
-@pytest.mark.parametrize("N,d,out_f16", [(128, 512, False), (32, 544, False), (64, 96, True)])
-def test_language_features_match_oracle(ctx, N, d, out_f16):
+@pytest.mark.parametrize("N,d,out_f16,n,misalign", [(128, 512, False, 3007, 0), (32, 544, False, 3007, 0),
+                                                    (64, 96, True, 3007, 0), (128, 544, True, 3010, 0),
+                                                    (64, 96, False, 3010, 0), (128, 512, True, 3010, 1)])
+def test_language_features_match_oracle(ctx, N, d, out_f16, n, misalign):
     """F = M S: against the float64 product of the very half-precision inputs
     the kernel read (float32 accumulation is the only rounding: within
     gamma_N of M |S|), and against the oracle's exact M S (the half roundings
     of M and S add at most 2^-10 of M |S|, plus 2^-25 |S| per class where a
-    probability is subnormal in half precision)."""
+    probability is subnormal in half precision). An even pixel count with F
+    16-byte aligned takes the kernel's paired-pixel stores, an odd one or an F
+    one element off alignment its element stores (ragged last group either
+    way)."""
     from paper_2311_18482_amd import decode as DEC
-    n = 3000 + 7
     f = features(n, 160 + d)
     ws, bs = synth.mlp_init((8, 128, 256, N), 161 + N)
     S = synth.codebook(N, d, 162 + d)
     params = DEC.mlp_pack(ws, bs).cuda()
-    note(f"language_features N={N} d={d} out_f16={out_f16}")
+    note(f"language_features N={N} d={d} out_f16={out_f16} n={n} misalign={misalign}")
     _, pr, p16 = DEC.decode_dmlp(ctx, DEC.rowmajor_features(torch.from_numpy(f).cuda()), params, N, probs=True,
                                  probs_f16=True, top1=False)
-    Fg = DEC.language_features(ctx, p16, torch.from_numpy(S).cuda(), out_f16=out_f16)
+    buf = torch.full((d * n + misalign,), float("nan"), dtype=torch.float16 if out_f16 else torch.float32,
+                     device="cuda")
+    Fg = DEC.language_features(ctx, p16, torch.from_numpy(S).cuda(), out_f16=out_f16,
+                               F=buf[misalign:].view(d, n))
     torch.cuda.synchronize()
     assert Fg.shape == (d, n)
     Fg = Fg.float().cpu().numpy().astype(np.float64).T
@@ -115,9 +122,13 @@ def test_paper_decoder_and_features_at_bench_size(ctx):
     t_only, _, _ = DEC.decode_dmlp(ctx, DEC.rowmajor_features(fd), params, N)
     t1, pr, p16 = DEC.decode_dmlp(ctx, DEC.rowmajor_features(fd), params, N, probs=True, probs_f16=True)
     Fg = DEC.language_features(ctx, p16, torch.from_numpy(S).cuda())
+    Fh = DEC.language_features(ctx, p16, torch.from_numpy(S).cuda(), out_f16=True)
     torch.cuda.synchronize()
     assert torch.equal(t_only, t1)
     assert torch.equal(p16, pr.half())
+    # the half map is the same float32 sums rounded to nearest
+    assert torch.equal(Fh, Fg.half())
+    del Fh
     rng = np.random.default_rng(193)
     idx = np.unique(np.concatenate([[0], np.arange(P - 40, P), rng.integers(0, P, 4000)]))
     it = torch.from_numpy(idx).cuda()
