@@ -64,7 +64,8 @@ def test_paper_decoder_matches_oracle(ctx, N, normalize):
 
 @pytest.mark.parametrize("N,d,out_f16,n,misalign", [(128, 512, False, 3007, 0), (32, 544, False, 3007, 0),
                                                     (64, 96, True, 3007, 0), (128, 544, True, 3010, 0),
-                                                    (64, 96, False, 3010, 0), (128, 512, True, 3010, 1)])
+                                                    (64, 96, False, 3010, 0), (128, 512, True, 3010, 1),
+                                                    (32, 4096, True, 1030, 0)])
 def test_language_features_match_oracle(ctx, N, d, out_f16, n, misalign):
     """F = M S: against the float64 product of the very half-precision inputs
     the kernel read (float32 accumulation is the only rounding: within
