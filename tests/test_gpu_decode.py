@@ -229,9 +229,12 @@ def test_adam_groups_and_clamp(ctx, DEC):
         assert np.allclose(got, h["p"], rtol=1e-6, atol=1e-6)
 
 
-def test_l1_loss_gradient(ctx, DEC):
+@pytest.mark.parametrize("sizes", [((37, 21), (64, 48)), ((32, 16), (64, 48)), ((32, 16), (37, 21), (16, 8))])
+def test_l1_loss_gradient(ctx, DEC, sizes):
+    """Unaligned planes (odd pixel counts) take the kernel's element path,
+    16-byte aligned ones its four-element path, a mix both."""
     from paper_2311_18482_amd import raster as R
-    cams = [synth.camera_front(37, 21, 40.0), synth.camera_front(64, 48, 64.0)]
+    cams = [synth.camera_front(w, h, float(w)) for w, h in sizes]
     C, ds = 20, 16
     rng = np.random.default_rng(60)
     total = sum(C * c.width * c.height for c in cams)
