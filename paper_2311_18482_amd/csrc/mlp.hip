@@ -437,32 +437,74 @@ int32_t legs_launch_semantic_loss_grad(legs_ctx *ctx, const float *feat, const f
 
 namespace {
 
+// Elements per workgroup of k_adam: four neighbouring floats per thread, four times.
+constexpr int ADAM_CHUNK = 256 * 4 * 4;
+
 struct AdamArgs {
     legs_adam_group g[LEGS_ADAM_MAX_GROUPS];
-    int64_t start[LEGS_ADAM_MAX_GROUPS + 1];
+    int64_t bstart[LEGS_ADAM_MAX_GROUPS + 1];   // first workgroup of each group
+    int vec[LEGS_ADAM_MAX_GROUPS];              // the group's four arrays are 16-byte aligned
     int n_groups;
     // omb = 1 - b rounded once from double (1 - 0.999f would be 1.3e-5 off
     // 0.001); c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t)
     float lr, b1, b2, omb1, omb2, eps, c1, c2;
 };
 
+__device__ __forceinline__ float adam_one(const AdamArgs &A, float p, float g, float &m, float &v)
+{
+    m = A.b1 * m + A.omb1 * g;
+    v = A.b2 * v + A.omb2 * g * g;
+    return p - A.lr * (m * A.c1) / (sqrtf(v * A.c2) + A.eps);
+}
+
+// Each workgroup updates one ADAM_CHUNK of one group, the group found by a
+// wave-uniform walk over the workgroup counts (so its pointers are scalars);
+// float4 access where the group is aligned, and the clamp test takes one
+// remainder per four elements.
 __global__ void __launch_bounds__(256)
 k_adam(AdamArgs A)
 {
-    const int64_t total = A.start[A.n_groups];
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
-        int k = 0;
-        while (k + 1 < A.n_groups && i >= A.start[k + 1]) ++k;
-        const legs_adam_group &G = A.g[k];
-        const int64_t j = i - A.start[k];
-        const float g = G.grad[j];
-        const float m = A.b1 * G.m[j] + A.omb1 * g;
-        const float v = A.b2 * G.v[j] + A.omb2 * g * g;
+    int k = 0;
+    while (k + 1 < A.n_groups && (int64_t)blockIdx.x >= A.bstart[k + 1]) ++k;
+    const legs_adam_group &G = A.g[k];
+    const int64_t c0 = ((int64_t)blockIdx.x - A.bstart[k]) * ADAM_CHUNK;
+    const int64_t c1 = c0 + ADAM_CHUNK < G.n ? c0 + ADAM_CHUNK : G.n;
+    const int64_t ce = G.clamp_every;
+    int64_t j0 = c0;
+    if (A.vec[k]) {
+        const int64_t q1 = c1 / 4;
+        for (int64_t q = c0 / 4 + threadIdx.x; q < q1; q += 256) {
+            float4 p = reinterpret_cast<const float4 *>(G.param)[q];
+            const float4 g = reinterpret_cast<const float4 *>(G.grad)[q];
+            float4 m = reinterpret_cast<const float4 *>(G.m)[q];
+            float4 v = reinterpret_cast<const float4 *>(G.v)[q];
+            p.x = adam_one(A, p.x, g.x, m.x, v.x);
+            p.y = adam_one(A, p.y, g.y, m.y, v.y);
+            p.z = adam_one(A, p.z, g.z, m.z, v.z);
+            p.w = adam_one(A, p.w, g.w, m.w, v.w);
+            if (ce > 0) {
+                const int64_t r0 = (4 * q) % ce;
+                const int64_t r1 = r0 + 1 == ce ? 0 : r0 + 1, r2 = r1 + 1 == ce ? 0 : r1 + 1,
+                              r3 = r2 + 1 == ce ? 0 : r2 + 1;
+                const float lo = G.clamp_lo, hi = G.clamp_hi;
+                const int64_t off = G.clamp_offset;
+                if (r0 == off) p.x = fminf(fmaxf(p.x, lo), hi);
+                if (r1 == off) p.y = fminf(fmaxf(p.y, lo), hi);
+                if (r2 == off) p.z = fminf(fmaxf(p.z, lo), hi);
+                if (r3 == off) p.w = fminf(fmaxf(p.w, lo), hi);
+            }
+            reinterpret_cast<float4 *>(G.m)[q] = m;
+            reinterpret_cast<float4 *>(G.v)[q] = v;
+            reinterpret_cast<float4 *>(G.param)[q] = p;
+        }
+        j0 = 4 * q1;
+    }
+    for (int64_t j = j0 + threadIdx.x; j < c1; j += 256) {
+        float m = G.m[j], v = G.v[j];
+        float p = adam_one(A, G.param[j], G.grad[j], m, v);
         G.m[j] = m;
         G.v[j] = v;
-        float p = G.param[j] - A.lr * (m * A.c1) / (sqrtf(v * A.c2) + A.eps);
-        if (G.clamp_every > 0 && (j % G.clamp_every) == G.clamp_offset)
-            p = fminf(fmaxf(p, G.clamp_lo), G.clamp_hi);
+        if (ce > 0 && (j % ce) == G.clamp_offset) p = fminf(fmaxf(p, G.clamp_lo), G.clamp_hi);
         G.param[j] = p;
     }
 }
@@ -474,22 +516,22 @@ int32_t legs_launch_adam(legs_ctx *ctx, const legs_adam_group *groups, int32_t n
 {
     AdamArgs A;
     A.n_groups = n_groups;
-    A.start[0] = 0;
+    A.bstart[0] = 0;
     for (int k = 0; k < n_groups; ++k) {
-        A.g[k] = groups[k];
-        A.start[k + 1] = A.start[k] + groups[k].n;
+        const legs_adam_group &G = groups[k];
+        A.g[k] = G;
+        A.bstart[k + 1] = A.bstart[k] + (G.n + ADAM_CHUNK - 1) / ADAM_CHUNK;
+        A.vec[k] = ((reinterpret_cast<uintptr_t>(G.param) | reinterpret_cast<uintptr_t>(G.grad) |
+                     reinterpret_cast<uintptr_t>(G.m) | reinterpret_cast<uintptr_t>(G.v)) & 15) == 0;
     }
     A.lr = lr; A.eps = eps;
     A.b1 = (float)beta1; A.b2 = (float)beta2;
     A.omb1 = (float)(1.0 - beta1); A.omb2 = (float)(1.0 - beta2);
     A.c1 = (float)(1.0 / (1.0 - pow(beta1, (double)step)));
     A.c2 = (float)(1.0 / (1.0 - pow(beta2, (double)step)));
-    const int64_t total = A.start[n_groups];
-    if (total == 0) return LEGS_OK;
-    int64_t g = (total + 255) / 256;
-    const int64_t cap = (int64_t)ctx->num_cus * 16;
-    if (g > cap) g = cap;
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)g), dim3(256), 0, s, A);
+    const int64_t blocks = A.bstart[n_groups];
+    if (blocks == 0) return LEGS_OK;
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, s, A);
     LEGS_CHECK_LAUNCH(ctx);
     return LEGS_OK;
 }

@@ -207,21 +207,32 @@ def test_mlp_gradient_and_train_step(ctx, DEC, normalize):
 
 
 def test_adam_groups_and_clamp(ctx, DEC):
+    """Groups of one and several workgroup chunks, an empty one, ragged tails;
+    16-byte aligned groups take the kernel's four-element path, the last one
+    (every array one element off alignment) its element path; clamps whose
+    period is shorter and longer than four."""
     rng = np.random.default_rng(50)
-    sizes = [1000, 37, 4096 * 5]
+    sizes = [1000, 37, 4096 * 5, 0, 4096 * 2 + 3]
     host = [dict(p=rng.normal(0, 1, n), m=np.zeros(n), v=np.zeros(n)) for n in sizes]
-    dev = [dict(param=torch.tensor(h["p"], dtype=torch.float32).cuda(),
-                m=torch.zeros(n, dtype=torch.float32).cuda(),
-                v=torch.zeros(n, dtype=torch.float32).cuda(),
-                grad=torch.zeros(n, dtype=torch.float32).cuda()) for h, n in zip(host, sizes)]
-    dev[2]["clamp"] = (5, 4, 0.0, 1.0)             # every 5th column clamped to [0, 1]
+
+    def buf(n, off, x=None):
+        b = torch.zeros(n + off, dtype=torch.float32, device="cuda")[off:]
+        if x is not None:
+            b.copy_(torch.tensor(x, dtype=torch.float32))
+        return b
+    dev = [dict(param=buf(n, off, h["p"]), m=buf(n, off), v=buf(n, off), grad=buf(n, off))
+           for h, n, off in zip(host, sizes, [0, 0, 0, 0, 1])]
+    clamps = {0: (3, 2, -0.2, 0.2), 2: (5, 4, 0.0, 1.0), 4: (7, 0, -0.5, 0.5)}
+    for k, c in clamps.items():
+        dev[k]["clamp"] = c                        # every c[0]-th column from c[1] clamped to [c[2], c[3]]
     for step in range(1, 5):
         for h, d in zip(host, dev):
             g = rng.normal(0, 1, h["p"].size).astype(np.float32)
             d["grad"].copy_(torch.from_numpy(g))
             h["p"], h["m"], h["v"] = D.adam(h["p"], g.astype(np.float64), h["m"], h["v"], step,
                                             lr=1e-2)
-        host[2]["p"][4::5] = np.clip(host[2]["p"][4::5], 0.0, 1.0)
+        for k, (every, off, lo, hi) in clamps.items():
+            host[k]["p"][off::every] = np.clip(host[k]["p"][off::every], lo, hi)
         DEC.adam(ctx, dev, step, lr=1e-2)
     torch.cuda.synchronize()
     for h, d in zip(host, dev):
